@@ -1,0 +1,193 @@
+"""Oracle for sketch-based dynamic connectivity (test infrastructure only).
+
+A plain CPU implementation of what the GPU hot path computes, used by the
+tests, the smoke check and the CPU-baseline leg of the benchmark, and by
+nothing else.  It shares no code with the product library: the sketch
+arithmetic lives in ``oracle.c`` (built with gcc into ``liboracle.so``), the
+forest replay and the connectivity truth are plain Python below.
+
+Paper: "Fast and Compact Sketch-Based Dynamic Connectivity" (arXiv
+2509.14433).  See ``oracle.c`` for the sketch definition and the readings of
+the points the paper leaves open.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+OK, EMPTY, FAILED = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` with gcc into ``liboracle.so`` (in place)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = ctypes.CDLL(_SO)
+        u64, u32, sz, p = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_void_p
+        L.orc_mix.restype = u64; L.orc_mix.argtypes = [u64]
+        L.orc_seed.restype = u64; L.orc_seed.argtypes = [u64, u32]
+        L.orc_hash.restype = u64; L.orc_hash.argtypes = [u64, u32, u64]
+        L.orc_depth_of_hash.restype = u32; L.orc_depth_of_hash.argtypes = [u64, u32]
+        L.orc_edge_index.restype = u64; L.orc_edge_index.argtypes = [u32, u32, u32]
+        L.orc_valid_index.restype = ctypes.c_int; L.orc_valid_index.argtypes = [u32, u64]
+        L.orc_new.restype = p; L.orc_new.argtypes = [u32, u32, u32, u64]
+        L.orc_free.restype = None; L.orc_free.argtypes = [p]
+        L.orc_clear.restype = None; L.orc_clear.argtypes = [p]
+        L.orc_alpha.restype = p; L.orc_alpha.argtypes = [p]
+        L.orc_gamma.restype = p; L.orc_gamma.argtypes = [p]
+        L.orc_toggle.restype = None; L.orc_toggle.argtypes = [p, u32, u32]
+        L.orc_apply.restype = None; L.orc_apply.argtypes = [p, p, p, sz]
+        L.orc_vertex_from_stream.restype = None
+        L.orc_vertex_from_stream.argtypes = [u32, u32, u32, u64, u32, p, p, sz, p, p]
+        L.orc_set_sketch.restype = None; L.orc_set_sketch.argtypes = [p, p, sz, p, p]
+        L.orc_sample.restype = ctypes.c_int
+        L.orc_sample.argtypes = [u32, u32, u32, u64, p, p, p, p]
+        L.orc_digest.restype = u64; L.orc_digest.argtypes = [p]
+        L.orc_digest_arrays.restype = u64
+        L.orc_digest_arrays.argtypes = [u32, u32, u64, u32, u32, p, p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+# ---- scalar hash functions ------------------------------------------------
+
+def mix(z: int) -> int:
+    return lib().orc_mix(z & 0xFFFFFFFFFFFFFFFF)
+
+
+def seed(S: int, c: int) -> int:
+    return lib().orc_seed(S, c)
+
+
+def hash_c(S: int, c: int, x: int) -> int:
+    return lib().orc_hash(S, c, x)
+
+
+def depth_of_hash(h: int, D: int) -> int:
+    return lib().orc_depth_of_hash(h, D)
+
+
+def edge_index(V: int, a: int, b: int) -> int:
+    return lib().orc_edge_index(V, a, b)
+
+
+# ---- sketch state -----------------------------------------------------------
+
+class Sketch:
+    """All vertex sketches of a graph on V vertices: C columns x D depth
+    buckets of (alpha, gamma) per vertex, canonical order [w][c][d]."""
+
+    def __init__(self, V: int, C: int, D: int, S: int):
+        self.V, self.C, self.D, self.S = V, C, D, S
+        self._h = lib().orc_new(V, C, D, S)
+        if not self._h:
+            raise MemoryError("oracle sketch allocation failed")
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_free(self._h)
+            self._h = None
+
+    def clear(self):
+        lib().orc_clear(self._h)
+
+    def apply(self, u, v):
+        u = np.ascontiguousarray(u, dtype=np.uint32)
+        v = np.ascontiguousarray(v, dtype=np.uint32)
+        assert u.shape == v.shape
+        lib().orc_apply(self._h, _ptr(u), _ptr(v), u.shape[0])
+
+    def toggle(self, a: int, b: int):
+        lib().orc_toggle(self._h, a, b)
+
+    def _view(self, fn):
+        n = self.V * self.C * self.D
+        buf = (ctypes.c_uint64 * n).from_address(fn(self._h))
+        return np.frombuffer(buf, dtype=np.uint64).reshape(self.V, self.C, self.D)
+
+    @property
+    def alpha(self) -> np.ndarray:
+        return self._view(lib().orc_alpha)
+
+    @property
+    def gamma(self) -> np.ndarray:
+        return self._view(lib().orc_gamma)
+
+    def set_sketch(self, verts):
+        verts = np.ascontiguousarray(verts, dtype=np.uint32)
+        a = np.zeros(self.C * self.D, np.uint64)
+        g = np.zeros(self.C * self.D, np.uint64)
+        lib().orc_set_sketch(self._h, _ptr(verts), verts.shape[0], _ptr(a), _ptr(g))
+        return a.reshape(self.C, self.D), g.reshape(self.C, self.D)
+
+    def sample(self, alpha, gamma):
+        return sample(self.V, self.C, self.D, self.S, alpha, gamma)
+
+    def digest(self) -> int:
+        return lib().orc_digest(self._h)
+
+
+def sample(V, C, D, S, alpha, gamma):
+    """(status, u, v) of the query on one aggregate sketch."""
+    a = np.ascontiguousarray(alpha, dtype=np.uint64).reshape(-1)
+    g = np.ascontiguousarray(gamma, dtype=np.uint64).reshape(-1)
+    assert a.shape[0] == C * D and g.shape[0] == C * D
+    ou, ov = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    st = lib().orc_sample(V, C, D, S, _ptr(a), _ptr(g), ctypes.byref(ou), ctypes.byref(ov))
+    if st != OK:
+        return st, 0, 0
+    return st, ou.value, ov.value
+
+
+def vertex_from_stream(V, C, D, S, w, u, v):
+    """Sketch of vertex w from the updates that touch it (C x D arrays)."""
+    u = np.ascontiguousarray(u, dtype=np.uint32)
+    v = np.ascontiguousarray(v, dtype=np.uint32)
+    a = np.zeros(C * D, np.uint64)
+    g = np.zeros(C * D, np.uint64)
+    lib().orc_vertex_from_stream(V, C, D, S, w, _ptr(u), _ptr(v), u.shape[0], _ptr(a), _ptr(g))
+    return a.reshape(C, D), g.reshape(C, D)
+
+
+def digest_arrays(C, D, S, w0, alpha, gamma) -> int:
+    """Digest contribution of vertices w0 .. w0+len-1 given as (n, C, D)
+    alpha / gamma arrays in canonical order."""
+    a = np.ascontiguousarray(alpha, dtype=np.uint64)
+    g = np.ascontiguousarray(gamma, dtype=np.uint64)
+    nv = a.shape[0]
+    assert a.shape == (nv, C, D) and g.shape == a.shape
+    return lib().orc_digest_arrays(C, D, S, w0, nv, _ptr(a), _ptr(g))
+
+
+from .forest import ForestReplay, components_truth, check_spanning_forest  # noqa: E402
+
+__all__ = [
+    "OK", "EMPTY", "FAILED", "build", "lib", "mix", "seed", "hash_c",
+    "depth_of_hash", "edge_index", "Sketch", "sample", "vertex_from_stream",
+    "digest_arrays", "ForestReplay", "components_truth", "check_spanning_forest",
+]

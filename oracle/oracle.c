@@ -1,0 +1,274 @@
+/*
+ * Oracle for sketch-based dynamic connectivity: a plain, slow, single-thread
+ * CPU implementation of what the GPU hot path computes.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It shares no code, header or table with the HIP path.
+ *
+ * What it computes (paper references are sections / equations / theorems of
+ * "Fast and Compact Sketch-Based Dynamic Connectivity", arXiv 2509.14433):
+ *
+ *  - Per-vertex l0-sketch of the vertex's characteristic vector (App. A.1.1,
+ *    "The AGM algorithm"): f_u has a 1 at index (u,v) for every incident
+ *    edge.  The sampler is a CameoSketch-style F2 sampler (Thm. "CameoSketch",
+ *    App. A.1.1; Sec. 3.1): C independent columns, each update touches one
+ *    bucket per column, each bucket holds the XOR of the indices (alpha) and
+ *    the XOR of their checksums (gamma).
+ *  - Sketch addition is word-wise XOR (App. A.1.1), so the sketch of a vertex
+ *    set is the XOR of its members' sketches; internal edges cancel and what
+ *    remains is exactly the sketch of the cut (App. A.1.1, cancellation).
+ *  - A query returns an edge from a bucket that holds exactly one index
+ *    (Sec. 2.1; l0-sampling in App. A.1.1), or fails.
+ *
+ * Readings of points the paper leaves open (the hash family, depth rule,
+ * checksum, the order in which good buckets are scanned) are fixed as:
+ *   seed_c   = c-th output of SplitMix64 started at state S
+ *              (Steele, Lea, Flood, OOPSLA 2014)
+ *   mix(z)   = SplitMix64 output finalizer
+ *   h_c(x)   = mix(x ^ seed_c)
+ *   d_c(x)   = min(ctz(h_c(x)), D-1), ctz(0) = 64
+ *   bucket (c, d) of a vertex sketch:
+ *            alpha = XOR of x_e over incident live edges e with d_c(x_e) = d
+ *            gamma = XOR of h_c(x_e) over the same edges
+ *   x_e      = u*V + v for edge {u,v} with u < v
+ *   good(c,d)= alpha != 0 and alpha decodes to u < v < V
+ *              and h_c(alpha) == gamma and d_c(alpha) == d
+ *   sample   = first good bucket scanning c = 0..C-1, and inside a column
+ *              d = D-1 down to 0; EMPTY if every word is zero, else FAILED.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EMPTY 1
+#define ORC_FAILED 2
+
+/* ---- hash ------------------------------------------------------------- */
+
+uint64_t orc_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* c-th output (c = 0, 1, ...) of SplitMix64 whose state starts at S:
+ * the state advances by the golden-ratio increment before each output. */
+uint64_t orc_seed(uint64_t S, uint32_t c)
+{
+    uint64_t state = S;
+    uint64_t out = 0;
+    for (uint32_t i = 0; i <= c; i++) {
+        state += 0x9E3779B97F4A7C15ULL;
+        out = orc_mix(state);
+    }
+    return out;
+}
+
+uint64_t orc_hash(uint64_t S, uint32_t c, uint64_t x)
+{
+    return orc_mix(x ^ orc_seed(S, c));
+}
+
+static uint32_t ctz64(uint64_t h)
+{
+    if (h == 0) return 64;
+    uint32_t n = 0;
+    while ((h & 1ULL) == 0) { h >>= 1; n++; }
+    return n;
+}
+
+uint32_t orc_depth_of_hash(uint64_t h, uint32_t D)
+{
+    uint32_t z = ctz64(h);
+    return z < D - 1 ? z : D - 1;
+}
+
+uint64_t orc_edge_index(uint32_t V, uint32_t a, uint32_t b)
+{
+    uint32_t u = a < b ? a : b;
+    uint32_t v = a < b ? b : a;
+    return (uint64_t)u * V + v;
+}
+
+/* valid(x): x decodes to u < v < V */
+int orc_valid_index(uint32_t V, uint64_t x)
+{
+    if (x == 0) return 0;
+    uint64_t u = x / V, v = x % V;
+    return u < v && v < V;
+}
+
+/* ---- sketch state ----------------------------------------------------- */
+
+/* Bucket (c, d) of vertex w lives at [(w*C + c)*D + d]: the canonical
+ * order.  alpha and gamma are separate arrays. */
+typedef struct {
+    uint32_t V, C, D;
+    uint64_t S;
+    uint64_t *seeds; /* seeds[c] */
+    uint64_t *alpha;
+    uint64_t *gamma;
+} orc_sketch;
+
+orc_sketch *orc_new(uint32_t V, uint32_t C, uint32_t D, uint64_t S)
+{
+    orc_sketch *s = (orc_sketch *)calloc(1, sizeof(orc_sketch));
+    if (!s) return NULL;
+    s->V = V; s->C = C; s->D = D; s->S = S;
+    s->seeds = (uint64_t *)malloc(sizeof(uint64_t) * C);
+    size_t nb = (size_t)V * C * D;
+    s->alpha = (uint64_t *)calloc(nb, sizeof(uint64_t));
+    s->gamma = (uint64_t *)calloc(nb, sizeof(uint64_t));
+    if (!s->seeds || !s->alpha || !s->gamma) {
+        free(s->seeds); free(s->alpha); free(s->gamma); free(s);
+        return NULL;
+    }
+    for (uint32_t c = 0; c < C; c++) s->seeds[c] = orc_seed(S, c);
+    return s;
+}
+
+void orc_free(orc_sketch *s)
+{
+    if (!s) return;
+    free(s->seeds); free(s->alpha); free(s->gamma); free(s);
+}
+
+void orc_clear(orc_sketch *s)
+{
+    size_t nb = (size_t)s->V * s->C * s->D;
+    memset(s->alpha, 0, nb * sizeof(uint64_t));
+    memset(s->gamma, 0, nb * sizeof(uint64_t));
+}
+
+const uint64_t *orc_alpha(const orc_sketch *s) { return s->alpha; }
+const uint64_t *orc_gamma(const orc_sketch *s) { return s->gamma; }
+
+/* One stream update ((a,b), +-1).  Over F2 an insert and a delete are the
+ * same operation: toggle index x in the characteristic vectors of both
+ * endpoints, i.e. XOR (x, h_c(x)) into bucket (c, d_c(x)) of each endpoint
+ * for every column c. */
+void orc_toggle(orc_sketch *s, uint32_t a, uint32_t b)
+{
+    uint64_t x = orc_edge_index(s->V, a, b);
+    for (uint32_t c = 0; c < s->C; c++) {
+        uint64_t h = orc_mix(x ^ s->seeds[c]);
+        uint32_t d = orc_depth_of_hash(h, s->D);
+        size_t iu = ((size_t)a * s->C + c) * s->D + d;
+        size_t iv = ((size_t)b * s->C + c) * s->D + d;
+        s->alpha[iu] ^= x; s->gamma[iu] ^= h;
+        s->alpha[iv] ^= x; s->gamma[iv] ^= h;
+    }
+}
+
+void orc_apply(orc_sketch *s, const uint32_t *u, const uint32_t *v, size_t n)
+{
+    for (size_t i = 0; i < n; i++) orc_toggle(s, u[i], v[i]);
+}
+
+/* Sketch of one vertex w computed from the stream alone: apply only the
+ * updates that touch w.  Output is C*D alpha and gamma words in canonical
+ * order.  Used to check single vertices of streams too long to replay in
+ * full. */
+void orc_vertex_from_stream(uint32_t V, uint32_t C, uint32_t D, uint64_t S,
+                            uint32_t w, const uint32_t *u, const uint32_t *v,
+                            size_t n, uint64_t *out_alpha, uint64_t *out_gamma)
+{
+    uint64_t *seeds = (uint64_t *)malloc(sizeof(uint64_t) * C);
+    for (uint32_t c = 0; c < C; c++) seeds[c] = orc_seed(S, c);
+    memset(out_alpha, 0, sizeof(uint64_t) * C * D);
+    memset(out_gamma, 0, sizeof(uint64_t) * C * D);
+    for (size_t i = 0; i < n; i++) {
+        if (u[i] != w && v[i] != w) continue;
+        uint64_t x = orc_edge_index(V, u[i], v[i]);
+        for (uint32_t c = 0; c < C; c++) {
+            uint64_t h = orc_mix(x ^ seeds[c]);
+            uint32_t d = orc_depth_of_hash(h, D);
+            out_alpha[c * D + d] ^= x;
+            out_gamma[c * D + d] ^= h;
+        }
+    }
+    free(seeds);
+}
+
+/* Sketch of a vertex set: XOR of the members' sketches (App. A.1.1). */
+void orc_set_sketch(const orc_sketch *s, const uint32_t *verts, size_t n,
+                    uint64_t *out_alpha, uint64_t *out_gamma)
+{
+    size_t w = (size_t)s->C * s->D;
+    memset(out_alpha, 0, sizeof(uint64_t) * w);
+    memset(out_gamma, 0, sizeof(uint64_t) * w);
+    for (size_t i = 0; i < n; i++) {
+        const uint64_t *a = s->alpha + (size_t)verts[i] * w;
+        const uint64_t *g = s->gamma + (size_t)verts[i] * w;
+        for (size_t k = 0; k < w; k++) {
+            out_alpha[k] ^= a[k];
+            out_gamma[k] ^= g[k];
+        }
+    }
+}
+
+/* Query of an aggregate sketch (C*D buckets, canonical order). */
+int orc_sample(uint32_t V, uint32_t C, uint32_t D, uint64_t S,
+               const uint64_t *alpha, const uint64_t *gamma,
+               uint32_t *out_u, uint32_t *out_v)
+{
+    for (uint32_t c = 0; c < C; c++) {
+        uint64_t seed = orc_seed(S, c);
+        for (uint32_t k = 0; k < D; k++) {
+            uint32_t d = D - 1 - k;
+            uint64_t a = alpha[c * D + d];
+            uint64_t g = gamma[c * D + d];
+            if (a == 0) continue;
+            if (!orc_valid_index(V, a)) continue;
+            uint64_t h = orc_mix(a ^ seed);
+            if (h != g) continue;
+            if (orc_depth_of_hash(h, D) != d) continue;
+            *out_u = (uint32_t)(a / V);
+            *out_v = (uint32_t)(a % V);
+            return ORC_OK;
+        }
+    }
+    for (uint32_t k = 0; k < C * D; k++)
+        if (alpha[k] != 0 || gamma[k] != 0) return ORC_FAILED;
+    return ORC_EMPTY;
+}
+
+/* Order-independent 64-bit digest of a whole sketch:
+ *   sum over (w,c,d) of mix(alpha ^ rotl(gamma,32) ^ mix(((w*C+c)*D+d) ^ S))
+ * modulo 2^64. */
+uint64_t orc_digest(const orc_sketch *s)
+{
+    uint64_t acc = 0;
+    size_t i = 0;
+    for (uint64_t w = 0; w < s->V; w++)
+        for (uint64_t c = 0; c < s->C; c++)
+            for (uint64_t d = 0; d < s->D; d++, i++) {
+                uint64_t pos = (w * s->C + c) * s->D + d;
+                uint64_t g = s->gamma[i];
+                uint64_t rg = (g << 32) | (g >> 32);
+                acc += orc_mix(s->alpha[i] ^ rg ^ orc_mix(pos ^ s->S));
+            }
+    return acc;
+}
+
+/* Same digest over explicit arrays of a vertex range [w0, w0+nv): the
+ * partial sum; partial sums of disjoint ranges add up to the whole. */
+uint64_t orc_digest_arrays(uint32_t C, uint32_t D, uint64_t S, uint32_t w0,
+                           uint32_t nv, const uint64_t *alpha,
+                           const uint64_t *gamma)
+{
+    uint64_t acc = 0;
+    size_t i = 0;
+    for (uint64_t w = w0; w < (uint64_t)w0 + nv; w++)
+        for (uint64_t c = 0; c < C; c++)
+            for (uint64_t d = 0; d < D; d++, i++) {
+                uint64_t pos = (w * C + c) * D + d;
+                uint64_t g = gamma[i];
+                uint64_t rg = (g << 32) | (g >> 32);
+                acc += orc_mix(alpha[i] ^ rg ^ orc_mix(pos ^ S));
+            }
+    return acc;
+}
