@@ -1,0 +1,232 @@
+/*
+ * cupk — sketch-based dynamic connectivity on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the data-parallel hot path of the CUPCaKE method ("Fast and
+ * Compact Sketch-Based Dynamic Connectivity", arXiv 2509.14433):
+ *   - every vertex keeps a resident l0-sketch of its characteristic vector
+ *     (App. A.1.1, AGM characteristic vectors; CameoSketch-style F2 sampler,
+ *     Sec. 3.1 and the CameoSketch theorem of App. A.1.1);
+ *   - a batch of edge inserts / deletes is hashed once per column and
+ *     XOR-scattered into one bucket per column of both endpoints' sketches
+ *     (cutset Update, Sec. 2.2.1; Alg. 1, first parallel loop);
+ *   - the sketch of a vertex set is the XOR of its members' sketches, which
+ *     cancels internal edges and leaves the cut (App. A.1.1);
+ *   - a query returns an edge from a bucket holding exactly one index
+ *     (cutset Query, Sec. 2.2.1);
+ *   - a spanning forest is kept on the host; deleting a forest edge triggers
+ *     replacement search by Boruvka-style rounds over the broken trees
+ *     (App. A.1.1, AGM Boruvka; Alg. 1 restoration loop) and connectivity
+ *     queries are answered from the forest (Sec. 2.1 problem statement,
+ *     Sec. 4.1 query tree).
+ *
+ * Sketch definition (bit-exact contract with the tests' CPU oracle):
+ *   seed_c  = c-th output of SplitMix64 from state `seed`
+ *   h_c(x)  = SplitMix64 finalizer of (x ^ seed_c)
+ *   d_c(x)  = min(ctz(h_c(x)), D-1)          (ctz(0) = 64)
+ *   x       = u*V + v for edge {u, v}, u < v
+ *   bucket (c, d) of vertex w holds
+ *           alpha = XOR of x over live edges at w with d_c(x) = d,
+ *           gamma = XOR of h_c(x) over the same edges.
+ *   good(c,d) iff alpha != 0, alpha decodes to u < v < V, h_c(alpha) == gamma
+ *           and d_c(alpha) == d.
+ *   sample  = the first good bucket scanning c = 0..C-1 and, inside a column,
+ *           d = D-1 down to 0.
+ *
+ * Conventions
+ *   - Return codes: 0 OK, positive = informational status, negative = error.
+ *   - Buckets at this boundary are always in canonical order: bucket (c, d)
+ *     of one sketch is element c*D + d of a cupk_bucket array.
+ *   - Pointers are host pointers unless the name says "device".
+ *   - No C++ exception crosses this boundary.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef CUPK_H
+#define CUPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status / error codes ---------------------------------------------- */
+#define CUPK_OK 0
+#define CUPK_EMPTY 1          /* aggregate sketch is all zero: the cut is empty */
+#define CUPK_SAMPLE_FAILED 2  /* nonzero aggregate but no bucket verifies       */
+#define CUPK_EINVAL (-1)      /* bad argument; nothing was changed              */
+#define CUPK_ENOMEM (-2)      /* device or pinned-host allocation failed        */
+#define CUPK_EDEVICE (-3)     /* a HIP call failed; see cupk_last_error         */
+#define CUPK_EBUSY (-4)       /* admission refused (serving loop)               */
+
+/* ---- scatter kernel selection ------------------------------------------ */
+#define CUPK_SCATTER_ATOMIC 0 /* plain kernel: one device atomic XOR per word  */
+#define CUPK_SCATTER_STAGED 1 /* vertex-binned, LDS-staged kernel              */
+
+typedef struct cupk_ctx cupk_ctx;
+
+/* One sketch bucket: XOR of indices and XOR of their checksums. */
+typedef struct {
+    uint64_t alpha;
+    uint64_t gamma;
+} cupk_bucket;
+
+/* Options for cupk_sketch_init.  Zero-initialise and set what you need. */
+typedef struct {
+    /* CUPK_SCATTER_ATOMIC or CUPK_SCATTER_STAGED (default: STAGED). */
+    uint32_t scatter_mode;
+    /* Initial capacity of the device update buffers, in updates (default
+     * 1<<20).  Larger batches grow the buffers on demand. */
+    uint32_t max_batch;
+    /* hipStream_t to launch on.  Used when use_given_stream is nonzero (a
+     * NULL stream then means the default stream); otherwise the library
+     * creates and owns a stream. */
+    void *stream;
+    uint32_t use_given_stream;
+    /* Device memory for the sketch, >= cupk_sketch_bytes(V, C, D) bytes,
+     * owned by the caller (e.g. a torch tensor) and kept alive until
+     * cupk_free.  NULL = the library allocates it.  It is zeroed at init. */
+    void *sketch_device_ptr;
+    /* Nonzero: record HIP events around every scatter launch so that
+     * cupk_counters reports the summed kernel time. */
+    uint32_t time_kernels;
+    /* Staged scatter tuning (0 = library default / autotuned value):
+     * vertices per LDS tile and depth rows kept in LDS. */
+    uint32_t tile_vertices;
+    uint32_t lds_rows;
+} cupk_opts;
+
+/* Counters, cumulative since init. */
+typedef struct {
+    uint64_t updates;            /* updates applied                              */
+    uint64_t batches;            /* batches applied                              */
+    uint64_t flagged;            /* updates the device classified as structural  */
+    uint64_t links;              /* forest links (inserts and replacements)      */
+    uint64_t cuts;               /* forest cuts (deleted forest edges)           */
+    uint64_t rounds;             /* replacement rounds run                       */
+    uint64_t sets_reduced;       /* vertex sets / fragments reduced              */
+    uint64_t slabs_reduced;      /* vertex sketches read by set reductions       */
+    uint64_t sample_failed;      /* trees whose sample failed (kept dirty)       */
+    uint64_t scatter_launches;   /* scatter kernel launches                      */
+    double scatter_ms;           /* summed scatter kernel time (time_kernels)    */
+    double bin_ms;               /* summed binning kernel time (time_kernels)    */
+} cupk_counters_t;
+
+/* Bytes of device memory the sketch of (V, C, D) occupies. */
+size_t cupk_sketch_bytes(uint32_t V, uint32_t C, uint32_t D);
+
+/* sketch_init — create a context holding V zeroed vertex sketches of C
+ * columns x D depth buckets (Sec. 2.1 l0 sketches; App. A.1.1: O(log V)
+ * sketches per vertex, each an array of machine words).
+ *   V: vertex count, 2 <= V <= 2^31.
+ *   C: columns; 0 means ceil(log2 V).  1 <= C <= 64.
+ *   D: depth buckets per column; 0 means 2*ceil(log2 V).  2 <= D <= 64.
+ *   seed: 64-bit master seed of the column hashes.
+ *   opts: NULL for defaults.
+ * On success *out owns device memory for the sketch (unless
+ * opts->sketch_device_ptr is given), label and parent arrays and staging
+ * buffers, and a host spanning forest of the empty graph.
+ * Errors: CUPK_EINVAL (bad sizes), CUPK_ENOMEM, CUPK_EDEVICE. */
+int cupk_sketch_init(cupk_ctx **out, uint32_t V, uint32_t C, uint32_t D,
+                     uint64_t seed, const cupk_opts *opts);
+
+/* Release everything the context owns.  NULL is a no-op. */
+void cupk_free(cupk_ctx *ctx);
+
+/* apply_updates — apply a batch of n stream updates ((u_i, v_i), +-1)
+ * in order (App. A.1 graph-stream model; fully-dynamic connectivity problem,
+ * App. A.1.2).  u, v, is_delete are host arrays of n elements, read before
+ * return; endpoints may come in either order.
+ * Every update toggles its edge in both endpoints' sketches (over F2 an
+ * insert and a delete are the same operation; cutset Update, Sec. 2.2.1).
+ * The forest is then brought up to date: inserts joining two trees link
+ * them, deletes of forest edges cut them, and at the end of the batch
+ * replacement rounds reconnect broken trees from their aggregate sketches.
+ * After return, cupk_connected reflects all n updates.
+ * Validation is all-or-nothing: u == v or an endpoint >= V returns
+ * CUPK_EINVAL and applies nothing.  Inserting a present edge or deleting an
+ * absent one breaks the stream contract (App. A.1) and is not detected.
+ * n == 0 is a no-op. */
+int cupk_apply_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
+                       const uint8_t *is_delete, size_t n);
+
+/* apply_updates_device — same as cupk_apply_updates for a batch already in
+ * device memory: n packed words  lo32 = one endpoint, bits 32..62 = the
+ * other endpoint, bit 63 = 1 for a delete.  The buffer is owned by the
+ * caller and only read; it must stay valid until the next call on ctx
+ * returns (the call synchronises before returning).  Invalid entries make
+ * the whole batch fail with CUPK_EINVAL with nothing applied. */
+int cupk_apply_updates_device(cupk_ctx *ctx, const uint64_t *d_packed, size_t n);
+
+/* component_sketch — aggregate sketch of a vertex set U: XOR of the
+ * members' sketches (App. A.1.1 sketch addition; the cutset's component
+ * aggregate, Sec. 2.2.1).  By cancellation it equals the sketch of the cut
+ * of U.  verts: n distinct vertex ids (host); duplicates cancel in pairs.
+ * out: C*D buckets (host), canonical order.  Reflects all applied updates.
+ * Errors: CUPK_EINVAL for an id >= V. */
+int cupk_component_sketch(cupk_ctx *ctx, const uint32_t *verts, size_t n,
+                          cupk_bucket *out);
+
+/* component_sketch_batch — k aggregate sketches in one launch.
+ * offsets: k+1 host offsets into verts (CSR); set j is
+ * verts[offsets[j] .. offsets[j+1]).  out: k*C*D buckets (host), set j at
+ * out[j*C*D].  Sets may have any sizes, including 0. */
+int cupk_component_sketch_batch(cupk_ctx *ctx, const uint64_t *offsets, size_t k,
+                                const uint32_t *verts, cupk_bucket *out);
+
+/* sample_cut_edge — query one aggregate sketch (cutset Query, Sec. 2.2.1;
+ * l0 sampling, App. A.1.1).  sketch: C*D buckets (host), canonical order.
+ * Returns CUPK_OK with *u < *v the edge of the first good bucket,
+ * CUPK_EMPTY when every word is zero, CUPK_SAMPLE_FAILED otherwise. */
+int cupk_sample_cut_edge(cupk_ctx *ctx, const cupk_bucket *sketch, uint32_t *u,
+                         uint32_t *v);
+
+/* sample_cut_edge_batch — k queries in one launch; status[j], u[j], v[j]
+ * receive the result of sketch j (host arrays of k). */
+int cupk_sample_cut_edge_batch(cupk_ctx *ctx, const cupk_bucket *sketches, size_t k,
+                               int32_t *status, uint32_t *u, uint32_t *v);
+
+/* connected — Connected(u, v) on the current graph (Sec. 2.1): 1 or 0 after
+ * every update applied so far; negative on error (CUPK_EINVAL for ids
+ * >= V). */
+int cupk_connected(cupk_ctx *ctx, uint32_t u, uint32_t v);
+
+/* ---- introspection (parity, tests, benchmarks) ------------------------- */
+
+/* Sketches of vertices w0 .. w0+nv-1 into out (host, nv*C*D buckets,
+ * canonical order per vertex). */
+int cupk_get_sketch(cupk_ctx *ctx, uint32_t w0, uint32_t nv, cupk_bucket *out);
+
+/* Order-independent digest of the whole sketch:
+ *   sum over (w,c,d) of mix(alpha ^ rotl(gamma, 32) ^ mix(((w*C+c)*D+d) ^ seed))
+ * modulo 2^64, mix = SplitMix64 finalizer. */
+int cupk_digest(cupk_ctx *ctx, uint64_t *out);
+
+/* Number of trees in the forest (= components, w.h.p.). */
+int cupk_num_components(cupk_ctx *ctx, uint64_t *out);
+
+/* Forest edges: writes up to cap pairs (u < v) and sets *n to the number of
+ * forest edges.  Returns CUPK_EINVAL if cap < *n (nothing written then). */
+int cupk_forest_edges(cupk_ctx *ctx, uint32_t *u, uint32_t *v, size_t cap, size_t *n);
+
+/* Component label of every vertex (host array of V).  Two vertices are
+ * connected iff their labels are equal. */
+int cupk_component_labels(cupk_ctx *ctx, uint32_t *out);
+
+int cupk_counters(cupk_ctx *ctx, cupk_counters_t *out);
+
+/* Wait for all work the context queued. */
+int cupk_sync(cupk_ctx *ctx);
+
+/* Static text of a return code. */
+const char *cupk_strerror(int code);
+
+/* Text of the last error on ctx (empty if none); with ctx == NULL, the
+ * text of the last failed cupk_sketch_init on this thread. */
+const char *cupk_last_error(cupk_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUPK_H */

@@ -1,0 +1,286 @@
+"""ctypes binding of ``libcupk.so`` (argument marshalling only).
+
+Every step of the hot path runs in the library's HIP kernels and its C++
+runtime; this module only converts numpy arrays / torch tensors to pointers
+and sizes.  PyTorch provides the device memory of the sketch and the stream
+the library launches on.  If the shared library is missing the import
+fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+# torch first: its HIP runtime (loaded by name "libamdhip64.so") then
+# satisfies this library's dependency on soname "libamdhip64.so.7", so the
+# process holds one HIP runtime.  Loading ours first would load a second
+# copy, and the two would compete for the device.
+try:
+    import torch as _torch_mod  # noqa: F401
+except Exception:  # pragma: no cover - torch is part of the image
+    _torch_mod = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcupk.so")
+
+OK, EMPTY, SAMPLE_FAILED = 0, 1, 2
+EINVAL, ENOMEM, EDEVICE, EBUSY = -1, -2, -3, -4
+SCATTER_ATOMIC, SCATTER_STAGED = 0, 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
+        "(hipcc --offload-arch=gfx950).  There is no CPU fallback.")
+
+
+class cupk_bucket(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_uint64), ("gamma", ctypes.c_uint64)]
+
+
+class cupk_opts(ctypes.Structure):
+    _fields_ = [
+        ("scatter_mode", ctypes.c_uint32),
+        ("max_batch", ctypes.c_uint32),
+        ("stream", ctypes.c_void_p),
+        ("use_given_stream", ctypes.c_uint32),
+        ("sketch_device_ptr", ctypes.c_void_p),
+        ("time_kernels", ctypes.c_uint32),
+        ("tile_vertices", ctypes.c_uint32),
+        ("lds_rows", ctypes.c_uint32),
+    ]
+
+
+class cupk_counters_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "updates", "batches", "flagged", "links", "cuts", "rounds", "sets_reduced",
+        "slabs_reduced", "sample_failed", "scatter_launches")] + [
+        ("scatter_ms", ctypes.c_double), ("bin_ms", ctypes.c_double)]
+
+
+def _load():
+    L = ctypes.CDLL(LIB_PATH)
+    p, u32, u64, sz, i32 = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64,
+                            ctypes.c_size_t, ctypes.c_int32)
+    sig = {
+        "cupk_sketch_bytes": (sz, [u32, u32, u32]),
+        "cupk_sketch_init": (ctypes.c_int, [ctypes.POINTER(p), u32, u32, u32, u64,
+                                            ctypes.POINTER(cupk_opts)]),
+        "cupk_free": (None, [p]),
+        "cupk_apply_updates": (ctypes.c_int, [p, p, p, p, sz]),
+        "cupk_apply_updates_device": (ctypes.c_int, [p, p, sz]),
+        "cupk_component_sketch": (ctypes.c_int, [p, p, sz, p]),
+        "cupk_component_sketch_batch": (ctypes.c_int, [p, p, sz, p, p]),
+        "cupk_sample_cut_edge": (ctypes.c_int, [p, p, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+        "cupk_sample_cut_edge_batch": (ctypes.c_int, [p, p, sz, p, p, p]),
+        "cupk_connected": (ctypes.c_int, [p, u32, u32]),
+        "cupk_get_sketch": (ctypes.c_int, [p, u32, u32, p]),
+        "cupk_digest": (ctypes.c_int, [p, ctypes.POINTER(u64)]),
+        "cupk_num_components": (ctypes.c_int, [p, ctypes.POINTER(u64)]),
+        "cupk_forest_edges": (ctypes.c_int, [p, p, p, sz, ctypes.POINTER(sz)]),
+        "cupk_component_labels": (ctypes.c_int, [p, p]),
+        "cupk_counters": (ctypes.c_int, [p, ctypes.POINTER(cupk_counters_t)]),
+        "cupk_sync": (ctypes.c_int, [p]),
+        "cupk_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "cupk_last_error": (ctypes.c_char_p, [p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+class CupkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cupk error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def pack_updates(u, v, is_delete) -> np.ndarray:
+    """Device update format: lo32 = u, bits 32..62 = v, bit 63 = delete."""
+    u = np.asarray(u, dtype=np.uint64)
+    v = np.asarray(v, dtype=np.uint64)
+    d = np.asarray(is_delete, dtype=np.uint64)
+    return (u | (v << np.uint64(32)) | (d << np.uint64(63))).astype(np.uint64)
+
+
+def _torch():
+    try:
+        import torch
+    except Exception:  # pragma: no cover - torch is part of the image
+        return None
+    return torch
+
+
+class Context:
+    """One resident sketch + host forest (``cupk_sketch_init``)."""
+
+    def __init__(self, V, C=0, D=0, seed=0, scatter_mode=SCATTER_STAGED, max_batch=0,
+                 stream=None, use_torch_memory=True, time_kernels=False, tile_vertices=0,
+                 lds_rows=0):
+        self._h = None
+        self._sk_tensor = None
+        opts = cupk_opts()
+        opts.scatter_mode = scatter_mode
+        opts.max_batch = max_batch
+        opts.time_kernels = 1 if time_kernels else 0
+        opts.tile_vertices = tile_vertices
+        opts.lds_rows = lds_rows
+        torch = _torch()
+        if stream is None and torch is not None and torch.cuda.is_available():
+            # launch on torch's current stream so that torch-produced device
+            # batches are ordered before the library's kernels
+            stream = torch.cuda.current_stream().cuda_stream
+        if stream is not None:
+            opts.stream = stream
+            opts.use_given_stream = 1
+        L = 1
+        while (1 << L) < V:
+            L += 1
+        self.V = V
+        self.C = C or L
+        self.D = D or 2 * L
+        self.seed = seed
+        if use_torch_memory and torch is not None and torch.cuda.is_available():
+            nbytes = lib.cupk_sketch_bytes(V, self.C, self.D)
+            self._sk_tensor = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda")
+            opts.sketch_device_ptr = self._sk_tensor.data_ptr()
+        h = ctypes.c_void_p()
+        rc = lib.cupk_sketch_init(ctypes.byref(h), V, C, D, seed, ctypes.byref(opts))
+        if rc != OK:
+            raise CupkError(rc, lib.cupk_strerror(rc).decode() + ": " +
+                            lib.cupk_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib.cupk_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc < 0:
+            raise CupkError(rc, lib.cupk_last_error(self._h).decode() or
+                            lib.cupk_strerror(rc).decode())
+        return rc
+
+    @property
+    def sketch_tensor(self):
+        """The torch tensor holding the device sketch (when torch memory is used)."""
+        return self._sk_tensor
+
+    # -- hot path -------------------------------------------------------------
+    def apply_updates(self, u, v, is_delete):
+        u = np.ascontiguousarray(u, dtype=np.uint32)
+        v = np.ascontiguousarray(v, dtype=np.uint32)
+        d = np.ascontiguousarray(is_delete, dtype=np.uint8)
+        n = u.shape[0]
+        if v.shape[0] != n or d.shape[0] != n:
+            raise ValueError("u, v, is_delete must have equal length")
+        return self._check(lib.cupk_apply_updates(self._h, _ptr(u), _ptr(v), _ptr(d), n))
+
+    def apply_updates_device(self, packed, n=None):
+        """packed: a cuda int64/uint64 tensor (or a raw device address with n)."""
+        if isinstance(packed, int):
+            ptr = packed
+            assert n is not None
+        else:
+            assert packed.is_cuda and packed.element_size() == 8 and packed.is_contiguous()
+            ptr = packed.data_ptr()
+            n = packed.numel() if n is None else n
+        return self._check(lib.cupk_apply_updates_device(self._h, ctypes.c_void_p(ptr), n))
+
+    def component_sketch(self, verts):
+        verts = np.ascontiguousarray(verts, dtype=np.uint32)
+        out = np.zeros(self.C * self.D * 2, dtype=np.uint64)
+        self._check(lib.cupk_component_sketch(self._h, _ptr(verts), verts.shape[0], _ptr(out)))
+        out = out.reshape(self.C, self.D, 2)
+        return out[..., 0].copy(), out[..., 1].copy()
+
+    def component_sketch_batch(self, sets):
+        sizes = [len(s) for s in sets]
+        offs = np.zeros(len(sets) + 1, dtype=np.uint64)
+        offs[1:] = np.cumsum(sizes)
+        verts = (np.ascontiguousarray(np.concatenate([np.asarray(s, np.uint32) for s in sets]))
+                 if sets and offs[-1] else np.zeros(1, np.uint32))
+        k = len(sets)
+        out = np.zeros(max(1, k) * self.C * self.D * 2, dtype=np.uint64)
+        self._check(lib.cupk_component_sketch_batch(self._h, _ptr(offs), k, _ptr(verts),
+                                                     _ptr(out)))
+        out = out[: k * self.C * self.D * 2].reshape(k, self.C, self.D, 2)
+        return out[..., 0].copy(), out[..., 1].copy()
+
+    def sample_cut_edge(self, alpha, gamma):
+        buf = np.empty((self.C, self.D, 2), dtype=np.uint64)
+        buf[..., 0] = np.asarray(alpha, np.uint64).reshape(self.C, self.D)
+        buf[..., 1] = np.asarray(gamma, np.uint64).reshape(self.C, self.D)
+        uu, vv = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        st = self._check(lib.cupk_sample_cut_edge(self._h, _ptr(buf), ctypes.byref(uu),
+                                                  ctypes.byref(vv)))
+        return (st, uu.value, vv.value) if st == OK else (st, 0, 0)
+
+    def sample_cut_edge_batch(self, alpha, gamma):
+        alpha = np.asarray(alpha, np.uint64).reshape(-1, self.C, self.D)
+        k = alpha.shape[0]
+        buf = np.empty((k, self.C, self.D, 2), dtype=np.uint64)
+        buf[..., 0] = alpha
+        buf[..., 1] = np.asarray(gamma, np.uint64).reshape(k, self.C, self.D)
+        st = np.zeros(max(1, k), np.int32)
+        u = np.zeros(max(1, k), np.uint32)
+        v = np.zeros(max(1, k), np.uint32)
+        self._check(lib.cupk_sample_cut_edge_batch(self._h, _ptr(buf), k, _ptr(st), _ptr(u),
+                                                   _ptr(v)))
+        return st[:k], u[:k], v[:k]
+
+    def connected(self, u, v) -> bool:
+        return bool(self._check(lib.cupk_connected(self._h, u, v)))
+
+    # -- introspection ------------------------------------------------------------
+    def get_sketch(self, w0=0, nv=None):
+        nv = self.V - w0 if nv is None else nv
+        out = np.zeros(max(1, nv) * self.C * self.D * 2, dtype=np.uint64)
+        self._check(lib.cupk_get_sketch(self._h, w0, nv, _ptr(out)))
+        out = out[: nv * self.C * self.D * 2].reshape(nv, self.C, self.D, 2)
+        return out[..., 0].copy(), out[..., 1].copy()
+
+    def digest(self) -> int:
+        o = ctypes.c_uint64(0)
+        self._check(lib.cupk_digest(self._h, ctypes.byref(o)))
+        return o.value
+
+    def num_components(self) -> int:
+        o = ctypes.c_uint64(0)
+        self._check(lib.cupk_num_components(self._h, ctypes.byref(o)))
+        return o.value
+
+    def forest_edges(self):
+        n = ctypes.c_size_t(0)
+        cap = self.V
+        u = np.zeros(cap, np.uint32)
+        v = np.zeros(cap, np.uint32)
+        self._check(lib.cupk_forest_edges(self._h, _ptr(u), _ptr(v), cap, ctypes.byref(n)))
+        return sorted(zip(u[: n.value].tolist(), v[: n.value].tolist()))
+
+    def component_labels(self):
+        out = np.zeros(self.V, np.uint32)
+        self._check(lib.cupk_component_labels(self._h, _ptr(out)))
+        return out
+
+    def counters(self) -> dict:
+        c = cupk_counters_t()
+        self._check(lib.cupk_counters(self._h, ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in cupk_counters_t._fields_}
+
+    def sync(self):
+        self._check(lib.cupk_sync(self._h))

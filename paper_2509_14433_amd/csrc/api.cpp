@@ -1,0 +1,933 @@
+// C ABI, context and per-batch orchestration of the sketch hot path.
+//
+// One batch (cupk_apply_updates / cupk_apply_updates_device):
+//   1. upload the forest's label / parent arrays if they changed;
+//   2. classify (validate, flag structural candidates, count tile records);
+//   3. scatter: plain atomic kernel, or bin + LDS-staged kernel;
+//   4. meanwhile on the host: read the flagged updates (copy stream), sort
+//      them back into stream order and apply links / cuts to the forest;
+//   5. replacement rounds for trees broken by cuts: segmented XOR reduction
+//      of every dirty tree in one launch, verify/sample in one launch, host
+//      links in ascending order of each tree's smallest vertex; merged trees
+//      are reduced from their fragments' sketches in the next round.
+// The batch semantics match the tests' CPU oracle bit for bit: same sketch,
+// same forest edges, same samples.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cupk.h"
+#include "forest.hpp"
+#include "kernels.hpp"
+
+using namespace cupk;
+
+namespace {
+
+// Message of the last failed cupk_sketch_init (no context survives it).
+thread_local std::string g_init_error;
+
+constexpr uint32_t kRedChunk = 64;          // members per reduction work item
+constexpr size_t kMaxBatchPerLaunch = 1u << 28;
+constexpr int kTimerRing = 64;
+
+// SplitMix64 (Steele, Lea, Flood 2014): state += golden gamma, then the
+// Stafford "Mix13" finalizer.
+uint64_t sm64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint32_t ceil_log2(uint32_t V)
+{
+    uint32_t L = 0;
+    while ((uint64_t(1) << L) < V) L++;
+    return L < 1 ? 1 : L;
+}
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+};
+template <class T>
+struct HostBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace
+
+struct cupk_ctx {
+    uint32_t V = 0, C = 0, D = 0;
+    uint64_t S = 0;
+    uint64_t seeds[64] = {};
+    uint32_t W = 0;  // words per vertex slab = 2*C*D
+    cupk_opts opts = {};
+    hipStream_t s = nullptr, cs = nullptr;
+    bool own_stream = false;
+    hipEvent_t ev_cls = nullptr, ev_hdr = nullptr;
+    struct TimerSlot {
+        hipEvent_t t0, tb, t1;
+        bool busy;
+    };
+    TimerSlot timers[kTimerRing] = {};
+    int timer_head = 0;
+
+    uint64_t *d_sk = nullptr;
+    bool own_sk = false;
+    uint64_t *d_seeds = nullptr;
+    uint32_t *d_lbl = nullptr, *d_par = nullptr;
+    uint32_t *h_lbl = nullptr, *h_par = nullptr;
+    bool forest_dev_stale = false;
+
+    // batch buffers
+    DevBuf<uint64_t> d_upd;
+    HostBuf<uint64_t> h_upd;
+    uint32_t *d_hdr = nullptr, *h_hdr = nullptr;
+    DevBuf<uint32_t> d_fpos;
+    DevBuf<uint64_t> d_fupd;
+    HostBuf<uint32_t> h_fpos;
+    HostBuf<uint64_t> h_fupd;
+
+    // staged scatter
+    uint32_t tile_shift = 5, rows = 8, chunk = 4096, ntiles = 0;
+    DevBuf<uint32_t> d_tcnt, d_toff, d_tcur, d_items;
+    DevBuf<uint64_t> d_bins;
+    uint32_t *d_nitems = nullptr;
+
+    // reductions / samples
+    DevBuf<uint32_t> d_ridx, d_ritems;
+    HostBuf<uint32_t> h_ridx, h_ritems;
+    DevBuf<uint64_t> d_sig[2];
+    DevBuf<int32_t> d_res;
+    HostBuf<int32_t> h_res;
+    DevBuf<uint64_t> d_tmp;
+    uint64_t *d_misc = nullptr, *h_misc = nullptr;
+
+    Forest forest;
+    cupk_counters_t ctr = {};
+    std::string err;
+
+    int fail(hipError_t e, const char *what, int line)
+    {
+        char buf[256];
+        snprintf(buf, sizeof buf, "%s failed at api.cpp:%d: %s", what, line, hipGetErrorString(e));
+        err = buf;
+        return e == hipErrorOutOfMemory ? CUPK_ENOMEM : CUPK_EDEVICE;
+    }
+    int invalid(const char *why)
+    {
+        err = why;
+        return CUPK_EINVAL;
+    }
+};
+
+#define HIPCHK(x)                                                   \
+    do {                                                            \
+        hipError_t e_ = (x);                                        \
+        if (e_ != hipSuccess) return ctx->fail(e_, #x, __LINE__);   \
+    } while (0)
+
+namespace {
+
+template <class T>
+hipError_t grow(DevBuf<T> &b, size_t need)
+{
+    if (need <= b.cap) return hipSuccess;
+    size_t cap = std::max(need, b.cap + b.cap / 2);
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc((void **)&b.p, cap * sizeof(T));
+    if (e != hipSuccess) return e;
+    b.cap = cap;
+    return hipSuccess;
+}
+
+template <class T>
+hipError_t grow(HostBuf<T> &b, size_t need)
+{
+    if (need <= b.cap) return hipSuccess;
+    size_t cap = std::max(need, b.cap + b.cap / 2);
+    if (b.p) {
+        hipError_t e = hipHostFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipHostMalloc((void **)&b.p, cap * sizeof(T), hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    b.cap = cap;
+    return hipSuccess;
+}
+
+template <class T>
+void release(DevBuf<T> &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+template <class T>
+void release(HostBuf<T> &b)
+{
+    if (b.p) (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+DevSketch dev_sketch(cupk_ctx *ctx)
+{
+    DevSketch d;
+    d.b = ctx->d_sk;
+    d.seeds = ctx->d_seeds;
+    d.V = ctx->V;
+    d.C = ctx->C;
+    d.D = ctx->D;
+    return d;
+}
+
+// Harvest finished kernel timers; with `all`, wait for every pending one.
+int harvest_timers(cupk_ctx *ctx, bool all)
+{
+    for (int k = 0; k < kTimerRing; k++) {
+        auto &t = ctx->timers[k];
+        if (!t.busy) continue;
+        if (all) {
+            HIPCHK(hipEventSynchronize(t.t1));
+        } else if (hipEventQuery(t.t1) != hipSuccess) {
+            continue;
+        }
+        float ms_b = 0.f, ms_s = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms_b, t.t0, t.tb));
+        HIPCHK(hipEventElapsedTime(&ms_s, t.tb, t.t1));
+        ctx->ctr.bin_ms += ms_b;
+        ctx->ctr.scatter_ms += ms_s;
+        t.busy = false;
+    }
+    return CUPK_OK;
+}
+
+int upload_forest(cupk_ctx *ctx)
+{
+    if (!ctx->forest_dev_stale) return CUPK_OK;
+    const size_t bytes = (size_t)ctx->V * sizeof(uint32_t);
+    HIPCHK(hipMemcpyAsync(ctx->d_lbl, ctx->h_lbl, bytes, hipMemcpyHostToDevice, ctx->s));
+    HIPCHK(hipMemcpyAsync(ctx->d_par, ctx->h_par, bytes, hipMemcpyHostToDevice, ctx->s));
+    ctx->forest_dev_stale = false;
+    return CUPK_OK;
+}
+
+// One replacement-search set: a tree of the forest, reduced either from its
+// vertices or from fragment sketches of the previous round.
+struct RoundSet {
+    uint32_t label;
+    uint32_t minv;
+    uint32_t size;
+};
+
+// Reduce k sets into d_sig[slot] (internal layout, W words per set) and
+// sample them into h_res.  Vertex sets come as (members, offsets) over
+// vertex ids; fragment sets as (members, offsets) over slots of
+// d_sig[1-slot].  Set order: vertex sets first, then fragment sets.
+int reduce_and_sample(cupk_ctx *ctx, int slot, const std::vector<uint32_t> &vmem,
+                      const std::vector<uint32_t> &voff, const std::vector<uint32_t> &fmem,
+                      const std::vector<uint32_t> &foff)
+{
+    const uint32_t kv = voff.empty() ? 0 : (uint32_t)voff.size() - 1;
+    const uint32_t kf = foff.empty() ? 0 : (uint32_t)foff.size() - 1;
+    const uint32_t k = kv + kf;
+    if (k == 0) return CUPK_OK;
+    const uint32_t W = ctx->W;
+    HIPCHK(grow(ctx->d_sig[slot], (size_t)k * W));
+    HIPCHK(grow(ctx->d_res, (size_t)3 * k));
+    HIPCHK(grow(ctx->h_res, (size_t)3 * k));
+    // work items
+    std::vector<uint32_t> items;
+    auto add_items = [&](const std::vector<uint32_t> &off, uint32_t set0, uint32_t mem0) {
+        for (size_t j = 0; j + 1 < off.size(); j++)
+            for (uint32_t b = off[j]; b < off[j + 1]; b += kRedChunk) {
+                items.push_back(set0 + (uint32_t)j);
+                items.push_back(mem0 + b);
+                items.push_back(mem0 + std::min(off[j + 1], b + kRedChunk));
+            }
+    };
+    add_items(voff, 0, 0);
+    const size_t nvi = items.size() / 3;
+    add_items(foff, kv, (uint32_t)vmem.size());
+    const size_t nitems = items.size() / 3;
+    const size_t nmem = vmem.size() + fmem.size();
+    HIPCHK(grow(ctx->h_ridx, nmem + 1));
+    HIPCHK(grow(ctx->d_ridx, nmem + 1));
+    HIPCHK(grow(ctx->h_ritems, items.size() + 1));
+    HIPCHK(grow(ctx->d_ritems, items.size() + 1));
+    std::copy(vmem.begin(), vmem.end(), ctx->h_ridx.p);
+    std::copy(fmem.begin(), fmem.end(), ctx->h_ridx.p + vmem.size());
+    std::copy(items.begin(), items.end(), ctx->h_ritems.p);
+    if (nmem)
+        HIPCHK(hipMemcpyAsync(ctx->d_ridx.p, ctx->h_ridx.p, nmem * 4, hipMemcpyHostToDevice,
+                              ctx->s));
+    if (!items.empty())
+        HIPCHK(hipMemcpyAsync(ctx->d_ritems.p, ctx->h_ritems.p, items.size() * 4,
+                              hipMemcpyHostToDevice, ctx->s));
+    uint64_t *sig = ctx->d_sig[slot].p;
+    HIPCHK(launch_zero(ctx->s, sig, (size_t)k * W));
+    if (nvi)
+        HIPCHK(launch_reduce(ctx->s, ctx->d_sk, W, ctx->d_ridx.p, ctx->d_ritems.p, (uint32_t)nvi,
+                             sig));
+    if (nitems > nvi)
+        HIPCHK(launch_reduce(ctx->s, ctx->d_sig[1 - slot].p, W, ctx->d_ridx.p,
+                             ctx->d_ritems.p + 3 * nvi, (uint32_t)(nitems - nvi), sig));
+    HIPCHK(launch_sample(ctx->s, sig, k, ctx->V, ctx->C, ctx->D, 1, ctx->C, W, ctx->d_seeds,
+                         ctx->d_res.p));
+    HIPCHK(hipMemcpyAsync(ctx->h_res.p, ctx->d_res.p, (size_t)3 * k * 4, hipMemcpyDeviceToHost,
+                          ctx->s));
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    ctx->ctr.sets_reduced += k;
+    ctx->ctr.slabs_reduced += nmem;
+    return CUPK_OK;
+}
+
+// Replacement rounds over the dirty trees (see file header).
+int run_rounds(cupk_ctx *ctx)
+{
+    Forest &F = ctx->forest;
+    std::vector<uint32_t> labels = F.dirty_labels();
+    if (labels.empty()) return CUPK_OK;
+
+    // round state: sets in sampling order
+    std::vector<RoundSet> sets;
+    std::vector<uint32_t> vmem, voff, fmem, foff;
+    std::vector<std::pair<uint32_t, size_t>> order;  // (minv, index)
+
+    // first round: every dirty tree from its vertices
+    {
+        std::vector<std::vector<uint32_t>> lists(labels.size());
+        std::vector<RoundSet> tmp(labels.size());
+        for (size_t i = 0; i < labels.size(); i++) {
+            const uint32_t mn = F.collect(labels[i], lists[i]);
+            tmp[i] = {labels[i], mn, (uint32_t)lists[i].size()};
+        }
+        order.clear();
+        for (size_t i = 0; i < tmp.size(); i++) order.push_back({tmp[i].minv, i});
+        std::sort(order.begin(), order.end());
+        voff.push_back(0);
+        for (auto &o : order) {
+            sets.push_back(tmp[o.second]);
+            vmem.insert(vmem.end(), lists[o.second].begin(), lists[o.second].end());
+            voff.push_back((uint32_t)vmem.size());
+        }
+    }
+    int slot = 0;
+    for (;;) {
+        ctx->ctr.rounds++;
+        int rc = reduce_and_sample(ctx, slot, vmem, voff, fmem, foff);
+        if (rc != CUPK_OK) return rc;
+        const int32_t *res = ctx->h_res.p;
+        const size_t k = sets.size();
+        // Link in ascending order of smallest vertex.  Sets are stored with
+        // vertex-reduced sets first, then fragment sets, each group sorted;
+        // merge the two orders.
+        const size_t kv = voff.empty() ? 0 : voff.size() - 1;
+        std::vector<size_t> ord(k);
+        for (size_t i = 0; i < k; i++) ord[i] = i;
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](size_t a, size_t b) { return sets[a].minv < sets[b].minv; });
+        (void)kv;
+        std::vector<uint32_t> linked_x;
+        for (size_t oi = 0; oi < k; oi++) {
+            const size_t i = ord[oi];
+            if (res[3 * i] != CUPK_OK) continue;
+            const uint32_t x = (uint32_t)res[3 * i + 1], y = (uint32_t)res[3 * i + 2];
+            if (!F.same_tree(x, y)) {
+                F.link(x, y);
+                ctx->ctr.links++;
+                linked_x.push_back(x);
+            }
+        }
+        for (size_t i = 0; i < k; i++) {
+            const int st = res[3 * i];
+            if (st == CUPK_EMPTY) {
+                // a whole component: clean, unless it was merged this round
+                const uint32_t l = F.label(sets[i].minv);
+                if (l == sets[i].label && F.tree_size(l) == sets[i].size) F.clear_dirty(l);
+            } else if (st == CUPK_SAMPLE_FAILED) {
+                ctx->ctr.sample_failed++;
+            }
+        }
+        if (linked_x.empty()) break;
+
+        // next round: trees that took part in a link, reduced from the
+        // fragments of this round when they consist of fragments only
+        std::vector<uint32_t> nl;
+        for (uint32_t x : linked_x) nl.push_back(F.label(x));
+        std::sort(nl.begin(), nl.end());
+        nl.erase(std::unique(nl.begin(), nl.end()), nl.end());
+        // fragments per label
+        std::vector<std::pair<uint32_t, uint32_t>> frag;  // (label, set index)
+        for (size_t i = 0; i < k; i++) frag.push_back({F.label(sets[i].minv), (uint32_t)i});
+        std::sort(frag.begin(), frag.end());
+        struct Group {
+            uint32_t label, minv, size;
+            std::vector<uint32_t> frags;
+            bool from_frags;
+        };
+        std::vector<Group> groups;
+        for (uint32_t l : nl) {
+            Group g{l, 0xffffffffu, 0, {}, true};
+            auto it = std::lower_bound(frag.begin(), frag.end(), std::make_pair(l, 0u));
+            uint32_t tot = 0;
+            for (; it != frag.end() && it->first == l; ++it) {
+                g.frags.push_back(it->second);
+                tot += sets[it->second].size;
+                g.minv = std::min(g.minv, sets[it->second].minv);
+            }
+            g.size = F.tree_size(l);
+            if (tot != g.size) {
+                g.from_frags = false;
+                g.frags.clear();
+            }
+            groups.push_back(std::move(g));
+        }
+        std::vector<std::vector<uint32_t>> lists(groups.size());
+        for (size_t gi = 0; gi < groups.size(); gi++)
+            if (!groups[gi].from_frags) groups[gi].minv = F.collect(groups[gi].label, lists[gi]);
+        std::vector<size_t> gord(groups.size());
+        for (size_t i = 0; i < gord.size(); i++) gord[i] = i;
+        std::sort(gord.begin(), gord.end(),
+                  [&](size_t a, size_t b) { return groups[a].minv < groups[b].minv; });
+        std::vector<RoundSet> nsets;
+        vmem.clear();
+        voff.clear();
+        fmem.clear();
+        foff.clear();
+        voff.push_back(0);
+        foff.push_back(0);
+        // vertex-reduced groups first, then fragment groups (see
+        // reduce_and_sample); each in ascending smallest-vertex order
+        for (size_t gi : gord)
+            if (!groups[gi].from_frags) {
+                nsets.push_back({groups[gi].label, groups[gi].minv, groups[gi].size});
+                vmem.insert(vmem.end(), lists[gi].begin(), lists[gi].end());
+                voff.push_back((uint32_t)vmem.size());
+            }
+        for (size_t gi : gord)
+            if (groups[gi].from_frags) {
+                nsets.push_back({groups[gi].label, groups[gi].minv, groups[gi].size});
+                fmem.insert(fmem.end(), groups[gi].frags.begin(), groups[gi].frags.end());
+                foff.push_back((uint32_t)fmem.size());
+            }
+        if (voff.size() == 1) voff.clear();
+        if (foff.size() == 1) foff.clear();
+        sets.swap(nsets);
+        slot = 1 - slot;
+    }
+    ctx->forest_dev_stale = true;
+    return CUPK_OK;
+}
+
+// Apply the flagged updates of one batch to the forest, in stream order.
+void apply_flags(cupk_ctx *ctx, uint32_t nflag)
+{
+    Forest &F = ctx->forest;
+    std::vector<std::pair<uint32_t, uint64_t>> fl(nflag);
+    for (uint32_t i = 0; i < nflag; i++) fl[i] = {ctx->h_fpos.p[i], ctx->h_fupd.p[i]};
+    std::sort(fl.begin(), fl.end(),
+              [](const std::pair<uint32_t, uint64_t> &a, const std::pair<uint32_t, uint64_t> &b) {
+                  return a.first < b.first;
+              });
+    bool changed = false;
+    for (auto &f : fl) {
+        const uint64_t p = f.second;
+        uint32_t a = (uint32_t)p, b = (uint32_t)(p >> 32) & 0x7fffffffu;
+        const bool del = (p >> 63) != 0;
+        if (a > b) std::swap(a, b);
+        if (!del) {
+            if (!F.same_tree(a, b)) {
+                F.link(a, b);
+                ctx->ctr.links++;
+                changed = true;
+            }
+        } else if (F.is_edge(a, b)) {
+            F.cut(a, b);
+            ctx->ctr.cuts++;
+            changed = true;
+        }
+    }
+    if (changed) ctx->forest_dev_stale = true;
+}
+
+int ensure_batch_buffers(cupk_ctx *ctx, size_t n)
+{
+    HIPCHK(grow(ctx->d_fpos, n));
+    HIPCHK(grow(ctx->d_fupd, n));
+    HIPCHK(grow(ctx->h_fpos, n));
+    HIPCHK(grow(ctx->h_fupd, n));
+    if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
+        HIPCHK(grow(ctx->d_bins, 2 * n));
+        const size_t icap = 2 * n / ctx->chunk + ctx->ntiles + 1;
+        HIPCHK(grow(ctx->d_items, 2 * icap));
+    }
+    return CUPK_OK;
+}
+
+int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
+{
+    int rc = harvest_timers(ctx, false);
+    if (rc != CUPK_OK) return rc;
+    rc = ensure_batch_buffers(ctx, n);
+    if (rc != CUPK_OK) return rc;
+    rc = upload_forest(ctx);
+    if (rc != CUPK_OK) return rc;
+    const bool staged = ctx->opts.scatter_mode == CUPK_SCATTER_STAGED;
+    HIPCHK(launch_zero32(ctx->s, ctx->d_hdr, HDR_WORDS));
+    if (staged) HIPCHK(launch_zero32(ctx->s, ctx->d_tcnt.p, ctx->ntiles));
+    HIPCHK(launch_classify(ctx->s, d_upd, n, ctx->V, ctx->d_lbl, ctx->d_par, ctx->d_hdr,
+                           ctx->d_fpos.p, ctx->d_fupd.p, staged ? ctx->d_tcnt.p : nullptr,
+                           ctx->tile_shift, ctx->ntiles));
+    HIPCHK(hipEventRecord(ctx->ev_cls, ctx->s));
+    HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->ev_cls, 0));
+    HIPCHK(hipMemcpyAsync(ctx->h_hdr, ctx->d_hdr, HDR_WORDS * 4, hipMemcpyDeviceToHost, ctx->cs));
+    HIPCHK(hipEventRecord(ctx->ev_hdr, ctx->cs));
+
+    // scatter (skipped on device if the batch was rejected)
+    cupk_ctx::TimerSlot *ts = nullptr;
+    if (ctx->opts.time_kernels) {
+        ts = &ctx->timers[ctx->timer_head];
+        ctx->timer_head = (ctx->timer_head + 1) % kTimerRing;
+        if (ts->busy) {
+            HIPCHK(hipEventSynchronize(ts->t1));
+            rc = harvest_timers(ctx, false);
+            if (rc != CUPK_OK) return rc;
+        }
+        HIPCHK(hipEventRecord(ts->t0, ctx->s));
+    }
+    DevSketch sk = dev_sketch(ctx);
+    if (staged) {
+        StagedParams p;
+        p.tile_shift = ctx->tile_shift;
+        p.rows = ctx->rows;
+        p.ntiles = ctx->ntiles;
+        p.chunk = ctx->chunk;
+        p.items_cap = (uint32_t)(2 * (size_t)n / ctx->chunk + ctx->ntiles + 1);
+        HIPCHK(launch_staged(ctx->s, d_upd, n, sk, ctx->d_hdr, p, ctx->d_tcnt.p, ctx->d_toff.p,
+                             ctx->d_tcur.p, ctx->d_bins.p, ctx->d_items.p, ctx->d_nitems,
+                             ts ? ts->tb : nullptr));
+    } else {
+        if (ts) HIPCHK(hipEventRecord(ts->tb, ctx->s));
+        HIPCHK(launch_scatter_atomic(ctx->s, d_upd, n, sk, ctx->d_hdr));
+    }
+    if (ts) {
+        HIPCHK(hipEventRecord(ts->t1, ctx->s));
+        ts->busy = true;
+    }
+
+    // host: flagged updates -> forest, overlapping the scatter
+    HIPCHK(hipEventSynchronize(ctx->ev_hdr));
+    if (ctx->h_hdr[HDR_ERR]) {
+        HIPCHK(hipStreamSynchronize(ctx->s));
+        return ctx->invalid("batch holds an update with u == v or an endpoint >= V");
+    }
+    const uint32_t nflag = ctx->h_hdr[HDR_NFLAG];
+    if (nflag) {
+        HIPCHK(hipMemcpyAsync(ctx->h_fpos.p, ctx->d_fpos.p, (size_t)nflag * 4,
+                              hipMemcpyDeviceToHost, ctx->cs));
+        HIPCHK(hipMemcpyAsync(ctx->h_fupd.p, ctx->d_fupd.p, (size_t)nflag * 8,
+                              hipMemcpyDeviceToHost, ctx->cs));
+        HIPCHK(hipStreamSynchronize(ctx->cs));
+        apply_flags(ctx, nflag);
+    }
+    ctx->ctr.flagged += nflag;
+    ctx->ctr.updates += n;
+    ctx->ctr.batches++;
+    ctx->ctr.scatter_launches++;
+    return run_rounds(ctx);
+}
+
+int apply_device(cupk_ctx *ctx, const uint64_t *d_upd, size_t n)
+{
+    for (size_t off = 0; off < n; off += kMaxBatchPerLaunch) {
+        const uint32_t m = (uint32_t)std::min(kMaxBatchPerLaunch, n - off);
+        int rc = apply_device_one(ctx, d_upd + off, m);
+        if (rc != CUPK_OK) return rc;
+    }
+    return CUPK_OK;
+}
+
+void destroy(cupk_ctx *ctx)
+{
+    if (ctx->s) (void)hipStreamSynchronize(ctx->s);
+    if (ctx->cs) (void)hipStreamSynchronize(ctx->cs);
+    if (ctx->own_sk && ctx->d_sk) (void)hipFree(ctx->d_sk);
+    if (ctx->d_seeds) (void)hipFree(ctx->d_seeds);
+    if (ctx->d_lbl) (void)hipFree(ctx->d_lbl);
+    if (ctx->d_par) (void)hipFree(ctx->d_par);
+    if (ctx->h_lbl) (void)hipHostFree(ctx->h_lbl);
+    if (ctx->h_par) (void)hipHostFree(ctx->h_par);
+    if (ctx->d_hdr) (void)hipFree(ctx->d_hdr);
+    if (ctx->h_hdr) (void)hipHostFree(ctx->h_hdr);
+    if (ctx->d_nitems) (void)hipFree(ctx->d_nitems);
+    if (ctx->d_misc) (void)hipFree(ctx->d_misc);
+    if (ctx->h_misc) (void)hipHostFree(ctx->h_misc);
+    release(ctx->d_upd);
+    release(ctx->h_upd);
+    release(ctx->d_fpos);
+    release(ctx->d_fupd);
+    release(ctx->h_fpos);
+    release(ctx->h_fupd);
+    release(ctx->d_tcnt);
+    release(ctx->d_toff);
+    release(ctx->d_tcur);
+    release(ctx->d_items);
+    release(ctx->d_bins);
+    release(ctx->d_ridx);
+    release(ctx->d_ritems);
+    release(ctx->h_ridx);
+    release(ctx->h_ritems);
+    release(ctx->d_sig[0]);
+    release(ctx->d_sig[1]);
+    release(ctx->d_res);
+    release(ctx->h_res);
+    release(ctx->d_tmp);
+    for (auto &t : ctx->timers) {
+        if (t.t0) (void)hipEventDestroy(t.t0);
+        if (t.tb) (void)hipEventDestroy(t.tb);
+        if (t.t1) (void)hipEventDestroy(t.t1);
+    }
+    if (ctx->ev_cls) (void)hipEventDestroy(ctx->ev_cls);
+    if (ctx->ev_hdr) (void)hipEventDestroy(ctx->ev_hdr);
+    if (ctx->cs) (void)hipStreamDestroy(ctx->cs);
+    if (ctx->own_stream && ctx->s) (void)hipStreamDestroy(ctx->s);
+    delete ctx;
+}
+
+int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
+{
+    const uint32_t V = ctx->V, C = ctx->C, D = ctx->D;
+    if (opts) ctx->opts = *opts;
+    else ctx->opts.scatter_mode = CUPK_SCATTER_STAGED;
+    if (ctx->opts.scatter_mode > CUPK_SCATTER_STAGED) return ctx->invalid("unknown scatter_mode");
+    uint64_t st = ctx->S;
+    for (uint32_t c = 0; c < C; c++) {
+        st += 0x9E3779B97F4A7C15ull;
+        ctx->seeds[c] = sm64_mix(st);
+    }
+    ctx->W = 2 * C * D;
+    if (ctx->opts.use_given_stream) {
+        ctx->s = (hipStream_t)ctx->opts.stream;
+    } else {
+        HIPCHK(hipStreamCreateWithFlags(&ctx->s, hipStreamNonBlocking));
+        ctx->own_stream = true;
+    }
+    HIPCHK(hipStreamCreateWithFlags(&ctx->cs, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_cls, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_hdr, hipEventDisableTiming));
+    if (ctx->opts.time_kernels)
+        for (auto &t : ctx->timers) {
+            HIPCHK(hipEventCreate(&t.t0));
+            HIPCHK(hipEventCreate(&t.tb));
+            HIPCHK(hipEventCreate(&t.t1));
+        }
+    const size_t sk_bytes = cupk_sketch_bytes(V, C, D);
+    if (ctx->opts.sketch_device_ptr) {
+        ctx->d_sk = (uint64_t *)ctx->opts.sketch_device_ptr;
+    } else {
+        HIPCHK(hipMalloc((void **)&ctx->d_sk, sk_bytes));
+        ctx->own_sk = true;
+    }
+    HIPCHK(launch_zero(ctx->s, ctx->d_sk, sk_bytes / 8));
+    HIPCHK(hipMalloc((void **)&ctx->d_seeds, 64 * 8));
+    HIPCHK(hipMemcpy(ctx->d_seeds, ctx->seeds, 64 * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc((void **)&ctx->d_lbl, (size_t)V * 4));
+    HIPCHK(hipMalloc((void **)&ctx->d_par, (size_t)V * 4));
+    HIPCHK(hipHostMalloc((void **)&ctx->h_lbl, (size_t)V * 4, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&ctx->h_par, (size_t)V * 4, hipHostMallocDefault));
+    HIPCHK(hipMalloc((void **)&ctx->d_hdr, HDR_WORDS * 4));
+    HIPCHK(hipHostMalloc((void **)&ctx->h_hdr, HDR_WORDS * 4, hipHostMallocDefault));
+    HIPCHK(hipMalloc((void **)&ctx->d_nitems, 4));
+    HIPCHK(hipMalloc((void **)&ctx->d_misc, 64));
+    HIPCHK(hipHostMalloc((void **)&ctx->h_misc, 64, hipHostMallocDefault));
+    ctx->forest.init(V, ctx->h_lbl, ctx->h_par);
+    ctx->forest_dev_stale = true;
+
+    // staged scatter geometry: LDS delta of `rows` depth rows x C columns x
+    // 2 words per vertex, at most 64 KiB per block
+    uint32_t rows = ctx->opts.lds_rows ? ctx->opts.lds_rows : 8;
+    rows = std::min(rows, D);
+    uint32_t tv = ctx->opts.tile_vertices;
+    if (tv == 0) {
+        tv = 1;
+        while ((size_t)2 * rows * C * (tv * 2) * 8 <= 65536 && tv < 64) tv *= 2;
+    }
+    uint32_t sh = 0;
+    while ((1u << sh) < tv) sh++;
+    if ((1u << sh) != tv) return ctx->invalid("tile_vertices must be a power of two");
+    if ((size_t)2 * rows * C * tv * 8 > 65536) return ctx->invalid("staged tile exceeds 64 KiB LDS");
+    ctx->tile_shift = sh;
+    ctx->rows = rows;
+    ctx->chunk = 4096;
+    ctx->ntiles = (uint32_t)(((uint64_t)V + tv - 1) >> sh);
+    if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
+        HIPCHK(grow(ctx->d_tcnt, ctx->ntiles + 1));
+        HIPCHK(grow(ctx->d_toff, ctx->ntiles + 1));
+        HIPCHK(grow(ctx->d_tcur, ctx->ntiles + 1));
+    }
+    const size_t mb = ctx->opts.max_batch ? ctx->opts.max_batch : (1u << 20);
+    int rc = ensure_batch_buffers(ctx, mb);
+    if (rc != CUPK_OK) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    return CUPK_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t cupk_sketch_bytes(uint32_t V, uint32_t C, uint32_t D)
+{
+    return (size_t)V * C * D * 2 * sizeof(uint64_t);
+}
+
+int cupk_sketch_init(cupk_ctx **out, uint32_t V, uint32_t C, uint32_t D, uint64_t seed,
+                     const cupk_opts *opts)
+{
+    if (!out) return CUPK_EINVAL;
+    *out = nullptr;
+    if (V < 2 || V > (1u << 31)) return CUPK_EINVAL;
+    const uint32_t L = ceil_log2(V);
+    if (C == 0) C = L;
+    if (D == 0) D = 2 * L;
+    if (C < 1 || C > 64 || D < 2 || D > 64) return CUPK_EINVAL;
+    cupk_ctx *ctx = new (std::nothrow) cupk_ctx();
+    if (!ctx) return CUPK_ENOMEM;
+    ctx->V = V;
+    ctx->C = C;
+    ctx->D = D;
+    ctx->S = seed;
+    int rc = init_impl(ctx, opts);
+    if (rc != CUPK_OK) {
+        g_init_error = ctx->err;
+        destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return CUPK_OK;
+}
+
+void cupk_free(cupk_ctx *ctx)
+{
+    if (ctx) destroy(ctx);
+}
+
+int cupk_apply_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
+                       const uint8_t *is_delete, size_t n)
+{
+    if (!ctx) return CUPK_EINVAL;
+    if (n == 0) return CUPK_OK;
+    if (!u || !v || !is_delete) return ctx->invalid("null array");
+    for (size_t i = 0; i < n; i++)
+        if (u[i] == v[i] || u[i] >= ctx->V || v[i] >= ctx->V)
+            return ctx->invalid("batch holds an update with u == v or an endpoint >= V");
+    HIPCHK(grow(ctx->h_upd, n));
+    HIPCHK(grow(ctx->d_upd, n));
+    // the previous batch's upload from h_upd finished: every call waits for
+    // its classify kernel, which follows the upload on the stream
+    uint64_t *h = ctx->h_upd.p;
+    for (size_t i = 0; i < n; i++)
+        h[i] = (uint64_t)u[i] | ((uint64_t)v[i] << 32) | ((uint64_t)(is_delete[i] != 0) << 63);
+    HIPCHK(hipMemcpyAsync(ctx->d_upd.p, h, n * 8, hipMemcpyHostToDevice, ctx->s));
+    return apply_device(ctx, ctx->d_upd.p, n);
+}
+
+int cupk_apply_updates_device(cupk_ctx *ctx, const uint64_t *d_packed, size_t n)
+{
+    if (!ctx) return CUPK_EINVAL;
+    if (n == 0) return CUPK_OK;
+    if (!d_packed) return ctx->invalid("null device pointer");
+    return apply_device(ctx, d_packed, n);
+}
+
+int cupk_component_sketch_batch(cupk_ctx *ctx, const uint64_t *offsets, size_t k,
+                                const uint32_t *verts, cupk_bucket *out)
+{
+    if (!ctx) return CUPK_EINVAL;
+    if (k == 0) return CUPK_OK;
+    if (!offsets || !out) return ctx->invalid("null array");
+    if (offsets[0] != 0) return ctx->invalid("offsets[0] must be 0");
+    for (size_t j = 0; j < k; j++)
+        if (offsets[j + 1] < offsets[j]) return ctx->invalid("offsets must be non-decreasing");
+    const size_t nv = offsets[k];
+    if (nv && !verts) return ctx->invalid("null verts");
+    if (nv >= (1ull << 32) || k >= (1ull << 31)) return ctx->invalid("too many members");
+    for (size_t i = 0; i < nv; i++)
+        if (verts[i] >= ctx->V) return ctx->invalid("vertex id >= V");
+    std::vector<uint32_t> vmem(verts, verts + nv), voff(k + 1), none;
+    for (size_t j = 0; j <= k; j++) voff[j] = (uint32_t)offsets[j];
+    int rc = reduce_and_sample(ctx, 0, vmem, voff, none, none);
+    if (rc != CUPK_OK) return rc;
+    HIPCHK(grow(ctx->d_tmp, (size_t)k * ctx->W));
+    HIPCHK(launch_to_canonical(ctx->s, ctx->d_sig[0].p, ctx->C, ctx->D, k, ctx->d_tmp.p));
+    HIPCHK(hipMemcpyAsync(out, ctx->d_tmp.p, (size_t)k * ctx->W * 8, hipMemcpyDeviceToHost, ctx->s));
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    return CUPK_OK;
+}
+
+int cupk_component_sketch(cupk_ctx *ctx, const uint32_t *verts, size_t n, cupk_bucket *out)
+{
+    const uint64_t off[2] = {0, n};
+    return cupk_component_sketch_batch(ctx, off, 1, verts, out);
+}
+
+int cupk_sample_cut_edge_batch(cupk_ctx *ctx, const cupk_bucket *sketches, size_t k,
+                               int32_t *status, uint32_t *u, uint32_t *v)
+{
+    if (!ctx) return CUPK_EINVAL;
+    if (k == 0) return CUPK_OK;
+    if (!sketches || !status || !u || !v) return ctx->invalid("null array");
+    if (k >= (1ull << 31)) return ctx->invalid("too many sketches");
+    const size_t words = (size_t)k * ctx->W;
+    HIPCHK(grow(ctx->d_tmp, words));
+    HIPCHK(grow(ctx->d_res, 3 * k));
+    HIPCHK(grow(ctx->h_res, 3 * k));
+    HIPCHK(hipMemcpyAsync(ctx->d_tmp.p, sketches, words * 8, hipMemcpyHostToDevice, ctx->s));
+    // canonical layout: bucket (c, d) at word (c*D + d)*2
+    HIPCHK(launch_sample(ctx->s, ctx->d_tmp.p, (uint32_t)k, ctx->V, ctx->C, ctx->D, ctx->D, 1,
+                         ctx->W, ctx->d_seeds, ctx->d_res.p));
+    HIPCHK(hipMemcpyAsync(ctx->h_res.p, ctx->d_res.p, 3 * k * 4, hipMemcpyDeviceToHost, ctx->s));
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    for (size_t j = 0; j < k; j++) {
+        status[j] = ctx->h_res.p[3 * j];
+        u[j] = (uint32_t)ctx->h_res.p[3 * j + 1];
+        v[j] = (uint32_t)ctx->h_res.p[3 * j + 2];
+    }
+    return CUPK_OK;
+}
+
+int cupk_sample_cut_edge(cupk_ctx *ctx, const cupk_bucket *sketch, uint32_t *u, uint32_t *v)
+{
+    int32_t st = 0;
+    uint32_t a = 0, b = 0;
+    int rc = cupk_sample_cut_edge_batch(ctx, sketch, 1, &st, &a, &b);
+    if (rc != CUPK_OK) return rc;
+    if (u) *u = a;
+    if (v) *v = b;
+    return st;
+}
+
+int cupk_connected(cupk_ctx *ctx, uint32_t u, uint32_t v)
+{
+    if (!ctx) return CUPK_EINVAL;
+    if (u >= ctx->V || v >= ctx->V) return ctx->invalid("vertex id >= V");
+    // every batch leaves the forest complete before returning; the sketch
+    // may still be in flight but queries do not read it
+    return ctx->forest.same_tree(u, v) ? 1 : 0;
+}
+
+int cupk_get_sketch(cupk_ctx *ctx, uint32_t w0, uint32_t nv, cupk_bucket *out)
+{
+    if (!ctx) return CUPK_EINVAL;
+    if (nv == 0) return CUPK_OK;
+    if (!out) return ctx->invalid("null out");
+    if ((uint64_t)w0 + nv > ctx->V) return ctx->invalid("vertex range beyond V");
+    const uint32_t step = 4096;
+    HIPCHK(grow(ctx->d_tmp, (size_t)step * ctx->W));
+    for (uint32_t o = 0; o < nv; o += step) {
+        const uint32_t m = std::min(step, nv - o);
+        HIPCHK(launch_to_canonical(ctx->s, ctx->d_sk + (uint64_t)(w0 + o) * ctx->W, ctx->C, ctx->D,
+                                   m, ctx->d_tmp.p));
+        HIPCHK(hipMemcpyAsync(out + (size_t)o * ctx->C * ctx->D, ctx->d_tmp.p,
+                              (size_t)m * ctx->W * 8, hipMemcpyDeviceToHost, ctx->s));
+        HIPCHK(hipStreamSynchronize(ctx->s));
+    }
+    return CUPK_OK;
+}
+
+int cupk_digest(cupk_ctx *ctx, uint64_t *out)
+{
+    if (!ctx || !out) return CUPK_EINVAL;
+    HIPCHK(launch_zero(ctx->s, ctx->d_misc, 1));
+    HIPCHK(launch_digest(ctx->s, dev_sketch(ctx), ctx->S, ctx->d_misc));
+    HIPCHK(hipMemcpyAsync(ctx->h_misc, ctx->d_misc, 8, hipMemcpyDeviceToHost, ctx->s));
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    *out = ctx->h_misc[0];
+    return CUPK_OK;
+}
+
+int cupk_num_components(cupk_ctx *ctx, uint64_t *out)
+{
+    if (!ctx || !out) return CUPK_EINVAL;
+    *out = ctx->forest.n_trees();
+    return CUPK_OK;
+}
+
+int cupk_forest_edges(cupk_ctx *ctx, uint32_t *u, uint32_t *v, size_t cap, size_t *n)
+{
+    if (!ctx || !n) return CUPK_EINVAL;
+    std::vector<uint32_t> eu, ev;
+    ctx->forest.edges(eu, ev);
+    *n = eu.size();
+    if (cap < eu.size()) return ctx->invalid("forest edge buffer too small");
+    if (eu.size() && (!u || !v)) return ctx->invalid("null array");
+    std::copy(eu.begin(), eu.end(), u);
+    std::copy(ev.begin(), ev.end(), v);
+    return CUPK_OK;
+}
+
+int cupk_component_labels(cupk_ctx *ctx, uint32_t *out)
+{
+    if (!ctx || !out) return CUPK_EINVAL;
+    for (uint32_t w = 0; w < ctx->V; w++) out[w] = ctx->forest.label(w);
+    return CUPK_OK;
+}
+
+int cupk_counters(cupk_ctx *ctx, cupk_counters_t *out)
+{
+    if (!ctx || !out) return CUPK_EINVAL;
+    int rc = harvest_timers(ctx, true);
+    if (rc != CUPK_OK) return rc;
+    *out = ctx->ctr;
+    return CUPK_OK;
+}
+
+int cupk_sync(cupk_ctx *ctx)
+{
+    if (!ctx) return CUPK_EINVAL;
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    HIPCHK(hipStreamSynchronize(ctx->cs));
+    return harvest_timers(ctx, true);
+}
+
+const char *cupk_strerror(int code)
+{
+    switch (code) {
+    case CUPK_OK: return "ok";
+    case CUPK_EMPTY: return "empty: the aggregate sketch is zero";
+    case CUPK_SAMPLE_FAILED: return "sample failed: no bucket verifies";
+    case CUPK_EINVAL: return "invalid argument";
+    case CUPK_ENOMEM: return "out of memory";
+    case CUPK_EDEVICE: return "HIP device error";
+    case CUPK_EBUSY: return "busy: admission refused";
+    default: return "unknown code";
+    }
+}
+
+const char *cupk_last_error(cupk_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+}  // extern "C"

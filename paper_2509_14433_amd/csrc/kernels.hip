@@ -1,0 +1,670 @@
+// gfx950 kernels of the sketch hot path.
+//
+// All arithmetic is integer / GF(2): the sketch is a set of 64-bit words
+// combined by XOR (App. A.1.1 of arXiv 2509.14433), so there is no matrix
+// work and no floating point.  What bounds these kernels is HBM (and L2/LDS)
+// traffic and, for the staged scatter, the 64-bit integer hashing.
+//
+// Bucket layout in HBM: bucket (w, d, c) at word ((w*D + d)*C + c)*2, alpha
+// then gamma.  A vertex's shallow depth rows, which receive almost all
+// updates (depth d is hit with probability 2^-(d+1)), are contiguous.
+#include "kernels.hpp"
+
+namespace cupk {
+
+#define DEVI __device__ __forceinline__
+
+// SplitMix64 output finalizer (Steele, Lea, Flood 2014).
+DEVI uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Depth of a column hash: trailing zero count, capped at D-1.
+DEVI uint32_t depth_of(uint64_t h, uint32_t D)
+{
+    uint32_t z = h ? (uint32_t)__builtin_ctzll(h) : 64u;
+    return z < D - 1 ? z : D - 1;
+}
+
+// Packed update: lo32 = one endpoint, bits 32..62 = the other, bit 63 = delete.
+DEVI bool unpack(uint64_t p, uint32_t V, uint32_t &u, uint32_t &v, bool &del)
+{
+    uint32_t a = (uint32_t)p;
+    uint32_t b = (uint32_t)(p >> 32) & 0x7fffffffu;
+    del = (p >> 63) != 0;
+    u = a < b ? a : b;
+    v = a < b ? b : a;
+    return a != b && v < V;
+}
+
+// Number of set bits of m below this lane.
+DEVI uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+DEVI void gxor(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+DEVI void lxor(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// ---------------------------------------------------------------------------
+// Classification: validate the batch, flag structural candidates and count
+// endpoint records per vertex tile.
+//
+// Flagged (using the forest as it stood at the start of the batch):
+//   insert {u,v} with lbl[u] != lbl[v]               (may join two trees)
+//   delete {u,v} that is a forest edge (par[u]==v or par[v]==u), or with
+//   lbl[u] != lbl[v] (an edge linked earlier in this same batch)
+// Everything else can only touch the sketch.  Flagged updates are appended
+// with a wave-aggregated atomic; their order is restored on the host.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kClsThreads = 256;
+constexpr uint32_t kClsPerBlock = 4096;
+constexpr uint32_t kLdsHistMax = 8192;
+
+__global__ __launch_bounds__(kClsThreads) void k_classify(
+    const uint64_t *__restrict__ upd, uint32_t n, uint32_t V, const uint32_t *__restrict__ lbl,
+    const uint32_t *__restrict__ par, uint32_t *__restrict__ hdr, uint32_t *__restrict__ fpos,
+    uint64_t *__restrict__ fupd, uint32_t *__restrict__ tile_cnt, uint32_t tile_shift,
+    uint32_t ntiles)
+{
+    __shared__ uint32_t hist[kLdsHistMax];
+    const bool count = tile_cnt != nullptr;
+    const bool use_lds = count && ntiles <= kLdsHistMax;
+    if (use_lds)
+        for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) hist[t] = 0;
+    __syncthreads();
+
+    const uint32_t begin = blockIdx.x * kClsPerBlock;
+    const uint32_t end = min(n, begin + kClsPerBlock);
+    const uint32_t lane = __lane_id();
+    for (uint32_t base = begin; base < end; base += blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        bool flag = false, bad = false;
+        uint64_t p = 0;
+        if (i < end) {
+            p = upd[i];
+            uint32_t u, v;
+            bool del;
+            if (!unpack(p, V, u, v, del)) {
+                bad = true;
+            } else {
+                const uint32_t lu = lbl[u], lv = lbl[v];
+                flag = (lu != lv) || (del && (par[u] == v || par[v] == u));
+                if (count) {
+                    const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
+                    uint32_t *h = use_lds ? hist : tile_cnt;
+                    atomicAdd(&h[tu], 1u);
+                    if (tv != tu) atomicAdd(&h[tv], 1u);
+                }
+            }
+        }
+        const uint64_t m = __ballot(flag);
+        if (m) {
+            const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+            uint32_t pos = 0;
+            if (lane == leader) pos = atomicAdd(&hdr[HDR_NFLAG], (uint32_t)__popcll(m));
+            pos = __shfl(pos, leader);
+            if (flag) {
+                const uint32_t o = pos + lanes_below(m);
+                fpos[o] = i;
+                fupd[o] = p;
+            }
+        }
+        const uint64_t mb = __ballot(bad);
+        if (mb && lane == (uint32_t)__builtin_ctzll(mb)) atomicOr(&hdr[HDR_ERR], 1u);
+    }
+    if (use_lds) {
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x)
+            if (hist[t]) atomicAdd(&tile_cnt[t], hist[t]);
+    }
+}
+
+hipError_t launch_classify(hipStream_t s, const uint64_t *upd, uint32_t n, uint32_t V,
+                           const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
+                           uint32_t *fpos, uint64_t *fupd, uint32_t *tile_cnt,
+                           uint32_t tile_shift, uint32_t ntiles)
+{
+    if (n == 0) return hipSuccess;
+    const uint32_t blocks = (n + kClsPerBlock - 1) / kClsPerBlock;
+    k_classify<<<blocks, kClsThreads, 0, s>>>(upd, n, V, lbl, par, hdr, fpos, fupd, tile_cnt,
+                                              tile_shift, ntiles);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Plain scatter: one thread per update, hashing the edge index once per
+// column and XOR-ing (x, h) into bucket (c, d) of both endpoints with
+// device-scope atomics (4 per column).  Skipped when the batch was rejected.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scatter_atomic(const uint64_t *__restrict__ upd,
+                                                        uint32_t n, DevSketch sk,
+                                                        const uint32_t *__restrict__ hdr)
+{
+    if (hdr[HDR_ERR]) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t u, v;
+    bool del;
+    unpack(upd[i], sk.V, u, v, del);
+    const uint64_t x = (uint64_t)u * sk.V + v;
+    const uint64_t ru = (uint64_t)u * sk.D, rv = (uint64_t)v * sk.D;
+    for (uint32_t c = 0; c < sk.C; c++) {
+        const uint64_t h = mix64(x ^ sk.seeds[c]);
+        const uint32_t d = depth_of(h, sk.D);
+        uint64_t *bu = sk.b + ((ru + d) * sk.C + c) * 2;
+        uint64_t *bv = sk.b + ((rv + d) * sk.C + c) * 2;
+        gxor(bu, x);
+        gxor(bu + 1, h);
+        gxor(bv, x);
+        gxor(bv + 1, h);
+    }
+}
+
+hipError_t launch_scatter_atomic(hipStream_t s, const uint64_t *upd, uint32_t n, DevSketch sk,
+                                 const uint32_t *hdr)
+{
+    if (n == 0) return hipSuccess;
+    k_scatter_atomic<<<(n + 255) / 256, 256, 0, s>>>(upd, n, sk, hdr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Staged scatter.
+//
+// 1. k_tile_scan (one block): exclusive scan of the per-tile record counts
+//    into bin offsets, and a list of work items (tile, chunk) where a chunk
+//    is at most `chunk` records of one tile's bin.
+// 2. k_tile_fill: each update writes its record (u | v << 32) into the bin
+//    of u's tile and, if different, of v's tile.  Slots are reserved per
+//    block in LDS first, so global atomics are per (block, tile), not per
+//    record.
+// 3. k_tile_scatter: one work item per block iteration.  The block keeps a
+//    zeroed LDS delta of depth rows 0..rows-1 for the tile's vertices, XORs
+//    every record of the chunk into it (LDS atomics; depths >= rows go
+//    straight to HBM with device atomics), then folds the nonzero delta
+//    words into HBM: a plain read-XOR-write when the chunk is the tile's
+//    whole bin (no other block touches these vertices), a device atomic XOR
+//    otherwise.  LDS holds alpha and gamma in separate planes ordered
+//    [d][c][vertex], so lanes working on different vertices of the same
+//    (c, d) hit consecutive words.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kScanThreads = 1024;
+
+// Block-wide exclusive scan of one value per thread; returns the prefix and
+// sets `total`.
+template <uint32_t NT>
+DEVI uint32_t block_exscan(uint32_t x, uint32_t &total, uint32_t *sh)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t wid = threadIdx.x / 64;
+    uint32_t inc = x;
+#pragma unroll
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) sh[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        uint32_t w = threadIdx.x < NT / 64 ? sh[threadIdx.x] : 0u;
+        uint32_t wi = w;
+#pragma unroll
+        for (uint32_t o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(wi, o);
+            if (lane >= o) wi += y;
+        }
+        if (threadIdx.x < NT / 64) sh[64 + threadIdx.x] = wi - w;
+        if (threadIdx.x == NT / 64 - 1) sh[128] = wi;
+    }
+    __syncthreads();
+    const uint32_t ex = sh[64 + wid] + inc - x;
+    total = sh[128];
+    __syncthreads();
+    return ex;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(
+    const uint32_t *__restrict__ cnt, uint32_t ntiles, uint32_t chunk, uint32_t *__restrict__ off,
+    uint32_t *__restrict__ cur, uint32_t *__restrict__ items, uint32_t items_cap,
+    uint32_t *__restrict__ nitems, const uint32_t *__restrict__ hdr)
+{
+    __shared__ uint32_t sh[160];
+    if (hdr[HDR_ERR]) {
+        if (threadIdx.x == 0) *nitems = 0;
+        return;
+    }
+    uint32_t carry_r = 0, carry_i = 0;
+    for (uint32_t base = 0; base < ntiles; base += kScanThreads) {
+        const uint32_t t = base + threadIdx.x;
+        const uint32_t c = t < ntiles ? cnt[t] : 0u;
+        const uint32_t k = (c + chunk - 1) / chunk;
+        uint32_t tot_c, tot_k;
+        const uint32_t ex_c = block_exscan<kScanThreads>(c, tot_c, sh);
+        const uint32_t ex_k = block_exscan<kScanThreads>(k, tot_k, sh);
+        if (t < ntiles) {
+            off[t] = carry_r + ex_c;
+            cur[t] = carry_r + ex_c;
+            for (uint32_t j = 0; j < k; j++) {
+                const uint32_t q = carry_i + ex_k + j;
+                if (q < items_cap) {
+                    items[2 * q] = t;
+                    items[2 * q + 1] = j;
+                }
+            }
+        }
+        carry_r += tot_c;
+        carry_i += tot_k;
+    }
+    if (threadIdx.x == 0) {
+        off[ntiles] = carry_r;
+        *nitems = min(carry_i, items_cap);
+    }
+}
+
+constexpr uint32_t kFillThreads = 256;
+constexpr uint32_t kFillPerBlock = 4096;
+
+__global__ __launch_bounds__(kFillThreads) void k_tile_fill(
+    const uint64_t *__restrict__ upd, uint32_t n, uint32_t V, uint32_t tile_shift,
+    uint32_t ntiles, uint32_t *__restrict__ cur, uint64_t *__restrict__ bins,
+    const uint32_t *__restrict__ hdr)
+{
+    __shared__ uint32_t lcnt[kLdsHistMax];
+    if (hdr[HDR_ERR]) return;
+    const uint32_t begin = blockIdx.x * kFillPerBlock;
+    const uint32_t end = min(n, begin + kFillPerBlock);
+    if (ntiles > kLdsHistMax) {
+        // Many small tiles: contention is low, reserve per record.
+        for (uint32_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+            uint32_t u, v;
+            bool del;
+            unpack(upd[i], V, u, v, del);
+            const uint64_t rec = (uint64_t)u | ((uint64_t)v << 32);
+            const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
+            bins[atomicAdd(&cur[tu], 1u)] = rec;
+            if (tv != tu) bins[atomicAdd(&cur[tv], 1u)] = rec;
+        }
+        return;
+    }
+    for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) lcnt[t] = 0;
+    __syncthreads();
+    // pass 1: block-local counts
+    for (uint32_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+        uint32_t u, v;
+        bool del;
+        unpack(upd[i], V, u, v, del);
+        const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
+        atomicAdd(&lcnt[tu], 1u);
+        if (tv != tu) atomicAdd(&lcnt[tv], 1u);
+    }
+    __syncthreads();
+    // reserve one contiguous range per tile present in this block
+    for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        const uint32_t c = lcnt[t];
+        if (c) lcnt[t] = atomicAdd(&cur[t], c);
+    }
+    __syncthreads();
+    // pass 2: write records
+    for (uint32_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+        uint32_t u, v;
+        bool del;
+        unpack(upd[i], V, u, v, del);
+        const uint64_t rec = (uint64_t)u | ((uint64_t)v << 32);
+        const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
+        bins[atomicAdd(&lcnt[tu], 1u)] = rec;
+        if (tv != tu) bins[atomicAdd(&lcnt[tv], 1u)] = rec;
+    }
+}
+
+constexpr uint32_t kTileThreads = 256;
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
+    DevSketch sk, const uint64_t *__restrict__ bins, const uint32_t *__restrict__ off,
+    const uint32_t *__restrict__ items, const uint32_t *__restrict__ nitems_p, uint32_t tile_shift,
+    uint32_t rows, uint32_t chunk, const uint32_t *__restrict__ hdr)
+{
+    extern __shared__ uint64_t lds[];
+    if (hdr[HDR_ERR]) return;
+    const uint32_t TV = 1u << tile_shift;
+    const uint32_t C = sk.C, D = sk.D, V = sk.V;
+    const uint32_t plane = rows * C * TV;  // words per LDS plane
+    uint64_t *la = lds;                    // alpha plane [d][c][vl]
+    uint64_t *lg = lds + plane;            // gamma plane
+    const uint32_t nitems = *nitems_p;
+
+    for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t tile = items[2 * it];
+        const uint32_t j = items[2 * it + 1];
+        const uint32_t rb = off[tile], re = off[tile + 1];
+        const uint32_t cb = rb + j * chunk;
+        const uint32_t ce = min(re, cb + chunk);
+        const bool single = (re - rb) <= chunk;
+        const uint32_t w0 = tile << tile_shift;
+
+        for (uint32_t q = threadIdx.x; q < 2 * plane; q += blockDim.x) lds[q] = 0;
+        __syncthreads();
+
+        for (uint32_t r = cb + threadIdx.x; r < ce; r += blockDim.x) {
+            const uint64_t rec = bins[r];
+            const uint32_t u = (uint32_t)rec, v = (uint32_t)(rec >> 32);
+            const uint64_t x = (uint64_t)u * V + v;
+            const bool inu = (u >> tile_shift) == tile;
+            const bool inv = (v >> tile_shift) == tile;
+            const uint32_t lu = u - w0, lv = v - w0;
+            for (uint32_t c = 0; c < C; c++) {
+                const uint64_t h = mix64(x ^ sk.seeds[c]);
+                const uint32_t d = depth_of(h, D);
+                if (d < rows) {
+                    const uint32_t rowoff = (d * C + c) * TV;
+                    if (inu) {
+                        lxor(&la[rowoff + lu], x);
+                        lxor(&lg[rowoff + lu], h);
+                    }
+                    if (inv) {
+                        lxor(&la[rowoff + lv], x);
+                        lxor(&lg[rowoff + lv], h);
+                    }
+                } else {
+                    if (inu) {
+                        uint64_t *bu = sk.b + (((uint64_t)u * D + d) * C + c) * 2;
+                        gxor(bu, x);
+                        gxor(bu + 1, h);
+                    }
+                    if (inv) {
+                        uint64_t *bv = sk.b + (((uint64_t)v * D + d) * C + c) * 2;
+                        gxor(bv, x);
+                        gxor(bv + 1, h);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        // Fold the delta into HBM, walking buckets in HBM order
+        // (vertex, d, c) so that consecutive lanes touch consecutive words.
+        const uint32_t nvt = min(TV, V - w0);
+        const uint32_t per_v = rows * C;
+        const uint32_t nb = nvt * per_v;
+        for (uint32_t q = threadIdx.x; q < nb; q += blockDim.x) {
+            const uint32_t vl = q / per_v;
+            const uint32_t rc = q - vl * per_v;  // d*C + c
+            const uint64_t da = la[rc * TV + vl];
+            const uint64_t dg = lg[rc * TV + vl];
+            if ((da | dg) == 0) continue;
+            uint64_t *g = sk.b + (((uint64_t)(w0 + vl) * D) * C + rc) * 2;
+            if (single) {
+                g[0] ^= da;
+                g[1] ^= dg;
+            } else {
+                if (da) gxor(g, da);
+                if (dg) gxor(g + 1, dg);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_staged(hipStream_t s, const uint64_t *upd, uint32_t n, DevSketch sk,
+                         const uint32_t *hdr, const StagedParams &p, uint32_t *tile_cnt,
+                         uint32_t *tile_off, uint32_t *tile_cur, uint64_t *bins,
+                         uint32_t *items, uint32_t *nitems, hipEvent_t ev_binned)
+{
+    if (n == 0) return hipSuccess;
+    k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, p.ntiles, p.chunk, tile_off, tile_cur, items,
+                                           p.items_cap, nitems, hdr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint32_t fb = (n + kFillPerBlock - 1) / kFillPerBlock;
+    k_tile_fill<<<fb, kFillThreads, 0, s>>>(upd, n, sk.V, p.tile_shift, p.ntiles, tile_cur, bins,
+                                            hdr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev_binned) {
+        e = hipEventRecord(ev_binned, s);
+        if (e != hipSuccess) return e;
+    }
+    const size_t lds = (size_t)2 * p.rows * sk.C * (1u << p.tile_shift) * sizeof(uint64_t);
+    // Persistent grid: a few blocks per CU, each looping over work items.
+    const uint32_t grid = min(p.items_cap, 256u * 8u);
+    k_tile_scatter<<<grid, kTileThreads, lds, s>>>(sk, bins, tile_off, items, nitems, p.tile_shift,
+                                                  p.rows, p.chunk, hdr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Utility fills.
+// ---------------------------------------------------------------------------
+__global__ void k_zero64(uint64_t *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void k_zero32(uint32_t *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_zero(hipStream_t s, uint64_t *p, size_t n)
+{
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    k_zero64<<<(uint32_t)blocks, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero32(hipStream_t s, uint32_t *p, size_t n)
+{
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    k_zero32<<<(uint32_t)blocks, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Segmented XOR reduction (component sketches).  A work item is
+// (set, begin, end) over the member list; the block streams the members'
+// slabs (W words each, coalesced across lanes) and XORs them into
+// registers, then folds the nonzero words into out[set] with device
+// atomics (a set may span several work items).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRedThreads = 256;
+constexpr uint32_t kRedMaxK = 32;  // W <= 8192 words (C*D <= 4096)
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const uint64_t *__restrict__ src,
+                                                        uint32_t W,
+                                                        const uint32_t *__restrict__ idx,
+                                                        const uint32_t *__restrict__ items,
+                                                        uint32_t nitems,
+                                                        uint64_t *__restrict__ out)
+{
+    for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t set = items[3 * it];
+        const uint32_t b = items[3 * it + 1];
+        const uint32_t e = items[3 * it + 2];
+        uint64_t acc[kRedMaxK];
+#pragma unroll
+        for (uint32_t k = 0; k < kRedMaxK; k++) acc[k] = 0;
+        for (uint32_t j = b; j < e; j++) {
+            const uint64_t *slab = src + (uint64_t)idx[j] * W;
+#pragma unroll
+            for (uint32_t k = 0; k < kRedMaxK; k++) {
+                const uint32_t w = k * kRedThreads + threadIdx.x;
+                if (w < W) acc[k] ^= slab[w];
+            }
+        }
+        uint64_t *o = out + (uint64_t)set * W;
+#pragma unroll
+        for (uint32_t k = 0; k < kRedMaxK; k++) {
+            const uint32_t w = k * kRedThreads + threadIdx.x;
+            if (w < W && acc[k]) gxor(&o[w], acc[k]);
+        }
+    }
+}
+
+hipError_t launch_reduce(hipStream_t s, const uint64_t *src, uint32_t W, const uint32_t *idx,
+                         const uint32_t *items, uint32_t nitems, uint64_t *out)
+{
+    if (nitems == 0) return hipSuccess;
+    if (W > kRedMaxK * kRedThreads) return hipErrorInvalidValue;
+    const uint32_t grid = min(nitems, 4096u);
+    k_reduce<<<grid, kRedThreads, 0, s>>>(src, W, idx, items, nitems, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Verify and sample.  One block per aggregate sketch: every lane checks its
+// buckets (alpha != 0, checksum and depth re-derived from alpha, alpha
+// decodes to u < v < V) and the block takes the minimum canonical rank
+// c*D + (D-1-d) among the good ones; a block-wide OR detects the all-zero
+// (EMPTY) case.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSmpThreads = 256;
+
+__global__ __launch_bounds__(kSmpThreads) void k_sample(const uint64_t *__restrict__ sig,
+                                                        uint32_t k, uint32_t V, uint32_t C,
+                                                        uint32_t D, uint32_t sc, uint32_t sd,
+                                                        uint64_t set_stride,
+                                                        const uint64_t *__restrict__ seeds,
+                                                        int32_t *__restrict__ res)
+{
+    __shared__ uint32_t s_best[kSmpThreads / 64];
+    __shared__ uint64_t s_any[kSmpThreads / 64];
+    const uint32_t set = blockIdx.x;
+    if (set >= k) return;
+    const uint64_t *S = sig + (uint64_t)set * set_stride;
+    uint32_t best = 0xffffffffu;
+    uint64_t any = 0;
+    const uint32_t nb = C * D;
+    for (uint32_t q = threadIdx.x; q < nb; q += blockDim.x) {
+        const uint32_t c = q / D, d = q - c * D;
+        const uint64_t o = ((uint64_t)c * sc + (uint64_t)d * sd) * 2;
+        const uint64_t a = S[o], g = S[o + 1];
+        any |= a | g;
+        if (a == 0) continue;
+        const uint64_t h = mix64(a ^ seeds[c]);
+        if (h != g || depth_of(h, D) != d) continue;
+        const uint64_t uu = a / V, vv = a - uu * V;
+        if (!(uu < vv)) continue;
+        const uint32_t key = c * D + (D - 1 - d);
+        best = key < best ? key : best;
+    }
+    // wave reductions
+    for (uint32_t o = 32; o > 0; o >>= 1) {
+        const uint32_t ob = __shfl_xor(best, o);
+        best = ob < best ? ob : best;
+        any |= __shfl_xor(any, o);
+    }
+    const uint32_t wid = threadIdx.x / 64;
+    if (__lane_id() == 0) {
+        s_best[wid] = best;
+        s_any[wid] = any;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (uint32_t w = 1; w < blockDim.x / 64; w++) {
+            best = s_best[w] < best ? s_best[w] : best;
+            any |= s_any[w];
+        }
+        int32_t *r = res + 3 * (uint64_t)set;
+        if (best != 0xffffffffu) {
+            const uint32_t c = best / D, d = D - 1 - (best - c * D);
+            const uint64_t a = S[((uint64_t)c * sc + (uint64_t)d * sd) * 2];
+            r[0] = 0;
+            r[1] = (int32_t)(uint32_t)(a / V);
+            r[2] = (int32_t)(uint32_t)(a % V);
+        } else {
+            r[0] = any ? 2 : 1;
+            r[1] = 0;
+            r[2] = 0;
+        }
+    }
+}
+
+hipError_t launch_sample(hipStream_t s, const uint64_t *sig, uint32_t k, uint32_t V, uint32_t C,
+                         uint32_t D, uint32_t sc, uint32_t sd, uint64_t set_stride,
+                         const uint64_t *seeds, int32_t *res)
+{
+    if (k == 0) return hipSuccess;
+    k_sample<<<k, kSmpThreads, 0, s>>>(sig, k, V, C, D, sc, sd, set_stride, seeds, res);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Digest: order-independent sum over all buckets of
+// mix(alpha ^ rotl(gamma, 32) ^ mix(canonical_position ^ seed)).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_digest(DevSketch sk, uint64_t S, uint64_t *out)
+{
+    const uint32_t C = sk.C, D = sk.D;
+    const uint32_t per_v = C * D;
+    uint64_t acc = 0;
+    for (uint32_t w = blockIdx.x; w < sk.V; w += gridDim.x) {
+        const uint64_t *b = sk.b + (uint64_t)w * per_v * 2;
+        for (uint32_t r = threadIdx.x; r < per_v; r += blockDim.x) {
+            const uint32_t d = r / C, c = r - d * C;
+            const uint64_t pos = ((uint64_t)w * C + c) * D + d;
+            const uint64_t a = b[2 * r], g = b[2 * r + 1];
+            const uint64_t rg = (g << 32) | (g >> 32);
+            acc += mix64(a ^ rg ^ mix64(pos ^ S));
+        }
+    }
+    for (uint32_t o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (__lane_id() == 0) atomicAdd((unsigned long long *)out, (unsigned long long)acc);
+}
+
+hipError_t launch_digest(hipStream_t s, DevSketch sk, uint64_t master_seed, uint64_t *out)
+{
+    const uint32_t grid = min(sk.V, 8192u);
+    k_digest<<<grid, 256, 0, s>>>(sk, master_seed, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Internal layout -> canonical (c, d) order.
+// ---------------------------------------------------------------------------
+__global__ void k_to_canonical(const uint64_t *__restrict__ src, uint32_t C, uint32_t D,
+                               uint64_t nv, uint64_t *__restrict__ dst)
+{
+    const uint32_t per_v = C * D;
+    const uint64_t total = nv * per_v;
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
+         q += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = q / per_v;
+        const uint32_t r = (uint32_t)(q - i * per_v);
+        const uint32_t c = r / D, d = r - c * D;
+        const uint64_t s = (i * per_v + (uint64_t)d * C + c) * 2;
+        dst[2 * q] = src[s];
+        dst[2 * q + 1] = src[s + 1];
+    }
+}
+
+hipError_t launch_to_canonical(hipStream_t s, const uint64_t *src, uint32_t C, uint32_t D,
+                               uint64_t nv, uint64_t *dst)
+{
+    const uint64_t total = nv * C * D;
+    if (total == 0) return hipSuccess;
+    uint64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    k_to_canonical<<<(uint32_t)blocks, 256, 0, s>>>(src, C, D, nv, dst);
+    return hipGetLastError();
+}
+
+}  // namespace cupk

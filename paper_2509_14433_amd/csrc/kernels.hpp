@@ -1,0 +1,73 @@
+// Launch wrappers of the gfx950 kernels.  Host code calls only these.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cupk {
+
+// Device view of the resident sketch.
+// Internal layout: bucket (w, d, c) of vertex w at word ((w*D + d)*C + c)*2,
+// alpha at +0 and gamma at +1 ("depth-major inside a vertex": the shallow
+// rows that take most updates are contiguous at the front of a vertex).
+struct DevSketch {
+    uint64_t *b;           // 2*V*C*D words
+    const uint64_t *seeds; // C column seeds
+    uint32_t V, C, D;
+};
+
+// Header words written by the classify kernel.
+enum { HDR_ERR = 0, HDR_NFLAG = 1, HDR_WORDS = 4 };
+
+struct StagedParams {
+    uint32_t tile_shift;   // vertices per tile = 1 << tile_shift
+    uint32_t rows;         // depth rows held in LDS (d < rows)
+    uint32_t ntiles;
+    uint32_t chunk;        // max records per work item
+    uint32_t items_cap;    // capacity of the work-item array
+};
+
+// Per-batch: validation, structural classification and compaction of the
+// flagged updates.  hdr must be zeroed first.  When `tile_cnt` is non-null
+// the kernel also counts how many endpoint records each vertex tile gets.
+hipError_t launch_classify(hipStream_t s, const uint64_t *upd, uint32_t n, uint32_t V,
+                           const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
+                           uint32_t *fpos, uint64_t *fupd, uint32_t *tile_cnt,
+                           uint32_t tile_shift, uint32_t ntiles);
+
+// Plain scatter: device-scope atomic XOR of (x, h) into both endpoints.
+hipError_t launch_scatter_atomic(hipStream_t s, const uint64_t *upd, uint32_t n,
+                                 DevSketch sk, const uint32_t *hdr);
+
+// Staged scatter, three launches: scan of tile counts into bin offsets and
+// work items; fill of the per-tile bins; LDS-staged XOR per work item.
+hipError_t launch_staged(hipStream_t s, const uint64_t *upd, uint32_t n, DevSketch sk,
+                         const uint32_t *hdr, const StagedParams &p, uint32_t *tile_cnt,
+                         uint32_t *tile_off, uint32_t *tile_cur, uint64_t *bins,
+                         uint32_t *items, uint32_t *nitems, hipEvent_t ev_binned);
+
+// Fill n words with zero.
+hipError_t launch_zero(hipStream_t s, uint64_t *p, size_t n);
+hipError_t launch_zero32(hipStream_t s, uint32_t *p, size_t n);
+
+// Segmented XOR reduction: out[set] = XOR of src slabs listed by `idx`.
+// items: triples (set, begin, end) into idx; slab = W words.
+hipError_t launch_reduce(hipStream_t s, const uint64_t *src, uint32_t W, const uint32_t *idx,
+                         const uint32_t *items, uint32_t nitems, uint64_t *out);
+
+// Query each of k aggregate sketches (bucket (c,d) at word (c*sc + d*sd)*2).
+// res: 3 words per set (status, u, v).
+hipError_t launch_sample(hipStream_t s, const uint64_t *sig, uint32_t k, uint32_t V, uint32_t C,
+                         uint32_t D, uint32_t sc, uint32_t sd, uint64_t set_stride,
+                         const uint64_t *seeds, int32_t *res);
+
+// Digest of the whole sketch, added into *out (zero it first).
+hipError_t launch_digest(hipStream_t s, DevSketch sk, uint64_t master_seed, uint64_t *out);
+
+// Copy nv sketches from internal layout (first vertex w0) or from an
+// internal-layout aggregate array (w0 ignored when `agg` is set) into
+// canonical (c, d) order.
+hipError_t launch_to_canonical(hipStream_t s, const uint64_t *src, uint32_t C, uint32_t D,
+                               uint64_t nv, uint64_t *dst);
+
+}  // namespace cupk

@@ -1,0 +1,223 @@
+"""Parity of the HIP path with the CPU oracle (bit-exact).
+
+Every case runs the same seeded stream through the library (via the C ABI)
+and through the oracle with the same batch boundaries, then compares the
+whole sketch array, the digest, the forest edges, component sketches and
+samples.  Sizes span several vertex tiles and leave a ragged last tile and
+a ragged last batch.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import streamgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cupk():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a machine without a GPU"
+    import paper_2509_14433_amd as m
+    return m
+
+
+MODES = ["atomic", "staged"]
+
+
+def _mode(cupk, name):
+    return cupk.SCATTER_ATOMIC if name == "atomic" else cupk.SCATTER_STAGED
+
+
+def _replay(cupk, mode, V, C, D, S, u, v, d, bs, **kw):
+    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode), **kw)
+    ref = oracle.Sketch(V, C, D, S)
+    fr = oracle.ForestReplay(ref)
+    n = len(u)
+    bs = n if bs is None else bs
+    for s in range(0, n, bs):
+        e = min(n, s + bs)
+        print(f"batch {s}:{e}", flush=True)
+        ctx.apply_updates(u[s:e], v[s:e], d[s:e])
+        fr.apply_batch(u[s:e], v[s:e], d[s:e])
+    return ctx, ref, fr
+
+
+def _assert_same_sketch(ctx, ref):
+    a, g = ctx.get_sketch()
+    assert a.shape == ref.alpha.shape
+    bad = np.argwhere((a != ref.alpha) | (g != ref.gamma))
+    assert bad.size == 0, f"{len(bad)} buckets differ, first (w,c,d) = {bad[:5].tolist()}"
+    assert ctx.digest() == ref.digest()
+
+
+CASES = [
+    # V, p, del_frac, batch, tile_vertices, lds_rows
+    (200, 0.15, 0.4, 97, 8, 0),
+    (200, 0.15, 0.4, None, 0, 0),
+    (333, 0.1, 0.5, 1000, 16, 2),
+    (1000, 0.02, 0.3, 777, 4, 0),
+    (2, 1.0, 0.0, None, 0, 0),
+]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("V,p,df,bs,tv,rows", CASES)
+def test_stream_parity(cupk, mode, V, p, df, bs, tv, rows):
+    C = max(1, math.ceil(math.log2(V)))
+    D = 2 * C
+    S = 0x5EED0000 + V
+    u, v, d = streamgen.er_standard(V, p, df, V * 7 + 1)
+    print(f"case V={V} n={len(u)} mode={mode} bs={bs} tv={tv} rows={rows}", flush=True)
+    ctx, ref, fr = _replay(cupk, mode, V, C, D, S, u, v, d, bs, tile_vertices=tv,
+                           lds_rows=rows)
+    _assert_same_sketch(ctx, ref)
+    assert ctx.forest_edges() == fr.forest_edges()
+    fu, fv = streamgen.final_edges(u, v, d)
+    truth = oracle.components_truth(V, fu, fv)
+    lab = ctx.component_labels()
+    assert ctx.num_components() == len(set(truth.tolist()))
+    for w in range(V):
+        assert (lab[w] == lab[truth[w]])
+    # queries
+    rng = np.random.default_rng(V)
+    for _ in range(200):
+        a, b = (int(x) for x in rng.integers(0, V, 2))
+        assert ctx.connected(a, b) == (truth[a] == truth[b])
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_hot_vertex_star(cupk, mode):
+    # every update touches vertex 0: one tile's bin spans several work items
+    # (multi-chunk fold with device atomics) and LDS atomics collide
+    V, C, D, S = 6000, 5, 10, 99
+    u, v, d = streamgen.star_stream(V, 12000, 5)
+    print(f"star n={len(u)} mode={mode}", flush=True)
+    ctx, ref, fr = _replay(cupk, mode, V, C, D, S, u, v, d, 9000)
+    _assert_same_sketch(ctx, ref)
+    assert ctx.forest_edges() == fr.forest_edges()
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config0_full(cupk, mode):
+    V, C, D, S = 1024, 10, 20, 0x5EED0000
+    u, v, d = streamgen.config_stream(0)
+    for bs in (None, 65536):
+        print(f"config0 bs={bs} mode={mode}", flush=True)
+        ctx, ref, fr = _replay(cupk, mode, V, C, D, S, u, v, d, bs)
+        _assert_same_sketch(ctx, ref)
+        assert ctx.forest_edges() == fr.forest_edges()
+        fu, fv = streamgen.final_edges(u, v, d)
+        truth = oracle.components_truth(V, fu, fv)
+        lab = ctx.component_labels()
+        # all 523,776 pairs: equal partitions
+        assert len(set(lab.tolist())) == len(set(truth.tolist()))
+        pairs = {}
+        for w in range(V):
+            pairs.setdefault(int(lab[w]), set()).add(int(truth[w]))
+        assert all(len(s) == 1 for s in pairs.values())
+        ctx.close()
+
+
+def test_component_sketch_and_sample_parity(cupk):
+    V, C, D, S = 300, 9, 18, 4321
+    u, v, d = streamgen.er_standard(V, 0.05, 0.3, 77)
+    ctx, ref, fr = _replay(cupk, "staged", V, C, D, S, u, v, d, 500)
+    rng = np.random.default_rng(1)
+    sets = [np.array([], np.uint32), np.arange(V, dtype=np.uint32),
+            np.array([5], np.uint32)]
+    for _ in range(40):
+        k = int(rng.integers(1, V))
+        sets.append(np.sort(rng.choice(V, size=k, replace=False)).astype(np.uint32))
+    ga, gg = ctx.component_sketch_batch(sets)
+    for j, s in enumerate(sets):
+        oa, og = ref.set_sketch(s)
+        assert np.array_equal(ga[j], oa) and np.array_equal(gg[j], og), j
+        one_a, one_g = ctx.component_sketch(s)
+        assert np.array_equal(one_a, oa) and np.array_equal(one_g, og)
+        assert ctx.sample_cut_edge(oa, og) == ref.sample(oa, og)
+    st, su, sv = ctx.sample_cut_edge_batch(ga, gg)
+    for j in range(len(sets)):
+        want = ref.sample(ga[j], gg[j])
+        assert (int(st[j]), int(su[j]) if st[j] == 0 else 0, int(sv[j]) if st[j] == 0 else 0) \
+            == want
+    ctx.close()
+
+
+def test_sample_statuses(cupk):
+    # EMPTY for a whole component, SAMPLE_FAILED for two colliding indices
+    V, C, D, S = 1000, 1, 4, 55
+    ctx = cupk.Context(V, C, D, S)
+    ref = oracle.Sketch(V, C, D, S)
+    first, pair = {}, None
+    for b in range(1, V):
+        x = oracle.edge_index(V, 0, b)
+        dd = oracle.depth_of_hash(oracle.hash_c(S, 0, x), D)
+        if dd in first:
+            pair = (first[dd], b)
+            break
+        first[dd] = b
+    uu = np.array([0, 0], np.uint32)
+    vv = np.array(pair, np.uint32)
+    ctx.apply_updates(uu, vv, np.zeros(2, np.uint8))
+    ref.apply(uu, vv)
+    a, g = ctx.component_sketch([0])
+    assert ctx.sample_cut_edge(a, g)[0] == cupk.SAMPLE_FAILED
+    assert ref.sample(a, g)[0] == oracle.FAILED
+    a, g = ctx.component_sketch([0, int(pair[0]), int(pair[1])])
+    assert ctx.sample_cut_edge(a, g)[0] == cupk.EMPTY
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_invalid_batch_applies_nothing(cupk, mode):
+    V, C, D, S = 100, 7, 14, 3
+    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    u, v, d = streamgen.er_standard(V, 0.1, 0.0, 4)
+    ctx.apply_updates(u, v, d)
+    dg = ctx.digest()
+    edges = ctx.forest_edges()
+    for bad in ((5, 5), (3, 100)):
+        uu = np.array([1, bad[0], 2], np.uint32)
+        vv = np.array([9, bad[1], 8], np.uint32)
+        with pytest.raises(cupk.CupkError) as ei:
+            ctx.apply_updates(uu, vv, np.zeros(3, np.uint8))
+        assert ei.value.code == cupk.EINVAL
+        # the device path validates on the GPU
+        import torch
+        packed = torch.from_numpy(cupk.pack_updates(uu, vv, np.zeros(3)).view(np.int64)).cuda()
+        with pytest.raises(cupk.CupkError) as ei:
+            ctx.apply_updates_device(packed)
+        assert ei.value.code == cupk.EINVAL
+    assert ctx.digest() == dg and ctx.forest_edges() == edges
+    ctx.apply_updates(np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.uint8))
+    assert ctx.digest() == dg
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_device_batches_match_host_batches(cupk, mode):
+    import torch
+    V, C, D, S = 500, 9, 18, 8
+    u, v, d = streamgen.er_standard(V, 0.08, 0.5, 12)
+    # endpoints in either order on the device path
+    sw = np.arange(len(u)) % 2 == 1
+    uu = np.where(sw, v, u)
+    vv = np.where(sw, u, v)
+    packed = torch.from_numpy(cupk.pack_updates(uu, vv, d).view(np.int64)).cuda()
+    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    ref = oracle.Sketch(V, C, D, S)
+    fr = oracle.ForestReplay(ref)
+    bs = 3001
+    for s in range(0, len(u), bs):
+        e = min(len(u), s + bs)
+        ctx.apply_updates_device(packed[s:e])
+        fr.apply_batch(u[s:e], v[s:e], d[s:e])
+    _assert_same_sketch(ctx, ref)
+    assert ctx.forest_edges() == fr.forest_edges()
+    ctx.close()
