@@ -1,0 +1,203 @@
+"""Benchmark of the sketch hot path on one MI355X.
+
+Workload: V=16384 vertices, Erdos-Renyi G(V, 0.3) insert stream in random
+order followed by deletion of a random 10% of the inserted edges
+(44,276,290 updates), applied in fixed batches of 1,000,000 updates; sketch
+of C=14 columns x D=28 depth buckets per vertex.
+
+One step = one batch through the whole path: device classification,
+scatter into both endpoints' sketches, host forest links/cuts, replacement
+rounds (component XOR-reduce + verify/sample) for every broken tree.  The
+packed stream is resident in HBM before timing starts.  K steps walk the
+stream from its start; past its end a fresh context replays it again.
+
+Prints one JSON line: whole-job updates/s, the scatter kernel's roofline
+figures (algorithmic bytes per update = 8 + 64*C over HIP-event kernel
+time), the plain (atomic) kernel's figures, and the CPU oracle timed on a
+bounded sample of the same stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+V, C, D, SEED, BATCH = 16384, 14, 28, 0x5EED0001, 1_000_000
+WORKLOAD = ("er16384_p0.3_del10: V=16384, G(V,0.3) inserts in random order then 10% random "
+            "deletions (44,276,290 updates), 1,000,000-update batches, C=14 x D=28 buckets")
+
+
+def algorithmic_bytes_per_update(C: int) -> int:
+    # 8 B packed update read + 2 endpoints x C buckets x 16 B x (read + write)
+    return 8 + 64 * C
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2509_14433_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
+    summary, or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        with open(path) as f:
+            prof = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = prof.get(kernel)
+    if not ent or ent.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def run_path(cupk, torch, packed, sizes, steps, warmup, mode, time_kernels=True):
+    """Warm up, then time `steps` batches.  Returns (seconds, updates, ctr)."""
+    offs = [0]
+    for s in sizes:
+        offs.append(offs[-1] + s)
+    nb = len(sizes)
+
+    def new_ctx():
+        return cupk.Context(V, C, D, SEED, scatter_mode=mode, max_batch=BATCH,
+                            time_kernels=time_kernels)
+
+    # warmup on a throwaway context (code objects, buffers, clocks)
+    w = new_ctx()
+    for i in range(warmup):
+        j = i % nb
+        if j == 0 and i:
+            w.close()
+            w = new_ctx()
+        w.apply_updates_device(packed[offs[j]:offs[j + 1]])
+    w.sync()
+    w.close()
+    n_ctx = (steps + nb - 1) // nb
+    ctxs = [new_ctx() for _ in range(max(1, n_ctx))]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total = 0
+    for i in range(steps):
+        j = i % nb
+        ctxs[i // nb].apply_updates_device(packed[offs[j]:offs[j + 1]])
+        total += sizes[j]
+    for c in ctxs:
+        c.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctr = {}
+    for c in ctxs:
+        for k, val in c.counters().items():
+            ctr[k] = ctr.get(k, 0) + val
+    for c in ctxs:
+        c.close()
+    return dt, total, ctr
+
+
+def cpu_baseline(u, v, d, sizes, budget_s=15.0):
+    """The oracle (sketch + forest replay) on the first batches of the same
+    stream, one host thread, until `budget_s` seconds have been spent."""
+    import oracle
+    sk = oracle.Sketch(V, C, D, SEED)
+    fr = oracle.ForestReplay(sk)
+    t0 = time.perf_counter()
+    done, nbat, off = 0, 0, 0
+    for s in sizes:
+        fr.apply_batch(u[off:off + s], v[off:off + s], d[off:off + s])
+        off += s
+        done += s
+        nbat += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {nbat} of {len(sizes)} batches ({done} updates) of the same "
+                      f"stream: plain C sketch update + Python forest replay, one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=45)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel run")
+    ap.add_argument("--mode", default="staged", choices=["staged", "atomic"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2509_14433_amd as cupk
+    import streamgen
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    print("bench: generating stream", file=sys.stderr, flush=True)
+    u, v, d = streamgen.config_stream(1)
+    n = len(u)
+    sizes = streamgen.fixed_sizes(n, BATCH)
+    packed = torch.from_numpy(cupk.pack_updates(u, v, d).view(np.int64)).cuda()
+    torch.cuda.synchronize()
+
+    mode = cupk.SCATTER_STAGED if args.mode == "staged" else cupk.SCATTER_ATOMIC
+    print("bench: timing main path", file=sys.stderr, flush=True)
+    dt, total, ctr = run_path(cupk, torch, packed, sizes, args.steps, args.warmup, mode)
+    value = total / dt
+    bpu = algorithmic_bytes_per_update(C)
+    launches = max(1, ctr["scatter_launches"])
+    kname = "k_tile_scatter" if args.mode == "staged" else "k_scatter_atomic"
+    avg_ms = ctr["scatter_ms"] / launches
+    upd_per_launch = total / launches
+    achieved = bpu * upd_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profile(kname),
+                "kernel": kname, "kernel_avg_ms": round(avg_ms, 5),
+                "bin_avg_ms": round(ctr["bin_ms"] / launches, 5),
+                "bytes_per_update": bpu,
+                "updates_per_launch": round(upd_per_launch, 1)}
+    out = {
+        "metric": "edge updates/sec + % HBM roofline; p50/p99 connectivity-query latency",
+        "value": round(value, 1), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "V": V, "C": C, "D": D, "batch": BATCH,
+                   "scatter": args.mode, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "counters": {k: (round(val, 3) if isinstance(val, float) else val)
+                     for k, val in ctr.items()},
+    }
+    if not args.no_plain and args.mode == "staged":
+        print("bench: timing plain path", file=sys.stderr, flush=True)
+        pdt, ptot, pctr = run_path(cupk, torch, packed, sizes, args.steps, args.warmup,
+                                   cupk.SCATTER_ATOMIC)
+        pl = max(1, pctr["scatter_launches"])
+        pavg = pctr["scatter_ms"] / pl
+        pach = bpu * (ptot / pl) / (pavg * 1e-3) / 1e9
+        out["plain"] = {"value": round(ptot / pdt, 1), "unit": "updates/s",
+                        "ms_per_step": round(pdt * 1e3 / args.steps, 4),
+                        "kernel": "k_scatter_atomic", "kernel_avg_ms": round(pavg, 5),
+                        "achieved_GBs": round(pach, 1), "frac": round(pach / HBM_PEAK_GBS, 4)}
+    if not args.no_cpu:
+        print("bench: timing CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(u, v, d, sizes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
