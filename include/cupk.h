@@ -94,6 +94,10 @@ typedef struct {
      * vertices per LDS tile and depth rows kept in LDS. */
     uint32_t tile_vertices;
     uint32_t lds_rows;
+    /* Records per work item of the staged kernel (0 = default 4096) and
+     * blocks of its persistent grid (0 = default 2048). */
+    uint32_t chunk_records;
+    uint32_t tile_grid;
 } cupk_opts;
 
 /* Counters, cumulative since init. */

@@ -49,6 +49,8 @@ class cupk_opts(ctypes.Structure):
         ("time_kernels", ctypes.c_uint32),
         ("tile_vertices", ctypes.c_uint32),
         ("lds_rows", ctypes.c_uint32),
+        ("chunk_records", ctypes.c_uint32),
+        ("tile_grid", ctypes.c_uint32),
     ]
 
 
@@ -126,7 +128,7 @@ class Context:
 
     def __init__(self, V, C=0, D=0, seed=0, scatter_mode=SCATTER_STAGED, max_batch=0,
                  stream=None, use_torch_memory=True, time_kernels=False, tile_vertices=0,
-                 lds_rows=0):
+                 lds_rows=0, chunk_records=0, tile_grid=0):
         self._h = None
         self._sk_tensor = None
         opts = cupk_opts()
@@ -135,6 +137,8 @@ class Context:
         opts.time_kernels = 1 if time_kernels else 0
         opts.tile_vertices = tile_vertices
         opts.lds_rows = lds_rows
+        opts.chunk_records = chunk_records
+        opts.tile_grid = tile_grid
         torch = _torch()
         if stream is None and torch is not None and torch.cuda.is_available():
             # launch on torch's current stream so that torch-produced device

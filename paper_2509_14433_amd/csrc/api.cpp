@@ -98,7 +98,7 @@ struct cupk_ctx {
     HostBuf<uint64_t> h_fupd;
 
     // staged scatter
-    uint32_t tile_shift = 5, rows = 8, chunk = 4096, ntiles = 0;
+    uint32_t tile_shift = 5, rows = 8, chunk = 4096, ntiles = 0, tile_grid = 0;
     DevBuf<uint32_t> d_tcnt, d_toff, d_tcur, d_items;
     DevBuf<uint64_t> d_bins;
     uint32_t *d_nitems = nullptr;
@@ -113,6 +113,9 @@ struct cupk_ctx {
     uint64_t *d_misc = nullptr, *h_misc = nullptr;
 
     Forest forest;
+    std::vector<std::pair<uint32_t, uint64_t>> flag_scratch;
+    std::vector<uint8_t> slot_has;
+    std::vector<uint64_t> slot_val;
     cupk_counters_t ctr = {};
     std::string err;
 
@@ -438,15 +441,42 @@ int run_rounds(cupk_ctx *ctx)
 }
 
 // Apply the flagged updates of one batch to the forest, in stream order.
-void apply_flags(cupk_ctx *ctx, uint32_t nflag)
+void apply_flags(cupk_ctx *ctx, uint32_t nflag, uint32_t batch_n)
 {
     Forest &F = ctx->forest;
-    std::vector<std::pair<uint32_t, uint64_t>> fl(nflag);
-    for (uint32_t i = 0; i < nflag; i++) fl[i] = {ctx->h_fpos.p[i], ctx->h_fupd.p[i]};
-    std::sort(fl.begin(), fl.end(),
-              [](const std::pair<uint32_t, uint64_t> &a, const std::pair<uint32_t, uint64_t> &b) {
-                  return a.first < b.first;
-              });
+    // Restore stream order.  Entries were appended by whole waves in any
+    // order.  Dense lists (a large share of the batch flagged) go through a
+    // direct-address table over batch positions; sparse ones are bucketed by
+    // position >> 12 (counting sort) and each small bucket is sorted.
+    const uint32_t *pos = ctx->h_fpos.p;
+    const uint64_t *upd = ctx->h_fupd.p;
+    std::vector<std::pair<uint32_t, uint64_t>> &fl = ctx->flag_scratch;
+    fl.resize(nflag);
+    if ((uint64_t)nflag * 16 >= batch_n) {
+        ctx->slot_has.assign(batch_n, 0);
+        ctx->slot_val.resize(batch_n);
+        for (uint32_t i = 0; i < nflag; i++) {
+            ctx->slot_has[pos[i]] = 1;
+            ctx->slot_val[pos[i]] = upd[i];
+        }
+        uint32_t k = 0;
+        for (uint32_t q = 0; q < batch_n; q++)
+            if (ctx->slot_has[q]) fl[k++] = {q, ctx->slot_val[q]};
+    } else {
+        uint32_t maxpos = 0;
+        for (uint32_t i = 0; i < nflag; i++) maxpos = std::max(maxpos, pos[i]);
+        const uint32_t nb = (maxpos >> 12) + 1;
+        std::vector<uint32_t> start(nb + 1, 0);
+        for (uint32_t i = 0; i < nflag; i++) start[(pos[i] >> 12) + 1]++;
+        for (uint32_t b = 0; b < nb; b++) start[b + 1] += start[b];
+        std::vector<uint32_t> cur(start.begin(), start.end() - 1);
+        for (uint32_t i = 0; i < nflag; i++) fl[cur[pos[i] >> 12]++] = {pos[i], upd[i]};
+        for (uint32_t b = 0; b < nb; b++)
+            if (start[b + 1] - start[b] > 1)
+                std::sort(fl.begin() + start[b], fl.begin() + start[b + 1],
+                          [](const std::pair<uint32_t, uint64_t> &x,
+                             const std::pair<uint32_t, uint64_t> &y) { return x.first < y.first; });
+    }
     bool changed = false;
     for (auto &f : fl) {
         const uint64_t p = f.second;
@@ -492,7 +522,6 @@ int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
     if (rc != CUPK_OK) return rc;
     const bool staged = ctx->opts.scatter_mode == CUPK_SCATTER_STAGED;
     HIPCHK(launch_zero32(ctx->s, ctx->d_hdr, HDR_WORDS));
-    if (staged) HIPCHK(launch_zero32(ctx->s, ctx->d_tcnt.p, ctx->ntiles));
     HIPCHK(launch_classify(ctx->s, d_upd, n, ctx->V, ctx->d_lbl, ctx->d_par, ctx->d_hdr,
                            ctx->d_fpos.p, ctx->d_fupd.p, staged ? ctx->d_tcnt.p : nullptr,
                            ctx->tile_shift, ctx->ntiles));
@@ -521,6 +550,7 @@ int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
         p.ntiles = ctx->ntiles;
         p.chunk = ctx->chunk;
         p.items_cap = (uint32_t)(2 * (size_t)n / ctx->chunk + ctx->ntiles + 1);
+        p.grid = ctx->tile_grid;
         HIPCHK(launch_staged(ctx->s, d_upd, n, sk, ctx->d_hdr, p, ctx->d_tcnt.p, ctx->d_toff.p,
                              ctx->d_tcur.p, ctx->d_bins.p, ctx->d_items.p, ctx->d_nitems,
                              ts ? ts->tb : nullptr));
@@ -546,7 +576,7 @@ int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
         HIPCHK(hipMemcpyAsync(ctx->h_fupd.p, ctx->d_fupd.p, (size_t)nflag * 8,
                               hipMemcpyDeviceToHost, ctx->cs));
         HIPCHK(hipStreamSynchronize(ctx->cs));
-        apply_flags(ctx, nflag);
+        apply_flags(ctx, nflag, n);
     }
     ctx->ctr.flagged += nflag;
     ctx->ctr.updates += n;
@@ -667,8 +697,11 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     rows = std::min(rows, D);
     uint32_t tv = ctx->opts.tile_vertices;
     if (tv == 0) {
+        // measured best on the V=16384, C=14 workload: 16 vertices per tile
+        // (about 28 KiB of LDS, several blocks per CU); smaller when C*rows
+        // does not fit
         tv = 1;
-        while ((size_t)2 * rows * C * (tv * 2) * 8 <= 65536 && tv < 64) tv *= 2;
+        while ((size_t)2 * rows * C * (tv * 2) * 8 <= 32768 && tv < 16) tv *= 2;
     }
     uint32_t sh = 0;
     while ((1u << sh) < tv) sh++;
@@ -676,12 +709,15 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     if ((size_t)2 * rows * C * tv * 8 > 65536) return ctx->invalid("staged tile exceeds 64 KiB LDS");
     ctx->tile_shift = sh;
     ctx->rows = rows;
-    ctx->chunk = 4096;
+    ctx->chunk = ctx->opts.chunk_records ? ctx->opts.chunk_records : 4096;
+    ctx->tile_grid = ctx->opts.tile_grid;
     ctx->ntiles = (uint32_t)(((uint64_t)V + tv - 1) >> sh);
     if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
         HIPCHK(grow(ctx->d_tcnt, ctx->ntiles + 1));
         HIPCHK(grow(ctx->d_toff, ctx->ntiles + 1));
         HIPCHK(grow(ctx->d_tcur, ctx->ntiles + 1));
+        // the scan kernel re-zeroes the counts after every batch
+        HIPCHK(launch_zero32(ctx->s, ctx->d_tcnt.p, ctx->ntiles + 1));
     }
     const size_t mb = ctx->opts.max_batch ? ctx->opts.max_batch : (1u << 20);
     int rc = ensure_batch_buffers(ctx, mb);

@@ -236,12 +236,14 @@ DEVI uint32_t block_exscan(uint32_t x, uint32_t &total, uint32_t *sh)
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(
-    const uint32_t *__restrict__ cnt, uint32_t ntiles, uint32_t chunk, uint32_t *__restrict__ off,
+    uint32_t *__restrict__ cnt, uint32_t ntiles, uint32_t chunk, uint32_t *__restrict__ off,
     uint32_t *__restrict__ cur, uint32_t *__restrict__ items, uint32_t items_cap,
     uint32_t *__restrict__ nitems, const uint32_t *__restrict__ hdr)
 {
     __shared__ uint32_t sh[160];
     if (hdr[HDR_ERR]) {
+        // rejected batch: leave the counts zeroed for the next one
+        for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) cnt[t] = 0;
         if (threadIdx.x == 0) *nitems = 0;
         return;
     }
@@ -249,6 +251,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(
     for (uint32_t base = 0; base < ntiles; base += kScanThreads) {
         const uint32_t t = base + threadIdx.x;
         const uint32_t c = t < ntiles ? cnt[t] : 0u;
+        if (t < ntiles) cnt[t] = 0;  // ready for the next batch's counts
         const uint32_t k = (c + chunk - 1) / chunk;
         uint32_t tot_c, tot_k;
         const uint32_t ex_c = block_exscan<kScanThreads>(c, tot_c, sh);
@@ -330,6 +333,41 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
 
 constexpr uint32_t kTileThreads = 256;
 
+// XOR one (record, column) pair into the LDS delta, or into HBM for depths
+// beyond the rows held in LDS.
+DEVI void tile_column(const DevSketch &sk, uint64_t *la, uint64_t *lg, uint32_t TV,
+                      uint32_t rows, uint32_t c, uint64_t seed, uint64_t x, uint32_t u,
+                      uint32_t v, bool inu, bool inv, uint32_t lu, uint32_t lv)
+{
+    const uint64_t h = mix64(x ^ seed);
+    const uint32_t d = depth_of(h, sk.D);
+    if (d < rows) {
+        const uint32_t rowoff = (d * sk.C + c) * TV;
+        if (inu) {
+            lxor(&la[rowoff + lu], x);
+            lxor(&lg[rowoff + lu], h);
+        }
+        if (inv) {
+            lxor(&la[rowoff + lv], x);
+            lxor(&lg[rowoff + lv], h);
+        }
+    } else {
+        if (inu) {
+            uint64_t *bu = sk.b + (((uint64_t)u * sk.D + d) * sk.C + c) * 2;
+            gxor(bu, x);
+            gxor(bu + 1, h);
+        }
+        if (inv) {
+            uint64_t *bv = sk.b + (((uint64_t)v * sk.D + d) * sk.C + c) * 2;
+            gxor(bv, x);
+            gxor(bv + 1, h);
+        }
+    }
+}
+
+// CMAX > 0: columns unrolled at compile time (C <= CMAX); CMAX == 0: a
+// runtime loop for any C.
+template <uint32_t CMAX>
 __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
     DevSketch sk, const uint64_t *__restrict__ bins, const uint32_t *__restrict__ off,
     const uint32_t *__restrict__ items, const uint32_t *__restrict__ nitems_p, uint32_t tile_shift,
@@ -343,6 +381,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
     uint64_t *la = lds;                    // alpha plane [d][c][vl]
     uint64_t *lg = lds + plane;            // gamma plane
     const uint32_t nitems = *nitems_p;
+    uint64_t seed[CMAX > 0 ? CMAX : 1];
+    if (CMAX > 0) {
+#pragma unroll
+        for (uint32_t c = 0; c < CMAX; c++) seed[c] = c < C ? sk.seeds[c] : 0;
+    }
 
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const uint32_t tile = items[2 * it];
@@ -363,31 +406,13 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
             const bool inu = (u >> tile_shift) == tile;
             const bool inv = (v >> tile_shift) == tile;
             const uint32_t lu = u - w0, lv = v - w0;
-            for (uint32_t c = 0; c < C; c++) {
-                const uint64_t h = mix64(x ^ sk.seeds[c]);
-                const uint32_t d = depth_of(h, D);
-                if (d < rows) {
-                    const uint32_t rowoff = (d * C + c) * TV;
-                    if (inu) {
-                        lxor(&la[rowoff + lu], x);
-                        lxor(&lg[rowoff + lu], h);
-                    }
-                    if (inv) {
-                        lxor(&la[rowoff + lv], x);
-                        lxor(&lg[rowoff + lv], h);
-                    }
-                } else {
-                    if (inu) {
-                        uint64_t *bu = sk.b + (((uint64_t)u * D + d) * C + c) * 2;
-                        gxor(bu, x);
-                        gxor(bu + 1, h);
-                    }
-                    if (inv) {
-                        uint64_t *bv = sk.b + (((uint64_t)v * D + d) * C + c) * 2;
-                        gxor(bv, x);
-                        gxor(bv + 1, h);
-                    }
-                }
+            if (CMAX > 0) {
+#pragma unroll
+                for (uint32_t c = 0; c < (CMAX > 0 ? CMAX : 1); c++)
+                    if (c < C) tile_column(sk, la, lg, TV, rows, c, seed[c], x, u, v, inu, inv, lu, lv);
+            } else {
+                for (uint32_t c = 0; c < C; c++)
+                    tile_column(sk, la, lg, TV, rows, c, sk.seeds[c], x, u, v, inu, inv, lu, lv);
             }
         }
         __syncthreads();
@@ -437,9 +462,16 @@ hipError_t launch_staged(hipStream_t s, const uint64_t *upd, uint32_t n, DevSket
     }
     const size_t lds = (size_t)2 * p.rows * sk.C * (1u << p.tile_shift) * sizeof(uint64_t);
     // Persistent grid: a few blocks per CU, each looping over work items.
-    const uint32_t grid = min(p.items_cap, 256u * 8u);
-    k_tile_scatter<<<grid, kTileThreads, lds, s>>>(sk, bins, tile_off, items, nitems, p.tile_shift,
-                                                  p.rows, p.chunk, hdr);
+    const uint32_t grid = min(p.items_cap, p.grid ? p.grid : 256u * 8u);
+#define CUPK_TILE_LAUNCH(CM)                                                                  \
+    k_tile_scatter<CM><<<grid, kTileThreads, lds, s>>>(sk, bins, tile_off, items, nitems,     \
+                                                       p.tile_shift, p.rows, p.chunk, hdr)
+    if (sk.C <= 8) CUPK_TILE_LAUNCH(8);
+    else if (sk.C <= 16) CUPK_TILE_LAUNCH(16);
+    else if (sk.C <= 24) CUPK_TILE_LAUNCH(24);
+    else if (sk.C <= 32) CUPK_TILE_LAUNCH(32);
+    else CUPK_TILE_LAUNCH(0);
+#undef CUPK_TILE_LAUNCH
     return hipGetLastError();
 }
 

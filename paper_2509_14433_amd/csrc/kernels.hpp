@@ -25,6 +25,7 @@ struct StagedParams {
     uint32_t ntiles;
     uint32_t chunk;        // max records per work item
     uint32_t items_cap;    // capacity of the work-item array
+    uint32_t grid;         // blocks of the persistent tile kernel (0 = default)
 };
 
 // Per-batch: validation, structural classification and compaction of the
