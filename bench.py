@@ -125,6 +125,38 @@ def cpu_baseline(u, v, d, sizes, budget_s=15.0):
                       f"stream: plain C sketch update + Python forest replay, one thread"}
 
 
+def served_leg(cupk, u, v, d, rho=100_000, inflight=4, max_batch=BATCH):
+    """The same stream through the serving loop: update requests of `rho`
+    updates, each followed by a Connected query on a random pair, pushed as
+    fast as memory admission allows (a budget of `inflight` requests).
+    Inputs come from host memory (PCIe included).  Returns updates/s and the
+    query latency percentiles (submission to answer)."""
+    import numpy as np
+    ctx = cupk.Context(V, C, D, SEED, max_batch=max_batch)
+    ctx.serve_start(max_batch=max_batch, mem_budget_bytes=inflight * rho * 8)
+    rng = np.random.default_rng(11)
+    n = len(u)
+    qs = rng.integers(0, V, size=(n // rho + 2, 2))
+    t0 = time.perf_counter()
+    tickets = []
+    for k, s in enumerate(range(0, n, rho)):
+        tickets.append(ctx.submit_updates(u[s:s + rho], v[s:s + rho], d[s:s + rho]))
+        tickets.append(ctx.submit_query(int(qs[k, 0]), int(qs[k, 1])))
+    for t in tickets:
+        ctx.wait(t)
+    dt = time.perf_counter() - t0
+    st = ctx.serve_stats()
+    ctx.serve_stop()
+    ctx.close()
+    return {"value": round(n / dt, 1), "unit": "updates/s", "queries": st["queries"],
+            "query_p50_us": round(st["query_p50_us"], 1),
+            "query_p99_us": round(st["query_p99_us"], 1),
+            "query_max_us": round(st["query_max_us"], 1), "batches": st["batches"],
+            "admission_waits": st["admission_waits"],
+            "setup": f"update requests of {rho} updates, a query after each, admission budget "
+                     f"{inflight} requests ({inflight * rho * 8} B), host-memory input"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +164,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel run")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served run")
     ap.add_argument("--mode", default="staged", choices=["staged", "atomic"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -193,6 +226,11 @@ def main():
                         "ms_per_step": round(pdt * 1e3 / args.steps, 4),
                         "kernel": "k_scatter_atomic", "kernel_avg_ms": round(pavg, 5),
                         "achieved_GBs": round(pach, 1), "frac": round(pach / HBM_PEAK_GBS, 4)}
+    if not args.no_serve:
+        print("bench: timing served path", file=sys.stderr, flush=True)
+        out["served"] = served_leg(cupk, u, v, d)
+        out["query_latency_us"] = {"p50": out["served"]["query_p50_us"],
+                                   "p99": out["served"]["query_p99_us"]}
     if not args.no_cpu:
         print("bench: timing CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(u, v, d, sizes)

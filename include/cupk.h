@@ -114,6 +114,9 @@ typedef struct {
     uint64_t scatter_launches;   /* scatter kernel launches                      */
     double scatter_ms;           /* summed scatter kernel time (time_kernels)    */
     double bin_ms;               /* summed binning kernel time (time_kernels)    */
+    double host_wait_ms;         /* host time waiting for classification results */
+    double host_flags_ms;        /* host time applying flagged updates to forest */
+    double host_rounds_ms;       /* host time in replacement rounds (incl. GPU)  */
 } cupk_counters_t;
 
 /* Bytes of device memory the sketch of (V, C, D) occupies. */
@@ -221,6 +224,80 @@ int cupk_counters(cupk_ctx *ctx, cupk_counters_t *out);
 
 /* Wait for all work the context queued. */
 int cupk_sync(cupk_ctx *ctx);
+
+/* ---- autotuner ------------------------------------------------------------
+ * Picks the staged scatter's tile geometry (vertices per LDS tile, depth
+ * rows in LDS, records per work item) by timing every candidate on a sample
+ * batch, and derives a batch-size schedule.  Each candidate applies the
+ * sample an even number of times, so the XOR toggles cancel and the sketch
+ * is left exactly as it was; the forest is not touched.
+ * d_sample: n packed updates in device memory (format of
+ * cupk_apply_updates_device).  The chosen setting stays in force on ctx.
+ * Errors: CUPK_EINVAL (not in staged mode, n == 0, invalid sample). */
+typedef struct {
+    uint32_t tile_vertices;    /* chosen                                       */
+    uint32_t lds_rows;
+    uint32_t chunk_records;
+    uint32_t candidates;       /* settings timed                               */
+    double best_ms;            /* bin + scatter time of the sample, chosen     */
+    double before_ms;          /* same with the setting in force before        */
+    uint32_t batch_target;     /* smallest timed batch reaching 80% of the
+                                  best throughput (batch-size schedule)       */
+    double batch_ms[8];        /* time of prefixes n/128, n/64, ... , n        */
+    uint32_t batch_sizes[8];
+} cupk_tune_result;
+
+int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_result *out);
+
+/* ---- serving loop -------------------------------------------------------
+ * Continuous batching of interleaved update and query requests.  While the
+ * loop runs, a worker thread owns the context: use only the calls below on
+ * it until cupk_serve_stop.  Requests are ordered by submission; a query
+ * observes exactly the updates submitted before it (queries flush pending
+ * updates first, Sec. 4.3).  Update requests submitted while a batch is on
+ * the GPU join the next batch. */
+
+typedef struct {
+    uint32_t max_batch;        /* updates per device batch (0 = 1<<20)         */
+    uint32_t nonblocking;      /* 1: refuse with CUPK_EBUSY instead of waiting */
+    size_t mem_budget_bytes;   /* host staging for pending updates, 8 B each
+                                  (0 = 64 MiB); admission waits for room      */
+} cupk_serve_opts;
+
+typedef struct {
+    uint64_t update_requests;  /* update requests admitted                     */
+    uint64_t queries;          /* queries admitted                             */
+    uint64_t batches;          /* device batches applied                       */
+    uint64_t updates;          /* updates applied                              */
+    uint64_t admission_waits;  /* submissions that waited for memory           */
+    double query_p50_us;       /* query latency, submission to answer          */
+    double query_p99_us;
+    double query_max_us;
+} cupk_serve_stats_t;
+
+/* Start the loop.  CUPK_EINVAL if it already runs. */
+int cupk_serve_start(cupk_ctx *ctx, const cupk_serve_opts *opts);
+
+/* Submit n updates (host arrays, copied before return; validated
+ * all-or-nothing: CUPK_EINVAL for u == v or an endpoint >= V, or for a
+ * request larger than the memory budget).  *ticket identifies it.  Blocks
+ * for admission unless the loop is non-blocking (then CUPK_EBUSY).  Safe to
+ * call from several threads. */
+int cupk_submit_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
+                        const uint8_t *is_delete, size_t n, uint64_t *ticket);
+
+/* Submit Connected(u, v). */
+int cupk_submit_query(cupk_ctx *ctx, uint32_t u, uint32_t v, uint64_t *ticket);
+
+/* Wait for a ticket; *result = 1/0 for a query, the apply status (0 or a
+ * negative error) for an update request.  Each ticket is waited for once. */
+int cupk_wait(cupk_ctx *ctx, uint64_t ticket, int32_t *result);
+
+int cupk_serve_stats(cupk_ctx *ctx, cupk_serve_stats_t *out);
+int cupk_serve_reset_stats(cupk_ctx *ctx);
+
+/* Drain the queue and stop the loop; the context is usable again. */
+int cupk_serve_stop(cupk_ctx *ctx);
 
 /* Static text of a return code. */
 const char *cupk_strerror(int code);

@@ -58,7 +58,28 @@ class cupk_counters_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "updates", "batches", "flagged", "links", "cuts", "rounds", "sets_reduced",
         "slabs_reduced", "sample_failed", "scatter_launches")] + [
-        ("scatter_ms", ctypes.c_double), ("bin_ms", ctypes.c_double)]
+        ("scatter_ms", ctypes.c_double), ("bin_ms", ctypes.c_double),
+        ("host_wait_ms", ctypes.c_double), ("host_flags_ms", ctypes.c_double),
+        ("host_rounds_ms", ctypes.c_double)]
+
+
+class cupk_serve_opts(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_uint32), ("nonblocking", ctypes.c_uint32),
+                ("mem_budget_bytes", ctypes.c_size_t)]
+
+
+class cupk_serve_stats_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "update_requests", "queries", "batches", "updates", "admission_waits")] + [
+        (n, ctypes.c_double) for n in ("query_p50_us", "query_p99_us", "query_max_us")]
+
+
+class cupk_tune_result(ctypes.Structure):
+    _fields_ = [("tile_vertices", ctypes.c_uint32), ("lds_rows", ctypes.c_uint32),
+                ("chunk_records", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
+                ("best_ms", ctypes.c_double), ("before_ms", ctypes.c_double),
+                ("batch_target", ctypes.c_uint32), ("batch_ms", ctypes.c_double * 8),
+                ("batch_sizes", ctypes.c_uint32 * 8)]
 
 
 def _load():
@@ -84,6 +105,14 @@ def _load():
         "cupk_component_labels": (ctypes.c_int, [p, p]),
         "cupk_counters": (ctypes.c_int, [p, ctypes.POINTER(cupk_counters_t)]),
         "cupk_sync": (ctypes.c_int, [p]),
+        "cupk_autotune": (ctypes.c_int, [p, p, sz, ctypes.POINTER(cupk_tune_result)]),
+        "cupk_serve_start": (ctypes.c_int, [p, ctypes.POINTER(cupk_serve_opts)]),
+        "cupk_submit_updates": (ctypes.c_int, [p, p, p, p, sz, ctypes.POINTER(u64)]),
+        "cupk_submit_query": (ctypes.c_int, [p, u32, u32, ctypes.POINTER(u64)]),
+        "cupk_wait": (ctypes.c_int, [p, u64, ctypes.POINTER(i32)]),
+        "cupk_serve_stats": (ctypes.c_int, [p, ctypes.POINTER(cupk_serve_stats_t)]),
+        "cupk_serve_reset_stats": (ctypes.c_int, [p]),
+        "cupk_serve_stop": (ctypes.c_int, [p]),
         "cupk_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "cupk_last_error": (ctypes.c_char_p, [p]),
     }
@@ -288,3 +317,50 @@ class Context:
 
     def sync(self):
         self._check(lib.cupk_sync(self._h))
+
+    def autotune(self, sample) -> dict:
+        """Tune the staged scatter on a device sample batch (cuda tensor of
+        packed updates); the sketch is left unchanged."""
+        assert sample.is_cuda and sample.element_size() == 8 and sample.is_contiguous()
+        r = cupk_tune_result()
+        self._check(lib.cupk_autotune(self._h, ctypes.c_void_p(sample.data_ptr()),
+                                      sample.numel(), ctypes.byref(r)))
+        out = {f: getattr(r, f) for f, _ in cupk_tune_result._fields_}
+        out["batch_ms"] = list(r.batch_ms)
+        out["batch_sizes"] = list(r.batch_sizes)
+        return out
+
+    # -- serving loop ---------------------------------------------------------------
+    def serve_start(self, max_batch=0, mem_budget_bytes=0, nonblocking=False):
+        o = cupk_serve_opts(max_batch, 1 if nonblocking else 0, mem_budget_bytes)
+        self._check(lib.cupk_serve_start(self._h, ctypes.byref(o)))
+
+    def submit_updates(self, u, v, is_delete) -> int:
+        u = np.ascontiguousarray(u, dtype=np.uint32)
+        v = np.ascontiguousarray(v, dtype=np.uint32)
+        d = np.ascontiguousarray(is_delete, dtype=np.uint8)
+        t = ctypes.c_uint64(0)
+        self._check(lib.cupk_submit_updates(self._h, _ptr(u), _ptr(v), _ptr(d), u.shape[0],
+                                            ctypes.byref(t)))
+        return t.value
+
+    def submit_query(self, u, v) -> int:
+        t = ctypes.c_uint64(0)
+        self._check(lib.cupk_submit_query(self._h, u, v, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket) -> int:
+        r = ctypes.c_int32(0)
+        self._check(lib.cupk_wait(self._h, ticket, ctypes.byref(r)))
+        return r.value
+
+    def serve_stats(self) -> dict:
+        st = cupk_serve_stats_t()
+        self._check(lib.cupk_serve_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in cupk_serve_stats_t._fields_}
+
+    def serve_reset_stats(self):
+        self._check(lib.cupk_serve_reset_stats(self._h))
+
+    def serve_stop(self):
+        self._check(lib.cupk_serve_stop(self._h))

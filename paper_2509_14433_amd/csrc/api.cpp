@@ -15,8 +15,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -24,10 +27,18 @@
 #include "cupk.h"
 #include "forest.hpp"
 #include "kernels.hpp"
+#include "serve.hpp"
 
 using namespace cupk;
 
 namespace {
+
+double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
 
 // Message of the last failed cupk_sketch_init (no context survives it).
 thread_local std::string g_init_error;
@@ -92,9 +103,8 @@ struct cupk_ctx {
     DevBuf<uint64_t> d_upd;
     HostBuf<uint64_t> h_upd;
     uint32_t *d_hdr = nullptr, *h_hdr = nullptr;
-    DevBuf<uint32_t> d_fpos;
-    DevBuf<uint64_t> d_fupd;
-    HostBuf<uint32_t> h_fpos;
+    DevBuf<uint32_t> d_fcnt, d_foff;  // flagged updates: per-block counts and offsets,
+    DevBuf<uint64_t> d_fupd, d_oupd;  // per-block regions, the compacted ordered list
     HostBuf<uint64_t> h_fupd;
 
     // staged scatter
@@ -112,10 +122,11 @@ struct cupk_ctx {
     DevBuf<uint64_t> d_tmp;
     uint64_t *d_misc = nullptr, *h_misc = nullptr;
 
+
+    int device = 0;
+    bool trace = false;  // CUPK_TRACE=1: per-batch host timings on stderr
+    std::unique_ptr<Server> server;
     Forest forest;
-    std::vector<std::pair<uint32_t, uint64_t>> flag_scratch;
-    std::vector<uint8_t> slot_has;
-    std::vector<uint64_t> slot_val;
     cupk_counters_t ctr = {};
     std::string err;
 
@@ -440,46 +451,21 @@ int run_rounds(cupk_ctx *ctx)
     return CUPK_OK;
 }
 
-// Apply the flagged updates of one batch to the forest, in stream order.
-void apply_flags(cupk_ctx *ctx, uint32_t nflag, uint32_t batch_n)
+// Apply flagged updates [k0, k1) of one batch (host copies, stream order) to
+// the forest.  Returns true when the rest of the list cannot change the
+// forest: without flagged deletes nothing splits a tree during the walk, so
+// once one tree is left no later insert can link.
+bool apply_flags(cupk_ctx *ctx, uint32_t k0, uint32_t k1, bool all_inserts)
 {
     Forest &F = ctx->forest;
-    // Restore stream order.  Entries were appended by whole waves in any
-    // order.  Dense lists (a large share of the batch flagged) go through a
-    // direct-address table over batch positions; sparse ones are bucketed by
-    // position >> 12 (counting sort) and each small bucket is sorted.
-    const uint32_t *pos = ctx->h_fpos.p;
     const uint64_t *upd = ctx->h_fupd.p;
-    std::vector<std::pair<uint32_t, uint64_t>> &fl = ctx->flag_scratch;
-    fl.resize(nflag);
-    if ((uint64_t)nflag * 16 >= batch_n) {
-        ctx->slot_has.assign(batch_n, 0);
-        ctx->slot_val.resize(batch_n);
-        for (uint32_t i = 0; i < nflag; i++) {
-            ctx->slot_has[pos[i]] = 1;
-            ctx->slot_val[pos[i]] = upd[i];
+    bool done = false;
+    for (uint32_t k = k0; k < k1; k++) {
+        if (all_inserts && F.n_trees() == 1) {
+            done = true;
+            break;
         }
-        uint32_t k = 0;
-        for (uint32_t q = 0; q < batch_n; q++)
-            if (ctx->slot_has[q]) fl[k++] = {q, ctx->slot_val[q]};
-    } else {
-        uint32_t maxpos = 0;
-        for (uint32_t i = 0; i < nflag; i++) maxpos = std::max(maxpos, pos[i]);
-        const uint32_t nb = (maxpos >> 12) + 1;
-        std::vector<uint32_t> start(nb + 1, 0);
-        for (uint32_t i = 0; i < nflag; i++) start[(pos[i] >> 12) + 1]++;
-        for (uint32_t b = 0; b < nb; b++) start[b + 1] += start[b];
-        std::vector<uint32_t> cur(start.begin(), start.end() - 1);
-        for (uint32_t i = 0; i < nflag; i++) fl[cur[pos[i] >> 12]++] = {pos[i], upd[i]};
-        for (uint32_t b = 0; b < nb; b++)
-            if (start[b + 1] - start[b] > 1)
-                std::sort(fl.begin() + start[b], fl.begin() + start[b + 1],
-                          [](const std::pair<uint32_t, uint64_t> &x,
-                             const std::pair<uint32_t, uint64_t> &y) { return x.first < y.first; });
-    }
-    bool changed = false;
-    for (auto &f : fl) {
-        const uint64_t p = f.second;
+        const uint64_t p = upd[k];
         uint32_t a = (uint32_t)p, b = (uint32_t)(p >> 32) & 0x7fffffffu;
         const bool del = (p >> 63) != 0;
         if (a > b) std::swap(a, b);
@@ -487,22 +473,24 @@ void apply_flags(cupk_ctx *ctx, uint32_t nflag, uint32_t batch_n)
             if (!F.same_tree(a, b)) {
                 F.link(a, b);
                 ctx->ctr.links++;
-                changed = true;
+                ctx->forest_dev_stale = true;
             }
         } else if (F.is_edge(a, b)) {
             F.cut(a, b);
             ctx->ctr.cuts++;
-            changed = true;
+            ctx->forest_dev_stale = true;
         }
     }
-    if (changed) ctx->forest_dev_stale = true;
+    return done || (all_inserts && F.n_trees() == 1);
 }
 
 int ensure_batch_buffers(cupk_ctx *ctx, size_t n)
 {
-    HIPCHK(grow(ctx->d_fpos, n));
-    HIPCHK(grow(ctx->d_fupd, n));
-    HIPCHK(grow(ctx->h_fpos, n));
+    const size_t nb = (n + 4095) / 4096;
+    HIPCHK(grow(ctx->d_fupd, nb * 4096));
+    HIPCHK(grow(ctx->d_fcnt, nb + 1));
+    HIPCHK(grow(ctx->d_foff, nb + 1));
+    HIPCHK(grow(ctx->d_oupd, n));
     HIPCHK(grow(ctx->h_fupd, n));
     if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
         HIPCHK(grow(ctx->d_bins, 2 * n));
@@ -523,7 +511,7 @@ int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
     const bool staged = ctx->opts.scatter_mode == CUPK_SCATTER_STAGED;
     HIPCHK(launch_zero32(ctx->s, ctx->d_hdr, HDR_WORDS));
     HIPCHK(launch_classify(ctx->s, d_upd, n, ctx->V, ctx->d_lbl, ctx->d_par, ctx->d_hdr,
-                           ctx->d_fpos.p, ctx->d_fupd.p, staged ? ctx->d_tcnt.p : nullptr,
+                           ctx->d_fupd.p, ctx->d_fcnt.p, staged ? ctx->d_tcnt.p : nullptr,
                            ctx->tile_shift, ctx->ntiles));
     HIPCHK(hipEventRecord(ctx->ev_cls, ctx->s));
     HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->ev_cls, 0));
@@ -564,25 +552,51 @@ int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
     }
 
     // host: flagged updates -> forest, overlapping the scatter
+    double t0 = now_ms();
     HIPCHK(hipEventSynchronize(ctx->ev_hdr));
+    double t1 = now_ms();
+    ctx->ctr.host_wait_ms += t1 - t0;
     if (ctx->h_hdr[HDR_ERR]) {
         HIPCHK(hipStreamSynchronize(ctx->s));
         return ctx->invalid("batch holds an update with u == v or an endpoint >= V");
     }
     const uint32_t nflag = ctx->h_hdr[HDR_NFLAG];
+    const uint32_t nflag_del = ctx->h_hdr[HDR_NFLAG_DEL];
+    double tcopy = t1;
     if (nflag) {
-        HIPCHK(hipMemcpyAsync(ctx->h_fpos.p, ctx->d_fpos.p, (size_t)nflag * 4,
-                              hipMemcpyDeviceToHost, ctx->cs));
-        HIPCHK(hipMemcpyAsync(ctx->h_fupd.p, ctx->d_fupd.p, (size_t)nflag * 8,
-                              hipMemcpyDeviceToHost, ctx->cs));
-        HIPCHK(hipStreamSynchronize(ctx->cs));
-        apply_flags(ctx, nflag, n);
+        // pack the per-block regions into one ordered list (copy stream,
+        // already ordered after the classify kernel), then fetch and walk it
+        // in growing chunks: the walk may stop early
+        HIPCHK(launch_flag_compact(ctx->cs, n, ctx->d_fupd.p, ctx->d_fcnt.p, ctx->d_foff.p,
+                                   ctx->d_oupd.p));
+        uint32_t k0 = 0, step = 1u << 16;
+        while (k0 < nflag) {
+            const uint32_t m = std::min(step, nflag - k0);
+            HIPCHK(hipMemcpyAsync(ctx->h_fupd.p + k0, ctx->d_oupd.p + k0, (size_t)m * 8,
+                                  hipMemcpyDeviceToHost, ctx->cs));
+            HIPCHK(hipStreamSynchronize(ctx->cs));
+            if (k0 == 0) tcopy = now_ms();
+            const bool stop = apply_flags(ctx, k0, k0 + m, nflag_del == 0);
+            k0 += m;
+            step *= 2;
+            if (stop) break;
+        }
     }
+    double t2 = now_ms();
+    ctx->ctr.host_flags_ms += t2 - t1;
     ctx->ctr.flagged += nflag;
     ctx->ctr.updates += n;
     ctx->ctr.batches++;
     ctx->ctr.scatter_launches++;
-    return run_rounds(ctx);
+    rc = run_rounds(ctx);
+    const double t3 = now_ms();
+    ctx->ctr.host_rounds_ms += t3 - t2;
+    if (ctx->trace)
+        fprintf(stderr,
+                "cupk batch %llu n=%u nflag=%u wait=%.3f copy=%.3f flags=%.3f rounds=%.3f ms\n",
+                (unsigned long long)ctx->ctr.batches, n, nflag, t1 - t0, tcopy - t1, t2 - tcopy,
+                t3 - t2);
+    return rc;
 }
 
 int apply_device(cupk_ctx *ctx, const uint64_t *d_upd, size_t n)
@@ -595,8 +609,25 @@ int apply_device(cupk_ctx *ctx, const uint64_t *d_upd, size_t n)
     return CUPK_OK;
 }
 
+// One batch of packed updates held in host memory (serving loop).
+int apply_packed_host(cupk_ctx *ctx, const uint64_t *packed, size_t n)
+{
+    if (n == 0) return CUPK_OK;
+    HIPCHK(grow(ctx->h_upd, n));
+    HIPCHK(grow(ctx->d_upd, n));
+    std::copy(packed, packed + n, ctx->h_upd.p);
+    HIPCHK(hipMemcpyAsync(ctx->d_upd.p, ctx->h_upd.p, n * 8, hipMemcpyHostToDevice, ctx->s));
+    return apply_device(ctx, ctx->d_upd.p, n);
+}
+
+int connected_impl(cupk_ctx *ctx, uint32_t u, uint32_t v)
+{
+    return ctx->forest.same_tree(u, v) ? 1 : 0;
+}
+
 void destroy(cupk_ctx *ctx)
 {
+    ctx->server.reset();
     if (ctx->s) (void)hipStreamSynchronize(ctx->s);
     if (ctx->cs) (void)hipStreamSynchronize(ctx->cs);
     if (ctx->own_sk && ctx->d_sk) (void)hipFree(ctx->d_sk);
@@ -612,9 +643,10 @@ void destroy(cupk_ctx *ctx)
     if (ctx->h_misc) (void)hipHostFree(ctx->h_misc);
     release(ctx->d_upd);
     release(ctx->h_upd);
-    release(ctx->d_fpos);
     release(ctx->d_fupd);
-    release(ctx->h_fpos);
+    release(ctx->d_oupd);
+    release(ctx->d_foff);
+    release(ctx->d_fcnt);
     release(ctx->h_fupd);
     release(ctx->d_tcnt);
     release(ctx->d_toff);
@@ -642,6 +674,34 @@ void destroy(cupk_ctx *ctx)
     delete ctx;
 }
 
+// Staged-scatter geometry: tv vertices per tile (power of two), `rows` depth
+// rows in LDS, `chunk` records per work item.
+int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk)
+{
+    uint32_t sh = 0;
+    while ((1u << sh) < tv) sh++;
+    if (tv == 0 || (1u << sh) != tv) return ctx->invalid("tile_vertices must be a power of two");
+    if (rows < 1 || rows > ctx->D) return ctx->invalid("lds_rows must be in [1, D]");
+    if ((size_t)2 * rows * ctx->C * tv * 8 > 65536)
+        return ctx->invalid("staged tile exceeds 64 KiB LDS");
+    if (chunk < 64) return ctx->invalid("chunk_records must be >= 64");
+    ctx->tile_shift = sh;
+    ctx->rows = rows;
+    ctx->chunk = chunk;
+    ctx->ntiles = (uint32_t)(((uint64_t)ctx->V + tv - 1) >> sh);
+    if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
+        HIPCHK(grow(ctx->d_tcnt, ctx->ntiles + 1));
+        HIPCHK(grow(ctx->d_toff, ctx->ntiles + 1));
+        HIPCHK(grow(ctx->d_tcur, ctx->ntiles + 1));
+        // the scan kernel re-zeroes the counts after every batch
+        HIPCHK(launch_zero32(ctx->s, ctx->d_tcnt.p, ctx->ntiles + 1));
+        // work-item capacity depends on ntiles and chunk
+        const size_t icap = 2 * ctx->d_fupd.cap / chunk + ctx->ntiles + 1;
+        HIPCHK(grow(ctx->d_items, 2 * icap));
+    }
+    return CUPK_OK;
+}
+
 int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
 {
     const uint32_t V = ctx->V, C = ctx->C, D = ctx->D;
@@ -654,6 +714,11 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
         ctx->seeds[c] = sm64_mix(st);
     }
     ctx->W = 2 * C * D;
+    HIPCHK(hipGetDevice(&ctx->device));
+    {
+        const char *tr = getenv("CUPK_TRACE");
+        ctx->trace = tr && tr[0] == '1';
+    }
     if (ctx->opts.use_given_stream) {
         ctx->s = (hipStream_t)ctx->opts.stream;
     } else {
@@ -703,22 +768,9 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
         tv = 1;
         while ((size_t)2 * rows * C * (tv * 2) * 8 <= 32768 && tv < 16) tv *= 2;
     }
-    uint32_t sh = 0;
-    while ((1u << sh) < tv) sh++;
-    if ((1u << sh) != tv) return ctx->invalid("tile_vertices must be a power of two");
-    if ((size_t)2 * rows * C * tv * 8 > 65536) return ctx->invalid("staged tile exceeds 64 KiB LDS");
-    ctx->tile_shift = sh;
-    ctx->rows = rows;
-    ctx->chunk = ctx->opts.chunk_records ? ctx->opts.chunk_records : 4096;
     ctx->tile_grid = ctx->opts.tile_grid;
-    ctx->ntiles = (uint32_t)(((uint64_t)V + tv - 1) >> sh);
-    if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
-        HIPCHK(grow(ctx->d_tcnt, ctx->ntiles + 1));
-        HIPCHK(grow(ctx->d_toff, ctx->ntiles + 1));
-        HIPCHK(grow(ctx->d_tcur, ctx->ntiles + 1));
-        // the scan kernel re-zeroes the counts after every batch
-        HIPCHK(launch_zero32(ctx->s, ctx->d_tcnt.p, ctx->ntiles + 1));
-    }
+    int rc0 = set_geometry(ctx, tv, rows, ctx->opts.chunk_records ? ctx->opts.chunk_records : 4096);
+    if (rc0 != CUPK_OK) return rc0;
     const size_t mb = ctx->opts.max_batch ? ctx->opts.max_batch : (1u << 20);
     int rc = ensure_batch_buffers(ctx, mb);
     if (rc != CUPK_OK) return rc;
@@ -945,6 +997,194 @@ int cupk_sync(cupk_ctx *ctx)
     HIPCHK(hipStreamSynchronize(ctx->s));
     HIPCHK(hipStreamSynchronize(ctx->cs));
     return harvest_timers(ctx, true);
+}
+
+// Time the bin + scatter of `n` sample updates (one application) with the
+// geometry in force, reading the tile counts from a classify pass.
+static int time_scatter_once(cupk_ctx *ctx, const uint64_t *d, uint32_t n, hipEvent_t e0,
+                             hipEvent_t e1, float *ms)
+{
+    int rc = ensure_batch_buffers(ctx, n);
+    if (rc != CUPK_OK) return rc;
+    HIPCHK(launch_zero32(ctx->s, ctx->d_hdr, HDR_WORDS));
+    HIPCHK(launch_classify(ctx->s, d, n, ctx->V, ctx->d_lbl, ctx->d_par, ctx->d_hdr,
+                           ctx->d_fupd.p, ctx->d_fcnt.p, ctx->d_tcnt.p, ctx->tile_shift,
+                           ctx->ntiles));
+    HIPCHK(hipEventRecord(e0, ctx->s));
+    StagedParams p;
+    p.tile_shift = ctx->tile_shift;
+    p.rows = ctx->rows;
+    p.ntiles = ctx->ntiles;
+    p.chunk = ctx->chunk;
+    p.items_cap = (uint32_t)(2 * (size_t)n / ctx->chunk + ctx->ntiles + 1);
+    p.grid = ctx->tile_grid;
+    HIPCHK(launch_staged(ctx->s, d, n, dev_sketch(ctx), ctx->d_hdr, p, ctx->d_tcnt.p,
+                         ctx->d_toff.p, ctx->d_tcur.p, ctx->d_bins.p, ctx->d_items.p,
+                         ctx->d_nitems, nullptr));
+    HIPCHK(hipEventRecord(e1, ctx->s));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(ms, e0, e1));
+    HIPCHK(hipMemcpy(ctx->h_hdr, ctx->d_hdr, HDR_WORDS * 4, hipMemcpyDeviceToHost));
+    if (ctx->h_hdr[HDR_ERR]) return ctx->invalid("sample batch holds an invalid update");
+    return CUPK_OK;
+}
+
+// Median over `reps` pairs of applications (each pair cancels out).
+static int time_scatter(cupk_ctx *ctx, const uint64_t *d, uint32_t n, int reps, hipEvent_t e0,
+                        hipEvent_t e1, double *out_ms)
+{
+    std::vector<float> t;
+    for (int r = 0; r < reps; r++)
+        for (int k = 0; k < 2; k++) {
+            float ms = 0;
+            int rc = time_scatter_once(ctx, d, n, e0, e1, &ms);
+            if (rc != CUPK_OK) return rc;
+            t.push_back(ms);
+        }
+    std::sort(t.begin(), t.end());
+    *out_ms = t[t.size() / 2];
+    return CUPK_OK;
+}
+
+int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_result *out)
+{
+    if (!ctx || !out || !d_sample) return CUPK_EINVAL;
+    if (ctx->server) return ctx->invalid("autotune while the serving loop runs");
+    if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED) return ctx->invalid("autotune needs staged mode");
+    if (n == 0 || n > kMaxBatchPerLaunch) return ctx->invalid("bad sample size");
+    *out = cupk_tune_result{};
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    int rc = upload_forest(ctx);
+    if (rc != CUPK_OK) return rc;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const uint32_t tv0 = 1u << ctx->tile_shift, rows0 = ctx->rows, chunk0 = ctx->chunk;
+    const uint32_t m = (uint32_t)n;
+    double before = 0;
+    rc = time_scatter(ctx, d_sample, m, 1, e0, e1, &before);  // also warms up
+    if (rc == CUPK_OK) rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &before);
+    double best = before;
+    uint32_t btv = tv0, brows = rows0, bchunk = chunk0, tried = 1;
+    const uint32_t tvs[] = {4, 8, 16, 32, 64};
+    const uint32_t rowss[] = {6, 8, 10, 12};
+    const uint32_t chunks[] = {2048, 4096, 8192};
+    for (uint32_t tv : tvs)
+        for (uint32_t rows : rowss)
+            for (uint32_t ch : chunks) {
+                if (rc != CUPK_OK) break;
+                if (rows > ctx->D || (size_t)2 * rows * ctx->C * tv * 8 > 65536) continue;
+                if (tv == tv0 && rows == rows0 && ch == chunk0) continue;
+                rc = set_geometry(ctx, tv, rows, ch);
+                if (rc != CUPK_OK) break;
+                double ms = 0;
+                rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &ms);
+                tried++;
+                if (rc == CUPK_OK && ms < best) {
+                    best = ms;
+                    btv = tv;
+                    brows = rows;
+                    bchunk = ch;
+                }
+            }
+    if (rc == CUPK_OK) rc = set_geometry(ctx, btv, brows, bchunk);
+    // batch-size schedule: throughput of prefixes n/128 .. n
+    double best_rate = 0;
+    for (int k = 0; k < 8 && rc == CUPK_OK; k++) {
+        const uint32_t sz = std::max<uint32_t>(1, m >> (7 - k));
+        double ms = 0;
+        rc = time_scatter(ctx, d_sample, sz, 2, e0, e1, &ms);
+        out->batch_sizes[k] = sz;
+        out->batch_ms[k] = ms;
+        if (ms > 0) best_rate = std::max(best_rate, sz / ms);
+    }
+    if (rc == CUPK_OK) {
+        out->batch_target = m;
+        for (int k = 0; k < 8; k++)
+            if (out->batch_ms[k] > 0 && out->batch_sizes[k] / out->batch_ms[k] >= 0.8 * best_rate) {
+                out->batch_target = out->batch_sizes[k];
+                break;
+            }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != CUPK_OK) {
+        (void)set_geometry(ctx, tv0, rows0, chunk0);
+        return rc;
+    }
+    out->tile_vertices = btv;
+    out->lds_rows = brows;
+    out->chunk_records = bchunk;
+    out->candidates = tried;
+    out->best_ms = best;
+    out->before_ms = before;
+    return CUPK_OK;
+}
+
+int cupk_serve_start(cupk_ctx *ctx, const cupk_serve_opts *opts)
+{
+    if (!ctx) return CUPK_EINVAL;
+    if (ctx->server) return ctx->invalid("serving loop already running");
+    cupk_serve_opts o = {};
+    if (opts) o = *opts;
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    const int dev = ctx->device;
+    ctx->server.reset(new (std::nothrow) Server(
+        ctx, o,
+        [](cupk_ctx *c, const uint64_t *p, size_t n) -> int {
+            static thread_local int bound = -1;
+            if (bound != c->device) {
+                if (hipSetDevice(c->device) != hipSuccess) return CUPK_EDEVICE;
+                bound = c->device;
+            }
+            return apply_packed_host(c, p, n);
+        },
+        connected_impl));
+    (void)dev;
+    if (!ctx->server) return CUPK_ENOMEM;
+    return CUPK_OK;
+}
+
+int cupk_submit_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
+                        const uint8_t *is_delete, size_t n, uint64_t *ticket)
+{
+    if (!ctx || !ctx->server || !ticket) return CUPK_EINVAL;
+    if (n && (!u || !v || !is_delete)) return CUPK_EINVAL;
+    return ctx->server->submit_updates(u, v, is_delete, n, ctx->V, ticket);
+}
+
+int cupk_submit_query(cupk_ctx *ctx, uint32_t u, uint32_t v, uint64_t *ticket)
+{
+    if (!ctx || !ctx->server || !ticket) return CUPK_EINVAL;
+    return ctx->server->submit_query(u, v, ctx->V, ticket);
+}
+
+int cupk_wait(cupk_ctx *ctx, uint64_t ticket, int32_t *result)
+{
+    if (!ctx || !ctx->server) return CUPK_EINVAL;
+    return ctx->server->wait(ticket, result);
+}
+
+int cupk_serve_stats(cupk_ctx *ctx, cupk_serve_stats_t *out)
+{
+    if (!ctx || !ctx->server || !out) return CUPK_EINVAL;
+    ctx->server->get_stats(out);
+    return CUPK_OK;
+}
+
+int cupk_serve_reset_stats(cupk_ctx *ctx)
+{
+    if (!ctx || !ctx->server) return CUPK_EINVAL;
+    ctx->server->reset_stats();
+    return CUPK_OK;
+}
+
+int cupk_serve_stop(cupk_ctx *ctx)
+{
+    if (!ctx || !ctx->server) return CUPK_EINVAL;
+    ctx->server.reset();  // drains the queue, joins the worker
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    return CUPK_OK;
 }
 
 const char *cupk_strerror(int code)

@@ -34,6 +34,9 @@ class Forest {
         lbl_ = lbl;
         par_ = par;
         adj_.assign(V, {});
+        // most forest vertices have a few tree neighbours: reserving them
+        // up front keeps links free of small reallocations
+        for (auto &a : adj_) a.reserve(4);
         size_.assign(V, 1);
         root_.resize(V);
         dirty_.assign(V, 0);

@@ -65,8 +65,11 @@ DEVI void lxor(uint64_t *p, uint64_t v)
 //   insert {u,v} with lbl[u] != lbl[v]               (may join two trees)
 //   delete {u,v} that is a forest edge (par[u]==v or par[v]==u), or with
 //   lbl[u] != lbl[v] (an edge linked earlier in this same batch)
-// Everything else can only touch the sketch.  Flagged updates are appended
-// with a wave-aggregated atomic; their order is restored on the host.
+// Everything else can only touch the sketch.  Block b covers positions
+// [b*4096, (b+1)*4096) and writes its flagged updates in stream order into
+// its own region of the flag buffers (same offsets), with a block-wide
+// prefix over the waves of every 256-update step; cnt[b] gets their number.
+// k_flag_compact later packs the regions into one ordered list.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kClsThreads = 256;
 constexpr uint32_t kClsPerBlock = 4096;
@@ -74,11 +77,12 @@ constexpr uint32_t kLdsHistMax = 8192;
 
 __global__ __launch_bounds__(kClsThreads) void k_classify(
     const uint64_t *__restrict__ upd, uint32_t n, uint32_t V, const uint32_t *__restrict__ lbl,
-    const uint32_t *__restrict__ par, uint32_t *__restrict__ hdr, uint32_t *__restrict__ fpos,
-    uint64_t *__restrict__ fupd, uint32_t *__restrict__ tile_cnt, uint32_t tile_shift,
-    uint32_t ntiles)
+    const uint32_t *__restrict__ par, uint32_t *__restrict__ hdr, uint64_t *__restrict__ fupd,
+    uint32_t *__restrict__ fcnt, uint32_t *__restrict__ tile_cnt,
+    uint32_t tile_shift, uint32_t ntiles)
 {
     __shared__ uint32_t hist[kLdsHistMax];
+    __shared__ uint32_t wtot[kClsThreads / 64];
     const bool count = tile_cnt != nullptr;
     const bool use_lds = count && ntiles <= kLdsHistMax;
     if (use_lds)
@@ -88,6 +92,9 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
     const uint32_t begin = blockIdx.x * kClsPerBlock;
     const uint32_t end = min(n, begin + kClsPerBlock);
     const uint32_t lane = __lane_id();
+    const uint32_t wid = threadIdx.x / 64;
+    uint32_t run = 0;  // flagged so far in this block (uniform)
+    uint32_t ndel = 0;
     for (uint32_t base = begin; base < end; base += blockDim.x) {
         const uint32_t i = base + threadIdx.x;
         bool flag = false, bad = false;
@@ -110,20 +117,29 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
             }
         }
         const uint64_t m = __ballot(flag);
-        if (m) {
-            const uint32_t leader = (uint32_t)__builtin_ctzll(m);
-            uint32_t pos = 0;
-            if (lane == leader) pos = atomicAdd(&hdr[HDR_NFLAG], (uint32_t)__popcll(m));
-            pos = __shfl(pos, leader);
-            if (flag) {
-                const uint32_t o = pos + lanes_below(m);
-                fpos[o] = i;
-                fupd[o] = p;
-            }
-        }
+        if (lane == 0) wtot[wid] = (uint32_t)__popcll(m);
+        const uint64_t md = __ballot(flag && (p >> 63));
+        ndel += (uint32_t)__popcll(md);
         const uint64_t mb = __ballot(bad);
         if (mb && lane == (uint32_t)__builtin_ctzll(mb)) atomicOr(&hdr[HDR_ERR], 1u);
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (uint32_t w = 0; w < kClsThreads / 64; w++) {
+            before += w < wid ? wtot[w] : 0u;
+            tot += wtot[w];
+        }
+        if (flag) {
+            fupd[begin + run + before + lanes_below(m)] = p;
+        }
+        run += tot;
+        __syncthreads();
     }
+    if (threadIdx.x == 0) {
+        fcnt[blockIdx.x] = run;
+        if (run) atomicAdd(&hdr[HDR_NFLAG], run);
+    }
+    // ndel is per wave; lane 0 of each wave adds its share
+    if (lane == 0 && ndel) atomicAdd(&hdr[HDR_NFLAG_DEL], ndel);
     if (use_lds) {
         __syncthreads();
         for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x)
@@ -131,15 +147,16 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
     }
 }
 
+uint32_t classify_blocks(uint32_t n) { return (n + kClsPerBlock - 1) / kClsPerBlock; }
+
 hipError_t launch_classify(hipStream_t s, const uint64_t *upd, uint32_t n, uint32_t V,
                            const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
-                           uint32_t *fpos, uint64_t *fupd, uint32_t *tile_cnt,
+                           uint64_t *fupd, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles)
 {
     if (n == 0) return hipSuccess;
-    const uint32_t blocks = (n + kClsPerBlock - 1) / kClsPerBlock;
-    k_classify<<<blocks, kClsThreads, 0, s>>>(upd, n, V, lbl, par, hdr, fpos, fupd, tile_cnt,
-                                              tile_shift, ntiles);
+    k_classify<<<classify_blocks(n), kClsThreads, 0, s>>>(upd, n, V, lbl, par, hdr, fupd, fcnt,
+                                                         tile_cnt, tile_shift, ntiles);
     return hipGetLastError();
 }
 
@@ -472,6 +489,50 @@ hipError_t launch_staged(hipStream_t s, const uint64_t *upd, uint32_t n, DevSket
     else if (sk.C <= 32) CUPK_TILE_LAUNCH(32);
     else CUPK_TILE_LAUNCH(0);
 #undef CUPK_TILE_LAUNCH
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Flag compaction: exclusive scan of the per-block flag counts (one block),
+// then every classify block's region is copied to its offset, giving the
+// flagged updates of the batch in stream order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kScanThreads) void k_flag_scan(const uint32_t *__restrict__ fcnt,
+                                                            uint32_t nb,
+                                                            uint32_t *__restrict__ foff)
+{
+    __shared__ uint32_t sh[160];
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < nb; base += kScanThreads) {
+        const uint32_t b = base + threadIdx.x;
+        const uint32_t c = b < nb ? fcnt[b] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exscan<kScanThreads>(c, tot, sh);
+        if (b < nb) foff[b] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_flag_compact(const uint64_t *__restrict__ fupd,
+                                                      const uint32_t *__restrict__ fcnt,
+                                                      const uint32_t *__restrict__ foff,
+                                                      uint64_t *__restrict__ oupd)
+{
+    const uint32_t b = blockIdx.x;
+    const uint32_t c = fcnt[b], o = foff[b];
+    const uint32_t src = b * kClsPerBlock;
+    for (uint32_t k = threadIdx.x; k < c; k += blockDim.x) oupd[o + k] = fupd[src + k];
+}
+
+hipError_t launch_flag_compact(hipStream_t s, uint32_t n, const uint64_t *fupd,
+                               const uint32_t *fcnt, uint32_t *foff, uint64_t *oupd)
+{
+    const uint32_t nb = classify_blocks(n);
+    if (nb == 0) return hipSuccess;
+    k_flag_scan<<<1, kScanThreads, 0, s>>>(fcnt, nb, foff);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_flag_compact<<<nb, 256, 0, s>>>(fupd, fcnt, foff, oupd);
     return hipGetLastError();
 }
 

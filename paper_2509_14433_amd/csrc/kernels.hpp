@@ -17,7 +17,7 @@ struct DevSketch {
 };
 
 // Header words written by the classify kernel.
-enum { HDR_ERR = 0, HDR_NFLAG = 1, HDR_WORDS = 4 };
+enum { HDR_ERR = 0, HDR_NFLAG = 1, HDR_NFLAG_DEL = 2, HDR_WORDS = 4 };
 
 struct StagedParams {
     uint32_t tile_shift;   // vertices per tile = 1 << tile_shift
@@ -31,10 +31,19 @@ struct StagedParams {
 // Per-batch: validation, structural classification and compaction of the
 // flagged updates.  hdr must be zeroed first.  When `tile_cnt` is non-null
 // the kernel also counts how many endpoint records each vertex tile gets.
+// Flagged updates of classify block b (positions [b*4096, (b+1)*4096)) land
+// in stream order at offsets b*4096.. of fupd (capacity: the batch rounded
+// up to a multiple of 4096); fcnt[b] receives their number.
 hipError_t launch_classify(hipStream_t s, const uint64_t *upd, uint32_t n, uint32_t V,
                            const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
-                           uint32_t *fpos, uint64_t *fupd, uint32_t *tile_cnt,
+                           uint64_t *fupd, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles);
+uint32_t classify_blocks(uint32_t n);
+
+// Pack the per-block flag regions into one list in stream order (foff:
+// classify_blocks(n) words of scratch).
+hipError_t launch_flag_compact(hipStream_t s, uint32_t n, const uint64_t *fupd,
+                               const uint32_t *fcnt, uint32_t *foff, uint64_t *oupd);
 
 // Plain scatter: device-scope atomic XOR of (x, h) into both endpoints.
 hipError_t launch_scatter_atomic(hipStream_t s, const uint64_t *upd, uint32_t n,

@@ -98,3 +98,20 @@ def test_benchmark_workload_full_size(workload, mode):
     print(ctr, flush=True)
     assert ctr["sample_failed"] == 0
     ctx.close()
+
+
+def test_benchmark_workload_first_batch_forest(workload):
+    # the first 1,000,000-update batch flags every insert (every vertex is
+    # its own tree); its forest must equal the oracle's replay exactly
+    W = workload
+    cupk, cfg = W["cupk"], W["cfg"]
+    V, B = cfg["V"], cfg["batch"]
+    C = streamgen.ceil_log2(V)
+    D = 2 * C
+    ctx = cupk.Context(V, C, D, cfg["S"], max_batch=B)
+    ctx.apply_updates_device(W["packed"][:B])
+    fr = oracle.ForestReplay(oracle.Sketch(V, C, D, cfg["S"]))
+    fr.apply_batch(W["u"][:B], W["v"][:B], W["d"][:B])
+    assert ctx.forest_edges() == fr.forest_edges()
+    assert ctx.counters()["links"] == fr.n_links
+    ctx.close()

@@ -221,3 +221,44 @@ def test_device_batches_match_host_batches(cupk, mode):
     _assert_same_sketch(ctx, ref)
     assert ctx.forest_edges() == fr.forest_edges()
     ctx.close()
+
+
+def test_autotune_leaves_sketch_unchanged_and_parity_holds(cupk):
+    import torch
+    V, C, D, S = 3000, 12, 24, 31337
+    u, v, d = streamgen.er_standard(V, 0.02, 0.3, 8)
+    half = len(u) // 2
+    ctx = cupk.Context(V, C, D, S)
+    ref = oracle.Sketch(V, C, D, S)
+    fr = oracle.ForestReplay(ref)
+    ctx.apply_updates(u[:half], v[:half], d[:half])
+    fr.apply_batch(u[:half], v[:half], d[:half])
+    dg = ctx.digest()
+    sample = torch.from_numpy(cupk.pack_updates(u, v, d).view(np.int64)).cuda()
+    res = ctx.autotune(sample)
+    print(res, flush=True)
+    assert ctx.digest() == dg
+    assert res["candidates"] > 10 and res["best_ms"] <= res["before_ms"]
+    assert res["tile_vertices"] in (4, 8, 16, 32, 64)
+    assert res["batch_target"] in res["batch_sizes"]
+    ctx.apply_updates(u[half:], v[half:], d[half:])
+    fr.apply_batch(u[half:], v[half:], d[half:])
+    _assert_same_sketch(ctx, ref)
+    assert ctx.forest_edges() == fr.forest_edges()
+    ctx.close()
+
+
+@pytest.mark.parametrize("V,p,bs", [(3000, 0.002, None), (3000, 0.01, 20000), (500, 0.3, 9000)])
+def test_insert_only_batches(cupk, V, p, bs):
+    # batches whose flagged updates are all inserts take the union-find walk
+    # (with early stop once one tree remains) and bulk linking; sparse cases
+    # end with many trees, dense ones with one
+    C = math.ceil(math.log2(V))
+    D = 2 * C
+    S = 4242
+    u, v, d = streamgen.er_standard(V, p, 0.0, 40 + V)
+    ctx, ref, fr = _replay(cupk, "staged", V, C, D, S, u, v, d, bs)
+    assert ctx.forest_edges() == fr.forest_edges()
+    assert ctx.num_components() == len(set(fr.labels().tolist()))
+    _assert_same_sketch(ctx, ref)
+    ctx.close()
