@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+CALIB_BYTES = 256 << 20  # plain copy used to scale the HBM byte counters
 V, C, D, SEED, BATCH = 16384, 14, 28, 0x5EED0001, 1_000_000
 WORKLOAD = ("er16384_p0.3_del10: V=16384, G(V,0.3) inserts in random order then 10% random "
             "deletions (44,276,290 updates), 1,000,000-update batches, C=14 x D=28 buckets")
@@ -166,6 +167,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel run")
     ap.add_argument("--no-serve", action="store_true", help="skip the served run")
     ap.add_argument("--mode", default="staged", choices=["staged", "atomic"])
+    ap.add_argument("--calib", action="store_true",
+                    help="first run a plain 256 MiB device copy (4 times) as the reference "
+                         "for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -186,6 +190,13 @@ def main():
     packed = torch.from_numpy(cupk.pack_updates(u, v, d).view(np.int64)).cuda()
     torch.cuda.synchronize()
 
+    if args.calib:
+        src = torch.ones(CALIB_BYTES // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     mode = cupk.SCATTER_STAGED if args.mode == "staged" else cupk.SCATTER_ATOMIC
     print("bench: timing main path", file=sys.stderr, flush=True)
     dt, total, ctr = run_path(cupk, torch, packed, sizes, args.steps, args.warmup, mode)
