@@ -98,6 +98,11 @@ typedef struct {
      * blocks of its persistent grid (0 = default 2048). */
     uint32_t chunk_records;
     uint32_t tile_grid;
+    /* Nonzero: replay each batch's device work (classification with its
+     * header copy, binning, scatter) as captured HIP graphs sized for the
+     * batch capacity; the kernels read the batch size from device memory,
+     * so one capture serves batches of any size up to the capacity. */
+    uint32_t use_graph;
 } cupk_opts;
 
 /* Counters, cumulative since init. */

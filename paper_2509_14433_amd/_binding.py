@@ -51,6 +51,7 @@ class cupk_opts(ctypes.Structure):
         ("lds_rows", ctypes.c_uint32),
         ("chunk_records", ctypes.c_uint32),
         ("tile_grid", ctypes.c_uint32),
+        ("use_graph", ctypes.c_uint32),
     ]
 
 
@@ -157,7 +158,7 @@ class Context:
 
     def __init__(self, V, C=0, D=0, seed=0, scatter_mode=SCATTER_STAGED, max_batch=0,
                  stream=None, use_torch_memory=True, time_kernels=False, tile_vertices=0,
-                 lds_rows=0, chunk_records=0, tile_grid=0):
+                 lds_rows=0, chunk_records=0, tile_grid=0, use_graph=False):
         self._h = None
         self._sk_tensor = None
         opts = cupk_opts()
@@ -168,6 +169,7 @@ class Context:
         opts.lds_rows = lds_rows
         opts.chunk_records = chunk_records
         opts.tile_grid = tile_grid
+        opts.use_graph = 1 if use_graph else 0
         torch = _torch()
         if stream is None and torch is not None and torch.cuda.is_available():
             # launch on torch's current stream so that torch-produced device

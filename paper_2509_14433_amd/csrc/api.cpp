@@ -121,6 +121,13 @@ struct cupk_ctx {
     HostBuf<int32_t> h_res;
     DevBuf<uint64_t> d_tmp;
     uint64_t *d_misc = nullptr, *h_misc = nullptr;
+    BatchDesc *d_desc = nullptr, *h_desc = nullptr;
+
+    // captured step (use_graph): classify + header copy, bin, tile
+    hipStream_t gs = nullptr;  // capture stream
+    hipGraphExec_t gx_cls = nullptr, gx_bin = nullptr, gx_tile = nullptr;
+    uint32_t graph_cap = 0;    // batch capacity the graphs were captured for
+    size_t batch_cap = 0;      // updates per batch every batch buffer holds
 
 
     int device = 0;
@@ -200,6 +207,8 @@ void release(HostBuf<T> &b)
     b.p = nullptr;
     b.cap = 0;
 }
+
+void drop_graphs(cupk_ctx *ctx);
 
 DevSketch dev_sketch(cupk_ctx *ctx)
 {
@@ -484,19 +493,110 @@ bool apply_flags(cupk_ctx *ctx, uint32_t k0, uint32_t k1, bool all_inserts)
     return done || (all_inserts && F.n_trees() == 1);
 }
 
+// Size every per-batch buffer for one capacity (updates per batch); growth
+// is geometric.  Captured graphs embed buffer pointers and are dropped.
 int ensure_batch_buffers(cupk_ctx *ctx, size_t n)
 {
-    const size_t nb = (n + 4095) / 4096;
+    if (n <= ctx->batch_cap) return CUPK_OK;
+    const size_t cap = std::max(n, ctx->batch_cap + ctx->batch_cap / 2);
+    drop_graphs(ctx);
+    const size_t nb = (cap + 4095) / 4096;
     HIPCHK(grow(ctx->d_fupd, nb * 4096));
     HIPCHK(grow(ctx->d_fcnt, nb + 1));
     HIPCHK(grow(ctx->d_foff, nb + 1));
-    HIPCHK(grow(ctx->d_oupd, n));
-    HIPCHK(grow(ctx->h_fupd, n));
+    HIPCHK(grow(ctx->d_oupd, cap));
+    HIPCHK(grow(ctx->h_fupd, cap));
     if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
-        HIPCHK(grow(ctx->d_bins, 2 * n));
-        const size_t icap = 2 * n / ctx->chunk + ctx->ntiles + 1;
+        HIPCHK(grow(ctx->d_bins, 2 * cap));
+        const size_t icap = 2 * cap / ctx->chunk + ctx->ntiles + 1;
         HIPCHK(grow(ctx->d_items, 2 * icap));
     }
+    ctx->batch_cap = cap;
+    return CUPK_OK;
+}
+
+void drop_graphs(cupk_ctx *ctx)
+{
+    for (hipGraphExec_t *g : {&ctx->gx_cls, &ctx->gx_bin, &ctx->gx_tile})
+        if (*g) {
+            (void)hipGraphExecDestroy(*g);
+            *g = nullptr;
+        }
+    ctx->graph_cap = 0;
+}
+
+StagedParams staged_params(cupk_ctx *ctx, uint32_t grid_n)
+{
+    StagedParams p;
+    p.tile_shift = ctx->tile_shift;
+    p.rows = ctx->rows;
+    p.ntiles = ctx->ntiles;
+    p.chunk = ctx->chunk;
+    p.items_cap = (uint32_t)(2 * (size_t)grid_n / ctx->chunk + ctx->ntiles + 1);
+    p.grid = ctx->tile_grid;
+    return p;
+}
+
+// Device work of one batch, in three parts.  Grids are sized for grid_n;
+// the kernels read the batch from ctx->d_desc.
+int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n, bool copy_header)
+{
+    const bool staged = ctx->opts.scatter_mode == CUPK_SCATTER_STAGED;
+    HIPCHK(launch_zero32(s, ctx->d_hdr, HDR_WORDS));
+    HIPCHK(launch_classify(s, ctx->d_desc, grid_n, ctx->V, ctx->d_lbl, ctx->d_par, ctx->d_hdr,
+                           ctx->d_fupd.p, ctx->d_fcnt.p, staged ? ctx->d_tcnt.p : nullptr,
+                           ctx->tile_shift, ctx->ntiles));
+    if (copy_header)
+        HIPCHK(hipMemcpyAsync(ctx->h_hdr, ctx->d_hdr, HDR_WORDS * 4, hipMemcpyDeviceToHost, s));
+    return CUPK_OK;
+}
+
+int enqueue_bin(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
+{
+    if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED) return CUPK_OK;
+    HIPCHK(launch_bin(s, ctx->d_desc, grid_n, dev_sketch(ctx), ctx->d_hdr,
+                      staged_params(ctx, grid_n), ctx->d_tcnt.p, ctx->d_toff.p, ctx->d_tcur.p,
+                      ctx->d_bins.p, ctx->d_items.p, ctx->d_nitems));
+    return CUPK_OK;
+}
+
+int enqueue_tile(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
+{
+    if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
+        HIPCHK(launch_tile(s, dev_sketch(ctx), ctx->d_hdr, staged_params(ctx, grid_n),
+                           ctx->d_toff.p, ctx->d_bins.p, ctx->d_items.p, ctx->d_nitems));
+    } else {
+        HIPCHK(launch_scatter_atomic(s, ctx->d_desc, grid_n, dev_sketch(ctx), ctx->d_hdr));
+    }
+    return CUPK_OK;
+}
+
+// Capture the three parts as graphs sized for the current batch capacity.
+// Captured on an internal stream; replayed on the context's stream.
+int capture_graphs(cupk_ctx *ctx)
+{
+    drop_graphs(ctx);
+    if (!ctx->gs) HIPCHK(hipStreamCreateWithFlags(&ctx->gs, hipStreamNonBlocking));
+    const uint32_t cap = (uint32_t)std::min<size_t>(ctx->batch_cap, kMaxBatchPerLaunch);
+    for (int part = 0; part < 3; part++) {
+        HIPCHK(hipStreamBeginCapture(ctx->gs, hipStreamCaptureModeThreadLocal));
+        int rc = part == 0 ? enqueue_classify(ctx, ctx->gs, cap, true)
+                 : part == 1 ? enqueue_bin(ctx, ctx->gs, cap)
+                             : enqueue_tile(ctx, ctx->gs, cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->gs, &g);
+        if (rc != CUPK_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return ctx->fail(e, "hipStreamEndCapture", __LINE__);
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return ctx->fail(e, "hipGraphInstantiate", __LINE__);
+        (part == 0 ? ctx->gx_cls : part == 1 ? ctx->gx_bin : ctx->gx_tile) = x;
+    }
+    ctx->graph_cap = cap;
     return CUPK_OK;
 }
 
@@ -508,15 +608,31 @@ int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
     if (rc != CUPK_OK) return rc;
     rc = upload_forest(ctx);
     if (rc != CUPK_OK) return rc;
-    const bool staged = ctx->opts.scatter_mode == CUPK_SCATTER_STAGED;
-    HIPCHK(launch_zero32(ctx->s, ctx->d_hdr, HDR_WORDS));
-    HIPCHK(launch_classify(ctx->s, d_upd, n, ctx->V, ctx->d_lbl, ctx->d_par, ctx->d_hdr,
-                           ctx->d_fupd.p, ctx->d_fcnt.p, staged ? ctx->d_tcnt.p : nullptr,
-                           ctx->tile_shift, ctx->ntiles));
-    HIPCHK(hipEventRecord(ctx->ev_cls, ctx->s));
-    HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->ev_cls, 0));
-    HIPCHK(hipMemcpyAsync(ctx->h_hdr, ctx->d_hdr, HDR_WORDS * 4, hipMemcpyDeviceToHost, ctx->cs));
-    HIPCHK(hipEventRecord(ctx->ev_hdr, ctx->cs));
+    // the batch descriptor (pinned staging; the previous batch's copy has
+    // completed: every call waits for its classify step)
+    ctx->h_desc->upd = d_upd;
+    ctx->h_desc->n = n;
+    HIPCHK(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
+                          ctx->s));
+    const bool graph = ctx->opts.use_graph != 0;
+    if (graph && (ctx->graph_cap < n || !ctx->gx_cls)) {
+        rc = capture_graphs(ctx);
+        if (rc != CUPK_OK) return rc;
+    }
+    if (graph) {
+        HIPCHK(hipGraphLaunch(ctx->gx_cls, ctx->s));
+        HIPCHK(hipEventRecord(ctx->ev_cls, ctx->s));
+        HIPCHK(hipEventRecord(ctx->ev_hdr, ctx->s));  // the header copy is in the graph
+    } else {
+        rc = enqueue_classify(ctx, ctx->s, n, false);
+        if (rc != CUPK_OK) return rc;
+        HIPCHK(hipEventRecord(ctx->ev_cls, ctx->s));
+        HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->ev_cls, 0));
+        HIPCHK(hipMemcpyAsync(ctx->h_hdr, ctx->d_hdr, HDR_WORDS * 4, hipMemcpyDeviceToHost,
+                              ctx->cs));
+        HIPCHK(hipEventRecord(ctx->ev_hdr, ctx->cs));
+    }
+    if (graph) HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->ev_cls, 0));
 
     // scatter (skipped on device if the batch was rejected)
     cupk_ctx::TimerSlot *ts = nullptr;
@@ -530,21 +646,16 @@ int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
         }
         HIPCHK(hipEventRecord(ts->t0, ctx->s));
     }
-    DevSketch sk = dev_sketch(ctx);
-    if (staged) {
-        StagedParams p;
-        p.tile_shift = ctx->tile_shift;
-        p.rows = ctx->rows;
-        p.ntiles = ctx->ntiles;
-        p.chunk = ctx->chunk;
-        p.items_cap = (uint32_t)(2 * (size_t)n / ctx->chunk + ctx->ntiles + 1);
-        p.grid = ctx->tile_grid;
-        HIPCHK(launch_staged(ctx->s, d_upd, n, sk, ctx->d_hdr, p, ctx->d_tcnt.p, ctx->d_toff.p,
-                             ctx->d_tcur.p, ctx->d_bins.p, ctx->d_items.p, ctx->d_nitems,
-                             ts ? ts->tb : nullptr));
-    } else {
+    if (graph) {
+        if (ctx->gx_bin) HIPCHK(hipGraphLaunch(ctx->gx_bin, ctx->s));
         if (ts) HIPCHK(hipEventRecord(ts->tb, ctx->s));
-        HIPCHK(launch_scatter_atomic(ctx->s, d_upd, n, sk, ctx->d_hdr));
+        HIPCHK(hipGraphLaunch(ctx->gx_tile, ctx->s));
+    } else {
+        rc = enqueue_bin(ctx, ctx->s, n);
+        if (rc != CUPK_OK) return rc;
+        if (ts) HIPCHK(hipEventRecord(ts->tb, ctx->s));
+        rc = enqueue_tile(ctx, ctx->s, n);
+        if (rc != CUPK_OK) return rc;
     }
     if (ts) {
         HIPCHK(hipEventRecord(ts->t1, ctx->s));
@@ -639,6 +750,10 @@ void destroy(cupk_ctx *ctx)
     if (ctx->d_hdr) (void)hipFree(ctx->d_hdr);
     if (ctx->h_hdr) (void)hipHostFree(ctx->h_hdr);
     if (ctx->d_nitems) (void)hipFree(ctx->d_nitems);
+    drop_graphs(ctx);
+    if (ctx->gs) (void)hipStreamDestroy(ctx->gs);
+    if (ctx->d_desc) (void)hipFree(ctx->d_desc);
+    if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
     if (ctx->d_misc) (void)hipFree(ctx->d_misc);
     if (ctx->h_misc) (void)hipHostFree(ctx->h_misc);
     release(ctx->d_upd);
@@ -678,6 +793,7 @@ void destroy(cupk_ctx *ctx)
 // rows in LDS, `chunk` records per work item.
 int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk)
 {
+    drop_graphs(ctx);  // captured graphs embed the geometry and buffers
     uint32_t sh = 0;
     while ((1u << sh) < tv) sh++;
     if (tv == 0 || (1u << sh) != tv) return ctx->invalid("tile_vertices must be a power of two");
@@ -696,7 +812,7 @@ int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk)
         // the scan kernel re-zeroes the counts after every batch
         HIPCHK(launch_zero32(ctx->s, ctx->d_tcnt.p, ctx->ntiles + 1));
         // work-item capacity depends on ntiles and chunk
-        const size_t icap = 2 * ctx->d_fupd.cap / chunk + ctx->ntiles + 1;
+        const size_t icap = 2 * ctx->batch_cap / chunk + ctx->ntiles + 1;
         HIPCHK(grow(ctx->d_items, 2 * icap));
     }
     return CUPK_OK;
@@ -751,6 +867,8 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     HIPCHK(hipMalloc((void **)&ctx->d_hdr, HDR_WORDS * 4));
     HIPCHK(hipHostMalloc((void **)&ctx->h_hdr, HDR_WORDS * 4, hipHostMallocDefault));
     HIPCHK(hipMalloc((void **)&ctx->d_nitems, 4));
+    HIPCHK(hipMalloc((void **)&ctx->d_desc, sizeof(BatchDesc)));
+    HIPCHK(hipHostMalloc((void **)&ctx->h_desc, sizeof(BatchDesc), hipHostMallocDefault));
     HIPCHK(hipMalloc((void **)&ctx->d_misc, 64));
     HIPCHK(hipHostMalloc((void **)&ctx->h_misc, 64, hipHostMallocDefault));
     ctx->forest.init(V, ctx->h_lbl, ctx->h_par);
@@ -1006,21 +1124,16 @@ static int time_scatter_once(cupk_ctx *ctx, const uint64_t *d, uint32_t n, hipEv
 {
     int rc = ensure_batch_buffers(ctx, n);
     if (rc != CUPK_OK) return rc;
-    HIPCHK(launch_zero32(ctx->s, ctx->d_hdr, HDR_WORDS));
-    HIPCHK(launch_classify(ctx->s, d, n, ctx->V, ctx->d_lbl, ctx->d_par, ctx->d_hdr,
-                           ctx->d_fupd.p, ctx->d_fcnt.p, ctx->d_tcnt.p, ctx->tile_shift,
-                           ctx->ntiles));
+    ctx->h_desc->upd = d;
+    ctx->h_desc->n = n;
+    HIPCHK(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
+                          ctx->s));
+    rc = enqueue_classify(ctx, ctx->s, n, false);
+    if (rc != CUPK_OK) return rc;
     HIPCHK(hipEventRecord(e0, ctx->s));
-    StagedParams p;
-    p.tile_shift = ctx->tile_shift;
-    p.rows = ctx->rows;
-    p.ntiles = ctx->ntiles;
-    p.chunk = ctx->chunk;
-    p.items_cap = (uint32_t)(2 * (size_t)n / ctx->chunk + ctx->ntiles + 1);
-    p.grid = ctx->tile_grid;
-    HIPCHK(launch_staged(ctx->s, d, n, dev_sketch(ctx), ctx->d_hdr, p, ctx->d_tcnt.p,
-                         ctx->d_toff.p, ctx->d_tcur.p, ctx->d_bins.p, ctx->d_items.p,
-                         ctx->d_nitems, nullptr));
+    rc = enqueue_bin(ctx, ctx->s, n);
+    if (rc == CUPK_OK) rc = enqueue_tile(ctx, ctx->s, n);
+    if (rc != CUPK_OK) return rc;
     HIPCHK(hipEventRecord(e1, ctx->s));
     HIPCHK(hipEventSynchronize(e1));
     HIPCHK(hipEventElapsedTime(ms, e0, e1));

@@ -76,7 +76,7 @@ constexpr uint32_t kClsPerBlock = 4096;
 constexpr uint32_t kLdsHistMax = 8192;
 
 __global__ __launch_bounds__(kClsThreads) void k_classify(
-    const uint64_t *__restrict__ upd, uint32_t n, uint32_t V, const uint32_t *__restrict__ lbl,
+    const BatchDesc *__restrict__ desc, uint32_t V, const uint32_t *__restrict__ lbl,
     const uint32_t *__restrict__ par, uint32_t *__restrict__ hdr, uint64_t *__restrict__ fupd,
     uint32_t *__restrict__ fcnt, uint32_t *__restrict__ tile_cnt,
     uint32_t tile_shift, uint32_t ntiles)
@@ -89,6 +89,8 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
         for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) hist[t] = 0;
     __syncthreads();
 
+    const uint64_t *__restrict__ upd = desc->upd;
+    const uint32_t n = desc->n;
     const uint32_t begin = blockIdx.x * kClsPerBlock;
     const uint32_t end = min(n, begin + kClsPerBlock);
     const uint32_t lane = __lane_id();
@@ -149,14 +151,14 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
 
 uint32_t classify_blocks(uint32_t n) { return (n + kClsPerBlock - 1) / kClsPerBlock; }
 
-hipError_t launch_classify(hipStream_t s, const uint64_t *upd, uint32_t n, uint32_t V,
+hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, uint32_t grid_n, uint32_t V,
                            const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles)
 {
-    if (n == 0) return hipSuccess;
-    k_classify<<<classify_blocks(n), kClsThreads, 0, s>>>(upd, n, V, lbl, par, hdr, fupd, fcnt,
-                                                         tile_cnt, tile_shift, ntiles);
+    if (grid_n == 0) return hipSuccess;
+    k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(desc, V, lbl, par, hdr, fupd, fcnt,
+                                                              tile_cnt, tile_shift, ntiles);
     return hipGetLastError();
 }
 
@@ -165,16 +167,16 @@ hipError_t launch_classify(hipStream_t s, const uint64_t *upd, uint32_t n, uint3
 // column and XOR-ing (x, h) into bucket (c, d) of both endpoints with
 // device-scope atomics (4 per column).  Skipped when the batch was rejected.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_scatter_atomic(const uint64_t *__restrict__ upd,
-                                                        uint32_t n, DevSketch sk,
+__global__ __launch_bounds__(256) void k_scatter_atomic(const BatchDesc *__restrict__ desc,
+                                                        DevSketch sk,
                                                         const uint32_t *__restrict__ hdr)
 {
     if (hdr[HDR_ERR]) return;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= desc->n) return;
     uint32_t u, v;
     bool del;
-    unpack(upd[i], sk.V, u, v, del);
+    unpack(desc->upd[i], sk.V, u, v, del);
     const uint64_t x = (uint64_t)u * sk.V + v;
     const uint64_t ru = (uint64_t)u * sk.D, rv = (uint64_t)v * sk.D;
     for (uint32_t c = 0; c < sk.C; c++) {
@@ -189,11 +191,11 @@ __global__ __launch_bounds__(256) void k_scatter_atomic(const uint64_t *__restri
     }
 }
 
-hipError_t launch_scatter_atomic(hipStream_t s, const uint64_t *upd, uint32_t n, DevSketch sk,
-                                 const uint32_t *hdr)
+hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, uint32_t grid_n,
+                                 DevSketch sk, const uint32_t *hdr)
 {
-    if (n == 0) return hipSuccess;
-    k_scatter_atomic<<<(n + 255) / 256, 256, 0, s>>>(upd, n, sk, hdr);
+    if (grid_n == 0) return hipSuccess;
+    k_scatter_atomic<<<(grid_n + 255) / 256, 256, 0, s>>>(desc, sk, hdr);
     return hipGetLastError();
 }
 
@@ -297,12 +299,14 @@ constexpr uint32_t kFillThreads = 256;
 constexpr uint32_t kFillPerBlock = 4096;
 
 __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
-    const uint64_t *__restrict__ upd, uint32_t n, uint32_t V, uint32_t tile_shift,
-    uint32_t ntiles, uint32_t *__restrict__ cur, uint64_t *__restrict__ bins,
-    const uint32_t *__restrict__ hdr)
+    const BatchDesc *__restrict__ desc, uint32_t V, uint32_t tile_shift, uint32_t ntiles,
+    uint32_t *__restrict__ cur, uint64_t *__restrict__ bins, const uint32_t *__restrict__ hdr)
 {
     __shared__ uint32_t lcnt[kLdsHistMax];
     if (hdr[HDR_ERR]) return;
+    const uint64_t *__restrict__ upd = desc->upd;
+    const uint32_t n = desc->n;
+    if (blockIdx.x * kFillPerBlock >= n) return;
     const uint32_t begin = blockIdx.x * kFillPerBlock;
     const uint32_t end = min(n, begin + kFillPerBlock);
     if (ntiles > kLdsHistMax) {
@@ -458,25 +462,26 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
     }
 }
 
-hipError_t launch_staged(hipStream_t s, const uint64_t *upd, uint32_t n, DevSketch sk,
-                         const uint32_t *hdr, const StagedParams &p, uint32_t *tile_cnt,
-                         uint32_t *tile_off, uint32_t *tile_cur, uint64_t *bins,
-                         uint32_t *items, uint32_t *nitems, hipEvent_t ev_binned)
+hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, uint32_t grid_n, DevSketch sk,
+                      const uint32_t *hdr, const StagedParams &p, uint32_t *tile_cnt,
+                      uint32_t *tile_off, uint32_t *tile_cur, uint64_t *bins, uint32_t *items,
+                      uint32_t *nitems)
 {
-    if (n == 0) return hipSuccess;
+    if (grid_n == 0) return hipSuccess;
     k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, p.ntiles, p.chunk, tile_off, tile_cur, items,
                                            p.items_cap, nitems, hdr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const uint32_t fb = (n + kFillPerBlock - 1) / kFillPerBlock;
-    k_tile_fill<<<fb, kFillThreads, 0, s>>>(upd, n, sk.V, p.tile_shift, p.ntiles, tile_cur, bins,
+    const uint32_t fb = (grid_n + kFillPerBlock - 1) / kFillPerBlock;
+    k_tile_fill<<<fb, kFillThreads, 0, s>>>(desc, sk.V, p.tile_shift, p.ntiles, tile_cur, bins,
                                             hdr);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (ev_binned) {
-        e = hipEventRecord(ev_binned, s);
-        if (e != hipSuccess) return e;
-    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tile(hipStream_t s, DevSketch sk, const uint32_t *hdr, const StagedParams &p,
+                       const uint32_t *tile_off, const uint64_t *bins, const uint32_t *items,
+                       const uint32_t *nitems)
+{
     const size_t lds = (size_t)2 * p.rows * sk.C * (1u << p.tile_shift) * sizeof(uint64_t);
     // Persistent grid: a few blocks per CU, each looping over work items.
     const uint32_t grid = min(p.items_cap, p.grid ? p.grid : 256u * 8u);

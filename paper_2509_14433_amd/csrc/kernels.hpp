@@ -16,6 +16,14 @@ struct DevSketch {
     uint32_t V, C, D;
 };
 
+// The batch a step works on, read by the kernels from device memory so that
+// one captured graph serves batches of any size up to its capacity.
+struct BatchDesc {
+    const uint64_t *upd;  // packed updates
+    uint32_t n;           // number of updates
+    uint32_t pad;
+};
+
 // Header words written by the classify kernel.
 enum { HDR_ERR = 0, HDR_NFLAG = 1, HDR_NFLAG_DEL = 2, HDR_WORDS = 4 };
 
@@ -34,7 +42,9 @@ struct StagedParams {
 // Flagged updates of classify block b (positions [b*4096, (b+1)*4096)) land
 // in stream order at offsets b*4096.. of fupd (capacity: the batch rounded
 // up to a multiple of 4096); fcnt[b] receives their number.
-hipError_t launch_classify(hipStream_t s, const uint64_t *upd, uint32_t n, uint32_t V,
+// grid_n sizes the grids (the batch size, or the capacity of a captured
+// graph); the kernels read the actual batch from desc.
+hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, uint32_t grid_n, uint32_t V,
                            const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles);
@@ -46,15 +56,19 @@ hipError_t launch_flag_compact(hipStream_t s, uint32_t n, const uint64_t *fupd,
                                const uint32_t *fcnt, uint32_t *foff, uint64_t *oupd);
 
 // Plain scatter: device-scope atomic XOR of (x, h) into both endpoints.
-hipError_t launch_scatter_atomic(hipStream_t s, const uint64_t *upd, uint32_t n,
+hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, uint32_t grid_n,
                                  DevSketch sk, const uint32_t *hdr);
 
-// Staged scatter, three launches: scan of tile counts into bin offsets and
-// work items; fill of the per-tile bins; LDS-staged XOR per work item.
-hipError_t launch_staged(hipStream_t s, const uint64_t *upd, uint32_t n, DevSketch sk,
-                         const uint32_t *hdr, const StagedParams &p, uint32_t *tile_cnt,
-                         uint32_t *tile_off, uint32_t *tile_cur, uint64_t *bins,
-                         uint32_t *items, uint32_t *nitems, hipEvent_t ev_binned);
+// Staged scatter: launch_bin = scan of tile counts into bin offsets and
+// work items, then fill of the per-tile bins; launch_tile = LDS-staged XOR
+// per work item.
+hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, uint32_t grid_n, DevSketch sk,
+                      const uint32_t *hdr, const StagedParams &p, uint32_t *tile_cnt,
+                      uint32_t *tile_off, uint32_t *tile_cur, uint64_t *bins, uint32_t *items,
+                      uint32_t *nitems);
+hipError_t launch_tile(hipStream_t s, DevSketch sk, const uint32_t *hdr, const StagedParams &p,
+                       const uint32_t *tile_off, const uint64_t *bins, const uint32_t *items,
+                       const uint32_t *nitems);
 
 // Fill n words with zero.
 hipError_t launch_zero(hipStream_t s, uint64_t *p, size_t n);

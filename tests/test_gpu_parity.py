@@ -262,3 +262,27 @@ def test_insert_only_batches(cupk, V, p, bs):
     assert ctx.num_components() == len(set(fr.labels().tolist()))
     _assert_same_sketch(ctx, ref)
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_graph_replay_ragged_batches(cupk, mode):
+    # captured graphs are replayed for ragged batch sizes (the kernels read
+    # the size from device memory), re-captured when the capacity grows, and
+    # checked against the oracle between replays
+    V, C, D, S = 700, 10, 20, 9
+    u, v, d = streamgen.er_standard(V, 0.05, 0.5, 99)
+    sizes = streamgen.ragged_sizes(len(u), 1, 3000, 5)
+    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode), use_graph=True, max_batch=512)
+    ref = oracle.Sketch(V, C, D, S)
+    fr = oracle.ForestReplay(ref)
+    off = 0
+    for k, sz in enumerate(sizes):
+        ctx.apply_updates(u[off:off + sz], v[off:off + sz], d[off:off + sz])
+        fr.apply_batch(u[off:off + sz], v[off:off + sz], d[off:off + sz])
+        off += sz
+        if k % 7 == 0:
+            assert ctx.digest() == ref.digest(), k
+    assert off == len(u) and len(sizes) > 10
+    _assert_same_sketch(ctx, ref)
+    assert ctx.forest_edges() == fr.forest_edges()
+    ctx.close()
