@@ -62,7 +62,7 @@ def traffic_from_profile(kernel: str):
     return ent.get("hbm_bytes_per_launch")
 
 
-def run_path(cupk, torch, packed, sizes, steps, warmup, mode, time_kernels=True):
+def run_path(cupk, torch, packed, sizes, steps, warmup, mode, time_kernels=True, graph=False):
     """Warm up, then time `steps` batches.  Returns (seconds, updates, ctr)."""
     offs = [0]
     for s in sizes:
@@ -71,7 +71,7 @@ def run_path(cupk, torch, packed, sizes, steps, warmup, mode, time_kernels=True)
 
     def new_ctx():
         return cupk.Context(V, C, D, SEED, scatter_mode=mode, max_batch=BATCH,
-                            time_kernels=time_kernels)
+                            time_kernels=time_kernels, use_graph=graph)
 
     # warmup on a throwaway context (code objects, buffers, clocks)
     w = new_ctx()
@@ -167,6 +167,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel run")
     ap.add_argument("--no-serve", action="store_true", help="skip the served run")
     ap.add_argument("--mode", default="staged", choices=["staged", "atomic"])
+    ap.add_argument("--graph", type=int, default=0,
+                    help="1: replay each batch's device work as captured HIP graphs")
     ap.add_argument("--calib", action="store_true",
                     help="first run a plain 256 MiB device copy (4 times) as the reference "
                          "for HBM byte counters")
@@ -199,7 +201,8 @@ def main():
         del src, dst
     mode = cupk.SCATTER_STAGED if args.mode == "staged" else cupk.SCATTER_ATOMIC
     print("bench: timing main path", file=sys.stderr, flush=True)
-    dt, total, ctr = run_path(cupk, torch, packed, sizes, args.steps, args.warmup, mode)
+    dt, total, ctr = run_path(cupk, torch, packed, sizes, args.steps, args.warmup, mode,
+                              graph=bool(args.graph))
     value = total / dt
     bpu = algorithmic_bytes_per_update(C)
     launches = max(1, ctr["scatter_launches"])
@@ -221,7 +224,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "V": V, "C": C, "D": D, "batch": BATCH,
-                   "scatter": args.mode, "parallelism": "single GPU"},
+                   "scatter": args.mode, "graph": bool(args.graph), "parallelism": "single GPU"},
         "roofline": roofline,
         "counters": {k: (round(val, 3) if isinstance(val, float) else val)
                      for k, val in ctr.items()},

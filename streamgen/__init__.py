@@ -24,10 +24,165 @@ all, then delete" stream shape of Sec. 5 / App. C):
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
+import subprocess
+
 import numpy as np
 
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libstreamgen.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile gen.c (the long-stream generators) with gcc, in place."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp,
+                               os.path.join(_HERE, "gen.c"), "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _c():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = ctypes.CDLL(_SO)
+        p, u32, u64, sz, dbl = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64,
+                                ctypes.c_size_t, ctypes.c_double)
+        L.sg_rmat.restype = sz
+        L.sg_rmat.argtypes = [u32, sz, dbl, dbl, dbl, dbl, u64, p, p, p]
+        L.sg_clustered.restype = sz
+        L.sg_clustered.argtypes = [u32, u32, dbl, u32, u32, u32, u32, u32, u64, sz, p, p, p]
+        _lib = L
+    return _lib
+
+
+def _arrays(n):
+    return (np.zeros(n, np.uint32), np.zeros(n, np.uint32), np.zeros(n, np.uint8))
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def rmat_interleaved(logV: int, n: int, del_prob: float, seed: int,
+                     a: float = 0.57, b: float = 0.19, c: float = 0.19):
+    """R-MAT (a, b, c, d=1-a-b-c) inserts with interleaved deletions: each
+    step deletes a uniformly random live edge with probability del_prob."""
+    u, v, d = _arrays(n)
+    got = _c().sg_rmat(logV, n, del_prob, a, b, c, seed, _p(u), _p(v), _p(d))
+    if got != n:
+        raise MemoryError("R-MAT generator failed")
+    return u, v, d
+
+
+class ForestTargetedDeletes:
+    """G(V, p) inserts in random order, then ``del_frac`` of the inserted
+    edges deleted, in chunks of ``rho`` updates.
+
+    Before each deletion chunk the caller passes the current spanning-forest
+    edges of whatever engine replays the stream (batch boundaries = chunk
+    boundaries; the library and the oracle hold the same forest there).  A
+    Binomial(chunk, ``forest_frac``) share of the chunk's deletions are
+    distinct uniform forest edges; the rest are uniform live non-forest
+    edges.  The order inside a chunk is random.  This module only picks
+    edges; it computes no forest itself.
+    """
+
+    def __init__(self, V: int, p: float, del_frac: float, forest_frac: float, seed: int,
+                 rho: int):
+        self.V, self.rho, self.forest_frac = V, rho, forest_frac
+        self.rng = np.random.default_rng(seed)
+        u, v = er_pairs(V, p, self.rng)
+        order = self.rng.permutation(u.shape[0])
+        self.u, self.v = u[order], v[order]
+        self.m = self.u.shape[0]
+        self.keys = self.u.astype(np.uint64) * V + self.v
+        self.sorted_idx = np.argsort(self.keys)
+        self.sorted_keys = self.keys[self.sorted_idx]
+        self.alive = np.ones(self.m, bool)
+        self.k = int(math.floor(del_frac * self.m))
+        self.deleted = 0
+
+    def insert_chunks(self):
+        """The insert phase, in chunks of rho updates."""
+        for s in range(0, self.m, self.rho):
+            e = min(self.m, s + self.rho)
+            yield self.u[s:e], self.v[s:e], np.zeros(e - s, np.uint8)
+
+    def _index(self, keys):
+        pos = np.searchsorted(self.sorted_keys, keys)
+        assert (self.sorted_keys[pos] == keys).all(), "forest edge not in the graph"
+        return self.sorted_idx[pos]
+
+    def deletes_left(self) -> int:
+        return self.k - self.deleted
+
+    def delete_chunk(self, forest_u, forest_v):
+        """The next chunk of deletions given the current forest edges."""
+        size = min(self.rho, self.k - self.deleted)
+        if size <= 0:
+            return None
+        fu = np.asarray(forest_u, np.uint64)
+        fv = np.asarray(forest_v, np.uint64)
+        f_idx = self._index(fu * self.V + fv) if fu.size else np.zeros(0, np.int64)
+        nf = min(int(self.rng.binomial(size, self.forest_frac)), f_idx.size)
+        pick_f = self.rng.choice(f_idx, size=nf, replace=False) if nf else np.zeros(0, np.int64)
+        in_forest = np.zeros(self.m, bool)
+        in_forest[f_idx] = True
+        chosen = np.zeros(self.m, bool)
+        chosen[pick_f] = True
+        need = size - nf
+        picks = []
+        while need > 0:
+            cand = self.rng.integers(0, self.m, size=2 * need + 16)
+            cand = cand[self.alive[cand] & ~in_forest[cand] & ~chosen[cand]]
+            cand = np.unique(cand)[:need]
+            if cand.size == 0:
+                break
+            self.rng.shuffle(cand)
+            chosen[cand] = True
+            picks.append(cand)
+            need -= cand.size
+        idx = np.concatenate([pick_f] + picks).astype(np.int64)
+        self.rng.shuffle(idx)
+        self.alive[idx] = False
+        self.deleted += idx.size
+        return self.u[idx], self.v[idx], np.ones(idx.size, np.uint8)
+
+
+def clustered_churn(K: int, S: int, p_in: float, n_sparse: int, extra_bridges: int,
+                    rounds: int, adv_every: int, adv_k: int, seed: int):
+    """Dense clusters joined by bridges plus a sparse remainder; each
+    cluster's first-arrival forest is inserted once, then `rounds` passes
+    insert and delete every other cluster edge; every adv_every updates
+    adv_k random bridges are toggled (vertices: clusters first, then the
+    sparse part)."""
+    per = S * (S - 1) / 2 * p_in
+    mean = K * per
+    churn = mean * (1 + 2 * rounds) + 8 * math.sqrt(mean + 1) * (1 + 2 * rounds)
+    base = 2 * n_sparse + K + extra_bridges + churn + 4096
+    adv = (base / adv_every + 1) * adv_k if adv_every else 0
+    cap = int((base + adv) * 1.05)
+    u, v, d = _arrays(cap)
+    got = _c().sg_clustered(K, S, p_in, n_sparse, extra_bridges, rounds, adv_every, adv_k, seed,
+                            cap, _p(u), _p(v), _p(d))
+    if got == 0:
+        raise MemoryError("generator failed or capacity too small")
+    return u[:got].copy(), v[:got].copy(), d[:got].copy()
+
 __all__ = [
+    "build",
+    "rmat_interleaved",
+    "ForestTargetedDeletes",
+    "clustered_churn",
+    "stream_of",
+    "SCALED",
     "er_standard",
     "er_pairs",
     "ragged_sizes",
@@ -150,13 +305,53 @@ CONFIGS = {
             S=0x5EED0000 + 0, batch=None),
     1: dict(name="er16384_p0.3_del10", V=16384, p=0.3, del_frac=0.10, seed=2,
             S=0x5EED0000 + 1, batch=1_000_000),
+    # R-MAT (0.57, 0.19, 0.19, 0.05) over 2^17 vertices, 5e8 updates, 15%
+    # interleaved deletions; ragged batches log-uniform in [1e3, 4e6]
+    2: dict(name="rmat17_del15", V=1 << 17, logV=17, n=500_000_000, del_prob=0.15, seed=3,
+            S=0x5EED0000 + 2, batch=(1000, 4_000_000)),
+    # G(65536, 0.2) inserts then 10% deletions, 30% of them on forest edges;
+    # a connectivity query every 1e5 updates
+    3: dict(name="er65536_p0.2_forestdel", V=65536, p=0.2, del_frac=0.10, forest_frac=0.30,
+            seed=4, S=0x5EED0000 + 3, rho=100_000),
+    # 64 clusters of 2048 (p=0.5) + sparse G(n, 2n) on the other 917,504
+    # vertices, 63 tree + 65 extra bridges, 11 churn rounds, 100 bridges
+    # toggled every 1e5 updates
+    4: dict(name="clusters64x2048_churn", V=1 << 20, K=64, Sc=2048, p_in=0.5, n_sparse=917_504,
+            extra_bridges=65, rounds=11, adv_every=100_000, adv_k=100, seed=5,
+            S=0x5EED0000 + 4, batch=1_000_000),
+}
+
+# The same recipes at sizes the CPU oracle replays in seconds (parity tests).
+SCALED = {
+    2: dict(name="rmat12_del15", V=1 << 12, logV=12, n=1_000_000, del_prob=0.15, seed=13,
+            S=0x5EED1002, batch=(100, 100_000)),
+    3: dict(name="er1024_p0.2_forestdel", V=1024, p=0.2, del_frac=0.10, forest_frac=0.30,
+            seed=14, S=0x5EED1003, rho=2_000),
+    4: dict(name="clusters8x128_churn", V=8 * 128 + 1024, K=8, Sc=128, p_in=0.5, n_sparse=1024,
+            extra_bridges=4, rounds=2, adv_every=3000, adv_k=3, seed=15, S=0x5EED1004,
+            batch=20_000),
 }
 
 
-def config_stream(i: int):
-    """The update stream of workload ``i`` (0 or 1) as (u, v, is_delete)."""
-    cfg = CONFIGS[i]
+def stream_of(cfg: dict):
+    """The update stream of a workload description (CONFIGS / SCALED); the
+    forest-targeted workload needs an engine and is built with
+    ``ForestTargetedDeletes`` instead."""
+    if "logV" in cfg:
+        return rmat_interleaved(cfg["logV"], cfg["n"], cfg["del_prob"], cfg["seed"])
+    if "forest_frac" in cfg:
+        raise ValueError("forest-targeted deletions need the current forest: "
+                         "use ForestTargetedDeletes")
+    if "K" in cfg:
+        return clustered_churn(cfg["K"], cfg["Sc"], cfg["p_in"], cfg["n_sparse"],
+                               cfg["extra_bridges"], cfg["rounds"], cfg["adv_every"],
+                               cfg["adv_k"], cfg["seed"])
     return er_standard(cfg["V"], cfg["p"], cfg["del_frac"], cfg["seed"])
+
+
+def config_stream(i: int, scaled: bool = False):
+    """The update stream of workload ``i`` as (u, v, is_delete)."""
+    return stream_of((SCALED if scaled else CONFIGS)[i])
 
 
 def ceil_log2(V: int) -> int:
