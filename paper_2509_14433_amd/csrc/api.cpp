@@ -43,7 +43,7 @@ double now_ms()
 // Message of the last failed cupk_sketch_init (no context survives it).
 thread_local std::string g_init_error;
 
-constexpr uint32_t kRedChunk = 64;          // members per reduction work item
+constexpr uint32_t kRedChunk = 32;          // members per reduction work item
 constexpr size_t kMaxBatchPerLaunch = 1u << 28;
 constexpr int kTimerRing = 64;
 
@@ -163,7 +163,7 @@ template <class T>
 hipError_t grow(DevBuf<T> &b, size_t need)
 {
     if (need <= b.cap) return hipSuccess;
-    size_t cap = std::max(need, b.cap + b.cap / 2);
+    size_t cap = std::max(need, 2 * b.cap);
     if (b.p) {
         hipError_t e = hipFree(b.p);
         b.p = nullptr;
@@ -180,7 +180,7 @@ template <class T>
 hipError_t grow(HostBuf<T> &b, size_t need)
 {
     if (need <= b.cap) return hipSuccess;
-    size_t cap = std::max(need, b.cap + b.cap / 2);
+    size_t cap = std::max(need, 2 * b.cap);
     if (b.p) {
         hipError_t e = hipHostFree(b.p);
         b.p = nullptr;
@@ -353,10 +353,16 @@ int run_rounds(cupk_ctx *ctx)
         }
     }
     int slot = 0;
+    double tr0 = now_ms();
     for (;;) {
         ctx->ctr.rounds++;
+        const double tr1 = now_ms();
         int rc = reduce_and_sample(ctx, slot, vmem, voff, fmem, foff);
         if (rc != CUPK_OK) return rc;
+        const double tr2 = now_ms();
+        if (ctx->trace)
+            fprintf(stderr, "cupk   round sets=%zu vmembers=%zu fmembers=%zu prep=%.3f gpu=%.3f ms\n",
+                    sets.size(), vmem.size(), fmem.size(), tr1 - tr0, tr2 - tr1);
         const int32_t *res = ctx->h_res.p;
         const size_t k = sets.size();
         // Link in ascending order of smallest vertex.  Sets are stored with
@@ -455,6 +461,7 @@ int run_rounds(cupk_ctx *ctx)
         if (foff.size() == 1) foff.clear();
         sets.swap(nsets);
         slot = 1 - slot;
+        tr0 = now_ms();
     }
     ctx->forest_dev_stale = true;
     return CUPK_OK;
@@ -892,6 +899,21 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     const size_t mb = ctx->opts.max_batch ? ctx->opts.max_batch : (1u << 20);
     int rc = ensure_batch_buffers(ctx, mb);
     if (rc != CUPK_OK) return rc;
+    // replacement-round buffers sized up front (every vertex as a member,
+    // up to 1024 sets), so rounds do not allocate (allocation and free can
+    // synchronise the device)
+    {
+        const size_t sets = std::min<size_t>(V, 1024);
+        const size_t items = V / kRedChunk + sets + 1;
+        HIPCHK(grow(ctx->d_sig[0], sets * ctx->W));
+        HIPCHK(grow(ctx->d_sig[1], sets * ctx->W));
+        HIPCHK(grow(ctx->d_res, 3 * sets));
+        HIPCHK(grow(ctx->h_res, 3 * sets));
+        HIPCHK(grow(ctx->d_ridx, (size_t)V + 1));
+        HIPCHK(grow(ctx->h_ridx, (size_t)V + 1));
+        HIPCHK(grow(ctx->d_ritems, 3 * items));
+        HIPCHK(grow(ctx->h_ritems, 3 * items));
+    }
     HIPCHK(hipStreamSynchronize(ctx->s));
     return CUPK_OK;
 }

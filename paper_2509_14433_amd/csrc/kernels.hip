@@ -584,8 +584,9 @@ hipError_t launch_zero32(hipStream_t s, uint32_t *p, size_t n)
 // atomics (a set may span several work items).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRedThreads = 256;
-constexpr uint32_t kRedMaxK = 32;  // W <= 8192 words (C*D <= 4096)
 
+// KMAX words per lane: slabs of up to KMAX*256 words (C*D*2 <= KMAX*256).
+template <uint32_t KMAX>
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const uint64_t *__restrict__ src,
                                                         uint32_t W,
                                                         const uint32_t *__restrict__ idx,
@@ -597,20 +598,31 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const uint64_t *__restri
         const uint32_t set = items[3 * it];
         const uint32_t b = items[3 * it + 1];
         const uint32_t e = items[3 * it + 2];
-        uint64_t acc[kRedMaxK];
+        uint64_t acc[KMAX];
 #pragma unroll
-        for (uint32_t k = 0; k < kRedMaxK; k++) acc[k] = 0;
-        for (uint32_t j = b; j < e; j++) {
-            const uint64_t *slab = src + (uint64_t)idx[j] * W;
+        for (uint32_t k = 0; k < KMAX; k++) acc[k] = 0;
+        uint32_t j = b;
+        // two slabs per step: twice the loads in flight
+        for (; j + 2 <= e; j += 2) {
+            const uint64_t *s0 = src + (uint64_t)idx[j] * W;
+            const uint64_t *s1 = src + (uint64_t)idx[j + 1] * W;
 #pragma unroll
-            for (uint32_t k = 0; k < kRedMaxK; k++) {
+            for (uint32_t k = 0; k < KMAX; k++) {
                 const uint32_t w = k * kRedThreads + threadIdx.x;
-                if (w < W) acc[k] ^= slab[w];
+                if (w < W) acc[k] ^= s0[w] ^ s1[w];
+            }
+        }
+        if (j < e) {
+            const uint64_t *s0 = src + (uint64_t)idx[j] * W;
+#pragma unroll
+            for (uint32_t k = 0; k < KMAX; k++) {
+                const uint32_t w = k * kRedThreads + threadIdx.x;
+                if (w < W) acc[k] ^= s0[w];
             }
         }
         uint64_t *o = out + (uint64_t)set * W;
 #pragma unroll
-        for (uint32_t k = 0; k < kRedMaxK; k++) {
+        for (uint32_t k = 0; k < KMAX; k++) {
             const uint32_t w = k * kRedThreads + threadIdx.x;
             if (w < W && acc[k]) gxor(&o[w], acc[k]);
         }
@@ -621,9 +633,17 @@ hipError_t launch_reduce(hipStream_t s, const uint64_t *src, uint32_t W, const u
                          const uint32_t *items, uint32_t nitems, uint64_t *out)
 {
     if (nitems == 0) return hipSuccess;
-    if (W > kRedMaxK * kRedThreads) return hipErrorInvalidValue;
-    const uint32_t grid = min(nitems, 4096u);
-    k_reduce<<<grid, kRedThreads, 0, s>>>(src, W, idx, items, nitems, out);
+    const uint32_t grid = min(nitems, 8192u);
+    if (W <= 4 * kRedThreads)
+        k_reduce<4><<<grid, kRedThreads, 0, s>>>(src, W, idx, items, nitems, out);
+    else if (W <= 8 * kRedThreads)
+        k_reduce<8><<<grid, kRedThreads, 0, s>>>(src, W, idx, items, nitems, out);
+    else if (W <= 16 * kRedThreads)
+        k_reduce<16><<<grid, kRedThreads, 0, s>>>(src, W, idx, items, nitems, out);
+    else if (W <= 32 * kRedThreads)
+        k_reduce<32><<<grid, kRedThreads, 0, s>>>(src, W, idx, items, nitems, out);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
