@@ -19,7 +19,10 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of oracle.c to load instead (the mutation
+# test uses it to check that the pins catch planted mistakes).
+_BUILT = os.path.join(_HERE, "liboracle.so")
+_SO = os.environ.get("ORACLE_LIB") or _BUILT
 _SRC = os.path.join(_HERE, "oracle.c")
 
 OK, EMPTY, FAILED = 0, 1, 2
@@ -27,12 +30,12 @@ OK, EMPTY, FAILED = 0, 1, 2
 
 def build(force: bool = True) -> str:
     """Compile ``oracle.c`` with gcc into ``liboracle.so`` (in place)."""
-    if force or not os.path.exists(_SO):
-        tmp = _SO + ".tmp%d" % os.getpid()
+    if force or not os.path.exists(_BUILT):
+        tmp = _BUILT + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC",
                                "-o", tmp, _SRC])
-        os.replace(tmp, _SO)
-    return _SO
+        os.replace(tmp, _BUILT)
+    return _BUILT
 
 
 _lib = None
