@@ -158,6 +158,142 @@ def served_leg(cupk, u, v, d, rho=100_000, inflight=4, max_batch=BATCH):
                      f"{inflight} requests ({inflight * rho * 8} B), host-memory input"}
 
 
+def _time_batches(cupk, torch, ctxkw, packed, sizes, V_, C_, D_, S_, tune_sample=None):
+    """One context over the whole stream in the given batches; returns
+    (seconds, counters, tune result)."""
+    ctx = cupk.Context(V_, C_, D_, S_, **ctxkw)
+    tune = None
+    if tune_sample is not None:
+        tune = ctx.autotune(tune_sample)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    off = 0
+    for sz in sizes:
+        ctx.apply_updates_device(packed[off:off + sz])
+        off += sz
+    ctx.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctr = ctx.counters()
+    ctx.close()
+    return dt, ctr, tune
+
+
+def workload_leg(args, cupk, torch, np, streamgen):
+    """Full-size runs of the other workload recipes (extra measurements)."""
+    name = args.workload
+    out = {"metric": "edge updates/sec", "unit": "updates/s", "n_gpus": 1, "data": "synthetic",
+           "dtype": "u64"}
+    if name in ("rmat17", "clusters"):
+        i = 2 if name == "rmat17" else 4
+        cfg = streamgen.CONFIGS[i]
+        print(f"bench: generating {cfg['name']}", file=sys.stderr, flush=True)
+        Vw = cfg["V"]
+        Cw = streamgen.ceil_log2(Vw)
+        Dw = 2 * Cw
+        if name == "rmat17":
+            n = cfg["n"]
+            packed = torch.empty(n, dtype=torch.int64, device="cuda")
+            off = 0
+            for u, v, d in streamgen.rmat_chunks(cfg["logV"], n, cfg["del_prob"], cfg["seed"]):
+                m = len(u)
+                packed[off:off + m].copy_(torch.from_numpy(cupk.pack_updates(u, v, d)
+                                                           .view(np.int64)))
+                off += m
+                print(f"bench: generated {off} of {n}", file=sys.stderr, flush=True)
+            sizes = streamgen.ragged_sizes(n, cfg["batch"][0], cfg["batch"][1], cfg["seed"])
+        else:
+            u, v, d = streamgen.config_stream(i)
+            n = len(u)
+            print(f"bench: generated {n} updates", file=sys.stderr, flush=True)
+            sizes = streamgen.fixed_sizes(n, cfg["batch"])
+            packed = torch.empty(n, dtype=torch.int64, device="cuda")
+            step = 1 << 26
+            for off in range(0, n, step):
+                e = min(n, off + step)
+                packed[off:e].copy_(torch.from_numpy(
+                    cupk.pack_updates(u[off:e], v[off:e], d[off:e]).view(np.int64)))
+            del u, v, d
+        torch.cuda.synchronize()
+        sample = packed[: min(n, 1 << 20)].contiguous()
+        res = {}
+        for label, kw, tune in (
+                ("plain_atomic", dict(scatter_mode=cupk.SCATTER_ATOMIC), False),
+                ("staged_autotuned", dict(scatter_mode=cupk.SCATTER_STAGED), True),
+                ("staged_autotuned_graph", dict(scatter_mode=cupk.SCATTER_STAGED,
+                                                use_graph=True), True)):
+            print(f"bench: {name} {label}", file=sys.stderr, flush=True)
+            dt, ctr, tr = _time_batches(cupk, torch, dict(kw, max_batch=max(sizes),
+                                                          time_kernels=True),
+                                        packed, sizes, Vw, Cw, Dw, cfg["S"],
+                                        sample if tune else None)
+            res[label] = {"value": round(n / dt, 1), "seconds": round(dt, 4),
+                          "scatter_ms": round(ctr["scatter_ms"], 3),
+                          "bin_ms": round(ctr["bin_ms"], 3), "links": ctr["links"],
+                          "cuts": ctr["cuts"], "rounds": ctr["rounds"],
+                          "sample_failed": ctr["sample_failed"]}
+            if tr:
+                res[label]["tune"] = {k: tr[k] for k in ("tile_vertices", "lds_rows",
+                                                         "chunk_records", "batch_target")}
+        out.update({"workload": cfg["name"], "updates": n, "batches": len(sizes), "V": Vw,
+                    "C": Cw, "D": Dw, "results": res})
+    elif name == "er65536_served":
+        cfg = streamgen.CONFIGS[3]
+        Vw = cfg["V"]
+        Cw = streamgen.ceil_log2(Vw)
+        Dw = 2 * Cw
+        print("bench: generating the insert phase", file=sys.stderr, flush=True)
+        g = streamgen.ForestTargetedDeletes(Vw, cfg["p"], cfg["del_frac"], cfg["forest_frac"],
+                                            cfg["seed"], cfg["rho"])
+        # record the stream: deletions pick forest edges of the library's own
+        # forest (untimed), so a replay with the same chunk boundaries hits
+        # current forest edges again
+        rec = list(g.insert_chunks())
+        ctx = cupk.Context(Vw, Cw, Dw, cfg["S"])
+        for ch in rec:
+            ctx.apply_updates(*ch)
+        nfd = 0
+        print("bench: recording forest-targeted deletions", file=sys.stderr, flush=True)
+        while True:
+            fe = ctx.forest_edges()
+            ch = g.delete_chunk([e[0] for e in fe], [e[1] for e in fe])
+            if ch is None:
+                break
+            fset = set(fe)
+            nfd += sum((a, b) in fset for a, b in zip(ch[0].tolist(), ch[1].tolist()))
+            ctx.apply_updates(*ch)
+            rec.append(ch)
+        ctx.close()
+        n = sum(len(ch[0]) for ch in rec)
+        rng = np.random.default_rng(17)
+        qs = rng.integers(0, Vw, size=(len(rec), 2))
+        res = {}
+        for inflight in (1, 4):
+            print(f"bench: served replay inflight={inflight}", file=sys.stderr, flush=True)
+            ctx = cupk.Context(Vw, Cw, Dw, cfg["S"], max_batch=cfg["rho"])
+            ctx.serve_start(max_batch=cfg["rho"], mem_budget_bytes=inflight * cfg["rho"] * 8)
+            t0 = time.perf_counter()
+            tickets = []
+            for k, ch in enumerate(rec):
+                tickets.append(ctx.submit_updates(*ch))
+                tickets.append(ctx.submit_query(int(qs[k, 0]), int(qs[k, 1])))
+            for t in tickets:
+                ctx.wait(t)
+            dt = time.perf_counter() - t0
+            st = ctx.serve_stats()
+            ctx.serve_stop()
+            c2 = ctx.counters()
+            ctx.close()
+            res[f"served_inflight{inflight}"] = {
+                "value": round(n / dt, 1), "query_p50_us": round(st["query_p50_us"], 1),
+                "query_p99_us": round(st["query_p99_us"], 1), "queries": st["queries"],
+                "batches": st["batches"], "cuts": c2["cuts"], "rounds": c2["rounds"]}
+        out.update({"workload": cfg["name"], "updates": n, "forest_deletions": nfd,
+                    "V": Vw, "C": Cw, "D": Dw, "rho": cfg["rho"], "results": res,
+                    "input": "host memory (PCIe included)"})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +305,10 @@ def main():
     ap.add_argument("--mode", default="staged", choices=["staged", "atomic"])
     ap.add_argument("--graph", type=int, default=0,
                     help="1: replay each batch's device work as captured HIP graphs")
+    ap.add_argument("--workload", default="er16384",
+                    choices=["er16384", "rmat17", "er65536_served", "clusters"],
+                    help="er16384: the benchmark line; the others print extra full-size "
+                         "measurements of the other workload recipes")
     ap.add_argument("--calib", action="store_true",
                     help="first run a plain 256 MiB device copy (4 times) as the reference "
                          "for HBM byte counters")
@@ -185,6 +325,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload != "er16384":
+        workload_leg(args, cupk, torch, np, streamgen)
+        return
     print("bench: generating stream", file=sys.stderr, flush=True)
     u, v, d = streamgen.config_stream(1)
     n = len(u)

@@ -54,8 +54,12 @@ def _c():
         L = ctypes.CDLL(_SO)
         p, u32, u64, sz, dbl = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64,
                                 ctypes.c_size_t, ctypes.c_double)
-        L.sg_rmat.restype = sz
-        L.sg_rmat.argtypes = [u32, sz, dbl, dbl, dbl, dbl, u64, p, p, p]
+        L.sg_rmat_new.restype = p
+        L.sg_rmat_new.argtypes = [u32, u64, sz]
+        L.sg_rmat_free.restype = None
+        L.sg_rmat_free.argtypes = [p]
+        L.sg_rmat_next.restype = sz
+        L.sg_rmat_next.argtypes = [p, sz, dbl, dbl, dbl, dbl, p, p, p]
         L.sg_clustered.restype = sz
         L.sg_clustered.argtypes = [u32, u32, dbl, u32, u32, u32, u32, u32, u64, sz, p, p, p]
         _lib = L
@@ -70,15 +74,36 @@ def _p(a):
     return ctypes.c_void_p(a.ctypes.data)
 
 
+def rmat_chunks(logV: int, n: int, del_prob: float, seed: int, chunk: int = 1 << 24,
+                a: float = 0.57, b: float = 0.19, c: float = 0.19):
+    """R-MAT (a, b, c, d=1-a-b-c) inserts with interleaved deletions (each
+    step deletes a uniformly random live edge with probability del_prob),
+    yielded in pieces of ``chunk`` updates; the pieces concatenate to the
+    stream ``rmat_interleaved`` returns."""
+    L = _c()
+    h = L.sg_rmat_new(logV, seed, n)
+    if not h:
+        raise MemoryError("R-MAT generator allocation failed")
+    try:
+        done = 0
+        while done < n:
+            m = min(chunk, n - done)
+            u, v, d = _arrays(m)
+            if L.sg_rmat_next(h, m, del_prob, a, b, c, _p(u), _p(v), _p(d)) != m:
+                raise MemoryError("R-MAT generator failed")
+            done += m
+            yield u, v, d
+    finally:
+        L.sg_rmat_free(h)
+
+
 def rmat_interleaved(logV: int, n: int, del_prob: float, seed: int,
                      a: float = 0.57, b: float = 0.19, c: float = 0.19):
-    """R-MAT (a, b, c, d=1-a-b-c) inserts with interleaved deletions: each
-    step deletes a uniformly random live edge with probability del_prob."""
-    u, v, d = _arrays(n)
-    got = _c().sg_rmat(logV, n, del_prob, a, b, c, seed, _p(u), _p(v), _p(d))
-    if got != n:
-        raise MemoryError("R-MAT generator failed")
-    return u, v, d
+    """The whole R-MAT stream as (u, v, is_delete) arrays."""
+    parts = list(rmat_chunks(logV, n, del_prob, seed, a=a, b=b, c=c))
+    if not parts:
+        return _arrays(0)
+    return tuple(np.concatenate([p[k] for p in parts]) for k in range(3))
 
 
 class ForestTargetedDeletes:
@@ -179,6 +204,7 @@ def clustered_churn(K: int, S: int, p_in: float, n_sparse: int, extra_bridges: i
 __all__ = [
     "build",
     "rmat_interleaved",
+    "rmat_chunks",
     "ForestTargetedDeletes",
     "clustered_churn",
     "stream_of",

@@ -63,57 +63,86 @@ static void bit_set(uint64_t *bm, uint64_t k) { bm[k >> 6] |= 1ULL << (k & 63); 
 static void bit_clr(uint64_t *bm, uint64_t k) { bm[k >> 6] &= ~(1ULL << (k & 63)); }
 
 /*
- * R-MAT stream with interleaved deletions.
+ * R-MAT stream with interleaved deletions, drawn in resumable pieces.
  * At each step, with probability del_prob (if any edge is live) a uniformly
  * random live edge is deleted; otherwise an R-MAT edge (quadrant
  * probabilities a, b, c, 1-a-b-c over logV levels) is drawn, canonicalised
  * to u < v and inserted; self loops and live pairs are re-drawn (after 64
  * failed R-MAT draws, uniform pairs are drawn instead).
- * Returns the number of updates written (n), or 0 on allocation failure.
  */
-size_t sg_rmat(uint32_t logV, size_t n, double del_prob, double a, double b, double c,
-               uint64_t seed, uint32_t *u, uint32_t *v, uint8_t *d)
-{
-    const uint64_t V = 1ULL << logV;
-    const uint64_t nbits = V * V;
-    uint64_t *bm = (uint64_t *)calloc((nbits + 63) / 64, 8);
-    uint64_t *live = (uint64_t *)malloc(sizeof(uint64_t) * (n ? n : 1));
-    if (!bm || !live) {
-        free(bm);
-        free(live);
-        return 0;
-    }
+typedef struct {
     rng_t r;
-    rng_seed(&r, seed);
-    size_t nlive = 0;
+    uint32_t logV;
+    uint64_t V;
+    uint64_t *bm;   /* live pairs, V*V bits */
+    uint64_t *live; /* live edge keys */
+    size_t nlive, cap;
+} rmat_t;
+
+void *sg_rmat_new(uint32_t logV, uint64_t seed, size_t max_live)
+{
+    rmat_t *g = (rmat_t *)calloc(1, sizeof(rmat_t));
+    if (!g) return NULL;
+    g->logV = logV;
+    g->V = 1ULL << logV;
+    g->bm = (uint64_t *)calloc((g->V * g->V + 63) / 64, 8);
+    g->cap = max_live ? max_live : 1;
+    g->live = (uint64_t *)malloc(sizeof(uint64_t) * g->cap);
+    if (!g->bm || !g->live) {
+        free(g->bm);
+        free(g->live);
+        free(g);
+        return NULL;
+    }
+    rng_seed(&g->r, seed);
+    return g;
+}
+
+void sg_rmat_free(void *h)
+{
+    rmat_t *g = (rmat_t *)h;
+    if (!g) return;
+    free(g->bm);
+    free(g->live);
+    free(g);
+}
+
+/* Next n updates; returns n, or 0 if the live list would overflow. */
+size_t sg_rmat_next(void *h, size_t n, double del_prob, double a, double b, double c,
+                    uint32_t *u, uint32_t *v, uint8_t *d)
+{
+    rmat_t *g = (rmat_t *)h;
+    rng_t *r = &g->r;
+    const uint64_t V = g->V;
     const double ab = a + b, abc = a + b + c;
     for (size_t i = 0; i < n; i++) {
-        if (nlive > 0 && rng_unif(&r) < del_prob) {
-            const uint64_t j = rng_below(&r, nlive);
-            const uint64_t key = live[j];
-            live[j] = live[--nlive];
-            bit_clr(bm, key);
+        if (g->nlive > 0 && rng_unif(r) < del_prob) {
+            const uint64_t j = rng_below(r, g->nlive);
+            const uint64_t key = g->live[j];
+            g->live[j] = g->live[--g->nlive];
+            bit_clr(g->bm, key);
             u[i] = (uint32_t)(key / V);
             v[i] = (uint32_t)(key % V);
             d[i] = 1;
             continue;
         }
+        if (g->nlive >= g->cap) return 0;
         uint64_t x, y, key;
         int tries = 0;
         for (;;) {
             if (tries < 64) {
                 x = 0;
                 y = 0;
-                for (uint32_t l = 0; l < logV; l++) {
-                    const double q = rng_unif(&r);
+                for (uint32_t l = 0; l < g->logV; l++) {
+                    const double q = rng_unif(r);
                     const int bx = q >= ab;                       /* quadrants c, d */
                     const int by = (q >= a && q < ab) || q >= abc; /* quadrants b, d */
                     x = (x << 1) | (uint64_t)bx;
                     y = (y << 1) | (uint64_t)by;
                 }
             } else {
-                x = rng_below(&r, V);
-                y = rng_below(&r, V);
+                x = rng_below(r, V);
+                y = rng_below(r, V);
             }
             tries++;
             if (x == y) continue;
@@ -123,16 +152,14 @@ size_t sg_rmat(uint32_t logV, size_t n, double del_prob, double a, double b, dou
                 y = t;
             }
             key = x * V + y;
-            if (!bit_get(bm, key)) break;
+            if (!bit_get(g->bm, key)) break;
         }
-        bit_set(bm, key);
-        live[nlive++] = key;
+        bit_set(g->bm, key);
+        g->live[g->nlive++] = key;
         u[i] = (uint32_t)x;
         v[i] = (uint32_t)y;
         d[i] = 0;
     }
-    free(bm);
-    free(live);
     return n;
 }
 
