@@ -2,14 +2,17 @@
 //
 // The paper answers connectivity queries from a sketchless dynamic tree on
 // the top level (Sec. 4.1) and links / cuts forest edges as updates demand
-// (cutset Link / Cut, Sec. 2.2.1).  Here the forest is a rooted forest with
-// parent pointers plus one label per vertex naming its tree:
+// (cutset Link / Cut, Sec. 2.2.1).  Here the forest is a rooted forest:
+// parent pointers, child lists (each child knows its slot in its parent's
+// list, so an edge is removed in O(1)), and one label per vertex naming its
+// tree:
 //   - link(a, b): the smaller tree is re-rooted at its endpoint, hung below
 //     the other endpoint and relabelled (work proportional to the smaller
 //     tree);
 //   - cut(a, b): the edge is removed and the two sides are explored by
-//     interleaved breadth-first search, so the work is proportional to the
-//     smaller side, which gets a fresh label.
+//     breadth-first searches interleaved edge by edge, so the work is
+//     proportional to the smaller side (even next to a high-degree
+//     vertex); the smaller side gets a fresh label.
 // Labels come from a free list in [0, V), so label arrays are V words and
 // the device can classify updates against them (lbl[u] != lbl[v] means u
 // and v are in different trees; par[] identifies forest edges).
@@ -33,10 +36,12 @@ class Forest {
         V_ = V;
         lbl_ = lbl;
         par_ = par;
-        adj_.assign(V, {});
-        // most forest vertices have a few tree neighbours: reserving them
-        // up front keeps links free of small reallocations
-        for (auto &a : adj_) a.reserve(4);
+        kids_.assign(V, {});
+        // most tree vertices have a few children: reserving them keeps
+        // relinking free of small reallocations
+        for (auto &k : kids_) k.reserve(2);
+        kid_pos_.assign(V, 0);
+        bfs_par_.assign(V, kNone);
         size_.assign(V, 1);
         root_.resize(V);
         dirty_.assign(V, 0);
@@ -95,25 +100,40 @@ class Forest {
             std::swap(a, b);
             std::swap(la, lb);
         }
-        // re-root a's (smaller) tree at a, hang it below b, relabel to lb
+        // re-root a's (smaller) tree at a: breadth-first search over its
+        // undirected tree edges, remembering each vertex's search parent
         const uint32_t ep = next_epoch();
         queue_.clear();
         queue_.push_back(a);
         stamp_[a] = ep;
-        par_[a] = b;
-        lbl_[a] = lb;
+        bfs_par_[a] = kNone;
         for (size_t qi = 0; qi < queue_.size(); qi++) {
             const uint32_t x = queue_[qi];
-            for (uint32_t y : adj_[x]) {
+            const uint32_t px = par_[x];
+            if (px != kNone && stamp_[px] != ep) {
+                stamp_[px] = ep;
+                bfs_par_[px] = x;
+                queue_.push_back(px);
+            }
+            for (uint32_t y : kids_[x]) {
                 if (stamp_[y] == ep) continue;
                 stamp_[y] = ep;
-                par_[y] = x;
-                lbl_[y] = lb;
+                bfs_par_[y] = x;
                 queue_.push_back(y);
             }
         }
-        adj_[a].push_back(b);
-        adj_[b].push_back(a);
+        // rebuild parent pointers and child lists from the search tree, hang
+        // a below b and relabel
+        for (uint32_t x : queue_) kids_[x].clear();
+        for (uint32_t x : queue_) {
+            lbl_[x] = lb;
+            const uint32_t p = bfs_par_[x];
+            if (p == kNone) continue;
+            par_[x] = p;
+            add_kid(p, x);
+        }
+        par_[a] = b;
+        add_kid(b, a);
         size_[lb] += size_[la];
         if (dirty_[la]) set_dirty(lb);
         dirty_[la] = 0;
@@ -126,14 +146,14 @@ class Forest {
     // Cut forest edge {a, b}.  Returns (label of a's side, label of b's side).
     std::pair<uint32_t, uint32_t> cut(uint32_t a, uint32_t b)
     {
-        remove_adj(a, b);
-        remove_adj(b, a);
         const uint32_t old = lbl_[a];
         // the child endpoint becomes the root of its side
-        uint32_t child = par_[a] == b ? a : b;
+        const uint32_t child = par_[a] == b ? a : b;
+        const uint32_t parent = child == a ? b : a;
+        remove_kid(parent, child);
         par_[child] = kNone;
-        // interleaved BFS from a and b; the side that finishes first is the
-        // smaller one (up to one vertex)
+        // breadth-first searches from a and b, interleaved one edge at a
+        // time; the side that finishes first is the smaller one
         const uint32_t ea = next_epoch();
         const uint32_t eb = next_epoch();
         qa_.clear();
@@ -142,19 +162,17 @@ class Forest {
         qb_.push_back(b);
         stamp_[a] = ea;
         stamp_[b] = eb;
-        size_t ia = 0, ib = 0;
+        Walk wa{0, 0}, wb{0, 0};
         bool a_small;
         for (;;) {
-            if (ia == qa_.size()) {
+            if (!step(qa_, wa, ea)) {
                 a_small = true;
                 break;
             }
-            if (ib == qb_.size()) {
+            if (!step(qb_, wb, eb)) {
                 a_small = false;
                 break;
             }
-            expand(qa_, ia, ea);
-            expand(qb_, ib, eb);
         }
         const std::vector<uint32_t> &small = a_small ? qa_ : qb_;
         const uint32_t nl = free_.back();
@@ -191,11 +209,10 @@ class Forest {
         out.push_back(r);
         stamp_[r] = ep;
         uint32_t mn = r;
+        (void)ep;
         for (size_t qi = start; qi < out.size(); qi++) {
             const uint32_t x = out[qi];
-            for (uint32_t y : adj_[x]) {
-                if (stamp_[y] == ep) continue;
-                stamp_[y] = ep;
+            for (uint32_t y : kids_[x]) {
                 out.push_back(y);
                 mn = std::min(mn, y);
             }
@@ -221,30 +238,64 @@ class Forest {
         }
         return epoch_;
     }
-    void expand(std::vector<uint32_t> &q, size_t &i, uint32_t ep)
+    // position of an interleaved search: queue index, and the next
+    // neighbour of that vertex to look at (0 = its parent, 1+k = child k)
+    struct Walk {
+        size_t qi;
+        size_t ni;
+    };
+    // Advance a search by one tree edge.  Returns false when the search has
+    // no vertex left to expand (its side is complete).
+    bool step(std::vector<uint32_t> &q, Walk &w, uint32_t ep)
     {
-        const uint32_t x = q[i++];
-        for (uint32_t y : adj_[x]) {
-            if (stamp_[y] == ep) continue;
-            stamp_[y] = ep;
-            q.push_back(y);
+        for (;;) {
+            if (w.qi == q.size()) return false;
+            const uint32_t x = q[w.qi];
+            const auto &k = kids_[x];
+            if (w.ni == 0) {
+                w.ni = 1;
+                const uint32_t p = par_[x];
+                if (p != kNone && stamp_[p] != ep) {
+                    stamp_[p] = ep;
+                    q.push_back(p);
+                    return true;
+                }
+                continue;
+            }
+            if (w.ni - 1 < k.size()) {
+                const uint32_t y = k[w.ni - 1];
+                w.ni++;
+                if (stamp_[y] != ep) {
+                    stamp_[y] = ep;
+                    q.push_back(y);
+                }
+                return true;
+            }
+            w.qi++;
+            w.ni = 0;
         }
     }
-    void remove_adj(uint32_t a, uint32_t b)
+    void add_kid(uint32_t p, uint32_t c)
     {
-        auto &v = adj_[a];
-        for (size_t i = 0; i < v.size(); i++)
-            if (v[i] == b) {
-                v[i] = v.back();
-                v.pop_back();
-                return;
-            }
+        kid_pos_[c] = (uint32_t)kids_[p].size();
+        kids_[p].push_back(c);
+    }
+    void remove_kid(uint32_t p, uint32_t c)
+    {
+        auto &k = kids_[p];
+        const uint32_t i = kid_pos_[c];
+        const uint32_t last = k.back();
+        k[i] = last;
+        kid_pos_[last] = i;
+        k.pop_back();
     }
 
     uint32_t V_ = 0;
     uint32_t *lbl_ = nullptr;
     uint32_t *par_ = nullptr;
-    std::vector<std::vector<uint32_t>> adj_;
+    std::vector<std::vector<uint32_t>> kids_;  // children of each vertex
+    std::vector<uint32_t> kid_pos_;            // slot of a vertex in its parent's list
+    std::vector<uint32_t> bfs_par_;            // scratch of link
     std::vector<uint32_t> size_;   // by label
     std::vector<uint32_t> root_;   // by label
     std::vector<uint8_t> dirty_;   // by label

@@ -1,0 +1,30 @@
+"""Host forest (links, cuts, labels, roots, member collection) checked
+against a naive adjacency-set model under random operations, including a
+high-degree hub and long paths; built with address and undefined-behaviour
+sanitizers (host code only)."""
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def binary():
+    d = tempfile.mkdtemp()
+    exe = os.path.join(d, "forest_check")
+    subprocess.check_call([
+        "g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+        "-fno-sanitize-recover=all", "-I", os.path.join(ROOT, "paper_2509_14433_amd", "csrc"),
+        os.path.join(ROOT, "tests", "native", "forest_check.cpp"), "-o", exe])
+    return exe
+
+
+@pytest.mark.parametrize("V,steps,seed", [(8, 3000, 1), (60, 3000, 2), (200, 1500, 3),
+                                          (2, 200, 4)])
+def test_forest_matches_naive_model(binary, V, steps, seed):
+    r = subprocess.run([binary, str(V), str(steps), str(seed)], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
