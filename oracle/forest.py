@@ -18,14 +18,19 @@ start of the batch:
    resulting trees are marked dirty.  Any other update only touches the
    sketch (an insert inside a batch-start component that a cut separated is
    left to step 3);
-3. replacement rounds: the dirty trees, ordered by their smallest vertex id,
-   are each reduced to one sketch (XOR of the members' sketches) and sampled;
-   then, in that order, each sampled edge (x,y) is linked if x and y are in
-   different trees at that moment.  A tree whose sample is EMPTY has no cut
-   edge (it is a whole component) and becomes clean.  Trees that took part in
-   a link form the next round; a tree whose sample FAILED and that was not
-   merged stays dirty for the next batch.  Rounds stop when a round links
-   nothing.
+3. replacement rounds over the dirty trees.  Clean trees are whole
+   components, so every edge leaving a dirty tree ends in another dirty tree
+   (the search-from-the-smaller-side argument).  Each round therefore skips
+   the largest dirty tree (ties: smallest vertex id) and samples all the
+   others: each is reduced to one sketch (XOR of its members' sketches) and
+   queried; then, in ascending order of smallest vertex id, each sampled
+   edge (x,y) is linked if x and y are in different trees at that moment.  A
+   tree whose sample is EMPTY has no cut edge (it is a whole component) and
+   becomes clean.  A single remaining dirty tree is a whole component and
+   becomes clean.  If a round links nothing, the rounds stop: when no sample
+   FAILED the skipped tree is a whole component too and becomes clean;
+   otherwise the failed trees and the skipped one stay dirty for the next
+   batch.
 
 With batches of one update this is the per-update method; larger batches
 defer replacement search to the end of the batch, where queries observe the
@@ -138,48 +143,49 @@ class ForestReplay:
                     self.mark.add(b)
         self._rounds()
 
-    def _rounds(self):
-        # trees containing a marked vertex, each once
-        active = []
-        seen = set()
+    def _dirty_trees(self):
+        trees, seen = [], set()
         for w in sorted(self.mark):
             if w in seen:
                 continue
             t = self.tree_of(w)
             seen |= t
-            active.append(t)
-        while active:
+            trees.append(t)
+        return trees
+
+    def _rounds(self):
+        while True:
+            D = self._dirty_trees()
+            if not D:
+                return
+            if len(D) == 1:
+                self.mark -= D[0]
+                return
+            L = max(D, key=lambda t: (len(t), -min(t)))
+            S = sorted((t for t in D if t is not L), key=min)
             self.n_rounds += 1
-            active.sort(key=min)
             results = []
-            for t in active:
+            for t in S:
                 a, g = self.sk.set_sketch(np.fromiter(sorted(t), np.uint32, len(t)))
                 results.append(self.sk.sample(a, g))
-            self.round_log.append([(min(t), r[0], r[1], r[2]) for t, r in zip(active, results)])
-            link_ends = []
-            for t, (st, x, y) in zip(active, results):
+            self.round_log.append([(min(t), r[0], r[1], r[2]) for t, r in zip(S, results)])
+            linked = False
+            for t, (st, x, y) in zip(S, results):
                 if st == 0 and not self.connected(x, y):
                     self._link(x, y)
-                    link_ends.append(x)
-            for t, (st, x, y) in zip(active, results):
+                    linked = True
+            failed = False
+            for t, (st, x, y) in zip(S, results):
                 if st == 1:
-                    self.mark -= t
+                    if self.tree_of(min(t)) == t:   # not merged this round
+                        self.mark -= t
                 elif st == 2:
                     self.n_failed += 1
-            if not link_ends:
-                break
-            nxt = []
-            seen = set()
-            for w in link_ends:
-                if w in seen:
-                    continue
-                t = self.tree_of(w)
-                seen |= t
-                nxt.append(t)
-            # a merged tree stays dirty
-            for t in nxt:
-                self.mark.add(min(t))
-            active = nxt
+                    failed = True
+            if not linked:
+                if not failed:
+                    self.mark -= L
+                return
 
 
 def components_truth(V, u, v):

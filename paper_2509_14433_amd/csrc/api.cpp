@@ -7,9 +7,10 @@
 //   4. meanwhile on the host: read the flagged updates (copy stream), sort
 //      them back into stream order and apply links / cuts to the forest;
 //   5. replacement rounds for trees broken by cuts: segmented XOR reduction
-//      of every dirty tree in one launch, verify/sample in one launch, host
-//      links in ascending order of each tree's smallest vertex; merged trees
-//      are reduced from their fragments' sketches in the next round.
+//      of every dirty tree but the largest in one launch, verify/sample in
+//      one launch, host links in ascending order of each tree's smallest
+//      vertex; merged trees are reduced from their fragments' sketches in
+//      the next round.
 // The batch semantics match the tests' CPU oracle bit for bit: same sketch,
 // same forest edges, same samples.
 #include <hip/hip_runtime.h>
@@ -322,120 +323,87 @@ int reduce_and_sample(cupk_ctx *ctx, int slot, const std::vector<uint32_t> &vmem
     return CUPK_OK;
 }
 
-// Replacement rounds over the dirty trees (see file header).
+// Replacement rounds over the dirty trees.
+//
+// Clean trees are whole components, so every edge that leaves a dirty tree
+// ends in another dirty tree.  Each round therefore leaves out the largest
+// dirty tree (ties: smallest vertex id) and samples all the others, each
+// reduced from its vertices or, when it is a union of trees sampled in the
+// previous round, from their sketches; links go in ascending order of each
+// tree's smallest vertex.  A tree that samples EMPTY is a whole component;
+// so is a lone dirty tree, and so is the left-out tree once a round links
+// nothing and no sample failed.  Trees whose sample failed stay dirty.
 int run_rounds(cupk_ctx *ctx)
 {
     Forest &F = ctx->forest;
-    std::vector<uint32_t> labels = F.dirty_labels();
-    if (labels.empty()) return CUPK_OK;
-
-    // round state: sets in sampling order
-    std::vector<RoundSet> sets;
+    std::vector<RoundSet> sets;  // sets of the previous round, in d_sig order
     std::vector<uint32_t> vmem, voff, fmem, foff;
-    std::vector<std::pair<uint32_t, size_t>> order;  // (minv, index)
-
-    // first round: every dirty tree from its vertices
-    {
-        std::vector<std::vector<uint32_t>> lists(labels.size());
-        std::vector<RoundSet> tmp(labels.size());
-        for (size_t i = 0; i < labels.size(); i++) {
-            const uint32_t mn = F.collect(labels[i], lists[i]);
-            tmp[i] = {labels[i], mn, (uint32_t)lists[i].size()};
-        }
-        order.clear();
-        for (size_t i = 0; i < tmp.size(); i++) order.push_back({tmp[i].minv, i});
-        std::sort(order.begin(), order.end());
-        voff.push_back(0);
-        for (auto &o : order) {
-            sets.push_back(tmp[o.second]);
-            vmem.insert(vmem.end(), lists[o.second].begin(), lists[o.second].end());
-            voff.push_back((uint32_t)vmem.size());
-        }
-    }
+    struct Group {
+        uint32_t label, minv, size;
+        std::vector<uint32_t> frags;  // previous-round sets forming the tree
+        bool from_frags, have_minv;
+    };
     int slot = 0;
+    bool linked_any = false;
     double tr0 = now_ms();
     for (;;) {
-        ctx->ctr.rounds++;
-        const double tr1 = now_ms();
-        int rc = reduce_and_sample(ctx, slot, vmem, voff, fmem, foff);
-        if (rc != CUPK_OK) return rc;
-        const double tr2 = now_ms();
-        if (ctx->trace)
-            fprintf(stderr, "cupk   round sets=%zu vmembers=%zu fmembers=%zu prep=%.3f gpu=%.3f ms\n",
-                    sets.size(), vmem.size(), fmem.size(), tr1 - tr0, tr2 - tr1);
-        const int32_t *res = ctx->h_res.p;
-        const size_t k = sets.size();
-        // Link in ascending order of smallest vertex.  Sets are stored with
-        // vertex-reduced sets first, then fragment sets, each group sorted;
-        // merge the two orders.
-        const size_t kv = voff.empty() ? 0 : voff.size() - 1;
-        std::vector<size_t> ord(k);
-        for (size_t i = 0; i < k; i++) ord[i] = i;
-        std::stable_sort(ord.begin(), ord.end(),
-                         [&](size_t a, size_t b) { return sets[a].minv < sets[b].minv; });
-        (void)kv;
-        std::vector<uint32_t> linked_x;
-        for (size_t oi = 0; oi < k; oi++) {
-            const size_t i = ord[oi];
-            if (res[3 * i] != CUPK_OK) continue;
-            const uint32_t x = (uint32_t)res[3 * i + 1], y = (uint32_t)res[3 * i + 2];
-            if (!F.same_tree(x, y)) {
-                F.link(x, y);
-                ctx->ctr.links++;
-                linked_x.push_back(x);
-            }
+        const std::vector<uint32_t> labels = F.dirty_labels();
+        if (labels.empty()) break;
+        if (labels.size() == 1) {
+            F.clear_dirty(labels[0]);
+            break;
         }
-        for (size_t i = 0; i < k; i++) {
-            const int st = res[3 * i];
-            if (st == CUPK_EMPTY) {
-                // a whole component: clean, unless it was merged this round
-                const uint32_t l = F.label(sets[i].minv);
-                if (l == sets[i].label && F.tree_size(l) == sets[i].size) F.clear_dirty(l);
-            } else if (st == CUPK_SAMPLE_FAILED) {
-                ctx->ctr.sample_failed++;
-            }
-        }
-        if (linked_x.empty()) break;
-
-        // next round: trees that took part in a link, reduced from the
-        // fragments of this round when they consist of fragments only
-        std::vector<uint32_t> nl;
-        for (uint32_t x : linked_x) nl.push_back(F.label(x));
-        std::sort(nl.begin(), nl.end());
-        nl.erase(std::unique(nl.begin(), nl.end()), nl.end());
-        // fragments per label
+        // previous-round sets grouped by the tree they now belong to
         std::vector<std::pair<uint32_t, uint32_t>> frag;  // (label, set index)
-        for (size_t i = 0; i < k; i++) frag.push_back({F.label(sets[i].minv), (uint32_t)i});
+        frag.reserve(sets.size());
+        for (size_t i = 0; i < sets.size(); i++)
+            frag.push_back({F.label(sets[i].minv), (uint32_t)i});
         std::sort(frag.begin(), frag.end());
-        struct Group {
-            uint32_t label, minv, size;
-            std::vector<uint32_t> frags;
-            bool from_frags;
-        };
-        std::vector<Group> groups;
-        for (uint32_t l : nl) {
-            Group g{l, 0xffffffffu, 0, {}, true};
-            auto it = std::lower_bound(frag.begin(), frag.end(), std::make_pair(l, 0u));
+        std::vector<Group> groups(labels.size());
+        uint32_t maxs = 0;
+        for (size_t gi = 0; gi < labels.size(); gi++) {
+            Group &g = groups[gi];
+            g.label = labels[gi];
+            g.size = F.tree_size(g.label);
+            g.minv = 0xffffffffu;
             uint32_t tot = 0;
-            for (; it != frag.end() && it->first == l; ++it) {
+            auto it = std::lower_bound(frag.begin(), frag.end(), std::make_pair(g.label, 0u));
+            for (; it != frag.end() && it->first == g.label; ++it) {
                 g.frags.push_back(it->second);
                 tot += sets[it->second].size;
                 g.minv = std::min(g.minv, sets[it->second].minv);
             }
-            g.size = F.tree_size(l);
-            if (tot != g.size) {
-                g.from_frags = false;
-                g.frags.clear();
-            }
-            groups.push_back(std::move(g));
+            g.from_frags = g.have_minv = (tot == g.size);
+            if (!g.from_frags) g.frags.clear();
+            maxs = std::max(maxs, g.size);
         }
+        // the left-out tree: largest, ties broken by smallest vertex id
         std::vector<std::vector<uint32_t>> lists(groups.size());
+        size_t skip = groups.size();
+        for (size_t gi = 0; gi < groups.size(); gi++) {
+            if (groups[gi].size != maxs) continue;
+            if (skip == groups.size()) {
+                skip = gi;
+                continue;
+            }
+            for (size_t t : {skip, gi})
+                if (!groups[t].have_minv) {
+                    groups[t].minv = F.collect(groups[t].label, lists[t]);
+                    groups[t].have_minv = true;
+                }
+            if (groups[gi].minv < groups[skip].minv) skip = gi;
+        }
         for (size_t gi = 0; gi < groups.size(); gi++)
-            if (!groups[gi].from_frags) groups[gi].minv = F.collect(groups[gi].label, lists[gi]);
-        std::vector<size_t> gord(groups.size());
-        for (size_t i = 0; i < gord.size(); i++) gord[i] = i;
+            if (gi != skip && !groups[gi].from_frags && lists[gi].empty())
+                groups[gi].minv = F.collect(groups[gi].label, lists[gi]);
+        std::vector<size_t> gord;
+        gord.reserve(groups.size());
+        for (size_t gi = 0; gi < groups.size(); gi++)
+            if (gi != skip) gord.push_back(gi);
         std::sort(gord.begin(), gord.end(),
                   [&](size_t a, size_t b) { return groups[a].minv < groups[b].minv; });
+        // vertex-reduced sets first, then fragment sets (see
+        // reduce_and_sample); each group in ascending smallest-vertex order
         std::vector<RoundSet> nsets;
         vmem.clear();
         voff.clear();
@@ -443,8 +411,6 @@ int run_rounds(cupk_ctx *ctx)
         foff.clear();
         voff.push_back(0);
         foff.push_back(0);
-        // vertex-reduced groups first, then fragment groups (see
-        // reduce_and_sample); each in ascending smallest-vertex order
         for (size_t gi : gord)
             if (!groups[gi].from_frags) {
                 nsets.push_back({groups[gi].label, groups[gi].minv, groups[gi].size});
@@ -460,10 +426,55 @@ int run_rounds(cupk_ctx *ctx)
         if (voff.size() == 1) voff.clear();
         if (foff.size() == 1) foff.clear();
         sets.swap(nsets);
+        const uint32_t skip_label = groups[skip].label;
+
+        ctx->ctr.rounds++;
+        const double tr1 = now_ms();
+        int rc = reduce_and_sample(ctx, slot, vmem, voff, fmem, foff);
+        if (rc != CUPK_OK) return rc;
+        const double tr2 = now_ms();
+        if (ctx->trace)
+            fprintf(stderr,
+                    "cupk   round sets=%zu left_out=%u vmembers=%zu fmembers=%zu prep=%.3f "
+                    "gpu=%.3f ms\n",
+                    sets.size(), groups[skip].size, vmem.size(), fmem.size(), tr1 - tr0,
+                    tr2 - tr1);
+        const int32_t *res = ctx->h_res.p;
+        const size_t k = sets.size();
+        std::vector<size_t> ord(k);
+        for (size_t i = 0; i < k; i++) ord[i] = i;
+        std::sort(ord.begin(), ord.end(),
+                  [&](size_t a, size_t b) { return sets[a].minv < sets[b].minv; });
+        bool linked = false, failed = false;
+        for (size_t i : ord) {
+            if (res[3 * i] != CUPK_OK) continue;
+            const uint32_t x = (uint32_t)res[3 * i + 1], y = (uint32_t)res[3 * i + 2];
+            if (!F.same_tree(x, y)) {
+                F.link(x, y);
+                ctx->ctr.links++;
+                linked = true;
+            }
+        }
+        for (size_t i = 0; i < k; i++) {
+            const int st = res[3 * i];
+            if (st == CUPK_EMPTY) {
+                // a whole component: clean, unless it was merged this round
+                const uint32_t l = F.label(sets[i].minv);
+                if (l == sets[i].label && F.tree_size(l) == sets[i].size) F.clear_dirty(l);
+            } else if (st == CUPK_SAMPLE_FAILED) {
+                ctx->ctr.sample_failed++;
+                failed = true;
+            }
+        }
+        if (!linked) {
+            if (!failed) F.clear_dirty(skip_label);
+            break;
+        }
+        linked_any = true;
         slot = 1 - slot;
         tr0 = now_ms();
     }
-    ctx->forest_dev_stale = true;
+    if (linked_any) ctx->forest_dev_stale = true;
     return CUPK_OK;
 }
 

@@ -376,4 +376,27 @@ def test_forest_replay_is_spanning_forest_at_every_boundary(orc, V, p, df, batch
             ev = np.array([x[1] for x in live], np.uint32)
             truth = orc.components_truth(V, eu, ev)
             orc.check_spanning_forest(V, fr.forest_edges(), live, truth)
+        # with no failed sample every tree is known to be a whole component
+        # at the end of a batch, including the one the rounds left out
+        assert not fr.mark
     assert fr.n_failed == 0
+
+
+def test_rounds_leave_out_the_largest_dirty_tree(orc):
+    """Cutting a path splits it into sides of 3 and 5 vertices; the only
+    edge between them is an insert of this batch (same batch-start tree, so
+    not linked directly).  One round samples only the smaller side, whose
+    single cut edge is always recovered; the larger side is never reduced and
+    ends clean with the rest."""
+    V = 8
+    sk = orc.Sketch(V, 3, 6, 0x5EED)
+    fr = orc.ForestReplay(sk)
+    path = np.arange(V - 1, dtype=np.uint32)
+    fr.apply_batch(path, path + 1, np.zeros(V - 1, np.uint8))
+    assert fr.n_rounds == 0 and not fr.mark
+    fr.apply_batch(np.array([2, 0], np.uint32), np.array([3, 7], np.uint32),
+                   np.array([1, 0], np.uint8))
+    assert fr.n_cuts == 1 and fr.n_rounds == 1
+    assert fr.round_log[-1] == [(0, orc.OK, 0, 7)]
+    assert (0, 7) in fr.forest_edges() and (2, 3) not in fr.forest_edges()
+    assert not fr.mark
