@@ -3,16 +3,17 @@
 // The paper answers connectivity queries from a sketchless dynamic tree on
 // the top level (Sec. 4.1) and links / cuts forest edges as updates demand
 // (cutset Link / Cut, Sec. 2.2.1).  Here the forest is a rooted forest:
-// parent pointers, child lists (each child knows its slot in its parent's
-// list, so an edge is removed in O(1)), and one label per vertex naming its
-// tree:
-//   - link(a, b): the smaller tree is re-rooted at its endpoint, hung below
-//     the other endpoint and relabelled (work proportional to the smaller
-//     tree);
-//   - cut(a, b): the edge is removed and the two sides are explored by
-//     breadth-first searches interleaved edge by edge, so the work is
-//     proportional to the smaller side (even next to a high-degree
-//     vertex); the smaller side gets a fresh label.
+// parent pointers, doubly linked child lists (an edge is removed in O(1)),
+// and one label per vertex naming its tree:
+//   - link(a, b): the smaller tree is relabelled, re-rooted at its endpoint
+//     (parent pointers reversed along one path) and hung below the other
+//     endpoint (work proportional to the smaller tree);
+//   - cut(a, b): the edge is removed and the two sides are searched
+//     top-down (from the old root and from the child endpoint), interleaved
+//     edge by edge, so the work is proportional to the smaller side (even
+//     next to a high-degree vertex); the smaller side gets a fresh label.
+//     A run of cuts can remove all its edges first and split each tree once
+//     into all its pieces (remove_edge / split_pending).
 // Labels come from a free list in [0, V), so label arrays are V words and
 // the device can classify updates against them (lbl[u] != lbl[v] means u
 // and v are in different trees; par[] identifies forest edges).
@@ -36,12 +37,9 @@ class Forest {
         V_ = V;
         lbl_ = lbl;
         par_ = par;
-        kids_.assign(V, {});
-        // most tree vertices have a few children: reserving them keeps
-        // relinking free of small reallocations
-        for (auto &k : kids_) k.reserve(2);
-        kid_pos_.assign(V, 0);
-        bfs_par_.assign(V, kNone);
+        first_kid_.assign(V, kNone);
+        next_sib_.assign(V, kNone);
+        prev_sib_.assign(V, kNone);
         size_.assign(V, 1);
         root_.resize(V);
         dirty_.assign(V, 0);
@@ -51,8 +49,6 @@ class Forest {
             par_[w] = kNone;
             root_[w] = w;
         }
-        stamp_.assign(V, 0);
-        epoch_ = 0;
         n_trees_ = V;
         n_edges_ = 0;
         dirty_list_.clear();
@@ -100,38 +96,27 @@ class Forest {
             std::swap(a, b);
             std::swap(la, lb);
         }
-        // re-root a's (smaller) tree at a: breadth-first search over its
-        // undirected tree edges, remembering each vertex's search parent
-        const uint32_t ep = next_epoch();
+        // relabel a's (smaller) tree, top-down from its root
         queue_.clear();
-        queue_.push_back(a);
-        stamp_[a] = ep;
-        bfs_par_[a] = kNone;
+        queue_.push_back(root_[la]);
         for (size_t qi = 0; qi < queue_.size(); qi++) {
             const uint32_t x = queue_[qi];
-            const uint32_t px = par_[x];
-            if (px != kNone && stamp_[px] != ep) {
-                stamp_[px] = ep;
-                bfs_par_[px] = x;
-                queue_.push_back(px);
-            }
-            for (uint32_t y : kids_[x]) {
-                if (stamp_[y] == ep) continue;
-                stamp_[y] = ep;
-                bfs_par_[y] = x;
-                queue_.push_back(y);
-            }
-        }
-        // rebuild parent pointers and child lists from the search tree, hang
-        // a below b and relabel
-        for (uint32_t x : queue_) kids_[x].clear();
-        for (uint32_t x : queue_) {
             lbl_[x] = lb;
-            const uint32_t p = bfs_par_[x];
-            if (p == kNone) continue;
-            par_[x] = p;
-            add_kid(p, x);
+            for (uint32_t y = first_kid_[x]; y != kNone; y = next_sib_[y]) queue_.push_back(y);
         }
+        // re-root it at a: reverse the parent pointers on the path from a up
+        // to the old root
+        for (uint32_t x = a, below = kNone; x != kNone;) {
+            const uint32_t up = par_[x];
+            if (up != kNone) remove_kid(up, x);
+            if (below != kNone) {
+                par_[x] = below;
+                add_kid(below, x);
+            }
+            below = x;
+            x = up;
+        }
+        // hang it below b
         par_[a] = b;
         add_kid(b, a);
         size_[lb] += size_[la];
@@ -146,57 +131,84 @@ class Forest {
     // Cut forest edge {a, b}.  Returns (label of a's side, label of b's side).
     std::pair<uint32_t, uint32_t> cut(uint32_t a, uint32_t b)
     {
-        const uint32_t old = lbl_[a];
-        // the child endpoint becomes the root of its side
+        remove_edge(a, b);
+        split_pending();
+        return {lbl_[a], lbl_[b]};
+    }
+
+    // Remove forest edge {a, b} from the structure (parent pointer and
+    // child list) and leave the labels to split_pending().  A run of
+    // removals followed by one split costs about as much as splitting each
+    // tree once into all its pieces.  Until split_pending() runs, labels,
+    // sizes and roots still describe the trees before the removals: only
+    // is_edge() and remove_edge() may be called in between.
+    void remove_edge(uint32_t a, uint32_t b)
+    {
         const uint32_t child = par_[a] == b ? a : b;
         const uint32_t parent = child == a ? b : a;
         remove_kid(parent, child);
         par_[child] = kNone;
-        // breadth-first searches from a and b, interleaved one edge at a
-        // time; the side that finishes first is the smaller one
-        const uint32_t ea = next_epoch();
-        const uint32_t eb = next_epoch();
-        qa_.clear();
-        qb_.clear();
-        qa_.push_back(a);
-        qb_.push_back(b);
-        stamp_[a] = ea;
-        stamp_[b] = eb;
-        Walk wa{0, 0}, wb{0, 0};
-        bool a_small;
-        for (;;) {
-            if (!step(qa_, wa, ea)) {
-                a_small = true;
-                break;
-            }
-            if (!step(qb_, wb, eb)) {
-                a_small = false;
-                break;
-            }
-        }
-        const std::vector<uint32_t> &small = a_small ? qa_ : qb_;
-        const uint32_t nl = free_.back();
-        free_.pop_back();
-        for (uint32_t x : small) lbl_[x] = nl;
-        size_[nl] = (uint32_t)small.size();
-        size_[old] -= (uint32_t)small.size();
-        // roots: the side holding the old root keeps it; the other side is
-        // rooted at the child endpoint
-        const uint32_t small_end = a_small ? a : b;
-        const bool small_has_child = small_end == child;
-        if (small_has_child) {
-            root_[nl] = child;
-        } else {
-            root_[nl] = root_[old];
-            root_[old] = child;
-        }
-        dirty_[nl] = 0;
-        set_dirty(old);
-        set_dirty(nl);
+        pending_.push_back({lbl_[child], child});
         n_trees_++;
         n_edges_--;
-        const uint32_t la = lbl_[a], lb2 = lbl_[b];
-        return {la, lb2};
+    }
+    bool has_pending() const { return !pending_.empty(); }
+
+    // Relabel the trees split by remove_edge().  Every piece of a split tree
+    // is the subtree below its top vertex (the old root, or the child
+    // endpoint of a removed edge), so the pieces are searched top-down,
+    // interleaved one tree edge at a time; all but the last piece to finish
+    // get fresh labels, and the work is about twice the size of the pieces
+    // that finish.  Every piece is dirty.
+    void split_pending()
+    {
+        if (pending_.empty()) return;
+        std::sort(pending_.begin(), pending_.end());
+        for (size_t g0 = 0; g0 < pending_.size();) {
+            const uint32_t old = pending_[g0].first;
+            size_t g1 = g0;
+            while (g1 < pending_.size() && pending_[g1].first == old) g1++;
+            const size_t k = g1 - g0 + 1;  // pieces: the old root's, then one per removal
+            if (pq_.size() < k) pq_.resize(k);
+            pw_.assign(k, Walk{0, kNone});
+            active_.clear();
+            for (size_t i = 0; i < k; i++) {
+                pq_[i].clear();
+                pq_[i].push_back(i == 0 ? root_[old] : pending_[g0 + i - 1].second);
+                active_.push_back((uint32_t)i);
+            }
+            uint32_t moved = 0;
+            while (active_.size() > 1) {
+                for (size_t j = 0; j < active_.size();) {
+                    const uint32_t i = active_[j];
+                    // a few edges per turn keep the switching cost low
+                    bool more = true;
+                    for (int t = 0; t < 16 && more; t++) more = step_down(pq_[i], pw_[i]);
+                    if (more) {
+                        j++;
+                        continue;
+                    }
+                    // piece i is complete: it takes a fresh label
+                    const uint32_t nl = free_.back();
+                    free_.pop_back();
+                    for (uint32_t x : pq_[i]) lbl_[x] = nl;
+                    size_[nl] = (uint32_t)pq_[i].size();
+                    root_[nl] = pq_[i][0];
+                    dirty_[nl] = 0;
+                    set_dirty(nl);
+                    moved += (uint32_t)pq_[i].size();
+                    active_[j] = active_.back();
+                    active_.pop_back();
+                    if (active_.size() == 1) break;
+                }
+            }
+            // the last piece keeps the old label
+            size_[old] -= moved;
+            root_[old] = pq_[active_[0]][0];
+            set_dirty(old);
+            g0 = g1;
+        }
+        pending_.clear();
     }
 
     // Vertices of the tree with the given label (BFS from its root); also
@@ -204,15 +216,12 @@ class Forest {
     uint32_t collect(uint32_t label, std::vector<uint32_t> &out)
     {
         const uint32_t r = root_[label];
-        const uint32_t ep = next_epoch();
         const size_t start = out.size();
         out.push_back(r);
-        stamp_[r] = ep;
         uint32_t mn = r;
-        (void)ep;
         for (size_t qi = start; qi < out.size(); qi++) {
             const uint32_t x = out[qi];
-            for (uint32_t y : kids_[x]) {
+            for (uint32_t y = first_kid_[x]; y != kNone; y = next_sib_[y]) {
                 out.push_back(y);
                 mn = std::min(mn, y);
             }
@@ -230,80 +239,65 @@ class Forest {
     }
 
   private:
-    uint32_t next_epoch()
-    {
-        if (++epoch_ == 0) {
-            std::fill(stamp_.begin(), stamp_.end(), 0u);
-            epoch_ = 1;
-        }
-        return epoch_;
-    }
-    // position of an interleaved search: queue index, and the next
-    // neighbour of that vertex to look at (0 = its parent, 1+k = child k)
+    // position of a top-down piece search: queue index, and the next child
+    // of that vertex to look at (kNone: start at its first child)
     struct Walk {
         size_t qi;
-        size_t ni;
+        uint32_t next;
     };
-    // Advance a search by one tree edge.  Returns false when the search has
-    // no vertex left to expand (its side is complete).
-    bool step(std::vector<uint32_t> &q, Walk &w, uint32_t ep)
+    // Advance a top-down search of one piece by one tree edge.  Returns
+    // false when the piece is complete.
+    bool step_down(std::vector<uint32_t> &q, Walk &w)
     {
         for (;;) {
             if (w.qi == q.size()) return false;
-            const uint32_t x = q[w.qi];
-            const auto &k = kids_[x];
-            if (w.ni == 0) {
-                w.ni = 1;
-                const uint32_t p = par_[x];
-                if (p != kNone && stamp_[p] != ep) {
-                    stamp_[p] = ep;
-                    q.push_back(p);
-                    return true;
-                }
-                continue;
-            }
-            if (w.ni - 1 < k.size()) {
-                const uint32_t y = k[w.ni - 1];
-                w.ni++;
-                if (stamp_[y] != ep) {
-                    stamp_[y] = ep;
-                    q.push_back(y);
+            const uint32_t y = w.next == kNone ? first_kid_[q[w.qi]] : w.next;
+            if (y != kNone) {
+                q.push_back(y);
+                w.next = next_sib_[y];
+                if (w.next == kNone) {
+                    w.qi++;
                 }
                 return true;
             }
             w.qi++;
-            w.ni = 0;
+            w.next = kNone;
         }
     }
+    // children of a vertex form a doubly linked list (insert and remove in
+    // O(1), one memory access per child when walking it)
     void add_kid(uint32_t p, uint32_t c)
     {
-        kid_pos_[c] = (uint32_t)kids_[p].size();
-        kids_[p].push_back(c);
+        const uint32_t f = first_kid_[p];
+        next_sib_[c] = f;
+        prev_sib_[c] = kNone;
+        if (f != kNone) prev_sib_[f] = c;
+        first_kid_[p] = c;
     }
     void remove_kid(uint32_t p, uint32_t c)
     {
-        auto &k = kids_[p];
-        const uint32_t i = kid_pos_[c];
-        const uint32_t last = k.back();
-        k[i] = last;
-        kid_pos_[last] = i;
-        k.pop_back();
+        const uint32_t pv = prev_sib_[c], nx = next_sib_[c];
+        if (pv == kNone)
+            first_kid_[p] = nx;
+        else
+            next_sib_[pv] = nx;
+        if (nx != kNone) prev_sib_[nx] = pv;
     }
 
     uint32_t V_ = 0;
     uint32_t *lbl_ = nullptr;
     uint32_t *par_ = nullptr;
-    std::vector<std::vector<uint32_t>> kids_;  // children of each vertex
-    std::vector<uint32_t> kid_pos_;            // slot of a vertex in its parent's list
-    std::vector<uint32_t> bfs_par_;            // scratch of link
+    std::vector<uint32_t> first_kid_, next_sib_, prev_sib_;  // child lists
     std::vector<uint32_t> size_;   // by label
     std::vector<uint32_t> root_;   // by label
     std::vector<uint8_t> dirty_;   // by label
     std::vector<uint32_t> dirty_list_;
     std::vector<uint32_t> free_;
-    std::vector<uint32_t> stamp_;
-    std::vector<uint32_t> queue_, qa_, qb_;
-    uint32_t epoch_ = 0;
+    std::vector<uint32_t> queue_;
+    std::vector<std::pair<uint32_t, uint32_t>> pending_;  // (old label, top) per removal
+    std::vector<std::vector<uint32_t>> pq_;              // per-piece search queues
+    std::vector<Walk> pw_;
+    std::vector<uint32_t> active_;
     uint64_t n_trees_ = 0;
     uint64_t n_edges_ = 0;
 };

@@ -108,7 +108,7 @@ int main(int argc, char **argv)
             F.link(a, b);
             N.adj[a].insert(b);
             N.adj[b].insert(a);
-        } else {
+        } else if (mode < 9) {
             std::vector<uint32_t> eu, ev;
             F.edges(eu, ev);
             if (eu.empty()) continue;
@@ -116,6 +116,28 @@ int main(int argc, char **argv)
             F.cut(eu[k], ev[k]);
             N.adj[eu[k]].erase(ev[k]);
             N.adj[ev[k]].erase(eu[k]);
+        } else {
+            // a run of removals, then one split of every tree they broke
+            for (uint32_t l : F.dirty_labels()) F.clear_dirty(l);
+            const std::vector<uint32_t> before = N.comp();
+            std::set<uint32_t> broken;  // components (naive ids) that lost an edge
+            const uint32_t run = 1 + (uint32_t)(rng() % 8);
+            for (uint32_t r = 0; r < run; r++) {
+                std::vector<uint32_t> eu, ev;
+                F.edges(eu, ev);
+                if (eu.empty()) break;
+                const size_t k = rng() % eu.size();
+                if (!F.is_edge(eu[k], ev[k])) return fail("is_edge during a run", s);
+                F.remove_edge(eu[k], ev[k]);
+                broken.insert(before[eu[k]]);
+                N.adj[eu[k]].erase(ev[k]);
+                N.adj[ev[k]].erase(eu[k]);
+            }
+            F.split_pending();
+            // exactly the pieces of the broken trees are dirty
+            for (uint32_t w = 0; w < V; w++)
+                if (F.is_dirty(F.label(w)) != (broken.count(before[w]) != 0))
+                    return fail("dirty pieces", s);
         }
         if (check(F, N, s)) return 1;
     }
