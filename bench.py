@@ -126,6 +126,33 @@ def cpu_baseline(u, v, d, sizes, budget_s=15.0):
                       f"stream: plain C sketch update + Python forest replay, one thread"}
 
 
+def static_leg(cupk, torch, packed, sizes, reps=5):
+    """Components of the final graph from the sketches alone (Boruvka over
+    supernodes, App. A.1.1) on the resident sketch after the whole stream;
+    the stream itself is applied untimed.  Reports the time per run and the
+    vertex-slab rate of its first two rounds (every vertex slab is read once
+    by the in-place samples of round 1 and once by round 2's reduction)
+    against the HBM bound for those slabs."""
+    ctx = cupk.Context(V, C, D, SEED, max_batch=BATCH)
+    off = 0
+    for s in sizes:
+        ctx.apply_updates_device(packed[off:off + s])
+        off += s
+    ctx.sync()
+    ctx.static_components()  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, _, info = ctx.static_components()
+    dt = (time.perf_counter() - t0) / reps
+    ctx.close()
+    slab = C * D * 16
+    return {"ms": round(dt * 1e3, 4), "rounds": info["rounds"],
+            "components": info["n_components"], "sample_failed": info["sample_failed"],
+            "vertex_slabs_per_s": round(2 * V / dt, 1),
+            "hbm_bound_ms": round(2 * V * slab / (HBM_PEAK_GBS * 1e9) * 1e3, 5)}
+
+
 def served_leg(cupk, u, v, d, rho=100_000, inflight=4, max_batch=BATCH):
     """The same stream through the serving loop: update requests of `rho`
     updates, each followed by a Connected query on a random pair, pushed as
@@ -184,8 +211,8 @@ def workload_leg(args, cupk, torch, np, streamgen):
     name = args.workload
     out = {"metric": "edge updates/sec", "unit": "updates/s", "n_gpus": 1, "data": "synthetic",
            "dtype": "u64"}
-    if name in ("rmat17", "clusters"):
-        i = 2 if name == "rmat17" else 4
+    if name in ("rmat17", "clusters", "fixed_forest"):
+        i = {"rmat17": 2, "clusters": 4, "fixed_forest": 5}[name]
         cfg = streamgen.CONFIGS[i]
         print(f"bench: generating {cfg['name']}", file=sys.stderr, flush=True)
         Vw = cfg["V"]
@@ -231,12 +258,61 @@ def workload_leg(args, cupk, torch, np, streamgen):
                           "scatter_ms": round(ctr["scatter_ms"], 3),
                           "bin_ms": round(ctr["bin_ms"], 3), "links": ctr["links"],
                           "cuts": ctr["cuts"], "rounds": ctr["rounds"],
-                          "sample_failed": ctr["sample_failed"]}
+                          "sample_failed": ctr["sample_failed"],
+                          # updates that changed the forest (the single-level
+                          # analogue of the paper's isolated updates)
+                          "structural_rate": round((ctr["links"] + ctr["cuts"]) / n, 7)}
             if tr:
                 res[label]["tune"] = {k: tr[k] for k in ("tile_vertices", "lds_rows",
                                                          "chunk_records", "batch_target")}
         out.update({"workload": cfg["name"], "updates": n, "batches": len(sizes), "V": Vw,
                     "C": Cw, "D": Dw, "results": res})
+    elif name == "exact_sweep":
+        # throughput against batch (buffer) size with per-update semantics
+        # (exact mode) and with batch semantics, over a window of 1,000,000
+        # updates: the first deletions of the benchmark stream (standard
+        # stream: many forest-edge deletions) and the first deletions of the
+        # fixed-forest stream (no forest-edge deletion)
+        windows = []
+        for i, label in ((1, "standard"), (5, "fixed_forest")):
+            cfg = streamgen.CONFIGS[i]
+            print(f"bench: generating {cfg['name']}", file=sys.stderr, flush=True)
+            u, v, d = streamgen.config_stream(i)
+            start = int(np.argmax(d))          # first deletion
+            win = 1_000_000
+            packed = torch.from_numpy(cupk.pack_updates(u[:start + win], v[:start + win],
+                                                        d[:start + win]).view(np.int64)).cuda()
+            windows.append((label, cfg, packed, start, win))
+            del u, v, d
+        res = {}
+        for label, cfg, packed, start, win in windows:
+            Vw = cfg["V"]
+            Cw = streamgen.ceil_log2(Vw)
+            for exact in (True, False):
+                for bsz in (100, 1000, 10_000, 100_000, 1_000_000):
+                    ctx = cupk.Context(Vw, Cw, 2 * Cw, cfg["S"], max_batch=1_000_000,
+                                       exact=exact)
+                    for off in range(0, start, 1_000_000):
+                        ctx.apply_updates_device(packed[off:min(start, off + 1_000_000)])
+                    ctx.sync()
+                    c0 = ctx.counters()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for off in range(start, start + win, bsz):
+                        ctx.apply_updates_device(packed[off:min(start + win, off + bsz)])
+                    ctx.sync()
+                    dt = time.perf_counter() - t0
+                    c1 = ctx.counters()
+                    ctx.close()
+                    key = f"{label}/{'exact' if exact else 'batch'}/{bsz}"
+                    res[key] = {"value": round(win / dt, 1), "seconds": round(dt, 4),
+                                "cuts": c1["cuts"] - c0["cuts"],
+                                "reverts": c1["reverts"] - c0["reverts"],
+                                "rounds": c1["rounds"] - c0["rounds"]}
+                    print(f"bench: {key} {res[key]}", file=sys.stderr, flush=True)
+        out.update({"workload": "exact-mode buffer sweep: 1,000,000-update windows at the "
+                                "first deletion of er16384_p0.3_del10 and "
+                                "er16384_p0.3_fixedforest", "results": res})
     elif name == "er65536_served":
         cfg = streamgen.CONFIGS[3]
         Vw = cfg["V"]
@@ -302,11 +378,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel run")
     ap.add_argument("--no-serve", action="store_true", help="skip the served run")
+    ap.add_argument("--no-static", action="store_true",
+                    help="skip the static-components run on the final sketch")
     ap.add_argument("--mode", default="staged", choices=["staged", "atomic"])
     ap.add_argument("--graph", type=int, default=0,
                     help="1: replay each batch's device work as captured HIP graphs")
     ap.add_argument("--workload", default="er16384",
-                    choices=["er16384", "rmat17", "er65536_served", "clusters"],
+                    choices=["er16384", "rmat17", "er65536_served", "clusters", "fixed_forest",
+                             "exact_sweep"],
                     help="er16384: the benchmark line; the others print extra full-size "
                          "measurements of the other workload recipes")
     ap.add_argument("--calib", action="store_true",
@@ -383,6 +462,9 @@ def main():
                         "ms_per_step": round(pdt * 1e3 / args.steps, 4),
                         "kernel": "k_scatter_atomic", "kernel_avg_ms": round(pavg, 5),
                         "achieved_GBs": round(pach, 1), "frac": round(pach / HBM_PEAK_GBS, 4)}
+    if not args.no_static:
+        print("bench: timing static components", file=sys.stderr, flush=True)
+        out["static_components"] = static_leg(cupk, torch, packed, sizes)
     if not args.no_serve:
         print("bench: timing served path", file=sys.stderr, flush=True)
         out["served"] = served_leg(cupk, u, v, d)

@@ -103,6 +103,18 @@ typedef struct {
      * batch capacity; the kernels read the batch size from device memory,
      * so one capture serves batches of any size up to the capacity. */
     uint32_t use_graph;
+    /* Nonzero: per-update semantics inside every batch (speculative update
+     * buffering, Sec. 4.3).  A batch is classified and scattered as a
+     * whole; at the first update that cuts a forest edge, the scatter of
+     * the updates after it is undone (applied again: XOR toggles back), the
+     * cut and its replacement rounds run on the sketch as of that update,
+     * and the rest of the batch is processed again the same way.  The
+     * forest then equals the one obtained by applying the updates one at a
+     * time (batches of one), whatever the batch size, as long as no
+     * replacement query fails (a failed tree is retried at the next cut or
+     * batch end rather than after every update).  Captured graphs
+     * (use_graph) are not used in this mode. */
+    uint32_t exact;
 } cupk_opts;
 
 /* Counters, cumulative since init. */
@@ -122,6 +134,8 @@ typedef struct {
     double host_wait_ms;         /* host time waiting for classification results */
     double host_flags_ms;        /* host time applying flagged updates to forest */
     double host_rounds_ms;       /* host time in replacement rounds (incl. GPU)  */
+    uint64_t reverts;            /* exact mode: batch tails scattered again to
+                                    undo speculation past a cut                 */
 } cupk_counters_t;
 
 /* Bytes of device memory the sketch of (V, C, D) occupies. */
@@ -229,6 +243,35 @@ int cupk_counters(cupk_ctx *ctx, cupk_counters_t *out);
 
 /* Wait for all work the context queued. */
 int cupk_sync(cupk_ctx *ctx);
+
+/* ---- static connectivity from the sketch -----------------------------------
+ * Connected components of the current graph computed from the vertex
+ * sketches alone, ignoring the maintained forest: Boruvka's algorithm over
+ * supernodes, where a supernode's incident edge is recovered by querying the
+ * XOR of its members' sketches and merging supernodes merges their sketches
+ * (App. A.1.1, the AGM connectivity sketch).  Rounds take the active
+ * supernodes in ascending order of smallest vertex; each sampled edge merges
+ * the two supernodes unless they are already one (recorded as a spanning
+ * forest edge); an EMPTY supernode not merged in the round is a whole
+ * component; a round that merges nothing ends the run (supernodes whose
+ * query failed then stay as they are, counted in sample_failed).
+ * labels: NULL or V host words, set to the smallest vertex of each vertex's
+ *   component.
+ * eu, ev: NULL or V-1 host words each; the merge edges (eu < ev) in merge
+ *   order; info->n_edges of them are written.
+ * info: NULL or filled with the counts below.
+ * Reflects every update applied so far; the forest is not touched.  Uses
+ * device scratch of up to V/2 set sketches.
+ * Errors: CUPK_EINVAL (serving loop running), CUPK_ENOMEM, CUPK_EDEVICE. */
+typedef struct {
+    uint32_t n_components;
+    uint32_t rounds;
+    uint32_t sample_failed;
+    uint32_t n_edges;
+} cupk_static_info;
+
+int cupk_static_components(cupk_ctx *ctx, uint32_t *labels, uint32_t *eu, uint32_t *ev,
+                           cupk_static_info *info);
 
 /* ---- autotuner ------------------------------------------------------------
  * Picks the staged scatter's tile geometry (vertices per LDS tile, depth

@@ -188,9 +188,11 @@ def digest_arrays(C, D, S, w0, alpha, gamma) -> int:
 
 
 from .forest import ForestReplay, components_truth, check_spanning_forest  # noqa: E402
+from .static_cc import static_components  # noqa: E402
 
 __all__ = [
     "OK", "EMPTY", "FAILED", "build", "lib", "mix", "seed", "hash_c",
     "depth_of_hash", "edge_index", "Sketch", "sample", "vertex_from_stream",
     "digest_arrays", "ForestReplay", "components_truth", "check_spanning_forest",
+    "static_components",
 ]

@@ -52,6 +52,7 @@ class cupk_opts(ctypes.Structure):
         ("chunk_records", ctypes.c_uint32),
         ("tile_grid", ctypes.c_uint32),
         ("use_graph", ctypes.c_uint32),
+        ("exact", ctypes.c_uint32),
     ]
 
 
@@ -61,7 +62,7 @@ class cupk_counters_t(ctypes.Structure):
         "slabs_reduced", "sample_failed", "scatter_launches")] + [
         ("scatter_ms", ctypes.c_double), ("bin_ms", ctypes.c_double),
         ("host_wait_ms", ctypes.c_double), ("host_flags_ms", ctypes.c_double),
-        ("host_rounds_ms", ctypes.c_double)]
+        ("host_rounds_ms", ctypes.c_double), ("reverts", ctypes.c_uint64)]
 
 
 class cupk_serve_opts(ctypes.Structure):
@@ -81,6 +82,11 @@ class cupk_tune_result(ctypes.Structure):
                 ("best_ms", ctypes.c_double), ("before_ms", ctypes.c_double),
                 ("batch_target", ctypes.c_uint32), ("batch_ms", ctypes.c_double * 8),
                 ("batch_sizes", ctypes.c_uint32 * 8)]
+
+
+class cupk_static_info(ctypes.Structure):
+    _fields_ = [("n_components", ctypes.c_uint32), ("rounds", ctypes.c_uint32),
+                ("sample_failed", ctypes.c_uint32), ("n_edges", ctypes.c_uint32)]
 
 
 def _load():
@@ -107,6 +113,7 @@ def _load():
         "cupk_counters": (ctypes.c_int, [p, ctypes.POINTER(cupk_counters_t)]),
         "cupk_sync": (ctypes.c_int, [p]),
         "cupk_autotune": (ctypes.c_int, [p, p, sz, ctypes.POINTER(cupk_tune_result)]),
+        "cupk_static_components": (ctypes.c_int, [p, p, p, p, ctypes.POINTER(cupk_static_info)]),
         "cupk_serve_start": (ctypes.c_int, [p, ctypes.POINTER(cupk_serve_opts)]),
         "cupk_submit_updates": (ctypes.c_int, [p, p, p, p, sz, ctypes.POINTER(u64)]),
         "cupk_submit_query": (ctypes.c_int, [p, u32, u32, ctypes.POINTER(u64)]),
@@ -158,7 +165,7 @@ class Context:
 
     def __init__(self, V, C=0, D=0, seed=0, scatter_mode=SCATTER_STAGED, max_batch=0,
                  stream=None, use_torch_memory=True, time_kernels=False, tile_vertices=0,
-                 lds_rows=0, chunk_records=0, tile_grid=0, use_graph=False):
+                 lds_rows=0, chunk_records=0, tile_grid=0, use_graph=False, exact=False):
         self._h = None
         self._sk_tensor = None
         opts = cupk_opts()
@@ -170,6 +177,7 @@ class Context:
         opts.chunk_records = chunk_records
         opts.tile_grid = tile_grid
         opts.use_graph = 1 if use_graph else 0
+        opts.exact = 1 if exact else 0
         torch = _torch()
         if stream is None and torch is not None and torch.cuda.is_available():
             # launch on torch's current stream so that torch-produced device
@@ -311,6 +319,20 @@ class Context:
         out = np.zeros(self.V, np.uint32)
         self._check(lib.cupk_component_labels(self._h, _ptr(out)))
         return out
+
+    def static_components(self):
+        """Components from the sketches alone (``cupk_static_components``):
+        (labels = smallest vertex per component, merge edges in merge order,
+        info dict)."""
+        labels = np.zeros(self.V, np.uint32)
+        eu = np.zeros(max(1, self.V - 1), np.uint32)
+        ev = np.zeros(max(1, self.V - 1), np.uint32)
+        info = cupk_static_info()
+        self._check(lib.cupk_static_components(self._h, _ptr(labels), _ptr(eu), _ptr(ev),
+                                               ctypes.byref(info)))
+        n = info.n_edges
+        edges = list(zip(eu[:n].tolist(), ev[:n].tolist()))
+        return labels, edges, {f: getattr(info, f) for f, _ in cupk_static_info._fields_}
 
     def counters(self) -> dict:
         c = cupk_counters_t()

@@ -22,6 +22,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -107,6 +108,8 @@ struct cupk_ctx {
     DevBuf<uint32_t> d_fcnt, d_foff;  // flagged updates: per-block counts and offsets,
     DevBuf<uint64_t> d_fupd, d_oupd;  // per-block regions, the compacted ordered list
     HostBuf<uint64_t> h_fupd;
+    DevBuf<uint32_t> d_fpos, d_opos;  // positions of flagged updates (exact mode)
+    HostBuf<uint32_t> h_fpos;
 
     // staged scatter
     uint32_t tile_shift = 5, rows = 8, chunk = 4096, ntiles = 0, tile_grid = 0;
@@ -134,6 +137,7 @@ struct cupk_ctx {
     int device = 0;
     bool trace = false;  // CUPK_TRACE=1: per-batch host timings on stderr
     std::unique_ptr<Server> server;
+    std::vector<int32_t> round_gmap;  // label -> round group, -1 elsewhere
     Forest forest;
     cupk_counters_t ctr = {};
     std::string err;
@@ -157,6 +161,25 @@ struct cupk_ctx {
         hipError_t e_ = (x);                                        \
         if (e_ != hipSuccess) return ctx->fail(e_, #x, __LINE__);   \
     } while (0)
+
+// No C++ exception crosses the C ABI: a failed host allocation inside an
+// entry point becomes CUPK_ENOMEM with a message.
+template <class F>
+int guarded(cupk_ctx *ctx, F &&f)
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host memory allocation failed";
+        return CUPK_ENOMEM;
+    } catch (const std::length_error &) {
+        ctx->err = "host allocation too large";
+        return CUPK_ENOMEM;
+    } catch (const std::exception &e) {
+        ctx->err = e.what();
+        return CUPK_EDEVICE;
+    }
+}
 
 namespace {
 
@@ -336,6 +359,7 @@ int reduce_and_sample(cupk_ctx *ctx, int slot, const std::vector<uint32_t> &vmem
 int run_rounds(cupk_ctx *ctx)
 {
     Forest &F = ctx->forest;
+    F.split_pending();
     std::vector<RoundSet> sets;  // sets of the previous round, in d_sig order
     std::vector<uint32_t> vmem, voff, fmem, foff;
     struct Group {
@@ -393,9 +417,34 @@ int run_rounds(cupk_ctx *ctx)
                 }
             if (groups[gi].minv < groups[skip].minv) skip = gi;
         }
+        // members of the trees reduced from their vertices: one pass over
+        // the labels when these trees hold a large share of all vertices
+        // (members then come in ascending order), else a search of each
+        size_t need = 0;
         for (size_t gi = 0; gi < groups.size(); gi++)
-            if (gi != skip && !groups[gi].from_frags && lists[gi].empty())
-                groups[gi].minv = F.collect(groups[gi].label, lists[gi]);
+            if (gi != skip && !groups[gi].from_frags && lists[gi].empty()) need += groups[gi].size;
+        if (need * 4 >= F.V()) {
+            std::vector<int32_t> &gmap = ctx->round_gmap;
+            if (gmap.size() != F.V()) gmap.assign(F.V(), -1);
+            for (size_t gi = 0; gi < groups.size(); gi++)
+                if (gi != skip && !groups[gi].from_frags && lists[gi].empty()) {
+                    gmap[groups[gi].label] = (int32_t)gi;
+                    lists[gi].reserve(groups[gi].size);
+                }
+            for (uint32_t w = 0; w < F.V(); w++) {
+                const int32_t g = gmap[F.label(w)];
+                if (g >= 0) lists[g].push_back(w);
+            }
+            for (size_t gi = 0; gi < groups.size(); gi++)
+                if (gmap[groups[gi].label] >= 0) {
+                    gmap[groups[gi].label] = -1;
+                    groups[gi].minv = lists[gi][0];
+                }
+        } else {
+            for (size_t gi = 0; gi < groups.size(); gi++)
+                if (gi != skip && !groups[gi].from_frags && lists[gi].empty())
+                    groups[gi].minv = F.collect(groups[gi].label, lists[gi]);
+        }
         std::vector<size_t> gord;
         gord.reserve(groups.size());
         for (size_t gi = 0; gi < groups.size(); gi++)
@@ -497,13 +546,17 @@ bool apply_flags(cupk_ctx *ctx, uint32_t k0, uint32_t k1, bool all_inserts)
         const bool del = (p >> 63) != 0;
         if (a > b) std::swap(a, b);
         if (!del) {
+            // labels are exact again before an insert looks at them
+            if (F.has_pending()) F.split_pending();
             if (!F.same_tree(a, b)) {
                 F.link(a, b);
                 ctx->ctr.links++;
                 ctx->forest_dev_stale = true;
             }
         } else if (F.is_edge(a, b)) {
-            F.cut(a, b);
+            // a run of cuts removes its edges now and splits the trees once
+            // (before the next insert or the rounds)
+            F.remove_edge(a, b);
             ctx->ctr.cuts++;
             ctx->forest_dev_stale = true;
         }
@@ -524,6 +577,11 @@ int ensure_batch_buffers(cupk_ctx *ctx, size_t n)
     HIPCHK(grow(ctx->d_foff, nb + 1));
     HIPCHK(grow(ctx->d_oupd, cap));
     HIPCHK(grow(ctx->h_fupd, cap));
+    if (ctx->opts.exact) {
+        HIPCHK(grow(ctx->d_fpos, nb * 4096));
+        HIPCHK(grow(ctx->d_opos, cap));
+        HIPCHK(grow(ctx->h_fpos, cap));
+    }
     if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
         HIPCHK(grow(ctx->d_bins, 2 * cap));
         const size_t icap = 2 * cap / ctx->chunk + ctx->ntiles + 1;
@@ -562,8 +620,9 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n, bool copy_he
     const bool staged = ctx->opts.scatter_mode == CUPK_SCATTER_STAGED;
     HIPCHK(launch_zero32(s, ctx->d_hdr, HDR_WORDS));
     HIPCHK(launch_classify(s, ctx->d_desc, grid_n, ctx->V, ctx->d_lbl, ctx->d_par, ctx->d_hdr,
-                           ctx->d_fupd.p, ctx->d_fcnt.p, staged ? ctx->d_tcnt.p : nullptr,
-                           ctx->tile_shift, ctx->ntiles));
+                           ctx->d_fupd.p, ctx->opts.exact ? ctx->d_fpos.p : nullptr,
+                           ctx->d_fcnt.p, staged ? ctx->d_tcnt.p : nullptr, ctx->tile_shift,
+                           ctx->ntiles));
     if (copy_header)
         HIPCHK(hipMemcpyAsync(ctx->h_hdr, ctx->d_hdr, HDR_WORDS * 4, hipMemcpyDeviceToHost, s));
     return CUPK_OK;
@@ -618,21 +677,27 @@ int capture_graphs(cupk_ctx *ctx)
     return CUPK_OK;
 }
 
-int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
+// Device work of one pass over the updates [0, n) at d_upd: forest upload,
+// batch descriptor, classification (with the header copy) and scatter.  A
+// revert pass applies updates again to undo a speculative scatter (XOR
+// toggles back); it leaves the forest mirror alone and its flags are not
+// read.
+int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
 {
     int rc = harvest_timers(ctx, false);
     if (rc != CUPK_OK) return rc;
-    rc = ensure_batch_buffers(ctx, n);
-    if (rc != CUPK_OK) return rc;
-    rc = upload_forest(ctx);
-    if (rc != CUPK_OK) return rc;
-    // the batch descriptor (pinned staging; the previous batch's copy has
-    // completed: every call waits for its classify step)
+    if (!revert) {
+        rc = upload_forest(ctx);
+        if (rc != CUPK_OK) return rc;
+    }
+    // the batch descriptor (pinned staging; the previous pass's copy has
+    // completed: every pass is followed by a wait for its classify step or
+    // for the whole stream)
     ctx->h_desc->upd = d_upd;
     ctx->h_desc->n = n;
     HIPCHK(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
                           ctx->s));
-    const bool graph = ctx->opts.use_graph != 0;
+    const bool graph = ctx->opts.use_graph != 0 && !ctx->opts.exact;
     if (graph && (ctx->graph_cap < n || !ctx->gx_cls)) {
         rc = capture_graphs(ctx);
         if (rc != CUPK_OK) return rc;
@@ -679,52 +744,155 @@ int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
         HIPCHK(hipEventRecord(ts->t1, ctx->s));
         ts->busy = true;
     }
+    ctx->ctr.scatter_launches++;
+    return CUPK_OK;
+}
 
-    // host: flagged updates -> forest, overlapping the scatter
+// Walk flagged updates [k0, k1) of an exact-mode pass: inserts link as
+// usual; the walk stops before the first delete of a current forest edge
+// and returns its index in *kc.  Returns 0 (list done), 1 (stop: insert-only
+// list and one tree left) or 2 (a cut at *kc).
+int walk_exact(cupk_ctx *ctx, uint32_t k0, uint32_t k1, bool all_inserts, uint32_t *kc)
+{
+    Forest &F = ctx->forest;
+    const uint64_t *upd = ctx->h_fupd.p;
+    for (uint32_t k = k0; k < k1; k++) {
+        if (all_inserts && F.n_trees() == 1) return 1;
+        const uint64_t p = upd[k];
+        uint32_t a = (uint32_t)p, b = (uint32_t)(p >> 32) & 0x7fffffffu;
+        if (a > b) std::swap(a, b);
+        if ((p >> 63) == 0) {
+            if (!F.same_tree(a, b)) {
+                F.link(a, b);
+                ctx->ctr.links++;
+                ctx->forest_dev_stale = true;
+            }
+        } else if (F.is_edge(a, b)) {
+            *kc = k;
+            return 2;
+        }
+    }
+    return 0;
+}
+
+// Host side of a pass: wait for the classification header, pack and fetch
+// the flagged updates in growing chunks and walk them into the forest.
+// exact: stop at the first cut and report its position in the pass and its
+// endpoints (*cut_pos = UINT32_MAX when the pass has no cut).
+int walk_pass(cupk_ctx *ctx, uint32_t n, bool exact, uint32_t *cut_pos, uint32_t *cut_a,
+              uint32_t *cut_b, uint32_t *nflag_out, double *t_wait, double *t_copy)
+{
     double t0 = now_ms();
     HIPCHK(hipEventSynchronize(ctx->ev_hdr));
     double t1 = now_ms();
     ctx->ctr.host_wait_ms += t1 - t0;
+    *t_wait = t1 - t0;
     if (ctx->h_hdr[HDR_ERR]) {
         HIPCHK(hipStreamSynchronize(ctx->s));
         return ctx->invalid("batch holds an update with u == v or an endpoint >= V");
     }
     const uint32_t nflag = ctx->h_hdr[HDR_NFLAG];
     const uint32_t nflag_del = ctx->h_hdr[HDR_NFLAG_DEL];
+    *nflag_out = nflag;
+    if (cut_pos) *cut_pos = UINT32_MAX;
     double tcopy = t1;
     if (nflag) {
         // pack the per-block regions into one ordered list (copy stream,
         // already ordered after the classify kernel), then fetch and walk it
         // in growing chunks: the walk may stop early
-        HIPCHK(launch_flag_compact(ctx->cs, n, ctx->d_fupd.p, ctx->d_fcnt.p, ctx->d_foff.p,
-                                   ctx->d_oupd.p));
+        uint32_t *opos = exact ? ctx->d_opos.p : nullptr;
+        HIPCHK(launch_flag_compact(ctx->cs, n, ctx->d_fupd.p, exact ? ctx->d_fpos.p : nullptr,
+                                   ctx->d_fcnt.p, ctx->d_foff.p, ctx->d_oupd.p, opos));
         uint32_t k0 = 0, step = 1u << 16;
         while (k0 < nflag) {
             const uint32_t m = std::min(step, nflag - k0);
             HIPCHK(hipMemcpyAsync(ctx->h_fupd.p + k0, ctx->d_oupd.p + k0, (size_t)m * 8,
                                   hipMemcpyDeviceToHost, ctx->cs));
+            if (exact)
+                HIPCHK(hipMemcpyAsync(ctx->h_fpos.p + k0, opos + k0, (size_t)m * 4,
+                                      hipMemcpyDeviceToHost, ctx->cs));
             HIPCHK(hipStreamSynchronize(ctx->cs));
             if (k0 == 0) tcopy = now_ms();
-            const bool stop = apply_flags(ctx, k0, k0 + m, nflag_del == 0);
+            if (exact) {
+                uint32_t kc = 0;
+                const int r = walk_exact(ctx, k0, k0 + m, nflag_del == 0, &kc);
+                if (r == 2) {
+                    const uint64_t p = ctx->h_fupd.p[kc];
+                    *cut_pos = ctx->h_fpos.p[kc];
+                    *cut_a = std::min((uint32_t)p, (uint32_t)(p >> 32) & 0x7fffffffu);
+                    *cut_b = std::max((uint32_t)p, (uint32_t)(p >> 32) & 0x7fffffffu);
+                    break;
+                }
+                if (r == 1) break;
+            } else if (apply_flags(ctx, k0, k0 + m, nflag_del == 0)) {
+                break;
+            }
             k0 += m;
             step *= 2;
-            if (stop) break;
         }
     }
-    double t2 = now_ms();
-    ctx->ctr.host_flags_ms += t2 - t1;
+    *t_copy = tcopy - t1;
+    ctx->ctr.host_flags_ms += now_ms() - t1;
     ctx->ctr.flagged += nflag;
+    return CUPK_OK;
+}
+
+int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
+{
+    int rc = ensure_batch_buffers(ctx, n);
+    if (rc != CUPK_OK) return rc;
     ctx->ctr.updates += n;
     ctx->ctr.batches++;
-    ctx->ctr.scatter_launches++;
+    uint32_t nflag = 0;
+    double tw = 0, tc = 0;
+    if (!ctx->opts.exact) {
+        rc = enqueue_pass(ctx, d_upd, n, false);
+        if (rc != CUPK_OK) return rc;
+        const double t0 = now_ms();
+        rc = walk_pass(ctx, n, false, nullptr, nullptr, nullptr, &nflag, &tw, &tc);
+        if (rc != CUPK_OK) return rc;
+        const double t2 = now_ms();
+        rc = run_rounds(ctx);
+        const double t3 = now_ms();
+        ctx->ctr.host_rounds_ms += t3 - t2;
+        if (ctx->trace)
+            fprintf(stderr,
+                    "cupk batch %llu n=%u nflag=%u wait=%.3f copy=%.3f flags=%.3f rounds=%.3f ms\n",
+                    (unsigned long long)ctx->ctr.batches, n, nflag, tw, tc, t2 - t0 - tw - tc,
+                    t3 - t2);
+        return rc;
+    }
+    // exact mode: speculate over the rest of the batch, stop at the first
+    // cut, undo the speculation past it, cut and search replacements on the
+    // sketch as of that update, then go on after it
+    uint32_t s = 0;
+    while (s < n) {
+        rc = enqueue_pass(ctx, d_upd + s, n - s, false);
+        if (rc != CUPK_OK) return rc;
+        uint32_t pos, a = 0, b = 0;
+        rc = walk_pass(ctx, n - s, true, &pos, &a, &b, &nflag, &tw, &tc);
+        if (rc != CUPK_OK) return rc;
+        if (pos == UINT32_MAX) break;
+        const uint32_t next = s + pos + 1;
+        if (next < n) {
+            rc = enqueue_pass(ctx, d_upd + next, n - next, true);
+            if (rc != CUPK_OK) return rc;
+            ctx->ctr.reverts++;
+            // the descriptor staging is written again by the next pass
+            HIPCHK(hipStreamSynchronize(ctx->s));
+        }
+        ctx->forest.cut(a, b);
+        ctx->ctr.cuts++;
+        ctx->forest_dev_stale = true;
+        const double t2 = now_ms();
+        rc = run_rounds(ctx);
+        ctx->ctr.host_rounds_ms += now_ms() - t2;
+        if (rc != CUPK_OK) return rc;
+        s = next;
+    }
+    const double t2 = now_ms();
     rc = run_rounds(ctx);
-    const double t3 = now_ms();
-    ctx->ctr.host_rounds_ms += t3 - t2;
-    if (ctx->trace)
-        fprintf(stderr,
-                "cupk batch %llu n=%u nflag=%u wait=%.3f copy=%.3f flags=%.3f rounds=%.3f ms\n",
-                (unsigned long long)ctx->ctr.batches, n, nflag, t1 - t0, tcopy - t1, t2 - tcopy,
-                t3 - t2);
+    ctx->ctr.host_rounds_ms += now_ms() - t2;
     return rc;
 }
 
@@ -781,6 +949,9 @@ void destroy(cupk_ctx *ctx)
     release(ctx->d_foff);
     release(ctx->d_fcnt);
     release(ctx->h_fupd);
+    release(ctx->d_fpos);
+    release(ctx->d_opos);
+    release(ctx->h_fpos);
     release(ctx->d_tcnt);
     release(ctx->d_toff);
     release(ctx->d_tcur);
@@ -957,7 +1128,7 @@ int cupk_sketch_init(cupk_ctx **out, uint32_t V, uint32_t C, uint32_t D, uint64_
     ctx->C = C;
     ctx->D = D;
     ctx->S = seed;
-    int rc = init_impl(ctx, opts);
+    int rc = guarded(ctx, [&] { return init_impl(ctx, opts); });
     if (rc != CUPK_OK) {
         g_init_error = ctx->err;
         destroy(ctx);
@@ -976,53 +1147,59 @@ int cupk_apply_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
                        const uint8_t *is_delete, size_t n)
 {
     if (!ctx) return CUPK_EINVAL;
-    if (n == 0) return CUPK_OK;
-    if (!u || !v || !is_delete) return ctx->invalid("null array");
-    for (size_t i = 0; i < n; i++)
-        if (u[i] == v[i] || u[i] >= ctx->V || v[i] >= ctx->V)
-            return ctx->invalid("batch holds an update with u == v or an endpoint >= V");
-    HIPCHK(grow(ctx->h_upd, n));
-    HIPCHK(grow(ctx->d_upd, n));
-    // the previous batch's upload from h_upd finished: every call waits for
-    // its classify kernel, which follows the upload on the stream
-    uint64_t *h = ctx->h_upd.p;
-    for (size_t i = 0; i < n; i++)
-        h[i] = (uint64_t)u[i] | ((uint64_t)v[i] << 32) | ((uint64_t)(is_delete[i] != 0) << 63);
-    HIPCHK(hipMemcpyAsync(ctx->d_upd.p, h, n * 8, hipMemcpyHostToDevice, ctx->s));
-    return apply_device(ctx, ctx->d_upd.p, n);
+    return guarded(ctx, [&]() -> int {
+        if (n == 0) return CUPK_OK;
+        if (!u || !v || !is_delete) return ctx->invalid("null array");
+        for (size_t i = 0; i < n; i++)
+            if (u[i] == v[i] || u[i] >= ctx->V || v[i] >= ctx->V)
+                return ctx->invalid("batch holds an update with u == v or an endpoint >= V");
+        HIPCHK(grow(ctx->h_upd, n));
+        HIPCHK(grow(ctx->d_upd, n));
+        // the previous batch's upload from h_upd finished: every call waits for
+        // its classify kernel, which follows the upload on the stream
+        uint64_t *h = ctx->h_upd.p;
+        for (size_t i = 0; i < n; i++)
+            h[i] = (uint64_t)u[i] | ((uint64_t)v[i] << 32) | ((uint64_t)(is_delete[i] != 0) << 63);
+        HIPCHK(hipMemcpyAsync(ctx->d_upd.p, h, n * 8, hipMemcpyHostToDevice, ctx->s));
+        return apply_device(ctx, ctx->d_upd.p, n);
+    });
 }
 
 int cupk_apply_updates_device(cupk_ctx *ctx, const uint64_t *d_packed, size_t n)
 {
     if (!ctx) return CUPK_EINVAL;
-    if (n == 0) return CUPK_OK;
-    if (!d_packed) return ctx->invalid("null device pointer");
-    return apply_device(ctx, d_packed, n);
+    return guarded(ctx, [&]() -> int {
+        if (n == 0) return CUPK_OK;
+        if (!d_packed) return ctx->invalid("null device pointer");
+        return apply_device(ctx, d_packed, n);
+    });
 }
 
 int cupk_component_sketch_batch(cupk_ctx *ctx, const uint64_t *offsets, size_t k,
                                 const uint32_t *verts, cupk_bucket *out)
 {
     if (!ctx) return CUPK_EINVAL;
-    if (k == 0) return CUPK_OK;
-    if (!offsets || !out) return ctx->invalid("null array");
-    if (offsets[0] != 0) return ctx->invalid("offsets[0] must be 0");
-    for (size_t j = 0; j < k; j++)
-        if (offsets[j + 1] < offsets[j]) return ctx->invalid("offsets must be non-decreasing");
-    const size_t nv = offsets[k];
-    if (nv && !verts) return ctx->invalid("null verts");
-    if (nv >= (1ull << 32) || k >= (1ull << 31)) return ctx->invalid("too many members");
-    for (size_t i = 0; i < nv; i++)
-        if (verts[i] >= ctx->V) return ctx->invalid("vertex id >= V");
-    std::vector<uint32_t> vmem(verts, verts + nv), voff(k + 1), none;
-    for (size_t j = 0; j <= k; j++) voff[j] = (uint32_t)offsets[j];
-    int rc = reduce_and_sample(ctx, 0, vmem, voff, none, none);
-    if (rc != CUPK_OK) return rc;
-    HIPCHK(grow(ctx->d_tmp, (size_t)k * ctx->W));
-    HIPCHK(launch_to_canonical(ctx->s, ctx->d_sig[0].p, ctx->C, ctx->D, k, ctx->d_tmp.p));
-    HIPCHK(hipMemcpyAsync(out, ctx->d_tmp.p, (size_t)k * ctx->W * 8, hipMemcpyDeviceToHost, ctx->s));
-    HIPCHK(hipStreamSynchronize(ctx->s));
-    return CUPK_OK;
+    return guarded(ctx, [&]() -> int {
+        if (k == 0) return CUPK_OK;
+        if (!offsets || !out) return ctx->invalid("null array");
+        if (offsets[0] != 0) return ctx->invalid("offsets[0] must be 0");
+        for (size_t j = 0; j < k; j++)
+            if (offsets[j + 1] < offsets[j]) return ctx->invalid("offsets must be non-decreasing");
+        const size_t nv = offsets[k];
+        if (nv && !verts) return ctx->invalid("null verts");
+        if (nv >= (1ull << 32) || k >= (1ull << 31)) return ctx->invalid("too many members");
+        for (size_t i = 0; i < nv; i++)
+            if (verts[i] >= ctx->V) return ctx->invalid("vertex id >= V");
+        std::vector<uint32_t> vmem(verts, verts + nv), voff(k + 1), none;
+        for (size_t j = 0; j <= k; j++) voff[j] = (uint32_t)offsets[j];
+        int rc = reduce_and_sample(ctx, 0, vmem, voff, none, none);
+        if (rc != CUPK_OK) return rc;
+        HIPCHK(grow(ctx->d_tmp, (size_t)k * ctx->W));
+        HIPCHK(launch_to_canonical(ctx->s, ctx->d_sig[0].p, ctx->C, ctx->D, k, ctx->d_tmp.p));
+        HIPCHK(hipMemcpyAsync(out, ctx->d_tmp.p, (size_t)k * ctx->W * 8, hipMemcpyDeviceToHost, ctx->s));
+        HIPCHK(hipStreamSynchronize(ctx->s));
+        return CUPK_OK;
+    });
 }
 
 int cupk_component_sketch(cupk_ctx *ctx, const uint32_t *verts, size_t n, cupk_bucket *out)
@@ -1035,25 +1212,27 @@ int cupk_sample_cut_edge_batch(cupk_ctx *ctx, const cupk_bucket *sketches, size_
                                int32_t *status, uint32_t *u, uint32_t *v)
 {
     if (!ctx) return CUPK_EINVAL;
-    if (k == 0) return CUPK_OK;
-    if (!sketches || !status || !u || !v) return ctx->invalid("null array");
-    if (k >= (1ull << 31)) return ctx->invalid("too many sketches");
-    const size_t words = (size_t)k * ctx->W;
-    HIPCHK(grow(ctx->d_tmp, words));
-    HIPCHK(grow(ctx->d_res, 3 * k));
-    HIPCHK(grow(ctx->h_res, 3 * k));
-    HIPCHK(hipMemcpyAsync(ctx->d_tmp.p, sketches, words * 8, hipMemcpyHostToDevice, ctx->s));
-    // canonical layout: bucket (c, d) at word (c*D + d)*2
-    HIPCHK(launch_sample(ctx->s, ctx->d_tmp.p, (uint32_t)k, ctx->V, ctx->C, ctx->D, ctx->D, 1,
-                         ctx->W, ctx->d_seeds, ctx->d_res.p));
-    HIPCHK(hipMemcpyAsync(ctx->h_res.p, ctx->d_res.p, 3 * k * 4, hipMemcpyDeviceToHost, ctx->s));
-    HIPCHK(hipStreamSynchronize(ctx->s));
-    for (size_t j = 0; j < k; j++) {
-        status[j] = ctx->h_res.p[3 * j];
-        u[j] = (uint32_t)ctx->h_res.p[3 * j + 1];
-        v[j] = (uint32_t)ctx->h_res.p[3 * j + 2];
-    }
-    return CUPK_OK;
+    return guarded(ctx, [&]() -> int {
+        if (k == 0) return CUPK_OK;
+        if (!sketches || !status || !u || !v) return ctx->invalid("null array");
+        if (k >= (1ull << 31)) return ctx->invalid("too many sketches");
+        const size_t words = (size_t)k * ctx->W;
+        HIPCHK(grow(ctx->d_tmp, words));
+        HIPCHK(grow(ctx->d_res, 3 * k));
+        HIPCHK(grow(ctx->h_res, 3 * k));
+        HIPCHK(hipMemcpyAsync(ctx->d_tmp.p, sketches, words * 8, hipMemcpyHostToDevice, ctx->s));
+        // canonical layout: bucket (c, d) at word (c*D + d)*2
+        HIPCHK(launch_sample(ctx->s, ctx->d_tmp.p, (uint32_t)k, ctx->V, ctx->C, ctx->D, ctx->D, 1,
+                             ctx->W, ctx->d_seeds, ctx->d_res.p));
+        HIPCHK(hipMemcpyAsync(ctx->h_res.p, ctx->d_res.p, 3 * k * 4, hipMemcpyDeviceToHost, ctx->s));
+        HIPCHK(hipStreamSynchronize(ctx->s));
+        for (size_t j = 0; j < k; j++) {
+            status[j] = ctx->h_res.p[3 * j];
+            u[j] = (uint32_t)ctx->h_res.p[3 * j + 1];
+            v[j] = (uint32_t)ctx->h_res.p[3 * j + 2];
+        }
+        return CUPK_OK;
+    });
 }
 
 int cupk_sample_cut_edge(cupk_ctx *ctx, const cupk_bucket *sketch, uint32_t *u, uint32_t *v)
@@ -1070,40 +1249,46 @@ int cupk_sample_cut_edge(cupk_ctx *ctx, const cupk_bucket *sketch, uint32_t *u, 
 int cupk_connected(cupk_ctx *ctx, uint32_t u, uint32_t v)
 {
     if (!ctx) return CUPK_EINVAL;
-    if (u >= ctx->V || v >= ctx->V) return ctx->invalid("vertex id >= V");
-    // every batch leaves the forest complete before returning; the sketch
-    // may still be in flight but queries do not read it
-    return ctx->forest.same_tree(u, v) ? 1 : 0;
+    return guarded(ctx, [&]() -> int {
+        if (u >= ctx->V || v >= ctx->V) return ctx->invalid("vertex id >= V");
+        // every batch leaves the forest complete before returning; the sketch
+        // may still be in flight but queries do not read it
+        return ctx->forest.same_tree(u, v) ? 1 : 0;
+    });
 }
 
 int cupk_get_sketch(cupk_ctx *ctx, uint32_t w0, uint32_t nv, cupk_bucket *out)
 {
     if (!ctx) return CUPK_EINVAL;
-    if (nv == 0) return CUPK_OK;
-    if (!out) return ctx->invalid("null out");
-    if ((uint64_t)w0 + nv > ctx->V) return ctx->invalid("vertex range beyond V");
-    const uint32_t step = 4096;
-    HIPCHK(grow(ctx->d_tmp, (size_t)step * ctx->W));
-    for (uint32_t o = 0; o < nv; o += step) {
-        const uint32_t m = std::min(step, nv - o);
-        HIPCHK(launch_to_canonical(ctx->s, ctx->d_sk + (uint64_t)(w0 + o) * ctx->W, ctx->C, ctx->D,
-                                   m, ctx->d_tmp.p));
-        HIPCHK(hipMemcpyAsync(out + (size_t)o * ctx->C * ctx->D, ctx->d_tmp.p,
-                              (size_t)m * ctx->W * 8, hipMemcpyDeviceToHost, ctx->s));
-        HIPCHK(hipStreamSynchronize(ctx->s));
-    }
-    return CUPK_OK;
+    return guarded(ctx, [&]() -> int {
+        if (nv == 0) return CUPK_OK;
+        if (!out) return ctx->invalid("null out");
+        if ((uint64_t)w0 + nv > ctx->V) return ctx->invalid("vertex range beyond V");
+        const uint32_t step = 4096;
+        HIPCHK(grow(ctx->d_tmp, (size_t)step * ctx->W));
+        for (uint32_t o = 0; o < nv; o += step) {
+            const uint32_t m = std::min(step, nv - o);
+            HIPCHK(launch_to_canonical(ctx->s, ctx->d_sk + (uint64_t)(w0 + o) * ctx->W, ctx->C, ctx->D,
+                                       m, ctx->d_tmp.p));
+            HIPCHK(hipMemcpyAsync(out + (size_t)o * ctx->C * ctx->D, ctx->d_tmp.p,
+                                  (size_t)m * ctx->W * 8, hipMemcpyDeviceToHost, ctx->s));
+            HIPCHK(hipStreamSynchronize(ctx->s));
+        }
+        return CUPK_OK;
+    });
 }
 
 int cupk_digest(cupk_ctx *ctx, uint64_t *out)
 {
     if (!ctx || !out) return CUPK_EINVAL;
-    HIPCHK(launch_zero(ctx->s, ctx->d_misc, 1));
-    HIPCHK(launch_digest(ctx->s, dev_sketch(ctx), ctx->S, ctx->d_misc));
-    HIPCHK(hipMemcpyAsync(ctx->h_misc, ctx->d_misc, 8, hipMemcpyDeviceToHost, ctx->s));
-    HIPCHK(hipStreamSynchronize(ctx->s));
-    *out = ctx->h_misc[0];
-    return CUPK_OK;
+    return guarded(ctx, [&]() -> int {
+        HIPCHK(launch_zero(ctx->s, ctx->d_misc, 1));
+        HIPCHK(launch_digest(ctx->s, dev_sketch(ctx), ctx->S, ctx->d_misc));
+        HIPCHK(hipMemcpyAsync(ctx->h_misc, ctx->d_misc, 8, hipMemcpyDeviceToHost, ctx->s));
+        HIPCHK(hipStreamSynchronize(ctx->s));
+        *out = ctx->h_misc[0];
+        return CUPK_OK;
+    });
 }
 
 int cupk_num_components(cupk_ctx *ctx, uint64_t *out)
@@ -1116,14 +1301,16 @@ int cupk_num_components(cupk_ctx *ctx, uint64_t *out)
 int cupk_forest_edges(cupk_ctx *ctx, uint32_t *u, uint32_t *v, size_t cap, size_t *n)
 {
     if (!ctx || !n) return CUPK_EINVAL;
-    std::vector<uint32_t> eu, ev;
-    ctx->forest.edges(eu, ev);
-    *n = eu.size();
-    if (cap < eu.size()) return ctx->invalid("forest edge buffer too small");
-    if (eu.size() && (!u || !v)) return ctx->invalid("null array");
-    std::copy(eu.begin(), eu.end(), u);
-    std::copy(ev.begin(), ev.end(), v);
-    return CUPK_OK;
+    return guarded(ctx, [&]() -> int {
+        std::vector<uint32_t> eu, ev;
+        ctx->forest.edges(eu, ev);
+        *n = eu.size();
+        if (cap < eu.size()) return ctx->invalid("forest edge buffer too small");
+        if (eu.size() && (!u || !v)) return ctx->invalid("null array");
+        std::copy(eu.begin(), eu.end(), u);
+        std::copy(ev.begin(), ev.end(), v);
+        return CUPK_OK;
+    });
 }
 
 int cupk_component_labels(cupk_ctx *ctx, uint32_t *out)
@@ -1136,18 +1323,22 @@ int cupk_component_labels(cupk_ctx *ctx, uint32_t *out)
 int cupk_counters(cupk_ctx *ctx, cupk_counters_t *out)
 {
     if (!ctx || !out) return CUPK_EINVAL;
-    int rc = harvest_timers(ctx, true);
-    if (rc != CUPK_OK) return rc;
-    *out = ctx->ctr;
-    return CUPK_OK;
+    return guarded(ctx, [&]() -> int {
+        int rc = harvest_timers(ctx, true);
+        if (rc != CUPK_OK) return rc;
+        *out = ctx->ctr;
+        return CUPK_OK;
+    });
 }
 
 int cupk_sync(cupk_ctx *ctx)
 {
     if (!ctx) return CUPK_EINVAL;
-    HIPCHK(hipStreamSynchronize(ctx->s));
-    HIPCHK(hipStreamSynchronize(ctx->cs));
-    return harvest_timers(ctx, true);
+    return guarded(ctx, [&]() -> int {
+        HIPCHK(hipStreamSynchronize(ctx->s));
+        HIPCHK(hipStreamSynchronize(ctx->cs));
+        return harvest_timers(ctx, true);
+    });
 }
 
 // Time the bin + scatter of `n` sample updates (one application) with the
@@ -1192,117 +1383,263 @@ static int time_scatter(cupk_ctx *ctx, const uint64_t *d, uint32_t n, int reps, 
     return CUPK_OK;
 }
 
+// Boruvka over supernodes on the resident sketch (see cupk.h).  Round 1
+// samples every vertex sketch in place; round 2 reduces the new supernodes
+// from their vertices, later rounds from the previous round's supernode
+// sketches (each new supernode is a union of previous active ones).
+int static_components(cupk_ctx *ctx, uint32_t *labels, uint32_t *eu, uint32_t *ev,
+                      cupk_static_info *info)
+{
+    const uint32_t V = ctx->V, W = ctx->W;
+    std::vector<uint32_t> parent(V), size(V, 1);
+    for (uint32_t w = 0; w < V; w++) parent[w] = w;
+    auto find = [&](uint32_t x) {
+        while (parent[x] != x) {
+            parent[x] = parent[parent[x]];
+            x = parent[x];
+        }
+        return x;
+    };
+    std::vector<uint32_t> edges_u, edges_v;
+    uint32_t rounds = 0, failed = 0;
+    // active sets of the current round, ascending smallest vertex
+    std::vector<uint32_t> set_min, set_size;
+    std::vector<uint32_t> vmem, voff, fmem, foff;
+    int slot = 0;
+    bool first = true;
+    for (;;) {
+        uint32_t k;
+        const int32_t *res;
+        rounds++;
+        if (first) {
+            k = V;
+            set_min.resize(V);
+            set_size.assign(V, 1);
+            for (uint32_t w = 0; w < V; w++) set_min[w] = w;
+            HIPCHK(grow(ctx->d_res, (size_t)3 * V));
+            HIPCHK(grow(ctx->h_res, (size_t)3 * V));
+            HIPCHK(launch_sample(ctx->s, ctx->d_sk, V, V, ctx->C, ctx->D, 1, ctx->C, W,
+                                 ctx->d_seeds, ctx->d_res.p));
+            HIPCHK(hipMemcpyAsync(ctx->h_res.p, ctx->d_res.p, (size_t)3 * V * 4,
+                                  hipMemcpyDeviceToHost, ctx->s));
+            HIPCHK(hipStreamSynchronize(ctx->s));
+        } else {
+            k = (uint32_t)set_min.size();
+            int rc = reduce_and_sample(ctx, slot, vmem, voff, fmem, foff);
+            if (rc != CUPK_OK) return rc;
+        }
+        res = ctx->h_res.p;
+        bool merged = false;
+        for (uint32_t i = 0; i < k; i++) {
+            if (res[3 * i] != CUPK_OK) continue;
+            const uint32_t x = (uint32_t)res[3 * i + 1], y = (uint32_t)res[3 * i + 2];
+            const uint32_t rx = find(x), ry = find(y);
+            if (rx == ry) continue;
+            parent[rx] = ry;
+            size[ry] += size[rx];
+            edges_u.push_back(std::min(x, y));
+            edges_v.push_back(std::max(x, y));
+            merged = true;
+        }
+        // next round: every supernode with an active part, except EMPTY
+        // ones that nothing joined.  Sets are kept in ascending order of
+        // smallest vertex, so numbering the supernodes in order of their
+        // first part numbers them in that order too.
+        std::vector<int32_t> &gid = ctx->round_gmap;  // by root vertex
+        if (gid.size() != V) gid.assign(V, -1);
+        std::vector<uint32_t> part_gid(k), gcount, nmin, nsize;
+        uint32_t ng = 0;
+        for (uint32_t i = 0; i < k; i++) {
+            const int st = res[3 * i];
+            const uint32_t r = find(set_min[i]);
+            if (st == CUPK_SAMPLE_FAILED) failed++;
+            if (st == CUPK_EMPTY && size[r] == set_size[i]) {
+                part_gid[i] = UINT32_MAX;
+                continue;
+            }
+            if (gid[r] < 0) {
+                gid[r] = (int32_t)ng++;
+                gcount.push_back(0);
+                nmin.push_back(set_min[i]);
+                nsize.push_back(0);
+            }
+            const uint32_t g = (uint32_t)gid[r];
+            part_gid[i] = g;
+            gcount[g]++;
+            nsize[g] += set_size[i];
+        }
+        for (uint32_t i = 0; i < k; i++)
+            if (part_gid[i] != UINT32_MAX) gid[find(set_min[i])] = -1;
+        if (!merged || ng == 0) break;
+        vmem.clear();
+        voff.clear();
+        fmem.clear();
+        foff.clear();
+        std::vector<uint32_t> &mem = first ? vmem : fmem;
+        std::vector<uint32_t> &off = first ? voff : foff;
+        off.assign(ng + 1, 0);
+        for (uint32_t g = 0; g < ng; g++) off[g + 1] = off[g] + gcount[g];
+        mem.resize(off[ng]);
+        std::vector<uint32_t> fill(off.begin(), off.end() - 1);
+        for (uint32_t i = 0; i < k; i++)
+            if (part_gid[i] != UINT32_MAX)
+                mem[fill[part_gid[i]]++] = first ? set_min[i] : i;  // round 1 sets are vertices
+        set_min.swap(nmin);
+        set_size.swap(nsize);
+        if (!first) slot = 1 - slot;
+        first = false;
+    }
+    // labels: smallest vertex of each final supernode
+    std::vector<uint32_t> low(V, 0xffffffffu);
+    uint32_t ncomp = 0;
+    for (uint32_t w = 0; w < V; w++) {
+        const uint32_t r = find(w);
+        if (low[r] == 0xffffffffu) {
+            low[r] = w;
+            ncomp++;
+        }
+        if (labels) labels[w] = low[r];
+    }
+    if (eu && ev) {
+        std::copy(edges_u.begin(), edges_u.end(), eu);
+        std::copy(edges_v.begin(), edges_v.end(), ev);
+    }
+    if (info) {
+        info->n_components = ncomp;
+        info->rounds = rounds;
+        info->sample_failed = failed;
+        info->n_edges = (uint32_t)edges_u.size();
+    }
+    return CUPK_OK;
+}
+
+int cupk_static_components(cupk_ctx *ctx, uint32_t *labels, uint32_t *eu, uint32_t *ev,
+                           cupk_static_info *info)
+{
+    if (!ctx) return CUPK_EINVAL;
+    if (ctx->server) return ctx->invalid("static components while the serving loop runs");
+    return guarded(ctx, [&] { return static_components(ctx, labels, eu, ev, info); });
+}
+
 int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_result *out)
 {
     if (!ctx || !out || !d_sample) return CUPK_EINVAL;
-    if (ctx->server) return ctx->invalid("autotune while the serving loop runs");
-    if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED) return ctx->invalid("autotune needs staged mode");
-    if (n == 0 || n > kMaxBatchPerLaunch) return ctx->invalid("bad sample size");
-    *out = cupk_tune_result{};
-    HIPCHK(hipStreamSynchronize(ctx->s));
-    int rc = upload_forest(ctx);
-    if (rc != CUPK_OK) return rc;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    const uint32_t tv0 = 1u << ctx->tile_shift, rows0 = ctx->rows, chunk0 = ctx->chunk;
-    const uint32_t m = (uint32_t)n;
-    double before = 0;
-    rc = time_scatter(ctx, d_sample, m, 1, e0, e1, &before);  // also warms up
-    if (rc == CUPK_OK) rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &before);
-    double best = before;
-    uint32_t btv = tv0, brows = rows0, bchunk = chunk0, tried = 1;
-    const uint32_t tvs[] = {4, 8, 16, 32, 64};
-    const uint32_t rowss[] = {6, 8, 10, 12};
-    const uint32_t chunks[] = {2048, 4096, 8192};
-    for (uint32_t tv : tvs)
-        for (uint32_t rows : rowss)
-            for (uint32_t ch : chunks) {
-                if (rc != CUPK_OK) break;
-                if (rows > ctx->D || (size_t)2 * rows * ctx->C * tv * 8 > 65536) continue;
-                if (tv == tv0 && rows == rows0 && ch == chunk0) continue;
-                rc = set_geometry(ctx, tv, rows, ch);
-                if (rc != CUPK_OK) break;
-                double ms = 0;
-                rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &ms);
-                tried++;
-                if (rc == CUPK_OK && ms < best) {
-                    best = ms;
-                    btv = tv;
-                    brows = rows;
-                    bchunk = ch;
+    return guarded(ctx, [&]() -> int {
+        if (ctx->server) return ctx->invalid("autotune while the serving loop runs");
+        if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED) return ctx->invalid("autotune needs staged mode");
+        if (n == 0 || n > kMaxBatchPerLaunch) return ctx->invalid("bad sample size");
+        *out = cupk_tune_result{};
+        HIPCHK(hipStreamSynchronize(ctx->s));
+        int rc = upload_forest(ctx);
+        if (rc != CUPK_OK) return rc;
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        const uint32_t tv0 = 1u << ctx->tile_shift, rows0 = ctx->rows, chunk0 = ctx->chunk;
+        const uint32_t m = (uint32_t)n;
+        double before = 0;
+        rc = time_scatter(ctx, d_sample, m, 1, e0, e1, &before);  // also warms up
+        if (rc == CUPK_OK) rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &before);
+        double best = before;
+        uint32_t btv = tv0, brows = rows0, bchunk = chunk0, tried = 1;
+        const uint32_t tvs[] = {4, 8, 16, 32, 64};
+        const uint32_t rowss[] = {6, 8, 10, 12};
+        const uint32_t chunks[] = {2048, 4096, 8192};
+        for (uint32_t tv : tvs)
+            for (uint32_t rows : rowss)
+                for (uint32_t ch : chunks) {
+                    if (rc != CUPK_OK) break;
+                    if (rows > ctx->D || (size_t)2 * rows * ctx->C * tv * 8 > 65536) continue;
+                    if (tv == tv0 && rows == rows0 && ch == chunk0) continue;
+                    rc = set_geometry(ctx, tv, rows, ch);
+                    if (rc != CUPK_OK) break;
+                    double ms = 0;
+                    rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &ms);
+                    tried++;
+                    if (rc == CUPK_OK && ms < best) {
+                        best = ms;
+                        btv = tv;
+                        brows = rows;
+                        bchunk = ch;
+                    }
                 }
-            }
-    if (rc == CUPK_OK) rc = set_geometry(ctx, btv, brows, bchunk);
-    // batch-size schedule: throughput of prefixes n/128 .. n
-    double best_rate = 0;
-    for (int k = 0; k < 8 && rc == CUPK_OK; k++) {
-        const uint32_t sz = std::max<uint32_t>(1, m >> (7 - k));
-        double ms = 0;
-        rc = time_scatter(ctx, d_sample, sz, 2, e0, e1, &ms);
-        out->batch_sizes[k] = sz;
-        out->batch_ms[k] = ms;
-        if (ms > 0) best_rate = std::max(best_rate, sz / ms);
-    }
-    if (rc == CUPK_OK) {
-        out->batch_target = m;
-        for (int k = 0; k < 8; k++)
-            if (out->batch_ms[k] > 0 && out->batch_sizes[k] / out->batch_ms[k] >= 0.8 * best_rate) {
-                out->batch_target = out->batch_sizes[k];
-                break;
-            }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (rc != CUPK_OK) {
-        (void)set_geometry(ctx, tv0, rows0, chunk0);
-        return rc;
-    }
-    out->tile_vertices = btv;
-    out->lds_rows = brows;
-    out->chunk_records = bchunk;
-    out->candidates = tried;
-    out->best_ms = best;
-    out->before_ms = before;
-    return CUPK_OK;
+        if (rc == CUPK_OK) rc = set_geometry(ctx, btv, brows, bchunk);
+        // batch-size schedule: throughput of prefixes n/128 .. n
+        double best_rate = 0;
+        for (int k = 0; k < 8 && rc == CUPK_OK; k++) {
+            const uint32_t sz = std::max<uint32_t>(1, m >> (7 - k));
+            double ms = 0;
+            rc = time_scatter(ctx, d_sample, sz, 2, e0, e1, &ms);
+            out->batch_sizes[k] = sz;
+            out->batch_ms[k] = ms;
+            if (ms > 0) best_rate = std::max(best_rate, sz / ms);
+        }
+        if (rc == CUPK_OK) {
+            out->batch_target = m;
+            for (int k = 0; k < 8; k++)
+                if (out->batch_ms[k] > 0 && out->batch_sizes[k] / out->batch_ms[k] >= 0.8 * best_rate) {
+                    out->batch_target = out->batch_sizes[k];
+                    break;
+                }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != CUPK_OK) {
+            (void)set_geometry(ctx, tv0, rows0, chunk0);
+            return rc;
+        }
+        out->tile_vertices = btv;
+        out->lds_rows = brows;
+        out->chunk_records = bchunk;
+        out->candidates = tried;
+        out->best_ms = best;
+        out->before_ms = before;
+        return CUPK_OK;
+    });
 }
 
 int cupk_serve_start(cupk_ctx *ctx, const cupk_serve_opts *opts)
 {
     if (!ctx) return CUPK_EINVAL;
-    if (ctx->server) return ctx->invalid("serving loop already running");
-    cupk_serve_opts o = {};
-    if (opts) o = *opts;
-    HIPCHK(hipStreamSynchronize(ctx->s));
-    const int dev = ctx->device;
-    ctx->server.reset(new (std::nothrow) Server(
-        ctx, o,
-        [](cupk_ctx *c, const uint64_t *p, size_t n) -> int {
-            static thread_local int bound = -1;
-            if (bound != c->device) {
-                if (hipSetDevice(c->device) != hipSuccess) return CUPK_EDEVICE;
-                bound = c->device;
-            }
-            return apply_packed_host(c, p, n);
-        },
-        connected_impl));
-    (void)dev;
-    if (!ctx->server) return CUPK_ENOMEM;
-    return CUPK_OK;
+    return guarded(ctx, [&]() -> int {
+        if (ctx->server) return ctx->invalid("serving loop already running");
+        cupk_serve_opts o = {};
+        if (opts) o = *opts;
+        HIPCHK(hipStreamSynchronize(ctx->s));
+        const int dev = ctx->device;
+        ctx->server.reset(new (std::nothrow) Server(
+            ctx, o,
+            [](cupk_ctx *c, const uint64_t *p, size_t n) -> int {
+                static thread_local int bound = -1;
+                if (bound != c->device) {
+                    if (hipSetDevice(c->device) != hipSuccess) return CUPK_EDEVICE;
+                    bound = c->device;
+                }
+                return apply_packed_host(c, p, n);
+            },
+            connected_impl));
+        (void)dev;
+        if (!ctx->server) return CUPK_ENOMEM;
+        return CUPK_OK;
+    });
 }
 
 int cupk_submit_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
                         const uint8_t *is_delete, size_t n, uint64_t *ticket)
 {
     if (!ctx || !ctx->server || !ticket) return CUPK_EINVAL;
-    if (n && (!u || !v || !is_delete)) return CUPK_EINVAL;
-    return ctx->server->submit_updates(u, v, is_delete, n, ctx->V, ticket);
+    return guarded(ctx, [&]() -> int {
+        if (n && (!u || !v || !is_delete)) return CUPK_EINVAL;
+        return ctx->server->submit_updates(u, v, is_delete, n, ctx->V, ticket);
+    });
 }
 
 int cupk_submit_query(cupk_ctx *ctx, uint32_t u, uint32_t v, uint64_t *ticket)
 {
     if (!ctx || !ctx->server || !ticket) return CUPK_EINVAL;
-    return ctx->server->submit_query(u, v, ctx->V, ticket);
+    return guarded(ctx, [&]() -> int {
+        return ctx->server->submit_query(u, v, ctx->V, ticket);
+    });
 }
 
 int cupk_wait(cupk_ctx *ctx, uint64_t ticket, int32_t *result)
@@ -1314,8 +1651,10 @@ int cupk_wait(cupk_ctx *ctx, uint64_t ticket, int32_t *result)
 int cupk_serve_stats(cupk_ctx *ctx, cupk_serve_stats_t *out)
 {
     if (!ctx || !ctx->server || !out) return CUPK_EINVAL;
-    ctx->server->get_stats(out);
-    return CUPK_OK;
+    return guarded(ctx, [&]() -> int {
+        ctx->server->get_stats(out);
+        return CUPK_OK;
+    });
 }
 
 int cupk_serve_reset_stats(cupk_ctx *ctx)
@@ -1328,9 +1667,11 @@ int cupk_serve_reset_stats(cupk_ctx *ctx)
 int cupk_serve_stop(cupk_ctx *ctx)
 {
     if (!ctx || !ctx->server) return CUPK_EINVAL;
-    ctx->server.reset();  // drains the queue, joins the worker
-    HIPCHK(hipStreamSynchronize(ctx->s));
-    return CUPK_OK;
+    return guarded(ctx, [&]() -> int {
+        ctx->server.reset();  // drains the queue, joins the worker
+        HIPCHK(hipStreamSynchronize(ctx->s));
+        return CUPK_OK;
+    });
 }
 
 const char *cupk_strerror(int code)

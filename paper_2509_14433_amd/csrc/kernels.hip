@@ -66,81 +66,130 @@ DEVI void lxor(uint64_t *p, uint64_t v)
 //   delete {u,v} that is a forest edge (par[u]==v or par[v]==u), or with
 //   lbl[u] != lbl[v] (an edge linked earlier in this same batch)
 // Everything else can only touch the sketch.  Block b covers positions
-// [b*4096, (b+1)*4096) and writes its flagged updates in stream order into
-// its own region of the flag buffers (same offsets), with a block-wide
-// prefix over the waves of every 256-update step; cnt[b] gets their number.
-// k_flag_compact later packs the regions into one ordered list.
+// [b*4096, (b+1)*4096); each thread issues the loads of all its 16 updates
+// (and their label / parent words) before using any, so one block keeps
+// thousands of loads in flight.  The block writes its flagged updates in
+// stream order into its own region of the flag buffers (same offsets), at
+// positions from one prefix over (step, wave) counts; cnt[b] gets their
+// number.  k_flag_compact later packs the regions into one ordered list.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kClsThreads = 256;
 constexpr uint32_t kClsPerBlock = 4096;
+constexpr uint32_t kClsPerThread = kClsPerBlock / kClsThreads;
+constexpr uint32_t kClsWaves = kClsThreads / 64;
 constexpr uint32_t kLdsHistMax = 8192;
+static_assert(kClsPerThread * kClsWaves == 64, "one wave scans the (step, wave) counts");
 
 __global__ __launch_bounds__(kClsThreads) void k_classify(
     const BatchDesc *__restrict__ desc, uint32_t V, const uint32_t *__restrict__ lbl,
     const uint32_t *__restrict__ par, uint32_t *__restrict__ hdr, uint64_t *__restrict__ fupd,
-    uint32_t *__restrict__ fcnt, uint32_t *__restrict__ tile_cnt,
+    uint32_t *__restrict__ fpos, uint32_t *__restrict__ fcnt, uint32_t *__restrict__ tile_cnt,
     uint32_t tile_shift, uint32_t ntiles)
 {
     __shared__ uint32_t hist[kLdsHistMax];
-    __shared__ uint32_t wtot[kClsThreads / 64];
+    __shared__ uint32_t pre[64 + 1];  // flagged per (step, wave) -> exclusive prefix; total
     const bool count = tile_cnt != nullptr;
     const bool use_lds = count && ntiles <= kLdsHistMax;
     if (use_lds)
         for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) hist[t] = 0;
-    __syncthreads();
 
     const uint64_t *__restrict__ upd = desc->upd;
     const uint32_t n = desc->n;
     const uint32_t begin = blockIdx.x * kClsPerBlock;
-    const uint32_t end = min(n, begin + kClsPerBlock);
     const uint32_t lane = __lane_id();
     const uint32_t wid = threadIdx.x / 64;
-    uint32_t run = 0;  // flagged so far in this block (uniform)
-    uint32_t ndel = 0;
-    for (uint32_t base = begin; base < end; base += blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
-        bool flag = false, bad = false;
-        uint64_t p = 0;
-        if (i < end) {
-            p = upd[i];
+    uint64_t p[kClsPerThread];
+    uint32_t lu[kClsPerThread], lv[kClsPerThread];
+#pragma unroll
+    for (uint32_t k = 0; k < kClsPerThread; k++) {
+        const uint32_t i = begin + k * kClsThreads + threadIdx.x;
+        p[k] = i < n ? upd[i] : 0;
+    }
+    // bit k of `ok`: update k exists and is valid
+    uint32_t ok = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kClsPerThread; k++) {
+        const uint32_t i = begin + k * kClsThreads + threadIdx.x;
+        uint32_t u, v;
+        bool del;
+        lu[k] = lv[k] = 0;
+        if (i < n && unpack(p[k], V, u, v, del)) {
+            ok |= 1u << k;
+            lu[k] = lbl[u];
+            lv[k] = lbl[v];
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (uint32_t k = 0; k < kClsPerThread; k++) {
+        const uint32_t i = begin + k * kClsThreads + threadIdx.x;
+        if (i < n && !((ok >> k) & 1u)) bad = true;
+    }
+    uint32_t fl = 0;  // bit k: update k flagged
+#pragma unroll
+    for (uint32_t k = 0; k < kClsPerThread; k++) {
+        if (!((ok >> k) & 1u)) continue;
+        uint32_t u, v;
+        bool del;
+        unpack(p[k], V, u, v, del);
+        bool f = lu[k] != lv[k];
+        if (!f && del) f = par[u] == v || par[v] == u;
+        if (f) fl |= 1u << k;
+    }
+    __syncthreads();  // hist zeroed
+    if (count) {
+        uint32_t *h = use_lds ? hist : tile_cnt;
+#pragma unroll
+        for (uint32_t k = 0; k < kClsPerThread; k++) {
+            if (!((ok >> k) & 1u)) continue;
             uint32_t u, v;
             bool del;
-            if (!unpack(p, V, u, v, del)) {
-                bad = true;
-            } else {
-                const uint32_t lu = lbl[u], lv = lbl[v];
-                flag = (lu != lv) || (del && (par[u] == v || par[v] == u));
-                if (count) {
-                    const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
-                    uint32_t *h = use_lds ? hist : tile_cnt;
-                    atomicAdd(&h[tu], 1u);
-                    if (tv != tu) atomicAdd(&h[tv], 1u);
-                }
-            }
+            unpack(p[k], V, u, v, del);
+            const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
+            atomicAdd(&h[tu], 1u);
+            if (tv != tu) atomicAdd(&h[tv], 1u);
         }
-        const uint64_t m = __ballot(flag);
-        if (lane == 0) wtot[wid] = (uint32_t)__popcll(m);
-        const uint64_t md = __ballot(flag && (p >> 63));
-        ndel += (uint32_t)__popcll(md);
-        const uint64_t mb = __ballot(bad);
-        if (mb && lane == (uint32_t)__builtin_ctzll(mb)) atomicOr(&hdr[HDR_ERR], 1u);
-        __syncthreads();
-        uint32_t before = 0, tot = 0;
-        for (uint32_t w = 0; w < kClsThreads / 64; w++) {
-            before += w < wid ? wtot[w] : 0u;
-            tot += wtot[w];
-        }
-        if (flag) {
-            fupd[begin + run + before + lanes_below(m)] = p;
-        }
-        run += tot;
-        __syncthreads();
     }
+    uint32_t ndel = 0;  // flagged deletes of this lane, then of this wave
+#pragma unroll
+    for (uint32_t k = 0; k < kClsPerThread; k++) {
+        const bool f = (fl >> k) & 1u;
+        const uint64_t m = __ballot(f);
+        if (lane == 0) pre[k * kClsWaves + wid] = (uint32_t)__popcll(m);
+        ndel += (f && (p[k] >> 63)) ? 1u : 0u;
+    }
+#pragma unroll
+    for (uint32_t o = 32; o > 0; o >>= 1) ndel += __shfl_xor(ndel, o);
+    const uint64_t mb = __ballot(bad);
+    if (mb && lane == (uint32_t)__builtin_ctzll(mb)) atomicOr(&hdr[HDR_ERR], 1u);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t x = pre[threadIdx.x];
+        uint32_t inc = x;
+#pragma unroll
+        for (uint32_t o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        pre[threadIdx.x] = inc - x;
+        if (threadIdx.x == 63) pre[64] = inc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kClsPerThread; k++) {
+        const bool f = (fl >> k) & 1u;
+        const uint64_t m = __ballot(f);
+        if (f) {
+            const uint32_t q = begin + pre[k * kClsWaves + wid] + lanes_below(m);
+            fupd[q] = p[k];
+            if (fpos) fpos[q] = begin + k * kClsThreads + threadIdx.x;
+        }
+    }
+    const uint32_t total = pre[64];
     if (threadIdx.x == 0) {
-        fcnt[blockIdx.x] = run;
-        if (run) atomicAdd(&hdr[HDR_NFLAG], run);
+        fcnt[blockIdx.x] = total;
+        if (total) atomicAdd(&hdr[HDR_NFLAG], total);
     }
-    // ndel is per wave; lane 0 of each wave adds its share
     if (lane == 0 && ndel) atomicAdd(&hdr[HDR_NFLAG_DEL], ndel);
     if (use_lds) {
         __syncthreads();
@@ -153,12 +202,12 @@ uint32_t classify_blocks(uint32_t n) { return (n + kClsPerBlock - 1) / kClsPerBl
 
 hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, uint32_t grid_n, uint32_t V,
                            const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
-                           uint64_t *fupd, uint32_t *fcnt, uint32_t *tile_cnt,
+                           uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles)
 {
     if (grid_n == 0) return hipSuccess;
-    k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(desc, V, lbl, par, hdr, fupd, fcnt,
-                                                              tile_cnt, tile_shift, ntiles);
+    k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(desc, V, lbl, par, hdr, fupd, fpos,
+                                                              fcnt, tile_cnt, tile_shift, ntiles);
     return hipGetLastError();
 }
 
@@ -297,6 +346,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(
 
 constexpr uint32_t kFillThreads = 256;
 constexpr uint32_t kFillPerBlock = 4096;
+constexpr uint32_t kFillPerThread = kFillPerBlock / kFillThreads;
 
 __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
     const BatchDesc *__restrict__ desc, uint32_t V, uint32_t tile_shift, uint32_t ntiles,
@@ -306,15 +356,23 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
     if (hdr[HDR_ERR]) return;
     const uint64_t *__restrict__ upd = desc->upd;
     const uint32_t n = desc->n;
-    if (blockIdx.x * kFillPerBlock >= n) return;
     const uint32_t begin = blockIdx.x * kFillPerBlock;
-    const uint32_t end = min(n, begin + kFillPerBlock);
+    if (begin >= n) return;
+    // all of this thread's updates are loaded once, up front
+    uint64_t p[kFillPerThread];
+#pragma unroll
+    for (uint32_t k = 0; k < kFillPerThread; k++) {
+        const uint32_t i = begin + k * kFillThreads + threadIdx.x;
+        p[k] = i < n ? upd[i] : 0;
+    }
     if (ntiles > kLdsHistMax) {
         // Many small tiles: contention is low, reserve per record.
-        for (uint32_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+#pragma unroll
+        for (uint32_t k = 0; k < kFillPerThread; k++) {
+            if (begin + k * kFillThreads + threadIdx.x >= n) continue;
             uint32_t u, v;
             bool del;
-            unpack(upd[i], V, u, v, del);
+            unpack(p[k], V, u, v, del);
             const uint64_t rec = (uint64_t)u | ((uint64_t)v << 32);
             const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
             bins[atomicAdd(&cur[tu], 1u)] = rec;
@@ -324,14 +382,18 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
     }
     for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) lcnt[t] = 0;
     __syncthreads();
-    // pass 1: block-local counts
-    for (uint32_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+    // ranks of each record inside its tile's share of this block
+    uint32_t ru[kFillPerThread], rv[kFillPerThread];
+#pragma unroll
+    for (uint32_t k = 0; k < kFillPerThread; k++) {
+        ru[k] = rv[k] = 0;
+        if (begin + k * kFillThreads + threadIdx.x >= n) continue;
         uint32_t u, v;
         bool del;
-        unpack(upd[i], V, u, v, del);
+        unpack(p[k], V, u, v, del);
         const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
-        atomicAdd(&lcnt[tu], 1u);
-        if (tv != tu) atomicAdd(&lcnt[tv], 1u);
+        ru[k] = atomicAdd(&lcnt[tu], 1u);
+        if (tv != tu) rv[k] = atomicAdd(&lcnt[tv], 1u);
     }
     __syncthreads();
     // reserve one contiguous range per tile present in this block
@@ -340,15 +402,16 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
         if (c) lcnt[t] = atomicAdd(&cur[t], c);
     }
     __syncthreads();
-    // pass 2: write records
-    for (uint32_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+#pragma unroll
+    for (uint32_t k = 0; k < kFillPerThread; k++) {
+        if (begin + k * kFillThreads + threadIdx.x >= n) continue;
         uint32_t u, v;
         bool del;
-        unpack(upd[i], V, u, v, del);
+        unpack(p[k], V, u, v, del);
         const uint64_t rec = (uint64_t)u | ((uint64_t)v << 32);
         const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
-        bins[atomicAdd(&lcnt[tu], 1u)] = rec;
-        if (tv != tu) bins[atomicAdd(&lcnt[tv], 1u)] = rec;
+        bins[lcnt[tu] + ru[k]] = rec;
+        if (tv != tu) bins[lcnt[tv] + rv[k]] = rec;
     }
 }
 
@@ -519,25 +582,31 @@ __global__ __launch_bounds__(kScanThreads) void k_flag_scan(const uint32_t *__re
 }
 
 __global__ __launch_bounds__(256) void k_flag_compact(const uint64_t *__restrict__ fupd,
+                                                      const uint32_t *__restrict__ fpos,
                                                       const uint32_t *__restrict__ fcnt,
                                                       const uint32_t *__restrict__ foff,
-                                                      uint64_t *__restrict__ oupd)
+                                                      uint64_t *__restrict__ oupd,
+                                                      uint32_t *__restrict__ opos)
 {
     const uint32_t b = blockIdx.x;
     const uint32_t c = fcnt[b], o = foff[b];
     const uint32_t src = b * kClsPerBlock;
-    for (uint32_t k = threadIdx.x; k < c; k += blockDim.x) oupd[o + k] = fupd[src + k];
+    for (uint32_t k = threadIdx.x; k < c; k += blockDim.x) {
+        oupd[o + k] = fupd[src + k];
+        if (opos) opos[o + k] = fpos[src + k];
+    }
 }
 
 hipError_t launch_flag_compact(hipStream_t s, uint32_t n, const uint64_t *fupd,
-                               const uint32_t *fcnt, uint32_t *foff, uint64_t *oupd)
+                               const uint32_t *fpos, const uint32_t *fcnt, uint32_t *foff,
+                               uint64_t *oupd, uint32_t *opos)
 {
     const uint32_t nb = classify_blocks(n);
     if (nb == 0) return hipSuccess;
     k_flag_scan<<<1, kScanThreads, 0, s>>>(fcnt, nb, foff);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_flag_compact<<<nb, 256, 0, s>>>(fupd, fcnt, foff, oupd);
+    k_flag_compact<<<nb, 256, 0, s>>>(fupd, fpos, fcnt, foff, oupd, opos);
     return hipGetLastError();
 }
 

@@ -41,19 +41,22 @@ struct StagedParams {
 // the kernel also counts how many endpoint records each vertex tile gets.
 // Flagged updates of classify block b (positions [b*4096, (b+1)*4096)) land
 // in stream order at offsets b*4096.. of fupd (capacity: the batch rounded
-// up to a multiple of 4096); fcnt[b] receives their number.
+// up to a multiple of 4096); fcnt[b] receives their number.  fpos (may be
+// null) receives each flagged update's position in the batch, alongside.
 // grid_n sizes the grids (the batch size, or the capacity of a captured
 // graph); the kernels read the actual batch from desc.
 hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, uint32_t grid_n, uint32_t V,
                            const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
-                           uint64_t *fupd, uint32_t *fcnt, uint32_t *tile_cnt,
+                           uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles);
 uint32_t classify_blocks(uint32_t n);
 
 // Pack the per-block flag regions into one list in stream order (foff:
-// classify_blocks(n) words of scratch).
+// classify_blocks(n) words of scratch); positions too when fpos and opos
+// are not null.
 hipError_t launch_flag_compact(hipStream_t s, uint32_t n, const uint64_t *fupd,
-                               const uint32_t *fcnt, uint32_t *foff, uint64_t *oupd);
+                               const uint32_t *fpos, const uint32_t *fcnt, uint32_t *foff,
+                               uint64_t *oupd, uint32_t *opos);
 
 // Plain scatter: device-scope atomic XOR of (x, h) into both endpoints.
 hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, uint32_t grid_n,

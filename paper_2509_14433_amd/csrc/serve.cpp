@@ -29,6 +29,8 @@
 #include "cupk.h"
 #include "serve.hpp"
 
+#include <exception>
+
 namespace cupk {
 
 namespace {
@@ -179,7 +181,12 @@ void Server::loop()
         }
         int rc = CUPK_OK;
         if (!batch.empty()) {
-            rc = apply_(ctx_, batch.data(), batch.size());
+            // no exception may leave the worker thread
+            try {
+                rc = apply_(ctx_, batch.data(), batch.size());
+            } catch (const std::exception &) {
+                rc = CUPK_ENOMEM;
+            }
             std::lock_guard<std::mutex> g(m_);
             stats_.batches++;
             stats_.updates += batch.size();

@@ -62,6 +62,8 @@ def _c():
         L.sg_rmat_next.argtypes = [p, sz, dbl, dbl, dbl, dbl, p, p, p]
         L.sg_clustered.restype = sz
         L.sg_clustered.argtypes = [u32, u32, dbl, u32, u32, u32, u32, u32, u64, sz, p, p, p]
+        L.sg_forest_mask.restype = sz
+        L.sg_forest_mask.argtypes = [u32, sz, p, p, p]
         _lib = L
     return _lib
 
@@ -259,6 +261,43 @@ def er_standard(V: int, p: float, del_frac: float, seed: int):
     return uu, vv, dd
 
 
+def forest_mask(V: int, u, v) -> np.ndarray:
+    """Boolean mask of the first-arrival spanning forest of the edge
+    sequence (u, v): an edge is in it iff it joins two components of the
+    edges before it."""
+    u = np.ascontiguousarray(u, np.uint32)
+    v = np.ascontiguousarray(v, np.uint32)
+    m = np.zeros(u.shape[0], np.uint8)
+    k = _c().sg_forest_mask(V, u.shape[0], _p(u), _p(v), _p(m))
+    if k == ctypes.c_size_t(-1).value:
+        raise MemoryError("forest mask")
+    return m.astype(bool)
+
+
+def fixed_forest(V: int, p: float, reps: int, seed: int):
+    """Fixed-forest stream of G(V, p) (the paper's second stream type,
+    Sec. 5 and App. C.1): insert a spanning forest of the graph (the
+    first-arrival forest of a random edge order), then ``reps`` times insert
+    every other edge in random order and delete them all in random order.
+    The forest is never deleted, so after the forest no update changes the
+    components: almost every update is a non-tree-edge update."""
+    rng = np.random.default_rng(seed)
+    u, v = er_pairs(V, p, rng)
+    order = rng.permutation(u.shape[0])
+    u, v = u[order], v[order]
+    fm = forest_mask(V, u, v)
+    parts_u, parts_v, parts_d = [u[fm]], [v[fm]], [np.zeros(int(fm.sum()), np.uint8)]
+    ou, ov = u[~fm], v[~fm]
+    m = ou.shape[0]
+    for _ in range(reps):
+        pi = rng.permutation(m)
+        pd = rng.permutation(m)
+        parts_u += [ou[pi], ou[pd]]
+        parts_v += [ov[pi], ov[pd]]
+        parts_d += [np.zeros(m, np.uint8), np.ones(m, np.uint8)]
+    return np.concatenate(parts_u), np.concatenate(parts_v), np.concatenate(parts_d)
+
+
 def star_stream(V: int, n_rounds: int, seed: int, center: int = 0):
     """Hot-vertex adversary: every update touches ``center``.  Inserts the
     star edges in random order, then toggles random star edges
@@ -345,6 +384,10 @@ CONFIGS = {
     4: dict(name="clusters64x2048_churn", V=1 << 20, K=64, Sc=2048, p_in=0.5, n_sparse=917_504,
             extra_bridges=65, rounds=11, adv_every=100_000, adv_k=100, seed=5,
             S=0x5EED0000 + 4, batch=1_000_000),
+    # fixed-forest stream of G(16384, 0.3): the forest, then every other edge
+    # inserted and deleted once (the paper repeats once for large graphs)
+    5: dict(name="er16384_p0.3_fixedforest", V=16384, p=0.3, reps=1, seed=6,
+            S=0x5EED0000 + 5, batch=1_000_000),
 }
 
 # The same recipes at sizes the CPU oracle replays in seconds (parity tests).
@@ -356,6 +399,8 @@ SCALED = {
     4: dict(name="clusters8x128_churn", V=8 * 128 + 1024, K=8, Sc=128, p_in=0.5, n_sparse=1024,
             extra_bridges=4, rounds=2, adv_every=3000, adv_k=3, seed=15, S=0x5EED1004,
             batch=20_000),
+    5: dict(name="er1024_p0.3_fixedforest", V=1024, p=0.3, reps=2, seed=16, S=0x5EED1005,
+            batch=50_000),
 }
 
 
@@ -368,6 +413,8 @@ def stream_of(cfg: dict):
     if "forest_frac" in cfg:
         raise ValueError("forest-targeted deletions need the current forest: "
                          "use ForestTargetedDeletes")
+    if "reps" in cfg:
+        return fixed_forest(cfg["V"], cfg["p"], cfg["reps"], cfg["seed"])
     if "K" in cfg:
         return clustered_churn(cfg["K"], cfg["Sc"], cfg["p_in"], cfg["n_sparse"],
                                cfg["extra_bridges"], cfg["rounds"], cfg["adv_every"],

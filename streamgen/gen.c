@@ -381,3 +381,26 @@ done:
     free(hs);
     return ok ? w : 0;
 }
+
+/*
+ * First-arrival spanning forest of an edge sequence: mask[i] = 1 iff edge i
+ * joins two components of the edges before it (union-find).  Returns the
+ * number of forest edges, or (size_t)-1 when out of memory.
+ */
+size_t sg_forest_mask(uint32_t V, size_t n, const uint32_t *u, const uint32_t *v, uint8_t *mask)
+{
+    uint32_t *p = (uint32_t *)malloc((size_t)V * sizeof(uint32_t));
+    if (!p) return (size_t)-1;
+    for (uint32_t w = 0; w < V; w++) p[w] = w;
+    size_t k = 0;
+    for (size_t i = 0; i < n; i++) {
+        const uint32_t a = uf_find(p, u[i]), b = uf_find(p, v[i]);
+        mask[i] = a != b;
+        if (a != b) {
+            p[a] = b;
+            k++;
+        }
+    }
+    free(p);
+    return k;
+}

@@ -206,3 +206,29 @@ def test_clustered_churn(cupk, mode):
     assert ctx.forest_edges() == fr.forest_edges()
     assert ctx.counters()["cuts"] == fr.n_cuts
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", ["atomic", "staged"])
+def test_fixed_forest_stream(cupk, mode):
+    # the forest first, then every other edge inserted and deleted twice:
+    # the forest never changes after it is built and no update is a cut
+    cfg = streamgen.SCALED[5]
+    V = cfg["V"]
+    C, D = _cd(V)
+    u, v, d = streamgen.config_stream(5, scaled=True)
+    sm = cupk.SCATTER_ATOMIC if mode == "atomic" else cupk.SCATTER_STAGED
+    ctx = cupk.Context(V, C, D, cfg["S"], scatter_mode=sm)
+    sk = oracle.Sketch(V, C, D, cfg["S"])
+    fr = oracle.ForestReplay(sk)
+    B = cfg["batch"]
+    print(f"fixed forest n={len(u)} mode={mode}", flush=True)
+    for s in range(0, len(u), B):
+        ctx.apply_updates(u[s:s + B], v[s:s + B], d[s:s + B])
+        fr.apply_batch(u[s:s + B], v[s:s + B], d[s:s + B])
+    assert ctx.digest() == sk.digest()
+    assert ctx.forest_edges() == fr.forest_edges()
+    fu, fv = streamgen.final_edges(u, v, d)
+    assert set(ctx.forest_edges()) == set(zip(fu.tolist(), fv.tolist()))
+    ctr = ctx.counters()
+    assert ctr["cuts"] == 0 and ctr["links"] == len(fu) == fr.n_links
+    ctx.close()

@@ -97,6 +97,26 @@ def test_benchmark_workload_full_size(workload, mode):
     ctr = ctx.counters()
     print(ctr, flush=True)
     assert ctr["sample_failed"] == 0
+    # components from the sketches alone: same partition, merge edges are a
+    # spanning forest of the final graph, Boruvka's round bound
+    sl, se, si = ctx.static_components()
+    assert si["sample_failed"] == 0 and si["n_components"] == W["ncomp"]
+    assert all(comp[w] == comp[sl[w]] for w in range(V))
+    assert len(set(sl.tolist())) == W["ncomp"]
+    assert si["n_edges"] == V - W["ncomp"] and si["rounds"] <= C + 1
+    sk_keys = np.array([a * V + b for a, b in se], dtype=np.uint64)
+    assert np.isin(sk_keys, W["final"]).all()
+    par = list(range(V))
+
+    def find(x):
+        while par[x] != x:
+            par[x] = par[par[x]]
+            x = par[x]
+        return x
+    for a, b in se:
+        ra, rb = find(a), find(b)
+        assert ra != rb
+        par[ra] = rb
     ctx.close()
 
 

@@ -400,3 +400,34 @@ def test_rounds_leave_out_the_largest_dirty_tree(orc):
     assert fr.round_log[-1] == [(0, orc.OK, 0, 7)]
     assert (0, 7) in fr.forest_edges() and (2, 3) not in fr.forest_edges()
     assert not fr.mark
+
+
+def test_static_components_hand_worked(orc):
+    """Two disjoint edges on four vertices: round 1 samples the four
+    singletons (each has one incident edge, always recovered) and merges
+    {0,1} then {2,3}; round 2 finds both supernodes EMPTY."""
+    sk = orc.Sketch(4, 2, 4, 0x5EED)
+    sk.apply(np.array([0, 2], np.uint32), np.array([1, 3], np.uint32))
+    labels, edges, rounds, failed = orc.static_components(sk)
+    assert labels.tolist() == [0, 0, 2, 2]
+    assert edges == [(0, 1), (2, 3)]
+    assert rounds == 2 and failed == 0
+
+
+@pytest.mark.parametrize("V,p,seed", [(40, 0.05, 1), (120, 0.02, 2), (200, 0.3, 3),
+                                      (300, 0.004, 4)])
+def test_static_components_match_bfs(orc, V, p, seed):
+    """Boruvka over the sketch finds the true components (w.h.p.; no query
+    fails at these sizes), its merge edges are a spanning forest of the
+    graph, and the rounds at most halve the active supernodes each time."""
+    C = math.ceil(math.log2(V))
+    u, v, d = _small_stream(V, p, 0.3, seed)
+    sk = orc.Sketch(V, C, 2 * C, 0x5EED + seed)
+    sk.apply(u, v)
+    fu, fv = streamgen.final_edges(u, v, d)
+    truth = orc.components_truth(V, fu, fv)
+    labels, edges, rounds, failed = orc.static_components(sk)
+    assert failed == 0
+    assert labels.tolist() == truth.tolist()
+    orc.check_spanning_forest(V, edges, set(zip(fu.tolist(), fv.tolist())), truth)
+    assert rounds <= math.ceil(math.log2(V)) + 1

@@ -59,3 +59,32 @@ def test_forest_targeted_deletes_picks_supplied_forest_edges():
     assert got <= live
     nf = len(got & set(forest))
     assert 100 <= nf <= 200  # Binomial(500, 0.3) capped at the 100 forest edges
+
+
+def test_fixed_forest_stream():
+    """The forest comes first and is never deleted; every other edge is
+    inserted and deleted reps times; replaying it links exactly the forest
+    and never cuts."""
+    import oracle
+    V, reps = 300, 2
+    u, v, d = streamgen.fixed_forest(V, 0.05, reps, 9)
+    fu, fv = streamgen.final_edges(u, v, d)
+    k = len(fu)
+    assert set(zip(u[:k].tolist(), v[:k].tolist())) == set(zip(fu.tolist(), fv.tolist()))
+    assert not d[:k].any()
+    rest = len(u) - k
+    assert rest % (2 * reps) == 0
+    m = rest // (2 * reps)
+    truth = oracle.components_truth(V, fu, fv)
+    assert k == V - len(set(truth.tolist()))     # a spanning forest
+    sk = oracle.Sketch(V, 9, 18, 0x5EED)
+    fr = oracle.ForestReplay(sk)
+    for s in range(0, len(u), 997):
+        fr.apply_batch(u[s:s + 997], v[s:s + 997], d[s:s + 997])
+    assert fr.n_cuts == 0 and fr.n_links == k
+    assert set(fr.forest_edges()) == set(zip(fu.tolist(), fv.tolist()))
+    for r in range(reps):
+        ins = slice(k + 2 * r * m, k + (2 * r + 1) * m)
+        dele = slice(k + (2 * r + 1) * m, k + (2 * r + 2) * m)
+        assert not d[ins].any() and d[dele].all()
+        assert set(zip(u[ins].tolist(), v[ins].tolist())) == set(zip(u[dele].tolist(), v[dele].tolist()))
