@@ -267,6 +267,35 @@ def workload_leg(args, cupk, torch, np, streamgen):
                                                          "chunk_records", "batch_target")}
         out.update({"workload": cfg["name"], "updates": n, "batches": len(sizes), "V": Vw,
                     "C": Cw, "D": Dw, "results": res})
+    elif name == "levels":
+        # the multi-level hierarchy on the benchmark stream, and on the
+        # fixed-forest stream, against the single-level path
+        res = {}
+        for i, label in ((1, "standard"), (5, "fixed_forest")):
+            cfg = streamgen.CONFIGS[i]
+            print(f"bench: generating {cfg['name']}", file=sys.stderr, flush=True)
+            u, v, d = streamgen.config_stream(i)
+            n = len(u)
+            packed = torch.from_numpy(cupk.pack_updates(u, v, d).view(np.int64)).cuda()
+            del u, v, d
+            sizes = streamgen.fixed_sizes(n, cfg["batch"])
+            Vw = cfg["V"]
+            Cw = streamgen.ceil_log2(Vw)
+            for lv in (True, False):
+                print(f"bench: levels={lv} {label}", file=sys.stderr, flush=True)
+                dt, ctr, _ = _time_batches(cupk, torch, dict(levels=lv, max_batch=cfg["batch"]),
+                                           packed, sizes, Vw, Cw, 2 * Cw, cfg["S"])
+                res[f"{label}/{'levels' if lv else 'single_level'}"] = {
+                    "value": round(n / dt, 1), "seconds": round(dt, 4), "links": ctr["links"],
+                    "cuts": ctr["cuts"], "level_passes": ctr["level_passes"],
+                    "level_repairs": ctr["level_repairs"], "level_failed": ctr["level_failed"],
+                    "top_rounds": ctr["rounds"], "sample_failed": ctr["sample_failed"],
+                    "host_rounds_ms": round(ctr["host_rounds_ms"], 3)}
+            del packed
+            torch.cuda.synchronize()
+        out.update({"workload": "levels mode on er16384_p0.3_del10 and "
+                                "er16384_p0.3_fixedforest, 1,000,000-update batches",
+                    "results": res})
     elif name == "exact_sweep":
         # throughput against batch (buffer) size with per-update semantics
         # (exact mode) and with batch semantics, over a window of 1,000,000
@@ -385,7 +414,7 @@ def main():
                     help="1: replay each batch's device work as captured HIP graphs")
     ap.add_argument("--workload", default="er16384",
                     choices=["er16384", "rmat17", "er65536_served", "clusters", "fixed_forest",
-                             "exact_sweep"],
+                             "exact_sweep", "levels"],
                     help="er16384: the benchmark line; the others print extra full-size "
                          "measurements of the other workload recipes")
     ap.add_argument("--calib", action="store_true",

@@ -115,6 +115,21 @@ typedef struct {
      * batch end rather than after every update).  Captured graphs
      * (use_graph) are not used in this mode. */
     uint32_t exact;
+    /* Nonzero: multi-level hierarchy (Gibb's cutset levels, Sec. 2.2.2 and
+     * Alg. 1).  Levels 0..C: level i < C keeps its own forest and queries
+     * its components with sketch column i alone; level C is the forest that
+     * answers connectivity.  Inserts only update the sketch; a delete of a
+     * forest edge removes it from every level from its weight (the lowest
+     * level holding it) up.  At the end of each batch, Invariant 3 (a
+     * level-i component whose query returns an edge is a proper subset of
+     * its level-(i+1) component) is restored pass by pass from the lowest
+     * violating level, each pass one reduce + query launch over the
+     * components that could violate it; a repair removes the heaviest edge
+     * of the cycle it would close (ties: the smaller edge) from its weight
+     * up and adds the sampled edge to every level above.  The top forest is
+     * then completed with replacement rounds on the all-column sampler.
+     * Not combinable with exact. */
+    uint32_t levels;
 } cupk_opts;
 
 /* Counters, cumulative since init. */
@@ -136,6 +151,9 @@ typedef struct {
     double host_rounds_ms;       /* host time in replacement rounds (incl. GPU)  */
     uint64_t reverts;            /* exact mode: batch tails scattered again to
                                     undo speculation past a cut                 */
+    uint64_t level_passes;       /* levels mode: restoration passes              */
+    uint64_t level_repairs;      /* levels mode: violating components repaired   */
+    uint64_t level_failed;       /* levels mode: one-column queries that failed  */
 } cupk_counters_t;
 
 /* Bytes of device memory the sketch of (V, C, D) occupies. */
@@ -238,6 +256,13 @@ int cupk_forest_edges(cupk_ctx *ctx, uint32_t *u, uint32_t *v, size_t cap, size_
 /* Component label of every vertex (host array of V).  Two vertices are
  * connected iff their labels are equal. */
 int cupk_component_labels(cupk_ctx *ctx, uint32_t *out);
+
+/* Levels mode: edges of the forest of `level` (1..C; C is the forest of
+ * cupk_forest_edges), same contract as cupk_forest_edges.
+ * Errors: CUPK_EINVAL (not in levels mode, level out of range, cap too
+ * small: *n is then the count needed). */
+int cupk_level_forest_edges(cupk_ctx *ctx, uint32_t level, uint32_t *u, uint32_t *v, size_t cap,
+                            size_t *n);
 
 int cupk_counters(cupk_ctx *ctx, cupk_counters_t *out);
 

@@ -66,6 +66,8 @@ def lib():
         L.orc_set_sketch.restype = None; L.orc_set_sketch.argtypes = [p, p, sz, p, p]
         L.orc_sample.restype = ctypes.c_int
         L.orc_sample.argtypes = [u32, u32, u32, u64, p, p, p, p]
+        L.orc_sample_col.restype = ctypes.c_int
+        L.orc_sample_col.argtypes = [u32, u32, u32, u64, u32, p, p, p, p]
         L.orc_digest.restype = u64; L.orc_digest.argtypes = [p]
         L.orc_digest_arrays.restype = u64
         L.orc_digest_arrays.argtypes = [u32, u32, u64, u32, u32, p, p]
@@ -167,6 +169,19 @@ def sample(V, C, D, S, alpha, gamma):
     return st, ou.value, ov.value
 
 
+def sample_col(V, C, D, S, c, alpha, gamma):
+    """(status, u, v) of the query of column c alone on one aggregate
+    sketch (C x D arrays): the sampler of level c of the hierarchy."""
+    a = np.ascontiguousarray(alpha, dtype=np.uint64).reshape(-1)
+    g = np.ascontiguousarray(gamma, dtype=np.uint64).reshape(-1)
+    assert a.shape[0] == C * D and g.shape[0] == C * D and 0 <= c < C
+    ou, ov = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    st = lib().orc_sample_col(V, C, D, S, c, _ptr(a), _ptr(g), ctypes.byref(ou), ctypes.byref(ov))
+    if st != OK:
+        return st, 0, 0
+    return st, ou.value, ov.value
+
+
 def vertex_from_stream(V, C, D, S, w, u, v):
     """Sketch of vertex w from the updates that touch it (C x D arrays)."""
     u = np.ascontiguousarray(u, dtype=np.uint32)
@@ -189,10 +204,11 @@ def digest_arrays(C, D, S, w0, alpha, gamma) -> int:
 
 from .forest import ForestReplay, components_truth, check_spanning_forest  # noqa: E402
 from .static_cc import static_components  # noqa: E402
+from .levels import LevelsReplay  # noqa: E402
 
 __all__ = [
     "OK", "EMPTY", "FAILED", "build", "lib", "mix", "seed", "hash_c",
-    "depth_of_hash", "edge_index", "Sketch", "sample", "vertex_from_stream",
+    "depth_of_hash", "edge_index", "Sketch", "sample", "sample_col", "vertex_from_stream",
     "digest_arrays", "ForestReplay", "components_truth", "check_spanning_forest",
-    "static_components",
+    "static_components", "LevelsReplay",
 ]

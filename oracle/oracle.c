@@ -236,6 +236,33 @@ int orc_sample(uint32_t V, uint32_t C, uint32_t D, uint64_t S,
     return ORC_EMPTY;
 }
 
+/* The query of column c alone: the sampler of one level of the multi-level
+ * hierarchy (Sec. 2.2.2; level c uses column c).  Same scan as orc_sample
+ * over that column's depths; EMPTY when the column is all zero. */
+int orc_sample_col(uint32_t V, uint32_t C, uint32_t D, uint64_t S, uint32_t c,
+                   const uint64_t *alpha, const uint64_t *gamma,
+                   uint32_t *out_u, uint32_t *out_v)
+{
+    uint64_t seed = orc_seed(S, c);
+    (void)C;
+    for (uint32_t k = 0; k < D; k++) {
+        uint32_t d = D - 1 - k;
+        uint64_t a = alpha[c * D + d];
+        uint64_t g = gamma[c * D + d];
+        if (a == 0) continue;
+        if (!orc_valid_index(V, a)) continue;
+        uint64_t h = orc_mix(a ^ seed);
+        if (h != g) continue;
+        if (orc_depth_of_hash(h, D) != d) continue;
+        *out_u = (uint32_t)(a / V);
+        *out_v = (uint32_t)(a % V);
+        return ORC_OK;
+    }
+    for (uint32_t d = 0; d < D; d++)
+        if (alpha[c * D + d] != 0 || gamma[c * D + d] != 0) return ORC_FAILED;
+    return ORC_EMPTY;
+}
+
 /* Order-independent 64-bit digest of a whole sketch:
  *   sum over (w,c,d) of mix(alpha ^ rotl(gamma,32) ^ mix(((w*C+c)*D+d) ^ S))
  * modulo 2^64. */

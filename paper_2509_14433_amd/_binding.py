@@ -53,6 +53,7 @@ class cupk_opts(ctypes.Structure):
         ("tile_grid", ctypes.c_uint32),
         ("use_graph", ctypes.c_uint32),
         ("exact", ctypes.c_uint32),
+        ("levels", ctypes.c_uint32),
     ]
 
 
@@ -62,7 +63,9 @@ class cupk_counters_t(ctypes.Structure):
         "slabs_reduced", "sample_failed", "scatter_launches")] + [
         ("scatter_ms", ctypes.c_double), ("bin_ms", ctypes.c_double),
         ("host_wait_ms", ctypes.c_double), ("host_flags_ms", ctypes.c_double),
-        ("host_rounds_ms", ctypes.c_double), ("reverts", ctypes.c_uint64)]
+        ("host_rounds_ms", ctypes.c_double), ("reverts", ctypes.c_uint64),
+        ("level_passes", ctypes.c_uint64), ("level_repairs", ctypes.c_uint64),
+        ("level_failed", ctypes.c_uint64)]
 
 
 class cupk_serve_opts(ctypes.Structure):
@@ -110,6 +113,7 @@ def _load():
         "cupk_num_components": (ctypes.c_int, [p, ctypes.POINTER(u64)]),
         "cupk_forest_edges": (ctypes.c_int, [p, p, p, sz, ctypes.POINTER(sz)]),
         "cupk_component_labels": (ctypes.c_int, [p, p]),
+        "cupk_level_forest_edges": (ctypes.c_int, [p, u32, p, p, sz, ctypes.POINTER(sz)]),
         "cupk_counters": (ctypes.c_int, [p, ctypes.POINTER(cupk_counters_t)]),
         "cupk_sync": (ctypes.c_int, [p]),
         "cupk_autotune": (ctypes.c_int, [p, p, sz, ctypes.POINTER(cupk_tune_result)]),
@@ -165,7 +169,8 @@ class Context:
 
     def __init__(self, V, C=0, D=0, seed=0, scatter_mode=SCATTER_STAGED, max_batch=0,
                  stream=None, use_torch_memory=True, time_kernels=False, tile_vertices=0,
-                 lds_rows=0, chunk_records=0, tile_grid=0, use_graph=False, exact=False):
+                 lds_rows=0, chunk_records=0, tile_grid=0, use_graph=False, exact=False,
+                 levels=False):
         self._h = None
         self._sk_tensor = None
         opts = cupk_opts()
@@ -178,6 +183,7 @@ class Context:
         opts.tile_grid = tile_grid
         opts.use_graph = 1 if use_graph else 0
         opts.exact = 1 if exact else 0
+        opts.levels = 1 if levels else 0
         torch = _torch()
         if stream is None and torch is not None and torch.cuda.is_available():
             # launch on torch's current stream so that torch-produced device
@@ -313,6 +319,15 @@ class Context:
         u = np.zeros(cap, np.uint32)
         v = np.zeros(cap, np.uint32)
         self._check(lib.cupk_forest_edges(self._h, _ptr(u), _ptr(v), cap, ctypes.byref(n)))
+        return sorted(zip(u[: n.value].tolist(), v[: n.value].tolist()))
+
+    def level_forest_edges(self, level):
+        """Levels mode: edges of the forest of `level` (1..C)."""
+        n = ctypes.c_size_t(0)
+        u = np.zeros(self.V, np.uint32)
+        v = np.zeros(self.V, np.uint32)
+        self._check(lib.cupk_level_forest_edges(self._h, level, _ptr(u), _ptr(v), self.V,
+                                                ctypes.byref(n)))
         return sorted(zip(u[: n.value].tolist(), v[: n.value].tolist()))
 
     def component_labels(self):

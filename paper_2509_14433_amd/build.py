@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libcupk.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "api.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "levels.cpp", "serve.cpp"]
 # Packed FP32 instructions are switched off for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,

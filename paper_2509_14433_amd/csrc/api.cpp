@@ -26,28 +26,15 @@
 #include <string>
 #include <vector>
 
-#include "cupk.h"
-#include "forest.hpp"
-#include "kernels.hpp"
-#include "serve.hpp"
+#include "context.hpp"
+#include "levels.hpp"
 
 using namespace cupk;
 
 namespace {
 
-double now_ms()
-{
-    return std::chrono::duration<double, std::milli>(
-               std::chrono::steady_clock::now().time_since_epoch())
-        .count();
-}
-
 // Message of the last failed cupk_sketch_init (no context survives it).
 thread_local std::string g_init_error;
-
-constexpr uint32_t kRedChunk = 32;          // members per reduction work item
-constexpr size_t kMaxBatchPerLaunch = 1u << 28;
-constexpr int kTimerRing = 64;
 
 // SplitMix64 (Steele, Lea, Flood 2014): state += golden gamma, then the
 // Stafford "Mix13" finalizer.
@@ -65,172 +52,9 @@ uint32_t ceil_log2(uint32_t V)
     return L < 1 ? 1 : L;
 }
 
-template <class T>
-struct DevBuf {
-    T *p = nullptr;
-    size_t cap = 0;
-};
-template <class T>
-struct HostBuf {
-    T *p = nullptr;
-    size_t cap = 0;
-};
-
 }  // namespace
 
-struct cupk_ctx {
-    uint32_t V = 0, C = 0, D = 0;
-    uint64_t S = 0;
-    uint64_t seeds[64] = {};
-    uint32_t W = 0;  // words per vertex slab = 2*C*D
-    cupk_opts opts = {};
-    hipStream_t s = nullptr, cs = nullptr;
-    bool own_stream = false;
-    hipEvent_t ev_cls = nullptr, ev_hdr = nullptr;
-    struct TimerSlot {
-        hipEvent_t t0, tb, t1;
-        bool busy;
-    };
-    TimerSlot timers[kTimerRing] = {};
-    int timer_head = 0;
-
-    uint64_t *d_sk = nullptr;
-    bool own_sk = false;
-    uint64_t *d_seeds = nullptr;
-    uint32_t *d_lbl = nullptr, *d_par = nullptr;
-    uint32_t *h_lbl = nullptr, *h_par = nullptr;
-    bool forest_dev_stale = false;
-
-    // batch buffers
-    DevBuf<uint64_t> d_upd;
-    HostBuf<uint64_t> h_upd;
-    uint32_t *d_hdr = nullptr, *h_hdr = nullptr;
-    DevBuf<uint32_t> d_fcnt, d_foff;  // flagged updates: per-block counts and offsets,
-    DevBuf<uint64_t> d_fupd, d_oupd;  // per-block regions, the compacted ordered list
-    HostBuf<uint64_t> h_fupd;
-    DevBuf<uint32_t> d_fpos, d_opos;  // positions of flagged updates (exact mode)
-    HostBuf<uint32_t> h_fpos;
-
-    // staged scatter
-    uint32_t tile_shift = 5, rows = 8, chunk = 4096, ntiles = 0, tile_grid = 0;
-    DevBuf<uint32_t> d_tcnt, d_toff, d_tcur, d_items;
-    DevBuf<uint64_t> d_bins;
-    uint32_t *d_nitems = nullptr;
-
-    // reductions / samples
-    DevBuf<uint32_t> d_ridx, d_ritems;
-    HostBuf<uint32_t> h_ridx, h_ritems;
-    DevBuf<uint64_t> d_sig[2];
-    DevBuf<int32_t> d_res;
-    HostBuf<int32_t> h_res;
-    DevBuf<uint64_t> d_tmp;
-    uint64_t *d_misc = nullptr, *h_misc = nullptr;
-    BatchDesc *d_desc = nullptr, *h_desc = nullptr;
-
-    // captured step (use_graph): classify + header copy, bin, tile
-    hipStream_t gs = nullptr;  // capture stream
-    hipGraphExec_t gx_cls = nullptr, gx_bin = nullptr, gx_tile = nullptr;
-    uint32_t graph_cap = 0;    // batch capacity the graphs were captured for
-    size_t batch_cap = 0;      // updates per batch every batch buffer holds
-
-
-    int device = 0;
-    bool trace = false;  // CUPK_TRACE=1: per-batch host timings on stderr
-    std::unique_ptr<Server> server;
-    std::vector<int32_t> round_gmap;  // label -> round group, -1 elsewhere
-    Forest forest;
-    cupk_counters_t ctr = {};
-    std::string err;
-
-    int fail(hipError_t e, const char *what, int line)
-    {
-        char buf[256];
-        snprintf(buf, sizeof buf, "%s failed at api.cpp:%d: %s", what, line, hipGetErrorString(e));
-        err = buf;
-        return e == hipErrorOutOfMemory ? CUPK_ENOMEM : CUPK_EDEVICE;
-    }
-    int invalid(const char *why)
-    {
-        err = why;
-        return CUPK_EINVAL;
-    }
-};
-
-#define HIPCHK(x)                                                   \
-    do {                                                            \
-        hipError_t e_ = (x);                                        \
-        if (e_ != hipSuccess) return ctx->fail(e_, #x, __LINE__);   \
-    } while (0)
-
-// No C++ exception crosses the C ABI: a failed host allocation inside an
-// entry point becomes CUPK_ENOMEM with a message.
-template <class F>
-int guarded(cupk_ctx *ctx, F &&f)
-{
-    try {
-        return f();
-    } catch (const std::bad_alloc &) {
-        ctx->err = "host memory allocation failed";
-        return CUPK_ENOMEM;
-    } catch (const std::length_error &) {
-        ctx->err = "host allocation too large";
-        return CUPK_ENOMEM;
-    } catch (const std::exception &e) {
-        ctx->err = e.what();
-        return CUPK_EDEVICE;
-    }
-}
-
-namespace {
-
-template <class T>
-hipError_t grow(DevBuf<T> &b, size_t need)
-{
-    if (need <= b.cap) return hipSuccess;
-    size_t cap = std::max(need, 2 * b.cap);
-    if (b.p) {
-        hipError_t e = hipFree(b.p);
-        b.p = nullptr;
-        b.cap = 0;
-        if (e != hipSuccess) return e;
-    }
-    hipError_t e = hipMalloc((void **)&b.p, cap * sizeof(T));
-    if (e != hipSuccess) return e;
-    b.cap = cap;
-    return hipSuccess;
-}
-
-template <class T>
-hipError_t grow(HostBuf<T> &b, size_t need)
-{
-    if (need <= b.cap) return hipSuccess;
-    size_t cap = std::max(need, 2 * b.cap);
-    if (b.p) {
-        hipError_t e = hipHostFree(b.p);
-        b.p = nullptr;
-        b.cap = 0;
-        if (e != hipSuccess) return e;
-    }
-    hipError_t e = hipHostMalloc((void **)&b.p, cap * sizeof(T), hipHostMallocDefault);
-    if (e != hipSuccess) return e;
-    b.cap = cap;
-    return hipSuccess;
-}
-
-template <class T>
-void release(DevBuf<T> &b)
-{
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.cap = 0;
-}
-template <class T>
-void release(HostBuf<T> &b)
-{
-    if (b.p) (void)hipHostFree(b.p);
-    b.p = nullptr;
-    b.cap = 0;
-}
+namespace cupk {
 
 void drop_graphs(cupk_ctx *ctx);
 
@@ -535,6 +359,17 @@ bool apply_flags(cupk_ctx *ctx, uint32_t k0, uint32_t k1, bool all_inserts)
 {
     Forest &F = ctx->forest;
     const uint64_t *upd = ctx->h_fupd.p;
+    if (ctx->levels) {
+        // the hierarchy links only through its restoration passes
+        for (uint32_t k = k0; k < k1; k++) {
+            const uint64_t p = upd[k];
+            if ((p >> 63) == 0) continue;
+            uint32_t a = (uint32_t)p, b = (uint32_t)(p >> 32) & 0x7fffffffu;
+            if (a > b) std::swap(a, b);
+            levels_delete(ctx, a, b);
+        }
+        return false;
+    }
     bool done = false;
     for (uint32_t k = k0; k < k1; k++) {
         if (all_inserts && F.n_trees() == 1) {
@@ -796,7 +631,7 @@ int walk_pass(cupk_ctx *ctx, uint32_t n, bool exact, uint32_t *cut_pos, uint32_t
     *nflag_out = nflag;
     if (cut_pos) *cut_pos = UINT32_MAX;
     double tcopy = t1;
-    if (nflag) {
+    if (nflag && !(ctx->levels && nflag_del == 0)) {
         // pack the per-block regions into one ordered list (copy stream,
         // already ordered after the classify kernel), then fetch and walk it
         // in growing chunks: the walk may stop early
@@ -852,7 +687,7 @@ int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
         rc = walk_pass(ctx, n, false, nullptr, nullptr, nullptr, &nflag, &tw, &tc);
         if (rc != CUPK_OK) return rc;
         const double t2 = now_ms();
-        rc = run_rounds(ctx);
+        rc = ctx->levels ? levels_restore(ctx) : run_rounds(ctx);
         const double t3 = now_ms();
         ctx->ctr.host_rounds_ms += t3 - t2;
         if (ctx->trace)
@@ -925,6 +760,7 @@ int connected_impl(cupk_ctx *ctx, uint32_t u, uint32_t v)
 void destroy(cupk_ctx *ctx)
 {
     ctx->server.reset();
+    levels_release(ctx);
     if (ctx->s) (void)hipStreamSynchronize(ctx->s);
     if (ctx->cs) (void)hipStreamSynchronize(ctx->cs);
     if (ctx->own_sk && ctx->d_sk) (void)hipFree(ctx->d_sk);
@@ -1013,6 +849,8 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     if (opts) ctx->opts = *opts;
     else ctx->opts.scatter_mode = CUPK_SCATTER_STAGED;
     if (ctx->opts.scatter_mode > CUPK_SCATTER_STAGED) return ctx->invalid("unknown scatter_mode");
+    if (ctx->opts.levels && ctx->opts.exact)
+        return ctx->invalid("levels and exact modes do not combine");
     uint64_t st = ctx->S;
     for (uint32_t c = 0; c < C; c++) {
         st += 0x9E3779B97F4A7C15ull;
@@ -1061,6 +899,10 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     HIPCHK(hipMalloc((void **)&ctx->d_misc, 64));
     HIPCHK(hipHostMalloc((void **)&ctx->h_misc, 64, hipHostMallocDefault));
     ctx->forest.init(V, ctx->h_lbl, ctx->h_par);
+    if (ctx->opts.levels) {
+        int rc = levels_init(ctx);
+        if (rc != CUPK_OK) return rc;
+    }
     ctx->forest_dev_stale = true;
 
     // staged scatter geometry: LDS delta of `rows` depth rows x C columns x
@@ -1313,6 +1155,24 @@ int cupk_forest_edges(cupk_ctx *ctx, uint32_t *u, uint32_t *v, size_t cap, size_
     });
 }
 
+int cupk_level_forest_edges(cupk_ctx *ctx, uint32_t level, uint32_t *u, uint32_t *v, size_t cap,
+                            size_t *n)
+{
+    if (!ctx || !n) return CUPK_EINVAL;
+    return guarded(ctx, [&]() -> int {
+        if (!ctx->levels) return ctx->invalid("not in levels mode");
+        if (level < 1 || level > ctx->levels->top) return ctx->invalid("level out of range");
+        std::vector<uint32_t> eu, ev;
+        levels_edges(ctx, level, eu, ev);
+        *n = eu.size();
+        if (cap < eu.size()) return ctx->invalid("forest edge buffer too small");
+        if (eu.size() && (!u || !v)) return ctx->invalid("null array");
+        std::copy(eu.begin(), eu.end(), u);
+        std::copy(ev.begin(), ev.end(), v);
+        return CUPK_OK;
+    });
+}
+
 int cupk_component_labels(cupk_ctx *ctx, uint32_t *out)
 {
     if (!ctx || !out) return CUPK_EINVAL;
@@ -1387,8 +1247,8 @@ static int time_scatter(cupk_ctx *ctx, const uint64_t *d, uint32_t n, int reps, 
 // samples every vertex sketch in place; round 2 reduces the new supernodes
 // from their vertices, later rounds from the previous round's supernode
 // sketches (each new supernode is a union of previous active ones).
-int static_components(cupk_ctx *ctx, uint32_t *labels, uint32_t *eu, uint32_t *ev,
-                      cupk_static_info *info)
+static int static_components(cupk_ctx *ctx, uint32_t *labels, uint32_t *eu, uint32_t *ev,
+                             cupk_static_info *info)
 {
     const uint32_t V = ctx->V, W = ctx->W;
     std::vector<uint32_t> parent(V), size(V, 1);

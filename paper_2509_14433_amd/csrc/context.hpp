@@ -1,0 +1,213 @@
+// Context of the C ABI and helpers shared by the library's translation
+// units (api.cpp: batches, rounds, ABI; levels.cpp: the multi-level
+// hierarchy).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "cupk.h"
+#include "forest.hpp"
+#include "kernels.hpp"
+#include "serve.hpp"
+
+namespace cupk {
+
+constexpr uint32_t kRedChunk = 32;          // members per reduction work item
+constexpr size_t kMaxBatchPerLaunch = 1u << 28;
+constexpr int kTimerRing = 64;
+
+inline double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+};
+template <class T>
+struct HostBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+};
+
+struct Levels;  // multi-level hierarchy state (levels.cpp)
+
+}  // namespace cupk
+
+struct cupk_ctx {
+    uint32_t V = 0, C = 0, D = 0;
+    uint64_t S = 0;
+    uint64_t seeds[64] = {};
+    uint32_t W = 0;  // words per vertex slab = 2*C*D
+    cupk_opts opts = {};
+    hipStream_t s = nullptr, cs = nullptr;
+    bool own_stream = false;
+    hipEvent_t ev_cls = nullptr, ev_hdr = nullptr;
+    struct TimerSlot {
+        hipEvent_t t0, tb, t1;
+        bool busy;
+    };
+    TimerSlot timers[cupk::kTimerRing] = {};
+    int timer_head = 0;
+
+    uint64_t *d_sk = nullptr;
+    bool own_sk = false;
+    uint64_t *d_seeds = nullptr;
+    uint32_t *d_lbl = nullptr, *d_par = nullptr;
+    uint32_t *h_lbl = nullptr, *h_par = nullptr;
+    bool forest_dev_stale = false;
+
+    // batch buffers
+    cupk::DevBuf<uint64_t> d_upd;
+    cupk::HostBuf<uint64_t> h_upd;
+    uint32_t *d_hdr = nullptr, *h_hdr = nullptr;
+    cupk::DevBuf<uint32_t> d_fcnt, d_foff;  // flagged updates: per-block counts and offsets,
+    cupk::DevBuf<uint64_t> d_fupd, d_oupd;  // per-block regions, the compacted ordered list
+    cupk::HostBuf<uint64_t> h_fupd;
+    cupk::DevBuf<uint32_t> d_fpos, d_opos;  // positions of flagged updates (exact mode)
+    cupk::HostBuf<uint32_t> h_fpos;
+
+    // staged scatter
+    uint32_t tile_shift = 5, rows = 8, chunk = 4096, ntiles = 0, tile_grid = 0;
+    cupk::DevBuf<uint32_t> d_tcnt, d_toff, d_tcur, d_items;
+    cupk::DevBuf<uint64_t> d_bins;
+    uint32_t *d_nitems = nullptr;
+
+    // reductions / samples
+    cupk::DevBuf<uint32_t> d_ridx, d_ritems;
+    cupk::HostBuf<uint32_t> h_ridx, h_ritems;
+    cupk::DevBuf<uint64_t> d_sig[2];
+    cupk::DevBuf<int32_t> d_res;
+    cupk::HostBuf<int32_t> h_res;
+    cupk::DevBuf<uint64_t> d_tmp;
+    uint64_t *d_misc = nullptr, *h_misc = nullptr;
+    cupk::BatchDesc *d_desc = nullptr, *h_desc = nullptr;
+
+    // captured step (use_graph): classify + header copy, bin, tile
+    hipStream_t gs = nullptr;  // capture stream
+    hipGraphExec_t gx_cls = nullptr, gx_bin = nullptr, gx_tile = nullptr;
+    uint32_t graph_cap = 0;    // batch capacity the graphs were captured for
+    size_t batch_cap = 0;      // updates per batch every batch buffer holds
+
+
+    int device = 0;
+    bool trace = false;  // CUPK_TRACE=1: per-batch host timings on stderr
+    std::unique_ptr<cupk::Server> server;
+    std::vector<int32_t> round_gmap;  // label -> round group, -1 elsewhere
+    std::unique_ptr<cupk::Levels> levels;  // multi-level hierarchy (opts.levels)
+    cupk::Forest forest;
+    cupk_counters_t ctr = {};
+    std::string err;
+
+    int fail(hipError_t e, const char *what, int line)
+    {
+        char buf[256];
+        snprintf(buf, sizeof buf, "%s failed at api.cpp:%d: %s", what, line, hipGetErrorString(e));
+        err = buf;
+        return e == hipErrorOutOfMemory ? CUPK_ENOMEM : CUPK_EDEVICE;
+    }
+    int invalid(const char *why)
+    {
+        err = why;
+        return CUPK_EINVAL;
+    }
+};
+
+#define HIPCHK(x)                                                   \
+    do {                                                            \
+        hipError_t e_ = (x);                                        \
+        if (e_ != hipSuccess) return ctx->fail(e_, #x, __LINE__);   \
+    } while (0)
+
+// No C++ exception crosses the C ABI: a failed host allocation inside an
+// entry point becomes CUPK_ENOMEM with a message.
+template <class F>
+inline int guarded(cupk_ctx *ctx, F &&f)
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host memory allocation failed";
+        return CUPK_ENOMEM;
+    } catch (const std::length_error &) {
+        ctx->err = "host allocation too large";
+        return CUPK_ENOMEM;
+    } catch (const std::exception &e) {
+        ctx->err = e.what();
+        return CUPK_EDEVICE;
+    }
+}
+
+namespace cupk {
+
+template <class T>
+inline hipError_t grow(DevBuf<T> &b, size_t need)
+{
+    if (need <= b.cap) return hipSuccess;
+    size_t cap = std::max(need, 2 * b.cap);
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc((void **)&b.p, cap * sizeof(T));
+    if (e != hipSuccess) return e;
+    b.cap = cap;
+    return hipSuccess;
+}
+
+template <class T>
+inline hipError_t grow(HostBuf<T> &b, size_t need)
+{
+    if (need <= b.cap) return hipSuccess;
+    size_t cap = std::max(need, 2 * b.cap);
+    if (b.p) {
+        hipError_t e = hipHostFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipHostMalloc((void **)&b.p, cap * sizeof(T), hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    b.cap = cap;
+    return hipSuccess;
+}
+
+template <class T>
+inline void release(DevBuf<T> &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+template <class T>
+inline void release(HostBuf<T> &b)
+{
+    if (b.p) (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+// Shared by the translation units (api.cpp).
+DevSketch dev_sketch(cupk_ctx *ctx);
+int upload_forest(cupk_ctx *ctx);
+int reduce_and_sample(cupk_ctx *ctx, int slot, const std::vector<uint32_t> &vmem,
+                      const std::vector<uint32_t> &voff, const std::vector<uint32_t> &fmem,
+                      const std::vector<uint32_t> &foff);
+int run_rounds(cupk_ctx *ctx);
+
+}  // namespace cupk

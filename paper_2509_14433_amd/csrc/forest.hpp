@@ -72,6 +72,19 @@ class Forest {
         }
     }
     void clear_dirty(uint32_t label) { dirty_[label] = 0; }
+    // Mark every tree dirty (one pass over the vertices).
+    void mark_all_dirty()
+    {
+        for (uint32_t w = 0; w < V_; w++)
+            if (root_[lbl_[w]] == w) set_dirty(lbl_[w]);
+    }
+    // Forget all dirty marks (forests whose marks nobody reads).
+    void discard_dirty()
+    {
+        for (uint32_t l : dirty_list_) dirty_[l] = 0;
+        dirty_list_.clear();
+    }
+    uint32_t parent(uint32_t w) const { return par_[w]; }
     // Labels currently dirty (deduplicated; stale entries dropped).
     std::vector<uint32_t> dirty_labels()
     {

@@ -795,6 +795,101 @@ hipError_t launch_sample(hipStream_t s, const uint64_t *sig, uint32_t k, uint32_
 }
 
 // ---------------------------------------------------------------------------
+// One-column aggregates for the multi-level hierarchy: set k is reduced over
+// column col[k] only (level col[k]'s sampler).  A wave takes one work item
+// (set, members [b, e)) at a time; lane l < 2D holds word l of the
+// aggregate (depth l/2, alpha or gamma), read from each member's slab with a
+// stride of one bucket row; the result is XORed into out[k*2D + l].
+// ---------------------------------------------------------------------------
+constexpr uint32_t kColThreads = 256;
+
+__global__ __launch_bounds__(kColThreads) void k_reduce_col(
+    const uint64_t *__restrict__ sk, uint32_t C, uint32_t D, const uint32_t *__restrict__ idx,
+    const uint32_t *__restrict__ items, uint32_t nitems, const uint32_t *__restrict__ col,
+    uint64_t *__restrict__ out)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t waves = kColThreads / 64;
+    const uint32_t W2 = 2 * D;
+    for (uint32_t it = blockIdx.x * waves + threadIdx.x / 64; it < nitems;
+         it += gridDim.x * waves) {
+        const uint32_t set = items[3 * it], b = items[3 * it + 1], e = items[3 * it + 2];
+        const uint32_t c = col[set];
+        for (uint32_t l = lane; l < W2; l += 64) {
+            const uint32_t d = l >> 1;
+            uint64_t acc = 0;
+            for (uint32_t m = b; m < e; m++) {
+                const uint64_t w = idx[m];
+                acc ^= sk[((w * D + d) * C + c) * 2 + (l & 1)];
+            }
+            if (acc) gxor(out + (uint64_t)set * W2 + l, acc);
+        }
+    }
+}
+
+hipError_t launch_reduce_col(hipStream_t s, const uint64_t *sk, uint32_t C, uint32_t D,
+                             const uint32_t *idx, const uint32_t *items, uint32_t nitems,
+                             const uint32_t *col, uint64_t *out)
+{
+    if (nitems == 0) return hipSuccess;
+    const uint32_t waves = kColThreads / 64;
+    const uint32_t grid = min((nitems + waves - 1) / waves, 8192u);
+    k_reduce_col<<<grid, kColThreads, 0, s>>>(sk, C, D, idx, items, nitems, col, out);
+    return hipGetLastError();
+}
+
+// Query of one column: a wave per set; lane d checks bucket d of the
+// set's one-column aggregate; the deepest good bucket wins (depths are
+// scanned from D-1 down).
+__global__ __launch_bounds__(kColThreads) void k_sample_col(
+    const uint64_t *__restrict__ agg, uint32_t k, uint32_t V, uint32_t D,
+    const uint32_t *__restrict__ col, const uint64_t *__restrict__ seeds, int32_t *__restrict__ res)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t set = blockIdx.x * (kColThreads / 64) + threadIdx.x / 64;
+    if (set >= k) return;
+    const uint64_t *A = agg + (uint64_t)set * 2 * D;
+    const uint64_t seed = seeds[col[set]];
+    uint64_t a = 0, g = 0;
+    bool good = false;
+    if (lane < D) {
+        a = A[2 * lane];
+        g = A[2 * lane + 1];
+        if (a != 0) {
+            const uint64_t h = mix64(a ^ seed);
+            const uint64_t uu = a / V, vv = a - uu * V;
+            good = h == g && depth_of(h, D) == lane && uu < vv;
+        }
+    }
+    const uint64_t mg = __ballot(good);
+    const uint64_t mz = __ballot((a | g) != 0);
+    const uint32_t top = mg ? 63u - (uint32_t)__builtin_clzll(mg) : 0u;
+    const uint64_t pick = __shfl(a, (int)top);
+    if (lane == 0) {
+        int32_t *r = res + 3 * (uint64_t)set;
+        if (mg) {
+            r[0] = 0;
+            r[1] = (int32_t)(uint32_t)(pick / V);
+            r[2] = (int32_t)(uint32_t)(pick % V);
+        } else {
+            r[0] = mz ? 2 : 1;
+            r[1] = 0;
+            r[2] = 0;
+        }
+    }
+}
+
+hipError_t launch_sample_col(hipStream_t s, const uint64_t *agg, uint32_t k, uint32_t V,
+                             uint32_t D, const uint32_t *col, const uint64_t *seeds,
+                             int32_t *res)
+{
+    if (k == 0) return hipSuccess;
+    const uint32_t waves = kColThreads / 64;
+    k_sample_col<<<(k + waves - 1) / waves, kColThreads, 0, s>>>(agg, k, V, D, col, seeds, res);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Digest: order-independent sum over all buckets of
 // mix(alpha ^ rotl(gamma, 32) ^ mix(canonical_position ^ seed)).
 // ---------------------------------------------------------------------------

@@ -97,4 +97,15 @@ hipError_t launch_digest(hipStream_t s, DevSketch sk, uint64_t master_seed, uint
 hipError_t launch_to_canonical(hipStream_t s, const uint64_t *src, uint32_t C, uint32_t D,
                                uint64_t nv, uint64_t *dst);
 
+// Multi-level hierarchy: reduce set k over column col[k] only (items:
+// (set, begin, end) triples over idx, vertex ids; out: k sets x 2D words,
+// [depth][alpha, gamma], zeroed by the caller), then query each set's one
+// column (res: status, u, v per set, as launch_sample).  D <= 64.
+hipError_t launch_reduce_col(hipStream_t s, const uint64_t *sk, uint32_t C, uint32_t D,
+                             const uint32_t *idx, const uint32_t *items, uint32_t nitems,
+                             const uint32_t *col, uint64_t *out);
+hipError_t launch_sample_col(hipStream_t s, const uint64_t *agg, uint32_t k, uint32_t V,
+                             uint32_t D, const uint32_t *col, const uint64_t *seeds,
+                             int32_t *res);
+
 }  // namespace cupk

@@ -44,6 +44,7 @@ def test_host_only_calls_without_gpu():
     assert cupk.lib.cupk_sketch_init(ctypes.byref(h), 16, 4, 1, 0, None) == cupk.EINVAL
     assert cupk.lib.cupk_connected(None, 0, 1) == cupk.EINVAL
     assert cupk.lib.cupk_static_components(None, None, None, None, None) == cupk.EINVAL
+    assert cupk.lib.cupk_level_forest_edges(None, 1, None, None, 0, None) == cupk.EINVAL
 
 
 def test_packing_format():
