@@ -66,14 +66,14 @@ DEVI void lxor(uint64_t *p, uint64_t v)
 //   delete {u,v} that is a forest edge (par[u]==v or par[v]==u), or with
 //   lbl[u] != lbl[v] (an edge linked earlier in this same batch)
 // Everything else can only touch the sketch.  Block b covers positions
-// [b*4096, (b+1)*4096); each thread issues the loads of all its 16 updates
-// (and their label / parent words) before using any, so one block keeps
-// thousands of loads in flight.  The block writes its flagged updates in
+// [b*4096, (b+1)*4096) with 1024 threads (16 waves, so one block per CU
+// still hides latency); each thread issues the loads of all its 4 updates
+// (and their label / parent words) before using any.  The block writes its flagged updates in
 // stream order into its own region of the flag buffers (same offsets), at
 // positions from one prefix over (step, wave) counts; cnt[b] gets their
 // number.  k_flag_compact later packs the regions into one ordered list.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kClsThreads = 256;
+constexpr uint32_t kClsThreads = 1024;
 constexpr uint32_t kClsPerBlock = 4096;
 constexpr uint32_t kClsPerThread = kClsPerBlock / kClsThreads;
 constexpr uint32_t kClsWaves = kClsThreads / 64;
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(
     }
 }
 
-constexpr uint32_t kFillThreads = 256;
+constexpr uint32_t kFillThreads = 1024;
 constexpr uint32_t kFillPerBlock = 4096;
 constexpr uint32_t kFillPerThread = kFillPerBlock / kFillThreads;
 
