@@ -13,8 +13,11 @@ stream from its start; past its end a fresh context replays it again.
 
 Prints one JSON line: whole-job updates/s, the scatter kernel's roofline
 figures (algorithmic bytes per update = 8 + 64*C over HIP-event kernel
-time), the plain (atomic) kernel's figures, and the CPU oracle timed on a
-bounded sample of the same stream.
+time), the plain (atomic) kernel's figures, components from the final
+sketch alone, the served path (large update requests; the paper's query
+bursts, open and closed loop), and the CPU oracle timed on a bounded sample
+of the same stream.  --workload selects the extra full-size measurements
+of the other workload recipes and modes instead.
 """
 from __future__ import annotations
 
@@ -151,6 +154,56 @@ def static_leg(cupk, torch, packed, sizes, reps=5):
             "components": info["n_components"], "sample_failed": info["sample_failed"],
             "vertex_slabs_per_s": round(2 * V / dt, 1),
             "hbm_bound_ms": round(2 * V * slab / (HBM_PEAK_GBS * 1e9) * 1e3, 5)}
+
+
+def served_bursts_leg(cupk, torch, packed, u, v, d, window=4_000_000, closed=False):
+    """The paper's query pattern through the serving loop (App. C.1): update
+    periods of uniform length in [1000, 2000], each followed by a burst of
+    period/9 connectivity queries on uniform random pairs.  The context
+    first takes the stream up to the last `window` updates as device batches
+    (untimed); the timed part is the window (the deletions, with forest-edge
+    cuts), from host memory.  Latency is per query, submission to answer."""
+    import numpy as np
+    n = len(u)
+    start = n - window
+    ctx = cupk.Context(V, C, D, SEED, max_batch=BATCH)
+    for off in range(0, start, BATCH):
+        ctx.apply_updates_device(packed[off:min(start, off + BATCH)])
+    ctx.sync()
+    ctx.serve_start(max_batch=1 << 16, mem_budget_bytes=16 * 2000 * 8)
+    rng = np.random.default_rng(23)
+    tickets = []
+    i = start
+    nq = 0
+    t0 = time.perf_counter()
+    while i < n:
+        period = int(rng.integers(1000, 2001))
+        e = min(n, i + period)
+        ctx.submit_updates(u[i:e], v[i:e], d[i:e])
+        k = period // 9
+        q = rng.integers(0, V, size=(2, k)).astype(np.uint32)
+        t = ctx.submit_queries(q[0], q[1])[0]
+        if closed:
+            ctx.wait(t)        # one period in flight: latency without queueing
+        else:
+            tickets.append(t)
+        nq += k
+        i = e
+    for t in tickets:
+        ctx.wait(t)
+    dt = time.perf_counter() - t0
+    st = ctx.serve_stats()
+    ctx.serve_stop()
+    ctx.close()
+    return {"value": round(window / dt, 1), "unit": "updates/s",
+            "queries_per_s": round(nq / dt, 1), "queries": st["queries"],
+            "query_p50_us": round(st["query_p50_us"], 1),
+            "query_p99_us": round(st["query_p99_us"], 1),
+            "query_max_us": round(st["query_max_us"], 1), "batches": st["batches"],
+            "setup": f"last {window} updates (the deletions) in periods of U[1000, 2000] "
+                     "updates, each followed by a burst of period/9 queries, host-memory input, "
+                     + ("one period in flight (closed loop)" if closed else
+                        "submitted as fast as admission allows (16 periods of budget)")}
 
 
 def served_leg(cupk, u, v, d, rho=100_000, inflight=4, max_batch=BATCH):
@@ -499,6 +552,10 @@ def main():
         out["served"] = served_leg(cupk, u, v, d)
         out["query_latency_us"] = {"p50": out["served"]["query_p50_us"],
                                    "p99": out["served"]["query_p99_us"]}
+        print("bench: timing served path with query bursts", file=sys.stderr, flush=True)
+        out["served_bursts"] = served_bursts_leg(cupk, torch, packed, u, v, d)
+        out["served_bursts_closed_loop"] = served_bursts_leg(cupk, torch, packed, u, v, d,
+                                                             closed=True)
     if not args.no_cpu:
         print("bench: timing CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(u, v, d, sizes)

@@ -362,6 +362,17 @@ int cupk_submit_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
 /* Submit Connected(u, v). */
 int cupk_submit_query(cupk_ctx *ctx, uint32_t u, uint32_t v, uint64_t *ticket);
 
+/* A burst of n connectivity queries (the paper's streams interleave bursts
+ * of queries between update periods, App. C.1).  The burst is one request:
+ * it observes exactly the updates submitted before it, and its answers
+ * (1 connected, 0 not, < 0 error) are written to out[0..n-1], a host array
+ * the caller keeps alive until cupk_wait on *ticket returns (its result is
+ * CUPK_OK or the first error).  Every query of the burst is counted with
+ * the burst's latency (submission to last answer).
+ * Errors: CUPK_EINVAL (loop not running, an endpoint >= V). */
+int cupk_submit_queries(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v, size_t n,
+                        int32_t *out, uint64_t *ticket);
+
 /* Wait for a ticket; *result = 1/0 for a query, the apply status (0 or a
  * negative error) for an update request.  Each ticket is waited for once. */
 int cupk_wait(cupk_ctx *ctx, uint64_t ticket, int32_t *result);

@@ -121,6 +121,7 @@ def _load():
         "cupk_serve_start": (ctypes.c_int, [p, ctypes.POINTER(cupk_serve_opts)]),
         "cupk_submit_updates": (ctypes.c_int, [p, p, p, p, sz, ctypes.POINTER(u64)]),
         "cupk_submit_query": (ctypes.c_int, [p, u32, u32, ctypes.POINTER(u64)]),
+        "cupk_submit_queries": (ctypes.c_int, [p, p, p, sz, p, ctypes.POINTER(u64)]),
         "cupk_wait": (ctypes.c_int, [p, u64, ctypes.POINTER(i32)]),
         "cupk_serve_stats": (ctypes.c_int, [p, ctypes.POINTER(cupk_serve_stats_t)]),
         "cupk_serve_reset_stats": (ctypes.c_int, [p]),
@@ -173,6 +174,7 @@ class Context:
                  levels=False):
         self._h = None
         self._sk_tensor = None
+        self._keep = {}
         opts = cupk_opts()
         opts.scatter_mode = scatter_mode
         opts.max_batch = max_batch
@@ -388,9 +390,24 @@ class Context:
         self._check(lib.cupk_submit_query(self._h, u, v, ctypes.byref(t)))
         return t.value
 
+    def submit_queries(self, u, v):
+        """Submit a burst of queries; returns (ticket, answers array).  The
+        answers are valid after wait(ticket)."""
+        u = np.ascontiguousarray(u, dtype=np.uint32)
+        v = np.ascontiguousarray(v, dtype=np.uint32)
+        assert u.shape == v.shape
+        out = np.full(u.shape[0], -1, np.int32)
+        t = ctypes.c_uint64(0)
+        self._check(lib.cupk_submit_queries(self._h, _ptr(u), _ptr(v), u.shape[0], _ptr(out),
+                                            ctypes.byref(t)))
+        # the library writes into these arrays until the burst is answered
+        self._keep[t.value] = (u, v, out)
+        return t.value, out
+
     def wait(self, ticket) -> int:
         r = ctypes.c_int32(0)
         self._check(lib.cupk_wait(self._h, ticket, ctypes.byref(r)))
+        self._keep.pop(ticket, None)
         return r.value
 
     def serve_stats(self) -> dict:
@@ -403,3 +420,4 @@ class Context:
 
     def serve_stop(self):
         self._check(lib.cupk_serve_stop(self._h))
+        self._keep.clear()

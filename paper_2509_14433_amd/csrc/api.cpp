@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -106,6 +107,7 @@ struct RoundSet {
     uint32_t label;
     uint32_t minv;
     uint32_t size;
+    bool sampled;  // false: the left-out tree, reduced only to serve as a fragment
 };
 
 // Reduce k sets into d_sig[slot] (internal layout, W words per set) and
@@ -247,11 +249,18 @@ int run_rounds(cupk_ctx *ctx)
         size_t need = 0;
         for (size_t gi = 0; gi < groups.size(); gi++)
             if (gi != skip && !groups[gi].from_frags && lists[gi].empty()) need += groups[gi].size;
+        // The left-out tree is not sampled, but when it merges with sampled
+        // trees the merged tree can be reduced from fragments only if its
+        // sketch is known too.  It is carried along (reduced, not sampled)
+        // when that is cheap: from fragments, or in the same pass over the
+        // labels when it is no larger than the trees collected anyway.
+        bool carry = groups[skip].from_frags || !lists[skip].empty();
         if (need * 4 >= F.V()) {
             std::vector<int32_t> &gmap = ctx->round_gmap;
             if (gmap.size() != F.V()) gmap.assign(F.V(), -1);
+            if (!carry && lists[skip].empty() && groups[skip].size <= need) carry = true;
             for (size_t gi = 0; gi < groups.size(); gi++)
-                if (gi != skip && !groups[gi].from_frags && lists[gi].empty()) {
+                if ((gi != skip || carry) && !groups[gi].from_frags && lists[gi].empty()) {
                     gmap[groups[gi].label] = (int32_t)gi;
                     lists[gi].reserve(groups[gi].size);
                 }
@@ -284,15 +293,16 @@ int run_rounds(cupk_ctx *ctx)
         foff.clear();
         voff.push_back(0);
         foff.push_back(0);
+        if (carry) gord.push_back(skip);
         for (size_t gi : gord)
             if (!groups[gi].from_frags) {
-                nsets.push_back({groups[gi].label, groups[gi].minv, groups[gi].size});
+                nsets.push_back({groups[gi].label, groups[gi].minv, groups[gi].size, gi != skip});
                 vmem.insert(vmem.end(), lists[gi].begin(), lists[gi].end());
                 voff.push_back((uint32_t)vmem.size());
             }
         for (size_t gi : gord)
             if (groups[gi].from_frags) {
-                nsets.push_back({groups[gi].label, groups[gi].minv, groups[gi].size});
+                nsets.push_back({groups[gi].label, groups[gi].minv, groups[gi].size, gi != skip});
                 fmem.insert(fmem.end(), groups[gi].frags.begin(), groups[gi].frags.end());
                 foff.push_back((uint32_t)fmem.size());
             }
@@ -320,7 +330,7 @@ int run_rounds(cupk_ctx *ctx)
                   [&](size_t a, size_t b) { return sets[a].minv < sets[b].minv; });
         bool linked = false, failed = false;
         for (size_t i : ord) {
-            if (res[3 * i] != CUPK_OK) continue;
+            if (!sets[i].sampled || res[3 * i] != CUPK_OK) continue;
             const uint32_t x = (uint32_t)res[3 * i + 1], y = (uint32_t)res[3 * i + 2];
             if (!F.same_tree(x, y)) {
                 F.link(x, y);
@@ -329,6 +339,7 @@ int run_rounds(cupk_ctx *ctx)
             }
         }
         for (size_t i = 0; i < k; i++) {
+            if (!sets[i].sampled) continue;
             const int st = res[3 * i];
             if (st == CUPK_EMPTY) {
                 // a whole component: clean, unless it was merged this round
@@ -355,10 +366,9 @@ int run_rounds(cupk_ctx *ctx)
 // the forest.  Returns true when the rest of the list cannot change the
 // forest: without flagged deletes nothing splits a tree during the walk, so
 // once one tree is left no later insert can link.
-bool apply_flags(cupk_ctx *ctx, uint32_t k0, uint32_t k1, bool all_inserts)
+bool apply_flags(cupk_ctx *ctx, const uint64_t *upd, uint32_t k0, uint32_t k1, bool all_inserts)
 {
     Forest &F = ctx->forest;
-    const uint64_t *upd = ctx->h_fupd.p;
     if (ctx->levels) {
         // the hierarchy links only through its restoration passes
         for (uint32_t k = k0; k < k1; k++) {
@@ -525,6 +535,24 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
         rc = upload_forest(ctx);
         if (rc != CUPK_OK) return rc;
     }
+    const bool graph = ctx->opts.use_graph != 0 && !ctx->opts.exact;
+    ctx->small_pass = !graph && n <= kSmallMax;
+    if (ctx->small_pass) {
+        // two launches and one copy: classify into the result block, copy
+        // header + flags + positions to the host, scatter with device
+        // atomics (the previous small result was read before this pass:
+        // every pass waits for its header or for the whole stream)
+        HIPCHK(launch_small_classify(ctx->s, d_upd, n, ctx->V, ctx->d_lbl, ctx->d_par,
+                                     ctx->d_small, ctx->opts.exact != 0));
+        const size_t bytes = ctx->opts.exact ? sizeof(SmallResult)
+                                             : offsetof(SmallResult, fupd) + (size_t)n * 8;
+        HIPCHK(hipMemcpyAsync(ctx->h_small, ctx->d_small, bytes, hipMemcpyDeviceToHost, ctx->s));
+        HIPCHK(hipEventRecord(ctx->ev_hdr, ctx->s));
+        // the scatter follows the copy: the host walks the flags meanwhile
+        HIPCHK(launch_small_scatter(ctx->s, d_upd, n, dev_sketch(ctx), ctx->d_small));
+        ctx->ctr.scatter_launches++;
+        return CUPK_OK;
+    }
     // the batch descriptor (pinned staging; the previous pass's copy has
     // completed: every pass is followed by a wait for its classify step or
     // for the whole stream)
@@ -532,7 +560,6 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
     ctx->h_desc->n = n;
     HIPCHK(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
                           ctx->s));
-    const bool graph = ctx->opts.use_graph != 0 && !ctx->opts.exact;
     if (graph && (ctx->graph_cap < n || !ctx->gx_cls)) {
         rc = capture_graphs(ctx);
         if (rc != CUPK_OK) return rc;
@@ -587,10 +614,10 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
 // usual; the walk stops before the first delete of a current forest edge
 // and returns its index in *kc.  Returns 0 (list done), 1 (stop: insert-only
 // list and one tree left) or 2 (a cut at *kc).
-int walk_exact(cupk_ctx *ctx, uint32_t k0, uint32_t k1, bool all_inserts, uint32_t *kc)
+int walk_exact(cupk_ctx *ctx, const uint64_t *upd, uint32_t k0, uint32_t k1, bool all_inserts,
+               uint32_t *kc)
 {
     Forest &F = ctx->forest;
-    const uint64_t *upd = ctx->h_fupd.p;
     for (uint32_t k = k0; k < k1; k++) {
         if (all_inserts && F.n_trees() == 1) return 1;
         const uint64_t p = upd[k];
@@ -622,44 +649,52 @@ int walk_pass(cupk_ctx *ctx, uint32_t n, bool exact, uint32_t *cut_pos, uint32_t
     double t1 = now_ms();
     ctx->ctr.host_wait_ms += t1 - t0;
     *t_wait = t1 - t0;
-    if (ctx->h_hdr[HDR_ERR]) {
+    // a small pass left header, flags and positions in one host block
+    const bool small = ctx->small_pass;
+    const uint32_t *hdr = small ? ctx->h_small->hdr : ctx->h_hdr;
+    if (hdr[HDR_ERR]) {
         HIPCHK(hipStreamSynchronize(ctx->s));
         return ctx->invalid("batch holds an update with u == v or an endpoint >= V");
     }
-    const uint32_t nflag = ctx->h_hdr[HDR_NFLAG];
-    const uint32_t nflag_del = ctx->h_hdr[HDR_NFLAG_DEL];
+    const uint32_t nflag = hdr[HDR_NFLAG];
+    const uint32_t nflag_del = hdr[HDR_NFLAG_DEL];
     *nflag_out = nflag;
     if (cut_pos) *cut_pos = UINT32_MAX;
     double tcopy = t1;
+    const uint64_t *fl = small ? ctx->h_small->fupd : ctx->h_fupd.p;
+    const uint32_t *fp = small ? ctx->h_small->fpos : ctx->h_fpos.p;
     if (nflag && !(ctx->levels && nflag_del == 0)) {
         // pack the per-block regions into one ordered list (copy stream,
         // already ordered after the classify kernel), then fetch and walk it
         // in growing chunks: the walk may stop early
         uint32_t *opos = exact ? ctx->d_opos.p : nullptr;
-        HIPCHK(launch_flag_compact(ctx->cs, n, ctx->d_fupd.p, exact ? ctx->d_fpos.p : nullptr,
-                                   ctx->d_fcnt.p, ctx->d_foff.p, ctx->d_oupd.p, opos));
-        uint32_t k0 = 0, step = 1u << 16;
+        if (!small)
+            HIPCHK(launch_flag_compact(ctx->cs, n, ctx->d_fupd.p, exact ? ctx->d_fpos.p : nullptr,
+                                       ctx->d_fcnt.p, ctx->d_foff.p, ctx->d_oupd.p, opos));
+        uint32_t k0 = 0, step = small ? nflag : 1u << 16;
         while (k0 < nflag) {
             const uint32_t m = std::min(step, nflag - k0);
-            HIPCHK(hipMemcpyAsync(ctx->h_fupd.p + k0, ctx->d_oupd.p + k0, (size_t)m * 8,
-                                  hipMemcpyDeviceToHost, ctx->cs));
-            if (exact)
-                HIPCHK(hipMemcpyAsync(ctx->h_fpos.p + k0, opos + k0, (size_t)m * 4,
+            if (!small) {
+                HIPCHK(hipMemcpyAsync(ctx->h_fupd.p + k0, ctx->d_oupd.p + k0, (size_t)m * 8,
                                       hipMemcpyDeviceToHost, ctx->cs));
-            HIPCHK(hipStreamSynchronize(ctx->cs));
+                if (exact)
+                    HIPCHK(hipMemcpyAsync(ctx->h_fpos.p + k0, opos + k0, (size_t)m * 4,
+                                          hipMemcpyDeviceToHost, ctx->cs));
+                HIPCHK(hipStreamSynchronize(ctx->cs));
+            }
             if (k0 == 0) tcopy = now_ms();
             if (exact) {
                 uint32_t kc = 0;
-                const int r = walk_exact(ctx, k0, k0 + m, nflag_del == 0, &kc);
+                const int r = walk_exact(ctx, fl, k0, k0 + m, nflag_del == 0, &kc);
                 if (r == 2) {
-                    const uint64_t p = ctx->h_fupd.p[kc];
-                    *cut_pos = ctx->h_fpos.p[kc];
+                    const uint64_t p = fl[kc];
+                    *cut_pos = fp[kc];
                     *cut_a = std::min((uint32_t)p, (uint32_t)(p >> 32) & 0x7fffffffu);
                     *cut_b = std::max((uint32_t)p, (uint32_t)(p >> 32) & 0x7fffffffu);
                     break;
                 }
                 if (r == 1) break;
-            } else if (apply_flags(ctx, k0, k0 + m, nflag_del == 0)) {
+            } else if (apply_flags(ctx, fl, k0, k0 + m, nflag_del == 0)) {
                 break;
             }
             k0 += m;
@@ -777,6 +812,8 @@ void destroy(cupk_ctx *ctx)
     if (ctx->d_desc) (void)hipFree(ctx->d_desc);
     if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
     if (ctx->d_misc) (void)hipFree(ctx->d_misc);
+    if (ctx->d_small) (void)hipFree(ctx->d_small);
+    if (ctx->h_small) (void)hipHostFree(ctx->h_small);
     if (ctx->h_misc) (void)hipHostFree(ctx->h_misc);
     release(ctx->d_upd);
     release(ctx->h_upd);
@@ -897,6 +934,8 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     HIPCHK(hipMalloc((void **)&ctx->d_desc, sizeof(BatchDesc)));
     HIPCHK(hipHostMalloc((void **)&ctx->h_desc, sizeof(BatchDesc), hipHostMallocDefault));
     HIPCHK(hipMalloc((void **)&ctx->d_misc, 64));
+    HIPCHK(hipMalloc((void **)&ctx->d_small, sizeof(SmallResult)));
+    HIPCHK(hipHostMalloc((void **)&ctx->h_small, sizeof(SmallResult), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&ctx->h_misc, 64, hipHostMallocDefault));
     ctx->forest.init(V, ctx->h_lbl, ctx->h_par);
     if (ctx->opts.levels) {
@@ -1499,6 +1538,16 @@ int cupk_submit_query(cupk_ctx *ctx, uint32_t u, uint32_t v, uint64_t *ticket)
     if (!ctx || !ctx->server || !ticket) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
         return ctx->server->submit_query(u, v, ctx->V, ticket);
+    });
+}
+
+int cupk_submit_queries(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v, size_t n,
+                        int32_t *out, uint64_t *ticket)
+{
+    if (!ctx || !ctx->server || !ticket) return CUPK_EINVAL;
+    if (n && (!u || !v || !out)) return CUPK_EINVAL;
+    return guarded(ctx, [&]() -> int {
+        return ctx->server->submit_queries(u, v, n, out, ctx->V, ticket);
     });
 }
 

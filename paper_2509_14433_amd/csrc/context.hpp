@@ -94,6 +94,8 @@ struct cupk_ctx {
     cupk::HostBuf<int32_t> h_res;
     cupk::DevBuf<uint64_t> d_tmp;
     uint64_t *d_misc = nullptr, *h_misc = nullptr;
+    cupk::SmallResult *d_small = nullptr, *h_small = nullptr;  // small-batch pass results
+    bool small_pass = false;   // the last pass took the small-batch path
     cupk::BatchDesc *d_desc = nullptr, *h_desc = nullptr;
 
     // captured step (use_graph): classify + header copy, bin, tile

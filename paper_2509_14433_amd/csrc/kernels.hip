@@ -216,16 +216,12 @@ hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, uint32_t grid_n
 // column and XOR-ing (x, h) into bucket (c, d) of both endpoints with
 // device-scope atomics (4 per column).  Skipped when the batch was rejected.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_scatter_atomic(const BatchDesc *__restrict__ desc,
-                                                        DevSketch sk,
-                                                        const uint32_t *__restrict__ hdr)
+// All C columns of one update into both endpoints, with device atomics.
+DEVI void scatter_one(const DevSketch &sk, uint64_t p)
 {
-    if (hdr[HDR_ERR]) return;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= desc->n) return;
     uint32_t u, v;
     bool del;
-    unpack(desc->upd[i], sk.V, u, v, del);
+    unpack(p, sk.V, u, v, del);
     const uint64_t x = (uint64_t)u * sk.V + v;
     const uint64_t ru = (uint64_t)u * sk.D, rv = (uint64_t)v * sk.D;
     for (uint32_t c = 0; c < sk.C; c++) {
@@ -238,6 +234,131 @@ __global__ __launch_bounds__(256) void k_scatter_atomic(const BatchDesc *__restr
         gxor(bv, x);
         gxor(bv + 1, h);
     }
+}
+
+__global__ __launch_bounds__(256) void k_scatter_atomic(const BatchDesc *__restrict__ desc,
+                                                        DevSketch sk,
+                                                        const uint32_t *__restrict__ hdr)
+{
+    if (hdr[HDR_ERR]) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= desc->n) return;
+    scatter_one(sk, desc->upd[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Small batches (n <= kSmallMax): one block classifies the whole batch and
+// writes the header and the flagged updates (with positions) straight into
+// one result block, ready for a single copy to the host; a second kernel
+// scatters with device atomics.  The batch comes in the arguments, so no
+// descriptor copy, header clearing, compaction or binning is needed: the
+// latency of a small batch is two launches and one copy.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSmallThreads = 1024;
+constexpr uint32_t kSmallPerThread = kSmallMax / kSmallThreads;
+static_assert(kSmallPerThread * (kSmallThreads / 64) == 64, "one wave scans the step counts");
+
+__global__ __launch_bounds__(kSmallThreads) void k_small_classify(
+    const uint64_t *__restrict__ upd, uint32_t n, uint32_t V, const uint32_t *__restrict__ lbl,
+    const uint32_t *__restrict__ par, SmallResult *__restrict__ out, uint32_t with_pos)
+{
+    __shared__ uint32_t pre[64 + 1];
+    __shared__ uint32_t s_bad, s_del;
+    const uint32_t lane = __lane_id();
+    const uint32_t wid = threadIdx.x / 64;
+    constexpr uint32_t kWaves = kSmallThreads / 64;
+    if (threadIdx.x == 0) {
+        s_bad = 0;
+        s_del = 0;
+    }
+    uint64_t p[kSmallPerThread];
+    uint32_t fl = 0, bad = 0, ndel = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kSmallPerThread; k++) {
+        const uint32_t i = k * kSmallThreads + threadIdx.x;
+        p[k] = i < n ? upd[i] : 0;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kSmallPerThread; k++) {
+        const uint32_t i = k * kSmallThreads + threadIdx.x;
+        if (i >= n) continue;
+        uint32_t u, v;
+        bool del;
+        if (!unpack(p[k], V, u, v, del)) {
+            bad = 1;
+            continue;
+        }
+        bool f = lbl[u] != lbl[v];
+        if (!f && del) f = par[u] == v || par[v] == u;
+        if (f) {
+            fl |= 1u << k;
+            ndel += del ? 1u : 0u;
+        }
+    }
+    __syncthreads();  // s_bad, s_del cleared
+    if (bad) atomicOr(&s_bad, 1u);
+    if (ndel) atomicAdd(&s_del, ndel);
+#pragma unroll
+    for (uint32_t k = 0; k < kSmallPerThread; k++) {
+        const uint64_t m = __ballot((fl >> k) & 1u);
+        if (lane == 0) pre[k * kWaves + wid] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t x = pre[threadIdx.x];
+        uint32_t inc = x;
+#pragma unroll
+        for (uint32_t o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        pre[threadIdx.x] = inc - x;
+        if (threadIdx.x == 63) pre[64] = inc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kSmallPerThread; k++) {
+        const bool f = (fl >> k) & 1u;
+        const uint64_t m = __ballot(f);
+        if (f) {
+            const uint32_t q = pre[k * kWaves + wid] + lanes_below(m);
+            out->fupd[q] = p[k];
+            if (with_pos) out->fpos[q] = k * kSmallThreads + threadIdx.x;
+        }
+    }
+    if (threadIdx.x == 0) {
+        out->hdr[HDR_ERR] = s_bad;
+        out->hdr[HDR_NFLAG] = s_bad ? 0u : pre[64];
+        out->hdr[HDR_NFLAG_DEL] = s_bad ? 0u : s_del;
+        out->hdr[3] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_small_scatter(const uint64_t *__restrict__ upd,
+                                                       uint32_t n, DevSketch sk,
+                                                       const SmallResult *__restrict__ res)
+{
+    if (res->hdr[HDR_ERR]) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    scatter_one(sk, upd[i]);
+}
+
+hipError_t launch_small_classify(hipStream_t s, const uint64_t *upd, uint32_t n, uint32_t V,
+                                 const uint32_t *lbl, const uint32_t *par, SmallResult *out,
+                                 bool with_pos)
+{
+    if (n == 0 || n > kSmallMax) return hipErrorInvalidValue;
+    k_small_classify<<<1, kSmallThreads, 0, s>>>(upd, n, V, lbl, par, out, with_pos ? 1u : 0u);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_scatter(hipStream_t s, const uint64_t *upd, uint32_t n, DevSketch sk,
+                                const SmallResult *res)
+{
+    if (n == 0 || n > kSmallMax) return hipErrorInvalidValue;
+    k_small_scatter<<<(n + 255) / 256, 256, 0, s>>>(upd, n, sk, res);
+    return hipGetLastError();
 }
 
 hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, uint32_t grid_n,

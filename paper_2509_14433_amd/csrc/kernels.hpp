@@ -58,6 +58,26 @@ hipError_t launch_flag_compact(hipStream_t s, uint32_t n, const uint64_t *fupd,
                                const uint32_t *fpos, const uint32_t *fcnt, uint32_t *foff,
                                uint64_t *oupd, uint32_t *opos);
 
+// Small batches: header, flagged updates (stream order) and their positions
+// of one batch of at most kSmallMax updates, written by one kernel for one
+// copy to the host.
+constexpr uint32_t kSmallMax = 4096;
+struct SmallResult {
+    uint32_t hdr[HDR_WORDS];
+    uint64_t fupd[kSmallMax];
+    uint32_t fpos[kSmallMax];
+};
+// Classify (one block) a batch of 1..kSmallMax packed updates given in the
+// arguments into `out` (with_pos: also positions), then scatter it with
+// device atomics; the scatter does nothing if an update was invalid
+// (res->hdr[HDR_ERR] set).  The two are separate so that the result can be
+// copied to the host before the scatter runs.
+hipError_t launch_small_classify(hipStream_t s, const uint64_t *upd, uint32_t n, uint32_t V,
+                                 const uint32_t *lbl, const uint32_t *par, SmallResult *out,
+                                 bool with_pos);
+hipError_t launch_small_scatter(hipStream_t s, const uint64_t *upd, uint32_t n, DevSketch sk,
+                                const SmallResult *res);
+
 // Plain scatter: device-scope atomic XOR of (x, h) into both endpoints.
 hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, uint32_t grid_n,
                                  DevSketch sk, const uint32_t *hdr);

@@ -196,12 +196,15 @@ int levels_restore(cupk_ctx *ctx)
     uint32_t lo = 0;
     while (lo < L.top) {
         ctx->ctr.level_passes++;
+        const double t0 = now_ms();
         cands.clear();
         mem.clear();
         gather(ctx, lo, cands, mem);
         if (cands.empty()) break;
+        const double t1 = now_ms();
         int rc = query_cands(ctx, cands, mem);
         if (rc != CUPK_OK) return rc;
+        const double t2 = now_ms();
         const int32_t *res = ctx->h_res.p;
         uint32_t found = UINT32_MAX;
         for (size_t j = 0; j < cands.size(); j++)
@@ -236,6 +239,11 @@ int levels_restore(cupk_ctx *ctx)
             ctx->ctr.links++;
             ctx->ctr.level_repairs++;
         }
+        if (ctx->trace)
+            fprintf(stderr,
+                    "cupk   levels pass lo=%u level=%u cands=%zu members=%zu gather=%.3f "
+                    "gpu=%.3f repairs=%.3f ms\n",
+                    lo, i, cands.size(), mem.size(), t1 - t0, t2 - t1, now_ms() - t2);
         lo = i + 1;
     }
     for (uint32_t j = 1; j < L.top; j++) L.lv[j]->F.discard_dirty();

@@ -46,6 +46,9 @@ struct Server::Req {
     uint64_t ticket;
     bool query;
     uint32_t qu, qv;
+    bool burst = false;            // a burst of queries (bu, bv; answers go to bout)
+    std::vector<uint32_t> bu, bv;
+    int32_t *bout = nullptr;
     std::vector<uint64_t> packed;  // update requests: packed updates
     size_t done_upd = 0;           // updates of this request already applied
     double t_submit;
@@ -114,6 +117,28 @@ int Server::submit_query(uint32_t u, uint32_t v, uint32_t V, uint64_t *ticket)
     *ticket = r->ticket;
     queue_.push_back(std::move(r));
     stats_.queries++;
+    g.unlock();
+    cv_work_.notify_one();
+    return CUPK_OK;
+}
+
+int Server::submit_queries(const uint32_t *u, const uint32_t *v, size_t n, int32_t *out,
+                           uint32_t V, uint64_t *ticket)
+{
+    for (size_t i = 0; i < n; i++)
+        if (u[i] >= V || v[i] >= V) return CUPK_EINVAL;
+    auto r = std::make_unique<Req>();
+    r->query = true;
+    r->burst = true;
+    r->bu.assign(u, u + n);
+    r->bv.assign(v, v + n);
+    r->bout = out;
+    std::unique_lock<std::mutex> g(m_);
+    r->ticket = next_ticket_++;
+    r->t_submit = now_us();
+    *ticket = r->ticket;
+    queue_.push_back(std::move(r));
+    stats_.queries += n;
     g.unlock();
     cv_work_.notify_one();
     return CUPK_OK;
@@ -208,9 +233,22 @@ void Server::loop()
                     queue_.pop_front();
                     continue;
                 }
-                const int c = conn_(ctx_, r->qu, r->qv);
-                results_[r->ticket] = c;
-                latencies_.push_back(now_us() - r->t_submit);
+                if (r->burst) {
+                    // a burst: every answer, then one completion
+                    int c = CUPK_OK;
+                    for (size_t i = 0; i < r->bu.size(); i++) {
+                        const int a = conn_(ctx_, r->bu[i], r->bv[i]);
+                        r->bout[i] = a;
+                        if (a < 0) c = a;
+                    }
+                    results_[r->ticket] = c;
+                    const double lat = now_us() - r->t_submit;
+                    for (size_t i = 0; i < r->bu.size(); i++) latencies_.push_back(lat);
+                } else {
+                    const int c = conn_(ctx_, r->qu, r->qv);
+                    results_[r->ticket] = c;
+                    latencies_.push_back(now_us() - r->t_submit);
+                }
                 queue_.pop_front();
             }
             pending_bytes_ -= freed;

@@ -28,6 +28,8 @@ class Server {
     int submit_updates(const uint32_t *u, const uint32_t *v, const uint8_t *del, size_t n,
                        uint32_t V, uint64_t *ticket);
     int submit_query(uint32_t u, uint32_t v, uint32_t V, uint64_t *ticket);
+    int submit_queries(const uint32_t *u, const uint32_t *v, size_t n, int32_t *out, uint32_t V,
+                       uint64_t *ticket);
     int wait(uint64_t ticket, int32_t *result);
     void get_stats(cupk_serve_stats_t *out);
     void reset_stats();

@@ -192,3 +192,43 @@ def test_memory_admission(cupk):
     assert st["updates"] == 600
     ctx.close()
     ctx2.close()
+
+
+@pytest.mark.parametrize("mode", ["single", "exact", "levels"])
+def test_query_bursts(cupk, mode):
+    # the paper's query pattern: update periods of random length, each
+    # followed by a burst of about period/9 queries; every answer of a burst
+    # reflects exactly the updates submitted before it, in every mode
+    V, C, D, S = 300, 9, 18, 78
+    u, v, d = streamgen.er_standard(V, 0.03, 0.6, 4)
+    rng = np.random.default_rng(2)
+    live = set()
+    ctx = cupk.Context(V, C, D, S, exact=(mode == "exact"), levels=(mode == "levels"))
+    ctx.serve_start(max_batch=1 << 16, mem_budget_bytes=1 << 20)
+    i, n = 0, len(u)
+    bursts = []
+    while i < n:
+        period = int(rng.integers(100, 200))
+        e = min(n, i + period)
+        ctx.submit_updates(u[i:e], v[i:e], d[i:e])
+        for a, b, x in zip(u[i:e].tolist(), v[i:e].tolist(), d[i:e].tolist()):
+            (live.remove if x else live.add)((a, b))
+        i = e
+        k = max(1, period // 9)
+        qa = rng.integers(0, V, k).astype(np.uint32)
+        qb = rng.integers(0, V, k).astype(np.uint32)
+        eu = np.array([q[0] for q in live], np.uint32)
+        ev = np.array([q[1] for q in live], np.uint32)
+        lab = oracle.components_truth(V, eu, ev)
+        want = [int(lab[a] == lab[b]) for a, b in zip(qa.tolist(), qb.tolist())]
+        t, out = ctx.submit_queries(qa, qb)
+        bursts.append((t, out, want))
+    print(f"bursts mode={mode} n={n} bursts={len(bursts)}", flush=True)
+    for t, out, want in bursts:
+        assert ctx.wait(t) == 0
+        assert out.tolist() == want
+    st = ctx.serve_stats()
+    ctx.serve_stop()
+    assert st["queries"] == sum(len(w) for _, _, w in bursts)
+    assert st["query_p99_us"] >= st["query_p50_us"] > 0
+    ctx.close()
