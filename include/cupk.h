@@ -18,6 +18,11 @@
  *     (App. A.1.1, AGM Boruvka; Alg. 1 restoration loop) and connectivity
  *     queries are answered from the forest (Sec. 2.1 problem statement,
  *     Sec. 4.1 query tree).
+ * Modes beyond that path (cupk_opts): exact per-update semantics inside
+ * batches (speculative buffering, Sec. 4.3), the multi-level hierarchy of
+ * cutsets (Sec. 2.2.2, Alg. 1), and, as separate calls, components of the
+ * whole graph from the sketch alone (App. A.1.1) and a serving loop with
+ * query bursts.
  *
  * Sketch definition (bit-exact contract with the tests' CPU oracle):
  *   seed_c  = c-th output of SplitMix64 from state `seed`

@@ -44,10 +44,14 @@ class Forest {
         root_.resize(V);
         dirty_.assign(V, 0);
         free_.clear();
+        live_.resize(V);
+        live_pos_.resize(V);
         for (uint32_t w = 0; w < V; w++) {
             lbl_[w] = w;
             par_[w] = kNone;
             root_[w] = w;
+            live_[w] = w;
+            live_pos_[w] = w;
         }
         n_trees_ = V;
         n_edges_ = 0;
@@ -85,6 +89,8 @@ class Forest {
         dirty_list_.clear();
     }
     uint32_t parent(uint32_t w) const { return par_[w]; }
+    // Labels of the current trees (one each, in no particular order).
+    const std::vector<uint32_t> &live_labels() const { return live_; }
     // Labels currently dirty (deduplicated; stale entries dropped).
     std::vector<uint32_t> dirty_labels()
     {
@@ -136,6 +142,7 @@ class Forest {
         if (dirty_[la]) set_dirty(lb);
         dirty_[la] = 0;
         free_.push_back(la);
+        live_remove(la);
         n_trees_--;
         n_edges_++;
         return lb;
@@ -204,6 +211,7 @@ class Forest {
                     // piece i is complete: it takes a fresh label
                     const uint32_t nl = free_.back();
                     free_.pop_back();
+                    live_add(nl);
                     for (uint32_t x : pq_[i]) lbl_[x] = nl;
                     size_[nl] = (uint32_t)pq_[i].size();
                     root_[nl] = pq_[i][0];
@@ -279,6 +287,18 @@ class Forest {
     }
     // children of a vertex form a doubly linked list (insert and remove in
     // O(1), one memory access per child when walking it)
+    void live_add(uint32_t l)
+    {
+        live_pos_[l] = (uint32_t)live_.size();
+        live_.push_back(l);
+    }
+    void live_remove(uint32_t l)
+    {
+        const uint32_t i = live_pos_[l], last = live_.back();
+        live_[i] = last;
+        live_pos_[last] = i;
+        live_.pop_back();
+    }
     void add_kid(uint32_t p, uint32_t c)
     {
         const uint32_t f = first_kid_[p];
@@ -306,6 +326,7 @@ class Forest {
     std::vector<uint8_t> dirty_;   // by label
     std::vector<uint32_t> dirty_list_;
     std::vector<uint32_t> free_;
+    std::vector<uint32_t> live_, live_pos_;  // labels in use, and each one's slot
     std::vector<uint32_t> queue_;
     std::vector<std::pair<uint32_t, uint32_t>> pending_;  // (old label, top) per removal
     std::vector<std::vector<uint32_t>> pq_;              // per-piece search queues

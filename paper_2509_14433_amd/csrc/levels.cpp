@@ -75,28 +75,28 @@ struct Cand {
 void gather(cupk_ctx *ctx, uint32_t lo, std::vector<Cand> &cands, std::vector<uint32_t> &mem)
 {
     Levels &L = *ctx->levels;
-    const uint32_t V = ctx->V;
     for (uint32_t i = lo; i < L.top; i++) {
         Forest &N = level_forest(ctx, i + 1);
+        const size_t c0 = cands.size();
         if (i == 0) {
-            for (uint32_t w = 0; w < V; w++)
-                if (N.tree_size(N.label(w)) == 1) {
+            // singletons of F_1
+            for (uint32_t l : N.live_labels())
+                if (N.tree_size(l) == 1) {
+                    const uint32_t w = N.tree_root(l);
                     const uint32_t mb = (uint32_t)mem.size();
                     mem.push_back(w);
                     cands.push_back({0, w, 1, mb, mb + 1});
                 }
-            continue;
-        }
-        Forest &F = L.lv[i]->F;
-        const size_t c0 = cands.size();
-        for (uint32_t w = 0; w < V; w++) {
-            const uint32_t l = F.label(w);
-            if (F.tree_root(l) != w) continue;
-            const uint32_t sz = F.tree_size(l);
-            if (N.tree_size(N.label(w)) != sz) continue;
-            const uint32_t mb = (uint32_t)mem.size();
-            const uint32_t mn = F.collect(l, mem);
-            cands.push_back({i, mn, sz, mb, (uint32_t)mem.size()});
+        } else {
+            Forest &F = L.lv[i]->F;
+            for (uint32_t l : F.live_labels()) {
+                const uint32_t w = F.tree_root(l);
+                const uint32_t sz = F.tree_size(l);
+                if (N.tree_size(N.label(w)) != sz) continue;
+                const uint32_t mb = (uint32_t)mem.size();
+                const uint32_t mn = F.collect(l, mem);
+                cands.push_back({i, mn, sz, mb, (uint32_t)mem.size()});
+            }
         }
         std::sort(cands.begin() + (long)c0, cands.end(),
                   [](const Cand &a, const Cand &b) { return a.minv < b.minv; });

@@ -61,6 +61,13 @@ static int check(Forest &F, Naive &N, uint64_t step)
     if (fe != ne) return fail("edge set", step);
     for (auto &e : ne)
         if (!F.is_edge(e.first, e.second)) return fail("is_edge", step);
+    // the live label list names every tree once
+    {
+        std::set<uint32_t> labels_of_vertices, live(F.live_labels().begin(), F.live_labels().end());
+        for (uint32_t w = 0; w < N.V; w++) labels_of_vertices.insert(F.label(w));
+        if (live.size() != F.live_labels().size()) return fail("live labels repeat", step);
+        if (live != labels_of_vertices) return fail("live labels", step);
+    }
     // every tree: collect() returns exactly its vertices and the minimum
     std::set<uint32_t> seen_labels;
     for (uint32_t w = 0; w < N.V; w++) {

@@ -286,3 +286,25 @@ def test_graph_replay_ragged_batches(cupk, mode):
     _assert_same_sketch(ctx, ref)
     assert ctx.forest_edges() == fr.forest_edges()
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_small_batch_boundary(cupk, mode):
+    # batches just below, at and above the small-batch limit (4096), and a
+    # batch of one, in sequence: both batch paths must agree with the oracle
+    V, C, D, S = 700, 10, 20, 0x5EED77
+    u, v, d = streamgen.er_standard(V, 0.05, 0.5, 12)
+    sizes = [4095, 4096, 4097, 1, 3000]
+    assert len(u) >= sum(sizes)
+    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    ref = oracle.Sketch(V, C, D, S)
+    fr = oracle.ForestReplay(ref)
+    off = 0
+    for sz in sizes + [len(u) - sum(sizes)]:
+        print(f"boundary batch {off}:{off + sz} mode={mode}", flush=True)
+        ctx.apply_updates(u[off:off + sz], v[off:off + sz], d[off:off + sz])
+        fr.apply_batch(u[off:off + sz], v[off:off + sz], d[off:off + sz])
+        off += sz
+    _assert_same_sketch(ctx, ref)
+    assert ctx.forest_edges() == fr.forest_edges()
+    ctx.close()
