@@ -185,7 +185,9 @@ int reduce_and_sample(cupk_ctx *ctx, int slot, const std::vector<uint32_t> &vmem
 int run_rounds(cupk_ctx *ctx)
 {
     Forest &F = ctx->forest;
+    const double ts0 = now_ms();
     F.split_pending();
+    if (ctx->trace) fprintf(stderr, "cupk   split=%.3f ms\n", now_ms() - ts0);
     std::vector<RoundSet> sets;  // sets of the previous round, in d_sig order
     std::vector<uint32_t> vmem, voff, fmem, foff;
     struct Group {
@@ -329,15 +331,19 @@ int run_rounds(cupk_ctx *ctx)
         std::sort(ord.begin(), ord.end(),
                   [&](size_t a, size_t b) { return sets[a].minv < sets[b].minv; });
         bool linked = false, failed = false;
+        const double tl0 = now_ms();
+        uint32_t nlinks = 0;
         for (size_t i : ord) {
             if (!sets[i].sampled || res[3 * i] != CUPK_OK) continue;
             const uint32_t x = (uint32_t)res[3 * i + 1], y = (uint32_t)res[3 * i + 2];
             if (!F.same_tree(x, y)) {
                 F.link(x, y);
                 ctx->ctr.links++;
+                nlinks++;
                 linked = true;
             }
         }
+        if (ctx->trace) fprintf(stderr, "cupk   links=%u in %.3f ms\n", nlinks, now_ms() - tl0);
         for (size_t i = 0; i < k; i++) {
             if (!sets[i].sampled) continue;
             const int st = res[3 * i];

@@ -148,6 +148,37 @@ class Forest {
         return lb;
     }
 
+    // Replace forest edge {a, b} by {x, y}, where x and y are in the same
+    // tree and their tree path runs through {a, b}: the tree keeps its
+    // vertices (no relabelling); the side below {a, b} is re-rooted at its
+    // endpoint of {x, y} (one path reversed) and hung below the other one.
+    void swap_edge(uint32_t a, uint32_t b, uint32_t x, uint32_t y)
+    {
+        const uint32_t child = par_[a] == b ? a : b;
+        const uint32_t parent = child == a ? b : a;
+        // which of x, y lies below the removed edge
+        uint32_t s = x, t = y;
+        {
+            uint32_t c = x;
+            while (c != kNone && c != child) c = par_[c];
+            if (c != child) std::swap(s, t);
+        }
+        remove_kid(parent, child);
+        par_[child] = kNone;
+        for (uint32_t c = s, below = kNone; c != kNone;) {
+            const uint32_t up = par_[c];
+            if (up != kNone) remove_kid(up, c);
+            if (below != kNone) {
+                par_[c] = below;
+                add_kid(below, c);
+            }
+            below = c;
+            c = up;
+        }
+        par_[s] = t;
+        add_kid(t, s);
+    }
+
     // Cut forest edge {a, b}.  Returns (label of a's side, label of b's side).
     std::pair<uint32_t, uint32_t> cut(uint32_t a, uint32_t b)
     {

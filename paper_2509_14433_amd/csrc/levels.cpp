@@ -89,13 +89,36 @@ void gather(cupk_ctx *ctx, uint32_t lo, std::vector<Cand> &cands, std::vector<ui
                 }
         } else {
             Forest &F = L.lv[i]->F;
+            uint32_t giant = kNone, giant_sz = 0;
             for (uint32_t l : F.live_labels()) {
                 const uint32_t w = F.tree_root(l);
                 const uint32_t sz = F.tree_size(l);
                 if (N.tree_size(N.label(w)) != sz) continue;
+                if (2 * (uint64_t)sz > ctx->V) {
+                    giant = l;
+                    giant_sz = sz;
+                    continue;
+                }
                 const uint32_t mb = (uint32_t)mem.size();
                 const uint32_t mn = F.collect(l, mem);
                 cands.push_back({i, mn, sz, mb, (uint32_t)mem.size()});
+            }
+            if (giant != kNone) {
+                // Every edge adds the same words to both endpoints, so the
+                // sketches of all vertices XOR to zero and a set's aggregate
+                // equals its complement's: a tree holding most vertices is
+                // reduced over the other trees' vertices.
+                const uint32_t mb = (uint32_t)mem.size();
+                for (uint32_t l : F.live_labels())
+                    if (l != giant) F.collect(l, mem);
+                if (++L.epoch == 0) {
+                    std::fill(L.mark.begin(), L.mark.end(), 0u);
+                    L.epoch = 1;
+                }
+                for (size_t q = mb; q < mem.size(); q++) L.mark[mem[q]] = L.epoch;
+                uint32_t mn = 0;
+                while (L.mark[mn] == L.epoch) mn++;  // smallest vertex of the giant
+                cands.push_back({i, mn, giant_sz, mb, (uint32_t)mem.size()});
             }
         }
         std::sort(cands.begin() + (long)c0, cands.end(),
@@ -232,9 +255,17 @@ int levels_restore(cupk_ctx *ctx)
             if (N.tree_size(N.label(inside)) != cands[j].size) continue;
             uint32_t ea, eb;
             const uint32_t w = heaviest_on_path(ctx, x, y, ea, eb);
-            if (w) remove_from(ctx, ea, eb, w);
-            for (uint32_t l = i + 1; l < L.top; l++) L.lv[l]->F.link(x, y);
-            ctx->forest.link(x, y);
+            // from the cycle edge's weight up, (x, y) replaces it inside one
+            // tree (no split, no relabelling); below that it joins two trees
+            const uint32_t swap_from = w ? w : L.top + 1;
+            for (uint32_t l = i + 1; l <= L.top; l++) {
+                Forest &G = level_forest(ctx, l);
+                if (l >= swap_from)
+                    G.swap_edge(ea, eb, x, y);
+                else
+                    G.link(x, y);
+            }
+            if (w) ctx->ctr.cuts++;
             ctx->forest_dev_stale = true;
             ctx->ctr.links++;
             ctx->ctr.level_repairs++;

@@ -115,6 +115,37 @@ int main(int argc, char **argv)
             F.link(a, b);
             N.adj[a].insert(b);
             N.adj[b].insert(a);
+        } else if (mode == 8 && (rng() & 1)) {
+            // swap a tree edge for a non-tree pair whose path crosses it
+            const uint32_t x = (uint32_t)(rng() % V), y = (uint32_t)(rng() % V);
+            if (x == y || !F.same_tree(x, y) || F.is_edge(x, y)) continue;
+            // the naive path x .. y
+            std::vector<uint32_t> prev(V, UINT32_MAX);
+            std::deque<uint32_t> q{x};
+            prev[x] = x;
+            while (!q.empty()) {
+                const uint32_t a = q.front();
+                q.pop_front();
+                for (uint32_t b : N.adj[a])
+                    if (prev[b] == UINT32_MAX) {
+                        prev[b] = a;
+                        q.push_back(b);
+                    }
+            }
+            std::vector<uint32_t> path{y};
+            while (path.back() != x) path.push_back(prev[path.back()]);
+            const size_t k = rng() % (path.size() - 1);
+            const uint32_t ea = std::min(path[k], path[k + 1]);
+            const uint32_t eb = std::max(path[k], path[k + 1]);
+            const uint64_t trees = F.n_trees();
+            const uint32_t lx = F.label(x);
+            F.swap_edge(ea, eb, x, y);
+            N.adj[ea].erase(eb);
+            N.adj[eb].erase(ea);
+            N.adj[x].insert(y);
+            N.adj[y].insert(x);
+            if (F.n_trees() != trees || F.label(x) != lx || F.label(y) != lx)
+                return fail("swap changed the trees", s);
         } else if (mode < 9) {
             std::vector<uint32_t> eu, ev;
             F.edges(eu, ev);
