@@ -538,35 +538,22 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
 
 constexpr uint32_t kTileThreads = 256;
 
-// XOR one (record, column) pair into the LDS delta, or into HBM for depths
-// beyond the rows held in LDS.
+// XOR one (record, column) pair into endpoint p's LDS delta (local index
+// lp), or into HBM for depths beyond the rows held in LDS.
 DEVI void tile_column(const DevSketch &sk, uint64_t *la, uint64_t *lg, uint32_t TV,
-                      uint32_t rows, uint32_t c, uint64_t seed, uint64_t x, uint32_t u,
-                      uint32_t v, bool inu, bool inv, uint32_t lu, uint32_t lv)
+                      uint32_t rows, uint32_t c, uint64_t seed, uint64_t x, uint32_t p,
+                      uint32_t lp)
 {
     const uint64_t h = mix64(x ^ seed);
     const uint32_t d = depth_of(h, sk.D);
     if (d < rows) {
-        const uint32_t rowoff = (d * sk.C + c) * TV;
-        if (inu) {
-            lxor(&la[rowoff + lu], x);
-            lxor(&lg[rowoff + lu], h);
-        }
-        if (inv) {
-            lxor(&la[rowoff + lv], x);
-            lxor(&lg[rowoff + lv], h);
-        }
+        const uint32_t q = (d * sk.C + c) * TV + lp;
+        lxor(&la[q], x);
+        lxor(&lg[q], h);
     } else {
-        if (inu) {
-            uint64_t *bu = sk.b + (((uint64_t)u * sk.D + d) * sk.C + c) * 2;
-            gxor(bu, x);
-            gxor(bu + 1, h);
-        }
-        if (inv) {
-            uint64_t *bv = sk.b + (((uint64_t)v * sk.D + d) * sk.C + c) * 2;
-            gxor(bv, x);
-            gxor(bv + 1, h);
-        }
+        uint64_t *bp = sk.b + (((uint64_t)p * sk.D + d) * sk.C + c) * 2;
+        gxor(bp, x);
+        gxor(bp + 1, h);
     }
 }
 
@@ -610,14 +597,27 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
             const uint64_t x = (uint64_t)u * V + v;
             const bool inu = (u >> tile_shift) == tile;
             const bool inv = (v >> tile_shift) == tile;
-            const uint32_t lu = u - w0, lv = v - w0;
+            // a record is in this bin for an endpoint in this tile; both of
+            // its endpoints are here only when u and v share the tile (rare),
+            // so the common path has no branch on the endpoint
+            const uint32_t p = inu ? u : v;
             if (CMAX > 0) {
 #pragma unroll
                 for (uint32_t c = 0; c < (CMAX > 0 ? CMAX : 1); c++)
-                    if (c < C) tile_column(sk, la, lg, TV, rows, c, seed[c], x, u, v, inu, inv, lu, lv);
+                    if (c < C) tile_column(sk, la, lg, TV, rows, c, seed[c], x, p, p - w0);
             } else {
                 for (uint32_t c = 0; c < C; c++)
-                    tile_column(sk, la, lg, TV, rows, c, sk.seeds[c], x, u, v, inu, inv, lu, lv);
+                    tile_column(sk, la, lg, TV, rows, c, sk.seeds[c], x, p, p - w0);
+            }
+            if (inu && inv) {
+                if (CMAX > 0) {
+#pragma unroll
+                    for (uint32_t c = 0; c < (CMAX > 0 ? CMAX : 1); c++)
+                        if (c < C) tile_column(sk, la, lg, TV, rows, c, seed[c], x, v, v - w0);
+                } else {
+                    for (uint32_t c = 0; c < C; c++)
+                        tile_column(sk, la, lg, TV, rows, c, sk.seeds[c], x, v, v - w0);
+                }
             }
         }
         __syncthreads();
