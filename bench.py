@@ -297,11 +297,15 @@ def workload_leg(args, cupk, torch, np, streamgen):
         torch.cuda.synchronize()
         sample = packed[: min(n, 1 << 20)].contiguous()
         res = {}
-        for label, kw, tune in (
-                ("plain_atomic", dict(scatter_mode=cupk.SCATTER_ATOMIC), False),
+        legs = [("plain_atomic", dict(scatter_mode=cupk.SCATTER_ATOMIC), False),
                 ("staged_autotuned", dict(scatter_mode=cupk.SCATTER_STAGED), True),
                 ("staged_autotuned_graph", dict(scatter_mode=cupk.SCATTER_STAGED,
-                                                use_graph=True), True)):
+                                                use_graph=True), True)]
+        if name != "fixed_forest":
+            # flagged runs walked one update at a time instead of contracted
+            legs.append(("staged_autotuned_walk_plain", dict(scatter_mode=cupk.SCATTER_STAGED,
+                                                             walk_plain=True), True))
+        for label, kw, tune in legs:
             print(f"bench: {name} {label}", file=sys.stderr, flush=True)
             dt, ctr, tr = _time_batches(cupk, torch, dict(kw, max_batch=max(sizes),
                                                           time_kernels=True),
@@ -312,6 +316,10 @@ def workload_leg(args, cupk, torch, np, streamgen):
                           "bin_ms": round(ctr["bin_ms"], 3), "links": ctr["links"],
                           "cuts": ctr["cuts"], "rounds": ctr["rounds"],
                           "sample_failed": ctr["sample_failed"],
+                          "host_flags_ms": round(ctr["host_flags_ms"], 1),
+                          "host_rounds_ms": round(ctr["host_rounds_ms"], 1),
+                          "walks_contracted": ctr["walks_contracted"],
+                          "walks_fallback": ctr["walks_fallback"],
                           # updates that changed the forest (the single-level
                           # analogue of the paper's isolated updates)
                           "structural_rate": round((ctr["links"] + ctr["cuts"]) / n, 7)}

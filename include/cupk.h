@@ -135,6 +135,12 @@ typedef struct {
      * then completed with replacement rounds on the all-column sampler.
      * Not combinable with exact. */
     uint32_t levels;
+    /* Nonzero: walk the flagged updates of a batch into the forest one at a
+     * time.  Default: a run of flagged updates that holds deletes is walked
+     * contracted (the pieces the run's deletes leave of the forest as
+     * vertices, the run replayed on that small forest, only the net change
+     * applied), which gives the same forest, dirty trees and counts. */
+    uint32_t walk_plain;
 } cupk_opts;
 
 /* Counters, cumulative since init. */
@@ -159,6 +165,9 @@ typedef struct {
     uint64_t level_passes;       /* levels mode: restoration passes              */
     uint64_t level_repairs;      /* levels mode: violating components repaired   */
     uint64_t level_failed;       /* levels mode: one-column queries that failed  */
+    uint64_t walks_contracted;   /* runs of flagged updates walked contracted    */
+    uint64_t walks_fallback;     /* runs whose piece search gave up (walked one
+                                    update at a time)                           */
 } cupk_counters_t;
 
 /* Bytes of device memory the sketch of (V, C, D) occupies. */

@@ -54,6 +54,7 @@ class cupk_opts(ctypes.Structure):
         ("use_graph", ctypes.c_uint32),
         ("exact", ctypes.c_uint32),
         ("levels", ctypes.c_uint32),
+        ("walk_plain", ctypes.c_uint32),
     ]
 
 
@@ -65,7 +66,9 @@ class cupk_counters_t(ctypes.Structure):
         ("host_wait_ms", ctypes.c_double), ("host_flags_ms", ctypes.c_double),
         ("host_rounds_ms", ctypes.c_double), ("reverts", ctypes.c_uint64),
         ("level_passes", ctypes.c_uint64), ("level_repairs", ctypes.c_uint64),
-        ("level_failed", ctypes.c_uint64)]
+        ("level_failed", ctypes.c_uint64),
+        ("walks_contracted", ctypes.c_uint64),
+        ("walks_fallback", ctypes.c_uint64)]
 
 
 class cupk_serve_opts(ctypes.Structure):
@@ -171,7 +174,7 @@ class Context:
     def __init__(self, V, C=0, D=0, seed=0, scatter_mode=SCATTER_STAGED, max_batch=0,
                  stream=None, use_torch_memory=True, time_kernels=False, tile_vertices=0,
                  lds_rows=0, chunk_records=0, tile_grid=0, use_graph=False, exact=False,
-                 levels=False):
+                 levels=False, walk_plain=False):
         self._h = None
         self._sk_tensor = None
         self._keep = {}
@@ -186,6 +189,7 @@ class Context:
         opts.use_graph = 1 if use_graph else 0
         opts.exact = 1 if exact else 0
         opts.levels = 1 if levels else 0
+        opts.walk_plain = 1 if walk_plain else 0
         torch = _torch()
         if stream is None and torch is not None and torch.cuda.is_available():
             # launch on torch's current stream so that torch-produced device

@@ -386,6 +386,18 @@ bool apply_flags(cupk_ctx *ctx, const uint64_t *upd, uint32_t k0, uint32_t k1, b
         }
         return false;
     }
+    if (!all_inserts && !ctx->opts.walk_plain && k1 > k0) {
+        uint64_t nl = 0, nc = 0;
+        bool changed = false;
+        if (ctx->contract.run(F, upd, k0, k1, &nl, &nc, &changed)) {
+            ctx->ctr.links += nl;
+            ctx->ctr.cuts += nc;
+            ctx->ctr.walks_contracted++;
+            if (changed) ctx->forest_dev_stale = true;
+            return false;
+        }
+        ctx->ctr.walks_fallback++;
+    }
     bool done = false;
     for (uint32_t k = k0; k < k1; k++) {
         if (all_inserts && F.n_trees() == 1) {

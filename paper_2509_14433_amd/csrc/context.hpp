@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "cupk.h"
+#include "contract.hpp"
 #include "forest.hpp"
 #include "kernels.hpp"
 #include "serve.hpp"
@@ -111,6 +112,7 @@ struct cupk_ctx {
     std::vector<int32_t> round_gmap;  // label -> round group, -1 elsewhere
     std::unique_ptr<cupk::Levels> levels;  // multi-level hierarchy (opts.levels)
     cupk::Forest forest;
+    cupk::Contraction contract;  // contracted walks of flagged runs
     cupk_counters_t ctr = {};
     std::string err;
 

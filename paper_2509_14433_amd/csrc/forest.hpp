@@ -56,6 +56,7 @@ class Forest {
         n_trees_ = V;
         n_edges_ = 0;
         dirty_list_.clear();
+        pending_.clear();
     }
 
     uint32_t V() const { return V_; }

@@ -61,13 +61,17 @@ def rmat_ref():
                 truth=truth)
 
 
-@pytest.mark.parametrize("mode,graph", [("atomic", False), ("staged", False), ("staged", True)])
-def test_rmat_ragged_batches(cupk, rmat_ref, mode, graph):
+@pytest.mark.parametrize("mode,graph,walk_plain", [("atomic", False, False),
+                                                   ("staged", False, False),
+                                                   ("staged", True, False),
+                                                   ("staged", False, True)])
+def test_rmat_ragged_batches(cupk, rmat_ref, mode, graph, walk_plain):
     R = rmat_ref
     sm = cupk.SCATTER_ATOMIC if mode == "atomic" else cupk.SCATTER_STAGED
     ctx = cupk.Context(R["V"], R["C"], R["D"], R["cfg"]["S"], scatter_mode=sm, use_graph=graph,
-                       max_batch=4096)
-    print(f"rmat n={len(R['u'])} batches={len(R['sizes'])} mode={mode} graph={graph}", flush=True)
+                       max_batch=4096, walk_plain=walk_plain)
+    print(f"rmat n={len(R['u'])} batches={len(R['sizes'])} mode={mode} graph={graph} "
+          f"walk_plain={walk_plain}", flush=True)
     off = 0
     for s in R["sizes"]:
         ctx.apply_updates(R["u"][off:off + s], R["v"][off:off + s], R["d"][off:off + s])
@@ -179,14 +183,19 @@ def test_forest_targeted_deletions_served(cupk):
     ctx.close()
 
 
-@pytest.mark.parametrize("mode", ["atomic", "staged"])
-def test_clustered_churn(cupk, mode):
+@pytest.mark.parametrize("mode,walk_plain", [("atomic", False), ("staged", False),
+                                             ("staged", True)])
+def test_clustered_churn(cupk, mode, walk_plain):
+    """Bridges toggled many times per batch: the flagged runs are walked
+    contracted (or one by one), with the oracle's forest, links, cuts and
+    rounds either way."""
     cfg = streamgen.SCALED[4]
     V = cfg["V"]
     C, D = _cd(V)
     u, v, d = streamgen.config_stream(4, scaled=True)
     sm = cupk.SCATTER_ATOMIC if mode == "atomic" else cupk.SCATTER_STAGED
-    ctx = cupk.Context(V, C, D, cfg["S"], scatter_mode=sm)
+    print(f"clusters n={len(u)} mode={mode} walk_plain={walk_plain}", flush=True)
+    ctx = cupk.Context(V, C, D, cfg["S"], scatter_mode=sm, walk_plain=walk_plain)
     sk = oracle.Sketch(V, C, D, cfg["S"])
     fr = oracle.ForestReplay(sk)
     B = cfg["batch"]
@@ -204,7 +213,12 @@ def test_clustered_churn(cupk, mode):
             assert ctx.connected(a, b) == (lab[a] == lab[b])
     assert ctx.digest() == sk.digest()
     assert ctx.forest_edges() == fr.forest_edges()
-    assert ctx.counters()["cuts"] == fr.n_cuts
+    ctr = ctx.counters()
+    assert (ctr["links"], ctr["cuts"], ctr["rounds"]) == (fr.n_links, fr.n_cuts, fr.n_rounds)
+    if walk_plain:
+        assert ctr["walks_contracted"] == 0
+    else:
+        assert ctr["walks_contracted"] > 0
     ctx.close()
 
 
