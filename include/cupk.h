@@ -136,10 +136,11 @@ typedef struct {
      * Not combinable with exact. */
     uint32_t levels;
     /* Nonzero: walk the flagged updates of a batch into the forest one at a
-     * time.  Default: a run of flagged updates that holds deletes is walked
-     * contracted (the pieces the run's deletes leave of the forest as
-     * vertices, the run replayed on that small forest, only the net change
-     * applied), which gives the same forest, dirty trees and counts. */
+     * time.  Default: a run of flagged updates where an insert follows a
+     * delete is walked contracted (the pieces the run's deletes leave of the
+     * forest as vertices, the run replayed on that small forest, only the
+     * net change applied), which gives the same forest, dirty trees and
+     * counts. */
     uint32_t walk_plain;
 } cupk_opts;
 

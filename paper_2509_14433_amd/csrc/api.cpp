@@ -386,7 +386,19 @@ bool apply_flags(cupk_ctx *ctx, const uint64_t *upd, uint32_t k0, uint32_t k1, b
         }
         return false;
     }
-    if (!all_inserts && !ctx->opts.walk_plain && k1 > k0) {
+    // Contract only runs where an insert follows a delete: without one, the
+    // one-by-one walk removes edges in O(1) each and splits once at the end.
+    bool insert_after_delete = false;
+    if (!all_inserts && !ctx->opts.walk_plain) {
+        bool seen_delete = false;
+        for (uint32_t k = k0; k < k1 && !insert_after_delete; k++) {
+            if (upd[k] >> 63)
+                seen_delete = true;
+            else
+                insert_after_delete = seen_delete;
+        }
+    }
+    if (insert_after_delete) {
         uint64_t nl = 0, nc = 0;
         bool changed = false;
         if (ctx->contract.run(F, upd, k0, k1, &nl, &nc, &changed)) {
