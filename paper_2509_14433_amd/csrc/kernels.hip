@@ -145,9 +145,8 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
             uint32_t u, v;
             bool del;
             unpack(p[k], V, u, v, del);
-            const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
-            atomicAdd(&h[tu], 1u);
-            if (tv != tu) atomicAdd(&h[tv], 1u);
+            atomicAdd(&h[u >> tile_shift], 1u);
+            atomicAdd(&h[v >> tile_shift], 1u);
         }
     }
     uint32_t ndel = 0;  // flagged deletes of this lane, then of this wave
@@ -375,10 +374,10 @@ hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, uint32_t 
 // 1. k_tile_scan (one block): exclusive scan of the per-tile record counts
 //    into bin offsets, and a list of work items (tile, chunk) where a chunk
 //    is at most `chunk` records of one tile's bin.
-// 2. k_tile_fill: each update writes its record (u | v << 32) into the bin
-//    of u's tile and, if different, of v's tile.  Slots are reserved per
-//    block in LDS first, so global atomics are per (block, tile), not per
-//    record.
+// 2. k_tile_fill: each update writes one record per endpoint into the bin
+//    of that endpoint's tile: u | v << 32, with bit 63 set (kRecV) in the
+//    record of v.  Slots are reserved per block in LDS first, so global
+//    atomics are per (block, tile), not per record.
 // 3. k_tile_scatter: one work item per block iteration.  The block keeps a
 //    zeroed LDS delta of depth rows 0..rows-1 for the tile's vertices, XORs
 //    every record of the chunk into it (LDS atomics; depths >= rows go
@@ -390,6 +389,7 @@ hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, uint32_t 
 //    (c, d) hit consecutive words.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kScanThreads = 1024;
+constexpr uint64_t kRecV = 1ull << 63;  // the record is for endpoint v
 
 // Block-wide exclusive scan of one value per thread; returns the prefix and
 // sets `total`.
@@ -495,9 +495,8 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
             bool del;
             unpack(p[k], V, u, v, del);
             const uint64_t rec = (uint64_t)u | ((uint64_t)v << 32);
-            const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
-            bins[atomicAdd(&cur[tu], 1u)] = rec;
-            if (tv != tu) bins[atomicAdd(&cur[tv], 1u)] = rec;
+            bins[atomicAdd(&cur[u >> tile_shift], 1u)] = rec;
+            bins[atomicAdd(&cur[v >> tile_shift], 1u)] = rec | kRecV;
         }
         return;
     }
@@ -512,9 +511,8 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
         uint32_t u, v;
         bool del;
         unpack(p[k], V, u, v, del);
-        const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
-        ru[k] = atomicAdd(&lcnt[tu], 1u);
-        if (tv != tu) rv[k] = atomicAdd(&lcnt[tv], 1u);
+        ru[k] = atomicAdd(&lcnt[u >> tile_shift], 1u);
+        rv[k] = atomicAdd(&lcnt[v >> tile_shift], 1u);
     }
     __syncthreads();
     // reserve one contiguous range per tile present in this block
@@ -530,31 +528,41 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
         bool del;
         unpack(p[k], V, u, v, del);
         const uint64_t rec = (uint64_t)u | ((uint64_t)v << 32);
-        const uint32_t tu = u >> tile_shift, tv = v >> tile_shift;
-        bins[lcnt[tu] + ru[k]] = rec;
-        if (tv != tu) bins[lcnt[tv] + rv[k]] = rec;
+        bins[lcnt[u >> tile_shift] + ru[k]] = rec;
+        bins[lcnt[v >> tile_shift] + rv[k]] = rec | kRecV;
     }
 }
 
 constexpr uint32_t kTileThreads = 256;
 
-// XOR one (record, column) pair into endpoint p's LDS delta (local index
-// lp), or into HBM for depths beyond the rows held in LDS.
-DEVI void tile_column(const DevSketch &sk, uint64_t *la, uint64_t *lg, uint32_t TV,
-                      uint32_t rows, uint32_t c, uint64_t seed, uint64_t x, uint32_t p,
-                      uint32_t lp)
+// XOR one (record, column) pair into the endpoint's LDS delta, or into HBM
+// for depths beyond the rows held in LDS.  lq = c*TV + (local vertex index),
+// CTV = C*TV (words per LDS depth row); gb = the endpoint's first bucket in
+// HBM.  Index products use the full-rate 24-bit multiply (d < 64 and
+// C*TV, C < 2^24).  fmask = 2^r - 1 with r <= min(rows, D-1, 31): when the
+// hash's low word has a set bit below r, the depth is that bit's index
+// (one instruction); the full depth is computed only otherwise (odds 2^-r).
+DEVI void tile_column(uint64_t *la, uint64_t *lg, uint64_t *gb, uint32_t C, uint32_t D,
+                      uint32_t CTV, uint32_t rows, uint32_t fmask, uint32_t c, uint64_t seed,
+                      uint64_t x, uint32_t lq)
 {
     const uint64_t h = mix64(x ^ seed);
-    const uint32_t d = depth_of(h, sk.D);
-    if (d < rows) {
-        const uint32_t q = (d * sk.C + c) * TV + lp;
-        lxor(&la[q], x);
-        lxor(&lg[q], h);
+    const uint32_t lo = (uint32_t)h;
+    uint32_t d;
+    if (lo & fmask) {
+        d = (uint32_t)__builtin_ctz(lo);
     } else {
-        uint64_t *bp = sk.b + (((uint64_t)p * sk.D + d) * sk.C + c) * 2;
-        gxor(bp, x);
-        gxor(bp + 1, h);
+        d = depth_of(h, D);
+        if (d >= rows) {
+            uint64_t *bp = gb + 2 * (__umul24(d, C & 0xffffffu) + c);
+            gxor(bp, x);
+            gxor(bp + 1, h);
+            return;
+        }
     }
+    const uint32_t q = __umul24(d, CTV) + lq;
+    lxor(&la[q], x);
+    lxor(&lg[q], h);
 }
 
 // CMAX > 0: columns unrolled at compile time (C <= CMAX); CMAX == 0: a
@@ -570,6 +578,12 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
     const uint32_t TV = 1u << tile_shift;
     const uint32_t C = sk.C, D = sk.D, V = sk.V;
     const uint32_t plane = rows * C * TV;  // words per LDS plane
+    // words per LDS depth row (< 2^24: the mask lets the compiler use the
+    // 24-bit multiply for row offsets)
+    const uint32_t CTV = (C * TV) & 0xffffffu;
+    const uint64_t DC2 = (uint64_t)D * C * 2;  // words per vertex in HBM
+    const uint32_t rfast = min(min(rows, D - 1), 31u);
+    const uint32_t fmask = (1u << rfast) - 1;
     uint64_t *la = lds;                    // alpha plane [d][c][vl]
     uint64_t *lg = lds + plane;            // gamma plane
     const uint32_t nitems = *nitems_p;
@@ -593,31 +607,21 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
 
         for (uint32_t r = cb + threadIdx.x; r < ce; r += blockDim.x) {
             const uint64_t rec = bins[r];
-            const uint32_t u = (uint32_t)rec, v = (uint32_t)(rec >> 32);
+            const uint32_t u = (uint32_t)rec, v = (uint32_t)(rec >> 32) & 0x7fffffffu;
             const uint64_t x = (uint64_t)u * V + v;
-            const bool inu = (u >> tile_shift) == tile;
-            const bool inv = (v >> tile_shift) == tile;
-            // a record is in this bin for an endpoint in this tile; both of
-            // its endpoints are here only when u and v share the tile (rare),
-            // so the common path has no branch on the endpoint
-            const uint32_t p = inu ? u : v;
+            // the record's endpoint in this tile
+            const uint32_t p = (rec & kRecV) ? v : u;
+            uint64_t *gb = sk.b + (uint64_t)p * DC2;
             if (CMAX > 0) {
 #pragma unroll
                 for (uint32_t c = 0; c < (CMAX > 0 ? CMAX : 1); c++)
-                    if (c < C) tile_column(sk, la, lg, TV, rows, c, seed[c], x, p, p - w0);
+                    if (c < C)
+                        tile_column(la, lg, gb, C, D, CTV, rows, fmask, c, seed[c], x,
+                                    c * TV + (p - w0));
             } else {
                 for (uint32_t c = 0; c < C; c++)
-                    tile_column(sk, la, lg, TV, rows, c, sk.seeds[c], x, p, p - w0);
-            }
-            if (inu && inv) {
-                if (CMAX > 0) {
-#pragma unroll
-                    for (uint32_t c = 0; c < (CMAX > 0 ? CMAX : 1); c++)
-                        if (c < C) tile_column(sk, la, lg, TV, rows, c, seed[c], x, v, v - w0);
-                } else {
-                    for (uint32_t c = 0; c < C; c++)
-                        tile_column(sk, la, lg, TV, rows, c, sk.seeds[c], x, v, v - w0);
-                }
+                    tile_column(la, lg, gb, C, D, CTV, rows, fmask, c, sk.seeds[c], x,
+                                c * TV + (p - w0));
             }
         }
         __syncthreads();
