@@ -489,26 +489,36 @@ StagedParams staged_params(cupk_ctx *ctx, uint32_t grid_n)
 }
 
 // Device work of one batch, in three parts.  Grids are sized for grid_n;
-// the kernels read the batch from ctx->d_desc.
-int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n, bool copy_header)
+// the kernels read the batch from ctx->cur_desc (by value) or, while graphs
+// are captured, from ctx->d_desc.  The header is left zeroed by the previous
+// batch's scatter (and at init).
+static const BatchDesc *desc_ptr(cupk_ctx *ctx) { return ctx->capturing ? ctx->d_desc : nullptr; }
+
+int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
 {
     const bool staged = ctx->opts.scatter_mode == CUPK_SCATTER_STAGED;
-    HIPCHK(launch_zero32(s, ctx->d_hdr, HDR_WORDS));
-    HIPCHK(launch_classify(s, ctx->d_desc, grid_n, ctx->V, ctx->d_lbl, ctx->d_par, ctx->d_hdr,
-                           ctx->d_fupd.p, ctx->opts.exact ? ctx->d_fpos.p : nullptr,
-                           ctx->d_fcnt.p, staged ? ctx->d_tcnt.p : nullptr, ctx->tile_shift,
-                           ctx->ntiles));
-    if (copy_header)
-        HIPCHK(hipMemcpyAsync(ctx->h_hdr, ctx->d_hdr, HDR_WORDS * 4, hipMemcpyDeviceToHost, s));
+    ScanArgs sa = {};
+    if (staged) {
+        sa.off = ctx->d_toff.p;
+        sa.cur = ctx->d_tcur.p;
+        sa.items = ctx->d_items.p;
+        sa.nitems = ctx->d_nitems;
+        sa.chunk = ctx->chunk;
+        sa.items_cap = staged_params(ctx, grid_n).items_cap;
+    }
+    HIPCHK(launch_classify(s, desc_ptr(ctx), ctx->cur_desc, grid_n, ctx->V, ctx->d_lbl,
+                           ctx->d_par, ctx->d_hdr, ctx->d_fupd.p,
+                           ctx->opts.exact ? ctx->d_fpos.p : nullptr, ctx->d_fcnt.p,
+                           staged ? ctx->d_tcnt.p : nullptr, ctx->tile_shift, ctx->ntiles, sa,
+                           ctx->h_hdr));
     return CUPK_OK;
 }
 
 int enqueue_bin(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
 {
     if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED) return CUPK_OK;
-    HIPCHK(launch_bin(s, ctx->d_desc, grid_n, dev_sketch(ctx), ctx->d_hdr,
-                      staged_params(ctx, grid_n), ctx->d_tcnt.p, ctx->d_toff.p, ctx->d_tcur.p,
-                      ctx->d_bins.p, ctx->d_items.p, ctx->d_nitems));
+    HIPCHK(launch_bin(s, desc_ptr(ctx), ctx->cur_desc, grid_n, dev_sketch(ctx), ctx->d_hdr,
+                      staged_params(ctx, grid_n), ctx->d_tcur.p, ctx->d_bins.p));
     return CUPK_OK;
 }
 
@@ -518,7 +528,8 @@ int enqueue_tile(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
         HIPCHK(launch_tile(s, dev_sketch(ctx), ctx->d_hdr, staged_params(ctx, grid_n),
                            ctx->d_toff.p, ctx->d_bins.p, ctx->d_items.p, ctx->d_nitems));
     } else {
-        HIPCHK(launch_scatter_atomic(s, ctx->d_desc, grid_n, dev_sketch(ctx), ctx->d_hdr));
+        HIPCHK(launch_scatter_atomic(s, desc_ptr(ctx), ctx->cur_desc, grid_n, dev_sketch(ctx),
+                                     ctx->d_hdr));
     }
     return CUPK_OK;
 }
@@ -532,9 +543,11 @@ int capture_graphs(cupk_ctx *ctx)
     const uint32_t cap = (uint32_t)std::min<size_t>(ctx->batch_cap, kMaxBatchPerLaunch);
     for (int part = 0; part < 3; part++) {
         HIPCHK(hipStreamBeginCapture(ctx->gs, hipStreamCaptureModeThreadLocal));
-        int rc = part == 0 ? enqueue_classify(ctx, ctx->gs, cap, true)
+        ctx->capturing = true;
+        int rc = part == 0 ? enqueue_classify(ctx, ctx->gs, cap)
                  : part == 1 ? enqueue_bin(ctx, ctx->gs, cap)
                              : enqueue_tile(ctx, ctx->gs, cap);
+        ctx->capturing = false;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->gs, &g);
         if (rc != CUPK_OK) {
@@ -578,39 +591,41 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
                                              : offsetof(SmallResult, fupd) + (size_t)n * 8;
         HIPCHK(hipMemcpyAsync(ctx->h_small, ctx->d_small, bytes, hipMemcpyDeviceToHost, ctx->s));
         HIPCHK(hipEventRecord(ctx->ev_hdr, ctx->s));
+        ctx->hdr_event = ctx->ev_hdr;
         // the scatter follows the copy: the host walks the flags meanwhile
         HIPCHK(launch_small_scatter(ctx->s, d_upd, n, dev_sketch(ctx), ctx->d_small));
         ctx->ctr.scatter_launches++;
         return CUPK_OK;
     }
-    // the batch descriptor (pinned staging; the previous pass's copy has
-    // completed: every pass is followed by a wait for its classify step or
-    // for the whole stream)
-    ctx->h_desc->upd = d_upd;
-    ctx->h_desc->n = n;
-    HIPCHK(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
-                          ctx->s));
+    // the batch descriptor: kernel arguments, or for captured graphs device
+    // memory (pinned staging; the previous pass's copy has completed: every
+    // pass is followed by a wait for its classify step or for the whole
+    // stream)
+    ctx->cur_desc.upd = d_upd;
+    ctx->cur_desc.n = n;
+    if (graph) {
+        ctx->h_desc->upd = d_upd;
+        ctx->h_desc->n = n;
+        HIPCHK(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
+                              ctx->s));
+    }
     if (graph && (ctx->graph_cap < n || !ctx->gx_cls)) {
         rc = capture_graphs(ctx);
         if (rc != CUPK_OK) return rc;
     }
+    // the classify kernel writes the header to pinned host memory itself
     if (graph) {
         HIPCHK(hipGraphLaunch(ctx->gx_cls, ctx->s));
-        HIPCHK(hipEventRecord(ctx->ev_cls, ctx->s));
-        HIPCHK(hipEventRecord(ctx->ev_hdr, ctx->s));  // the header copy is in the graph
     } else {
-        rc = enqueue_classify(ctx, ctx->s, n, false);
+        rc = enqueue_classify(ctx, ctx->s, n);
         if (rc != CUPK_OK) return rc;
-        HIPCHK(hipEventRecord(ctx->ev_cls, ctx->s));
-        HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->ev_cls, 0));
-        HIPCHK(hipMemcpyAsync(ctx->h_hdr, ctx->d_hdr, HDR_WORDS * 4, hipMemcpyDeviceToHost,
-                              ctx->cs));
-        HIPCHK(hipEventRecord(ctx->ev_hdr, ctx->cs));
     }
-    if (graph) HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->ev_cls, 0));
-
-    // scatter (skipped on device if the batch was rejected)
+    // One marker after the classify step serves the host's wait for the
+    // header, the copy stream's wait (flag compaction) and, when kernels are
+    // timed, the start of the binning interval: every event recorded
+    // between two kernels leaves the GPU idle for a few microseconds.
     cupk_ctx::TimerSlot *ts = nullptr;
+    hipEvent_t mark = ctx->ev_hdr;
     if (ctx->opts.time_kernels) {
         ts = &ctx->timers[ctx->timer_head];
         ctx->timer_head = (ctx->timer_head + 1) % kTimerRing;
@@ -619,8 +634,13 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
             rc = harvest_timers(ctx, false);
             if (rc != CUPK_OK) return rc;
         }
-        HIPCHK(hipEventRecord(ts->t0, ctx->s));
+        mark = ts->t0;
     }
+    HIPCHK(hipEventRecord(mark, ctx->s));
+    ctx->hdr_event = mark;
+    HIPCHK(hipStreamWaitEvent(ctx->cs, mark, 0));
+
+    // scatter (skipped on device if the batch was rejected)
     if (graph) {
         if (ctx->gx_bin) HIPCHK(hipGraphLaunch(ctx->gx_bin, ctx->s));
         if (ts) HIPCHK(hipEventRecord(ts->tb, ctx->s));
@@ -675,7 +695,7 @@ int walk_pass(cupk_ctx *ctx, uint32_t n, bool exact, uint32_t *cut_pos, uint32_t
               uint32_t *cut_b, uint32_t *nflag_out, double *t_wait, double *t_copy)
 {
     double t0 = now_ms();
-    HIPCHK(hipEventSynchronize(ctx->ev_hdr));
+    HIPCHK(hipEventSynchronize(ctx->hdr_event));
     double t1 = now_ms();
     ctx->ctr.host_wait_ms += t1 - t0;
     *t_wait = t1 - t0;
@@ -874,7 +894,6 @@ void destroy(cupk_ctx *ctx)
         if (t.tb) (void)hipEventDestroy(t.tb);
         if (t.t1) (void)hipEventDestroy(t.t1);
     }
-    if (ctx->ev_cls) (void)hipEventDestroy(ctx->ev_cls);
     if (ctx->ev_hdr) (void)hipEventDestroy(ctx->ev_hdr);
     if (ctx->cs) (void)hipStreamDestroy(ctx->cs);
     if (ctx->own_stream && ctx->s) (void)hipStreamDestroy(ctx->s);
@@ -936,7 +955,6 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
         ctx->own_stream = true;
     }
     HIPCHK(hipStreamCreateWithFlags(&ctx->cs, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&ctx->ev_cls, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_hdr, hipEventDisableTiming));
     if (ctx->opts.time_kernels)
         for (auto &t : ctx->timers) {
@@ -959,6 +977,7 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     HIPCHK(hipHostMalloc((void **)&ctx->h_lbl, (size_t)V * 4, hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&ctx->h_par, (size_t)V * 4, hipHostMallocDefault));
     HIPCHK(hipMalloc((void **)&ctx->d_hdr, HDR_WORDS * 4));
+    HIPCHK(hipMemset(ctx->d_hdr, 0, HDR_WORDS * 4));
     HIPCHK(hipHostMalloc((void **)&ctx->h_hdr, HDR_WORDS * 4, hipHostMallocDefault));
     HIPCHK(hipMalloc((void **)&ctx->d_nitems, 4));
     HIPCHK(hipMalloc((void **)&ctx->d_desc, sizeof(BatchDesc)));
@@ -1277,11 +1296,9 @@ static int time_scatter_once(cupk_ctx *ctx, const uint64_t *d, uint32_t n, hipEv
 {
     int rc = ensure_batch_buffers(ctx, n);
     if (rc != CUPK_OK) return rc;
-    ctx->h_desc->upd = d;
-    ctx->h_desc->n = n;
-    HIPCHK(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(BatchDesc), hipMemcpyHostToDevice,
-                          ctx->s));
-    rc = enqueue_classify(ctx, ctx->s, n, false);
+    ctx->cur_desc.upd = d;
+    ctx->cur_desc.n = n;
+    rc = enqueue_classify(ctx, ctx->s, n);
     if (rc != CUPK_OK) return rc;
     HIPCHK(hipEventRecord(e0, ctx->s));
     rc = enqueue_bin(ctx, ctx->s, n);
@@ -1290,7 +1307,6 @@ static int time_scatter_once(cupk_ctx *ctx, const uint64_t *d, uint32_t n, hipEv
     HIPCHK(hipEventRecord(e1, ctx->s));
     HIPCHK(hipEventSynchronize(e1));
     HIPCHK(hipEventElapsedTime(ms, e0, e1));
-    HIPCHK(hipMemcpy(ctx->h_hdr, ctx->d_hdr, HDR_WORDS * 4, hipMemcpyDeviceToHost));
     if (ctx->h_hdr[HDR_ERR]) return ctx->invalid("sample batch holds an invalid update");
     return CUPK_OK;
 }

@@ -56,7 +56,8 @@ struct cupk_ctx {
     cupk_opts opts = {};
     hipStream_t s = nullptr, cs = nullptr;
     bool own_stream = false;
-    hipEvent_t ev_cls = nullptr, ev_hdr = nullptr;
+    hipEvent_t ev_hdr = nullptr;
+    hipEvent_t hdr_event = nullptr;  // marks the current pass's header (ev_hdr or a timer)
     struct TimerSlot {
         hipEvent_t t0, tb, t1;
         bool busy;
@@ -98,6 +99,10 @@ struct cupk_ctx {
     cupk::SmallResult *d_small = nullptr, *h_small = nullptr;  // small-batch pass results
     bool small_pass = false;   // the last pass took the small-batch path
     cupk::BatchDesc *d_desc = nullptr, *h_desc = nullptr;
+    // The batch of the pass being enqueued, passed to the kernels by value;
+    // while graphs are captured they read d_desc instead.
+    cupk::BatchDesc cur_desc = {};
+    bool capturing = false;
 
     // captured step (use_graph): classify + header copy, bin, tile
     hipStream_t gs = nullptr;  // capture stream

@@ -80,8 +80,95 @@ constexpr uint32_t kClsWaves = kClsThreads / 64;
 constexpr uint32_t kLdsHistMax = 8192;
 static_assert(kClsPerThread * kClsWaves == 64, "one wave scans the (step, wave) counts");
 
+constexpr uint32_t kScanThreads = 1024;
+
+// Block-wide exclusive scan of one value per thread; returns the prefix and
+// sets `total`.
+template <uint32_t NT>
+DEVI uint32_t block_exscan(uint32_t x, uint32_t &total, uint32_t *sh)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t wid = threadIdx.x / 64;
+    uint32_t inc = x;
+#pragma unroll
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) sh[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        uint32_t w = threadIdx.x < NT / 64 ? sh[threadIdx.x] : 0u;
+        uint32_t wi = w;
+#pragma unroll
+        for (uint32_t o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(wi, o);
+            if (lane >= o) wi += y;
+        }
+        if (threadIdx.x < NT / 64) sh[64 + threadIdx.x] = wi - w;
+        if (threadIdx.x == NT / 64 - 1) sh[128] = wi;
+    }
+    __syncthreads();
+    const uint32_t ex = sh[64 + wid] + inc - x;
+    total = sh[128];
+    __syncthreads();
+    return ex;
+}
+
+// Tile scan (one block, after the classify kernel): publishes the header
+// to the host, then (staged path, a.off set) scans the per-tile record
+// counts into bin offsets (and fill cursors) and lists the work items
+// (tile, chunk), a chunk being at most `chunk` records of one tile's bin.
+// The counts are zeroed for the next batch.
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict__ cnt,
+                                                            uint32_t ntiles, ScanArgs a,
+                                                            const uint32_t *__restrict__ hdr,
+                                                            uint32_t *__restrict__ hout)
+{
+    __shared__ uint32_t sh[160];
+    const bool err = hdr[HDR_ERR] != 0;
+    // the header goes straight to pinned host memory (no copy)
+    if (threadIdx.x < 3) hout[threadIdx.x] = hdr[threadIdx.x];
+    if (!a.off) return;
+    if (err) {
+        // rejected batch: leave the counts zeroed for the next one
+        for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) cnt[t] = 0;
+        if (threadIdx.x == 0) *a.nitems = 0;
+        return;
+    }
+    const uint32_t chunk = a.chunk, items_cap = a.items_cap;
+    uint32_t *off = a.off, *cur = a.cur, *items = a.items;
+    uint32_t carry_r = 0, carry_i = 0;
+    for (uint32_t base = 0; base < ntiles; base += kScanThreads) {
+        const uint32_t t = base + threadIdx.x;
+        const uint32_t c = t < ntiles ? cnt[t] : 0u;
+        if (t < ntiles) cnt[t] = 0;  // ready for the next batch's counts
+        const uint32_t k = (c + chunk - 1) / chunk;
+        uint32_t tot_c, tot_k;
+        const uint32_t ex_c = block_exscan<kScanThreads>(c, tot_c, sh);
+        const uint32_t ex_k = block_exscan<kScanThreads>(k, tot_k, sh);
+        if (t < ntiles) {
+            off[t] = carry_r + ex_c;
+            cur[t] = carry_r + ex_c;
+            for (uint32_t j = 0; j < k; j++) {
+                const uint32_t q = carry_i + ex_k + j;
+                if (q < items_cap) {
+                    items[2 * q] = t;
+                    items[2 * q + 1] = j;
+                }
+            }
+        }
+        carry_r += tot_c;
+        carry_i += tot_k;
+    }
+    if (threadIdx.x == 0) {
+        off[ntiles] = carry_r;
+        *a.nitems = min(carry_i, items_cap);
+    }
+}
+
 __global__ __launch_bounds__(kClsThreads) void k_classify(
-    const BatchDesc *__restrict__ desc, uint32_t V, const uint32_t *__restrict__ lbl,
+    const BatchDesc *__restrict__ desc, BatchDesc dv, uint32_t V, const uint32_t *__restrict__ lbl,
     const uint32_t *__restrict__ par, uint32_t *__restrict__ hdr, uint64_t *__restrict__ fupd,
     uint32_t *__restrict__ fpos, uint32_t *__restrict__ fcnt, uint32_t *__restrict__ tile_cnt,
     uint32_t tile_shift, uint32_t ntiles)
@@ -93,8 +180,8 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
     if (use_lds)
         for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) hist[t] = 0;
 
-    const uint64_t *__restrict__ upd = desc->upd;
-    const uint32_t n = desc->n;
+    const uint64_t *__restrict__ upd = desc ? desc->upd : dv.upd;
+    const uint32_t n = desc ? desc->n : dv.n;
     const uint32_t begin = blockIdx.x * kClsPerBlock;
     const uint32_t lane = __lane_id();
     const uint32_t wid = threadIdx.x / 64;
@@ -199,15 +286,36 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
 
 uint32_t classify_blocks(uint32_t n) { return (n + kClsPerBlock - 1) / kClsPerBlock; }
 
-hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, uint32_t grid_n, uint32_t V,
-                           const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
+hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
+                           uint32_t V, const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
-                           uint32_t tile_shift, uint32_t ntiles)
+                           uint32_t tile_shift, uint32_t ntiles, const ScanArgs &sa,
+                           uint32_t *hout)
 {
     if (grid_n == 0) return hipSuccess;
-    k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(desc, V, lbl, par, hdr, fupd, fpos,
-                                                              fcnt, tile_cnt, tile_shift, ntiles);
+    k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(
+        desc, dv, V, lbl, par, hdr, fupd, fpos, fcnt, tile_cnt, tile_shift, ntiles);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr, hout);
     return hipGetLastError();
+}
+
+// Last block of a scatter kernel to finish: clear the header for the next
+// batch.  Every block used its read of ERR before taking its ticket, so the
+// ticket needs no fence (a device-scope fence would write back L2).
+DEVI void scatter_done(uint32_t *hdr)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (__hip_atomic_fetch_add(&hdr[HDR_SCAT_DONE], 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
+            hdr[HDR_ERR] = 0;
+            hdr[HDR_NFLAG] = 0;
+            hdr[HDR_NFLAG_DEL] = 0;
+            hdr[HDR_SCAT_DONE] = 0;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -236,13 +344,15 @@ DEVI void scatter_one(const DevSketch &sk, uint64_t p)
 }
 
 __global__ __launch_bounds__(256) void k_scatter_atomic(const BatchDesc *__restrict__ desc,
-                                                        DevSketch sk,
-                                                        const uint32_t *__restrict__ hdr)
+                                                        BatchDesc dv, DevSketch sk,
+                                                        uint32_t *__restrict__ hdr)
 {
-    if (hdr[HDR_ERR]) return;
+    const bool err = hdr[HDR_ERR] != 0;
+    const uint32_t n = desc ? desc->n : dv.n;
+    const uint64_t *upd = desc ? desc->upd : dv.upd;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= desc->n) return;
-    scatter_one(sk, desc->upd[i]);
+    if (!err && i < n) scatter_one(sk, upd[i]);
+    scatter_done(hdr);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,20 +470,21 @@ hipError_t launch_small_scatter(hipStream_t s, const uint64_t *upd, uint32_t n, 
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, uint32_t grid_n,
-                                 DevSketch sk, const uint32_t *hdr)
+hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, BatchDesc dv,
+                                 uint32_t grid_n, DevSketch sk, uint32_t *hdr)
 {
     if (grid_n == 0) return hipSuccess;
-    k_scatter_atomic<<<(grid_n + 255) / 256, 256, 0, s>>>(desc, sk, hdr);
+    k_scatter_atomic<<<(grid_n + 255) / 256, 256, 0, s>>>(desc, dv, sk, hdr);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Staged scatter.
 //
-// 1. k_tile_scan (one block): exclusive scan of the per-tile record counts
-//    into bin offsets, and a list of work items (tile, chunk) where a chunk
-//    is at most `chunk` records of one tile's bin.
+// 1. tile scan (the last block of k_classify, once all counts are in):
+//    exclusive scan of the per-tile record counts into bin offsets, and a
+//    list of work items (tile, chunk) where a chunk is at most `chunk`
+//    records of one tile's bin.
 // 2. k_tile_fill: each update writes one record per endpoint into the bin
 //    of that endpoint's tile: u | v << 32, with bit 63 set (kRecV) in the
 //    record of v.  Slots are reserved per block in LDS first, so global
@@ -388,95 +499,21 @@ hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, uint32_t 
 //    [d][c][vertex], so lanes working on different vertices of the same
 //    (c, d) hit consecutive words.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kScanThreads = 1024;
 constexpr uint64_t kRecV = 1ull << 63;  // the record is for endpoint v
-
-// Block-wide exclusive scan of one value per thread; returns the prefix and
-// sets `total`.
-template <uint32_t NT>
-DEVI uint32_t block_exscan(uint32_t x, uint32_t &total, uint32_t *sh)
-{
-    const uint32_t lane = __lane_id();
-    const uint32_t wid = threadIdx.x / 64;
-    uint32_t inc = x;
-#pragma unroll
-    for (uint32_t o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(inc, o);
-        if (lane >= o) inc += y;
-    }
-    if (lane == 63) sh[wid] = inc;
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        uint32_t w = threadIdx.x < NT / 64 ? sh[threadIdx.x] : 0u;
-        uint32_t wi = w;
-#pragma unroll
-        for (uint32_t o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(wi, o);
-            if (lane >= o) wi += y;
-        }
-        if (threadIdx.x < NT / 64) sh[64 + threadIdx.x] = wi - w;
-        if (threadIdx.x == NT / 64 - 1) sh[128] = wi;
-    }
-    __syncthreads();
-    const uint32_t ex = sh[64 + wid] + inc - x;
-    total = sh[128];
-    __syncthreads();
-    return ex;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_tile_scan(
-    uint32_t *__restrict__ cnt, uint32_t ntiles, uint32_t chunk, uint32_t *__restrict__ off,
-    uint32_t *__restrict__ cur, uint32_t *__restrict__ items, uint32_t items_cap,
-    uint32_t *__restrict__ nitems, const uint32_t *__restrict__ hdr)
-{
-    __shared__ uint32_t sh[160];
-    if (hdr[HDR_ERR]) {
-        // rejected batch: leave the counts zeroed for the next one
-        for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) cnt[t] = 0;
-        if (threadIdx.x == 0) *nitems = 0;
-        return;
-    }
-    uint32_t carry_r = 0, carry_i = 0;
-    for (uint32_t base = 0; base < ntiles; base += kScanThreads) {
-        const uint32_t t = base + threadIdx.x;
-        const uint32_t c = t < ntiles ? cnt[t] : 0u;
-        if (t < ntiles) cnt[t] = 0;  // ready for the next batch's counts
-        const uint32_t k = (c + chunk - 1) / chunk;
-        uint32_t tot_c, tot_k;
-        const uint32_t ex_c = block_exscan<kScanThreads>(c, tot_c, sh);
-        const uint32_t ex_k = block_exscan<kScanThreads>(k, tot_k, sh);
-        if (t < ntiles) {
-            off[t] = carry_r + ex_c;
-            cur[t] = carry_r + ex_c;
-            for (uint32_t j = 0; j < k; j++) {
-                const uint32_t q = carry_i + ex_k + j;
-                if (q < items_cap) {
-                    items[2 * q] = t;
-                    items[2 * q + 1] = j;
-                }
-            }
-        }
-        carry_r += tot_c;
-        carry_i += tot_k;
-    }
-    if (threadIdx.x == 0) {
-        off[ntiles] = carry_r;
-        *nitems = min(carry_i, items_cap);
-    }
-}
 
 constexpr uint32_t kFillThreads = 1024;
 constexpr uint32_t kFillPerBlock = 4096;
 constexpr uint32_t kFillPerThread = kFillPerBlock / kFillThreads;
 
 __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
-    const BatchDesc *__restrict__ desc, uint32_t V, uint32_t tile_shift, uint32_t ntiles,
-    uint32_t *__restrict__ cur, uint64_t *__restrict__ bins, const uint32_t *__restrict__ hdr)
+    const BatchDesc *__restrict__ desc, BatchDesc dv, uint32_t V, uint32_t tile_shift,
+    uint32_t ntiles, uint32_t *__restrict__ cur, uint64_t *__restrict__ bins,
+    const uint32_t *__restrict__ hdr)
 {
     __shared__ uint32_t lcnt[kLdsHistMax];
     if (hdr[HDR_ERR]) return;
-    const uint64_t *__restrict__ upd = desc->upd;
-    const uint32_t n = desc->n;
+    const uint64_t *__restrict__ upd = desc ? desc->upd : dv.upd;
+    const uint32_t n = desc ? desc->n : dv.n;
     const uint32_t begin = blockIdx.x * kFillPerBlock;
     if (begin >= n) return;
     // all of this thread's updates are loaded once, up front
@@ -571,10 +608,10 @@ template <uint32_t CMAX>
 __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
     DevSketch sk, const uint64_t *__restrict__ bins, const uint32_t *__restrict__ off,
     const uint32_t *__restrict__ items, const uint32_t *__restrict__ nitems_p, uint32_t tile_shift,
-    uint32_t rows, uint32_t chunk, const uint32_t *__restrict__ hdr)
+    uint32_t rows, uint32_t chunk, uint32_t *__restrict__ hdr)
 {
     extern __shared__ uint64_t lds[];
-    if (hdr[HDR_ERR]) return;
+    const bool err = hdr[HDR_ERR] != 0;
     const uint32_t TV = 1u << tile_shift;
     const uint32_t C = sk.C, D = sk.D, V = sk.V;
     const uint32_t plane = rows * C * TV;  // words per LDS plane
@@ -586,7 +623,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
     const uint32_t fmask = (1u << rfast) - 1;
     uint64_t *la = lds;                    // alpha plane [d][c][vl]
     uint64_t *lg = lds + plane;            // gamma plane
-    const uint32_t nitems = *nitems_p;
+    const uint32_t nitems = err ? 0u : *nitems_p;
     uint64_t seed[CMAX > 0 ? CMAX : 1];
     if (CMAX > 0) {
 #pragma unroll
@@ -648,25 +685,21 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
         }
         __syncthreads();
     }
+    scatter_done(hdr);
 }
 
-hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, uint32_t grid_n, DevSketch sk,
-                      const uint32_t *hdr, const StagedParams &p, uint32_t *tile_cnt,
-                      uint32_t *tile_off, uint32_t *tile_cur, uint64_t *bins, uint32_t *items,
-                      uint32_t *nitems)
+hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
+                      DevSketch sk, const uint32_t *hdr, const StagedParams &p,
+                      uint32_t *tile_cur, uint64_t *bins)
 {
     if (grid_n == 0) return hipSuccess;
-    k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, p.ntiles, p.chunk, tile_off, tile_cur, items,
-                                           p.items_cap, nitems, hdr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const uint32_t fb = (grid_n + kFillPerBlock - 1) / kFillPerBlock;
-    k_tile_fill<<<fb, kFillThreads, 0, s>>>(desc, sk.V, p.tile_shift, p.ntiles, tile_cur, bins,
-                                            hdr);
+    k_tile_fill<<<fb, kFillThreads, 0, s>>>(desc, dv, sk.V, p.tile_shift, p.ntiles, tile_cur,
+                                            bins, hdr);
     return hipGetLastError();
 }
 
-hipError_t launch_tile(hipStream_t s, DevSketch sk, const uint32_t *hdr, const StagedParams &p,
+hipError_t launch_tile(hipStream_t s, DevSketch sk, uint32_t *hdr, const StagedParams &p,
                        const uint32_t *tile_off, const uint64_t *bins, const uint32_t *items,
                        const uint32_t *nitems)
 {

@@ -24,8 +24,18 @@ struct BatchDesc {
     uint32_t pad;
 };
 
-// Header words written by the classify kernel.
-enum { HDR_ERR = 0, HDR_NFLAG = 1, HDR_NFLAG_DEL = 2, HDR_WORDS = 4 };
+// Header words.  ERR / NFLAG / NFLAG_DEL are accumulated by the classify
+// kernel; SCAT_DONE counts finished blocks of the scatter kernel, whose last
+// block clears ERR / NFLAG / NFLAG_DEL (and SCAT_DONE) for the next batch.
+enum { HDR_ERR = 0, HDR_NFLAG = 1, HDR_NFLAG_DEL = 2, HDR_SCAT_DONE = 3, HDR_WORDS = 4 };
+
+// Where the tile scan (run by the last classify block) writes: bin offsets
+// and fill cursors (ntiles + 1 words each), work items (tile, chunk) and
+// their number.
+struct ScanArgs {
+    uint32_t *off, *cur, *items, *nitems;
+    uint32_t chunk, items_cap;
+};
 
 struct StagedParams {
     uint32_t tile_shift;   // vertices per tile = 1 << tile_shift
@@ -37,18 +47,24 @@ struct StagedParams {
 };
 
 // Per-batch: validation, structural classification and compaction of the
-// flagged updates.  hdr must be zeroed first.  When `tile_cnt` is non-null
-// the kernel also counts how many endpoint records each vertex tile gets.
-// Flagged updates of classify block b (positions [b*4096, (b+1)*4096)) land
-// in stream order at offsets b*4096.. of fupd (capacity: the batch rounded
-// up to a multiple of 4096); fcnt[b] receives their number.  fpos (may be
-// null) receives each flagged update's position in the batch, alongside.
-// grid_n sizes the grids (the batch size, or the capacity of a captured
-// graph); the kernels read the actual batch from desc.
-hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, uint32_t grid_n, uint32_t V,
-                           const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
+// flagged updates.  hdr's ERR / NFLAG / NFLAG_DEL words must be zero (as
+// the previous batch's scatter leaves them).  A one-block kernel after it
+// writes their final values to `hout` (pinned host memory, HDR_WORDS
+// words: no copy needed).  When `tile_cnt` is non-null the classify kernel
+// also counts how many endpoint records each vertex tile gets, and the
+// one-block kernel scans the counts into `sa` (sa.off set).  Flagged updates of
+// classify block b (positions [b*4096, (b+1)*4096)) land in stream order at
+// offsets b*4096.. of fupd (capacity: the batch rounded up to a multiple of
+// 4096); fcnt[b] receives their number.  fpos (may be null) receives each
+// flagged update's position in the batch, alongside.  grid_n sizes the
+// grids (the batch size, or the capacity of a captured graph); the kernels
+// read the batch from device memory at `desc` (captured graphs) or, when
+// desc is null, from `dv`.
+hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
+                           uint32_t V, const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
-                           uint32_t tile_shift, uint32_t ntiles);
+                           uint32_t tile_shift, uint32_t ntiles, const ScanArgs &sa,
+                           uint32_t *hout);
 uint32_t classify_blocks(uint32_t n);
 
 // Pack the per-block flag regions into one list in stream order (foff:
@@ -79,17 +95,17 @@ hipError_t launch_small_scatter(hipStream_t s, const uint64_t *upd, uint32_t n, 
                                 const SmallResult *res);
 
 // Plain scatter: device-scope atomic XOR of (x, h) into both endpoints.
-hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, uint32_t grid_n,
-                                 DevSketch sk, const uint32_t *hdr);
+// Its last block clears the header for the next batch.
+hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, BatchDesc dv,
+                                 uint32_t grid_n, DevSketch sk, uint32_t *hdr);
 
-// Staged scatter: launch_bin = scan of tile counts into bin offsets and
-// work items, then fill of the per-tile bins; launch_tile = LDS-staged XOR
-// per work item.
-hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, uint32_t grid_n, DevSketch sk,
-                      const uint32_t *hdr, const StagedParams &p, uint32_t *tile_cnt,
-                      uint32_t *tile_off, uint32_t *tile_cur, uint64_t *bins, uint32_t *items,
-                      uint32_t *nitems);
-hipError_t launch_tile(hipStream_t s, DevSketch sk, const uint32_t *hdr, const StagedParams &p,
+// Staged scatter: launch_bin = fill of the per-tile bins (at the offsets
+// the classify kernel's tile scan wrote); launch_tile = LDS-staged XOR per
+// work item, whose last block clears the header for the next batch.
+hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
+                      DevSketch sk, const uint32_t *hdr, const StagedParams &p,
+                      uint32_t *tile_cur, uint64_t *bins);
+hipError_t launch_tile(hipStream_t s, DevSketch sk, uint32_t *hdr, const StagedParams &p,
                        const uint32_t *tile_off, const uint64_t *bins, const uint32_t *items,
                        const uint32_t *nitems);
 
