@@ -12,8 +12,9 @@ packed stream is resident in HBM before timing starts.  K steps walk the
 stream from its start; past its end a fresh context replays it again.
 
 Prints one JSON line: whole-job updates/s, the scatter kernel's roofline
-figures (algorithmic bytes per update = 8 + 64*C over HIP-event kernel
-time), the plain (atomic) kernel's figures, components from the final
+figures (algorithmic bytes per update = 8 + 64*C over the kernel time of
+every 4th launch of the timed region, taken with HIP events on the launch
+stream), the plain (atomic) kernel's figures, components from the final
 sketch alone, the served path (large update requests; the paper's query
 bursts, open and closed loop), and the CPU oracle timed on a bounded sample
 of the same stream.  --workload selects the extra full-size measurements
@@ -65,7 +66,13 @@ def traffic_from_profile(kernel: str):
     return ent.get("hbm_bytes_per_launch")
 
 
-def run_path(cupk, torch, packed, sizes, steps, warmup, mode, time_kernels=True, graph=False):
+# Scatter launches timed with HIP events: every TIME_EVERY-th one (each
+# event between two kernels idles the GPU for a few microseconds).
+TIME_EVERY = 4
+
+
+def run_path(cupk, torch, packed, sizes, steps, warmup, mode, time_kernels=TIME_EVERY,
+             graph=False):
     """Warm up, then time `steps` batches.  Returns (seconds, updates, ctr)."""
     offs = [0]
     for s in sizes:
@@ -517,10 +524,11 @@ def main():
                               graph=bool(args.graph))
     value = total / dt
     bpu = algorithmic_bytes_per_update(C)
-    launches = max(1, ctr["scatter_launches"])
+    # the timed launches (every TIME_EVERY-th of the timed region)
+    launches = max(1, ctr["timed_launches"])
     kname = "k_tile_scatter" if args.mode == "staged" else "k_scatter_atomic"
     avg_ms = ctr["scatter_ms"] / launches
-    upd_per_launch = total / launches
+    upd_per_launch = ctr["timed_updates"] / launches
     achieved = bpu * upd_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -528,7 +536,9 @@ def main():
                 "kernel": kname, "kernel_avg_ms": round(avg_ms, 5),
                 "bin_avg_ms": round(ctr["bin_ms"] / launches, 5),
                 "bytes_per_update": bpu,
-                "updates_per_launch": round(upd_per_launch, 1)}
+                "updates_per_launch": round(upd_per_launch, 1),
+                "timed_launches": ctr["timed_launches"],
+                "timed_every": TIME_EVERY}
     out = {
         "metric": "edge updates/sec + % HBM roofline; p50/p99 connectivity-query latency",
         "value": round(value, 1), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
@@ -545,9 +555,9 @@ def main():
         print("bench: timing plain path", file=sys.stderr, flush=True)
         pdt, ptot, pctr = run_path(cupk, torch, packed, sizes, args.steps, args.warmup,
                                    cupk.SCATTER_ATOMIC)
-        pl = max(1, pctr["scatter_launches"])
+        pl = max(1, pctr["timed_launches"])
         pavg = pctr["scatter_ms"] / pl
-        pach = bpu * (ptot / pl) / (pavg * 1e-3) / 1e9
+        pach = bpu * (pctr["timed_updates"] / pl) / (pavg * 1e-3) / 1e9
         out["plain"] = {"value": round(ptot / pdt, 1), "unit": "updates/s",
                         "ms_per_step": round(pdt * 1e3 / args.steps, 4),
                         "kernel": "k_scatter_atomic", "kernel_avg_ms": round(pavg, 5),

@@ -92,8 +92,12 @@ typedef struct {
      * owned by the caller (e.g. a torch tensor) and kept alive until
      * cupk_free.  NULL = the library allocates it.  It is zeroed at init. */
     void *sketch_device_ptr;
-    /* Nonzero: record HIP events around every scatter launch so that
-     * cupk_counters reports the summed kernel time. */
+    /* k > 0: record HIP events around every k-th scatter launch (1 = every
+     * launch) so that cupk_counters reports the summed kernel time of the
+     * timed launches (scatter_ms, bin_ms) and their number and updates
+     * (timed_launches, timed_updates).  Every event recorded between two
+     * kernels leaves the GPU idle for a few microseconds, so sampling keeps
+     * the timed run close to an untimed one. */
     uint32_t time_kernels;
     /* Staged scatter tuning (0 = library default / autotuned value):
      * vertices per LDS tile and depth rows kept in LDS. */
@@ -156,8 +160,8 @@ typedef struct {
     uint64_t slabs_reduced;      /* vertex sketches read by set reductions       */
     uint64_t sample_failed;      /* trees whose sample failed (kept dirty)       */
     uint64_t scatter_launches;   /* scatter kernel launches                      */
-    double scatter_ms;           /* summed scatter kernel time (time_kernels)    */
-    double bin_ms;               /* summed binning kernel time (time_kernels)    */
+    double scatter_ms;           /* summed scatter kernel time of timed launches */
+    double bin_ms;               /* summed binning time of timed launches        */
     double host_wait_ms;         /* host time waiting for classification results */
     double host_flags_ms;        /* host time applying flagged updates to forest */
     double host_rounds_ms;       /* host time in replacement rounds (incl. GPU)  */
@@ -169,6 +173,8 @@ typedef struct {
     uint64_t walks_contracted;   /* runs of flagged updates walked contracted    */
     uint64_t walks_fallback;     /* runs whose piece search gave up (walked one
                                     update at a time)                           */
+    uint64_t timed_launches;     /* scatter launches timed (time_kernels)        */
+    uint64_t timed_updates;      /* updates in the timed launches                */
 } cupk_counters_t;
 
 /* Bytes of device memory the sketch of (V, C, D) occupies. */

@@ -68,7 +68,9 @@ class cupk_counters_t(ctypes.Structure):
         ("level_passes", ctypes.c_uint64), ("level_repairs", ctypes.c_uint64),
         ("level_failed", ctypes.c_uint64),
         ("walks_contracted", ctypes.c_uint64),
-        ("walks_fallback", ctypes.c_uint64)]
+        ("walks_fallback", ctypes.c_uint64),
+        ("timed_launches", ctypes.c_uint64),
+        ("timed_updates", ctypes.c_uint64)]
 
 
 class cupk_serve_opts(ctypes.Structure):
@@ -181,7 +183,8 @@ class Context:
         opts = cupk_opts()
         opts.scatter_mode = scatter_mode
         opts.max_batch = max_batch
-        opts.time_kernels = 1 if time_kernels else 0
+        # True = every launch; an int k = every k-th launch
+        opts.time_kernels = int(time_kernels)
         opts.tile_vertices = tile_vertices
         opts.lds_rows = lds_rows
         opts.chunk_records = chunk_records

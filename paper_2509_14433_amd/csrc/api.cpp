@@ -626,7 +626,9 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
     // between two kernels leaves the GPU idle for a few microseconds.
     cupk_ctx::TimerSlot *ts = nullptr;
     hipEvent_t mark = ctx->ev_hdr;
-    if (ctx->opts.time_kernels) {
+    if (ctx->opts.time_kernels && ctx->ctr.scatter_launches % ctx->opts.time_kernels == 0) {
+        ctx->ctr.timed_launches++;
+        ctx->ctr.timed_updates += n;
         ts = &ctx->timers[ctx->timer_head];
         ctx->timer_head = (ctx->timer_head + 1) % kTimerRing;
         if (ts->busy) {
