@@ -591,7 +591,7 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
                                              : offsetof(SmallResult, fupd) + (size_t)n * 8;
         HIPCHK(hipMemcpyAsync(ctx->h_small, ctx->d_small, bytes, hipMemcpyDeviceToHost, ctx->s));
         HIPCHK(hipEventRecord(ctx->ev_hdr, ctx->s));
-        ctx->hdr_event = ctx->ev_hdr;
+        ctx->hdr_polled = false;
         // the scatter follows the copy: the host walks the flags meanwhile
         HIPCHK(launch_small_scatter(ctx->s, d_upd, n, dev_sketch(ctx), ctx->d_small));
         ctx->ctr.scatter_launches++;
@@ -620,12 +620,13 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
         rc = enqueue_classify(ctx, ctx->s, n);
         if (rc != CUPK_OK) return rc;
     }
-    // One marker after the classify step serves the host's wait for the
-    // header, the copy stream's wait (flag compaction) and, when kernels are
-    // timed, the start of the binning interval: every event recorded
-    // between two kernels leaves the GPU idle for a few microseconds.
+    // The host waits for the header by its sequence number, not an event:
+    // every event recorded between two kernels leaves the GPU idle for a few
+    // microseconds.  (Flag compaction on the copy stream is launched only
+    // after the header has arrived, so after classification has finished.)
+    ctx->hdr_seq++;
+    ctx->hdr_polled = true;
     cupk_ctx::TimerSlot *ts = nullptr;
-    hipEvent_t mark = ctx->ev_hdr;
     if (ctx->opts.time_kernels && ctx->ctr.scatter_launches % ctx->opts.time_kernels == 0) {
         ctx->ctr.timed_launches++;
         ctx->ctr.timed_updates += n;
@@ -636,11 +637,8 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
             rc = harvest_timers(ctx, false);
             if (rc != CUPK_OK) return rc;
         }
-        mark = ts->t0;
+        HIPCHK(hipEventRecord(ts->t0, ctx->s));
     }
-    HIPCHK(hipEventRecord(mark, ctx->s));
-    ctx->hdr_event = mark;
-    HIPCHK(hipStreamWaitEvent(ctx->cs, mark, 0));
 
     // scatter (skipped on device if the batch was rejected)
     if (graph) {
@@ -689,6 +687,28 @@ int walk_exact(cupk_ctx *ctx, const uint64_t *upd, uint32_t k0, uint32_t k1, boo
     return 0;
 }
 
+// Wait until the header with sequence number `seq` has been published to
+// host memory.  The stream is queried now and then: if it has drained and
+// the header is still missing, or it reports an error, the wait fails
+// instead of spinning on.
+static int wait_header(cupk_ctx *ctx, uint32_t seq)
+{
+    uint32_t *w = &ctx->h_hdr[HDR_SEQ];
+    for (uint32_t spin = 1;; spin++) {
+        if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return CUPK_OK;
+        if ((spin & 255) == 0) {
+            const hipError_t e = hipStreamQuery(ctx->s);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return CUPK_OK;
+                return ctx->fail(hipErrorUnknown, "classification header was not published",
+                                 __LINE__);
+            }
+            if (e != hipErrorNotReady) return ctx->fail(e, "hipStreamQuery", __LINE__);
+        }
+        __builtin_ia32_pause();
+    }
+}
+
 // Host side of a pass: wait for the classification header, pack and fetch
 // the flagged updates in growing chunks and walk them into the forest.
 // exact: stop at the first cut and report its position in the pass and its
@@ -697,7 +717,12 @@ int walk_pass(cupk_ctx *ctx, uint32_t n, bool exact, uint32_t *cut_pos, uint32_t
               uint32_t *cut_b, uint32_t *nflag_out, double *t_wait, double *t_copy)
 {
     double t0 = now_ms();
-    HIPCHK(hipEventSynchronize(ctx->hdr_event));
+    if (ctx->hdr_polled) {
+        int rw = wait_header(ctx, ctx->hdr_seq);
+        if (rw != CUPK_OK) return rw;
+    } else {
+        HIPCHK(hipEventSynchronize(ctx->ev_hdr));
+    }
     double t1 = now_ms();
     ctx->ctr.host_wait_ms += t1 - t0;
     *t_wait = t1 - t0;
@@ -980,7 +1005,9 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     HIPCHK(hipHostMalloc((void **)&ctx->h_par, (size_t)V * 4, hipHostMallocDefault));
     HIPCHK(hipMalloc((void **)&ctx->d_hdr, HDR_WORDS * 4));
     HIPCHK(hipMemset(ctx->d_hdr, 0, HDR_WORDS * 4));
-    HIPCHK(hipHostMalloc((void **)&ctx->h_hdr, HDR_WORDS * 4, hipHostMallocDefault));
+    // coherent: the scan kernel's stores reach the host without a flush
+    HIPCHK(hipHostMalloc((void **)&ctx->h_hdr, HDR_WORDS * 4, hipHostMallocCoherent));
+    memset(ctx->h_hdr, 0, HDR_WORDS * 4);
     HIPCHK(hipMalloc((void **)&ctx->d_nitems, 4));
     HIPCHK(hipMalloc((void **)&ctx->d_desc, sizeof(BatchDesc)));
     HIPCHK(hipHostMalloc((void **)&ctx->h_desc, sizeof(BatchDesc), hipHostMallocDefault));
@@ -1301,6 +1328,7 @@ static int time_scatter_once(cupk_ctx *ctx, const uint64_t *d, uint32_t n, hipEv
     ctx->cur_desc.upd = d;
     ctx->cur_desc.n = n;
     rc = enqueue_classify(ctx, ctx->s, n);
+    ctx->hdr_seq++;  // published by the scan kernel (read after the sync below)
     if (rc != CUPK_OK) return rc;
     HIPCHK(hipEventRecord(e0, ctx->s));
     rc = enqueue_bin(ctx, ctx->s, n);

@@ -57,7 +57,8 @@ struct cupk_ctx {
     hipStream_t s = nullptr, cs = nullptr;
     bool own_stream = false;
     hipEvent_t ev_hdr = nullptr;
-    hipEvent_t hdr_event = nullptr;  // marks the current pass's header (ev_hdr or a timer)
+    uint32_t hdr_seq = 0;      // headers published by the device so far (expected)
+    bool hdr_polled = false;   // current pass: wait for hdr_seq (else for ev_hdr)
     struct TimerSlot {
         hipEvent_t t0, tb, t1;
         bool busy;

@@ -122,13 +122,21 @@ DEVI uint32_t block_exscan(uint32_t x, uint32_t &total, uint32_t *sh)
 // The counts are zeroed for the next batch.
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict__ cnt,
                                                             uint32_t ntiles, ScanArgs a,
-                                                            const uint32_t *__restrict__ hdr,
+                                                            uint32_t *__restrict__ hdr,
                                                             uint32_t *__restrict__ hout)
 {
     __shared__ uint32_t sh[160];
     const bool err = hdr[HDR_ERR] != 0;
-    // the header goes straight to pinned host memory (no copy)
-    if (threadIdx.x < 3) hout[threadIdx.x] = hdr[threadIdx.x];
+    // the header goes straight to host memory (no copy, no event): words
+    // first, then the sequence number with release semantics
+    if (threadIdx.x == 0) {
+        hout[HDR_ERR] = hdr[HDR_ERR];
+        hout[HDR_NFLAG] = hdr[HDR_NFLAG];
+        hout[HDR_NFLAG_DEL] = hdr[HDR_NFLAG_DEL];
+        const uint32_t seq = hdr[HDR_SEQ] + 1;
+        hdr[HDR_SEQ] = seq;
+        __hip_atomic_store(&hout[HDR_SEQ], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     if (!a.off) return;
     if (err) {
         // rejected batch: leave the counts zeroed for the next one

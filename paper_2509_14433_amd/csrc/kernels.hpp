@@ -27,7 +27,17 @@ struct BatchDesc {
 // Header words.  ERR / NFLAG / NFLAG_DEL are accumulated by the classify
 // kernel; SCAT_DONE counts finished blocks of the scatter kernel, whose last
 // block clears ERR / NFLAG / NFLAG_DEL (and SCAT_DONE) for the next batch.
-enum { HDR_ERR = 0, HDR_NFLAG = 1, HDR_NFLAG_DEL = 2, HDR_SCAT_DONE = 3, HDR_WORDS = 4 };
+// SEQ counts published headers: the one-block kernel after classify copies
+// ERR / NFLAG / NFLAG_DEL to the host, then the incremented SEQ (release
+// store), which the host waits for.
+enum {
+    HDR_ERR = 0,
+    HDR_NFLAG = 1,
+    HDR_NFLAG_DEL = 2,
+    HDR_SCAT_DONE = 3,
+    HDR_SEQ = 4,
+    HDR_WORDS = 8
+};
 
 // Where the tile scan (run by the last classify block) writes: bin offsets
 // and fill cursors (ntiles + 1 words each), work items (tile, chunk) and
@@ -49,8 +59,9 @@ struct StagedParams {
 // Per-batch: validation, structural classification and compaction of the
 // flagged updates.  hdr's ERR / NFLAG / NFLAG_DEL words must be zero (as
 // the previous batch's scatter leaves them).  A one-block kernel after it
-// writes their final values to `hout` (pinned host memory, HDR_WORDS
-// words: no copy needed).  When `tile_cnt` is non-null the classify kernel
+// writes their final values to `hout` (coherent pinned host memory,
+// HDR_WORDS words: no copy needed), then the next sequence number at
+// hout[HDR_SEQ].  When `tile_cnt` is non-null the classify kernel
 // also counts how many endpoint records each vertex tile gets, and the
 // one-block kernel scans the counts into `sa` (sa.off set).  Flagged updates of
 // classify block b (positions [b*4096, (b+1)*4096)) land in stream order at
