@@ -578,6 +578,88 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
     }
 }
 
+// Fill for up to kFillStageTiles tiles: the block's 2*kFillPerBlock records
+// are first counting-sorted by tile in LDS, then written out in that order,
+// so that the lanes of a wave store one (block, tile) run after another into
+// consecutive bin words (coalesced) instead of 8-byte words scattered over
+// all tiles.  Dynamic LDS: fill_stage_lds(ntiles) bytes.
+constexpr uint32_t kFillStageTiles = 2 * kFillThreads;
+static size_t fill_stage_lds(uint32_t ntiles)
+{
+    return (size_t)2 * kFillPerBlock * 8 + (size_t)2 * ntiles * 4 + 160 * 4;
+}
+
+__global__ __launch_bounds__(kFillThreads) void k_tile_fill_staged(
+    const BatchDesc *__restrict__ desc, BatchDesc dv, uint32_t V, uint32_t tile_shift,
+    uint32_t ntiles, uint32_t *__restrict__ cur, uint64_t *__restrict__ bins,
+    const uint32_t *__restrict__ hdr)
+{
+    extern __shared__ uint64_t fsm[];
+    uint64_t *stage = fsm;                                   // records in tile order
+    uint32_t *lcnt = (uint32_t *)(fsm + 2 * kFillPerBlock);  // per tile: count, then bin base
+    uint32_t *lpre = lcnt + ntiles;                          // per tile: first stage slot
+    uint32_t *sh = lpre + ntiles;                            // scan scratch (160 words)
+    if (hdr[HDR_ERR]) return;
+    const uint64_t *__restrict__ upd = desc ? desc->upd : dv.upd;
+    const uint32_t n = desc ? desc->n : dv.n;
+    const uint32_t begin = blockIdx.x * kFillPerBlock;
+    if (begin >= n) return;
+    uint64_t p[kFillPerThread];
+#pragma unroll
+    for (uint32_t k = 0; k < kFillPerThread; k++) {
+        const uint32_t i = begin + k * kFillThreads + threadIdx.x;
+        p[k] = i < n ? upd[i] : 0;
+    }
+    for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) lcnt[t] = 0;
+    __syncthreads();
+    // ranks of each record inside its tile's share of this block
+    uint32_t ru[kFillPerThread], rv[kFillPerThread];
+#pragma unroll
+    for (uint32_t k = 0; k < kFillPerThread; k++) {
+        ru[k] = rv[k] = 0;
+        if (begin + k * kFillThreads + threadIdx.x >= n) continue;
+        uint32_t u, v;
+        bool del;
+        unpack(p[k], V, u, v, del);
+        ru[k] = atomicAdd(&lcnt[u >> tile_shift], 1u);
+        rv[k] = atomicAdd(&lcnt[v >> tile_shift], 1u);
+    }
+    __syncthreads();
+    // first stage slot of each tile (two tiles per thread), and one
+    // contiguous bin range per tile present in this block
+    const uint32_t t0 = 2 * threadIdx.x;
+    const uint32_t c0 = t0 < ntiles ? lcnt[t0] : 0u;
+    const uint32_t c1 = t0 + 1 < ntiles ? lcnt[t0 + 1] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exscan<kFillThreads>(c0 + c1, tot, sh);
+    if (t0 < ntiles) {
+        lpre[t0] = ex;
+        lcnt[t0] = c0 ? atomicAdd(&cur[t0], c0) : 0u;
+    }
+    if (t0 + 1 < ntiles) {
+        lpre[t0 + 1] = ex + c0;
+        lcnt[t0 + 1] = c1 ? atomicAdd(&cur[t0 + 1], c1) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kFillPerThread; k++) {
+        if (begin + k * kFillThreads + threadIdx.x >= n) continue;
+        uint32_t u, v;
+        bool del;
+        unpack(p[k], V, u, v, del);
+        const uint64_t rec = (uint64_t)u | ((uint64_t)v << 32);
+        stage[lpre[u >> tile_shift] + ru[k]] = rec;
+        stage[lpre[v >> tile_shift] + rv[k]] = rec | kRecV;
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < tot; j += blockDim.x) {
+        const uint64_t rec = stage[j];
+        const uint32_t e = (rec & kRecV) ? (uint32_t)(rec >> 32) & 0x7fffffffu : (uint32_t)rec;
+        const uint32_t t = e >> tile_shift;
+        bins[lcnt[t] + (j - lpre[t])] = rec;
+    }
+}
+
 constexpr uint32_t kTileThreads = 256;
 
 // XOR one (record, column) pair into the endpoint's LDS delta, or into HBM
@@ -702,8 +784,12 @@ hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32
 {
     if (grid_n == 0) return hipSuccess;
     const uint32_t fb = (grid_n + kFillPerBlock - 1) / kFillPerBlock;
-    k_tile_fill<<<fb, kFillThreads, 0, s>>>(desc, dv, sk.V, p.tile_shift, p.ntiles, tile_cur,
-                                            bins, hdr);
+    if (p.ntiles <= kFillStageTiles)
+        k_tile_fill_staged<<<fb, kFillThreads, fill_stage_lds(p.ntiles), s>>>(
+            desc, dv, sk.V, p.tile_shift, p.ntiles, tile_cur, bins, hdr);
+    else
+        k_tile_fill<<<fb, kFillThreads, 0, s>>>(desc, dv, sk.V, p.tile_shift, p.ntiles, tile_cur,
+                                                bins, hdr);
     return hipGetLastError();
 }
 
