@@ -146,6 +146,13 @@ typedef struct {
      * net change applied), which gives the same forest, dirty trees and
      * counts. */
     uint32_t walk_plain;
+    /* Nonzero: split the trees broken by a batch's cuts (relabel every piece
+     * but the largest) before the first replacement round.  Default: the
+     * first round works on the pieces as found by the same search, links
+     * them by parent pointers only and labels the final trees once, which
+     * gives the same forest and counts without relabelling pieces that the
+     * round links back together. */
+    uint32_t split_rounds;
 } cupk_opts;
 
 /* Counters, cumulative since init. */

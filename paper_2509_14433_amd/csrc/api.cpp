@@ -172,6 +172,270 @@ int reduce_and_sample(cupk_ctx *ctx, int slot, const std::vector<uint32_t> &vmem
     return CUPK_OK;
 }
 
+// First replacement round over the pieces of the trees that pending
+// removals broke, without splitting them first.
+//
+// Splitting relabels every piece but the largest, and when the first round
+// links most pieces back together each link relabels one side again.  Here
+// the pieces below removed edges are listed top-down into one buffer (their
+// members are the round's vertex sets anyway); the old root's piece is
+// sized by subtraction and listed only when it is sampled or carried.  The
+// round decides its links on a union-find over pieces and applies them to
+// the parent pointers only, and the final trees are labelled once: a tree
+// holding a broken tree's unvisited piece keeps that tree's label, the
+// others keep the label most of their vertices already have or take a fresh
+// one, and only the vertices of listed pieces whose label changes are
+// written.  The round is the regular first round (same sets, order,
+// samples, links and dirty marks), so the forest is the one a split would
+// give.
+//
+// Applies only when the broken trees are the only dirty ones.  Returns 1
+// when the round ran (*done: no further round), 0 when the caller should
+// split and run the regular round instead, or a negative error.
+static int round_one_pieces(cupk_ctx *ctx, int slot, std::vector<RoundSet> &nsets, bool *linked,
+                            bool *done)
+{
+    Forest &F = ctx->forest;
+    if (F.pending().empty() || !F.dirty_labels().empty()) return 0;
+    const double tr0 = now_ms();
+    const uint32_t V = F.V();
+    auto &pid = ctx->piece_id;    // vertex -> listed piece (stamped)
+    auto &pst = ctx->piece_stamp;
+    auto &lst = ctx->piece_label_stamp;  // broken label -> its unvisited piece (stamped)
+    auto &lpc = ctx->piece_of_label;
+    // stamps: ep marks this call's pieces, ep + 1 the labels it has given
+    if (pid.size() != V || ctx->piece_epoch >= 0xfffffff0u) {
+        pid.assign(V, 0);
+        pst.assign(V, 0);
+        lst.assign(V, 0);
+        lpc.assign(V, 0);
+        ctx->piece_epoch = 0;
+    }
+    ctx->piece_epoch += 2;
+    const uint32_t ep = ctx->piece_epoch;
+    struct Piece {
+        uint32_t label, top, size, minv;
+        size_t off;  // members at mem[off, off + size) once listed
+        bool listed;
+    };
+    std::vector<Piece> P;
+    std::vector<uint32_t> &mem = ctx->piece_mem;
+    mem.clear();
+    // one piece top-down into mem, stamping its vertices
+    auto list = [&](uint32_t i) {
+        Piece &p = P[i];
+        const size_t b = mem.size();
+        mem.push_back(p.top);
+        uint32_t mn = kNone;
+        for (size_t qi = b; qi < mem.size(); qi++) {
+            const uint32_t x = mem[qi];
+            mn = std::min(mn, x);
+            pid[x] = i;
+            pst[x] = ep;
+            for (uint32_t y = F.first_child(x); y != kNone; y = F.next_sibling(y)) mem.push_back(y);
+        }
+        p.off = b;
+        p.size = (uint32_t)(mem.size() - b);
+        p.minv = mn;
+        p.listed = true;
+    };
+    // Pieces of each broken tree: one per removal, listed, and the old
+    // root's, sized by subtraction and listed only when needed.
+    std::vector<std::pair<uint32_t, uint32_t>> pend(F.pending().begin(), F.pending().end());
+    std::sort(pend.begin(), pend.end());
+    for (size_t g0 = 0; g0 < pend.size();) {
+        const uint32_t old = pend[g0].first;
+        size_t g1 = g0;
+        while (g1 < pend.size() && pend[g1].first == old) g1++;
+        uint32_t listed = 0;
+        for (size_t i = g0; i < g1; i++) {
+            P.push_back({old, pend[i].second, 0, kNone, 0, false});
+            list((uint32_t)P.size() - 1);
+            listed += P.back().size;
+        }
+        P.push_back({old, F.tree_root(old), F.tree_size(old) - listed, kNone, 0, false});
+        lst[old] = ep;
+        lpc[old] = (uint32_t)P.size() - 1;
+        g0 = g1;
+    }
+    const uint32_t np = (uint32_t)P.size();
+    // the left-out piece: largest, ties by smallest vertex (pieces in a tie
+    // are listed to know their smallest vertex)
+    uint32_t maxs = 0;
+    uint64_t total = 0;
+    for (const Piece &p : P) {
+        maxs = std::max(maxs, p.size);
+        total += p.size;
+    }
+    uint32_t nmax = 0;
+    for (const Piece &p : P) nmax += p.size == maxs;
+    if (nmax > 1)
+        for (uint32_t i = 0; i < np; i++)
+            if (P[i].size == maxs && !P[i].listed) list(i);
+    uint32_t skip = kNone;
+    for (uint32_t i = 0; i < np; i++)
+        if (P[i].size == maxs && (skip == kNone || P[i].minv < P[skip].minv)) skip = i;
+    // every other piece is sampled: list the unvisited ones; the left-out one
+    // is listed too (and carried, so that the next round can be built from
+    // this round's sets) when it is no larger than the others together
+    for (uint32_t i = 0; i < np; i++)
+        if (i != skip && !P[i].listed) list(i);
+    if (!P[skip].listed && 2 * (uint64_t)P[skip].size <= total) list(skip);
+    const bool carry = P[skip].listed;
+    // sets in ascending order of smallest vertex, the carried left-out last
+    std::vector<uint32_t> gord;
+    for (uint32_t i = 0; i < np; i++)
+        if (i != skip) gord.push_back(i);
+    std::sort(gord.begin(), gord.end(), [&](uint32_t a, uint32_t b) { return P[a].minv < P[b].minv; });
+    if (carry) gord.push_back(skip);
+    std::vector<uint32_t> vmem, voff{0}, none;
+    vmem.reserve(mem.size());
+    nsets.clear();
+    for (uint32_t i : gord) {
+        nsets.push_back({P[i].label, P[i].minv, P[i].size, i != skip});
+        vmem.insert(vmem.end(), mem.begin() + P[i].off, mem.begin() + P[i].off + P[i].size);
+        voff.push_back((uint32_t)vmem.size());
+    }
+    ctx->ctr.rounds++;
+    const double tr1 = now_ms();
+    int rc = reduce_and_sample(ctx, slot, vmem, voff, none, none);
+    if (rc != CUPK_OK) return rc;
+    const double tr2 = now_ms();
+    const int32_t *res = ctx->h_res.p;
+    const size_t k = nsets.size();
+    // the piece of a vertex: listed (stamped), or its broken tree's unvisited one
+    auto piece_of = [&](uint32_t v) -> uint32_t {
+        if (pst[v] == ep) return pid[v];
+        const uint32_t l = F.label(v);
+        return lst[l] == ep ? lpc[l] : kNone;
+    };
+    for (size_t i = 0; i < k; i++) {
+        if (!nsets[i].sampled || res[3 * i] != CUPK_OK) continue;
+        if (piece_of((uint32_t)res[3 * i + 1]) == kNone ||
+            piece_of((uint32_t)res[3 * i + 2]) == kNone) {
+            ctx->ctr.rounds--;  // an edge out of the broken trees: the regular round
+            return 0;           // runs instead (nothing has been changed)
+        }
+    }
+    if (ctx->trace)
+        fprintf(stderr,
+                "cupk   pieces=%u sets=%zu left_out=%u vmembers=%zu search=%.3f gpu=%.3f ms\n",
+                np, k, P[skip].size, vmem.size(), tr1 - tr0, tr2 - tr1);
+    // links on a union-find over pieces (sets are already in ascending order
+    // of smallest vertex); parent pointers follow at once
+    std::vector<uint32_t> up(np), groot(np), gsize(np);
+    std::vector<uint8_t> gclean(np, 0);
+    for (uint32_t i = 0; i < np; i++) {
+        up[i] = i;
+        groot[i] = P[i].top;
+        gsize[i] = P[i].size;
+    }
+    auto find = [&](uint32_t a) {
+        while (up[a] != a) a = up[a] = up[up[a]];
+        return a;
+    };
+    const double tl0 = now_ms();
+    bool lk = false, failed = false;
+    uint32_t nlinks = 0;
+    for (size_t i = 0; i < k; i++) {
+        if (!nsets[i].sampled || res[3 * i] != CUPK_OK) continue;
+        const uint32_t x = (uint32_t)res[3 * i + 1], y = (uint32_t)res[3 * i + 2];
+        const uint32_t rx = find(piece_of(x)), ry = find(piece_of(y));
+        if (rx == ry) continue;
+        F.link_structural(x, y);  // x's tree hangs below y: the root stays y's
+        const uint32_t r = gsize[rx] > gsize[ry] ? rx : ry, o = r == rx ? ry : rx;
+        up[o] = r;
+        groot[r] = groot[ry];
+        gsize[r] = gsize[rx] + gsize[ry];
+        ctx->ctr.links++;
+        nlinks++;
+        lk = true;
+    }
+    if (ctx->trace) fprintf(stderr, "cupk   links=%u in %.3f ms\n", nlinks, now_ms() - tl0);
+    for (size_t i = 0; i < k; i++) {
+        if (!nsets[i].sampled) continue;
+        const int st = res[3 * i];
+        if (st == CUPK_EMPTY) {
+            // a whole component: clean, unless it was merged this round
+            const uint32_t r = find(gord[i]);
+            if (gsize[r] == nsets[i].size) gclean[r] = 1;
+        } else if (st == CUPK_SAMPLE_FAILED) {
+            ctx->ctr.sample_failed++;
+            failed = true;
+        }
+    }
+    if (!lk) {
+        if (!failed) gclean[find(skip)] = 1;
+        *done = true;
+    }
+    // Final labels.  A broken tree's unvisited piece cannot be relabelled:
+    // its tree keeps that label.  Other trees keep the old label with the
+    // most of their listed vertices when no other tree has it, else take a
+    // fresh one.
+    std::vector<uint32_t> glabel(np, kNone), weight(np, 0), best(np, kNone);
+    std::vector<uint32_t> roots;
+    for (uint32_t i = 0; i < np; i++) {
+        const uint32_t r = find(i);
+        if (r == i) roots.push_back(r);
+    }
+    std::vector<uint32_t> used;  // labels given to trees (stamped via lst = ep + 1)
+    auto take = [&](uint32_t r, uint32_t l) {
+        glabel[r] = l;
+        used.push_back(l);
+        lst[l] = ep + 1;  // marks the label as given (no piece lookup needs it any more)
+    };
+    for (uint32_t i = 0; i < np; i++)
+        if (!P[i].listed) {
+            const uint32_t r = find(i);
+            if (glabel[r] == kNone) take(r, P[i].label);
+            else return ctx->invalid("two unvisited pieces in one tree");  // cannot happen
+        }
+    {
+        // per tree, the old label of its largest listed share
+        std::vector<std::pair<uint64_t, uint32_t>> share;  // ((root << 32) | label, size)
+        for (uint32_t i = 0; i < np; i++)
+            if (P[i].listed) share.push_back({(uint64_t)find(i) << 32 | P[i].label, P[i].size});
+        std::sort(share.begin(), share.end());
+        std::vector<std::pair<uint32_t, uint32_t>> cand;  // (weight, root)
+        for (size_t a = 0; a < share.size();) {
+            size_t b = a;
+            uint32_t w = 0;
+            while (b < share.size() && share[b].first == share[a].first) w += share[b++].second;
+            const uint32_t r = (uint32_t)(share[a].first >> 32), l = (uint32_t)share[a].first;
+            if (glabel[r] == kNone && w > weight[r]) {
+                weight[r] = w;
+                best[r] = l;
+            }
+            a = b;
+        }
+        for (uint32_t r : roots)
+            if (glabel[r] == kNone) cand.push_back({weight[r], r});
+        std::sort(cand.begin(), cand.end(), std::greater<>());
+        for (auto &c : cand) {
+            const uint32_t r = c.second, l = best[r];
+            if (lst[l] != ep + 1) take(r, l);
+        }
+        for (uint32_t r : roots)
+            if (glabel[r] == kNone) take(r, F.settle_take_label());
+    }
+    for (uint32_t i = 0; i < np; i++) {
+        const uint32_t l = glabel[find(i)];
+        if (P[i].listed && P[i].label != l) F.settle_relabel(mem.data() + P[i].off, P[i].size, l);
+    }
+    // broken trees' labels that no final tree kept are given back
+    for (size_t g = 0; g < pend.size(); g++) {
+        const uint32_t l = pend[g].first;
+        if (lst[l] == ep) {
+            lst[l] = ep + 1;
+            F.settle_drop_label(l);
+        }
+    }
+    for (uint32_t r : roots) F.settle_tree(glabel[r], groot[r], gsize[r], gclean[r] == 0);
+    F.settle_done();
+    if (lk) *linked = true;
+    return 1;
+}
+
 // Replacement rounds over the dirty trees.
 //
 // Clean trees are whole components, so every edge that leaves a dirty tree
@@ -185,9 +449,6 @@ int reduce_and_sample(cupk_ctx *ctx, int slot, const std::vector<uint32_t> &vmem
 int run_rounds(cupk_ctx *ctx)
 {
     Forest &F = ctx->forest;
-    const double ts0 = now_ms();
-    F.split_pending();
-    if (ctx->trace) fprintf(stderr, "cupk   split=%.3f ms\n", now_ms() - ts0);
     std::vector<RoundSet> sets;  // sets of the previous round, in d_sig order
     std::vector<uint32_t> vmem, voff, fmem, foff;
     struct Group {
@@ -197,8 +458,19 @@ int run_rounds(cupk_ctx *ctx)
     };
     int slot = 0;
     bool linked_any = false;
+    bool done = false;
+    const int r1 = ctx->opts.split_rounds ? 0 : round_one_pieces(ctx, slot, sets, &linked_any, &done);
+    if (r1 < 0) return r1;
+    if (r1 == 1) {
+        slot = 1 - slot;
+    } else {
+        sets.clear();
+        const double ts0 = now_ms();
+        F.split_pending();
+        if (ctx->trace) fprintf(stderr, "cupk   split=%.3f ms\n", now_ms() - ts0);
+    }
     double tr0 = now_ms();
-    for (;;) {
+    for (; !done;) {
         const std::vector<uint32_t> labels = F.dirty_labels();
         if (labels.empty()) break;
         if (labels.size() == 1) {

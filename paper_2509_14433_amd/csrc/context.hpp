@@ -116,6 +116,9 @@ struct cupk_ctx {
     bool trace = false;  // CUPK_TRACE=1: per-batch host timings on stderr
     std::unique_ptr<cupk::Server> server;
     std::vector<int32_t> round_gmap;  // label -> round group, -1 elsewhere
+    // first round over pieces (stamped per use)
+    std::vector<uint32_t> piece_id, piece_stamp, piece_label_stamp, piece_of_label, piece_mem;
+    uint32_t piece_epoch = 0;
     std::unique_ptr<cupk::Levels> levels;  // multi-level hierarchy (opts.levels)
     cupk::Forest forest;
     cupk::Contraction contract;  // contracted walks of flagged runs

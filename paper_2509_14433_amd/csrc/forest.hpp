@@ -264,6 +264,81 @@ class Forest {
         pending_.clear();
     }
 
+    // ---- pieces of pending removals, settled without a split ------------
+    //
+    // After a run of remove_edge(), the trees they broke can be worked on as
+    // their pieces (each the subtree below its top: the old root or a
+    // removed edge's child endpoint) without relabelling: pending() names
+    // them, link_structural() joins pieces by parent pointers only, and
+    // settle_*() then assigns the final labels, sizes, roots and dirty
+    // marks.  Labels, sizes and roots describe the trees before the
+    // removals until the settle.
+    const std::vector<std::pair<uint32_t, uint32_t>> &pending() const { return pending_; }
+    uint32_t first_child(uint32_t x) const { return first_kid_[x]; }
+    uint32_t next_sibling(uint32_t x) const { return next_sib_[x]; }
+    // Re-root x's tree at x (one path reversed) and hang it below y.
+    void link_structural(uint32_t x, uint32_t y)
+    {
+        for (uint32_t c = x, below = kNone; c != kNone;) {
+            const uint32_t up = par_[c];
+            if (up != kNone) remove_kid(up, c);
+            if (below != kNone) {
+                par_[c] = below;
+                add_kid(below, c);
+            }
+            below = c;
+            c = up;
+        }
+        par_[x] = y;
+        add_kid(y, x);
+        n_trees_--;
+        n_edges_++;
+    }
+    // Root of x's tree, by parent pointers.
+    uint32_t root_of(uint32_t x) const
+    {
+        while (par_[x] != kNone) x = par_[x];
+        return x;
+    }
+    // A fresh label (a new tree), and giving one back.
+    uint32_t settle_take_label()
+    {
+        const uint32_t l = free_.back();
+        free_.pop_back();
+        live_add(l);
+        dirty_[l] = 0;
+        return l;
+    }
+    void settle_drop_label(uint32_t l)
+    {
+        dirty_[l] = 0;
+        free_.push_back(l);
+        live_remove(l);
+    }
+    void settle_relabel(const uint32_t *v, size_t n, uint32_t l)
+    {
+        for (size_t i = 0; i < n; i++) lbl_[v[i]] = l;
+    }
+    // Relabel every vertex of the tree rooted at r (top-down).
+    void settle_relabel_tree(uint32_t r, uint32_t l)
+    {
+        queue_.clear();
+        queue_.push_back(r);
+        for (size_t qi = 0; qi < queue_.size(); qi++) {
+            const uint32_t x = queue_[qi];
+            lbl_[x] = l;
+            for (uint32_t y = first_kid_[x]; y != kNone; y = next_sib_[y]) queue_.push_back(y);
+        }
+    }
+    void settle_tree(uint32_t l, uint32_t root, uint32_t size, bool dirty)
+    {
+        root_[l] = root;
+        size_[l] = size;
+        dirty_[l] = 0;
+        if (dirty) set_dirty(l);
+    }
+    void settle_done() { pending_.clear(); }
+
     // Vertices of the tree with the given label (BFS from its root); also
     // returns the smallest vertex id.
     uint32_t collect(uint32_t label, std::vector<uint32_t> &out)

@@ -61,17 +61,18 @@ def rmat_ref():
                 truth=truth)
 
 
-@pytest.mark.parametrize("mode,graph,walk_plain", [("atomic", False, False),
-                                                   ("staged", False, False),
-                                                   ("staged", True, False),
-                                                   ("staged", False, True)])
-def test_rmat_ragged_batches(cupk, rmat_ref, mode, graph, walk_plain):
+@pytest.mark.parametrize("mode,graph,walk_plain,split", [("atomic", False, False, False),
+                                                         ("staged", False, False, False),
+                                                         ("staged", True, False, False),
+                                                         ("staged", False, True, False),
+                                                         ("staged", False, False, True)])
+def test_rmat_ragged_batches(cupk, rmat_ref, mode, graph, walk_plain, split):
     R = rmat_ref
     sm = cupk.SCATTER_ATOMIC if mode == "atomic" else cupk.SCATTER_STAGED
     ctx = cupk.Context(R["V"], R["C"], R["D"], R["cfg"]["S"], scatter_mode=sm, use_graph=graph,
-                       max_batch=4096, walk_plain=walk_plain)
+                       max_batch=4096, walk_plain=walk_plain, split_rounds=split)
     print(f"rmat n={len(R['u'])} batches={len(R['sizes'])} mode={mode} graph={graph} "
-          f"walk_plain={walk_plain}", flush=True)
+          f"walk_plain={walk_plain} split_rounds={split}", flush=True)
     off = 0
     for s in R["sizes"]:
         ctx.apply_updates(R["u"][off:off + s], R["v"][off:off + s], R["d"][off:off + s])
@@ -135,11 +136,16 @@ def _forest_targeted_run(cupk, ctx_apply, ctx_query, want_forest_fn, cfg):
     return answers, want, sk, fr, n_forest_del, g.k
 
 
-def test_forest_targeted_deletions_direct(cupk):
+@pytest.mark.parametrize("split", [False, True])
+def test_forest_targeted_deletions_direct(cupk, split):
+    """Cuts of forest edges in every chunk: the first replacement round runs
+    on the pieces (default) or after a split; both give the oracle's forest
+    and counts."""
     cfg = streamgen.SCALED[3]
     V = cfg["V"]
     C, D = _cd(V)
-    ctx = cupk.Context(V, C, D, cfg["S"])
+    print(f"forest-targeted split_rounds={split}", flush=True)
+    ctx = cupk.Context(V, C, D, cfg["S"], split_rounds=split)
     ans, want, sk, fr, nfd, k = _forest_targeted_run(
         cupk, lambda u, v, d: ctx.apply_updates(u, v, d),
         lambda a, b: int(ctx.connected(a, b)), None, cfg)
@@ -151,6 +157,7 @@ def test_forest_targeted_deletions_direct(cupk):
     assert ctx.forest_edges() == fr.forest_edges()
     ctr = ctx.counters()
     assert ctr["cuts"] == fr.n_cuts and ctr["rounds"] == fr.n_rounds
+    assert ctr["links"] == fr.n_links
     ctx.close()
 
 
