@@ -83,6 +83,13 @@ static int compare(Forest &A, Forest &B, uint64_t r)
         if (A.is_dirty(A.label(w)) != B.is_dirty(B.label(w))) return fail("dirty trees", r);
     for (uint32_t w = 0; w < A.V(); w++)
         if (A.tree_size(A.label(w)) != B.tree_size(B.label(w))) return fail("tree sizes", r);
+    // each tree's recorded root is a root of that tree
+    for (const Forest *F : {&A, &B})
+        for (uint32_t w = 0; w < F->V(); w++) {
+            const uint32_t rt = F->tree_root(F->label(w));
+            if (F->parent(rt) != cupk::kNone || F->label(rt) != F->label(w))
+                return fail("tree roots", r);
+        }
     return 0;
 }
 
