@@ -342,10 +342,12 @@ static int round_one_pieces(cupk_ctx *ctx, int slot, std::vector<RoundSet> &nset
         const uint32_t x = (uint32_t)res[3 * i + 1], y = (uint32_t)res[3 * i + 2];
         const uint32_t rx = find(piece_of(x)), ry = find(piece_of(y));
         if (rx == ry) continue;
-        F.link_structural(x, y);  // x's tree hangs below y: the root stays y's
+        // the endpoint with the shorter path to its root is re-rooted and
+        // hangs below the other: the other tree's root is the new root
+        const uint32_t nr = F.link_structural_short(x, y) ? groot[ry] : groot[rx];
         const uint32_t r = gsize[rx] > gsize[ry] ? rx : ry, o = r == rx ? ry : rx;
         up[o] = r;
-        groot[r] = groot[ry];
+        groot[r] = nr;
         gsize[r] = gsize[rx] + gsize[ry];
         ctx->ctr.links++;
         nlinks++;
@@ -604,17 +606,17 @@ int run_rounds(cupk_ctx *ctx)
                   [&](size_t a, size_t b) { return sets[a].minv < sets[b].minv; });
         bool linked = false, failed = false;
         const double tl0 = now_ms();
-        uint32_t nlinks = 0;
+        // the sampled edges, in ascending order of their tree's smallest
+        // vertex, link when their endpoints are in different trees at their
+        // turn (each merged tree relabelled once)
+        std::vector<std::pair<uint32_t, uint32_t>> cand;
         for (size_t i : ord) {
             if (!sets[i].sampled || res[3 * i] != CUPK_OK) continue;
-            const uint32_t x = (uint32_t)res[3 * i + 1], y = (uint32_t)res[3 * i + 2];
-            if (!F.same_tree(x, y)) {
-                F.link(x, y);
-                ctx->ctr.links++;
-                nlinks++;
-                linked = true;
-            }
+            cand.push_back({(uint32_t)res[3 * i + 1], (uint32_t)res[3 * i + 2]});
         }
+        const uint32_t nlinks = (uint32_t)F.link_many(cand, ctx->cand_linked);
+        ctx->ctr.links += nlinks;
+        linked = nlinks > 0;
         if (ctx->trace) fprintf(stderr, "cupk   links=%u in %.3f ms\n", nlinks, now_ms() - tl0);
         for (size_t i = 0; i < k; i++) {
             if (!sets[i].sampled) continue;

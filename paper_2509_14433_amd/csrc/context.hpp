@@ -122,6 +122,7 @@ struct cupk_ctx {
     std::unique_ptr<cupk::Levels> levels;  // multi-level hierarchy (opts.levels)
     cupk::Forest forest;
     cupk::Contraction contract;  // contracted walks of flagged runs
+    std::vector<uint8_t> cand_linked;  // which round candidates linked
     cupk_counters_t ctr = {};
     std::string err;
 

@@ -27,7 +27,8 @@
 //      are the same.
 //   3. The net change is applied to the whole forest: D0 edges that ended
 //      removed are removed, the pieces split once, and the edges the replay
-//      added that were not in T0 are linked.
+//      added that were not in T0 are linked (Forest::link_many: each merged
+//      tree relabelled once).
 //   4. Dirty marks: one by one, a tree ends dirty exactly when it holds an
 //      endpoint of an edge removed during the run (each removal makes both
 //      sides dirty, marks follow links, and every piece of a split holds
@@ -143,12 +144,18 @@ class Contraction {
                 ch = true;
             }
         F.split_pending();
+        net_.clear();
         for (uint64_t e : added_) {
             if (!live_.count(e)) continue;
             const uint32_t a = (uint32_t)e, b = (uint32_t)(e >> 32);
             if (F.is_edge(a, b)) continue;  // a D0 edge deleted and linked again
-            F.link(a, b);
+            net_.push_back({a, b});
             live_.erase(e);  // linked once, even if added more than once
+        }
+        // the net edges join different trees: all of them link (each merged
+        // tree relabelled once)
+        if (!net_.empty()) {
+            F.link_many(net_, net_linked_);
             ch = true;
         }
         for (uint32_t x : removed_) F.set_dirty(F.label(x));
@@ -208,6 +215,8 @@ class Contraction {
     size_t budget_per_update_ = 64, budget_base_ = 4096;
     std::vector<uint32_t> piece_top_, path_;
     std::vector<uint64_t> d0_, added_;
+    std::vector<std::pair<uint32_t, uint32_t>> net_;
+    std::vector<uint8_t> net_linked_;
     std::vector<uint32_t> removed_;
     std::unordered_set<uint64_t> live_;  // edges between pieces, by original endpoints
     std::vector<uint32_t> plbl_, ppar_;

@@ -5,9 +5,10 @@
 // (cutset Link / Cut, Sec. 2.2.1).  Here the forest is a rooted forest:
 // parent pointers, doubly linked child lists (an edge is removed in O(1)),
 // and one label per vertex naming its tree:
-//   - link(a, b): the smaller tree is relabelled, re-rooted at its endpoint
-//     (parent pointers reversed along one path) and hung below the other
-//     endpoint (work proportional to the smaller tree);
+//   - link(a, b): the smaller tree is relabelled; the endpoint whose path
+//     to its root is shorter is made its tree's root (parent pointers
+//     reversed along that path) and hung below the other endpoint (work
+//     proportional to the smaller tree plus the shorter path);
 //   - cut(a, b): the edge is removed and the two sides are searched
 //     top-down (from the old root and from the child endpoint), interleaved
 //     edge by edge, so the work is proportional to the smaller side (even
@@ -124,28 +125,16 @@ class Forest {
             lbl_[x] = lb;
             for (uint32_t y = first_kid_[x]; y != kNone; y = next_sib_[y]) queue_.push_back(y);
         }
-        // re-root it at a: reverse the parent pointers on the path from a up
-        // to the old root
-        for (uint32_t x = a, below = kNone; x != kNone;) {
-            const uint32_t up = par_[x];
-            if (up != kNone) remove_kid(up, x);
-            if (below != kNone) {
-                par_[x] = below;
-                add_kid(below, x);
-            }
-            below = x;
-            x = up;
-        }
-        // hang it below b
-        par_[a] = b;
-        add_kid(b, a);
+        // re-root the endpoint with the shorter path to its root (the paths
+        // are walked in lockstep) and hang it below the other one (the
+        // structural link counts the merge)
+        const uint32_t ra = root_[la];
+        if (!link_structural_short(a, b)) root_[lb] = ra;  // b's tree hangs below a
         size_[lb] += size_[la];
         if (dirty_[la]) set_dirty(lb);
         dirty_[la] = 0;
         free_.push_back(la);
         live_remove(la);
-        n_trees_--;
-        n_edges_++;
         return lb;
     }
 
@@ -294,6 +283,23 @@ class Forest {
         n_trees_--;
         n_edges_++;
     }
+    // Link a and b (different trees) by parent pointers only, re-rooting the
+    // endpoint whose path to its root is shorter (both paths are walked in
+    // lockstep, so the work is about twice the shorter path).  Returns true
+    // when a's tree was re-rooted (the root of b's tree is the new root).
+    bool link_structural_short(uint32_t a, uint32_t b)
+    {
+        for (uint32_t x = a, y = b;; x = par_[x], y = par_[y]) {
+            if (par_[x] == kNone) {
+                link_structural(a, b);
+                return true;
+            }
+            if (par_[y] == kNone) {
+                link_structural(b, a);
+                return false;
+            }
+        }
+    }
     // Root of x's tree, by parent pointers.
     uint32_t root_of(uint32_t x) const
     {
@@ -338,6 +344,89 @@ class Forest {
         if (dirty) set_dirty(l);
     }
     void settle_done() { pending_.clear(); }
+
+    // Link, in order, every pair (a, b) of `cand` whose endpoints are in
+    // different trees at its turn: the same links as calling link() for
+    // each pair that same_tree() rejects not, but decided on a union-find
+    // over the trees' labels, and each merged tree is labelled once (it
+    // keeps its largest part's label, whose vertices are not touched), so a
+    // vertex is relabelled at most once however many merges it takes part
+    // in.  Marks the pairs that linked in `linked` (same length as cand) and
+    // returns their number.  Must not be called with removals pending.
+    size_t link_many(const std::vector<std::pair<uint32_t, uint32_t>> &cand,
+                     std::vector<uint8_t> &linked)
+    {
+        linked.assign(cand.size(), 0);
+        if (lm_st_.size() != V_ || lm_ep_ == 0xffffffffu) {
+            lm_up_.assign(V_, 0);
+            lm_sz_.assign(V_, 0);
+            lm_st_.assign(V_, 0);
+            lm_best_.assign(V_, 0);
+            lm_ep_ = 0;
+        }
+        lm_ep_++;
+        lm_touched_.clear();
+        lm_edges_.clear();
+        auto node = [&](uint32_t l) {
+            if (lm_st_[l] != lm_ep_) {
+                lm_st_[l] = lm_ep_;
+                lm_up_[l] = l;
+                lm_sz_[l] = size_[l];
+                lm_touched_.push_back(l);
+            }
+            return l;
+        };
+        auto find = [&](uint32_t l) {
+            while (lm_up_[l] != l) l = lm_up_[l] = lm_up_[lm_up_[l]];
+            return l;
+        };
+        for (size_t i = 0; i < cand.size(); i++) {
+            uint32_t a = cand[i].first, b = cand[i].second;
+            uint32_t ra = find(node(lbl_[a])), rb = find(node(lbl_[b]));
+            if (ra == rb) continue;
+            if (lm_sz_[ra] > lm_sz_[rb]) {  // the smaller side is re-rooted
+                std::swap(a, b);
+                std::swap(ra, rb);
+            }
+            lm_edges_.push_back({a, b});
+            lm_up_[ra] = rb;
+            lm_sz_[rb] += lm_sz_[ra];
+            linked[i] = 1;
+        }
+        if (lm_edges_.empty()) return 0;
+        // the label each merged tree keeps: its largest part's (ties: the
+        // smaller label); dirty when a part is
+        for (uint32_t l : lm_touched_)
+            if (find(l) == l) lm_best_[l] = kNone;
+        for (uint32_t l : lm_touched_) {
+            const uint32_t r = find(l), c = lm_best_[r];
+            if (c == kNone || size_[l] > size_[c] || (size_[l] == size_[c] && l < c))
+                lm_best_[r] = l;
+        }
+        for (uint32_t l : lm_touched_)
+            if (dirty_[l]) set_dirty(lm_best_[find(l)]);
+        // relabel the other parts in the structure before the links
+        for (uint32_t l : lm_touched_) {
+            const uint32_t keep = lm_best_[find(l)];
+            if (l != keep) settle_relabel_tree(root_[l], keep);
+        }
+        for (const auto &e : lm_edges_) link_structural_short(e.first, e.second);
+        for (uint32_t l : lm_touched_) {
+            const uint32_t r = find(l), keep = lm_best_[r];
+            if (l != keep) {
+                dirty_[l] = 0;
+                free_.push_back(l);
+                live_remove(l);
+            } else {
+                size_[keep] = lm_sz_[r];
+            }
+        }
+        for (uint32_t l : lm_touched_) {
+            const uint32_t keep = lm_best_[find(l)];
+            if (l == keep) root_[keep] = root_of(root_[keep]);
+        }
+        return lm_edges_.size();
+    }
 
     // Vertices of the tree with the given label (BFS from its root); also
     // returns the smallest vertex id.
@@ -435,6 +524,9 @@ class Forest {
     std::vector<uint32_t> free_;
     std::vector<uint32_t> live_, live_pos_;  // labels in use, and each one's slot
     std::vector<uint32_t> queue_;
+    std::vector<uint32_t> lm_up_, lm_sz_, lm_st_, lm_best_, lm_touched_;  // link_many, by label
+    uint32_t lm_ep_ = 0;
+    std::vector<std::pair<uint32_t, uint32_t>> lm_edges_;
     std::vector<std::pair<uint32_t, uint32_t>> pending_;  // (old label, top) per removal
     std::vector<std::vector<uint32_t>> pq_;              // per-piece search queues
     std::vector<Walk> pw_;

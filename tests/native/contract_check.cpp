@@ -104,6 +104,7 @@ int main(int argc, char **argv)
     A.init(V, la.data(), pa.data());
     B.init(V, lb.data(), pb.data());
     Contraction C;
+    uint64_t many_runs = 0;
     // the graph's edges (what a valid stream toggles)
     std::set<std::pair<uint32_t, uint32_t>> G;
     // a pool of edges toggled again and again
@@ -132,6 +133,34 @@ int main(int argc, char **argv)
                 A.set_dirty(A.label(w));
                 B.set_dirty(B.label(w));
             }
+        }
+        if (rng() % 4 == 0) {
+            // a list of candidate links (as a replacement round produces):
+            // Forest::link_many against link() one pair at a time
+            A.split_pending();
+            B.split_pending();
+            std::vector<std::pair<uint32_t, uint32_t>> cand;
+            const uint32_t len = 1 + (uint32_t)(rng() % (2 * V));
+            for (uint32_t i = 0; i < len; i++) {
+                const uint32_t a = (uint32_t)(rng() % V), b = (uint32_t)(rng() % V);
+                if (a != b) cand.push_back({a, b});
+            }
+            std::vector<uint8_t> want(cand.size(), 0), got;
+            size_t nw = 0;
+            for (size_t i = 0; i < cand.size(); i++)
+                if (!A.same_tree(cand[i].first, cand[i].second)) {
+                    A.link(cand[i].first, cand[i].second);
+                    want[i] = 1;
+                    nw++;
+                }
+            const size_t ng = B.link_many(cand, got);
+            if (ng != nw || got != want) return fail("link_many: links", r);
+            for (size_t i = 0; i < cand.size(); i++)
+                if (want[i]) G.insert({std::min(cand[i].first, cand[i].second),
+                                       std::max(cand[i].first, cand[i].second)});
+            if (compare(A, B, r)) return 1;
+            many_runs++;
+            continue;
         }
         std::vector<uint64_t> run;
         const uint32_t len = 1 + (uint32_t)(rng() % 64);
@@ -196,8 +225,9 @@ int main(int argc, char **argv)
         if (l0 != l1 || c0 != c1) return fail("link / cut counts", r);
         if (compare(A, B, r)) return 1;
     }
-    printf("ok V=%u runs=%llu contracted=%llu fallbacks=%llu\n", V, (unsigned long long)runs,
-           (unsigned long long)contracted, (unsigned long long)fallbacks);
+    printf("ok V=%u runs=%llu contracted=%llu fallbacks=%llu link lists=%llu\n", V,
+           (unsigned long long)runs, (unsigned long long)contracted,
+           (unsigned long long)fallbacks, (unsigned long long)many_runs);
     // both paths must have run (tiny forests never exhaust a budget)
     return contracted && (fallbacks || V < 8 || runs < 20) ? 0 : 2;
 }
