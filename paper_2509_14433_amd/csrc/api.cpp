@@ -742,7 +742,7 @@ int ensure_batch_buffers(cupk_ctx *ctx, size_t n)
 
 void drop_graphs(cupk_ctx *ctx)
 {
-    for (hipGraphExec_t *g : {&ctx->gx_cls, &ctx->gx_bin, &ctx->gx_tile})
+    for (hipGraphExec_t *g : {&ctx->gx_cls, &ctx->gx_bin, &ctx->gx_tile, &ctx->gx_all})
         if (*g) {
             (void)hipGraphExecDestroy(*g);
             *g = nullptr;
@@ -815,12 +815,16 @@ int capture_graphs(cupk_ctx *ctx)
     drop_graphs(ctx);
     if (!ctx->gs) HIPCHK(hipStreamCreateWithFlags(&ctx->gs, hipStreamNonBlocking));
     const uint32_t cap = (uint32_t)std::min<size_t>(ctx->batch_cap, kMaxBatchPerLaunch);
-    for (int part = 0; part < 3; part++) {
+    // parts 0..2: classify, bin, scatter (launched apart when the pass is
+    // timed, with events between them); part 3: all three in one graph (the
+    // host needs nothing between them: the header reaches it by itself)
+    for (int part = 0; part < 4; part++) {
         HIPCHK(hipStreamBeginCapture(ctx->gs, hipStreamCaptureModeThreadLocal));
         ctx->capturing = true;
-        int rc = part == 0 ? enqueue_classify(ctx, ctx->gs, cap)
-                 : part == 1 ? enqueue_bin(ctx, ctx->gs, cap)
-                             : enqueue_tile(ctx, ctx->gs, cap);
+        int rc = CUPK_OK;
+        if (part == 0 || part == 3) rc = enqueue_classify(ctx, ctx->gs, cap);
+        if (rc == CUPK_OK && (part == 1 || part == 3)) rc = enqueue_bin(ctx, ctx->gs, cap);
+        if (rc == CUPK_OK && (part == 2 || part == 3)) rc = enqueue_tile(ctx, ctx->gs, cap);
         ctx->capturing = false;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->gs, &g);
@@ -833,7 +837,7 @@ int capture_graphs(cupk_ctx *ctx)
         e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return ctx->fail(e, "hipGraphInstantiate", __LINE__);
-        (part == 0 ? ctx->gx_cls : part == 1 ? ctx->gx_bin : ctx->gx_tile) = x;
+        (part == 0 ? ctx->gx_cls : part == 1 ? ctx->gx_bin : part == 2 ? ctx->gx_tile : ctx->gx_all) = x;
     }
     ctx->graph_cap = cap;
     return CUPK_OK;
@@ -887,19 +891,8 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
         rc = capture_graphs(ctx);
         if (rc != CUPK_OK) return rc;
     }
-    // the classify kernel writes the header to pinned host memory itself
-    if (graph) {
-        HIPCHK(hipGraphLaunch(ctx->gx_cls, ctx->s));
-    } else {
-        rc = enqueue_classify(ctx, ctx->s, n);
-        if (rc != CUPK_OK) return rc;
-    }
-    // The host waits for the header by its sequence number, not an event:
-    // every event recorded between two kernels leaves the GPU idle for a few
-    // microseconds.  (Flag compaction on the copy stream is launched only
-    // after the header has arrived, so after classification has finished.)
-    ctx->hdr_seq++;
-    ctx->hdr_polled = true;
+    // Timed passes (every time_kernels-th) get events around the binning and
+    // the scatter; captured graphs are then launched in their three parts.
     cupk_ctx::TimerSlot *ts = nullptr;
     if (ctx->opts.time_kernels && ctx->ctr.scatter_launches % ctx->opts.time_kernels == 0) {
         ctx->ctr.timed_launches++;
@@ -911,21 +904,33 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
             rc = harvest_timers(ctx, false);
             if (rc != CUPK_OK) return rc;
         }
-        HIPCHK(hipEventRecord(ts->t0, ctx->s));
     }
-
-    // scatter (skipped on device if the batch was rejected)
-    if (graph) {
-        if (ctx->gx_bin) HIPCHK(hipGraphLaunch(ctx->gx_bin, ctx->s));
-        if (ts) HIPCHK(hipEventRecord(ts->tb, ctx->s));
+    // The classify step publishes the header to pinned host memory itself,
+    // and the host waits for it by its sequence number, not an event: every
+    // event recorded between two kernels leaves the GPU idle for a few
+    // microseconds.  (Flag compaction on the copy stream is launched only
+    // after the header has arrived, so after classification has finished.)
+    if (graph && !ts) {
+        HIPCHK(hipGraphLaunch(ctx->gx_all, ctx->s));
+    } else if (graph) {
+        HIPCHK(hipGraphLaunch(ctx->gx_cls, ctx->s));
+        HIPCHK(hipEventRecord(ts->t0, ctx->s));
+        HIPCHK(hipGraphLaunch(ctx->gx_bin, ctx->s));
+        HIPCHK(hipEventRecord(ts->tb, ctx->s));
         HIPCHK(hipGraphLaunch(ctx->gx_tile, ctx->s));
     } else {
+        // scatter skipped on the device if the batch was rejected
+        rc = enqueue_classify(ctx, ctx->s, n);
+        if (rc != CUPK_OK) return rc;
+        if (ts) HIPCHK(hipEventRecord(ts->t0, ctx->s));
         rc = enqueue_bin(ctx, ctx->s, n);
         if (rc != CUPK_OK) return rc;
         if (ts) HIPCHK(hipEventRecord(ts->tb, ctx->s));
         rc = enqueue_tile(ctx, ctx->s, n);
         if (rc != CUPK_OK) return rc;
     }
+    ctx->hdr_seq++;
+    ctx->hdr_polled = true;
     if (ts) {
         HIPCHK(hipEventRecord(ts->t1, ctx->s));
         ts->busy = true;

@@ -107,7 +107,7 @@ struct cupk_ctx {
 
     // captured step (use_graph): classify + header copy, bin, tile
     hipStream_t gs = nullptr;  // capture stream
-    hipGraphExec_t gx_cls = nullptr, gx_bin = nullptr, gx_tile = nullptr;
+    hipGraphExec_t gx_cls = nullptr, gx_bin = nullptr, gx_tile = nullptr, gx_all = nullptr;
     uint32_t graph_cap = 0;    // batch capacity the graphs were captured for
     size_t batch_cap = 0;      // updates per batch every batch buffer holds
 
