@@ -863,15 +863,14 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
         // header + flags + positions to the host, scatter with device
         // atomics (the previous small result was read before this pass:
         // every pass waits for its header or for the whole stream)
+        uint32_t *derr = &ctx->d_small->hdr[HDR_ERR];
         HIPCHK(launch_small_classify(ctx->s, d_upd, n, ctx->V, ctx->d_lbl, ctx->d_par,
-                                     ctx->d_small, ctx->opts.exact != 0));
-        const size_t bytes = ctx->opts.exact ? sizeof(SmallResult)
-                                             : offsetof(SmallResult, fupd) + (size_t)n * 8;
-        HIPCHK(hipMemcpyAsync(ctx->h_small, ctx->d_small, bytes, hipMemcpyDeviceToHost, ctx->s));
-        HIPCHK(hipEventRecord(ctx->ev_hdr, ctx->s));
-        ctx->hdr_polled = false;
-        // the scatter follows the copy: the host walks the flags meanwhile
-        HIPCHK(launch_small_scatter(ctx->s, d_upd, n, dev_sketch(ctx), ctx->d_small));
+                                     ctx->h_small, derr, ctx->d_hdr + HDR_SEQ,
+                                     ctx->opts.exact != 0));
+        ctx->hdr_seq++;
+        ctx->hdr_word = &ctx->h_small->hdr[HDR_SEQ];
+        // the host walks the flags while the scatter runs
+        HIPCHK(launch_small_scatter(ctx->s, d_upd, n, dev_sketch(ctx), derr));
         ctx->ctr.scatter_launches++;
         return CUPK_OK;
     }
@@ -930,7 +929,7 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
         if (rc != CUPK_OK) return rc;
     }
     ctx->hdr_seq++;
-    ctx->hdr_polled = true;
+    ctx->hdr_word = &ctx->h_hdr[HDR_SEQ];
     if (ts) {
         HIPCHK(hipEventRecord(ts->t1, ctx->s));
         ts->busy = true;
@@ -972,7 +971,7 @@ int walk_exact(cupk_ctx *ctx, const uint64_t *upd, uint32_t k0, uint32_t k1, boo
 // instead of spinning on.
 static int wait_header(cupk_ctx *ctx, uint32_t seq)
 {
-    uint32_t *w = &ctx->h_hdr[HDR_SEQ];
+    uint32_t *w = ctx->hdr_word;
     for (uint32_t spin = 1;; spin++) {
         if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return CUPK_OK;
         if ((spin & 255) == 0) {
@@ -996,11 +995,9 @@ int walk_pass(cupk_ctx *ctx, uint32_t n, bool exact, uint32_t *cut_pos, uint32_t
               uint32_t *cut_b, uint32_t *nflag_out, double *t_wait, double *t_copy)
 {
     double t0 = now_ms();
-    if (ctx->hdr_polled) {
+    {
         int rw = wait_header(ctx, ctx->hdr_seq);
         if (rw != CUPK_OK) return rw;
-    } else {
-        HIPCHK(hipEventSynchronize(ctx->ev_hdr));
     }
     double t1 = now_ms();
     ctx->ctr.host_wait_ms += t1 - t0;
@@ -1200,7 +1197,6 @@ void destroy(cupk_ctx *ctx)
         if (t.tb) (void)hipEventDestroy(t.tb);
         if (t.t1) (void)hipEventDestroy(t.t1);
     }
-    if (ctx->ev_hdr) (void)hipEventDestroy(ctx->ev_hdr);
     if (ctx->cs) (void)hipStreamDestroy(ctx->cs);
     if (ctx->own_stream && ctx->s) (void)hipStreamDestroy(ctx->s);
     delete ctx;
@@ -1261,7 +1257,6 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
         ctx->own_stream = true;
     }
     HIPCHK(hipStreamCreateWithFlags(&ctx->cs, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&ctx->ev_hdr, hipEventDisableTiming));
     if (ctx->opts.time_kernels)
         for (auto &t : ctx->timers) {
             HIPCHK(hipEventCreate(&t.t0));
@@ -1292,7 +1287,9 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     HIPCHK(hipHostMalloc((void **)&ctx->h_desc, sizeof(BatchDesc), hipHostMallocDefault));
     HIPCHK(hipMalloc((void **)&ctx->d_misc, 64));
     HIPCHK(hipMalloc((void **)&ctx->d_small, sizeof(SmallResult)));
-    HIPCHK(hipHostMalloc((void **)&ctx->h_small, sizeof(SmallResult), hipHostMallocDefault));
+    // coherent: the small classify kernel writes its result here directly
+    HIPCHK(hipHostMalloc((void **)&ctx->h_small, sizeof(SmallResult), hipHostMallocCoherent));
+    memset(ctx->h_small, 0, sizeof(SmallResult));
     HIPCHK(hipHostMalloc((void **)&ctx->h_misc, 64, hipHostMallocDefault));
     ctx->forest.init(V, ctx->h_lbl, ctx->h_par);
     if (ctx->opts.levels) {

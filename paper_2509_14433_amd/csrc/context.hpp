@@ -56,9 +56,8 @@ struct cupk_ctx {
     cupk_opts opts = {};
     hipStream_t s = nullptr, cs = nullptr;
     bool own_stream = false;
-    hipEvent_t ev_hdr = nullptr;
-    uint32_t hdr_seq = 0;      // headers published by the device so far (expected)
-    bool hdr_polled = false;   // current pass: wait for hdr_seq (else for ev_hdr)
+    uint32_t hdr_seq = 0;          // headers published by the device so far (expected)
+    uint32_t *hdr_word = nullptr;  // where the current pass publishes its sequence number
     struct TimerSlot {
         hipEvent_t t0, tb, t1;
         bool busy;

@@ -366,10 +366,11 @@ __global__ __launch_bounds__(256) void k_scatter_atomic(const BatchDesc *__restr
 // ---------------------------------------------------------------------------
 // Small batches (n <= kSmallMax): one block classifies the whole batch and
 // writes the header and the flagged updates (with positions) straight into
-// one result block, ready for a single copy to the host; a second kernel
-// scatters with device atomics.  The batch comes in the arguments, so no
-// descriptor copy, header clearing, compaction or binning is needed: the
-// latency of a small batch is two launches and one copy.
+// a result block in coherent pinned host memory, then publishes the next
+// sequence number; a second kernel scatters with device atomics.  The batch
+// comes in the arguments, so no descriptor copy, header clearing,
+// compaction, binning, copy or event is needed: the latency of a small
+// batch is two launches.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSmallThreads = 1024;
 constexpr uint32_t kSmallPerThread = kSmallMax / kSmallThreads;
@@ -377,7 +378,8 @@ static_assert(kSmallPerThread * (kSmallThreads / 64) == 64, "one wave scans the 
 
 __global__ __launch_bounds__(kSmallThreads) void k_small_classify(
     const uint64_t *__restrict__ upd, uint32_t n, uint32_t V, const uint32_t *__restrict__ lbl,
-    const uint32_t *__restrict__ par, SmallResult *__restrict__ out, uint32_t with_pos)
+    const uint32_t *__restrict__ par, SmallResult *__restrict__ out, uint32_t *__restrict__ derr,
+    uint32_t *__restrict__ seqp, uint32_t with_pos)
 {
     __shared__ uint32_t pre[64 + 1];
     __shared__ uint32_t s_bad, s_del;
@@ -443,19 +445,25 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_classify(
             if (with_pos) out->fpos[q] = k * kSmallThreads + threadIdx.x;
         }
     }
+    // the result is in host memory before the sequence number says so
+    __threadfence_system();
+    __syncthreads();
     if (threadIdx.x == 0) {
+        *derr = s_bad;  // for the scatter
         out->hdr[HDR_ERR] = s_bad;
         out->hdr[HDR_NFLAG] = s_bad ? 0u : pre[64];
         out->hdr[HDR_NFLAG_DEL] = s_bad ? 0u : s_del;
-        out->hdr[3] = 0;
+        const uint32_t seq = *seqp + 1;
+        *seqp = seq;
+        __hip_atomic_store(&out->hdr[HDR_SEQ], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
 __global__ __launch_bounds__(256) void k_small_scatter(const uint64_t *__restrict__ upd,
                                                        uint32_t n, DevSketch sk,
-                                                       const SmallResult *__restrict__ res)
+                                                       const uint32_t *__restrict__ derr)
 {
-    if (res->hdr[HDR_ERR]) return;
+    if (*derr) return;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     scatter_one(sk, upd[i]);
@@ -463,18 +471,19 @@ __global__ __launch_bounds__(256) void k_small_scatter(const uint64_t *__restric
 
 hipError_t launch_small_classify(hipStream_t s, const uint64_t *upd, uint32_t n, uint32_t V,
                                  const uint32_t *lbl, const uint32_t *par, SmallResult *out,
-                                 bool with_pos)
+                                 uint32_t *derr, uint32_t *seqp, bool with_pos)
 {
     if (n == 0 || n > kSmallMax) return hipErrorInvalidValue;
-    k_small_classify<<<1, kSmallThreads, 0, s>>>(upd, n, V, lbl, par, out, with_pos ? 1u : 0u);
+    k_small_classify<<<1, kSmallThreads, 0, s>>>(upd, n, V, lbl, par, out, derr, seqp,
+                                                with_pos ? 1u : 0u);
     return hipGetLastError();
 }
 
 hipError_t launch_small_scatter(hipStream_t s, const uint64_t *upd, uint32_t n, DevSketch sk,
-                                const SmallResult *res)
+                                const uint32_t *derr)
 {
     if (n == 0 || n > kSmallMax) return hipErrorInvalidValue;
-    k_small_scatter<<<(n + 255) / 256, 256, 0, s>>>(upd, n, sk, res);
+    k_small_scatter<<<(n + 255) / 256, 256, 0, s>>>(upd, n, sk, derr);
     return hipGetLastError();
 }
 

@@ -86,8 +86,8 @@ hipError_t launch_flag_compact(hipStream_t s, uint32_t n, const uint64_t *fupd,
                                uint64_t *oupd, uint32_t *opos);
 
 // Small batches: header, flagged updates (stream order) and their positions
-// of one batch of at most kSmallMax updates, written by one kernel for one
-// copy to the host.
+// of one batch of at most kSmallMax updates, written by one kernel straight
+// into host memory.
 constexpr uint32_t kSmallMax = 4096;
 struct SmallResult {
     uint32_t hdr[HDR_WORDS];
@@ -95,15 +95,16 @@ struct SmallResult {
     uint32_t fpos[kSmallMax];
 };
 // Classify (one block) a batch of 1..kSmallMax packed updates given in the
-// arguments into `out` (with_pos: also positions), then scatter it with
-// device atomics; the scatter does nothing if an update was invalid
-// (res->hdr[HDR_ERR] set).  The two are separate so that the result can be
-// copied to the host before the scatter runs.
+// arguments into `out` (coherent pinned host memory; with_pos: also
+// positions), set *derr (device) to the error flag, and publish the next
+// value of the counter *seqp at out->hdr[HDR_SEQ] (release store) once the
+// rest of `out` is written.  Then scatter it with device atomics; the
+// scatter does nothing if an update was invalid (*derr set).
 hipError_t launch_small_classify(hipStream_t s, const uint64_t *upd, uint32_t n, uint32_t V,
                                  const uint32_t *lbl, const uint32_t *par, SmallResult *out,
-                                 bool with_pos);
+                                 uint32_t *derr, uint32_t *seqp, bool with_pos);
 hipError_t launch_small_scatter(hipStream_t s, const uint64_t *upd, uint32_t n, DevSketch sk,
-                                const SmallResult *res);
+                                const uint32_t *derr);
 
 // Plain scatter: device-scope atomic XOR of (x, h) into both endpoints.
 // Its last block clears the header for the next batch.
