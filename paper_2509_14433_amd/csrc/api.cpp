@@ -725,7 +725,7 @@ int ensure_batch_buffers(cupk_ctx *ctx, size_t n)
     HIPCHK(grow(ctx->d_fcnt, nb + 1));
     HIPCHK(grow(ctx->d_foff, nb + 1));
     HIPCHK(grow(ctx->d_oupd, cap));
-    HIPCHK(grow(ctx->h_fupd, cap));
+    HIPCHK(grow(ctx->h_fupd, cap, hipHostMallocCoherent));
     if (ctx->opts.exact) {
         HIPCHK(grow(ctx->d_fpos, nb * 4096));
         HIPCHK(grow(ctx->d_opos, cap));
@@ -780,11 +780,18 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
         sa.chunk = ctx->chunk;
         sa.items_cap = staged_params(ctx, grid_n).items_cap;
     }
+    // short flag lists come back with the header (not in exact mode, which
+    // also needs their positions)
+    FlagInline fi = {};
+    fi.fupd = ctx->d_fupd.p;
+    fi.fcnt = ctx->d_fcnt.p;
+    fi.nb = classify_blocks(grid_n);
+    fi.hflags = ctx->opts.exact ? nullptr : ctx->h_fupd.p;
     HIPCHK(launch_classify(s, desc_ptr(ctx), ctx->cur_desc, grid_n, ctx->V, ctx->d_lbl,
                            ctx->d_par, ctx->d_hdr, ctx->d_fupd.p,
                            ctx->opts.exact ? ctx->d_fpos.p : nullptr, ctx->d_fcnt.p,
                            staged ? ctx->d_tcnt.p : nullptr, ctx->tile_shift, ctx->ntiles, sa,
-                           ctx->h_hdr));
+                           ctx->h_hdr, fi));
     return CUPK_OK;
 }
 
@@ -1016,18 +1023,21 @@ int walk_pass(cupk_ctx *ctx, uint32_t n, bool exact, uint32_t *cut_pos, uint32_t
     double tcopy = t1;
     const uint64_t *fl = small ? ctx->h_small->fupd : ctx->h_fupd.p;
     const uint32_t *fp = small ? ctx->h_small->fpos : ctx->h_fpos.p;
+    // the flags are already in host memory after a small pass and when the
+    // device wrote a short list with the header
+    const bool have = small || hdr[HDR_INLINE] != 0;
     if (nflag && !(ctx->levels && nflag_del == 0)) {
         // pack the per-block regions into one ordered list (copy stream,
         // already ordered after the classify kernel), then fetch and walk it
         // in growing chunks: the walk may stop early
         uint32_t *opos = exact ? ctx->d_opos.p : nullptr;
-        if (!small)
+        if (!have)
             HIPCHK(launch_flag_compact(ctx->cs, n, ctx->d_fupd.p, exact ? ctx->d_fpos.p : nullptr,
                                        ctx->d_fcnt.p, ctx->d_foff.p, ctx->d_oupd.p, opos));
-        uint32_t k0 = 0, step = small ? nflag : 1u << 16;
+        uint32_t k0 = 0, step = have ? nflag : 1u << 16;
         while (k0 < nflag) {
             const uint32_t m = std::min(step, nflag - k0);
-            if (!small) {
+            if (!have) {
                 HIPCHK(hipMemcpyAsync(ctx->h_fupd.p + k0, ctx->d_oupd.p + k0, (size_t)m * 8,
                                       hipMemcpyDeviceToHost, ctx->cs));
                 if (exact)

@@ -78,7 +78,7 @@ struct cupk_ctx {
     uint32_t *d_hdr = nullptr, *h_hdr = nullptr;
     cupk::DevBuf<uint32_t> d_fcnt, d_foff;  // flagged updates: per-block counts and offsets,
     cupk::DevBuf<uint64_t> d_fupd, d_oupd;  // per-block regions, the compacted ordered list
-    cupk::HostBuf<uint64_t> h_fupd;
+    cupk::HostBuf<uint64_t> h_fupd;  // coherent: short flag lists are written there by the device
     cupk::DevBuf<uint32_t> d_fpos, d_opos;  // positions of flagged updates (exact mode)
     cupk::HostBuf<uint32_t> h_fpos;
 
@@ -184,7 +184,7 @@ inline hipError_t grow(DevBuf<T> &b, size_t need)
 }
 
 template <class T>
-inline hipError_t grow(HostBuf<T> &b, size_t need)
+inline hipError_t grow(HostBuf<T> &b, size_t need, unsigned flags = hipHostMallocDefault)
 {
     if (need <= b.cap) return hipSuccess;
     size_t cap = std::max(need, 2 * b.cap);
@@ -194,7 +194,7 @@ inline hipError_t grow(HostBuf<T> &b, size_t need)
         b.cap = 0;
         if (e != hipSuccess) return e;
     }
-    hipError_t e = hipHostMalloc((void **)&b.p, cap * sizeof(T), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void **)&b.p, cap * sizeof(T), flags);
     if (e != hipSuccess) return e;
     b.cap = cap;
     return hipSuccess;

@@ -123,16 +123,43 @@ DEVI uint32_t block_exscan(uint32_t x, uint32_t &total, uint32_t *sh)
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict__ cnt,
                                                             uint32_t ntiles, ScanArgs a,
                                                             uint32_t *__restrict__ hdr,
-                                                            uint32_t *__restrict__ hout)
+                                                            uint32_t *__restrict__ hout,
+                                                            FlagInline fi)
 {
     __shared__ uint32_t sh[160];
+    __shared__ uint32_t boff[kInlineMaxBlocks];
     const bool err = hdr[HDR_ERR] != 0;
+    const uint32_t nflag = hdr[HDR_NFLAG];
+    // few flagged updates: compact them into host memory in stream order
+    // (one wave per classify block's region)
+    const bool inl = fi.hflags && !err && nflag <= kInlineFlags && fi.nb <= kInlineMaxBlocks;
+    if (inl && nflag) {
+        uint32_t carry = 0;
+        for (uint32_t base = 0; base < fi.nb; base += kScanThreads) {
+            const uint32_t b = base + threadIdx.x;
+            const uint32_t c = b < fi.nb ? fi.fcnt[b] : 0u;
+            uint32_t tot;
+            const uint32_t ex = block_exscan<kScanThreads>(c, tot, sh);
+            if (b < fi.nb) boff[b] = carry + ex;
+            carry += tot;
+        }
+        __syncthreads();
+        const uint32_t lane = __lane_id();
+        for (uint32_t b = threadIdx.x / 64; b < fi.nb; b += kScanThreads / 64) {
+            const uint32_t c = fi.fcnt[b], o = boff[b];
+            for (uint32_t k = lane; k < c; k += 64)
+                fi.hflags[o + k] = fi.fupd[(size_t)b * kClsPerBlock + k];
+        }
+        __threadfence_system();
+        __syncthreads();
+    }
     // the header goes straight to host memory (no copy, no event): words
     // first, then the sequence number with release semantics
     if (threadIdx.x == 0) {
         hout[HDR_ERR] = hdr[HDR_ERR];
-        hout[HDR_NFLAG] = hdr[HDR_NFLAG];
+        hout[HDR_NFLAG] = nflag;
         hout[HDR_NFLAG_DEL] = hdr[HDR_NFLAG_DEL];
+        hout[HDR_INLINE] = inl ? 1u : 0u;
         const uint32_t seq = hdr[HDR_SEQ] + 1;
         hdr[HDR_SEQ] = seq;
         __hip_atomic_store(&hout[HDR_SEQ], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -298,14 +325,14 @@ hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, u
                            uint32_t V, const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles, const ScanArgs &sa,
-                           uint32_t *hout)
+                           uint32_t *hout, const FlagInline &fi)
 {
     if (grid_n == 0) return hipSuccess;
     k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(
         desc, dv, V, lbl, par, hdr, fupd, fpos, fcnt, tile_cnt, tile_shift, ntiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr, hout);
+    k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr, hout, fi);
     return hipGetLastError();
 }
 

@@ -36,7 +36,21 @@ enum {
     HDR_NFLAG_DEL = 2,
     HDR_SCAT_DONE = 3,
     HDR_SEQ = 4,
+    HDR_INLINE = 5,  // host copy only: the flagged updates came with the header
     HDR_WORDS = 8
+};
+
+// Flagged updates of a batch with at most kInlineFlags of them (and at most
+// kInlineMaxBlocks classify blocks) are compacted in stream order straight
+// into host memory by the one-block kernel after classification, before it
+// publishes the header (HDR_INLINE set): no compaction kernels, no copy.
+constexpr uint32_t kInlineFlags = 16384;
+constexpr uint32_t kInlineMaxBlocks = 8192;
+struct FlagInline {
+    const uint64_t *fupd;  // per-block regions (the classify kernel's output)
+    const uint32_t *fcnt;  // flags per classify block
+    uint32_t nb;           // classify blocks
+    uint64_t *hflags;      // coherent pinned host memory; null: never inline
 };
 
 // Where the tile scan (run by the last classify block) writes: bin offsets
@@ -75,7 +89,7 @@ hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, u
                            uint32_t V, const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles, const ScanArgs &sa,
-                           uint32_t *hout);
+                           uint32_t *hout, const FlagInline &fi);
 uint32_t classify_blocks(uint32_t n);
 
 // Pack the per-block flag regions into one list in stream order (foff:
