@@ -308,3 +308,44 @@ def test_small_batch_boundary(cupk, mode):
     _assert_same_sketch(ctx, ref)
     assert ctx.forest_edges() == fr.forest_edges()
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_flag_list_boundary(cupk, mode):
+    # Batches above the small-batch limit whose every update is flagged:
+    # 16384 flags (the longest list that comes back with the batch header)
+    # and 16385 (compacted and copied), then deletions of tree edges mixed
+    # with inserts; both flag paths must agree with the oracle.
+    V, C, D, S = 40000, 8, 18, 0x1F1A6
+    k = 16384
+    ua = np.arange(0, 2 * k, 2, dtype=np.uint32)
+    ub = np.arange(1, 2 * k + 2, 2, dtype=np.uint32)
+    batches = [
+        (ua, ua + 1, np.zeros(k, np.uint8)),          # 16384 pairs
+        (ub, ub + 1, np.zeros(k + 1, np.uint8)),      # 16385 links joining them
+    ]
+    rng = np.random.default_rng(5)
+    m = 200
+    cu = ua[:m]
+    ru = rng.integers(0, V, 6000).astype(np.uint32)
+    rv = rng.integers(0, V, 6000).astype(np.uint32)
+    keep = ru != rv
+    u3 = np.concatenate([cu, ru[keep]])
+    v3 = np.concatenate([cu + 1, rv[keep]])
+    d3 = np.concatenate([np.ones(m, np.uint8), np.zeros(int(keep.sum()), np.uint8)])
+    perm = rng.permutation(len(u3))
+    batches.append((u3[perm], v3[perm], d3[perm]))
+    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    ref = oracle.Sketch(V, C, D, S)
+    fr = oracle.ForestReplay(ref)
+    flagged = []
+    for i, (u, v, d) in enumerate(batches):
+        print(f"flag boundary batch {i} n={len(u)} mode={mode}", flush=True)
+        before = ctx.counters()["flagged"]
+        ctx.apply_updates(u, v, d)
+        flagged.append(ctx.counters()["flagged"] - before)
+        fr.apply_batch(u, v, d)
+    assert flagged[:2] == [k, k + 1]
+    _assert_same_sketch(ctx, ref)
+    assert ctx.forest_edges() == fr.forest_edges()
+    ctx.close()
