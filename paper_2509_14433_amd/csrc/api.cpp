@@ -58,6 +58,7 @@ uint32_t ceil_log2(uint32_t V)
 namespace cupk {
 
 void drop_graphs(cupk_ctx *ctx);
+int ensure_rel(cupk_ctx *ctx);
 
 DevSketch dev_sketch(cupk_ctx *ctx)
 {
@@ -737,7 +738,32 @@ int ensure_batch_buffers(cupk_ctx *ctx, size_t n)
         HIPCHK(grow(ctx->d_items, 2 * icap));
     }
     ctx->batch_cap = cap;
+    return ensure_rel(ctx);
+}
+
+// Block starts inside the tile bins (one word per classify block and tile)
+// for the batch capacity and geometry in force, when they fit a modest
+// buffer; otherwise the fill reserves its ranges with atomics.
+constexpr size_t kRelMaxWords = (size_t)1 << 25;
+static size_t rel_words(cupk_ctx *ctx, size_t n)
+{
+    if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED || ctx->ntiles > kRelMaxTiles) return 0;
+    const size_t w = (size_t)classify_blocks((uint32_t)std::min<size_t>(n, kMaxBatchPerLaunch)) *
+                     ctx->ntiles;
+    return w <= kRelMaxWords ? w : 0;
+}
+
+int ensure_rel(cupk_ctx *ctx)
+{
+    const size_t w = rel_words(ctx, ctx->batch_cap);
+    if (w) HIPCHK(grow(ctx->d_trel, w));
     return CUPK_OK;
+}
+
+static uint32_t *rel_ptr(cupk_ctx *ctx, uint32_t grid_n)
+{
+    const size_t w = rel_words(ctx, grid_n);
+    return w && w <= ctx->d_trel.cap ? ctx->d_trel.p : nullptr;
 }
 
 void drop_graphs(cupk_ctx *ctx)
@@ -791,7 +817,7 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
                            ctx->d_par, ctx->d_hdr, ctx->d_fupd.p,
                            ctx->opts.exact ? ctx->d_fpos.p : nullptr, ctx->d_fcnt.p,
                            staged ? ctx->d_tcnt.p : nullptr, ctx->tile_shift, ctx->ntiles, sa,
-                           ctx->h_hdr, fi));
+                           ctx->h_hdr, fi, staged ? rel_ptr(ctx, grid_n) : nullptr));
     return CUPK_OK;
 }
 
@@ -799,7 +825,8 @@ int enqueue_bin(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
 {
     if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED) return CUPK_OK;
     HIPCHK(launch_bin(s, desc_ptr(ctx), ctx->cur_desc, grid_n, dev_sketch(ctx), ctx->d_hdr,
-                      staged_params(ctx, grid_n), ctx->d_tcur.p, ctx->d_bins.p));
+                      staged_params(ctx, grid_n), ctx->d_tcur.p, ctx->d_bins.p, ctx->d_toff.p,
+                      rel_ptr(ctx, grid_n)));
     return CUPK_OK;
 }
 
@@ -1191,6 +1218,7 @@ void destroy(cupk_ctx *ctx)
     release(ctx->d_tcnt);
     release(ctx->d_toff);
     release(ctx->d_tcur);
+    release(ctx->d_trel);
     release(ctx->d_items);
     release(ctx->d_bins);
     release(ctx->d_ridx);
@@ -1238,7 +1266,7 @@ int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk)
         const size_t icap = 2 * ctx->batch_cap / chunk + ctx->ntiles + 1;
         HIPCHK(grow(ctx->d_items, 2 * icap));
     }
-    return CUPK_OK;
+    return ensure_rel(ctx);
 }
 
 int init_impl(cupk_ctx *ctx, const cupk_opts *opts)

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
     const BatchDesc *__restrict__ desc, BatchDesc dv, uint32_t V, const uint32_t *__restrict__ lbl,
     const uint32_t *__restrict__ par, uint32_t *__restrict__ hdr, uint64_t *__restrict__ fupd,
     uint32_t *__restrict__ fpos, uint32_t *__restrict__ fcnt, uint32_t *__restrict__ tile_cnt,
-    uint32_t tile_shift, uint32_t ntiles)
+    uint32_t tile_shift, uint32_t ntiles, uint32_t *__restrict__ tile_rel)
 {
     __shared__ uint32_t hist[kLdsHistMax];
     __shared__ uint32_t pre[64 + 1];  // flagged per (step, wave) -> exclusive prefix; total
@@ -314,8 +314,18 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
     if (lane == 0 && ndel) atomicAdd(&hdr[HDR_NFLAG_DEL], ndel);
     if (use_lds) {
         __syncthreads();
-        for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x)
-            if (hist[t]) atomicAdd(&tile_cnt[t], hist[t]);
+        if (tile_rel) {
+            // the returned count is where this block's records start in
+            // the tile's bin (relative to the tile's offset)
+            uint32_t *rb = tile_rel + (size_t)blockIdx.x * ntiles;
+            for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
+                const uint32_t h = hist[t];
+                if (h) rb[t] = atomicAdd(&tile_cnt[t], h);
+            }
+        } else {
+            for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x)
+                if (hist[t]) atomicAdd(&tile_cnt[t], hist[t]);
+        }
     }
 }
 
@@ -325,11 +335,12 @@ hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, u
                            uint32_t V, const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles, const ScanArgs &sa,
-                           uint32_t *hout, const FlagInline &fi)
+                           uint32_t *hout, const FlagInline &fi, uint32_t *tile_rel)
 {
     if (grid_n == 0) return hipSuccess;
+    if (tile_rel && (!tile_cnt || ntiles > kRelMaxTiles)) return hipErrorInvalidValue;
     k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(
-        desc, dv, V, lbl, par, hdr, fupd, fpos, fcnt, tile_cnt, tile_shift, ntiles);
+        desc, dv, V, lbl, par, hdr, fupd, fpos, fcnt, tile_cnt, tile_shift, ntiles, tile_rel);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr, hout, fi);
@@ -628,7 +639,8 @@ static size_t fill_stage_lds(uint32_t ntiles)
 __global__ __launch_bounds__(kFillThreads) void k_tile_fill_staged(
     const BatchDesc *__restrict__ desc, BatchDesc dv, uint32_t V, uint32_t tile_shift,
     uint32_t ntiles, uint32_t *__restrict__ cur, uint64_t *__restrict__ bins,
-    const uint32_t *__restrict__ hdr)
+    const uint32_t *__restrict__ hdr, const uint32_t *__restrict__ off,
+    const uint32_t *__restrict__ rel)
 {
     extern __shared__ uint64_t fsm[];
     uint64_t *stage = fsm;                                   // records in tile order
@@ -668,13 +680,16 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill_staged(
     const uint32_t c1 = t0 + 1 < ntiles ? lcnt[t0 + 1] : 0u;
     uint32_t tot;
     const uint32_t ex = block_exscan<kFillThreads>(c0 + c1, tot, sh);
+    // with `rel`, the classify block of the same updates has already taken
+    // this block's place in every tile
+    const uint32_t *rb = rel ? rel + (size_t)blockIdx.x * ntiles : nullptr;
     if (t0 < ntiles) {
         lpre[t0] = ex;
-        lcnt[t0] = c0 ? atomicAdd(&cur[t0], c0) : 0u;
+        lcnt[t0] = c0 ? (rb ? off[t0] + rb[t0] : atomicAdd(&cur[t0], c0)) : 0u;
     }
     if (t0 + 1 < ntiles) {
         lpre[t0 + 1] = ex + c0;
-        lcnt[t0 + 1] = c1 ? atomicAdd(&cur[t0 + 1], c1) : 0u;
+        lcnt[t0 + 1] = c1 ? (rb ? off[t0 + 1] + rb[t0 + 1] : atomicAdd(&cur[t0 + 1], c1)) : 0u;
     }
     __syncthreads();
 #pragma unroll
@@ -816,13 +831,20 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
 
 hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
                       DevSketch sk, const uint32_t *hdr, const StagedParams &p,
-                      uint32_t *tile_cur, uint64_t *bins)
+                      uint32_t *tile_cur, uint64_t *bins, const uint32_t *tile_off,
+                      const uint32_t *tile_rel)
 {
     if (grid_n == 0) return hipSuccess;
     const uint32_t fb = (grid_n + kFillPerBlock - 1) / kFillPerBlock;
+    // the fill's blocks cover the same updates as the classify blocks
+    static_assert(kFillPerBlock == kClsPerBlock && kFillThreads == kClsThreads,
+                  "fill and classify blocks must cover the same updates");
+    static_assert(kRelMaxTiles <= kFillStageTiles && kRelMaxTiles <= kLdsHistMax,
+                  "tile_rel needs the classify's LDS counts and the staged fill");
+    if (tile_rel && p.ntiles > kRelMaxTiles) return hipErrorInvalidValue;
     if (p.ntiles <= kFillStageTiles)
         k_tile_fill_staged<<<fb, kFillThreads, fill_stage_lds(p.ntiles), s>>>(
-            desc, dv, sk.V, p.tile_shift, p.ntiles, tile_cur, bins, hdr);
+            desc, dv, sk.V, p.tile_shift, p.ntiles, tile_cur, bins, hdr, tile_off, tile_rel);
     else
         k_tile_fill<<<fb, kFillThreads, 0, s>>>(desc, dv, sk.V, p.tile_shift, p.ntiles, tile_cur,
                                                 bins, hdr);

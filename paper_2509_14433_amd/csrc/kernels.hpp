@@ -84,12 +84,17 @@ struct StagedParams {
 // flagged update's position in the batch, alongside.  grid_n sizes the
 // grids (the batch size, or the capacity of a captured graph); the kernels
 // read the batch from device memory at `desc` (captured graphs) or, when
-// desc is null, from `dv`.
+// desc is null, from `dv`.  When `tile_rel` is non-null (tile counts on, at
+// most kRelMaxTiles tiles; classify_blocks(grid_n) * ntiles words), block b
+// also stores at tile_rel[b*ntiles + t] where its records start inside tile
+// t's bin (written only for tiles it has records in), so that the fill
+// reserves nothing.
+constexpr uint32_t kRelMaxTiles = 2048;
 hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
                            uint32_t V, const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles, const ScanArgs &sa,
-                           uint32_t *hout, const FlagInline &fi);
+                           uint32_t *hout, const FlagInline &fi, uint32_t *tile_rel);
 uint32_t classify_blocks(uint32_t n);
 
 // Pack the per-block flag regions into one list in stream order (foff:
@@ -126,11 +131,14 @@ hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, BatchDesc
                                  uint32_t grid_n, DevSketch sk, uint32_t *hdr);
 
 // Staged scatter: launch_bin = fill of the per-tile bins (at the offsets
-// the classify kernel's tile scan wrote); launch_tile = LDS-staged XOR per
-// work item, whose last block clears the header for the next batch.
+// the classify kernel's tile scan wrote: tile_off plus the classify block's
+// tile_rel entry when tile_rel is non-null, else reserved from tile_cur);
+// launch_tile = LDS-staged XOR per work item, whose last block clears the
+// header for the next batch.
 hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
                       DevSketch sk, const uint32_t *hdr, const StagedParams &p,
-                      uint32_t *tile_cur, uint64_t *bins);
+                      uint32_t *tile_cur, uint64_t *bins, const uint32_t *tile_off,
+                      const uint32_t *tile_rel);
 hipError_t launch_tile(hipStream_t s, DevSketch sk, uint32_t *hdr, const StagedParams &p,
                        const uint32_t *tile_off, const uint64_t *bins, const uint32_t *items,
                        const uint32_t *nitems);
