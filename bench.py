@@ -68,7 +68,7 @@ def traffic_from_profile(kernel: str):
 
 # Scatter launches timed with HIP events: every TIME_EVERY-th one (each
 # event between two kernels idles the GPU for a few microseconds).
-TIME_EVERY = 4
+TIME_EVERY = 8
 
 
 def run_path(cupk, torch, packed, sizes, steps, warmup, mode, time_kernels=TIME_EVERY,

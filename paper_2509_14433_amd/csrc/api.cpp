@@ -1003,12 +1003,23 @@ int walk_exact(cupk_ctx *ctx, const uint64_t *upd, uint32_t k0, uint32_t k1, boo
 // host memory.  The stream is queried now and then: if it has drained and
 // the header is still missing, or it reports an error, the wait fails
 // instead of spinning on.
+// The stream is queried only after a millisecond without the header, then
+// once per millisecond: a query of a busy stream can queue a marker, which
+// idles the GPU for a few microseconds between two kernels.
 static int wait_header(cupk_ctx *ctx, uint32_t seq)
 {
     uint32_t *w = ctx->hdr_word;
+    double next_query = 0;
     for (uint32_t spin = 1;; spin++) {
         if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return CUPK_OK;
         if ((spin & 255) == 0) {
+            const double t = now_ms();
+            if (next_query == 0) next_query = t + 1.0;
+            if (t < next_query) {
+                __builtin_ia32_pause();
+                continue;
+            }
+            next_query = t + 1.0;
             const hipError_t e = hipStreamQuery(ctx->s);
             if (e == hipSuccess) {
                 if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return CUPK_OK;
