@@ -260,6 +260,27 @@ static int round_one_pieces(cupk_ctx *ctx, int slot, std::vector<RoundSet> &nset
         g0 = g1;
     }
     const uint32_t np = (uint32_t)P.size();
+    // One broken tree holding a large share of V: the old root's piece is
+    // not listed when it is the left-out one.  Its vertices and the other
+    // pieces' make up the tree as it was before the cuts, a union of whole
+    // components of the graph after the batch (no other tree is dirty, and
+    // every insert between two trees was linked), so no edge leaves that
+    // union and the XOR of all its vertex sketches is zero (App. A.1's stream
+    // contract: no insert of a present edge, no delete of an absent one).
+    // The piece is carried without a sketch; the next round reduces a tree
+    // that holds it from the pieces it does not hold instead.  Its smallest
+    // vertex is the first vertex of the tree that no listed piece holds.
+    const uint32_t rp = np - 1;
+    bool virtual_root = pend.back().first == pend.front().first && !ctx->opts.exact &&
+                        !ctx->levels && (uint64_t)F.tree_size(P[rp].label) * 16 >= V;
+    if (virtual_root) {
+        const uint32_t old = P[rp].label;
+        for (uint32_t x = 0; x < V; x++)
+            if (pst[x] != ep && F.label(x) == old) {
+                P[rp].minv = x;
+                break;
+            }
+    }
     // the left-out piece: largest, ties by smallest vertex (pieces in a tie
     // are listed to know their smallest vertex)
     uint32_t maxs = 0;
@@ -270,19 +291,20 @@ static int round_one_pieces(cupk_ctx *ctx, int slot, std::vector<RoundSet> &nset
     }
     uint32_t nmax = 0;
     for (const Piece &p : P) nmax += p.size == maxs;
-    if (nmax > 1)
+    if (nmax > 1 && !virtual_root)
         for (uint32_t i = 0; i < np; i++)
             if (P[i].size == maxs && !P[i].listed) list(i);
     uint32_t skip = kNone;
     for (uint32_t i = 0; i < np; i++)
         if (P[i].size == maxs && (skip == kNone || P[i].minv < P[skip].minv)) skip = i;
+    virtual_root = virtual_root && skip == rp;
     // every other piece is sampled: list the unvisited ones; the left-out one
     // is listed too (and carried, so that the next round can be built from
     // this round's sets) when it is no larger than the others together
     for (uint32_t i = 0; i < np; i++)
         if (i != skip && !P[i].listed) list(i);
-    if (!P[skip].listed && 2 * (uint64_t)P[skip].size <= total) list(skip);
-    const bool carry = P[skip].listed;
+    if (!P[skip].listed && !virtual_root && 2 * (uint64_t)P[skip].size <= total) list(skip);
+    const bool carry = P[skip].listed || virtual_root;
     // sets in ascending order of smallest vertex, the carried left-out last
     std::vector<uint32_t> gord;
     for (uint32_t i = 0; i < np; i++)
@@ -294,9 +316,12 @@ static int round_one_pieces(cupk_ctx *ctx, int slot, std::vector<RoundSet> &nset
     nsets.clear();
     for (uint32_t i : gord) {
         nsets.push_back({P[i].label, P[i].minv, P[i].size, i != skip});
-        vmem.insert(vmem.end(), mem.begin() + P[i].off, mem.begin() + P[i].off + P[i].size);
+        if (P[i].listed)
+            vmem.insert(vmem.end(), mem.begin() + P[i].off, mem.begin() + P[i].off + P[i].size);
         voff.push_back((uint32_t)vmem.size());
     }
+    // the carried old root's piece is last: a set without a sketch
+    ctx->virtual_set = virtual_root ? (uint32_t)nsets.size() - 1 : kNone;
     ctx->ctr.rounds++;
     const double tr1 = now_ms();
     int rc = reduce_and_sample(ctx, slot, vmem, voff, none, none);
@@ -462,12 +487,14 @@ int run_rounds(cupk_ctx *ctx)
     int slot = 0;
     bool linked_any = false;
     bool done = false;
+    ctx->virtual_set = kNone;
     const int r1 = ctx->opts.split_rounds ? 0 : round_one_pieces(ctx, slot, sets, &linked_any, &done);
     if (r1 < 0) return r1;
     if (r1 == 1) {
         slot = 1 - slot;
     } else {
         sets.clear();
+        ctx->virtual_set = kNone;
         const double ts0 = now_ms();
         F.split_pending();
         if (ctx->trace) fprintf(stderr, "cupk   split=%.3f ms\n", now_ms() - ts0);
@@ -504,6 +531,21 @@ int run_rounds(cupk_ctx *ctx)
             if (!g.from_frags) g.frags.clear();
             maxs = std::max(maxs, g.size);
         }
+        // A tree holding the previous round's set without a sketch (the old
+        // root's piece of the one broken tree) is reduced from all the other
+        // previous-round sets, the pieces it does not hold: the pieces
+        // together XOR to zero.
+        const uint32_t vs = ctx->virtual_set;
+        ctx->virtual_set = kNone;
+        if (vs != kNone)
+            for (Group &g : groups)
+                if (g.from_frags && std::find(g.frags.begin(), g.frags.end(), vs) != g.frags.end()) {
+                    std::vector<uint8_t> in(sets.size(), 0);
+                    for (uint32_t f : g.frags) in[f] = 1;
+                    g.frags.clear();
+                    for (uint32_t i = 0; i < sets.size(); i++)
+                        if (!in[i]) g.frags.push_back(i);
+                }
         // the left-out tree: largest, ties broken by smallest vertex id
         std::vector<std::vector<uint32_t>> lists(groups.size());
         size_t skip = groups.size();

@@ -123,6 +123,9 @@ struct cupk_ctx {
     cupk::Forest forest;
     cupk::Contraction contract;  // contracted walks of flagged runs
     std::vector<uint8_t> cand_linked;  // which round candidates linked
+    // a carried set of the last round whose sketch was not reduced (the old
+    // root's piece of the one broken tree; kNone: none)
+    uint32_t virtual_set = 0xffffffffu;
     cupk_counters_t ctr = {};
     std::string err;
 
