@@ -182,6 +182,11 @@ typedef struct {
                                     update at a time)                           */
     uint64_t timed_launches;     /* scatter launches timed (time_kernels)        */
     uint64_t timed_updates;      /* updates in the timed launches                */
+    uint64_t pieces_sketchless;  /* first rounds whose left-out old-root piece of
+                                    the lone broken tree was carried unlisted,
+                                    without a sketch                            */
+    uint64_t sets_complemented;  /* trees holding such a piece reduced from the
+                                    other pieces (all pieces XOR to zero)       */
 } cupk_counters_t;
 
 /* Bytes of device memory the sketch of (V, C, D) occupies. */

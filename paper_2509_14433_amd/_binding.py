@@ -71,7 +71,9 @@ class cupk_counters_t(ctypes.Structure):
         ("walks_contracted", ctypes.c_uint64),
         ("walks_fallback", ctypes.c_uint64),
         ("timed_launches", ctypes.c_uint64),
-        ("timed_updates", ctypes.c_uint64)]
+        ("timed_updates", ctypes.c_uint64),
+        ("pieces_sketchless", ctypes.c_uint64),
+        ("sets_complemented", ctypes.c_uint64)]
 
 
 class cupk_serve_opts(ctypes.Structure):

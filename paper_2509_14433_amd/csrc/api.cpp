@@ -322,6 +322,7 @@ static int round_one_pieces(cupk_ctx *ctx, int slot, std::vector<RoundSet> &nset
     }
     // the carried old root's piece is last: a set without a sketch
     ctx->virtual_set = virtual_root ? (uint32_t)nsets.size() - 1 : kNone;
+    if (virtual_root) ctx->ctr.pieces_sketchless++;
     ctx->ctr.rounds++;
     const double tr1 = now_ms();
     int rc = reduce_and_sample(ctx, slot, vmem, voff, none, none);
@@ -545,6 +546,7 @@ int run_rounds(cupk_ctx *ctx)
                     g.frags.clear();
                     for (uint32_t i = 0; i < sets.size(); i++)
                         if (!in[i]) g.frags.push_back(i);
+                    ctx->ctr.sets_complemented++;
                 }
         // the left-out tree: largest, ties broken by smallest vertex id
         std::vector<std::vector<uint32_t>> lists(groups.size());

@@ -349,3 +349,43 @@ def test_flag_list_boundary(cupk, mode):
     _assert_same_sketch(ctx, ref)
     assert ctx.forest_edges() == fr.forest_edges()
     ctx.close()
+
+
+def test_sketchless_root_piece(cupk):
+    # One spanning tree over nearly all vertices, then batches that each cut
+    # 120 of its edges (chosen from the oracle's forest): the first round
+    # leaves the old root's piece out without listing or reducing it, and a
+    # tree that holds it in the second round is reduced from the other
+    # pieces.  Sketch, forest and counts must match the oracle.
+    V, C, D, S = 3000, 10, 20, 0x5EED99
+    rng = np.random.default_rng(11)
+    m = 15000
+    a = rng.integers(0, V, 3 * m)
+    b = rng.integers(0, V, 3 * m)
+    keep = a != b
+    key = np.unique(np.minimum(a, b)[keep].astype(np.int64) * V + np.maximum(a, b)[keep])[:m]
+    rng.shuffle(key)
+    eu, ev = (key // V).astype(np.uint32), (key % V).astype(np.uint32)
+    ctx = cupk.Context(V, C, D, S)
+    ref = oracle.Sketch(V, C, D, S)
+    fr = oracle.ForestReplay(ref)
+    print("sketchless root: inserts", flush=True)
+    ctx.apply_updates(eu, ev, np.zeros(m, np.uint8))
+    fr.apply_batch(eu, ev, np.zeros(m, np.uint8))
+    for it in range(4):
+        fe = fr.forest_edges()
+        pick = rng.choice(len(fe), 120, replace=False)
+        du = np.array([fe[i][0] for i in pick], np.uint32)
+        dv = np.array([fe[i][1] for i in pick], np.uint32)
+        print(f"sketchless root: cut batch {it}", flush=True)
+        ctx.apply_updates(du, dv, np.ones(len(du), np.uint8))
+        fr.apply_batch(du, dv, np.ones(len(du), np.uint8))
+        _assert_same_sketch(ctx, ref)
+        assert ctx.forest_edges() == fr.forest_edges()
+    ctr = ctx.counters()
+    assert ctr["cuts"] == fr.n_cuts and ctr["rounds"] == fr.n_rounds
+    assert ctr["links"] == fr.n_links
+    print(f"sketchless={ctr['pieces_sketchless']} complemented={ctr['sets_complemented']}",
+          flush=True)
+    assert ctr["pieces_sketchless"] >= 1 and ctr["sets_complemented"] >= 1
+    ctx.close()
