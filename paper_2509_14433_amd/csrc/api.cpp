@@ -1047,23 +1047,26 @@ int walk_exact(cupk_ctx *ctx, const uint64_t *upd, uint32_t k0, uint32_t k1, boo
 // host memory.  The stream is queried now and then: if it has drained and
 // the header is still missing, or it reports an error, the wait fails
 // instead of spinning on.
-// The stream is queried only after a millisecond without the header, then
-// once per millisecond: a query of a busy stream can queue a marker, which
-// idles the GPU for a few microseconds between two kernels.
+// A batch already in device memory: the stream is queried only after a
+// millisecond without the header, then once per millisecond (a query of a
+// busy stream can queue a marker, which idles the GPU for a few
+// microseconds between two kernels).  A batch uploaded from host memory:
+// every 256 spins, which kept the served query latency lower.
 static int wait_header(cupk_ctx *ctx, uint32_t seq)
 {
     uint32_t *w = ctx->hdr_word;
+    const double every = ctx->query_often ? 0.0 : 1.0;
     double next_query = 0;
     for (uint32_t spin = 1;; spin++) {
         if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return CUPK_OK;
         if ((spin & 255) == 0) {
             const double t = now_ms();
-            if (next_query == 0) next_query = t + 1.0;
+            if (next_query == 0) next_query = t + every;
             if (t < next_query) {
                 __builtin_ia32_pause();
                 continue;
             }
-            next_query = t + 1.0;
+            next_query = t + every;
             const hipError_t e = hipStreamQuery(ctx->s);
             if (e == hipSuccess) {
                 if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return CUPK_OK;
@@ -1229,7 +1232,10 @@ int apply_packed_host(cupk_ctx *ctx, const uint64_t *packed, size_t n)
     HIPCHK(grow(ctx->d_upd, n));
     std::copy(packed, packed + n, ctx->h_upd.p);
     HIPCHK(hipMemcpyAsync(ctx->d_upd.p, ctx->h_upd.p, n * 8, hipMemcpyHostToDevice, ctx->s));
-    return apply_device(ctx, ctx->d_upd.p, n);
+    ctx->query_often = true;
+    const int rc = apply_device(ctx, ctx->d_upd.p, n);
+    ctx->query_often = false;
+    return rc;
 }
 
 int connected_impl(cupk_ctx *ctx, uint32_t u, uint32_t v)
@@ -1489,7 +1495,10 @@ int cupk_apply_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
         for (size_t i = 0; i < n; i++)
             h[i] = (uint64_t)u[i] | ((uint64_t)v[i] << 32) | ((uint64_t)(is_delete[i] != 0) << 63);
         HIPCHK(hipMemcpyAsync(ctx->d_upd.p, h, n * 8, hipMemcpyHostToDevice, ctx->s));
-        return apply_device(ctx, ctx->d_upd.p, n);
+        ctx->query_often = true;
+        const int rc = apply_device(ctx, ctx->d_upd.p, n);
+        ctx->query_often = false;
+        return rc;
     });
 }
 

@@ -58,6 +58,7 @@ struct cupk_ctx {
     bool own_stream = false;
     uint32_t hdr_seq = 0;          // headers published by the device so far (expected)
     uint32_t *hdr_word = nullptr;  // where the current pass publishes its sequence number
+    bool query_often = false;      // the pass's batch was uploaded from host memory
     struct TimerSlot {
         hipEvent_t t0, tb, t1;
         bool busy;
