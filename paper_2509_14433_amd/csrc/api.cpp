@@ -849,6 +849,12 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
         sa.nitems = ctx->d_nitems;
         sa.chunk = ctx->chunk;
         sa.items_cap = staged_params(ctx, grid_n).items_cap;
+        sa.groups = 1;
+    }
+    uint32_t *rel = staged ? rel_ptr(ctx, grid_n) : nullptr;
+    if (rel) {
+        sa.groups = kCntGroups;
+        sa.goff = ctx->d_tgoff.p;
     }
     // short flag lists come back with the header (not in exact mode, which
     // also needs their positions)
@@ -861,7 +867,7 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
                            ctx->d_par, ctx->d_hdr, ctx->d_fupd.p,
                            ctx->opts.exact ? ctx->d_fpos.p : nullptr, ctx->d_fcnt.p,
                            staged ? ctx->d_tcnt.p : nullptr, ctx->tile_shift, ctx->ntiles, sa,
-                           ctx->h_hdr, fi, staged ? rel_ptr(ctx, grid_n) : nullptr));
+                           ctx->h_hdr, fi, rel));
     return CUPK_OK;
 }
 
@@ -869,7 +875,7 @@ int enqueue_bin(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
 {
     if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED) return CUPK_OK;
     HIPCHK(launch_bin(s, desc_ptr(ctx), ctx->cur_desc, grid_n, dev_sketch(ctx), ctx->d_hdr,
-                      staged_params(ctx, grid_n), ctx->d_tcur.p, ctx->d_bins.p, ctx->d_toff.p,
+                      staged_params(ctx, grid_n), ctx->d_tcur.p, ctx->d_bins.p, ctx->d_tgoff.p,
                       rel_ptr(ctx, grid_n)));
     return CUPK_OK;
 }
@@ -1280,6 +1286,7 @@ void destroy(cupk_ctx *ctx)
     release(ctx->d_toff);
     release(ctx->d_tcur);
     release(ctx->d_trel);
+    release(ctx->d_tgoff);
     release(ctx->d_items);
     release(ctx->d_bins);
     release(ctx->d_ridx);
@@ -1318,11 +1325,15 @@ int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk)
     ctx->chunk = chunk;
     ctx->ntiles = (uint32_t)(((uint64_t)ctx->V + tv - 1) >> sh);
     if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
-        HIPCHK(grow(ctx->d_tcnt, ctx->ntiles + 1));
+        // counts: kCntGroups copies (one in use unless classify blocks also
+        // store where their records start)
+        const size_t ncnt = (size_t)kCntGroups * ctx->ntiles + 1;
+        HIPCHK(grow(ctx->d_tcnt, ncnt));
+        HIPCHK(grow(ctx->d_tgoff, ncnt));
         HIPCHK(grow(ctx->d_toff, ctx->ntiles + 1));
         HIPCHK(grow(ctx->d_tcur, ctx->ntiles + 1));
         // the scan kernel re-zeroes the counts after every batch
-        HIPCHK(launch_zero32(ctx->s, ctx->d_tcnt.p, ctx->ntiles + 1));
+        HIPCHK(launch_zero32(ctx->s, ctx->d_tcnt.p, ncnt));
         // work-item capacity depends on ntiles and chunk
         const size_t icap = 2 * ctx->batch_cap / chunk + ctx->ntiles + 1;
         HIPCHK(grow(ctx->d_items, 2 * icap));

@@ -87,6 +87,7 @@ struct cupk_ctx {
     uint32_t tile_shift = 5, rows = 8, chunk = 4096, ntiles = 0, tile_grid = 0;
     cupk::DevBuf<uint32_t> d_tcnt, d_toff, d_tcur, d_items;
     cupk::DevBuf<uint32_t> d_trel;  // per (classify block, tile): start inside the tile's bin
+    cupk::DevBuf<uint32_t> d_tgoff; // per (count copy, tile): where the copy's records start
     cupk::DevBuf<uint64_t> d_bins;
     uint32_t *d_nitems = nullptr;
 

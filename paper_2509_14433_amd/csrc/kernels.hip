@@ -165,9 +165,10 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict
         __hip_atomic_store(&hout[HDR_SEQ], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     if (!a.off) return;
+    const uint32_t ng = a.groups;  // count copies (1 or kCntGroups)
     if (err) {
         // rejected batch: leave the counts zeroed for the next one
-        for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) cnt[t] = 0;
+        for (uint32_t t = threadIdx.x; t < ng * ntiles; t += blockDim.x) cnt[t] = 0;
         if (threadIdx.x == 0) *a.nitems = 0;
         return;
     }
@@ -176,8 +177,17 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict
     uint32_t carry_r = 0, carry_i = 0;
     for (uint32_t base = 0; base < ntiles; base += kScanThreads) {
         const uint32_t t = base + threadIdx.x;
-        const uint32_t c = t < ntiles ? cnt[t] : 0u;
-        if (t < ntiles) cnt[t] = 0;  // ready for the next batch's counts
+        uint32_t c = 0;
+        uint32_t cg[kCntGroups];
+#pragma unroll
+        for (uint32_t g = 0; g < kCntGroups; g++) {
+            cg[g] = 0;
+            if (t < ntiles && g < ng) {
+                cg[g] = cnt[g * ntiles + t];
+                cnt[g * ntiles + t] = 0;  // ready for the next batch's counts
+                c += cg[g];
+            }
+        }
         const uint32_t k = (c + chunk - 1) / chunk;
         uint32_t tot_c, tot_k;
         const uint32_t ex_c = block_exscan<kScanThreads>(c, tot_c, sh);
@@ -185,6 +195,16 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict
         if (t < ntiles) {
             off[t] = carry_r + ex_c;
             cur[t] = carry_r + ex_c;
+            if (a.goff) {
+                // where each copy's records start: after the copies before it
+                uint32_t o = carry_r + ex_c;
+#pragma unroll
+                for (uint32_t g = 0; g < kCntGroups; g++)
+                    if (g < ng) {
+                        a.goff[g * ntiles + t] = o;
+                        o += cg[g];
+                    }
+            }
             for (uint32_t j = 0; j < k; j++) {
                 const uint32_t q = carry_i + ex_k + j;
                 if (q < items_cap) {
@@ -315,12 +335,13 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
     if (use_lds) {
         __syncthreads();
         if (tile_rel) {
-            // the returned count is where this block's records start in
-            // the tile's bin (relative to the tile's offset)
+            // the returned count is where this block's records start among
+            // its count copy's records in the tile's bin
             uint32_t *rb = tile_rel + (size_t)blockIdx.x * ntiles;
+            uint32_t *tc = tile_cnt + (blockIdx.x % kCntGroups) * ntiles;
             for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
                 const uint32_t h = hist[t];
-                if (h) rb[t] = atomicAdd(&tile_cnt[t], h);
+                if (h) rb[t] = atomicAdd(&tc[t], h);
             }
         } else {
             for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x)
@@ -338,7 +359,9 @@ hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, u
                            uint32_t *hout, const FlagInline &fi, uint32_t *tile_rel)
 {
     if (grid_n == 0) return hipSuccess;
-    if (tile_rel && (!tile_cnt || ntiles > kRelMaxTiles)) return hipErrorInvalidValue;
+    if (tile_rel && (!tile_cnt || ntiles > kRelMaxTiles || sa.groups != kCntGroups || !sa.goff))
+        return hipErrorInvalidValue;
+    if (!tile_rel && tile_cnt && sa.groups != 1) return hipErrorInvalidValue;
     k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(
         desc, dv, V, lbl, par, hdr, fupd, fpos, fcnt, tile_cnt, tile_shift, ntiles, tile_rel);
     hipError_t e = hipGetLastError();
@@ -639,7 +662,7 @@ static size_t fill_stage_lds(uint32_t ntiles)
 __global__ __launch_bounds__(kFillThreads) void k_tile_fill_staged(
     const BatchDesc *__restrict__ desc, BatchDesc dv, uint32_t V, uint32_t tile_shift,
     uint32_t ntiles, uint32_t *__restrict__ cur, uint64_t *__restrict__ bins,
-    const uint32_t *__restrict__ hdr, const uint32_t *__restrict__ off,
+    const uint32_t *__restrict__ hdr, const uint32_t *__restrict__ goff,
     const uint32_t *__restrict__ rel)
 {
     extern __shared__ uint64_t fsm[];
@@ -681,15 +704,16 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill_staged(
     uint32_t tot;
     const uint32_t ex = block_exscan<kFillThreads>(c0 + c1, tot, sh);
     // with `rel`, the classify block of the same updates has already taken
-    // this block's place in every tile
+    // this block's place in every tile, among the records of its count copy
     const uint32_t *rb = rel ? rel + (size_t)blockIdx.x * ntiles : nullptr;
+    const uint32_t *go = rel ? goff + (blockIdx.x % kCntGroups) * ntiles : nullptr;
     if (t0 < ntiles) {
         lpre[t0] = ex;
-        lcnt[t0] = c0 ? (rb ? off[t0] + rb[t0] : atomicAdd(&cur[t0], c0)) : 0u;
+        lcnt[t0] = c0 ? (rb ? go[t0] + rb[t0] : atomicAdd(&cur[t0], c0)) : 0u;
     }
     if (t0 + 1 < ntiles) {
         lpre[t0 + 1] = ex + c0;
-        lcnt[t0 + 1] = c1 ? (rb ? off[t0 + 1] + rb[t0 + 1] : atomicAdd(&cur[t0 + 1], c1)) : 0u;
+        lcnt[t0 + 1] = c1 ? (rb ? go[t0 + 1] + rb[t0 + 1] : atomicAdd(&cur[t0 + 1], c1)) : 0u;
     }
     __syncthreads();
 #pragma unroll
@@ -831,7 +855,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
 
 hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
                       DevSketch sk, const uint32_t *hdr, const StagedParams &p,
-                      uint32_t *tile_cur, uint64_t *bins, const uint32_t *tile_off,
+                      uint32_t *tile_cur, uint64_t *bins, const uint32_t *tile_goff,
                       const uint32_t *tile_rel)
 {
     if (grid_n == 0) return hipSuccess;
@@ -841,10 +865,10 @@ hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32
                   "fill and classify blocks must cover the same updates");
     static_assert(kRelMaxTiles <= kFillStageTiles && kRelMaxTiles <= kLdsHistMax,
                   "tile_rel needs the classify's LDS counts and the staged fill");
-    if (tile_rel && p.ntiles > kRelMaxTiles) return hipErrorInvalidValue;
+    if (tile_rel && (p.ntiles > kRelMaxTiles || !tile_goff)) return hipErrorInvalidValue;
     if (p.ntiles <= kFillStageTiles)
         k_tile_fill_staged<<<fb, kFillThreads, fill_stage_lds(p.ntiles), s>>>(
-            desc, dv, sk.V, p.tile_shift, p.ntiles, tile_cur, bins, hdr, tile_off, tile_rel);
+            desc, dv, sk.V, p.tile_shift, p.ntiles, tile_cur, bins, hdr, tile_goff, tile_rel);
     else
         k_tile_fill<<<fb, kFillThreads, 0, s>>>(desc, dv, sk.V, p.tile_shift, p.ntiles, tile_cur,
                                                 bins, hdr);

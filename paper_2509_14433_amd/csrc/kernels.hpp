@@ -56,9 +56,17 @@ struct FlagInline {
 // Where the tile scan (run by the last classify block) writes: bin offsets
 // and fill cursors (ntiles + 1 words each), work items (tile, chunk) and
 // their number.
+// Tile counts are kept in `groups` copies of ntiles words (1, or
+// kCntGroups when classify blocks also store where their records start:
+// block b adds to copy b % kCntGroups, so that fewer blocks meet on one
+// counter).  goff (groups * ntiles words, may be null) receives where each
+// copy's records start in every tile's bin.
+constexpr uint32_t kCntGroups = 8;
 struct ScanArgs {
     uint32_t *off, *cur, *items, *nitems;
     uint32_t chunk, items_cap;
+    uint32_t groups;
+    uint32_t *goff;
 };
 
 struct StagedParams {
@@ -85,10 +93,11 @@ struct StagedParams {
 // grids (the batch size, or the capacity of a captured graph); the kernels
 // read the batch from device memory at `desc` (captured graphs) or, when
 // desc is null, from `dv`.  When `tile_rel` is non-null (tile counts on, at
-// most kRelMaxTiles tiles; classify_blocks(grid_n) * ntiles words), block b
-// also stores at tile_rel[b*ntiles + t] where its records start inside tile
-// t's bin (written only for tiles it has records in), so that the fill
-// reserves nothing.
+// most kRelMaxTiles tiles; classify_blocks(grid_n) * ntiles words; tile_cnt
+// of kCntGroups * ntiles words and sa.groups == kCntGroups), block b also
+// stores at tile_rel[b*ntiles + t] where its records start among the
+// records of count copy b % kCntGroups in tile t (written only for tiles it
+// has records in), so that the fill reserves nothing.
 constexpr uint32_t kRelMaxTiles = 2048;
 hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
                            uint32_t V, const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
@@ -131,13 +140,14 @@ hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, BatchDesc
                                  uint32_t grid_n, DevSketch sk, uint32_t *hdr);
 
 // Staged scatter: launch_bin = fill of the per-tile bins (at the offsets
-// the classify kernel's tile scan wrote: tile_off plus the classify block's
-// tile_rel entry when tile_rel is non-null, else reserved from tile_cur);
+// the classify kernel's tile scan wrote: the count copy's start in
+// tile_goff plus the classify block's tile_rel entry when tile_rel is
+// non-null, else reserved from tile_cur);
 // launch_tile = LDS-staged XOR per work item, whose last block clears the
 // header for the next batch.
 hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
                       DevSketch sk, const uint32_t *hdr, const StagedParams &p,
-                      uint32_t *tile_cur, uint64_t *bins, const uint32_t *tile_off,
+                      uint32_t *tile_cur, uint64_t *bins, const uint32_t *tile_goff,
                       const uint32_t *tile_rel);
 hipError_t launch_tile(hipStream_t s, DevSketch sk, uint32_t *hdr, const StagedParams &p,
                        const uint32_t *tile_off, const uint64_t *bins, const uint32_t *items,
