@@ -128,6 +128,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict
 {
     __shared__ uint32_t sh[160];
     __shared__ uint32_t boff[kInlineMaxBlocks];
+    static_assert(kInlineFlags < 65536 && kClsPerBlock < 65536, "packed region words");
     const bool err = hdr[HDR_ERR] != 0;
     const uint32_t nflag = hdr[HDR_NFLAG];
     // few flagged updates: compact them into host memory in stream order
@@ -140,17 +141,25 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict
             const uint32_t c = b < fi.nb ? fi.fcnt[b] : 0u;
             uint32_t tot;
             const uint32_t ex = block_exscan<kScanThreads>(c, tot, sh);
-            if (b < fi.nb) boff[b] = carry + ex;
+            // count (<= 4096) and start (<= kInlineFlags) of the region,
+            // packed: the copy below reads no global count again
+            if (b < fi.nb) boff[b] = c << 16 | (carry + ex);
             carry += tot;
         }
         __syncthreads();
         const uint32_t lane = __lane_id();
         for (uint32_t b = threadIdx.x / 64; b < fi.nb; b += kScanThreads / 64) {
-            const uint32_t c = fi.fcnt[b], o = boff[b];
+            const uint32_t w = boff[b];
+            const uint32_t c = w >> 16, o = w & 0xffffu;
             for (uint32_t k = lane; k < c; k += 64)
                 fi.hflags[o + k] = fi.fupd[(size_t)b * kClsPerBlock + k];
         }
-        __threadfence_system();
+        // every wave waits until its stores have been acknowledged; thread
+        // 0's system-scope release of the sequence number below then writes
+        // back L2 once for the whole block (a system fence in every wave
+        // would write it back once per wave)
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
     // the header goes straight to host memory (no copy, no event): words
