@@ -515,8 +515,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_classify(
             if (with_pos) out->fpos[q] = k * kSmallThreads + threadIdx.x;
         }
     }
-    // the result is in host memory before the sequence number says so
-    __threadfence_system();
+    // the result is in host memory before the sequence number says so:
+    // every wave waits until its stores have been acknowledged, and thread
+    // 0's system-scope release below writes back L2 once for the block
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         *derr = s_bad;  // for the scatter
