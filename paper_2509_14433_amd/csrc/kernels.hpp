@@ -53,9 +53,8 @@ struct FlagInline {
     uint64_t *hflags;      // coherent pinned host memory; null: never inline
 };
 
-// Where the tile scan (run by the last classify block) writes: bin offsets
-// and fill cursors (ntiles + 1 words each), work items (tile, chunk) and
-// their number.
+// Where the one-block tile scan writes: bin offsets and fill cursors
+// (ntiles + 1 words each), work items (tile, chunk) and their number.
 // Tile counts are kept in `groups` copies of ntiles words (1, or
 // kCntGroups when classify blocks also store where their records start:
 // block b adds to copy b % kCntGroups, so that fewer blocks meet on one
