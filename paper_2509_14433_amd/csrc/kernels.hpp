@@ -60,7 +60,7 @@ struct FlagInline {
 // block b adds to copy b % kCntGroups, so that fewer blocks meet on one
 // counter).  goff (groups * ntiles words, may be null) receives where each
 // copy's records start in every tile's bin.
-constexpr uint32_t kCntGroups = 8;
+constexpr uint32_t kCntGroups = 4;
 struct ScanArgs {
     uint32_t *off, *cur, *items, *nitems;
     uint32_t chunk, items_cap;
