@@ -61,6 +61,10 @@ CASES = [
     (333, 0.1, 0.5, 1000, 16, 2),
     (1000, 0.02, 0.3, 777, 4, 0),
     (2, 1.0, 0.0, None, 0, 0),
+    # one vertex per tile: 2048 tiles (the most for which classify blocks
+    # store their bin starts), then 2049 (fill reserves per record)
+    (2048, 0.004, 0.3, 5000, 1, 0),
+    (2049, 0.004, 0.3, 5000, 1, 0),
 ]
 
 
