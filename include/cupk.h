@@ -153,6 +153,14 @@ typedef struct {
      * gives the same forest and counts without relabelling pieces that the
      * round links back together. */
     uint32_t split_rounds;
+    /* Nonzero: the staged fill reserves each (block, tile) range in the bins
+     * with an atomic, and the classify kernel keeps one set of tile counts.
+     * Default: each classify block adds its tile counts to one of four
+     * copies and stores where its records start (one word per classify
+     * block and tile, up to 2^25 words, at most 2048 tiles; beyond that the
+     * fill reserves), so that the fill reserves nothing.  Same bins up to
+     * the order of records inside a tile, same sketch. */
+    uint32_t fill_reserve;
 } cupk_opts;
 
 /* Counters, cumulative since init. */

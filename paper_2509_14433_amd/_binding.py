@@ -56,6 +56,7 @@ class cupk_opts(ctypes.Structure):
         ("levels", ctypes.c_uint32),
         ("walk_plain", ctypes.c_uint32),
         ("split_rounds", ctypes.c_uint32),
+        ("fill_reserve", ctypes.c_uint32),
     ]
 
 
@@ -179,7 +180,7 @@ class Context:
     def __init__(self, V, C=0, D=0, seed=0, scatter_mode=SCATTER_STAGED, max_batch=0,
                  stream=None, use_torch_memory=True, time_kernels=False, tile_vertices=0,
                  lds_rows=0, chunk_records=0, tile_grid=0, use_graph=False, exact=False,
-                 levels=False, walk_plain=False, split_rounds=False):
+                 levels=False, walk_plain=False, split_rounds=False, fill_reserve=False):
         self._h = None
         self._sk_tensor = None
         self._keep = {}
@@ -197,6 +198,7 @@ class Context:
         opts.levels = 1 if levels else 0
         opts.walk_plain = 1 if walk_plain else 0
         opts.split_rounds = 1 if split_rounds else 0
+        opts.fill_reserve = 1 if fill_reserve else 0
         torch = _torch()
         if stream is None and torch is not None and torch.cuda.is_available():
             # launch on torch's current stream so that torch-produced device

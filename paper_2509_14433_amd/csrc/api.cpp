@@ -791,7 +791,9 @@ int ensure_batch_buffers(cupk_ctx *ctx, size_t n)
 constexpr size_t kRelMaxWords = (size_t)1 << 25;
 static size_t rel_words(cupk_ctx *ctx, size_t n)
 {
-    if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED || ctx->ntiles > kRelMaxTiles) return 0;
+    if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED || ctx->opts.fill_reserve ||
+        ctx->ntiles > kRelMaxTiles)
+        return 0;
     const size_t w = (size_t)classify_blocks((uint32_t)std::min<size_t>(n, kMaxBatchPerLaunch)) *
                      ctx->ntiles;
     return w <= kRelMaxWords ? w : 0;

@@ -393,3 +393,21 @@ def test_sketchless_root_piece(cupk):
           flush=True)
     assert ctr["pieces_sketchless"] >= 1 and ctr["sets_complemented"] >= 1
     ctx.close()
+
+
+def test_fill_reserve_option(cupk):
+    # The staged fill reserving its own bin ranges (one set of tile counts)
+    # gives the oracle's sketch and forest like the default, where classify
+    # blocks store their bin starts.
+    V, p, df = 1000, 0.02, 0.3
+    C = max(1, math.ceil(math.log2(V)))
+    D = 2 * C
+    S = 0x5EEDF111
+    u, v, d = streamgen.er_standard(V, p, df, 4242)
+    for reserve in (True, False):
+        print(f"fill_reserve={reserve} n={len(u)}", flush=True)
+        ctx, ref, fr = _replay(cupk, "staged", V, C, D, S, u, v, d, 4500, tile_vertices=8,
+                               fill_reserve=reserve)
+        _assert_same_sketch(ctx, ref)
+        assert ctx.forest_edges() == fr.forest_edges()
+        ctx.close()
