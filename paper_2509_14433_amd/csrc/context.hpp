@@ -22,7 +22,7 @@
 
 namespace cupk {
 
-constexpr uint32_t kRedChunk = 32;          // members per reduction work item
+constexpr uint32_t kRedChunk = 16;          // members per reduction work item
 constexpr size_t kMaxBatchPerLaunch = 1u << 28;
 constexpr int kTimerRing = 64;
 
