@@ -83,6 +83,18 @@ static int compare(Forest &A, Forest &B, uint64_t r)
         if (A.is_dirty(A.label(w)) != B.is_dirty(B.label(w))) return fail("dirty trees", r);
     for (uint32_t w = 0; w < A.V(); w++)
         if (A.tree_size(A.label(w)) != B.tree_size(B.label(w))) return fail("tree sizes", r);
+    // child lists agree with the parent pointers
+    for (const Forest *F : {&A, &B}) {
+        size_t kids = 0, nonroots = 0;
+        for (uint32_t w = 0; w < F->V(); w++) {
+            if (F->parent(w) != cupk::kNone) nonroots++;
+            for (uint32_t y = F->first_child(w); y != cupk::kNone; y = F->next_sibling(y)) {
+                if (F->parent(y) != w) return fail("child lists", r);
+                if (++kids > F->V()) return fail("child lists (cycle)", r);
+            }
+        }
+        if (kids != nonroots) return fail("child list count", r);
+    }
     // each tree's recorded root is a root of that tree
     for (const Forest *F : {&A, &B})
         for (uint32_t w = 0; w < F->V(); w++) {
@@ -114,13 +126,24 @@ int main(int argc, char **argv)
         if (a == b) continue;
         pool.push_back({std::min(a, b), std::max(a, b)});
     }
-    // a start forest: random links, grown on both copies alike
-    for (uint32_t i = 0; i < V; i++) {
-        const uint32_t a = (uint32_t)(rng() % V), b = (uint32_t)(rng() % V);
-        if (a == b || A.same_tree(a, b)) continue;
-        A.link(a, b);
-        B.link(a, b);
-        G.insert({std::min(a, b), std::max(a, b)});
+    // a start forest: random links from singletons, one by one on A and in
+    // one link_many on B
+    {
+        std::vector<std::pair<uint32_t, uint32_t>> cand;
+        for (uint32_t i = 0; i < V; i++) {
+            const uint32_t a = (uint32_t)(rng() % V), b = (uint32_t)(rng() % V);
+            if (a != b) cand.push_back({a, b});
+        }
+        std::vector<uint8_t> got;
+        size_t nw = 0;
+        for (const auto &e : cand)
+            if (!A.same_tree(e.first, e.second)) {
+                A.link(e.first, e.second);
+                G.insert({std::min(e.first, e.second), std::max(e.first, e.second)});
+                nw++;
+            }
+        if (B.link_many(cand, got) != nw) return fail("link_many: start forest", 0);
+        if (compare(A, B, 0)) return 1;
     }
     uint64_t fallbacks = 0, contracted = 0;
     for (uint64_t r = 0; r < runs; r++) {
