@@ -141,28 +141,26 @@ int reduce_and_sample(cupk_ctx *ctx, int slot, const std::vector<uint32_t> &vmem
     const size_t nvi = items.size() / 3;
     add_items(foff, kv, (uint32_t)vmem.size());
     const size_t nitems = items.size() / 3;
+    // members, then the work items, in one buffer and one copy
     const size_t nmem = vmem.size() + fmem.size();
-    HIPCHK(grow(ctx->h_ridx, nmem + 1));
-    HIPCHK(grow(ctx->d_ridx, nmem + 1));
-    HIPCHK(grow(ctx->h_ritems, items.size() + 1));
-    HIPCHK(grow(ctx->d_ritems, items.size() + 1));
+    const size_t nall = nmem + items.size();
+    HIPCHK(grow(ctx->h_ridx, nall + 1));
+    HIPCHK(grow(ctx->d_ridx, nall + 1));
     std::copy(vmem.begin(), vmem.end(), ctx->h_ridx.p);
     std::copy(fmem.begin(), fmem.end(), ctx->h_ridx.p + vmem.size());
-    std::copy(items.begin(), items.end(), ctx->h_ritems.p);
-    if (nmem)
-        HIPCHK(hipMemcpyAsync(ctx->d_ridx.p, ctx->h_ridx.p, nmem * 4, hipMemcpyHostToDevice,
+    std::copy(items.begin(), items.end(), ctx->h_ridx.p + nmem);
+    if (nall)
+        HIPCHK(hipMemcpyAsync(ctx->d_ridx.p, ctx->h_ridx.p, nall * 4, hipMemcpyHostToDevice,
                               ctx->s));
-    if (!items.empty())
-        HIPCHK(hipMemcpyAsync(ctx->d_ritems.p, ctx->h_ritems.p, items.size() * 4,
-                              hipMemcpyHostToDevice, ctx->s));
+    const uint32_t *d_items = ctx->d_ridx.p + nmem;
     uint64_t *sig = ctx->d_sig[slot].p;
     HIPCHK(launch_zero(ctx->s, sig, (size_t)k * W));
     if (nvi)
-        HIPCHK(launch_reduce(ctx->s, ctx->d_sk, W, ctx->d_ridx.p, ctx->d_ritems.p, (uint32_t)nvi,
+        HIPCHK(launch_reduce(ctx->s, ctx->d_sk, W, ctx->d_ridx.p, d_items, (uint32_t)nvi,
                              sig));
     if (nitems > nvi)
         HIPCHK(launch_reduce(ctx->s, ctx->d_sig[1 - slot].p, W, ctx->d_ridx.p,
-                             ctx->d_ritems.p + 3 * nvi, (uint32_t)(nitems - nvi), sig));
+                             d_items + 3 * nvi, (uint32_t)(nitems - nvi), sig));
     HIPCHK(launch_sample(ctx->s, sig, k, ctx->V, ctx->C, ctx->D, 1, ctx->C, W, ctx->d_seeds,
                          ctx->d_res.p));
     HIPCHK(hipMemcpyAsync(ctx->h_res.p, ctx->d_res.p, (size_t)3 * k * 4, hipMemcpyDeviceToHost,
@@ -1292,9 +1290,7 @@ void destroy(cupk_ctx *ctx)
     release(ctx->d_items);
     release(ctx->d_bins);
     release(ctx->d_ridx);
-    release(ctx->d_ritems);
     release(ctx->h_ridx);
-    release(ctx->h_ritems);
     release(ctx->d_sig[0]);
     release(ctx->d_sig[1]);
     release(ctx->d_res);
@@ -1438,10 +1434,8 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
         HIPCHK(grow(ctx->d_sig[1], sets * ctx->W));
         HIPCHK(grow(ctx->d_res, 3 * sets));
         HIPCHK(grow(ctx->h_res, 3 * sets));
-        HIPCHK(grow(ctx->d_ridx, (size_t)V + 1));
-        HIPCHK(grow(ctx->h_ridx, (size_t)V + 1));
-        HIPCHK(grow(ctx->d_ritems, 3 * items));
-        HIPCHK(grow(ctx->h_ritems, 3 * items));
+        HIPCHK(grow(ctx->d_ridx, (size_t)V + 1 + 3 * items));
+        HIPCHK(grow(ctx->h_ridx, (size_t)V + 1 + 3 * items));
     }
     HIPCHK(hipStreamSynchronize(ctx->s));
     return CUPK_OK;

@@ -92,8 +92,8 @@ struct cupk_ctx {
     uint32_t *d_nitems = nullptr;
 
     // reductions / samples
-    cupk::DevBuf<uint32_t> d_ridx, d_ritems;
-    cupk::HostBuf<uint32_t> h_ridx, h_ritems;
+    cupk::DevBuf<uint32_t> d_ridx;   // members, then the work items, of a reduction
+    cupk::HostBuf<uint32_t> h_ridx;
     cupk::DevBuf<uint64_t> d_sig[2];
     cupk::DevBuf<int32_t> d_res;
     cupk::HostBuf<int32_t> h_res;
