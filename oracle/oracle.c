@@ -237,30 +237,30 @@ int orc_sample(uint32_t V, uint32_t C, uint32_t D, uint64_t S,
 }
 
 /* The query of column c alone: the sampler of one level of the multi-level
- * hierarchy (Sec. 2.2.2; level c uses column c).  Same scan as orc_sample
- * over that column's depths; EMPTY when the column is all zero. */
+ * hierarchy (Sec. 2.2.2; level c uses column c).  The column's depths are
+ * scanned deepest first (the same order as inside a column of orc_sample);
+ * the first bucket that verifies is returned.  EMPTY when every word of
+ * the column is zero, FAILED when some word is not but nothing verified. */
 int orc_sample_col(uint32_t V, uint32_t C, uint32_t D, uint64_t S, uint32_t c,
                    const uint64_t *alpha, const uint64_t *gamma,
                    uint32_t *out_u, uint32_t *out_v)
 {
-    uint64_t seed = orc_seed(S, c);
+    const uint64_t seed_c = orc_seed(S, c);
+    const uint64_t *col_a = alpha + (size_t)c * D; /* column c: D depths */
+    const uint64_t *col_g = gamma + (size_t)c * D;
+    int nonzero = 0;
     (void)C;
-    for (uint32_t k = 0; k < D; k++) {
-        uint32_t d = D - 1 - k;
-        uint64_t a = alpha[c * D + d];
-        uint64_t g = gamma[c * D + d];
-        if (a == 0) continue;
-        if (!orc_valid_index(V, a)) continue;
-        uint64_t h = orc_mix(a ^ seed);
-        if (h != g) continue;
-        if (orc_depth_of_hash(h, D) != d) continue;
+    for (int32_t d = (int32_t)D - 1; d >= 0; d--) { /* deepest first */
+        const uint64_t a = col_a[d], g = col_g[d];
+        if ((a | g) != 0) nonzero = 1;
+        if (a == 0 || !orc_valid_index(V, a)) continue;
+        const uint64_t hc = orc_mix(a ^ seed_c);
+        if (hc != g || orc_depth_of_hash(hc, D) != (uint32_t)d) continue;
         *out_u = (uint32_t)(a / V);
         *out_v = (uint32_t)(a % V);
         return ORC_OK;
     }
-    for (uint32_t d = 0; d < D; d++)
-        if (alpha[c * D + d] != 0 || gamma[c * D + d] != 0) return ORC_FAILED;
-    return ORC_EMPTY;
+    return nonzero ? ORC_FAILED : ORC_EMPTY;
 }
 
 /* Order-independent 64-bit digest of a whole sketch:

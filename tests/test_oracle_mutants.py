@@ -27,6 +27,17 @@ MUTANTS = {
     "gamma_missing_at_one_endpoint": ("s->alpha[iv] ^= x; s->gamma[iv] ^= h;",
                                       "s->alpha[iv] ^= x;"),
     "index_transposed": ("return (uint64_t)u * V + v;", "return (uint64_t)v * V + u;"),
+    # the one-column sampler (level c of the hierarchy)
+    "column_scan_ascending": (
+        "for (int32_t d = (int32_t)D - 1; d >= 0; d--) { /* deepest first */",
+        "for (int32_t d = 0; d < (int32_t)D; d++) {"),
+    "column_checksum_dropped": (
+        "if (hc != g || orc_depth_of_hash(hc, D) != (uint32_t)d) continue;",
+        "if (orc_depth_of_hash(hc, D) != (uint32_t)d) continue;"),
+    "column_seed_of_column_zero": ("const uint64_t seed_c = orc_seed(S, c);",
+                                   "const uint64_t seed_c = orc_seed(S, 0);"),
+    "column_failed_reported_empty": ("return nonzero ? ORC_FAILED : ORC_EMPTY;",
+                                     "return ORC_EMPTY;"),
 }
 
 

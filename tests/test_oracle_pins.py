@@ -309,6 +309,132 @@ def test_sample_takes_first_good_bucket_in_canonical_order(orc):
             assert st == orc.OK and (x, y) == want
 
 
+# ---- the one-column sampler (level c of the hierarchy uses column c) -------
+#
+# These pins fix orc_sample_col from outside: which edges a column holds,
+# and how many, follows from the cut edge list and the depth function alone
+# (pinned above), not from the sampler's verification.
+
+
+def _column_from_edges(orc, V, C, D, S, c, edges):
+    """Column c of the aggregate sketch of an explicit edge list, built by
+    XOR-ing (x, h_c(x)) into depth d_c(x): the streaming definition written
+    out for one column.  Returns (alpha, gamma) as C x D arrays that are zero
+    outside column c, and {depth: [edges]}."""
+    a = np.zeros((C, D), np.uint64)
+    g = np.zeros((C, D), np.uint64)
+    at = {}
+    for (x0, y0) in edges:
+        x = orc.edge_index(V, x0, y0)
+        h = orc.hash_c(S, c, x)
+        dd = orc.depth_of_hash(h, D)
+        a[c, dd] ^= np.uint64(x)
+        g[c, dd] ^= np.uint64(h)
+        at.setdefault(dd, []).append((min(x0, y0), max(x0, y0)))
+    return a, g, at
+
+
+def test_column_sampler_returns_a_lone_cut_edge(orc):
+    # |delta(U)| = 1: every column holds that edge alone, so the query of
+    # any single column returns it.
+    rng = np.random.default_rng(31)
+    for trial in range(30):
+        V = int(rng.integers(8, 300))
+        C, D = 5, 2 * math.ceil(math.log2(V))
+        S = int(rng.integers(0, 1 << 62))
+        k = int(rng.integers(2, V - 2))
+        A, B = list(range(k)), list(range(k, V))
+        edges = set()
+        for blk in (A, B):
+            for i in range(1, len(blk)):
+                edges.add((blk[int(rng.integers(0, i))], blk[i]))
+        a0, b0 = int(rng.choice(A)), int(rng.choice(B))
+        bridge = (min(a0, b0), max(a0, b0))
+        edges.add(bridge)
+        sk = orc.Sketch(V, C, D, S)
+        sk.apply(np.array([e[0] for e in edges], np.uint32),
+                 np.array([e[1] for e in edges], np.uint32))
+        for U in (A, B):
+            a, g = sk.set_sketch(U)
+            for c in range(C):
+                assert orc.sample_col(V, C, D, S, c, a, g) == (orc.OK,) + bridge, (trial, c)
+
+
+def test_column_sampler_two_indices_at_one_depth_fail(orc):
+    # Two edges that land at the same depth of column c, and nothing else in
+    # the column: the bucket holds the XOR of two indices and does not
+    # verify, the column is not all zero, so the status is FAILED.
+    rng = np.random.default_rng(32)
+    V, C, D = 1000, 4, 12
+    n = 0
+    while n < 300:
+        S = int(rng.integers(0, 1 << 62))
+        c = int(rng.integers(0, C))
+        w = int(rng.integers(0, V))
+        first = {}
+        pair = None
+        for b in rng.permutation(V).tolist():
+            if b == w:
+                continue
+            x = orc.edge_index(V, w, b)
+            dd = orc.depth_of_hash(orc.hash_c(S, c, x), D)
+            if dd in first:
+                pair = [(w, first[dd]), (w, b)]
+                break
+            first[dd] = b
+        a, g, at = _column_from_edges(orc, V, C, D, S, c, pair)
+        assert len(at) == 1
+        assert orc.sample_col(V, C, D, S, c, a, g)[0] == orc.FAILED
+        n += 1
+
+
+def test_column_sampler_empty_only_when_the_column_is_zero(orc):
+    # EMPTY is decided by the queried column alone; any nonzero word in it
+    # (even a checksum with a zero index word) makes an unverified column
+    # FAILED.
+    V, C, D, S = 500, 3, 10, 77
+    a = np.zeros((C, D), np.uint64)
+    g = np.zeros((C, D), np.uint64)
+    for c in range(C):
+        assert orc.sample_col(V, C, D, S, c, a, g)[0] == orc.EMPTY
+    a[2, 3] = np.uint64(orc.edge_index(V, 4, 9))
+    g[2, 3] = np.uint64(12345)
+    for c in (0, 1):
+        assert orc.sample_col(V, C, D, S, c, a, g)[0] == orc.EMPTY
+    assert orc.sample_col(V, C, D, S, 2, a, g)[0] == orc.FAILED
+    a[2, 3] = 0
+    assert orc.sample_col(V, C, D, S, 2, a, g)[0] == orc.FAILED
+
+
+def test_column_sampler_returns_the_deepest_lone_edge(orc):
+    # For random edge sets, the expected answer is found by counting edges
+    # per depth of column c: among depths that hold exactly one edge, the
+    # deepest one's edge.  (A depth holding several edges does not verify
+    # except with probability about 2^-64.)
+    rng = np.random.default_rng(33)
+    V, C, D = 400, 6, 18
+    seen_multi = 0
+    for trial in range(400):
+        S = int(rng.integers(0, 1 << 62))
+        c = int(rng.integers(0, C))
+        m = int(rng.integers(1, 9))
+        edges = set()
+        while len(edges) < m:
+            x0, y0 = (int(t) for t in rng.integers(0, V, 2))
+            if x0 != y0:
+                edges.add((min(x0, y0), max(x0, y0)))
+        a, g, at = _column_from_edges(orc, V, C, D, S, c, sorted(edges))
+        lone = [dd for dd, es in at.items() if len(es) == 1]
+        got = orc.sample_col(V, C, D, S, c, a, g)
+        if lone:
+            want = at[max(lone)][0]
+            assert got == (orc.OK,) + want, (trial, got, want, at)
+            seen_multi += len(lone) > 1
+        else:
+            assert got[0] == orc.FAILED, (trial, got, at)
+    assert seen_multi > 50
+
+
 def test_vertex_from_stream_matches_full_replay(orc):
     V, C, D, S = 90, 7, 14, 606
     u, v, d = _small_stream(V, 0.3, 0.2, 23)
