@@ -40,8 +40,8 @@ def build(force: bool = True) -> str:
     """Compile gen.c (the long-stream generators) with gcc, in place."""
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp,
-                               os.path.join(_HERE, "gen.c"), "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-shared", "-fPIC", "-o",
+                               tmp, os.path.join(_HERE, "gen.c"), "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -60,8 +60,17 @@ def _c():
         L.sg_rmat_free.argtypes = [p]
         L.sg_rmat_next.restype = sz
         L.sg_rmat_next.argtypes = [p, sz, dbl, dbl, dbl, dbl, p, p, p]
-        L.sg_clustered.restype = sz
-        L.sg_clustered.argtypes = [u32, u32, dbl, u32, u32, u32, u32, u32, u64, sz, p, p, p]
+        L.sg_clu_new.restype = p
+        L.sg_clu_new.argtypes = [u32, u32, dbl, u32, u32, u32, u32, u64]
+        L.sg_clu_free.restype = None
+        L.sg_clu_free.argtypes = [p]
+        for f in (L.sg_clu_setup_len, L.sg_clu_round_cap, L.sg_clu_m2):
+            f.restype = sz
+            f.argtypes = [p]
+        L.sg_clu_setup.restype = sz
+        L.sg_clu_setup.argtypes = [p, p]
+        L.sg_clu_round.restype = sz
+        L.sg_clu_round.argtypes = [p, u32, p]
         L.sg_forest_mask.restype = sz
         L.sg_forest_mask.argtypes = [u32, sz, p, p, p]
         _lib = L
@@ -183,25 +192,81 @@ class ForestTargetedDeletes:
         return self.u[idx], self.v[idx], np.ones(idx.size, np.uint8)
 
 
+class ClusteredChurn:
+    """Clustered churn drawn one phase at a time (C generator): the setup
+    phase (sparse part, bridges, every cluster's first-arrival forest), then
+    churn rounds in order, each inserting every other cluster edge in a fresh
+    random order and deleting them all in another one; every adv_every
+    updates from the forest on, adv_k random bridges are toggled.  Phases
+    come packed (uint64: u | v<<32 | is_delete<<63, u < v); ``unpack`` gives
+    (u, v, is_delete).  Vertices: clusters first, then the sparse part."""
+
+    def __init__(self, K, S, p_in, n_sparse, extra_bridges, adv_every, adv_k, seed):
+        self._L = _c()
+        self._h = self._L.sg_clu_new(K, S, p_in, n_sparse, extra_bridges, adv_every, adv_k, seed)
+        if not self._h:
+            raise MemoryError("clustered churn generator allocation failed")
+        self.next_round = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sg_clu_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def churn_edges(self) -> int:
+        """Cluster edges outside the fixed forest (inserted and deleted once
+        per round)."""
+        return self._L.sg_clu_m2(self._h)
+
+    def setup(self) -> np.ndarray:
+        out = np.empty(self._L.sg_clu_setup_len(self._h), np.uint64)
+        n = self._L.sg_clu_setup(self._h, _p(out))
+        if n == 0:
+            raise RuntimeError("setup phase already drawn")
+        return out[:n]
+
+    def round(self) -> np.ndarray:
+        out = np.empty(self._L.sg_clu_round_cap(self._h), np.uint64)
+        n = self._L.sg_clu_round(self._h, self.next_round, _p(out))
+        if n == 0:
+            raise RuntimeError("churn round out of order or out of memory")
+        self.next_round += 1
+        return out[:n]
+
+
+def unpack(packed):
+    """(u, v, is_delete) arrays of packed updates (u | v<<32 | del<<63)."""
+    p = np.asarray(packed, np.uint64)
+    return ((p & np.uint64(0xFFFFFFFF)).astype(np.uint32),
+            ((p >> np.uint64(32)) & np.uint64(0x7FFFFFFF)).astype(np.uint32),
+            (p >> np.uint64(63)).astype(np.uint8))
+
+
 def clustered_churn(K: int, S: int, p_in: float, n_sparse: int, extra_bridges: int,
                     rounds: int, adv_every: int, adv_k: int, seed: int):
-    """Dense clusters joined by bridges plus a sparse remainder; each
-    cluster's first-arrival forest is inserted once, then `rounds` passes
-    insert and delete every other cluster edge; every adv_every updates
-    adv_k random bridges are toggled (vertices: clusters first, then the
-    sparse part)."""
-    per = S * (S - 1) / 2 * p_in
-    mean = K * per
-    churn = mean * (1 + 2 * rounds) + 8 * math.sqrt(mean + 1) * (1 + 2 * rounds)
-    base = 2 * n_sparse + K + extra_bridges + churn + 4096
-    adv = (base / adv_every + 1) * adv_k if adv_every else 0
-    cap = int((base + adv) * 1.05)
-    u, v, d = _arrays(cap)
-    got = _c().sg_clustered(K, S, p_in, n_sparse, extra_bridges, rounds, adv_every, adv_k, seed,
-                            cap, _p(u), _p(v), _p(d))
-    if got == 0:
-        raise MemoryError("generator failed or capacity too small")
-    return u[:got].copy(), v[:got].copy(), d[:got].copy()
+    """The whole clustered-churn stream (setup phase, then `rounds` churn
+    rounds) as (u, v, is_delete) arrays; see ``ClusteredChurn``."""
+    g = ClusteredChurn(K, S, p_in, n_sparse, extra_bridges, adv_every, adv_k, seed)
+    parts = [g.setup()] + [g.round() for _ in range(rounds)]
+    g.close()
+    return unpack(np.concatenate(parts))
+
+
+def clustered_phases(cfg: dict):
+    """Generator over the packed phases (setup, round 0, round 1, ...) of a
+    clustered-churn workload description."""
+    g = ClusteredChurn(cfg["K"], cfg["Sc"], cfg["p_in"], cfg["n_sparse"], cfg["extra_bridges"],
+                       cfg["adv_every"], cfg["adv_k"], cfg["seed"])
+    try:
+        yield g.setup()
+        for _ in range(cfg["rounds"]):
+            yield g.round()
+    finally:
+        g.close()
 
 __all__ = [
     "build",
@@ -209,6 +274,9 @@ __all__ = [
     "rmat_chunks",
     "ForestTargetedDeletes",
     "clustered_churn",
+    "ClusteredChurn",
+    "clustered_phases",
+    "unpack",
     "stream_of",
     "SCALED",
     "er_standard",

@@ -163,45 +163,6 @@ size_t sg_rmat_next(void *h, size_t n, double del_prob, double a, double b, doub
     return n;
 }
 
-/* G(V, p) pairs u < v by geometric skipping over each row; returns the
- * number of edges written (at most cap). */
-static size_t er_edges(rng_t *r, uint32_t V, double p, uint32_t *eu, uint32_t *ev, size_t cap)
-{
-    size_t m = 0;
-    const double lq = p < 1.0 ? __builtin_log(1.0 - p) : 0.0;
-    for (uint32_t x = 0; x + 1 < V; x++) {
-        int64_t y = x;
-        for (;;) {
-            if (p >= 1.0) {
-                y += 1;
-            } else {
-                double uu = rng_unif(r);
-                if (uu <= 0.0) uu = 0x1.0p-53;
-                y += 1 + (int64_t)(__builtin_log(uu) / lq);
-            }
-            if (y >= (int64_t)V) break;
-            if (m >= cap) return m;
-            eu[m] = x;
-            ev[m] = (uint32_t)y;
-            m++;
-        }
-    }
-    return m;
-}
-
-static void shuffle2(rng_t *r, uint32_t *a, uint32_t *b, size_t m)
-{
-    for (size_t i = m; i > 1; i--) {
-        const size_t j = (size_t)rng_below(r, i);
-        uint32_t t = a[i - 1];
-        a[i - 1] = a[j];
-        a[j] = t;
-        t = b[i - 1];
-        b[i - 1] = b[j];
-        b[j] = t;
-    }
-}
-
 static uint32_t uf_find(uint32_t *p, uint32_t x)
 {
     while (p[x] != x) {
@@ -211,72 +172,171 @@ static uint32_t uf_find(uint32_t *p, uint32_t x)
     return x;
 }
 
-/*
- * Clustered churn.  Vertices [0, K*S) form K clusters of S vertices, each a
- * G(S, p_in); the other n_sparse vertices carry a sparse G(n, m = 2n).
- * Stream:
- *   1. the sparse edges, random order;
- *   2. bridges: a random tree over the clusters (cluster i to a random
- *      earlier cluster) plus extra_bridges random ones, each between random
- *      vertices of two different clusters;
- *   3. each cluster's first-arrival spanning forest (fixed forest);
- *   4. `rounds` times: insert every other cluster edge in random order, then
- *      delete them all in random order.
- * During phases 3-4, after every adv_every updates, adv_k bridges drawn
- * uniformly are toggled (deleted if present, re-inserted if absent).
- * Returns the number of updates written (at most cap), 0 on failure.
- */
-size_t sg_clustered(uint32_t K, uint32_t S, double p_in, uint32_t n_sparse,
-                    uint32_t extra_bridges, uint32_t rounds, uint32_t adv_every, uint32_t adv_k,
-                    uint64_t seed, size_t cap, uint32_t *u, uint32_t *v, uint8_t *d)
+/* MurmurHash3's 64-bit finalizer (Appleby): the counter-based hash behind
+ * the parallel shuffle below (bucket choice and per-bucket seeds). */
+static uint64_t fmix64(uint64_t k)
 {
-    rng_t r;
-    rng_seed(&r, seed);
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdULL;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ULL;
+    k ^= k >> 33;
+    return k;
+}
+
+/*
+ * Uniformly random permutation of in[0..m) into out, the same for any
+ * number of threads: one level of the Rao-Sandelius method.  Element i goes
+ * to bucket fmix64(key + (i+1)*golden) >> 54 (1024 buckets), buckets are laid
+ * out in order (elements in input order inside each), and every bucket is
+ * then Fisher-Yates shuffled with its own xoshiro256** stream seeded from
+ * (key, bucket).  Input chunks are fixed, so threads only share the work.
+ */
+enum { PS_BUCKETS = 1024, PS_CHUNKS = 256 };
+
+static uint32_t ps_bucket(uint64_t key, size_t i)
+{
+    return (uint32_t)(fmix64(key + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL) >> 54);
+}
+
+static int par_shuffle(const uint64_t *in, uint64_t *out, size_t m, uint64_t key)
+{
+    size_t *cnt = (size_t *)calloc((size_t)PS_CHUNKS * PS_BUCKETS, sizeof(size_t));
+    size_t *bstart = (size_t *)malloc(sizeof(size_t) * (PS_BUCKETS + 1));
+    if (!cnt || !bstart) {
+        free(cnt);
+        free(bstart);
+        return 0;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int c = 0; c < PS_CHUNKS; c++) {
+        const size_t lo = m * (size_t)c / PS_CHUNKS, hi = m * (size_t)(c + 1) / PS_CHUNKS;
+        size_t *cc = cnt + (size_t)c * PS_BUCKETS;
+        for (size_t i = lo; i < hi; i++) cc[ps_bucket(key, i)]++;
+    }
+    /* start of (bucket b, chunk c) = elements of earlier buckets, then of
+     * earlier chunks inside bucket b */
+    size_t acc = 0;
+    for (int b = 0; b < PS_BUCKETS; b++) {
+        bstart[b] = acc;
+        for (int c = 0; c < PS_CHUNKS; c++) {
+            const size_t x = cnt[(size_t)c * PS_BUCKETS + b];
+            cnt[(size_t)c * PS_BUCKETS + b] = acc;
+            acc += x;
+        }
+    }
+    bstart[PS_BUCKETS] = acc;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int c = 0; c < PS_CHUNKS; c++) {
+        const size_t lo = m * (size_t)c / PS_CHUNKS, hi = m * (size_t)(c + 1) / PS_CHUNKS;
+        size_t *cc = cnt + (size_t)c * PS_BUCKETS;
+        for (size_t i = lo; i < hi; i++) out[cc[ps_bucket(key, i)]++] = in[i];
+    }
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int b = 0; b < PS_BUCKETS; b++) {
+        rng_t r;
+        rng_seed(&r, fmix64(key ^ ((uint64_t)(b + 1) << 40)));
+        uint64_t *a = out + bstart[b];
+        for (size_t i = bstart[b + 1] - bstart[b]; i > 1; i--) {
+            const size_t j = (size_t)rng_below(&r, i);
+            const uint64_t t = a[i - 1];
+            a[i - 1] = a[j];
+            a[j] = t;
+        }
+    }
+    free(cnt);
+    free(bstart);
+    return 1;
+}
+
+/*
+ * Clustered churn, drawn one phase at a time.  Vertices [0, K*S) form K
+ * clusters of S vertices, each a G(S, p_in); the other n_sparse vertices
+ * carry a sparse G(n, m = 2n).
+ *   setup:  the sparse edges (random order); bridges: a random tree over the
+ *           clusters (cluster i to a random earlier cluster) plus
+ *           extra_bridges random ones between random vertices of two
+ *           different clusters; then every cluster's first-arrival spanning
+ *           forest under one random order of all cluster edges (the fixed
+ *           forest, never deleted).
+ *   round:  every other cluster edge inserted in a fresh random order, then
+ *           all of them deleted in another one.
+ * From the forest on, after every adv_every updates, adv_k bridges drawn
+ * uniformly are toggled (deleted if present, re-inserted if absent); rounds
+ * must therefore be drawn in order.  Updates are written packed: u | v<<32
+ * | is_delete<<63 with u < v.
+ */
+typedef struct {
+    rng_t r;           /* sequential stream: sparse part, bridges, bridge picks */
+    uint64_t seed;
+    uint32_t K, S, n_sparse, nb, adv_every, adv_k;
+    uint32_t *bu, *bv;
+    uint8_t *blive;
+    uint64_t *sp;      /* sparse edges */
+    size_t nsp;
+    uint64_t *fe;      /* forest edges, arrival order */
+    size_t nf;
+    uint64_t *ce;      /* the other cluster edges */
+    size_t m2;
+    uint64_t *tmp;     /* shuffle output */
+    uint64_t since;
+    uint32_t next_round;
+    int setup_done;
+} clu_t;
+
+static uint64_t pk(uint32_t a, uint32_t b, int del)
+{
+    const uint32_t x = a < b ? a : b, y = a < b ? b : a;
+    return (uint64_t)x | ((uint64_t)y << 32) | ((uint64_t)(del != 0) << 63);
+}
+
+void sg_clu_free(void *h)
+{
+    clu_t *g = (clu_t *)h;
+    if (!g) return;
+    free(g->bu);
+    free(g->bv);
+    free(g->blive);
+    free(g->sp);
+    free(g->fe);
+    free(g->ce);
+    free(g->tmp);
+    free(g);
+}
+
+void *sg_clu_new(uint32_t K, uint32_t S, double p_in, uint32_t n_sparse, uint32_t extra_bridges,
+                 uint32_t adv_every, uint32_t adv_k, uint64_t seed)
+{
+    clu_t *g = (clu_t *)calloc(1, sizeof(clu_t));
+    if (!g) return NULL;
+    rng_seed(&g->r, seed);
+    g->seed = seed;
+    g->K = K;
+    g->S = S;
+    g->n_sparse = n_sparse;
+    g->adv_every = adv_every;
+    g->adv_k = adv_k;
+    g->nb = K > 1 ? (K - 1) + extra_bridges : 0;
     const uint32_t Vc = K * S;
-    const uint32_t nb = K > 1 ? (K - 1) + extra_bridges : 0;
     const size_t per = (size_t)S * (S > 0 ? S - 1 : 0) / 2;
-    const size_t mcap = (size_t)K * per + 1;
     const size_t msp = n_sparse >= 2 ? 2 * (size_t)n_sparse : 0;
+    g->bu = (uint32_t *)malloc(sizeof(uint32_t) * (g->nb + 1));
+    g->bv = (uint32_t *)malloc(sizeof(uint32_t) * (g->nb + 1));
+    g->blive = (uint8_t *)calloc(g->nb + 1, 1);
+    g->sp = (uint64_t *)malloc(sizeof(uint64_t) * (msp + 1));
     size_t hcap = 1;
     while (hcap < 4 * msp + 1) hcap <<= 1;
-    size_t w = 0, since = 0, m = 0;
-    int ok = 0;
-    uint32_t *bu = (uint32_t *)malloc(sizeof(uint32_t) * (nb + 1));
-    uint32_t *bv = (uint32_t *)malloc(sizeof(uint32_t) * (nb + 1));
-    uint8_t *blive = (uint8_t *)calloc(nb + 1, 1);
-    uint32_t *ce_u = (uint32_t *)malloc(sizeof(uint32_t) * mcap);
-    uint32_t *ce_v = (uint32_t *)malloc(sizeof(uint32_t) * mcap);
-    uint8_t *inf = (uint8_t *)calloc(mcap, 1);
-    uint32_t *par = (uint32_t *)malloc(sizeof(uint32_t) * (Vc + 1));
     uint64_t *hs = (uint64_t *)malloc(sizeof(uint64_t) * hcap);
-    if (!bu || !bv || !blive || !ce_u || !ce_v || !inf || !par || !hs) goto done;
-#define EMIT(a_, b_, del_)                   \
-    do {                                     \
-        if (w >= cap) goto done;             \
-        const uint32_t x_ = (a_), y_ = (b_); \
-        u[w] = x_ < y_ ? x_ : y_;            \
-        v[w] = x_ < y_ ? y_ : x_;            \
-        d[w] = (del_);                       \
-        w++;                                 \
-    } while (0)
-#define ADV_TICK()                                                \
-    do {                                                          \
-        if (adv_every && nb && ++since >= adv_every) {            \
-            since = 0;                                            \
-            for (uint32_t t_ = 0; t_ < adv_k; t_++) {             \
-                const uint32_t bi_ = (uint32_t)rng_below(&r, nb); \
-                EMIT(bu[bi_], bv[bi_], blive[bi_] ? 1 : 0);       \
-                blive[bi_] ^= 1;                                  \
-            }                                                     \
-        }                                                         \
-    } while (0)
-    /* 1. sparse part: m = 2n distinct random pairs (open-addressing set) */
+    size_t *cm = (size_t *)calloc((size_t)K + 1, sizeof(size_t));
+    uint64_t *all = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)K * per + 1));
+    uint32_t *par = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)Vc + 1));
+    if (!g->bu || !g->bv || !g->blive || !g->sp || !hs || !cm || !all || !par) goto fail;
+    /* sparse part: m = 2n distinct random pairs (open-addressing set) */
     for (size_t i = 0; i < hcap; i++) hs[i] = UINT64_MAX;
     {
         const uint64_t nn = n_sparse;
-        size_t got = 0;
-        while (got < msp && (uint64_t)got < nn * (nn - 1) / 2) {
-            uint64_t x = rng_below(&r, nn), y = rng_below(&r, nn);
+        while (g->nsp < msp && (uint64_t)g->nsp < nn * (nn - 1) / 2) {
+            uint64_t x = rng_below(&g->r, nn), y = rng_below(&g->r, nn);
             if (x == y) continue;
             if (x > y) {
                 const uint64_t t = x;
@@ -295,91 +355,157 @@ size_t sg_clustered(uint32_t K, uint32_t S, double p_in, uint32_t n_sparse,
             }
             if (dup) continue;
             hs[h] = key;
-            got++;
-            EMIT(Vc + (uint32_t)x, Vc + (uint32_t)y, 0);
+            g->sp[g->nsp++] = pk(Vc + (uint32_t)x, Vc + (uint32_t)y, 0);
         }
     }
-    /* 2. bridges */
+    /* bridges */
     {
         uint32_t q = 0;
         for (uint32_t i = 1; i < K; i++) {
-            const uint32_t j = (uint32_t)rng_below(&r, i);
-            bu[q] = i * S + (uint32_t)rng_below(&r, S);
-            bv[q] = j * S + (uint32_t)rng_below(&r, S);
+            const uint32_t j = (uint32_t)rng_below(&g->r, i);
+            g->bu[q] = i * S + (uint32_t)rng_below(&g->r, S);
+            g->bv[q] = j * S + (uint32_t)rng_below(&g->r, S);
             q++;
         }
-        while (q < nb) {
-            const uint32_t i = (uint32_t)rng_below(&r, K), j = (uint32_t)rng_below(&r, K);
+        while (q < g->nb) {
+            const uint32_t i = (uint32_t)rng_below(&g->r, K), j = (uint32_t)rng_below(&g->r, K);
             if (i == j) continue;
-            const uint32_t x = i * S + (uint32_t)rng_below(&r, S);
-            const uint32_t y = j * S + (uint32_t)rng_below(&r, S);
+            const uint32_t x = i * S + (uint32_t)rng_below(&g->r, S);
+            const uint32_t y = j * S + (uint32_t)rng_below(&g->r, S);
             int dup = 0;
             for (uint32_t t = 0; t < q; t++)
-                if ((bu[t] == x && bv[t] == y) || (bu[t] == y && bv[t] == x)) dup = 1;
+                if ((g->bu[t] == x && g->bv[t] == y) || (g->bu[t] == y && g->bv[t] == x)) dup = 1;
             if (dup) continue;
-            bu[q] = x;
-            bv[q] = y;
+            g->bu[q] = x;
+            g->bv[q] = y;
             q++;
         }
-        for (uint32_t t = 0; t < nb; t++) {
-            EMIT(bu[t], bv[t], 0);
-            blive[t] = 1;
-        }
     }
-    /* 3. clusters: edges, shuffled; first-arrival forest inserted once */
+    /* cluster graphs, one xoshiro stream per cluster, drawn in parallel
+     * into fixed slots and packed in cluster order */
+#pragma omp parallel for schedule(dynamic, 1)
     for (uint32_t c = 0; c < K; c++) {
-        const size_t m0 = m;
-        m += er_edges(&r, S, p_in, ce_u + m, ce_v + m, mcap - m);
-        for (size_t i = m0; i < m; i++) {
-            ce_u[i] += c * S;
-            ce_v[i] += c * S;
+        rng_t rc;
+        rng_seed(&rc, fmix64(seed ^ (0xC1u + ((uint64_t)c << 32))));
+        uint64_t *slot = all + (size_t)c * per;
+        const double lq = p_in < 1.0 ? __builtin_log(1.0 - p_in) : 0.0;
+        size_t k = 0;
+        for (uint32_t x = 0; x + 1 < S; x++) {
+            int64_t y = x;
+            for (;;) {
+                if (p_in >= 1.0) {
+                    y += 1;
+                } else {
+                    double uu = rng_unif(&rc);
+                    if (uu <= 0.0) uu = 0x1.0p-53;
+                    y += 1 + (int64_t)(__builtin_log(uu) / lq);
+                }
+                if (y >= (int64_t)S) break;
+                slot[k++] = pk(c * S + x, c * S + (uint32_t)y, 0);
+            }
         }
+        cm[c] = k;
     }
-    shuffle2(&r, ce_u, ce_v, m);
+    size_t m = 0;
+    for (uint32_t c = 0; c < K; c++) {
+        memmove(all + m, all + (size_t)c * per, cm[c] * sizeof(uint64_t));
+        m += cm[c];
+    }
+    g->tmp = (uint64_t *)malloc(sizeof(uint64_t) * (m + 1));
+    g->fe = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)Vc + 1));
+    g->ce = (uint64_t *)malloc(sizeof(uint64_t) * (m + 1));
+    if (!g->tmp || !g->fe || !g->ce) goto fail;
+    /* first-arrival forest of one random order of all cluster edges */
+    if (!par_shuffle(all, g->tmp, m, fmix64(seed ^ 0xF0F0F0F0ULL))) goto fail;
     for (uint32_t x = 0; x < Vc; x++) par[x] = x;
     for (size_t i = 0; i < m; i++) {
-        const uint32_t ra = uf_find(par, ce_u[i]), rb = uf_find(par, ce_v[i]);
-        if (ra == rb) continue;
-        par[ra] = rb;
-        inf[i] = 1;
-        EMIT(ce_u[i], ce_v[i], 0);
-        ADV_TICK();
-    }
-    /* 4. churn of the other cluster edges, fresh random order each pass */
-    for (uint32_t rd = 0; rd < rounds; rd++) {
-        for (int pass = 0; pass < 2; pass++) {
-            for (size_t i = m; i > 1; i--) {
-                const size_t j = (size_t)rng_below(&r, i);
-                uint32_t t = ce_u[i - 1];
-                ce_u[i - 1] = ce_u[j];
-                ce_u[j] = t;
-                t = ce_v[i - 1];
-                ce_v[i - 1] = ce_v[j];
-                ce_v[j] = t;
-                const uint8_t tf = inf[i - 1];
-                inf[i - 1] = inf[j];
-                inf[j] = tf;
-            }
-            for (size_t i = 0; i < m; i++) {
-                if (inf[i]) continue;
-                EMIT(ce_u[i], ce_v[i], pass);
-                ADV_TICK();
-            }
+        const uint64_t e = g->tmp[i];
+        const uint32_t ra = uf_find(par, (uint32_t)e), rb = uf_find(par, (uint32_t)(e >> 32));
+        if (ra != rb) {
+            par[ra] = rb;
+            g->fe[g->nf++] = e;
+        } else {
+            g->ce[g->m2++] = e;
         }
     }
-    ok = 1;
-#undef ADV_TICK
-#undef EMIT
-done:
-    free(bu);
-    free(bv);
-    free(blive);
-    free(ce_u);
-    free(ce_v);
-    free(inf);
-    free(par);
     free(hs);
-    return ok ? w : 0;
+    free(cm);
+    free(all);
+    free(par);
+    return g;
+fail:
+    free(hs);
+    free(cm);
+    free(all);
+    free(par);
+    sg_clu_free(g);
+    return NULL;
+}
+
+/* Updates in the setup phase and in one churn round (upper bound: the
+ * number of bridge toggles depends on where the ticks fall). */
+size_t sg_clu_setup_len(void *h)
+{
+    clu_t *g = (clu_t *)h;
+    const size_t base = g->nsp + g->nb + g->nf;
+    return base + (g->adv_every ? (g->nf / g->adv_every + 1) * g->adv_k : 0);
+}
+
+size_t sg_clu_round_cap(void *h)
+{
+    clu_t *g = (clu_t *)h;
+    return 2 * g->m2 + (g->adv_every ? (2 * g->m2 / g->adv_every + 2) * g->adv_k : 0);
+}
+
+size_t sg_clu_m2(void *h) { return ((clu_t *)h)->m2; }
+
+/* one update, then the bridge-toggle tick */
+static size_t clu_emit(clu_t *g, uint64_t *out, size_t w, uint64_t p)
+{
+    out[w++] = p;
+    if (g->adv_every && g->nb && ++g->since >= g->adv_every) {
+        g->since = 0;
+        for (uint32_t t = 0; t < g->adv_k; t++) {
+            const uint32_t bi = (uint32_t)rng_below(&g->r, g->nb);
+            out[w++] = pk(g->bu[bi], g->bv[bi], g->blive[bi]);
+            g->blive[bi] ^= 1;
+        }
+    }
+    return w;
+}
+
+/* The setup phase into out (sg_clu_setup_len(h) words); returns its length. */
+size_t sg_clu_setup(void *h, uint64_t *out)
+{
+    clu_t *g = (clu_t *)h;
+    if (g->setup_done) return 0;
+    size_t w = 0;
+    for (size_t i = 0; i < g->nsp; i++) out[w++] = g->sp[i];
+    for (uint32_t t = 0; t < g->nb; t++) {
+        out[w++] = pk(g->bu[t], g->bv[t], 0);
+        g->blive[t] = 1;
+    }
+    for (size_t i = 0; i < g->nf; i++) w = clu_emit(g, out, w, g->fe[i]);
+    g->setup_done = 1;
+    return w;
+}
+
+/* Churn round `rd` (rounds in order, after the setup) into out
+ * (sg_clu_round_cap(h) words); returns its length, 0 on misuse or when out
+ * of memory. */
+size_t sg_clu_round(void *h, uint32_t rd, uint64_t *out)
+{
+    clu_t *g = (clu_t *)h;
+    if (!g->setup_done || rd != g->next_round) return 0;
+    size_t w = 0;
+    for (int pass = 0; pass < 2; pass++) {
+        const uint64_t key = fmix64(g->seed ^ (((uint64_t)rd << 8) | (uint64_t)(pass + 1)) << 20);
+        if (!par_shuffle(g->ce, g->tmp, g->m2, key)) return 0;
+        const uint64_t del = pass ? 1ULL << 63 : 0;
+        for (size_t i = 0; i < g->m2; i++) w = clu_emit(g, out, w, g->tmp[i] | del);
+    }
+    g->next_round++;
+    return w;
 }
 
 /*
