@@ -195,6 +195,10 @@ typedef struct {
                                     without a sketch                            */
     uint64_t sets_complemented;  /* trees holding such a piece reduced from the
                                     other pieces (all pieces XOR to zero)       */
+    uint64_t timed_buckets;      /* buckets the timed staged scatter launches
+                                    changed in HBM (nonzero folded delta, or a
+                                    record's deep-row bucket): 32 B of
+                                    compulsory traffic each (read + write)      */
 } cupk_counters_t;
 
 /* Bytes of device memory the sketch of (V, C, D) occupies. */
@@ -235,27 +239,49 @@ void cupk_free(cupk_ctx *ctx);
 int cupk_apply_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
                        const uint8_t *is_delete, size_t n);
 
-/* apply_updates_device — same as cupk_apply_updates for a batch already in
- * device memory: n packed words  lo32 = one endpoint, bits 32..62 = the
- * other endpoint, bit 63 = 1 for a delete.  The buffer is owned by the
- * caller and only read; it must stay valid until the next call on ctx
- * returns (the call synchronises before returning).  Invalid entries make
- * the whole batch fail with CUPK_EINVAL with nothing applied. */
-int cupk_apply_updates_device(cupk_ctx *ctx, const uint64_t *d_packed, size_t n);
+/* apply_updates_device — cupk_apply_updates for a batch already in device
+ * memory, ordered on streams (graph-stream model, App. A.1; cutset Update,
+ * Sec. 2.2.1; updates buffered and flushed before queries, Sec. 4.3).
+ *   d_packed: n packed words in device memory: lo32 = one endpoint, bits
+ *     32..62 = the other, bit 63 = 1 for a delete.  Owned by the caller and
+ *     only read.
+ *   hip_stream: the hipStream_t on which the caller produced d_packed (NULL =
+ *     the null stream).  The library reads the batch after the work queued
+ *     on hip_stream before this call, and makes hip_stream wait for the
+ *     last kernel that reads the batch: work the caller queues on hip_stream
+ *     afterwards (freeing or reusing the buffer, reading the sketch) runs
+ *     after it.  Used with any other stream, the caller keeps the buffer
+ *     alive until cupk_sync returns.
+ * The call returns once the batch's device work is queued; it does not
+ * wait for the GPU.  The host part of the batch (links and cuts of the
+ * flagged updates, replacement rounds) stays pending until the next call on
+ * ctx that needs it: the next apply call, cupk_sync, cupk_connected and
+ * every other call that reads the forest, the sketch or the counters.
+ * Validation runs on the GPU: a batch with u == v or an endpoint >= V
+ * applies nothing, and CUPK_EINVAL is returned by the call that completes
+ * its host part (the next such call).  In exact and levels modes the call
+ * completes the batch before returning.  n == 0 is a no-op.
+ * Errors: CUPK_EINVAL (null pointer; an earlier invalid batch),
+ *   CUPK_ENOMEM, CUPK_EDEVICE. */
+int cupk_apply_updates_device(cupk_ctx *ctx, const uint64_t *d_packed, size_t n,
+                              void *hip_stream);
 
 /* component_sketch — aggregate sketch of a vertex set U: XOR of the
  * members' sketches (App. A.1.1 sketch addition; the cutset's component
  * aggregate, Sec. 2.2.1).  By cancellation it equals the sketch of the cut
  * of U.  verts: n distinct vertex ids (host); duplicates cancel in pairs.
- * out: C*D buckets (host), canonical order.  Reflects all applied updates.
- * Errors: CUPK_EINVAL for an id >= V. */
+ * out: C*D buckets, canonical order, in host or device memory (the kind is
+ * found with hipPointerGetAttributes; device memory is written on the
+ * library's stream and the call waits for it).  Reflects all applied
+ * updates.  Errors: CUPK_EINVAL for an id >= V. */
 int cupk_component_sketch(cupk_ctx *ctx, const uint32_t *verts, size_t n,
                           cupk_bucket *out);
 
 /* component_sketch_batch — k aggregate sketches in one launch.
  * offsets: k+1 host offsets into verts (CSR); set j is
- * verts[offsets[j] .. offsets[j+1]).  out: k*C*D buckets (host), set j at
- * out[j*C*D].  Sets may have any sizes, including 0. */
+ * verts[offsets[j] .. offsets[j+1]).  out: k*C*D buckets, set j at
+ * out[j*C*D], host or device memory as for cupk_component_sketch.  Sets
+ * may have any sizes, including 0. */
 int cupk_component_sketch_batch(cupk_ctx *ctx, const uint64_t *offsets, size_t k,
                                 const uint32_t *verts, cupk_bucket *out);
 

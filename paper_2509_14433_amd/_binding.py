@@ -74,7 +74,8 @@ class cupk_counters_t(ctypes.Structure):
         ("timed_launches", ctypes.c_uint64),
         ("timed_updates", ctypes.c_uint64),
         ("pieces_sketchless", ctypes.c_uint64),
-        ("sets_complemented", ctypes.c_uint64)]
+        ("sets_complemented", ctypes.c_uint64),
+        ("timed_buckets", ctypes.c_uint64)]
 
 
 class cupk_serve_opts(ctypes.Structure):
@@ -111,7 +112,7 @@ def _load():
                                             ctypes.POINTER(cupk_opts)]),
         "cupk_free": (None, [p]),
         "cupk_apply_updates": (ctypes.c_int, [p, p, p, p, sz]),
-        "cupk_apply_updates_device": (ctypes.c_int, [p, p, sz]),
+        "cupk_apply_updates_device": (ctypes.c_int, [p, p, sz, p]),
         "cupk_component_sketch": (ctypes.c_int, [p, p, sz, p]),
         "cupk_component_sketch_batch": (ctypes.c_int, [p, p, sz, p, p]),
         "cupk_sample_cut_edge": (ctypes.c_int, [p, p, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
@@ -254,8 +255,11 @@ class Context:
             raise ValueError("u, v, is_delete must have equal length")
         return self._check(lib.cupk_apply_updates(self._h, _ptr(u), _ptr(v), _ptr(d), n))
 
-    def apply_updates_device(self, packed, n=None):
-        """packed: a cuda int64/uint64 tensor (or a raw device address with n)."""
+    def apply_updates_device(self, packed, n=None, stream=None):
+        """packed: a cuda int64/uint64 tensor (or a raw device address with n).
+        stream: the hipStream_t (int) that produced it; default torch's
+        current stream.  Returns once the device work is queued; the host
+        part runs at the next call that needs it (see cupk.h)."""
         if isinstance(packed, int):
             ptr = packed
             assert n is not None
@@ -263,27 +267,44 @@ class Context:
             assert packed.is_cuda and packed.element_size() == 8 and packed.is_contiguous()
             ptr = packed.data_ptr()
             n = packed.numel() if n is None else n
-        return self._check(lib.cupk_apply_updates_device(self._h, ctypes.c_void_p(ptr), n))
+        if stream is None:
+            torch = _torch()
+            stream = torch.cuda.current_stream().cuda_stream if torch is not None else 0
+        return self._check(lib.cupk_apply_updates_device(self._h, ctypes.c_void_p(ptr), n,
+                                                         ctypes.c_void_p(stream or None)))
 
-    def component_sketch(self, verts):
+    def component_sketch(self, verts, out=None):
+        """(alpha, gamma) as C x D arrays; with out (a cuda tensor of
+        C*D*2 int64), the canonical buckets are written there instead."""
+        if out is not None:
+            return self.component_sketch_batch([verts], out=out)
         verts = np.ascontiguousarray(verts, dtype=np.uint32)
-        out = np.zeros(self.C * self.D * 2, dtype=np.uint64)
-        self._check(lib.cupk_component_sketch(self._h, _ptr(verts), verts.shape[0], _ptr(out)))
-        out = out.reshape(self.C, self.D, 2)
-        return out[..., 0].copy(), out[..., 1].copy()
+        buf = np.zeros(self.C * self.D * 2, dtype=np.uint64)
+        self._check(lib.cupk_component_sketch(self._h, _ptr(verts), verts.shape[0], _ptr(buf)))
+        buf = buf.reshape(self.C, self.D, 2)
+        return buf[..., 0].copy(), buf[..., 1].copy()
 
-    def component_sketch_batch(self, sets):
+    def component_sketch_batch(self, sets, out=None):
+        """(alpha, gamma) as k x C x D arrays; with out (a cuda tensor of
+        k*C*D*2 int64), the canonical buckets are written there instead
+        and out is returned."""
         sizes = [len(s) for s in sets]
         offs = np.zeros(len(sets) + 1, dtype=np.uint64)
         offs[1:] = np.cumsum(sizes)
         verts = (np.ascontiguousarray(np.concatenate([np.asarray(s, np.uint32) for s in sets]))
                  if sets and offs[-1] else np.zeros(1, np.uint32))
         k = len(sets)
-        out = np.zeros(max(1, k) * self.C * self.D * 2, dtype=np.uint64)
+        if out is not None:
+            assert out.is_cuda and out.element_size() == 8 and out.is_contiguous()
+            assert out.numel() >= k * self.C * self.D * 2
+            self._check(lib.cupk_component_sketch_batch(self._h, _ptr(offs), k, _ptr(verts),
+                                                         ctypes.c_void_p(out.data_ptr())))
+            return out
+        buf = np.zeros(max(1, k) * self.C * self.D * 2, dtype=np.uint64)
         self._check(lib.cupk_component_sketch_batch(self._h, _ptr(offs), k, _ptr(verts),
-                                                     _ptr(out)))
-        out = out[: k * self.C * self.D * 2].reshape(k, self.C, self.D, 2)
-        return out[..., 0].copy(), out[..., 1].copy()
+                                                     _ptr(buf)))
+        buf = buf[: k * self.C * self.D * 2].reshape(k, self.C, self.D, 2)
+        return buf[..., 0].copy(), buf[..., 1].copy()
 
     def sample_cut_edge(self, alpha, gamma):
         buf = np.empty((self.C, self.D, 2), dtype=np.uint64)

@@ -880,11 +880,14 @@ int enqueue_bin(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
     return CUPK_OK;
 }
 
-int enqueue_tile(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
+// count: the staged kernel adds the buckets it changes to ctx->d_touched
+// (timed passes).
+int enqueue_tile(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n, bool count)
 {
     if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
         HIPCHK(launch_tile(s, dev_sketch(ctx), ctx->d_hdr, staged_params(ctx, grid_n),
-                           ctx->d_toff.p, ctx->d_bins.p, ctx->d_items.p, ctx->d_nitems));
+                           ctx->d_toff.p, ctx->d_bins.p, ctx->d_items.p, ctx->d_nitems,
+                           count ? ctx->d_touched : nullptr));
     } else {
         HIPCHK(launch_scatter_atomic(s, desc_ptr(ctx), ctx->cur_desc, grid_n, dev_sketch(ctx),
                                      ctx->d_hdr));
@@ -908,7 +911,7 @@ int capture_graphs(cupk_ctx *ctx)
         int rc = CUPK_OK;
         if (part == 0 || part == 3) rc = enqueue_classify(ctx, ctx->gs, cap);
         if (rc == CUPK_OK && (part == 1 || part == 3)) rc = enqueue_bin(ctx, ctx->gs, cap);
-        if (rc == CUPK_OK && (part == 2 || part == 3)) rc = enqueue_tile(ctx, ctx->gs, cap);
+        if (rc == CUPK_OK && (part == 2 || part == 3)) rc = enqueue_tile(ctx, ctx->gs, cap, false);
         ctx->capturing = false;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->gs, &g);
@@ -1009,7 +1012,7 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
         rc = enqueue_bin(ctx, ctx->s, n);
         if (rc != CUPK_OK) return rc;
         if (ts) HIPCHK(hipEventRecord(ts->tb, ctx->s));
-        rc = enqueue_tile(ctx, ctx->s, n);
+        rc = enqueue_tile(ctx, ctx->s, n, ts != nullptr);
         if (rc != CUPK_OK) return rc;
     }
     ctx->hdr_seq++;
@@ -1161,34 +1164,63 @@ int walk_pass(cupk_ctx *ctx, uint32_t n, bool exact, uint32_t *cut_pos, uint32_t
     return CUPK_OK;
 }
 
-int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
+// Host part of a batch-semantics pass whose device work is enqueued: wait
+// for the classification header, walk the flagged updates into the forest,
+// then run the replacement rounds (or, in levels mode, the restoration).
+static int finish_pass(cupk_ctx *ctx, uint32_t n)
 {
-    int rc = ensure_batch_buffers(ctx, n);
+    uint32_t nflag = 0;
+    double tw = 0, tc = 0;
+    const double t0 = now_ms();
+    int rc = walk_pass(ctx, n, false, nullptr, nullptr, nullptr, &nflag, &tw, &tc);
+    if (rc != CUPK_OK) return rc;
+    const double t2 = now_ms();
+    rc = ctx->levels ? levels_restore(ctx) : run_rounds(ctx);
+    const double t3 = now_ms();
+    ctx->ctr.host_rounds_ms += t3 - t2;
+    if (ctx->trace)
+        fprintf(stderr,
+                "cupk batch %llu n=%u nflag=%u wait=%.3f copy=%.3f flags=%.3f rounds=%.3f ms\n",
+                (unsigned long long)ctx->ctr.batches, n, nflag, tw, tc, t2 - t0 - tw - tc,
+                t3 - t2);
+    return rc;
+}
+
+// The host part of the last enqueued batch, if it has not run yet.  Every
+// entry point that reads the forest, the sketch or the counters, or enqueues
+// more work, calls this first.
+int flush_pending(cupk_ctx *ctx)
+{
+    if (!ctx->pending) return CUPK_OK;
+    ctx->pending = false;
+    return finish_pass(ctx, ctx->pending_n);
+}
+
+// One batch of at most kMaxBatchPerLaunch updates.  defer: leave the host
+// part pending (batch semantics only; exact mode always completes).
+int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool defer)
+{
+    int rc = flush_pending(ctx);
+    if (rc != CUPK_OK) return rc;
+    rc = ensure_batch_buffers(ctx, n);
     if (rc != CUPK_OK) return rc;
     ctx->ctr.updates += n;
     ctx->ctr.batches++;
-    uint32_t nflag = 0;
-    double tw = 0, tc = 0;
     if (!ctx->opts.exact) {
         rc = enqueue_pass(ctx, d_upd, n, false);
         if (rc != CUPK_OK) return rc;
-        const double t0 = now_ms();
-        rc = walk_pass(ctx, n, false, nullptr, nullptr, nullptr, &nflag, &tw, &tc);
-        if (rc != CUPK_OK) return rc;
-        const double t2 = now_ms();
-        rc = ctx->levels ? levels_restore(ctx) : run_rounds(ctx);
-        const double t3 = now_ms();
-        ctx->ctr.host_rounds_ms += t3 - t2;
-        if (ctx->trace)
-            fprintf(stderr,
-                    "cupk batch %llu n=%u nflag=%u wait=%.3f copy=%.3f flags=%.3f rounds=%.3f ms\n",
-                    (unsigned long long)ctx->ctr.batches, n, nflag, tw, tc, t2 - t0 - tw - tc,
-                    t3 - t2);
-        return rc;
+        if (defer && !ctx->levels) {
+            ctx->pending = true;
+            ctx->pending_n = n;
+            return CUPK_OK;
+        }
+        return finish_pass(ctx, n);
     }
     // exact mode: speculate over the rest of the batch, stop at the first
     // cut, undo the speculation past it, cut and search replacements on the
     // sketch as of that update, then go on after it
+    uint32_t nflag = 0;
+    double tw = 0, tc = 0;
     uint32_t s = 0;
     while (s < n) {
         rc = enqueue_pass(ctx, d_upd + s, n - s, false);
@@ -1220,11 +1252,11 @@ int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
     return rc;
 }
 
-int apply_device(cupk_ctx *ctx, const uint64_t *d_upd, size_t n)
+int apply_device(cupk_ctx *ctx, const uint64_t *d_upd, size_t n, bool defer)
 {
     for (size_t off = 0; off < n; off += kMaxBatchPerLaunch) {
         const uint32_t m = (uint32_t)std::min(kMaxBatchPerLaunch, n - off);
-        int rc = apply_device_one(ctx, d_upd + off, m);
+        int rc = apply_device_one(ctx, d_upd + off, m, defer);
         if (rc != CUPK_OK) return rc;
     }
     return CUPK_OK;
@@ -1239,7 +1271,7 @@ int apply_packed_host(cupk_ctx *ctx, const uint64_t *packed, size_t n)
     std::copy(packed, packed + n, ctx->h_upd.p);
     HIPCHK(hipMemcpyAsync(ctx->d_upd.p, ctx->h_upd.p, n * 8, hipMemcpyHostToDevice, ctx->s));
     ctx->query_often = true;
-    const int rc = apply_device(ctx, ctx->d_upd.p, n);
+    const int rc = apply_device(ctx, ctx->d_upd.p, n, false);
     ctx->query_often = false;
     return rc;
 }
@@ -1264,6 +1296,7 @@ void destroy(cupk_ctx *ctx)
     if (ctx->d_hdr) (void)hipFree(ctx->d_hdr);
     if (ctx->h_hdr) (void)hipHostFree(ctx->h_hdr);
     if (ctx->d_nitems) (void)hipFree(ctx->d_nitems);
+    if (ctx->d_touched) (void)hipFree(ctx->d_touched);
     drop_graphs(ctx);
     if (ctx->gs) (void)hipStreamDestroy(ctx->gs);
     if (ctx->d_desc) (void)hipFree(ctx->d_desc);
@@ -1301,6 +1334,8 @@ void destroy(cupk_ctx *ctx)
         if (t.tb) (void)hipEventDestroy(t.tb);
         if (t.t1) (void)hipEventDestroy(t.t1);
     }
+    if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->cs) (void)hipStreamDestroy(ctx->cs);
     if (ctx->own_stream && ctx->s) (void)hipStreamDestroy(ctx->s);
     delete ctx;
@@ -1365,6 +1400,8 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
         ctx->own_stream = true;
     }
     HIPCHK(hipStreamCreateWithFlags(&ctx->cs, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
     if (ctx->opts.time_kernels)
         for (auto &t : ctx->timers) {
             HIPCHK(hipEventCreate(&t.t0));
@@ -1391,6 +1428,8 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     HIPCHK(hipHostMalloc((void **)&ctx->h_hdr, HDR_WORDS * 4, hipHostMallocCoherent));
     memset(ctx->h_hdr, 0, HDR_WORDS * 4);
     HIPCHK(hipMalloc((void **)&ctx->d_nitems, 4));
+    HIPCHK(hipMalloc((void **)&ctx->d_touched, 8));
+    HIPCHK(hipMemset(ctx->d_touched, 0, 8));
     HIPCHK(hipMalloc((void **)&ctx->d_desc, sizeof(BatchDesc)));
     HIPCHK(hipHostMalloc((void **)&ctx->h_desc, sizeof(BatchDesc), hipHostMallocDefault));
     HIPCHK(hipMalloc((void **)&ctx->d_misc, 64));
@@ -1446,6 +1485,26 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// Whether p is device memory (anything else is taken as host memory).  The
+// query of an unregistered host pointer may report an error; it is cleared
+// so that the next launch check does not see it.
+static bool is_device_ptr(const void *p)
+{
+    hipPointerAttribute_t a = {};
+    const hipError_t e = hipPointerGetAttributes(&a, p);
+    (void)hipGetLastError();
+    return e == hipSuccess && a.type == hipMemoryTypeDevice;
+}
+
+// Entry points that read the forest, the sketch or the counters, or that
+// enqueue other work, first complete the host part of a device batch left
+// pending by cupk_apply_updates_device; its error is theirs.
+#define CUPK_FLUSH()                                  \
+    do {                                              \
+        const int frc_ = flush_pending(ctx);          \
+        if (frc_ != CUPK_OK) return frc_;             \
+    } while (0)
+
 extern "C" {
 
 size_t cupk_sketch_bytes(uint32_t V, uint32_t C, uint32_t D)
@@ -1494,6 +1553,8 @@ int cupk_apply_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
         for (size_t i = 0; i < n; i++)
             if (u[i] == v[i] || u[i] >= ctx->V || v[i] >= ctx->V)
                 return ctx->invalid("batch holds an update with u == v or an endpoint >= V");
+        int rc = flush_pending(ctx);
+        if (rc != CUPK_OK) return rc;
         HIPCHK(grow(ctx->h_upd, n));
         HIPCHK(grow(ctx->d_upd, n));
         // the previous batch's upload from h_upd finished: every call waits for
@@ -1503,19 +1564,37 @@ int cupk_apply_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
             h[i] = (uint64_t)u[i] | ((uint64_t)v[i] << 32) | ((uint64_t)(is_delete[i] != 0) << 63);
         HIPCHK(hipMemcpyAsync(ctx->d_upd.p, h, n * 8, hipMemcpyHostToDevice, ctx->s));
         ctx->query_often = true;
-        const int rc = apply_device(ctx, ctx->d_upd.p, n);
+        rc = apply_device(ctx, ctx->d_upd.p, n, false);
         ctx->query_often = false;
         return rc;
     });
 }
 
-int cupk_apply_updates_device(cupk_ctx *ctx, const uint64_t *d_packed, size_t n)
+int cupk_apply_updates_device(cupk_ctx *ctx, const uint64_t *d_packed, size_t n,
+                              void *hip_stream)
 {
     if (!ctx) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
         if (n == 0) return CUPK_OK;
         if (!d_packed) return ctx->invalid("null device pointer");
-        return apply_device(ctx, d_packed, n);
+        // the host part of the previous batch first: its error is this call's
+        const hipStream_t cs = (hipStream_t)hip_stream;
+        int rc = flush_pending(ctx);
+        if (rc != CUPK_OK) return rc;
+        // the batch is read on the library's stream after what the caller's
+        // stream has queued so far, and the caller's stream waits for the
+        // scatter (the last kernel that reads the batch)
+        if (cs != ctx->s) {
+            HIPCHK(hipEventRecord(ctx->ev_in, cs));
+            HIPCHK(hipStreamWaitEvent(ctx->s, ctx->ev_in, 0));
+        }
+        rc = apply_device(ctx, d_packed, n, true);
+        if (cs != ctx->s) {
+            // also after a failure: whatever was enqueued is ordered
+            if (hipEventRecord(ctx->ev_out, ctx->s) == hipSuccess)
+                (void)hipStreamWaitEvent(cs, ctx->ev_out, 0);
+        }
+        return rc;
     });
 }
 
@@ -1524,6 +1603,7 @@ int cupk_component_sketch_batch(cupk_ctx *ctx, const uint64_t *offsets, size_t k
 {
     if (!ctx) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
         if (k == 0) return CUPK_OK;
         if (!offsets || !out) return ctx->invalid("null array");
         if (offsets[0] != 0) return ctx->invalid("offsets[0] must be 0");
@@ -1538,9 +1618,15 @@ int cupk_component_sketch_batch(cupk_ctx *ctx, const uint64_t *offsets, size_t k
         for (size_t j = 0; j <= k; j++) voff[j] = (uint32_t)offsets[j];
         int rc = reduce_and_sample(ctx, 0, vmem, voff, none, none);
         if (rc != CUPK_OK) return rc;
-        HIPCHK(grow(ctx->d_tmp, (size_t)k * ctx->W));
-        HIPCHK(launch_to_canonical(ctx->s, ctx->d_sig[0].p, ctx->C, ctx->D, k, ctx->d_tmp.p));
-        HIPCHK(hipMemcpyAsync(out, ctx->d_tmp.p, (size_t)k * ctx->W * 8, hipMemcpyDeviceToHost, ctx->s));
+        if (is_device_ptr(out)) {
+            HIPCHK(launch_to_canonical(ctx->s, ctx->d_sig[0].p, ctx->C, ctx->D, k,
+                                       (uint64_t *)out));
+        } else {
+            HIPCHK(grow(ctx->d_tmp, (size_t)k * ctx->W));
+            HIPCHK(launch_to_canonical(ctx->s, ctx->d_sig[0].p, ctx->C, ctx->D, k, ctx->d_tmp.p));
+            HIPCHK(hipMemcpyAsync(out, ctx->d_tmp.p, (size_t)k * ctx->W * 8,
+                                  hipMemcpyDeviceToHost, ctx->s));
+        }
         HIPCHK(hipStreamSynchronize(ctx->s));
         return CUPK_OK;
     });
@@ -1594,8 +1680,9 @@ int cupk_connected(cupk_ctx *ctx, uint32_t u, uint32_t v)
 {
     if (!ctx) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
         if (u >= ctx->V || v >= ctx->V) return ctx->invalid("vertex id >= V");
-        // every batch leaves the forest complete before returning; the sketch
+        // the forest is complete once pending host work has run; the sketch
         // may still be in flight but queries do not read it
         return ctx->forest.same_tree(u, v) ? 1 : 0;
     });
@@ -1605,6 +1692,7 @@ int cupk_get_sketch(cupk_ctx *ctx, uint32_t w0, uint32_t nv, cupk_bucket *out)
 {
     if (!ctx) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
         if (nv == 0) return CUPK_OK;
         if (!out) return ctx->invalid("null out");
         if ((uint64_t)w0 + nv > ctx->V) return ctx->invalid("vertex range beyond V");
@@ -1626,6 +1714,7 @@ int cupk_digest(cupk_ctx *ctx, uint64_t *out)
 {
     if (!ctx || !out) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
         HIPCHK(launch_zero(ctx->s, ctx->d_misc, 1));
         HIPCHK(launch_digest(ctx->s, dev_sketch(ctx), ctx->S, ctx->d_misc));
         HIPCHK(hipMemcpyAsync(ctx->h_misc, ctx->d_misc, 8, hipMemcpyDeviceToHost, ctx->s));
@@ -1638,14 +1727,18 @@ int cupk_digest(cupk_ctx *ctx, uint64_t *out)
 int cupk_num_components(cupk_ctx *ctx, uint64_t *out)
 {
     if (!ctx || !out) return CUPK_EINVAL;
-    *out = ctx->forest.n_trees();
-    return CUPK_OK;
+    return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
+        *out = ctx->forest.n_trees();
+        return CUPK_OK;
+    });
 }
 
 int cupk_forest_edges(cupk_ctx *ctx, uint32_t *u, uint32_t *v, size_t cap, size_t *n)
 {
     if (!ctx || !n) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
         std::vector<uint32_t> eu, ev;
         ctx->forest.edges(eu, ev);
         *n = eu.size();
@@ -1662,6 +1755,7 @@ int cupk_level_forest_edges(cupk_ctx *ctx, uint32_t level, uint32_t *u, uint32_t
 {
     if (!ctx || !n) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
         if (!ctx->levels) return ctx->invalid("not in levels mode");
         if (level < 1 || level > ctx->levels->top) return ctx->invalid("level out of range");
         std::vector<uint32_t> eu, ev;
@@ -1678,16 +1772,24 @@ int cupk_level_forest_edges(cupk_ctx *ctx, uint32_t level, uint32_t *u, uint32_t
 int cupk_component_labels(cupk_ctx *ctx, uint32_t *out)
 {
     if (!ctx || !out) return CUPK_EINVAL;
-    for (uint32_t w = 0; w < ctx->V; w++) out[w] = ctx->forest.label(w);
-    return CUPK_OK;
+    return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
+        for (uint32_t w = 0; w < ctx->V; w++) out[w] = ctx->forest.label(w);
+        return CUPK_OK;
+    });
 }
 
 int cupk_counters(cupk_ctx *ctx, cupk_counters_t *out)
 {
     if (!ctx || !out) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
         int rc = harvest_timers(ctx, true);
         if (rc != CUPK_OK) return rc;
+        HIPCHK(hipMemcpyAsync(ctx->h_misc + 1, ctx->d_touched, 8, hipMemcpyDeviceToHost,
+                              ctx->s));
+        HIPCHK(hipStreamSynchronize(ctx->s));
+        ctx->ctr.timed_buckets = ctx->h_misc[1];
         *out = ctx->ctr;
         return CUPK_OK;
     });
@@ -1697,6 +1799,7 @@ int cupk_sync(cupk_ctx *ctx)
 {
     if (!ctx) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
         HIPCHK(hipStreamSynchronize(ctx->s));
         HIPCHK(hipStreamSynchronize(ctx->cs));
         return harvest_timers(ctx, true);
@@ -1717,7 +1820,7 @@ static int time_scatter_once(cupk_ctx *ctx, const uint64_t *d, uint32_t n, hipEv
     if (rc != CUPK_OK) return rc;
     HIPCHK(hipEventRecord(e0, ctx->s));
     rc = enqueue_bin(ctx, ctx->s, n);
-    if (rc == CUPK_OK) rc = enqueue_tile(ctx, ctx->s, n);
+    if (rc == CUPK_OK) rc = enqueue_tile(ctx, ctx->s, n, false);
     if (rc != CUPK_OK) return rc;
     HIPCHK(hipEventRecord(e1, ctx->s));
     HIPCHK(hipEventSynchronize(e1));
@@ -1878,13 +1981,17 @@ int cupk_static_components(cupk_ctx *ctx, uint32_t *labels, uint32_t *eu, uint32
 {
     if (!ctx) return CUPK_EINVAL;
     if (ctx->server) return ctx->invalid("static components while the serving loop runs");
-    return guarded(ctx, [&] { return static_components(ctx, labels, eu, ev, info); });
+    return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
+        return static_components(ctx, labels, eu, ev, info);
+    });
 }
 
 int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_result *out)
 {
     if (!ctx || !out || !d_sample) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
         if (ctx->server) return ctx->invalid("autotune while the serving loop runs");
         if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED) return ctx->invalid("autotune needs staged mode");
         if (n == 0 || n > kMaxBatchPerLaunch) return ctx->invalid("bad sample size");
@@ -1962,6 +2069,7 @@ int cupk_serve_start(cupk_ctx *ctx, const cupk_serve_opts *opts)
 {
     if (!ctx) return CUPK_EINVAL;
     return guarded(ctx, [&]() -> int {
+        CUPK_FLUSH();
         if (ctx->server) return ctx->invalid("serving loop already running");
         cupk_serve_opts o = {};
         if (opts) o = *opts;

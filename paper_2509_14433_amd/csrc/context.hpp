@@ -90,6 +90,7 @@ struct cupk_ctx {
     cupk::DevBuf<uint32_t> d_tgoff; // per (count copy, tile): where the copy's records start
     cupk::DevBuf<uint64_t> d_bins;
     uint32_t *d_nitems = nullptr;
+    unsigned long long *d_touched = nullptr;  // buckets changed by timed staged launches
 
     // reductions / samples
     cupk::DevBuf<uint32_t> d_ridx;   // members, then the work items, of a reduction
@@ -101,6 +102,11 @@ struct cupk_ctx {
     uint64_t *d_misc = nullptr, *h_misc = nullptr;
     cupk::SmallResult *d_small = nullptr, *h_small = nullptr;  // small-batch pass results
     bool small_pass = false;   // the last pass took the small-batch path
+    // cupk_apply_updates_device leaves the host part of its batch (flag
+    // walk, replacement rounds) pending until the next call that needs it
+    bool pending = false;
+    uint32_t pending_n = 0;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;  // ordering with a caller's stream
     cupk::BatchDesc *d_desc = nullptr, *h_desc = nullptr;
     // The batch of the pass being enqueued, passed to the kernels by value;
     // while graphs are captured they read d_desc instead.
@@ -228,5 +234,6 @@ int reduce_and_sample(cupk_ctx *ctx, int slot, const std::vector<uint32_t> &vmem
                       const std::vector<uint32_t> &voff, const std::vector<uint32_t> &fmem,
                       const std::vector<uint32_t> &foff);
 int run_rounds(cupk_ctx *ctx);
+int flush_pending(cupk_ctx *ctx);
 
 }  // namespace cupk

@@ -758,7 +758,7 @@ constexpr uint32_t kTileThreads = 256;
 // (one instruction); the full depth is computed only otherwise (odds 2^-r).
 DEVI void tile_column(uint64_t *la, uint64_t *lg, uint64_t *gb, uint32_t C, uint32_t D,
                       uint32_t CTV, uint32_t rows, uint32_t fmask, uint32_t c, uint64_t seed,
-                      uint64_t x, uint32_t lq)
+                      uint64_t x, uint32_t lq, uint32_t &deep)
 {
     const uint64_t h = mix64(x ^ seed);
     const uint32_t lo = (uint32_t)h;
@@ -771,6 +771,7 @@ DEVI void tile_column(uint64_t *la, uint64_t *lg, uint64_t *gb, uint32_t C, uint
             uint64_t *bp = gb + 2 * (__umul24(d, C & 0xffffffu) + c);
             gxor(bp, x);
             gxor(bp + 1, h);
+            deep++;
             return;
         }
     }
@@ -780,13 +781,17 @@ DEVI void tile_column(uint64_t *la, uint64_t *lg, uint64_t *gb, uint32_t C, uint
 }
 
 // CMAX > 0: columns unrolled at compile time (C <= CMAX); CMAX == 0: a
-// runtime loop for any C.
+// runtime loop for any C.  touched (may be null) receives the number of
+// buckets the launch changes in HBM: folded buckets with a nonzero delta,
+// plus one per record column that goes to a deep row directly.
 template <uint32_t CMAX>
 __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
     DevSketch sk, const uint64_t *__restrict__ bins, const uint32_t *__restrict__ off,
     const uint32_t *__restrict__ items, const uint32_t *__restrict__ nitems_p, uint32_t tile_shift,
-    uint32_t rows, uint32_t chunk, uint32_t *__restrict__ hdr)
+    uint32_t rows, uint32_t chunk, uint32_t *__restrict__ hdr,
+    unsigned long long *__restrict__ touched)
 {
+    uint32_t nchanged = 0;  // buckets this thread changed in HBM
     extern __shared__ uint64_t lds[];
     const bool err = hdr[HDR_ERR] != 0;
     const uint32_t TV = 1u << tile_shift;
@@ -831,11 +836,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
                 for (uint32_t c = 0; c < (CMAX > 0 ? CMAX : 1); c++)
                     if (c < C)
                         tile_column(la, lg, gb, C, D, CTV, rows, fmask, c, seed[c], x,
-                                    c * TV + (p - w0));
+                                    c * TV + (p - w0), nchanged);
             } else {
                 for (uint32_t c = 0; c < C; c++)
                     tile_column(la, lg, gb, C, D, CTV, rows, fmask, c, sk.seeds[c], x,
-                                c * TV + (p - w0));
+                                c * TV + (p - w0), nchanged);
             }
         }
         __syncthreads();
@@ -851,6 +856,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
             const uint64_t da = la[rc * TV + vl];
             const uint64_t dg = lg[rc * TV + vl];
             if ((da | dg) == 0) continue;
+            nchanged++;
             uint64_t *g = sk.b + (((uint64_t)(w0 + vl) * D) * C + rc) * 2;
             if (single) {
                 g[0] ^= da;
@@ -861,6 +867,12 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
             }
         }
         __syncthreads();
+    }
+    if (touched) {
+        uint32_t t = nchanged;
+#pragma unroll
+        for (uint32_t o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (__lane_id() == 0 && t) atomicAdd(touched, (unsigned long long)t);
     }
     scatter_done(hdr);
 }
@@ -889,14 +901,15 @@ hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32
 
 hipError_t launch_tile(hipStream_t s, DevSketch sk, uint32_t *hdr, const StagedParams &p,
                        const uint32_t *tile_off, const uint64_t *bins, const uint32_t *items,
-                       const uint32_t *nitems)
+                       const uint32_t *nitems, unsigned long long *touched)
 {
     const size_t lds = (size_t)2 * p.rows * sk.C * (1u << p.tile_shift) * sizeof(uint64_t);
     // Persistent grid: a few blocks per CU, each looping over work items.
     const uint32_t grid = min(p.items_cap, p.grid ? p.grid : 256u * 8u);
 #define CUPK_TILE_LAUNCH(CM)                                                                  \
     k_tile_scatter<CM><<<grid, kTileThreads, lds, s>>>(sk, bins, tile_off, items, nitems,     \
-                                                       p.tile_shift, p.rows, p.chunk, hdr)
+                                                       p.tile_shift, p.rows, p.chunk, hdr,   \
+                                                       touched)
     if (sk.C <= 8) CUPK_TILE_LAUNCH(8);
     else if (sk.C <= 16) CUPK_TILE_LAUNCH(16);
     else if (sk.C <= 24) CUPK_TILE_LAUNCH(24);

@@ -143,14 +143,15 @@ hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, BatchDesc
 // tile_goff plus the classify block's tile_rel entry when tile_rel is
 // non-null, else reserved from tile_cur);
 // launch_tile = LDS-staged XOR per work item, whose last block clears the
-// header for the next batch.
+// header for the next batch; touched (may be null) is incremented by the
+// number of buckets the launch changes in HBM.
 hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
                       DevSketch sk, const uint32_t *hdr, const StagedParams &p,
                       uint32_t *tile_cur, uint64_t *bins, const uint32_t *tile_goff,
                       const uint32_t *tile_rel);
 hipError_t launch_tile(hipStream_t s, DevSketch sk, uint32_t *hdr, const StagedParams &p,
                        const uint32_t *tile_off, const uint64_t *bins, const uint32_t *items,
-                       const uint32_t *nitems);
+                       const uint32_t *nitems, unsigned long long *touched);
 
 // Fill n words with zero.
 hipError_t launch_zero(hipStream_t s, uint64_t *p, size_t n);

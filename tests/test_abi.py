@@ -25,6 +25,23 @@ def test_header_declares_the_boundary():
         assert want in names
 
 
+def _prototype(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"\b" + name + r"\s*\(([^)]*)\)", text)
+    assert m, name
+    return [a.strip() for a in m.group(1).split(",")]
+
+
+def test_device_apply_takes_a_stream():
+    # (ctx, device batch, count, hipStream_t the batch was produced on)
+    args = _prototype("cupk_apply_updates_device")
+    assert len(args) == 4
+    assert args[1].startswith("const uint64_t *") and args[2].startswith("size_t")
+    assert args[3].replace(" ", "") == "void*hip_stream"
+    import paper_2509_14433_amd as cupk
+    assert len(cupk.lib.cupk_apply_updates_device.argtypes) == 4
+
+
 def test_library_exports_every_declared_symbol():
     import paper_2509_14433_amd as cupk
     lib = ctypes.CDLL(cupk.LIB_PATH)

@@ -192,12 +192,16 @@ def test_invalid_batch_applies_nothing(cupk, mode):
         with pytest.raises(cupk.CupkError) as ei:
             ctx.apply_updates(uu, vv, np.zeros(3, np.uint8))
         assert ei.value.code == cupk.EINVAL
-        # the device path validates on the GPU
+        # the device path validates on the GPU; the call that completes the
+        # batch's host part (here cupk_sync) reports it
         import torch
         packed = torch.from_numpy(cupk.pack_updates(uu, vv, np.zeros(3)).view(np.int64)).cuda()
+        ctx.apply_updates_device(packed)
         with pytest.raises(cupk.CupkError) as ei:
-            ctx.apply_updates_device(packed)
+            ctx.sync()
         assert ei.value.code == cupk.EINVAL
+        # reported once: the context goes on
+        ctx.sync()
     assert ctx.digest() == dg and ctx.forest_edges() == edges
     ctx.apply_updates(np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.uint8))
     assert ctx.digest() == dg
@@ -411,3 +415,122 @@ def test_fill_reserve_option(cupk):
         _assert_same_sketch(ctx, ref)
         assert ctx.forest_edges() == fr.forest_edges()
         ctx.close()
+
+
+def _forest_cut_batches(rng, V, eu, ev, fr, nb, n_forest, n_other, n_new):
+    """Batches after an insert phase: each deletes n_forest edges of the
+    oracle's current forest and n_other other live edges, and inserts n_new
+    fresh pairs, in random order (applied by the caller to both sides)."""
+    live = set(zip(eu.tolist(), ev.tolist()))
+    for _ in range(nb):
+        fe = fr.forest_edges()
+        pick_f = [fe[i] for i in rng.choice(len(fe), n_forest, replace=False)]
+        fset = set(fe)
+        others = [e for e in live if e not in fset]
+        pick_o = [others[i] for i in rng.choice(len(others), n_other, replace=False)]
+        new = set()
+        while len(new) < n_new:
+            a, b = (int(t) for t in rng.integers(0, V, 2))
+            e = (min(a, b), max(a, b))
+            if a != b and e not in live:
+                new.add(e)
+        dels = pick_f + pick_o
+        ups = [(a, b, 1) for a, b in dels] + [(a, b, 0) for a, b in sorted(new)]
+        order = rng.permutation(len(ups))
+        u = np.array([ups[i][0] for i in order], np.uint32)
+        v = np.array([ups[i][1] for i in order], np.uint32)
+        d = np.array([ups[i][2] for i in order], np.uint8)
+        live -= set(dels)
+        live |= new
+        yield u, v, d
+
+
+# More than 8192 vertex tiles: the classify kernel counts tile records with
+# global atomics instead of an LDS histogram, and the fill reserves one bin
+# slot per record.  (V, tile_vertices): one-vertex tiles over 9000 vertices,
+# and the default 16-vertex tiles over 140,000 vertices (8750 tiles).
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("V,tv", [(9000, 1), (140_000, 16)])
+def test_many_tiles_parity(cupk, mode, V, tv):
+    C = max(1, math.ceil(math.log2(V)))
+    D = 2 * C
+    S = 0x5EED8192 + V
+    rng = np.random.default_rng(V + tv)
+    m = 3 * V
+    a = rng.integers(0, V, 2 * m)
+    b = rng.integers(0, V, 2 * m)
+    keep = a != b
+    key = np.unique(np.minimum(a, b)[keep].astype(np.int64) * V + np.maximum(a, b)[keep])[:m]
+    rng.shuffle(key)
+    eu, ev = (key // V).astype(np.uint32), (key % V).astype(np.uint32)
+    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode), tile_vertices=tv)
+    ref = oracle.Sketch(V, C, D, S)
+    fr = oracle.ForestReplay(ref)
+    bs = 5000 if V < 20000 else 60000
+    for s in range(0, m, bs):
+        e = min(m, s + bs)
+        print(f"many tiles V={V} tv={tv} mode={mode} insert batch {s}:{e}", flush=True)
+        z = np.zeros(e - s, np.uint8)
+        ctx.apply_updates(eu[s:e], ev[s:e], z)
+        fr.apply_batch(eu[s:e], ev[s:e], z)
+    assert ctx.digest() == ref.digest()
+    nfor = 25 if V < 20000 else 30
+    for k, (u, v, d) in enumerate(_forest_cut_batches(rng, V, eu, ev, fr, 3, nfor, 3000, 3000)):
+        print(f"many tiles V={V} tv={tv} mode={mode} cut batch {k} n={len(u)}", flush=True)
+        ctx.apply_updates(u, v, d)
+        fr.apply_batch(u, v, d)
+        assert ctx.digest() == ref.digest()
+        assert ctx.forest_edges() == fr.forest_edges()
+    _assert_same_sketch(ctx, ref)
+    ctr = ctx.counters()
+    assert ctr["cuts"] == fr.n_cuts >= 3 * nfor
+    assert ctr["links"] == fr.n_links and ctr["rounds"] == fr.n_rounds
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_device_batches_stream_ordered(cupk, mode):
+    # Eight device batches produced on a side torch stream and queued back
+    # to back without waiting in between: each call returns once its device
+    # work is queued (the host part runs at the next call); after cupk_sync
+    # the sketch, digest and forest equal the oracle's for the same batch
+    # boundaries.  The batches are built on the side stream right before
+    # each call and their tensors dropped at once, so the caching allocator
+    # reuses the memory in stream order.
+    import torch
+    V, C, D, S = 3000, 12, 24, 0x5EED5757
+    u, v, d = streamgen.er_standard(V, 0.01, 0.3, 77)
+    nb = 8
+    bounds = np.linspace(0, len(u), nb + 1).astype(int)
+    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    ref = oracle.Sketch(V, C, D, S)
+    fr = oracle.ForestReplay(ref)
+    side = torch.cuda.Stream()
+    host = [cupk.pack_updates(u[a:b], v[a:b], d[a:b]).view(np.int64)
+            for a, b in zip(bounds[:-1], bounds[1:])]
+    with torch.cuda.stream(side):
+        for k, h in enumerate(host):
+            print(f"stream-ordered batch {k} n={len(h)} mode={mode}", flush=True)
+            t = torch.from_numpy(h).pin_memory().to("cuda", non_blocking=True)
+            ctx.apply_updates_device(t, stream=side.cuda_stream)
+            del t
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        fr.apply_batch(u[a:b], v[a:b], d[a:b])
+    ctx.sync()
+    side.synchronize()
+    _assert_same_sketch(ctx, ref)
+    assert ctx.forest_edges() == fr.forest_edges()
+    assert ctx.counters()["batches"] == nb
+    # component sketches written straight into device memory equal the host
+    # copies and the oracle's
+    rng = np.random.default_rng(3)
+    sets = [sorted(rng.choice(V, size=int(s), replace=False).tolist()) for s in (1, 17, 900)]
+    ha, hg = ctx.component_sketch_batch(sets)
+    out = torch.zeros(len(sets) * C * D * 2, dtype=torch.int64, device="cuda")
+    ctx.component_sketch_batch(sets, out=out)
+    dv = out.cpu().numpy().view(np.uint64).reshape(len(sets), C, D, 2)
+    for j, U in enumerate(sets):
+        oa, og = ref.set_sketch(U)
+        assert np.array_equal(dv[j, ..., 0], oa) and np.array_equal(dv[j, ..., 1], og)
+        assert np.array_equal(ha[j], oa) and np.array_equal(hg[j], og)
+    ctx.close()
