@@ -285,6 +285,27 @@ int cupk_component_sketch(cupk_ctx *ctx, const uint32_t *verts, size_t n,
 int cupk_component_sketch_batch(cupk_ctx *ctx, const uint64_t *offsets, size_t k,
                                 const uint32_t *verts, cupk_bucket *out);
 
+/* component_sketch_batch_noalloc — cupk_component_sketch_batch for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the call allocates no device or host
+ * memory.  Its members, offsets and aggregates live in a file-scope device
+ * array of about 20 MiB, one per GPU, taken when the library's code is
+ * loaded on that GPU and held until the process ends; its address is looked
+ * up once per device by cupk_sketch_init.
+ *   offsets, k, verts: as for cupk_component_sketch_batch (host arrays).
+ *   out_device: k*C*D buckets in device memory, canonical order.
+ * Limits: k <= 4096 sets, offsets[k] <= 2^20 members, k*2*C*D <= 2^21
+ * aggregate words; beyond them CUPK_EINVAL with nothing done.  A device
+ * batch still pending from cupk_apply_updates_device is also CUPK_EINVAL
+ * (completing it may allocate: call cupk_sync first).  The call returns
+ * when out_device is written.  Every call on one GPU shares that GPU's
+ * array, so calls that overlap on one GPU (other threads, other contexts
+ * on the same device) race; the array keeps the last call's contents and
+ * each call zero-fills the part it uses.
+ * Errors: CUPK_EINVAL, CUPK_EDEVICE. */
+int cupk_component_sketch_batch_noalloc(cupk_ctx *ctx, const uint64_t *offsets, size_t k,
+                                        const uint32_t *verts, cupk_bucket *out_device);
+
 /* sample_cut_edge — query one aggregate sketch (cutset Query, Sec. 2.2.1;
  * l0 sampling, App. A.1.1).  sketch: C*D buckets (host), canonical order.
  * Returns CUPK_OK with *u < *v the edge of the first good bucket,

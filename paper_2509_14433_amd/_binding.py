@@ -115,6 +115,7 @@ def _load():
         "cupk_apply_updates_device": (ctypes.c_int, [p, p, sz, p]),
         "cupk_component_sketch": (ctypes.c_int, [p, p, sz, p]),
         "cupk_component_sketch_batch": (ctypes.c_int, [p, p, sz, p, p]),
+        "cupk_component_sketch_batch_noalloc": (ctypes.c_int, [p, p, sz, p, p]),
         "cupk_sample_cut_edge": (ctypes.c_int, [p, p, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
         "cupk_sample_cut_edge_batch": (ctypes.c_int, [p, p, sz, p, p, p]),
         "cupk_connected": (ctypes.c_int, [p, u32, u32]),

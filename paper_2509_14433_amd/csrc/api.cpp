@@ -1389,6 +1389,8 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     }
     ctx->W = 2 * C * D;
     HIPCHK(hipGetDevice(&ctx->device));
+    // the allocation-free entry point's scratch array on this device
+    HIPCHK(noalloc_scratch_address(ctx->device, &ctx->noalloc_scratch));
     {
         const char *tr = getenv("CUPK_TRACE");
         ctx->trace = tr && tr[0] == '1';
@@ -1627,6 +1629,49 @@ int cupk_component_sketch_batch(cupk_ctx *ctx, const uint64_t *offsets, size_t k
             HIPCHK(hipMemcpyAsync(out, ctx->d_tmp.p, (size_t)k * ctx->W * 8,
                                   hipMemcpyDeviceToHost, ctx->s));
         }
+        HIPCHK(hipStreamSynchronize(ctx->s));
+        return CUPK_OK;
+    });
+}
+
+int cupk_component_sketch_batch_noalloc(cupk_ctx *ctx, const uint64_t *offsets, size_t k,
+                                        const uint32_t *verts, cupk_bucket *out_device)
+{
+    if (!ctx) return CUPK_EINVAL;
+    return guarded(ctx, [&]() -> int {
+        if (k == 0) return CUPK_OK;
+        if (!offsets || !out_device) return ctx->invalid("null array");
+        if (ctx->server) return ctx->invalid("component sketches while the serving loop runs");
+        // completing a pending batch may allocate: the caller does it first
+        if (ctx->pending)
+            return ctx->invalid("a device batch is pending: call cupk_sync first");
+        if (k > kNoAllocMaxSets) return ctx->invalid("more sets than the scratch holds (4096)");
+        if ((uint64_t)k * ctx->W > kNoAllocAggWords)
+            return ctx->invalid("k * 2*C*D words exceed the scratch's 2^21 aggregate words");
+        if (offsets[0] != 0) return ctx->invalid("offsets[0] must be 0");
+        for (size_t j = 0; j < k; j++)
+            if (offsets[j + 1] < offsets[j]) return ctx->invalid("offsets must be non-decreasing");
+        const uint64_t nv = offsets[k];
+        if (nv > kNoAllocMaxMembers)
+            return ctx->invalid("more members than the scratch holds (2^20)");
+        if (nv && !verts) return ctx->invalid("null verts");
+        for (uint64_t i = 0; i < nv; i++)
+            if (verts[i] >= ctx->V) return ctx->invalid("vertex id >= V");
+        if (!is_device_ptr(out_device)) return ctx->invalid("out_device is not device memory");
+        uint64_t *agg = ctx->noalloc_scratch;
+        uint64_t *offs = agg + kNoAllocOffsWord;
+        uint32_t *mem = (uint32_t *)(agg + kNoAllocMemWord);
+        // inputs into the scratch (copies from the caller's host arrays), a
+        // zero fill of the aggregates, the reduction, canonical order into out
+        HIPCHK(hipMemcpyAsync(offs, offsets, (k + 1) * sizeof(uint64_t), hipMemcpyHostToDevice,
+                              ctx->s));
+        if (nv)
+            HIPCHK(hipMemcpyAsync(mem, verts, nv * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                  ctx->s));
+        HIPCHK(launch_zero(ctx->s, agg, (size_t)k * ctx->W));
+        HIPCHK(launch_reduce_csr(ctx->s, ctx->d_sk, ctx->W, mem, offs, (uint32_t)k, (uint32_t)nv,
+                                 agg));
+        HIPCHK(launch_to_canonical(ctx->s, agg, ctx->C, ctx->D, k, (uint64_t *)out_device));
         HIPCHK(hipStreamSynchronize(ctx->s));
         return CUPK_OK;
     });

@@ -107,6 +107,9 @@ struct cupk_ctx {
     bool pending = false;
     uint32_t pending_n = 0;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;  // ordering with a caller's stream
+    // device address of the allocation-free entry point's scratch array on
+    // this context's device (taken at init)
+    uint64_t *noalloc_scratch = nullptr;
     cupk::BatchDesc *d_desc = nullptr, *h_desc = nullptr;
     // The batch of the pass being enqueued, passed to the kernels by value;
     // while graphs are captured they read d_desc instead.

@@ -10,6 +10,8 @@
 // updates (depth d is hit with probability 2^-(d+1)), are contiguous.
 #include "kernels.hpp"
 
+#include <mutex>
+
 namespace cupk {
 
 #define DEVI __device__ __forceinline__
@@ -1073,6 +1075,109 @@ hipError_t launch_reduce(hipStream_t s, const uint64_t *src, uint32_t W, const u
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+// Reduction over CSR sets for the allocation-free entry point: a block takes
+// members [16q, 16q + 16) of the concatenated member list, finds the set of
+// the first one by binary search over the offsets (sets may be empty), and
+// walks forward, folding its accumulator into a set's aggregate whenever it
+// leaves that set.
+constexpr uint32_t kCsrChunk = 16;
+
+template <uint32_t KMAX>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_csr(const uint64_t *__restrict__ src,
+                                                            uint32_t W,
+                                                            const uint32_t *__restrict__ mem,
+                                                            const uint64_t *__restrict__ offs,
+                                                            uint32_t k, uint32_t nv,
+                                                            uint64_t *__restrict__ out)
+{
+    const uint32_t nchunks = (nv + kCsrChunk - 1) / kCsrChunk;
+    for (uint32_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+        const uint32_t b = q * kCsrChunk, e = min(nv, b + kCsrChunk);
+        // the last set j with offs[j] <= b; offs[0] = 0 <= b < nv = offs[k]
+        uint32_t lo = 0, hi = k;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (offs[mid] <= b) lo = mid;
+            else hi = mid;
+        }
+        uint32_t j = lo;
+        uint64_t end = offs[j + 1];
+        uint64_t acc[KMAX];
+#pragma unroll
+        for (uint32_t t = 0; t < KMAX; t++) acc[t] = 0;
+        for (uint32_t m = b; m < e; m++) {
+            if (m >= end) {
+                uint64_t *o = out + (uint64_t)j * W;
+#pragma unroll
+                for (uint32_t t = 0; t < KMAX; t++) {
+                    const uint32_t w = t * kRedThreads + threadIdx.x;
+                    if (w < W && acc[t]) gxor(&o[w], acc[t]);
+                    acc[t] = 0;
+                }
+                do {
+                    j++;
+                    end = offs[j + 1];
+                } while (m >= end);
+            }
+            const uint64_t *s0 = src + (uint64_t)mem[m] * W;
+#pragma unroll
+            for (uint32_t t = 0; t < KMAX; t++) {
+                const uint32_t w = t * kRedThreads + threadIdx.x;
+                if (w < W) acc[t] ^= s0[w];
+            }
+        }
+        uint64_t *o = out + (uint64_t)j * W;
+#pragma unroll
+        for (uint32_t t = 0; t < KMAX; t++) {
+            const uint32_t w = t * kRedThreads + threadIdx.x;
+            if (w < W && acc[t]) gxor(&o[w], acc[t]);
+        }
+    }
+}
+
+hipError_t launch_reduce_csr(hipStream_t s, const uint64_t *src, uint32_t W,
+                             const uint32_t *mem, const uint64_t *offs, uint32_t k,
+                             uint32_t nv, uint64_t *out)
+{
+    if (k == 0 || nv == 0) return hipSuccess;
+    const uint32_t grid = min((nv + kCsrChunk - 1) / kCsrChunk, 8192u);
+    if (W <= 4 * kRedThreads)
+        k_reduce_csr<4><<<grid, kRedThreads, 0, s>>>(src, W, mem, offs, k, nv, out);
+    else if (W <= 8 * kRedThreads)
+        k_reduce_csr<8><<<grid, kRedThreads, 0, s>>>(src, W, mem, offs, k, nv, out);
+    else if (W <= 16 * kRedThreads)
+        k_reduce_csr<16><<<grid, kRedThreads, 0, s>>>(src, W, mem, offs, k, nv, out);
+    else if (W <= 32 * kRedThreads)
+        k_reduce_csr<32><<<grid, kRedThreads, 0, s>>>(src, W, mem, offs, k, nv, out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// Scratch of the allocation-free entry point: one array per GPU, held until
+// the process ends.  In host code its name is a host-side stand-in, not a
+// device address: host code uses only the address hipGetSymbolAddress
+// returns for the current device, kept per device below.
+static __device__ __align__(256) uint64_t scratch[kNoAllocScratchWords];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint64_t *g_scratch_addr[kMaxDevices];
+
+hipError_t noalloc_scratch_address(int device, uint64_t **out)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        uint64_t *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

@@ -162,6 +162,30 @@ hipError_t launch_zero32(hipStream_t s, uint32_t *p, size_t n);
 hipError_t launch_reduce(hipStream_t s, const uint64_t *src, uint32_t W, const uint32_t *idx,
                          const uint32_t *items, uint32_t nitems, uint64_t *out);
 
+// Allocation-free aggregates (cupk_component_sketch_batch_noalloc): the
+// members, set offsets and aggregates of one call live in a file-scope
+// device array of kNoAllocScratchWords words, one per GPU for the life of
+// the process.  Layout in words: aggregates [0, kNoAllocAggWords), then the
+// kNoAllocMaxSets + 1 set offsets (uint64), then the members (uint32, two
+// per word).
+constexpr uint32_t kNoAllocMaxMembers = 1u << 20;
+constexpr uint32_t kNoAllocMaxSets = 4096;
+constexpr uint32_t kNoAllocAggWords = 1u << 21;  // 16 MiB of aggregates
+constexpr size_t kNoAllocOffsWord = kNoAllocAggWords;
+constexpr size_t kNoAllocMemWord = kNoAllocOffsWord + kNoAllocMaxSets + 1;
+constexpr size_t kNoAllocScratchWords = kNoAllocMemWord + kNoAllocMaxMembers / 2;
+// Device address of the scratch array on `device`, which must be current.
+// Taken with hipGetSymbolAddress on the first call per device and kept.
+hipError_t noalloc_scratch_address(int device, uint64_t **out);
+
+// Segmented XOR reduction over CSR sets: out[j] = XOR of the slabs of
+// mem[offs[j] .. offs[j+1]) for j < k (nv = offs[k] members).  Blocks take
+// 16 consecutive members at a time and find their set by binary search, so
+// no work-item list is needed.  out (k*W words) must be zeroed first.
+hipError_t launch_reduce_csr(hipStream_t s, const uint64_t *src, uint32_t W,
+                             const uint32_t *mem, const uint64_t *offs, uint32_t k,
+                             uint32_t nv, uint64_t *out);
+
 // Query each of k aggregate sketches (bucket (c,d) at word (c*sc + d*sd)*2).
 // res: 3 words per set (status, u, v).
 hipError_t launch_sample(hipStream_t s, const uint64_t *sig, uint32_t k, uint32_t V, uint32_t C,
