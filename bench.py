@@ -1,31 +1,40 @@
 """Benchmark of the sketch hot path on one MI355X.
 
-Workload: V=16384 vertices, Erdos-Renyi G(V, 0.3) insert stream in random
-order followed by deletion of a random 10% of the inserted edges
-(44,276,290 updates), applied in fixed batches of 1,000,000 updates; sketch
-of C=14 columns x D=28 depth buckets per vertex.
+Headline workload (the largest configuration, one GPU): clusters64x2048_churn.
+V = 2^20 vertices: 64 dense clusters of 2048 vertices (each G(2048, 0.5)),
+a sparse G(n, 2n) on the other 917,504 vertices, 63 tree bridges plus 65
+extra between clusters.  Setup phase: the sparse edges, the bridges and every
+cluster's first-arrival spanning forest (1.97M updates).  Then 11 churn
+rounds, each inserting every other cluster edge (66.9M) in a fresh random
+order and deleting them all in another (1.34e8 updates per round), with 100
+random bridges toggled every 1e5 updates (splits and merges of cluster
+groups).  Sketch: C=20 columns x D=40 depths per vertex (13.4 GB resident in
+HBM).  The whole stream is drawn before timing and held in HBM.
 
-One step = one batch through the whole path: device classification,
-scatter into both endpoints' sketches, host forest links/cuts, replacement
-rounds (component XOR-reduce + verify/sample) for every broken tree.  The
-packed stream is resident in HBM before timing starts.  K steps walk the
-stream from its start; past its end a fresh context replays it again.
+One step = one churn round through the whole path, in 1M-update device
+batches: classification, staged scatter into both endpoints' sketches, host
+forest links/cuts, replacement rounds (component XOR-reduce + verify/sample)
+for every broken tree.  K steps walk the stream's rounds in order; after the
+last round a fresh context (set up untimed) starts from round 0 again.  The
+setup phase of every context runs before the timed region.
 
-Prints one JSON line: whole-job updates/s, the scatter kernel's roofline
-figures (algorithmic bytes per update = 8 + 64*C over the kernel time of
-every 4th launch of the timed region, taken with HIP events on the launch
-stream), the plain (atomic) kernel's figures, components from the final
-sketch alone, the served path (large update requests; the paper's query
-bursts, open and closed loop), and the CPU oracle timed on a bounded sample
-of the same stream.  --workload selects the extra full-size measurements
-of the other workload recipes and modes instead.
+Prints one JSON line: whole-job updates/s; the staged scatter's roofline
+(compulsory bytes = 8 B per update + 32 B per bucket the timed launches
+changed in HBM, counted by the kernel, over the kernel time of every 8th
+launch taken with HIP events on its stream; the HBM traffic of the committed
+rocprofv3 PMC profile; the VALU issue rate of the committed SQ counter
+profile); the plain (atomic) kernel on the same workload; and the CPU oracle
+timed on a bounded sample of the same stream (all host cores, and one).
+--workload selects the extra measurements of the other workload recipes.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
+import subprocess
 import sys
 import time
 
@@ -33,7 +42,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# VALU issue peak: 256 CUs x 4 SIMDs, one wave instruction per SIMD per
+# cycle, at 2.4 GHz
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9
 CALIB_BYTES = 256 << 20  # plain copy used to scale the HBM byte counters
+BATCH4 = 1_000_000
+# the benchmark workload of the first build, kept as an extra measurement
 V, C, D, SEED, BATCH = 16384, 14, 28, 0x5EED0001, 1_000_000
 WORKLOAD = ("er16384_p0.3_del10: V=16384, G(V,0.3) inserts in random order then 10% random "
             "deletions (44,276,290 updates), 1,000,000-update batches, C=14 x D=28 buckets")
@@ -45,25 +59,29 @@ def algorithmic_bytes_per_update(C: int) -> int:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources (kernels.hip and kernels.hpp): profile
+    figures taken on other sources are not used."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2509_14433_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("kernels.hip", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2509_14433_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
-    summary, or None when absent or taken on a different kernel source."""
+def profile_entry(kernel: str, workload: str):
+    """Per-launch figures of `kernel` on `workload` from the committed
+    rocprofv3 PMC summary (profiles/pmc_traffic.json), or None when absent or
+    taken on different kernel sources."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     try:
         with open(path) as f:
             prof = json.load(f)
     except (OSError, ValueError):
         return None
-    ent = prof.get(kernel)
-    if not ent or ent.get("kernels_hip_sha256_16") != kernel_source_hash():
+    ent = prof.get(f"{kernel}@{workload}")
+    if not ent or ent.get("kernel_sources_sha256_16") != kernel_source_hash():
         return None
-    return ent.get("hbm_bytes_per_launch")
+    return ent
 
 
 # Scatter launches timed with HIP events: every TIME_EVERY-th one (each
@@ -271,8 +289,8 @@ def workload_leg(args, cupk, torch, np, streamgen):
     name = args.workload
     out = {"metric": "edge updates/sec", "unit": "updates/s", "n_gpus": 1, "data": "synthetic",
            "dtype": "u64"}
-    if name in ("rmat17", "clusters", "fixed_forest"):
-        i = {"rmat17": 2, "clusters": 4, "fixed_forest": 5}[name]
+    if name in ("rmat17", "fixed_forest"):
+        i = {"rmat17": 2, "fixed_forest": 5}[name]
         cfg = streamgen.CONFIGS[i]
         print(f"bench: generating {cfg['name']}", file=sys.stderr, flush=True)
         Vw = cfg["V"]
@@ -467,43 +485,9 @@ def workload_leg(args, cupk, torch, np, streamgen):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=45)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel run")
-    ap.add_argument("--no-serve", action="store_true", help="skip the served run")
-    ap.add_argument("--no-static", action="store_true",
-                    help="skip the static-components run on the final sketch")
-    ap.add_argument("--mode", default="staged", choices=["staged", "atomic"])
-    ap.add_argument("--graph", type=int, default=0,
-                    help="1: replay each batch's device work as captured HIP graphs")
-    ap.add_argument("--workload", default="er16384",
-                    choices=["er16384", "rmat17", "er65536_served", "clusters", "fixed_forest",
-                             "exact_sweep", "levels"],
-                    help="er16384: the benchmark line; the others print extra full-size "
-                         "measurements of the other workload recipes")
-    ap.add_argument("--calib", action="store_true",
-                    help="first run a plain 256 MiB device copy (4 times) as the reference "
-                         "for HBM byte counters")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
-              "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    import paper_2509_14433_amd as cupk
-    import streamgen
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    if args.workload != "er16384":
-        workload_leg(args, cupk, torch, np, streamgen)
-        return
+def er16384_leg(args, cupk, np, torch, streamgen):
+    """The first build's benchmark line (extra measurement): V=16384,
+    G(V,0.3) then 10% deletions, 1M-update batches; one step = one batch."""
     print("bench: generating stream", file=sys.stderr, flush=True)
     u, v, d = streamgen.config_stream(1)
     n = len(u)
@@ -511,13 +495,6 @@ def main():
     packed = torch.from_numpy(cupk.pack_updates(u, v, d).view(np.int64)).cuda()
     torch.cuda.synchronize()
 
-    if args.calib:
-        src = torch.ones(CALIB_BYTES // 8, dtype=torch.int64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(4):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     mode = cupk.SCATTER_STAGED if args.mode == "staged" else cupk.SCATTER_ATOMIC
     print("bench: timing main path", file=sys.stderr, flush=True)
     dt, total, ctr = run_path(cupk, torch, packed, sizes, args.steps, args.warmup, mode,
@@ -532,7 +509,8 @@ def main():
     achieved = bpu * upd_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_from_profile(kname),
+                "traffic": (profile_entry(kname, "er16384_p0.3_del10") or {}).get(
+                    "hbm_bytes_per_launch"),
                 "kernel": kname, "kernel_avg_ms": round(avg_ms, 5),
                 "bin_avg_ms": round(ctr["bin_ms"] / launches, 5),
                 "bytes_per_update": bpu,
@@ -578,6 +556,306 @@ def main():
         print("bench: timing CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(u, v, d, sizes)
     print(json.dumps(out), flush=True)
+
+
+
+
+# ---------------------------------------------------------------------------
+# Headline: clusters64x2048_churn
+# ---------------------------------------------------------------------------
+def clusters_phases_device(np, torch, streamgen, cfg):
+    """The stream's phases (setup, round 0, ..., round R-1) as device int64
+    tensors of packed updates."""
+    phases = []
+    t0 = time.perf_counter()
+    for k, ph in enumerate(streamgen.clustered_phases(cfg)):
+        phases.append(torch.from_numpy(ph.view(np.int64)).to("cuda"))
+        print(f"bench: drew {'setup' if k == 0 else f'round {k - 1}'} ({len(ph)} updates), "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        del ph
+    torch.cuda.synchronize()
+    return phases
+
+
+def _apply_phase(ctx, ph, batch):
+    n = ph.shape[0]
+    for s in range(0, n, batch):
+        ctx.apply_updates_device(ph[s:min(n, s + batch)])
+
+
+def _ctr_delta(c1, c0):
+    return {k: c1[k] - c0.get(k, 0) for k in c1}
+
+
+def run_clusters(cupk, torch, phases, cfg, steps, warmup, batch, mode, tune,
+                 time_kernels=TIME_EVERY, label="main"):
+    """Time `steps` churn rounds (see the module docstring).  Returns
+    (seconds, updates, counters of the timed rounds, tune result)."""
+    Vc = cfg["V"]
+    Cc = streamgen_ceil_log2(Vc)
+    nr = len(phases) - 1
+    sample = phases[1][: min(phases[1].shape[0], batch)].contiguous()
+    tuned = {}
+
+    def new_ctx():
+        ctx = cupk.Context(Vc, Cc, 2 * Cc, cfg["S"], scatter_mode=mode, max_batch=batch,
+                           time_kernels=time_kernels)
+        if tune:
+            tuned.update(ctx.autotune(sample))
+        _apply_phase(ctx, phases[0], batch)
+        ctx.sync()
+        return ctx
+
+    if warmup:
+        w = new_ctx()
+        for i in range(warmup):
+            if i and i % nr == 0:
+                w.close()
+                w = new_ctx()
+            _apply_phase(w, phases[1 + i % nr], batch)
+            w.sync()
+            print(f"bench: {label} warmup round {i % nr}", file=sys.stderr, flush=True)
+        w.close()
+    n_ctx = max(1, (steps + nr - 1) // nr)
+    ctxs = [new_ctx() for _ in range(n_ctx)]
+    c0 = [c.counters() for c in ctxs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total = 0
+    for i in range(steps):
+        ph = phases[1 + i % nr]
+        _apply_phase(ctxs[i // nr], ph, batch)
+        total += ph.shape[0]
+        if i % 4 == 3:
+            print(f"bench: {label} round {i + 1} of {steps} queued, "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    for c in ctxs:
+        c.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctr = {}
+    for c, a in zip(ctxs, c0):
+        for k, val in _ctr_delta(c.counters(), a).items():
+            ctr[k] = ctr.get(k, 0) + val
+    for c in ctxs:
+        c.close()
+    return dt, total, ctr, tuned
+
+
+def streamgen_ceil_log2(V):
+    return max(1, int(math.ceil(math.log2(V))))
+
+
+def host_cpu():
+    """(logical CPUs this process may use, CPU model name)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = "unknown"
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return n, model
+
+
+def cpu_baseline_clusters(np, streamgen, phases_host_sample, cfg, budget_s=12.0):
+    """The oracle's sketch update (hash + XOR into both endpoints, no forest)
+    on a bounded sample of the same stream: every host core (each thread
+    owns a vertex range), then one thread."""
+    import oracle
+    Vc = cfg["V"]
+    Cc = streamgen_ceil_log2(Vc)
+    nthreads, model = host_cpu()
+    u, v, _ = streamgen.unpack(phases_host_sample)
+    out = {}
+    for label, t in (("all_cores", nthreads), ("one_thread", 1)):
+        sk = oracle.Sketch(Vc, Cc, 2 * Cc, cfg["S"])
+        step = 1 << 22 if t > 1 else 1 << 19
+        done, used = 0, t
+        t0 = time.perf_counter()
+        while done < len(u) and time.perf_counter() - t0 < budget_s:
+            e = min(len(u), done + step)
+            used = sk.apply_threads(u[done:e], v[done:e], t)
+            done = e
+        dt = time.perf_counter() - t0
+        out[label] = {"value": round(done / dt, 1), "cores": used, "updates": done,
+                      "seconds": round(dt, 2)}
+        del sk
+        print(f"bench: cpu baseline {label}: {out[label]}", file=sys.stderr, flush=True)
+    a = out["all_cores"]
+    return {"value": a["value"], "unit": "updates/s", "cores": a["cores"], "kind": "oracle",
+            "cpu_model": model, "nproc": nthreads,
+            "sample": f"the first {a['updates']} updates of the same stream (setup phase, then "
+                      f"churn round 0): the oracle's sketch update (column hashes + XOR into "
+                      f"both endpoints' buckets), one thread per vertex range on every core; "
+                      f"forest work and stream generation excluded",
+            "one_thread": out["one_thread"]}
+
+
+def clusters_main(args, cupk, np, torch, streamgen):
+    cfg = streamgen.CONFIGS[4]
+    Vc = cfg["V"]
+    Cc = streamgen_ceil_log2(Vc)
+    Dc = 2 * Cc
+    batch = args.batch or BATCH4
+    print("bench: drawing clusters64x2048_churn", file=sys.stderr, flush=True)
+    phases = clusters_phases_device(np, torch, streamgen, cfg)
+    nr = len(phases) - 1
+    round_len = [int(p.shape[0]) for p in phases[1:]]
+    mode = cupk.SCATTER_STAGED if args.mode == "staged" else cupk.SCATTER_ATOMIC
+    print("bench: timing main path", file=sys.stderr, flush=True)
+    dt, total, ctr, tuned = run_clusters(cupk, torch, phases, cfg, args.steps, args.warmup, batch,
+                                         mode, tune=not args.no_tune)
+    value = total / dt
+    kname = "k_tile_scatter" if args.mode == "staged" else "k_scatter_atomic"
+    launches = max(1, ctr["timed_launches"])
+    avg_ms = ctr["scatter_ms"] / launches
+    upd_per_launch = ctr["timed_updates"] / launches
+    prof = profile_entry(kname, cfg["name"])
+    if args.mode == "staged":
+        buckets = ctr["timed_buckets"] / launches
+        comp = 8 * upd_per_launch + 32 * buckets
+        achieved = comp / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": prof.get("hbm_bytes_per_launch") if prof else None,
+                "kernel": kname, "kernel_avg_ms": round(avg_ms, 5),
+                "basis": "compulsory bytes per launch: 8 B per update + 32 B (16 B read + "
+                         "16 B written) per bucket the launch changed in HBM, counted by the "
+                         "kernel on the timed launches",
+                "compulsory_bytes_per_launch": round(comp),
+                "compulsory_bytes_per_update": round(comp / max(1.0, upd_per_launch), 1),
+                "buckets_changed_per_launch": round(buckets),
+                "updates_per_launch": round(upd_per_launch, 1),
+                "timed_launches": ctr["timed_launches"], "timed_every": TIME_EVERY,
+                "bin_avg_ms": round(ctr["bin_ms"] / launches, 5),
+                "algorithmic_GBs": round(algorithmic_bytes_per_update(Cc) * upd_per_launch /
+                                         (avg_ms * 1e-3) / 1e9, 1),
+                "algorithmic_basis": f"8 + 64*C = {algorithmic_bytes_per_update(Cc)} B per "
+                                     "update (every bucket update a 16 B read + write); not a "
+                                     "roofline fraction"}
+        if prof:
+            roof["traffic_frac"] = round(prof["hbm_bytes_per_launch"] / (avg_ms * 1e-3) /
+                                         (HBM_PEAK_GBS * 1e9), 4)
+            if prof.get("valu_insts_per_launch"):
+                vi = prof["valu_insts_per_launch"]
+                roof["valu"] = {"insts_per_launch": vi,
+                                "issue_frac": round(vi / (avg_ms * 1e-3) / VALU_PEAK_WAVE_INSTS,
+                                                    4),
+                                "peak": "256 CU x 4 SIMD x 2.4 GHz = 2.46e12 wave "
+                                        "instructions/s"}
+    else:
+        bpu = algorithmic_bytes_per_update(Cc)
+        achieved = bpu * upd_per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": prof.get("hbm_bytes_per_launch") if prof else None,
+                "kernel": kname, "kernel_avg_ms": round(avg_ms, 5),
+                "basis": f"8 + 64*C = {bpu} B per update (each bucket a device atomic XOR)"}
+    timed_rounds = [i % nr for i in range(args.steps)]
+    out = {
+        "metric": "edge updates/sec + % HBM roofline; p50/p99 connectivity-query latency",
+        "value": round(value, 1), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"clusters64x2048_churn: V=2^20, 64 clusters G(2048,0.5) + sparse "
+                               f"G(917504, 2n), 128 bridges toggled 100 per 1e5 updates; one "
+                               f"step = one churn round (insert then delete the "
+                               f"{(round_len[0] - 1) // 2 // 1000 * 1000}+ non-forest cluster "
+                               f"edges, ~{round_len[0] / 1e6:.0f}M updates) in {batch}-update "
+                               f"device batches; timed rounds {timed_rounds} (a fresh context "
+                               f"after round {nr - 1}); setup phase untimed",
+                   "V": Vc, "C": Cc, "D": Dc, "batch": batch, "scatter": args.mode,
+                   "updates_timed": total, "parallelism": "single GPU"},
+        "roofline": roof,
+        "counters": {k: (round(val, 3) if isinstance(val, float) else val)
+                     for k, val in ctr.items()},
+    }
+    if tuned:
+        out["config"]["tuned"] = {k: tuned[k] for k in ("tile_vertices", "lds_rows",
+                                                        "chunk_records", "batch_target")}
+    if not args.no_plain and args.mode == "staged":
+        print("bench: timing plain path", file=sys.stderr, flush=True)
+        psteps = max(1, min(args.steps, args.plain_steps))
+        pdt, ptot, pctr, _ = run_clusters(cupk, torch, phases, cfg, psteps, 0, batch,
+                                          cupk.SCATTER_ATOMIC, tune=False, label="plain")
+        pl = max(1, pctr["timed_launches"])
+        pavg = pctr["scatter_ms"] / pl
+        bpu = algorithmic_bytes_per_update(Cc)
+        pach = bpu * (pctr["timed_updates"] / pl) / (pavg * 1e-3) / 1e9
+        out["plain"] = {"value": round(ptot / pdt, 1), "unit": "updates/s", "steps": psteps,
+                        "ms_per_step": round(pdt * 1e3 / psteps, 3),
+                        "kernel": "k_scatter_atomic", "kernel_avg_ms": round(pavg, 5),
+                        "achieved_GBs": round(pach, 1), "frac": round(pach / HBM_PEAK_GBS, 4),
+                        "basis": f"8 + 64*C = {bpu} B per update",
+                        "host_flags_ms": round(pctr["host_flags_ms"], 1),
+                        "host_rounds_ms": round(pctr["host_rounds_ms"], 1)}
+    if not args.no_cpu:
+        print("bench: timing CPU oracle", file=sys.stderr, flush=True)
+        sample = np.concatenate([phases[0].cpu().numpy(), phases[1][:60_000_000].cpu().numpy()]
+                                ).view(np.uint64)
+        del phases
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline_clusters(np, streamgen, sample, cfg)
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=11,
+                    help="churn rounds timed (headline); batches for --workload er16384")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=0, help="updates per device batch (headline)")
+    ap.add_argument("--plain-steps", type=int, default=2,
+                    help="churn rounds timed with the plain atomic kernel")
+    ap.add_argument("--no-tune", action="store_true", help="headline: keep the default geometry")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel run")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served run")
+    ap.add_argument("--no-static", action="store_true",
+                    help="skip the static-components run on the final sketch")
+    ap.add_argument("--mode", default="staged", choices=["staged", "atomic"])
+    ap.add_argument("--graph", type=int, default=0,
+                    help="1: replay each batch's device work as captured HIP graphs")
+    ap.add_argument("--workload", default="clusters",
+                    choices=["clusters", "er16384", "rmat17", "er65536_served", "fixed_forest",
+                             "exact_sweep", "levels"],
+                    help="clusters: the benchmark line; the others print extra full-size "
+                         "measurements of the other workload recipes")
+    ap.add_argument("--calib", action="store_true",
+                    help="first run a plain 256 MiB device copy (4 times) as the reference "
+                         "for HBM byte counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2509_14433_amd as cupk
+    import streamgen
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.calib:
+        src = torch.ones(CALIB_BYTES // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload == "clusters":
+        clusters_main(args, cupk, np, torch, streamgen)
+    elif args.workload == "er16384":
+        er16384_leg(args, cupk, np, torch, streamgen)
+    else:
+        workload_leg(args, cupk, torch, np, streamgen)
 
 
 if __name__ == "__main__":

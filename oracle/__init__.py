@@ -32,7 +32,7 @@ def build(force: bool = True) -> str:
     """Compile ``oracle.c`` with gcc into ``liboracle.so`` (in place)."""
     if force or not os.path.exists(_BUILT):
         tmp = _BUILT + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-shared", "-fPIC",
                                "-o", tmp, _SRC])
         os.replace(tmp, _BUILT)
     return _BUILT
@@ -61,6 +61,9 @@ def lib():
         L.orc_gamma.restype = p; L.orc_gamma.argtypes = [p]
         L.orc_toggle.restype = None; L.orc_toggle.argtypes = [p, u32, u32]
         L.orc_apply.restype = None; L.orc_apply.argtypes = [p, p, p, sz]
+        if hasattr(L, "orc_apply_threads"):
+            L.orc_apply_threads.restype = ctypes.c_int
+            L.orc_apply_threads.argtypes = [p, p, p, sz, ctypes.c_int]
         L.orc_vertex_from_stream.restype = None
         L.orc_vertex_from_stream.argtypes = [u32, u32, u32, u64, u32, p, p, sz, p, p]
         L.orc_set_sketch.restype = None; L.orc_set_sketch.argtypes = [p, p, sz, p, p]
@@ -126,6 +129,15 @@ class Sketch:
         v = np.ascontiguousarray(v, dtype=np.uint32)
         assert u.shape == v.shape
         lib().orc_apply(self._h, _ptr(u), _ptr(v), u.shape[0])
+
+    def apply_threads(self, u, v, nthreads: int) -> int:
+        """``apply`` with the vertex range split over host threads (each
+        thread writes only the buckets of its own vertices, in stream order:
+        the same result).  Returns the number of threads used."""
+        u = np.ascontiguousarray(u, dtype=np.uint32)
+        v = np.ascontiguousarray(v, dtype=np.uint32)
+        assert u.shape == v.shape
+        return lib().orc_apply_threads(self._h, _ptr(u), _ptr(v), u.shape[0], int(nthreads))
 
     def toggle(self, a: int, b: int):
         lib().orc_toggle(self._h, a, b)

@@ -168,6 +168,56 @@ void orc_apply(orc_sketch *s, const uint32_t *u, const uint32_t *v, size_t n)
     for (size_t i = 0; i < n; i++) orc_toggle(s, u[i], v[i]);
 }
 
+/* orc_apply on several host threads (the all-core CPU baseline): thread t of
+ * T owns vertices [t*V/T, (t+1)*V/T) and, scanning the whole stream in
+ * order, applies the bucket writes of the endpoints it owns.  Every bucket
+ * has one writer and sees its updates in stream order, so the result is the
+ * one orc_apply gives.  Returns the number of threads used (1 when built
+ * without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_apply_threads(orc_sketch *s, const uint32_t *u, const uint32_t *v, size_t n,
+                      int nthreads)
+{
+    int used = 1;
+    if (nthreads < 1) nthreads = 1;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        int T = 1, t = 0;
+#ifdef _OPENMP
+        T = omp_get_num_threads();
+        t = omp_get_thread_num();
+        if (t == 0) used = T;
+#endif
+        const uint32_t lo = (uint32_t)((uint64_t)s->V * t / T);
+        const uint32_t hi = (uint32_t)((uint64_t)s->V * (t + 1) / T);
+        for (size_t i = 0; i < n; i++) {
+            const uint32_t a = u[i], b = v[i];
+            const int own_a = a >= lo && a < hi, own_b = b >= lo && b < hi;
+            if (!own_a && !own_b) continue;
+            const uint64_t x = orc_edge_index(s->V, a, b);
+            for (uint32_t c = 0; c < s->C; c++) {
+                const uint64_t h = orc_mix(x ^ s->seeds[c]);
+                const uint32_t d = orc_depth_of_hash(h, s->D);
+                if (own_a) {
+                    const size_t ia = ((size_t)a * s->C + c) * s->D + d;
+                    s->alpha[ia] ^= x;
+                    s->gamma[ia] ^= h;
+                }
+                if (own_b) {
+                    const size_t ib = ((size_t)b * s->C + c) * s->D + d;
+                    s->alpha[ib] ^= x;
+                    s->gamma[ib] ^= h;
+                }
+            }
+        }
+    }
+    return used;
+}
+
 /* Sketch of one vertex w computed from the stream alone: apply only the
  * updates that touch w.  Output is C*D alpha and gamma words in canonical
  * order.  Used to check single vertices of streams too long to replay in

@@ -557,3 +557,18 @@ def test_static_components_match_bfs(orc, V, p, seed):
     assert labels.tolist() == truth.tolist()
     orc.check_spanning_forest(V, edges, set(zip(fu.tolist(), fv.tolist())), truth)
     assert rounds <= math.ceil(math.log2(V)) + 1
+
+
+def test_threaded_apply_equals_plain_apply(orc):
+    # The all-core baseline (vertex ranges per thread) gives the sketch of the
+    # one-thread replay bit for bit, for any thread count.
+    V, C, D, S = 777, 10, 20, 0x5EEDC0DE
+    u, v, d = _small_stream(V, 0.05, 0.4, 23)
+    ref = orc.Sketch(V, C, D, S)
+    ref.apply(u, v)
+    for t in (1, 2, 3, 8):
+        sk = orc.Sketch(V, C, D, S)
+        used = sk.apply_threads(u, v, t)
+        assert 1 <= used <= t
+        assert np.array_equal(sk.alpha, ref.alpha) and np.array_equal(sk.gamma, ref.gamma)
+        assert sk.digest() == ref.digest()
