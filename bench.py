@@ -588,36 +588,52 @@ def _ctr_delta(c1, c0):
 
 
 def run_clusters(cupk, torch, phases, cfg, steps, warmup, batch, mode, tune,
-                 time_kernels=TIME_EVERY, label="main"):
-    """Time `steps` churn rounds (see the module docstring).  Returns
-    (seconds, updates, counters of the timed rounds, tune result)."""
+                 time_kernels=TIME_EVERY, label="main", tune_sample=1 << 24):
+    """Time `steps` churn rounds (see the module docstring).  With `tune`,
+    a warm-up context (setup phase, then 1M-update batches of round 0 so
+    that it has measured its host time per batch) runs the autotuner on a
+    sample of round 0, and the timed contexts use the tuned geometry and
+    batch target instead of `batch`.  Returns (seconds, updates, counters
+    of the timed rounds, tune result, batch used)."""
     Vc = cfg["V"]
     Cc = streamgen_ceil_log2(Vc)
     nr = len(phases) - 1
-    sample = phases[1][: min(phases[1].shape[0], batch)].contiguous()
     tuned = {}
+    geo = {}
 
-    def new_ctx():
-        ctx = cupk.Context(Vc, Cc, 2 * Cc, cfg["S"], scatter_mode=mode, max_batch=batch,
-                           time_kernels=time_kernels)
-        if tune:
-            tuned.update(ctx.autotune(sample))
-        _apply_phase(ctx, phases[0], batch)
+    def new_ctx(bsz):
+        ctx = cupk.Context(Vc, Cc, 2 * Cc, cfg["S"], scatter_mode=mode, max_batch=bsz,
+                           time_kernels=time_kernels, **geo)
+        _apply_phase(ctx, phases[0], bsz)
         ctx.sync()
         return ctx
 
-    if warmup:
-        w = new_ctx()
+    if tune or warmup:
+        w = new_ctx(BATCH4)
+        start = 0
+        if tune:
+            # host history at 1M batches, then the tuner on a sample of round 0
+            start = min(phases[1].shape[0], 8 * BATCH4)
+            _apply_phase(w, phases[1][:start], BATCH4)
+            w.sync()
+            sample = phases[1][start:start + min(tune_sample, phases[1].shape[0] - start)]
+            tuned = w.autotune(sample.contiguous())
+            geo = {"tile_vertices": tuned["tile_vertices"], "lds_rows": tuned["lds_rows"],
+                   "chunk_records": tuned["chunk_records"]}
+            batch = tuned["batch_target"]
+            print(f"bench: {label} tuned {geo} batch {batch} (host "
+                  f"{tuned['host_ms_per_batch']:.2f} ms per batch)", file=sys.stderr, flush=True)
         for i in range(warmup):
             if i and i % nr == 0:
                 w.close()
-                w = new_ctx()
-            _apply_phase(w, phases[1 + i % nr], batch)
+                w = new_ctx(batch)
+            ph = phases[1 + i % nr]
+            _apply_phase(w, ph[start:] if i == 0 else ph, batch)
             w.sync()
             print(f"bench: {label} warmup round {i % nr}", file=sys.stderr, flush=True)
         w.close()
     n_ctx = max(1, (steps + nr - 1) // nr)
-    ctxs = [new_ctx() for _ in range(n_ctx)]
+    ctxs = [new_ctx(batch) for _ in range(n_ctx)]
     c0 = [c.counters() for c in ctxs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -634,12 +650,12 @@ def run_clusters(cupk, torch, phases, cfg, steps, warmup, batch, mode, tune,
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctr = {}
-    for c, a in zip(ctxs, c0):
-        for k, val in _ctr_delta(c.counters(), a).items():
+    for c, a0 in zip(ctxs, c0):
+        for k, val in _ctr_delta(c.counters(), a0).items():
             ctr[k] = ctr.get(k, 0) + val
     for c in ctxs:
         c.close()
-    return dt, total, ctr, tuned
+    return dt, total, ctr, tuned, batch
 
 
 def streamgen_ceil_log2(V):
@@ -664,7 +680,7 @@ def host_cpu():
 def cpu_baseline_clusters(np, streamgen, phases_host_sample, cfg, budget_s=12.0):
     """The oracle's sketch update (hash + XOR into both endpoints, no forest)
     on a bounded sample of the same stream: every host core (each thread
-    owns a vertex range), then one thread."""
+    owns 256-vertex blocks dealt round-robin), then one thread."""
     import oracle
     Vc = cfg["V"]
     Cc = streamgen_ceil_log2(Vc)
@@ -690,7 +706,8 @@ def cpu_baseline_clusters(np, streamgen, phases_host_sample, cfg, budget_s=12.0)
             "cpu_model": model, "nproc": nthreads,
             "sample": f"the first {a['updates']} updates of the same stream (setup phase, then "
                       f"churn round 0): the oracle's sketch update (column hashes + XOR into "
-                      f"both endpoints' buckets), one thread per vertex range on every core; "
+                      f"both endpoints' buckets) on every core, each thread owning 256-vertex "
+                      f"blocks dealt round-robin; "
                       f"forest work and stream generation excluded",
             "one_thread": out["one_thread"]}
 
@@ -707,8 +724,8 @@ def clusters_main(args, cupk, np, torch, streamgen):
     round_len = [int(p.shape[0]) for p in phases[1:]]
     mode = cupk.SCATTER_STAGED if args.mode == "staged" else cupk.SCATTER_ATOMIC
     print("bench: timing main path", file=sys.stderr, flush=True)
-    dt, total, ctr, tuned = run_clusters(cupk, torch, phases, cfg, args.steps, args.warmup, batch,
-                                         mode, tune=not args.no_tune)
+    dt, total, ctr, tuned, batch = run_clusters(cupk, torch, phases, cfg, args.steps, args.warmup,
+                                                batch, mode, tune=not args.no_tune)
     value = total / dt
     kname = "k_tile_scatter" if args.mode == "staged" else "k_scatter_atomic"
     launches = max(1, ctr["timed_launches"])
@@ -767,8 +784,11 @@ def clusters_main(args, cupk, np, torch, streamgen):
                                f"step = one churn round (insert then delete the "
                                f"{(round_len[0] - 1) // 2 // 1000 * 1000}+ non-forest cluster "
                                f"edges, ~{round_len[0] / 1e6:.0f}M updates) in {batch}-update "
-                               f"device batches; timed rounds {timed_rounds} (a fresh context "
-                               f"after round {nr - 1}); setup phase untimed",
+                               f"device batches ("
+                               + ("batched form: geometry and batch size from the autotuner" if
+                                  tuned else "fixed batches") +
+                               f"); timed rounds {timed_rounds} (a fresh context after round "
+                               f"{nr - 1}); setup phase untimed",
                    "V": Vc, "C": Cc, "D": Dc, "batch": batch, "scatter": args.mode,
                    "updates_timed": total, "parallelism": "single GPU"},
         "roofline": roof,
@@ -777,17 +797,33 @@ def clusters_main(args, cupk, np, torch, streamgen):
     }
     if tuned:
         out["config"]["tuned"] = {k: tuned[k] for k in ("tile_vertices", "lds_rows",
-                                                        "chunk_records", "batch_target")}
+                                                        "chunk_records", "batch_target",
+                                                        "host_ms_per_batch", "batch_sizes",
+                                                        "batch_ms")}
     if not args.no_plain and args.mode == "staged":
-        print("bench: timing plain path", file=sys.stderr, flush=True)
         psteps = max(1, min(args.steps, args.plain_steps))
-        pdt, ptot, pctr, _ = run_clusters(cupk, torch, phases, cfg, psteps, 0, batch,
-                                          cupk.SCATTER_ATOMIC, tune=False, label="plain")
+        print("bench: timing staged kernel in fixed 1M batches", file=sys.stderr, flush=True)
+        sdt, stot, sctr, _, _ = run_clusters(cupk, torch, phases, cfg, psteps, 0, BATCH4, mode,
+                                             tune=False, label="staged_1M")
+        sl = max(1, sctr["timed_launches"])
+        savg = sctr["scatter_ms"] / sl
+        scomp = (8 * sctr["timed_updates"] + 32 * sctr["timed_buckets"]) / sl
+        out["staged_1M"] = {"value": round(stot / sdt, 1), "unit": "updates/s", "steps": psteps,
+                            "ms_per_step": round(sdt * 1e3 / psteps, 3), "batch": BATCH4,
+                            "kernel_avg_ms": round(savg, 5),
+                            "compulsory_bytes_per_launch": round(scomp),
+                            "frac": round(scomp / (savg * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                            "host_flags_ms": round(sctr["host_flags_ms"], 1),
+                            "host_rounds_ms": round(sctr["host_rounds_ms"], 1)}
+        print("bench: timing plain path", file=sys.stderr, flush=True)
+        pdt, ptot, pctr, _, _ = run_clusters(cupk, torch, phases, cfg, psteps, 0, BATCH4,
+                                             cupk.SCATTER_ATOMIC, tune=False, label="plain")
         pl = max(1, pctr["timed_launches"])
         pavg = pctr["scatter_ms"] / pl
         bpu = algorithmic_bytes_per_update(Cc)
         pach = bpu * (pctr["timed_updates"] / pl) / (pavg * 1e-3) / 1e9
         out["plain"] = {"value": round(ptot / pdt, 1), "unit": "updates/s", "steps": psteps,
+                        "batch": BATCH4,
                         "ms_per_step": round(pdt * 1e3 / psteps, 3),
                         "kernel": "k_scatter_atomic", "kernel_avg_ms": round(pavg, 5),
                         "achieved_GBs": round(pach, 1), "frac": round(pach / HBM_PEAK_GBS, 4),

@@ -388,8 +388,14 @@ int cupk_static_components(cupk_ctx *ctx, uint32_t *labels, uint32_t *eu, uint32
 
 /* ---- autotuner ------------------------------------------------------------
  * Picks the staged scatter's tile geometry (vertices per LDS tile, depth
- * rows in LDS, records per work item) by timing every candidate on a sample
- * batch, and derives a batch-size schedule.  Each candidate applies the
+ * rows in LDS, records per work item) by timing every candidate's device
+ * work (classification, tile scan, binning, scatter) on a sample batch, and
+ * derives a batch-size schedule: the device time of prefixes n/128 .. n of
+ * the sample plus the host time per batch this context has measured so far
+ * (flag walk and replacement rounds, nearly independent of the batch size);
+ * batch_target is the smallest prefix whose whole-path rate reaches 80% of
+ * the best one.  The serving loop then uses batch_target as its batch size
+ * unless cupk_serve_opts.max_batch is set.  Each candidate applies the
  * sample an even number of times, so the XOR toggles cancel and the sketch
  * is left exactly as it was; the forest is not touched.
  * d_sample: n packed updates in device memory (format of
@@ -403,9 +409,10 @@ typedef struct {
     double best_ms;            /* bin + scatter time of the sample, chosen     */
     double before_ms;          /* same with the setting in force before        */
     uint32_t batch_target;     /* smallest timed batch reaching 80% of the
-                                  best throughput (batch-size schedule)       */
-    double batch_ms[8];        /* time of prefixes n/128, n/64, ... , n        */
+                                  best whole-path rate (batch-size schedule)  */
+    double batch_ms[8];        /* device time of prefixes n/128, ... , n       */
     uint32_t batch_sizes[8];
+    double host_ms_per_batch;  /* host time per batch the schedule assumed     */
 } cupk_tune_result;
 
 int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_result *out);
@@ -419,7 +426,9 @@ int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_r
  * the GPU join the next batch. */
 
 typedef struct {
-    uint32_t max_batch;        /* updates per device batch (0 = 1<<20)         */
+    uint32_t max_batch;        /* updates per device batch (0 = the autotuned
+                                  batch target if cupk_autotune ran, else
+                                  1<<20)                                       */
     uint32_t nonblocking;      /* 1: refuse with CUPK_EBUSY instead of waiting */
     size_t mem_budget_bytes;   /* host staging for pending updates, 8 B each
                                   (0 = 64 MiB); admission waits for room      */

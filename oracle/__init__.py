@@ -72,6 +72,9 @@ def lib():
         L.orc_sample_col.restype = ctypes.c_int
         L.orc_sample_col.argtypes = [u32, u32, u32, u64, u32, p, p, p, p]
         L.orc_digest.restype = u64; L.orc_digest.argtypes = [p]
+        if hasattr(L, "orc_uf_components"):
+            L.orc_uf_components.restype = u64
+            L.orc_uf_components.argtypes = [u32, p, p, sz, p]
         L.orc_digest_arrays.restype = u64
         L.orc_digest_arrays.argtypes = [u32, u32, u64, u32, u32, p, p]
         _lib = L
@@ -194,6 +197,18 @@ def sample_col(V, C, D, S, c, alpha, gamma):
     return st, ou.value, ov.value
 
 
+def uf_components(V, u, v):
+    """(number of components, label array: smallest vertex of each vertex's
+    component) of the graph with edge list (u, v), by union-find in C."""
+    u = np.ascontiguousarray(u, dtype=np.uint32)
+    v = np.ascontiguousarray(v, dtype=np.uint32)
+    lab = np.zeros(V, np.uint32)
+    k = lib().orc_uf_components(V, _ptr(u), _ptr(v), u.shape[0], _ptr(lab))
+    if k == 0 and V > 0:
+        raise MemoryError("union-find allocation failed")
+    return int(k), lab
+
+
 def vertex_from_stream(V, C, D, S, w, u, v):
     """Sketch of vertex w from the updates that touch it (C x D arrays)."""
     u = np.ascontiguousarray(u, dtype=np.uint32)
@@ -221,6 +236,6 @@ from .levels import LevelsReplay  # noqa: E402
 __all__ = [
     "OK", "EMPTY", "FAILED", "build", "lib", "mix", "seed", "hash_c",
     "depth_of_hash", "edge_index", "Sketch", "sample", "sample_col", "vertex_from_stream",
-    "digest_arrays", "ForestReplay", "components_truth", "check_spanning_forest",
+    "digest_arrays", "uf_components", "ForestReplay", "components_truth", "check_spanning_forest",
     "static_components", "LevelsReplay",
 ]

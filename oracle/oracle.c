@@ -168,12 +168,14 @@ void orc_apply(orc_sketch *s, const uint32_t *u, const uint32_t *v, size_t n)
     for (size_t i = 0; i < n; i++) orc_toggle(s, u[i], v[i]);
 }
 
-/* orc_apply on several host threads (the all-core CPU baseline): thread t of
- * T owns vertices [t*V/T, (t+1)*V/T) and, scanning the whole stream in
- * order, applies the bucket writes of the endpoints it owns.  Every bucket
- * has one writer and sees its updates in stream order, so the result is the
- * one orc_apply gives.  Returns the number of threads used (1 when built
- * without OpenMP). */
+/* orc_apply on several host threads (the all-core CPU baseline): the
+ * vertices are dealt to the T threads in blocks of 256 consecutive ids,
+ * round-robin (thread t owns w with (w / 256) mod T == t, so that streams
+ * whose busy vertices have nearby ids still spread over all threads), and
+ * each thread, scanning the whole stream in order, applies the bucket
+ * writes of the endpoints it owns.  Every bucket has one writer and sees its
+ * updates in stream order, so the result is the one orc_apply gives.
+ * Returns the number of threads used (1 when built without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -192,11 +194,10 @@ int orc_apply_threads(orc_sketch *s, const uint32_t *u, const uint32_t *v, size_
         t = omp_get_thread_num();
         if (t == 0) used = T;
 #endif
-        const uint32_t lo = (uint32_t)((uint64_t)s->V * t / T);
-        const uint32_t hi = (uint32_t)((uint64_t)s->V * (t + 1) / T);
         for (size_t i = 0; i < n; i++) {
             const uint32_t a = u[i], b = v[i];
-            const int own_a = a >= lo && a < hi, own_b = b >= lo && b < hi;
+            const int own_a = (int)((a >> 8) % (uint32_t)T) == t;
+            const int own_b = (int)((b >> 8) % (uint32_t)T) == t;
             if (!own_a && !own_b) continue;
             const uint64_t x = orc_edge_index(s->V, a, b);
             for (uint32_t c = 0; c < s->C; c++) {
@@ -311,6 +312,40 @@ int orc_sample_col(uint32_t V, uint32_t C, uint32_t D, uint64_t S, uint32_t c,
         return ORC_OK;
     }
     return nonzero ? ORC_FAILED : ORC_EMPTY;
+}
+
+/* ---- connectivity truth ------------------------------------------------ */
+
+static uint32_t uf_root(uint32_t *p, uint32_t x)
+{
+    while (p[x] != x) {
+        p[x] = p[p[x]]; /* path halving */
+        x = p[x];
+    }
+    return x;
+}
+
+/* Connected components of the graph on V vertices with edges (u[i], v[i]):
+ * label[w] = smallest vertex of w's component.  Union-find, for graphs too
+ * large for the breadth-first search of the Python oracle.  Returns the
+ * number of components, or 0 when out of memory. */
+uint64_t orc_uf_components(uint32_t V, const uint32_t *u, const uint32_t *v, size_t n,
+                           uint32_t *label)
+{
+    uint32_t *p = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)V);
+    if (!p) return 0;
+    for (uint32_t w = 0; w < V; w++) p[w] = w;
+    for (size_t i = 0; i < n; i++) {
+        const uint32_t a = uf_root(p, u[i]), b = uf_root(p, v[i]);
+        if (a != b) p[a < b ? b : a] = a < b ? a : b; /* the smaller root survives */
+    }
+    uint64_t k = 0;
+    for (uint32_t w = 0; w < V; w++) {
+        label[w] = uf_root(p, w);
+        if (label[w] == w) k++;
+    }
+    free(p);
+    return k;
 }
 
 /* Order-independent 64-bit digest of a whole sketch:

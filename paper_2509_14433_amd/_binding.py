@@ -94,7 +94,7 @@ class cupk_tune_result(ctypes.Structure):
                 ("chunk_records", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
                 ("best_ms", ctypes.c_double), ("before_ms", ctypes.c_double),
                 ("batch_target", ctypes.c_uint32), ("batch_ms", ctypes.c_double * 8),
-                ("batch_sizes", ctypes.c_uint32 * 8)]
+                ("batch_sizes", ctypes.c_uint32 * 8), ("host_ms_per_batch", ctypes.c_double)]
 
 
 class cupk_static_info(ctypes.Structure):

@@ -850,6 +850,7 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
         sa.chunk = ctx->chunk;
         sa.items_cap = staged_params(ctx, grid_n).items_cap;
         sa.groups = 1;
+        if (ctx->ntiles > kScanOneBlockTiles) sa.sums = ctx->d_tsum.p;
     }
     uint32_t *rel = staged ? rel_ptr(ctx, grid_n) : nullptr;
     if (rel) {
@@ -1317,6 +1318,7 @@ void destroy(cupk_ctx *ctx)
     release(ctx->h_fpos);
     release(ctx->d_tcnt);
     release(ctx->d_toff);
+    release(ctx->d_tsum);
     release(ctx->d_tcur);
     release(ctx->d_trel);
     release(ctx->d_tgoff);
@@ -1364,6 +1366,7 @@ int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk)
         HIPCHK(grow(ctx->d_tcnt, ncnt));
         HIPCHK(grow(ctx->d_tgoff, ncnt));
         HIPCHK(grow(ctx->d_toff, ctx->ntiles + 1));
+        HIPCHK(grow(ctx->d_tsum, 2 * (size_t)tile_scan_chunks(ctx->ntiles) + 2));
         HIPCHK(grow(ctx->d_tcur, ctx->ntiles + 1));
         // the scan kernel re-zeroes the counts after every batch
         HIPCHK(launch_zero32(ctx->s, ctx->d_tcnt.p, ncnt));
@@ -1860,10 +1863,10 @@ static int time_scatter_once(cupk_ctx *ctx, const uint64_t *d, uint32_t n, hipEv
     if (rc != CUPK_OK) return rc;
     ctx->cur_desc.upd = d;
     ctx->cur_desc.n = n;
+    HIPCHK(hipEventRecord(e0, ctx->s));
     rc = enqueue_classify(ctx, ctx->s, n);
     ctx->hdr_seq++;  // published by the scan kernel (read after the sync below)
     if (rc != CUPK_OK) return rc;
-    HIPCHK(hipEventRecord(e0, ctx->s));
     rc = enqueue_bin(ctx, ctx->s, n);
     if (rc == CUPK_OK) rc = enqueue_tile(ctx, ctx->s, n, false);
     if (rc != CUPK_OK) return rc;
@@ -2076,7 +2079,16 @@ int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_r
                     }
                 }
         if (rc == CUPK_OK) rc = set_geometry(ctx, btv, brows, bchunk);
-        // batch-size schedule: throughput of prefixes n/128 .. n
+        // batch-size schedule: device time of prefixes n/128 .. n, plus the
+        // host time per batch (flag walk and replacement rounds, which cost
+        // about the same whatever the batch size) measured on this
+        // context's batches so far; the target is the smallest prefix whose
+        // whole-path rate reaches 80% of the best one
+        const double host_ms = ctx->ctr.batches
+                                   ? (ctx->ctr.host_flags_ms + ctx->ctr.host_rounds_ms) /
+                                         (double)ctx->ctr.batches
+                                   : 0.0;
+        out->host_ms_per_batch = host_ms;
         double best_rate = 0;
         for (int k = 0; k < 8 && rc == CUPK_OK; k++) {
             const uint32_t sz = std::max<uint32_t>(1, m >> (7 - k));
@@ -2084,15 +2096,17 @@ int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_r
             rc = time_scatter(ctx, d_sample, sz, 2, e0, e1, &ms);
             out->batch_sizes[k] = sz;
             out->batch_ms[k] = ms;
-            if (ms > 0) best_rate = std::max(best_rate, sz / ms);
+            if (ms + host_ms > 0) best_rate = std::max(best_rate, sz / (ms + host_ms));
         }
         if (rc == CUPK_OK) {
             out->batch_target = m;
             for (int k = 0; k < 8; k++)
-                if (out->batch_ms[k] > 0 && out->batch_sizes[k] / out->batch_ms[k] >= 0.8 * best_rate) {
+                if (out->batch_ms[k] + host_ms > 0 &&
+                    out->batch_sizes[k] / (out->batch_ms[k] + host_ms) >= 0.8 * best_rate) {
                     out->batch_target = out->batch_sizes[k];
                     break;
                 }
+            ctx->tuned_batch = out->batch_target;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -2118,6 +2132,8 @@ int cupk_serve_start(cupk_ctx *ctx, const cupk_serve_opts *opts)
         if (ctx->server) return ctx->invalid("serving loop already running");
         cupk_serve_opts o = {};
         if (opts) o = *opts;
+        // the autotuner's batch-size schedule, unless the caller sets one
+        if (o.max_batch == 0 && ctx->tuned_batch) o.max_batch = ctx->tuned_batch;
         HIPCHK(hipStreamSynchronize(ctx->s));
         const int dev = ctx->device;
         ctx->server.reset(new (std::nothrow) Server(

@@ -86,6 +86,7 @@ struct cupk_ctx {
     // staged scatter
     uint32_t tile_shift = 5, rows = 8, chunk = 4096, ntiles = 0, tile_grid = 0;
     cupk::DevBuf<uint32_t> d_tcnt, d_toff, d_tcur, d_items;
+    cupk::DevBuf<uint32_t> d_tsum;  // chunk totals of the multi-block tile scan
     cupk::DevBuf<uint32_t> d_trel;  // per (classify block, tile): start inside the tile's bin
     cupk::DevBuf<uint32_t> d_tgoff; // per (count copy, tile): where the copy's records start
     cupk::DevBuf<uint64_t> d_bins;
@@ -121,6 +122,7 @@ struct cupk_ctx {
     hipGraphExec_t gx_cls = nullptr, gx_bin = nullptr, gx_tile = nullptr, gx_all = nullptr;
     uint32_t graph_cap = 0;    // batch capacity the graphs were captured for
     size_t batch_cap = 0;      // updates per batch every batch buffer holds
+    uint32_t tuned_batch = 0;  // the autotuner's batch target (0: not tuned)
 
 
     int device = 0;

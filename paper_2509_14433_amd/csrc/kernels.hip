@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict
         hdr[HDR_SEQ] = seq;
         __hip_atomic_store(&hout[HDR_SEQ], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    if (!a.off) return;
+    if (!a.off || a.sums) return;  // no tile counts, or the multi-block kernels scan them
     const uint32_t ng = a.groups;  // count copies (1 or kCntGroups)
     if (err) {
         // rejected batch: leave the counts zeroed for the next one
@@ -230,6 +230,91 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict
     if (threadIdx.x == 0) {
         off[ntiles] = carry_r;
         *a.nitems = min(carry_i, items_cap);
+    }
+}
+
+// Multi-block tile scan (more than kScanOneBlockTiles tiles, one count
+// copy): block b covers tiles [b*kScanChunk, (b+1)*kScanChunk).
+// k_tile_sums writes each chunk's record total and work-item total;
+// k_tile_offsets adds the totals of the chunks before its own, scans its
+// chunk (kScanChunk / kScanThreads consecutive tiles per thread) into bin
+// offsets, fill cursors and work items, and zeroes the counts for the next
+// batch.  A rejected batch (header error) gets no work items.
+constexpr uint32_t kScanChunk = 4096;
+constexpr uint32_t kScanPer = kScanChunk / kScanThreads;
+static_assert(kScanPer * kScanThreads == kScanChunk, "whole tiles per thread");
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_sums(const uint32_t *__restrict__ cnt,
+                                                            uint32_t ntiles, uint32_t chunk,
+                                                            uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t sh[160];
+    const uint32_t t0 = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+    uint32_t c = 0, k = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kScanPer; j++) {
+        const uint32_t t = t0 + j;
+        const uint32_t x = t < ntiles ? cnt[t] : 0u;
+        c += x;
+        k += (x + chunk - 1) / chunk;
+    }
+    uint32_t tc, tk;
+    block_exscan<kScanThreads>(c, tc, sh);
+    block_exscan<kScanThreads>(k, tk, sh);
+    if (threadIdx.x == 0) {
+        sums[2 * blockIdx.x] = tc;
+        sums[2 * blockIdx.x + 1] = tk;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_offsets(uint32_t *__restrict__ cnt,
+                                                               uint32_t ntiles, ScanArgs a,
+                                                               const uint32_t *__restrict__ hdr)
+{
+    __shared__ uint32_t sh[160];
+    const bool err = hdr[HDR_ERR] != 0;
+    const uint32_t b = blockIdx.x;
+    // totals of the chunks before this one
+    uint32_t pc = 0, pk = 0;
+    for (uint32_t i = threadIdx.x; i < b; i += kScanThreads) {
+        pc += a.sums[2 * i];
+        pk += a.sums[2 * i + 1];
+    }
+    uint32_t carry_r, carry_i;
+    block_exscan<kScanThreads>(pc, carry_r, sh);
+    block_exscan<kScanThreads>(pk, carry_i, sh);
+    const uint32_t t0 = b * kScanChunk + threadIdx.x * kScanPer;
+    uint32_t c[kScanPer], k[kScanPer], lc = 0, lk = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kScanPer; j++) {
+        const uint32_t t = t0 + j;
+        c[j] = t < ntiles ? cnt[t] : 0u;
+        if (t < ntiles) cnt[t] = 0;  // ready for the next batch's counts
+        k[j] = err ? 0u : (c[j] + a.chunk - 1) / a.chunk;
+        lc += c[j];
+        lk += k[j];
+    }
+    uint32_t tot_c, tot_k;
+    const uint32_t ex_c = block_exscan<kScanThreads>(lc, tot_c, sh);
+    const uint32_t ex_k = block_exscan<kScanThreads>(lk, tot_k, sh);
+    uint32_t o = carry_r + ex_c, q = carry_i + ex_k;
+#pragma unroll
+    for (uint32_t j = 0; j < kScanPer; j++) {
+        const uint32_t t = t0 + j;
+        if (t < ntiles) {
+            a.off[t] = o;
+            a.cur[t] = o;
+            for (uint32_t i = 0; i < k[j]; i++, q++)
+                if (q < a.items_cap) {
+                    a.items[2 * q] = t;
+                    a.items[2 * q + 1] = i;
+                }
+        }
+        o += c[j];
+    }
+    if (b == gridDim.x - 1 && threadIdx.x == 0) {
+        a.off[ntiles] = carry_r + tot_c;
+        *a.nitems = err ? 0u : min(carry_i + tot_k, a.items_cap);
     }
 }
 
@@ -373,13 +458,24 @@ hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, u
     if (tile_rel && (!tile_cnt || ntiles > kRelMaxTiles || sa.groups != kCntGroups || !sa.goff))
         return hipErrorInvalidValue;
     if (!tile_rel && tile_cnt && sa.groups != 1) return hipErrorInvalidValue;
+    if (sa.sums && (tile_rel || sa.groups != 1 || ntiles <= kScanOneBlockTiles))
+        return hipErrorInvalidValue;
     k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(
         desc, dv, V, lbl, par, hdr, fupd, fpos, fcnt, tile_cnt, tile_shift, ntiles, tile_rel);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr, hout, fi);
+    e = hipGetLastError();
+    if (e != hipSuccess || !tile_cnt || !sa.sums) return e;
+    const uint32_t nch = tile_scan_chunks(ntiles);
+    k_tile_sums<<<nch, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa.chunk, sa.sums);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_tile_offsets<<<nch, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr);
     return hipGetLastError();
 }
+
+uint32_t tile_scan_chunks(uint32_t ntiles) { return (ntiles + kScanChunk - 1) / kScanChunk; }
 
 // Last block of a scatter kernel to finish: clear the header for the next
 // batch.  Every block used its read of ERR before taking its ticket, so the
@@ -849,6 +945,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
 
         // Fold the delta into HBM, walking buckets in HBM order
         // (vertex, d, c) so that consecutive lanes touch consecutive words.
+        // (Issuing several buckets' loads before their stores, to overlap
+        // the read-modify-writes, measured slower at V = 2^20.)
         const uint32_t nvt = min(TV, V - w0);
         const uint32_t per_v = rows * C;
         const uint32_t nb = nvt * per_v;

@@ -61,12 +61,19 @@ struct FlagInline {
 // counter).  goff (groups * ntiles words, may be null) receives where each
 // copy's records start in every tile's bin.
 constexpr uint32_t kCntGroups = 4;
+// sums (2 * tile_scan_chunks(ntiles) words, may be null): scratch of the
+// multi-block scan, used (and required) when ntiles > kScanOneBlockTiles:
+// the one-block kernel then only publishes the header and two multi-block
+// kernels scan the counts (one count copy only).
+constexpr uint32_t kScanOneBlockTiles = 4096;
 struct ScanArgs {
     uint32_t *off, *cur, *items, *nitems;
     uint32_t chunk, items_cap;
     uint32_t groups;
     uint32_t *goff;
+    uint32_t *sums;
 };
+uint32_t tile_scan_chunks(uint32_t ntiles);
 
 struct StagedParams {
     uint32_t tile_shift;   // vertices per tile = 1 << tile_shift

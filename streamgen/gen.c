@@ -66,7 +66,8 @@ static void bit_clr(uint64_t *bm, uint64_t k) { bm[k >> 6] &= ~(1ULL << (k & 63)
  * R-MAT stream with interleaved deletions, drawn in resumable pieces.
  * At each step, with probability del_prob (if any edge is live) a uniformly
  * random live edge is deleted; otherwise an R-MAT edge (quadrant
- * probabilities a, b, c, 1-a-b-c over logV levels) is drawn, canonicalised
+ * probabilities a, b, c, 1-a-b-c over logV levels, each level's quadrant
+ * from a 16-bit uniform, four levels per 64-bit draw) is drawn, canonicalised
  * to u < v and inserted; self loops and live pairs are re-drawn (after 64
  * failed R-MAT draws, uniform pairs are drawn instead).
  */
@@ -114,7 +115,9 @@ size_t sg_rmat_next(void *h, size_t n, double del_prob, double a, double b, doub
     rmat_t *g = (rmat_t *)h;
     rng_t *r = &g->r;
     const uint64_t V = g->V;
-    const double ab = a + b, abc = a + b + c;
+    /* quadrant thresholds on 16-bit uniforms: four levels per 64-bit draw */
+    const uint32_t ta = (uint32_t)(a * 65536.0 + 0.5), tab = (uint32_t)((a + b) * 65536.0 + 0.5);
+    const uint32_t tabc = (uint32_t)((a + b + c) * 65536.0 + 0.5);
     for (size_t i = 0; i < n; i++) {
         if (g->nlive > 0 && rng_unif(r) < del_prob) {
             const uint64_t j = rng_below(r, g->nlive);
@@ -133,10 +136,13 @@ size_t sg_rmat_next(void *h, size_t n, double del_prob, double a, double b, doub
             if (tries < 64) {
                 x = 0;
                 y = 0;
+                uint64_t bits = 0;
                 for (uint32_t l = 0; l < g->logV; l++) {
-                    const double q = rng_unif(r);
-                    const int bx = q >= ab;                       /* quadrants c, d */
-                    const int by = (q >= a && q < ab) || q >= abc; /* quadrants b, d */
+                    if ((l & 3) == 0) bits = rng_next(r);
+                    const uint32_t q = (uint32_t)(bits & 0xFFFF);
+                    bits >>= 16;
+                    const int bx = q >= tab;                         /* quadrants c, d */
+                    const int by = (q >= ta && q < tab) || q >= tabc; /* quadrants b, d */
                     x = (x << 1) | (uint64_t)bx;
                     y = (y << 1) | (uint64_t)by;
                 }

@@ -572,3 +572,19 @@ def test_threaded_apply_equals_plain_apply(orc):
         assert 1 <= used <= t
         assert np.array_equal(sk.alpha, ref.alpha) and np.array_equal(sk.gamma, ref.gamma)
         assert sk.digest() == ref.digest()
+
+
+def test_union_find_truth_equals_bfs(orc):
+    # The union-find connectivity truth (used for graphs too large for the
+    # BFS) gives the BFS partition, labelled by smallest member.
+    rng = np.random.default_rng(41)
+    for trial in range(20):
+        V = int(rng.integers(2, 400))
+        m = int(rng.integers(0, 2 * V))
+        a = rng.integers(0, V, m).astype(np.uint32)
+        b = rng.integers(0, V, m).astype(np.uint32)
+        keep = a != b
+        k, lab = orc.uf_components(V, a[keep], b[keep])
+        truth = orc.components_truth(V, a[keep], b[keep])
+        assert np.array_equal(lab.astype(np.int64), truth)
+        assert k == len(set(truth.tolist()))
