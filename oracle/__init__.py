@@ -72,6 +72,11 @@ def lib():
         L.orc_sample_col.restype = ctypes.c_int
         L.orc_sample_col.argtypes = [u32, u32, u32, u64, u32, p, p, p, p]
         L.orc_digest.restype = u64; L.orc_digest.argtypes = [p]
+        if hasattr(L, "orc_uf_new"):
+            L.orc_uf_new.restype = p; L.orc_uf_new.argtypes = [u32]
+            L.orc_uf_free.restype = None; L.orc_uf_free.argtypes = [p]
+            L.orc_uf_add.restype = u64; L.orc_uf_add.argtypes = [p, p, p, sz]
+            L.orc_uf_same.restype = ctypes.c_int; L.orc_uf_same.argtypes = [p, u32, u32]
         if hasattr(L, "orc_uf_components"):
             L.orc_uf_components.restype = u64
             L.orc_uf_components.argtypes = [u32, p, p, sz, p]
@@ -209,6 +214,30 @@ def uf_components(V, u, v):
     return int(k), lab
 
 
+class UnionFind:
+    """Connectivity truth along a growing edge set (union-find in C)."""
+
+    def __init__(self, V: int):
+        self._h = lib().orc_uf_new(V)
+        if not self._h:
+            raise MemoryError("union-find allocation failed")
+        self.n_components = V
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_uf_free(self._h)
+            self._h = None
+
+    def add(self, u, v) -> int:
+        u = np.ascontiguousarray(u, dtype=np.uint32)
+        v = np.ascontiguousarray(v, dtype=np.uint32)
+        self.n_components = int(lib().orc_uf_add(self._h, _ptr(u), _ptr(v), u.shape[0]))
+        return self.n_components
+
+    def same(self, a: int, b: int) -> bool:
+        return bool(lib().orc_uf_same(self._h, a, b))
+
+
 def vertex_from_stream(V, C, D, S, w, u, v):
     """Sketch of vertex w from the updates that touch it (C x D arrays)."""
     u = np.ascontiguousarray(u, dtype=np.uint32)
@@ -236,6 +265,6 @@ from .levels import LevelsReplay  # noqa: E402
 __all__ = [
     "OK", "EMPTY", "FAILED", "build", "lib", "mix", "seed", "hash_c",
     "depth_of_hash", "edge_index", "Sketch", "sample", "sample_col", "vertex_from_stream",
-    "digest_arrays", "uf_components", "ForestReplay", "components_truth", "check_spanning_forest",
+    "digest_arrays", "uf_components", "UnionFind", "ForestReplay", "components_truth", "check_spanning_forest",
     "static_components", "LevelsReplay",
 ]

@@ -69,6 +69,7 @@ class ForestReplay:
         self.adj = [set() for _ in range(self.V)]
         self.mark = set()          # vertices whose tree is dirty
         self.uf = _UF(self.V)
+        self._stale = False
         self.n_links = 0
         self.n_cuts = 0
         self.n_rounds = 0
@@ -83,20 +84,30 @@ class ForestReplay:
                 if a < b:
                     self.uf.union(a, b)
 
+    def _uf_now(self):
+        # cuts only mark the union-find stale; it is rebuilt once, when the
+        # next connectivity question comes (same answers, one rebuild per
+        # run of cuts instead of one per cut)
+        if self._stale:
+            self._rebuild_uf()
+            self._stale = False
+        return self.uf
+
     def connected(self, a, b):
-        return self.uf.find(a) == self.uf.find(b)
+        uf = self._uf_now()
+        return uf.find(a) == uf.find(b)
 
     def _link(self, a, b):
         assert not self.connected(a, b)
         self.adj[a].add(b)
         self.adj[b].add(a)
-        self.uf.union(a, b)
+        self._uf_now().union(a, b)
         self.n_links += 1
 
     def _cut(self, a, b):
         self.adj[a].discard(b)
         self.adj[b].discard(a)
-        self._rebuild_uf()
+        self._stale = True
         self.n_cuts += 1
 
     def tree_of(self, w):
@@ -111,9 +122,10 @@ class ForestReplay:
         return seen
 
     def labels(self):
+        uf = self._uf_now()
         lab = np.empty(self.V, np.int64)
         for w in range(self.V):
-            lab[w] = self.uf.find(w)
+            lab[w] = uf.find(w)
         return lab
 
     def forest_edges(self):

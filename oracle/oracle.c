@@ -348,6 +348,53 @@ uint64_t orc_uf_components(uint32_t V, const uint32_t *u, const uint32_t *v, siz
     return k;
 }
 
+/* Incremental union-find for connectivity truth along a growing edge set. */
+typedef struct {
+    uint32_t V;
+    uint32_t *p;
+    uint64_t n_comp;
+} orc_uf;
+
+orc_uf *orc_uf_new(uint32_t V)
+{
+    orc_uf *h = (orc_uf *)calloc(1, sizeof(orc_uf));
+    if (!h) return NULL;
+    h->p = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)V);
+    if (!h->p) {
+        free(h);
+        return NULL;
+    }
+    for (uint32_t w = 0; w < V; w++) h->p[w] = w;
+    h->V = V;
+    h->n_comp = V;
+    return h;
+}
+
+void orc_uf_free(orc_uf *h)
+{
+    if (!h) return;
+    free(h->p);
+    free(h);
+}
+
+/* Add edges (u[i], v[i]); returns the number of components after them. */
+uint64_t orc_uf_add(orc_uf *h, const uint32_t *u, const uint32_t *v, size_t n)
+{
+    for (size_t i = 0; i < n; i++) {
+        const uint32_t a = uf_root(h->p, u[i]), b = uf_root(h->p, v[i]);
+        if (a != b) {
+            h->p[a < b ? b : a] = a < b ? a : b;
+            h->n_comp--;
+        }
+    }
+    return h->n_comp;
+}
+
+int orc_uf_same(orc_uf *h, uint32_t a, uint32_t b)
+{
+    return uf_root(h->p, a) == uf_root(h->p, b);
+}
+
 /* Order-independent 64-bit digest of a whole sketch:
  *   sum over (w,c,d) of mix(alpha ^ rotl(gamma,32) ^ mix(((w*C+c)*D+d) ^ S))
  * modulo 2^64. */

@@ -588,3 +588,10 @@ def test_union_find_truth_equals_bfs(orc):
         truth = orc.components_truth(V, a[keep], b[keep])
         assert np.array_equal(lab.astype(np.int64), truth)
         assert k == len(set(truth.tolist()))
+        # incremental form: edges added in two parts, same answers
+        uf = orc.UnionFind(V)
+        h = int(keep.sum()) // 2
+        uf.add(a[keep][:h], b[keep][:h])
+        assert uf.add(a[keep][h:], b[keep][h:]) == k
+        for x, y in rng.integers(0, V, (20, 2)).tolist():
+            assert uf.same(x, y) == (truth[x] == truth[y])
