@@ -60,6 +60,17 @@ def _c():
         L.sg_rmat_free.argtypes = [p]
         L.sg_rmat_next.restype = sz
         L.sg_rmat_next.argtypes = [p, sz, dbl, dbl, dbl, dbl, p, p, p]
+        L.sg_ftd_new.restype = p
+        L.sg_ftd_new.argtypes = [u32, dbl, dbl, dbl, u64]
+        L.sg_ftd_free.restype = None
+        L.sg_ftd_free.argtypes = [p]
+        for f in (L.sg_ftd_m, L.sg_ftd_k, L.sg_ftd_deleted):
+            f.restype = sz
+            f.argtypes = [p]
+        L.sg_ftd_inserts.restype = sz
+        L.sg_ftd_inserts.argtypes = [p, sz, sz, p]
+        L.sg_ftd_delete_chunk.restype = sz
+        L.sg_ftd_delete_chunk.argtypes = [p, sz, p, sz, p]
         L.sg_clu_new.restype = p
         L.sg_clu_new.argtypes = [u32, u32, dbl, u32, u32, u32, u32, u64]
         L.sg_clu_free.restype = None
@@ -119,77 +130,70 @@ def rmat_interleaved(logV: int, n: int, del_prob: float, seed: int,
 
 class ForestTargetedDeletes:
     """G(V, p) inserts in random order, then ``del_frac`` of the inserted
-    edges deleted, in chunks of ``rho`` updates.
+    edges deleted, in chunks of ``rho`` updates (C generator).
 
     Before each deletion chunk the caller passes the current spanning-forest
     edges of whatever engine replays the stream (batch boundaries = chunk
     boundaries; the library and the oracle hold the same forest there).  A
     Binomial(chunk, ``forest_frac``) share of the chunk's deletions are
-    distinct uniform forest edges; the rest are uniform live non-forest
-    edges.  The order inside a chunk is random.  This module only picks
-    edges; it computes no forest itself.
-    """
+    distinct uniform forest edges (at most all of them); the rest are
+    uniform live non-forest edges.  The order inside a chunk is random.
+    This module only picks edges; it computes no forest itself.  The
+    ``*_packed`` forms give uint64 updates (u | v<<32 | del<<63)."""
 
     def __init__(self, V: int, p: float, del_frac: float, forest_frac: float, seed: int,
                  rho: int):
         self.V, self.rho, self.forest_frac = V, rho, forest_frac
-        self.rng = np.random.default_rng(seed)
-        u, v = er_pairs(V, p, self.rng)
-        order = self.rng.permutation(u.shape[0])
-        self.u, self.v = u[order], v[order]
-        self.m = self.u.shape[0]
-        self.keys = self.u.astype(np.uint64) * V + self.v
-        self.sorted_idx = np.argsort(self.keys)
-        self.sorted_keys = self.keys[self.sorted_idx]
-        self.alive = np.ones(self.m, bool)
-        self.k = int(math.floor(del_frac * self.m))
-        self.deleted = 0
+        self._L = _c()
+        self._h = self._L.sg_ftd_new(V, p, del_frac, forest_frac, seed)
+        if not self._h:
+            raise MemoryError("forest-targeted generator allocation failed")
+        self.m = self._L.sg_ftd_m(self._h)
+        self.k = self._L.sg_ftd_k(self._h)
 
-    def insert_chunks(self):
-        """The insert phase, in chunks of rho updates."""
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sg_ftd_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def insert_chunks_packed(self):
+        """The insert phase, in chunks of rho packed updates."""
         for s in range(0, self.m, self.rho):
             e = min(self.m, s + self.rho)
-            yield self.u[s:e], self.v[s:e], np.zeros(e - s, np.uint8)
+            out = np.empty(e - s, np.uint64)
+            if self._L.sg_ftd_inserts(self._h, s, e, _p(out)) != e - s:
+                raise RuntimeError("inserts drawn out of order")
+            yield out
 
-    def _index(self, keys):
-        pos = np.searchsorted(self.sorted_keys, keys)
-        assert (self.sorted_keys[pos] == keys).all(), "forest edge not in the graph"
-        return self.sorted_idx[pos]
+    def insert_chunks(self):
+        """The insert phase, in chunks of rho updates, as (u, v, is_delete)."""
+        for out in self.insert_chunks_packed():
+            yield unpack(out)
 
     def deletes_left(self) -> int:
-        return self.k - self.deleted
+        return self.k - self._L.sg_ftd_deleted(self._h)
+
+    def delete_chunk_packed(self, forest_keys):
+        """The next chunk of deletions (packed) given the current forest as
+        keys u*V + v (u < v); None when every deletion has been drawn."""
+        fk = np.array(forest_keys, dtype=np.uint64, copy=True)
+        out = np.empty(self.rho, np.uint64)
+        n = self._L.sg_ftd_delete_chunk(self._h, self.rho, _p(fk), fk.size, _p(out))
+        if n == ctypes.c_size_t(-1).value:
+            raise MemoryError("forest-targeted generator")
+        return out[:n] if n else None
 
     def delete_chunk(self, forest_u, forest_v):
-        """The next chunk of deletions given the current forest edges."""
-        size = min(self.rho, self.k - self.deleted)
-        if size <= 0:
-            return None
+        """The next chunk of deletions given the current forest edges, as
+        (u, v, is_delete); None when every deletion has been drawn."""
         fu = np.asarray(forest_u, np.uint64)
         fv = np.asarray(forest_v, np.uint64)
-        f_idx = self._index(fu * self.V + fv) if fu.size else np.zeros(0, np.int64)
-        nf = min(int(self.rng.binomial(size, self.forest_frac)), f_idx.size)
-        pick_f = self.rng.choice(f_idx, size=nf, replace=False) if nf else np.zeros(0, np.int64)
-        in_forest = np.zeros(self.m, bool)
-        in_forest[f_idx] = True
-        chosen = np.zeros(self.m, bool)
-        chosen[pick_f] = True
-        need = size - nf
-        picks = []
-        while need > 0:
-            cand = self.rng.integers(0, self.m, size=2 * need + 16)
-            cand = cand[self.alive[cand] & ~in_forest[cand] & ~chosen[cand]]
-            cand = np.unique(cand)[:need]
-            if cand.size == 0:
-                break
-            self.rng.shuffle(cand)
-            chosen[cand] = True
-            picks.append(cand)
-            need -= cand.size
-        idx = np.concatenate([pick_f] + picks).astype(np.int64)
-        self.rng.shuffle(idx)
-        self.alive[idx] = False
-        self.deleted += idx.size
-        return self.u[idx], self.v[idx], np.ones(idx.size, np.uint8)
+        out = self.delete_chunk_packed(np.minimum(fu, fv) * np.uint64(self.V) +
+                                       np.maximum(fu, fv))
+        return None if out is None else unpack(out)
 
 
 class ClusteredChurn:

@@ -515,6 +515,217 @@ size_t sg_clu_round(void *h, uint32_t rd, uint64_t *out)
 }
 
 /*
+ * G(V, p) inserts in random order, then deletions of a fraction of the
+ * inserted edges in chunks, part of each chunk on current forest edges that
+ * the caller supplies (the forest of whatever engine replays the stream).
+ *   - edges: row x's neighbours y > x by geometric skipping, one xoshiro
+ *     stream per block of 64 rows (drawn in parallel), in row order, then
+ *     put in a random order by par_shuffle;
+ *   - a chunk of `size` deletions: Binomial(size, forest_frac) distinct
+ *     uniform edges of the supplied forest (at most all of them), the rest
+ *     uniform live edges outside it (rejection over the insertion order),
+ *     the whole chunk in random order.
+ * A live bitmap over keys u*V + v (V*V bits) keeps the stream legal.
+ * Updates are packed: u | v<<32 | is_delete<<63 with u < v.
+ */
+typedef struct {
+    rng_t r;
+    uint32_t V;
+    double forest_frac;
+    uint64_t *ins;    /* packed inserts, stream order */
+    size_t m;
+    uint64_t *bm;     /* live keys */
+    size_t k, deleted;
+    uint64_t *fset;   /* open-addressing set of the supplied forest's keys */
+    size_t fcap;
+    size_t inserted;  /* inserts drawn so far (a prefix of ins) */
+} ftd_t;
+
+static int ftd_live(const ftd_t *g, uint64_t key) { return bit_get(g->bm, key); }
+
+void sg_ftd_free(void *h)
+{
+    ftd_t *g = (ftd_t *)h;
+    if (!g) return;
+    free(g->ins);
+    free(g->bm);
+    free(g->fset);
+    free(g);
+}
+
+void *sg_ftd_new(uint32_t V, double p, double del_frac, double forest_frac, uint64_t seed)
+{
+    ftd_t *g = (ftd_t *)calloc(1, sizeof(ftd_t));
+    if (!g || V < 2) {
+        free(g);
+        return NULL;
+    }
+    rng_seed(&g->r, seed);
+    g->V = V;
+    g->forest_frac = forest_frac;
+    const uint32_t RB = 64;
+    const uint32_t nblk = (V + RB - 1) / RB;
+    size_t *cnt = (size_t *)calloc((size_t)nblk + 1, sizeof(size_t));
+    uint64_t **part = (uint64_t **)calloc(nblk, sizeof(uint64_t *));
+    int ok = cnt && part;
+    const double lq = p < 1.0 ? __builtin_log(1.0 - p) : 0.0;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (uint32_t b = 0; b < nblk; b++) {
+        if (!ok) continue;
+        rng_t rb;
+        rng_seed(&rb, fmix64(seed ^ (0xE5u + ((uint64_t)b << 32))));
+        const uint32_t x0 = b * RB, x1 = x0 + RB < V ? x0 + RB : V;
+        size_t cap = 1024, k = 0;
+        uint64_t *buf = (uint64_t *)malloc(cap * sizeof(uint64_t));
+        for (uint32_t x = x0; x < x1 && buf; x++) {
+            int64_t y = x;
+            for (;;) {
+                if (p >= 1.0) {
+                    y += 1;
+                } else {
+                    double uu = rng_unif(&rb);
+                    if (uu <= 0.0) uu = 0x1.0p-53;
+                    y += 1 + (int64_t)(__builtin_log(uu) / lq);
+                }
+                if (y >= (int64_t)V) break;
+                if (k == cap) {
+                    cap *= 2;
+                    uint64_t *nb = (uint64_t *)realloc(buf, cap * sizeof(uint64_t));
+                    if (!nb) {
+                        free(buf);
+                        buf = NULL;
+                        break;
+                    }
+                    buf = nb;
+                }
+                buf[k++] = (uint64_t)x | ((uint64_t)y << 32);
+            }
+        }
+        if (!buf) ok = 0;
+        part[b] = buf;
+        cnt[b] = k;
+    }
+    size_t m = 0;
+    for (uint32_t b = 0; ok && b < nblk; b++) m += cnt[b];
+    uint64_t *all = ok ? (uint64_t *)malloc(sizeof(uint64_t) * (m + 1)) : NULL;
+    g->ins = ok ? (uint64_t *)malloc(sizeof(uint64_t) * (m + 1)) : NULL;
+    g->bm = ok ? (uint64_t *)calloc(((uint64_t)V * V + 63) / 64, 8) : NULL;
+    if (!all || !g->ins || !g->bm) ok = 0;
+    size_t w = 0;
+    for (uint32_t b = 0; b < nblk; b++) {
+        if (ok) memcpy(all + w, part[b], cnt[b] * sizeof(uint64_t));
+        w += ok ? cnt[b] : 0;
+        free(part ? part[b] : NULL);
+    }
+    free(part);
+    free(cnt);
+    if (ok && !par_shuffle(all, g->ins, m, fmix64(seed ^ 0x1A5E27ULL))) ok = 0;
+    free(all);
+    if (!ok) {
+        sg_ftd_free(g);
+        return NULL;
+    }
+    g->m = m;
+    g->k = (size_t)(del_frac * (double)m);
+    return g;
+}
+
+size_t sg_ftd_m(void *h) { return ((ftd_t *)h)->m; }
+size_t sg_ftd_k(void *h) { return ((ftd_t *)h)->k; }
+size_t sg_ftd_deleted(void *h) { return ((ftd_t *)h)->deleted; }
+
+/* Inserts [k0, k1) of the insert phase, packed, into out; marks them live. */
+size_t sg_ftd_inserts(void *h, size_t k0, size_t k1, uint64_t *out)
+{
+    ftd_t *g = (ftd_t *)h;
+    if (k1 > g->m) k1 = g->m;
+    if (k0 != g->inserted || k1 < k0) return 0;  /* in order, once */
+    size_t w = 0;
+    for (size_t i = k0; i < k1; i++) {
+        const uint64_t e = g->ins[i];
+        bit_set(g->bm, (e & 0xFFFFFFFFu) * g->V + (e >> 32));
+        out[w++] = e;
+    }
+    g->inserted = k1;
+    return w;
+}
+
+static int fset_has(const ftd_t *g, uint64_t key)
+{
+    size_t i = (size_t)(fmix64(key) & (g->fcap - 1));
+    while (g->fset[i] != UINT64_MAX) {
+        if (g->fset[i] == key) return 1;
+        i = (i + 1) & (g->fcap - 1);
+    }
+    return 0;
+}
+
+/* The next chunk of at most `size` deletions, given the current forest
+ * (nf edges as keys u*V + v, u < v, all live) in `forest` (reordered in
+ * place).  Writes packed deletions to out; returns their number (0 when
+ * every deletion has been drawn), or (size_t)-1 when out of memory. */
+size_t sg_ftd_delete_chunk(void *h, size_t size, uint64_t *forest, size_t nf, uint64_t *out)
+{
+    ftd_t *g = (ftd_t *)h;
+    const uint64_t V = g->V;
+    if (g->deleted + size > g->k) size = g->k - g->deleted;
+    if (size == 0) return 0;
+    size_t want = 0;
+    for (size_t i = 0; i < size; i++) want += rng_unif(&g->r) < g->forest_frac;
+    if (want > nf) want = nf;
+    /* at most every live edge outside the forest (nf forest edges are live) */
+    const size_t live = g->inserted - g->deleted;
+    const size_t avail = live > nf ? live - nf : 0;
+    if (size - want > avail) size = want + avail;
+    /* forest keys: a set for the rejection test below */
+    size_t cap = 16;
+    while (cap < 2 * nf + 16) cap <<= 1;
+    if (cap > g->fcap) {
+        free(g->fset);
+        g->fset = (uint64_t *)malloc(cap * sizeof(uint64_t));
+        if (!g->fset) {
+            g->fcap = 0;
+            return (size_t)-1;
+        }
+        g->fcap = cap;
+    }
+    for (size_t i = 0; i < g->fcap; i++) g->fset[i] = UINT64_MAX;
+    for (size_t i = 0; i < nf; i++) {
+        size_t j = (size_t)(fmix64(forest[i]) & (g->fcap - 1));
+        while (g->fset[j] != UINT64_MAX && g->fset[j] != forest[i]) j = (j + 1) & (g->fcap - 1);
+        g->fset[j] = forest[i];
+    }
+    size_t w = 0;
+    /* distinct uniform forest edges: a partial Fisher-Yates over the list */
+    for (size_t i = 0; i < want; i++) {
+        const size_t j = i + (size_t)rng_below(&g->r, nf - i);
+        const uint64_t t = forest[i];
+        forest[i] = forest[j];
+        forest[j] = t;
+        const uint64_t key = forest[i];
+        bit_clr(g->bm, key);
+        out[w++] = (key / V) | ((key % V) << 32) | (1ULL << 63);
+    }
+    /* uniform live non-forest edges (each drawn edge is dead at once, so
+     * the picks are distinct) */
+    while (w < size) {
+        const uint64_t e = g->ins[rng_below(&g->r, g->m)];
+        const uint64_t key = (e & 0xFFFFFFFFu) * V + (e >> 32);
+        if (!ftd_live(g, key) || fset_has(g, key)) continue;
+        bit_clr(g->bm, key);
+        out[w++] = e | (1ULL << 63);
+    }
+    for (size_t i = w; i > 1; i--) {
+        const size_t j = (size_t)rng_below(&g->r, i);
+        const uint64_t t = out[i - 1];
+        out[i - 1] = out[j];
+        out[j] = t;
+    }
+    g->deleted += w;
+    return w;
+}
+
+/*
  * First-arrival spanning forest of an edge sequence: mask[i] = 1 iff edge i
  * joins two components of the edges before it (union-find).  Returns the
  * number of forest edges, or (size_t)-1 when out of memory.
