@@ -423,15 +423,20 @@ int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_r
  * it until cupk_serve_stop.  Requests are ordered by submission; a query
  * observes exactly the updates submitted before it (queries flush pending
  * updates first, Sec. 4.3).  Update requests submitted while a batch is on
- * the GPU join the next batch. */
+ * the GPU join the next batch.  Admission is by device memory: an admitted
+ * request holds a slot of a device ring (mem_budget_bytes) and is uploaded
+ * at once on a copy stream, overlapping the batch on the GPU; the worker
+ * applies each batch straight from the ring. */
 
 typedef struct {
     uint32_t max_batch;        /* updates per device batch (0 = the autotuned
                                   batch target if cupk_autotune ran, else
                                   1<<20)                                       */
     uint32_t nonblocking;      /* 1: refuse with CUPK_EBUSY instead of waiting */
-    size_t mem_budget_bytes;   /* host staging for pending updates, 8 B each
-                                  (0 = 64 MiB); admission waits for room      */
+    size_t mem_budget_bytes;   /* device ring holding admitted update requests
+                                  until applied, 8 B per update (0 = 64 MiB;
+                                  as much pinned host staging again);
+                                  admission waits for room                    */
 } cupk_serve_opts;
 
 typedef struct {

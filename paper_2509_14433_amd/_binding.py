@@ -350,13 +350,18 @@ class Context:
         self._check(lib.cupk_num_components(self._h, ctypes.byref(o)))
         return o.value
 
-    def forest_edges(self):
+    def forest_edge_arrays(self):
+        """Forest edges as two uint32 arrays (u < v), in the library's order."""
         n = ctypes.c_size_t(0)
         cap = self.V
         u = np.zeros(cap, np.uint32)
         v = np.zeros(cap, np.uint32)
         self._check(lib.cupk_forest_edges(self._h, _ptr(u), _ptr(v), cap, ctypes.byref(n)))
-        return sorted(zip(u[: n.value].tolist(), v[: n.value].tolist()))
+        return u[: n.value].copy(), v[: n.value].copy()
+
+    def forest_edges(self):
+        u, v = self.forest_edge_arrays()
+        return sorted(zip(u.tolist(), v.tolist()))
 
     def level_forest_edges(self, level):
         """Levels mode: edges of the forest of `level` (1..C)."""

@@ -109,6 +109,7 @@ struct RoundSet {
     uint32_t minv;
     uint32_t size;
     bool sampled;  // false: the left-out tree, reduced only to serve as a fragment
+    uint8_t kind = 0;  // reduced from: 0 vertices, 1 fragments, 2 the other fragments
 };
 
 // Reduce k sets into d_sig[slot] (internal layout, W words per set) and
@@ -389,6 +390,9 @@ static int round_one_pieces(cupk_ctx *ctx, int slot, std::vector<RoundSet> &nset
         } else if (st == CUPK_SAMPLE_FAILED) {
             ctx->ctr.sample_failed++;
             failed = true;
+            if (ctx->trace)
+                fprintf(stderr, "cupk   failed: first round set %zu of %zu size %u minv %u\n", i,
+                        k, nsets[i].size, nsets[i].minv);
         }
     }
     if (!lk) {
@@ -482,6 +486,7 @@ int run_rounds(cupk_ctx *ctx)
         uint32_t label, minv, size;
         std::vector<uint32_t> frags;  // previous-round sets forming the tree
         bool from_frags, have_minv;
+        bool complemented = false;    // frags are the previous-round sets it does not hold
     };
     int slot = 0;
     bool linked_any = false;
@@ -544,6 +549,7 @@ int run_rounds(cupk_ctx *ctx)
                     g.frags.clear();
                     for (uint32_t i = 0; i < sets.size(); i++)
                         if (!in[i]) g.frags.push_back(i);
+                    g.complemented = true;
                     ctx->ctr.sets_complemented++;
                 }
         // the left-out tree: largest, ties broken by smallest vertex id
@@ -621,7 +627,8 @@ int run_rounds(cupk_ctx *ctx)
             }
         for (size_t gi : gord)
             if (groups[gi].from_frags) {
-                nsets.push_back({groups[gi].label, groups[gi].minv, groups[gi].size, gi != skip});
+                nsets.push_back({groups[gi].label, groups[gi].minv, groups[gi].size, gi != skip,
+                                 (uint8_t)(groups[gi].complemented ? 2 : 1)});
                 fmem.insert(fmem.end(), groups[gi].frags.begin(), groups[gi].frags.end());
                 foff.push_back((uint32_t)fmem.size());
             }
@@ -671,6 +678,10 @@ int run_rounds(cupk_ctx *ctx)
             } else if (st == CUPK_SAMPLE_FAILED) {
                 ctx->ctr.sample_failed++;
                 failed = true;
+                if (ctx->trace)
+                    fprintf(stderr, "cupk   failed: round %llu set %zu of %zu kind %u size %u minv %u\n",
+                            (unsigned long long)ctx->ctr.rounds, i, k, (unsigned)sets[i].kind,
+                            sets[i].size, sets[i].minv);
             }
         }
         if (!linked) {
@@ -1261,20 +1272,6 @@ int apply_device(cupk_ctx *ctx, const uint64_t *d_upd, size_t n, bool defer)
         if (rc != CUPK_OK) return rc;
     }
     return CUPK_OK;
-}
-
-// One batch of packed updates held in host memory (serving loop).
-int apply_packed_host(cupk_ctx *ctx, const uint64_t *packed, size_t n)
-{
-    if (n == 0) return CUPK_OK;
-    HIPCHK(grow(ctx->h_upd, n));
-    HIPCHK(grow(ctx->d_upd, n));
-    std::copy(packed, packed + n, ctx->h_upd.p);
-    HIPCHK(hipMemcpyAsync(ctx->d_upd.p, ctx->h_upd.p, n * 8, hipMemcpyHostToDevice, ctx->s));
-    ctx->query_often = true;
-    const int rc = apply_device(ctx, ctx->d_upd.p, n, false);
-    ctx->query_often = false;
-    return rc;
 }
 
 int connected_impl(cupk_ctx *ctx, uint32_t u, uint32_t v)
@@ -2138,17 +2135,30 @@ int cupk_serve_start(cupk_ctx *ctx, const cupk_serve_opts *opts)
         const int dev = ctx->device;
         ctx->server.reset(new (std::nothrow) Server(
             ctx, o,
-            [](cupk_ctx *c, const uint64_t *p, size_t n) -> int {
+            [](cupk_ctx *c, const uint64_t *d, size_t n, hipEvent_t ready) -> int {
                 static thread_local int bound = -1;
                 if (bound != c->device) {
                     if (hipSetDevice(c->device) != hipSuccess) return CUPK_EDEVICE;
                     bound = c->device;
                 }
-                return apply_packed_host(c, p, n);
+                // the batch sits in the server's device ring once its
+                // upload (on the server's copy stream) is done
+                if (ready && hipStreamWaitEvent(c->s, ready, 0) != hipSuccess)
+                    return CUPK_EDEVICE;
+                c->query_often = true;
+                const int rc = apply_device(c, d, n, false);
+                c->query_often = false;
+                return rc;
             },
             connected_impl));
         (void)dev;
         if (!ctx->server) return CUPK_ENOMEM;
+        const int src = ctx->server->start();
+        if (src != CUPK_OK) {
+            ctx->server.reset();
+            return src == CUPK_ENOMEM ? ctx->fail(hipErrorOutOfMemory, "serving ring", __LINE__)
+                                      : ctx->fail(hipErrorUnknown, "serving ring", __LINE__);
+        }
         return CUPK_OK;
     });
 }

@@ -11,10 +11,15 @@
 // the updates submitted before it (queries flush pending updates first,
 // Sec. 4.3 of arXiv 2509.14433).
 //
-// Admission is by memory: pending update requests hold host staging memory
-// (8 bytes per update); a submission that would exceed the budget blocks
-// until the worker frees space, or fails with CUPK_EBUSY in non-blocking
-// mode.  Query latency is measured from submission to answer.
+// Admission is by device memory: an admitted update request takes a
+// contiguous slot of a device ring of mem_budget_bytes (8 bytes per update),
+// packed into the slot's pinned host twin and uploaded on a copy stream at
+// once, so that its upload overlaps the batch the worker has on the GPU.
+// A submission that does not fit blocks until the worker retires requests
+// (slots are freed in submission order), or fails with CUPK_EBUSY in
+// non-blocking mode.  The worker applies a batch straight from its device
+// slots after the context's stream has waited for their uploads.  Query
+// latency is measured from submission to answer.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,7 +54,7 @@ struct Server::Req {
     bool burst = false;            // a burst of queries (bu, bv; answers go to bout)
     std::vector<uint32_t> bu, bv;
     int32_t *bout = nullptr;
-    std::vector<uint64_t> packed;  // update requests: packed updates
+    size_t slot = 0, n = 0;        // update requests: device ring slot, updates
     size_t done_upd = 0;           // updates of this request already applied
     double t_submit;
 };
@@ -59,7 +64,20 @@ Server::Server(cupk_ctx *ctx, const cupk_serve_opts &o, ApplyFn apply, ConnFn co
 {
     if (opts_.max_batch == 0) opts_.max_batch = 1u << 20;
     if (opts_.mem_budget_bytes == 0) opts_.mem_budget_bytes = (size_t)64 << 20;
+}
+
+int Server::start()
+{
+    cap_ = opts_.mem_budget_bytes / 8;
+    if (cap_ == 0) return CUPK_EINVAL;
+    if (hipStreamCreateWithFlags(&copy_s_, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&copied_, hipEventDisableTiming) != hipSuccess)
+        return CUPK_EDEVICE;
+    if (hipMalloc((void **)&d_ring_, cap_ * 8) != hipSuccess) return CUPK_ENOMEM;
+    if (hipHostMalloc((void **)&h_ring_, cap_ * 8, hipHostMallocDefault) != hipSuccess)
+        return CUPK_ENOMEM;
     th_ = std::thread([this] { loop(); });
+    return CUPK_OK;
 }
 
 Server::~Server()
@@ -71,6 +89,41 @@ Server::~Server()
     cv_work_.notify_all();
     cv_space_.notify_all();
     if (th_.joinable()) th_.join();
+    if (copy_s_) (void)hipStreamSynchronize(copy_s_);
+    if (d_ring_) (void)hipFree(d_ring_);
+    if (h_ring_) (void)hipHostFree(h_ring_);
+    if (copied_) (void)hipEventDestroy(copied_);
+    if (copy_s_) (void)hipStreamDestroy(copy_s_);
+}
+
+// A contiguous slot of n words after the newest one, wrapping to the start
+// of the ring when the end is too short; false when it does not fit yet.
+// In use: slots_ from its oldest (tail) to the newest, which ends at head_.
+bool Server::reserve(size_t n, size_t *slot)
+{
+    if (slots_.empty()) {
+        head_ = 0;
+        if (n > cap_) return false;
+        *slot = 0;
+        return true;
+    }
+    const size_t tail = slots_.front().first;
+    if (head_ > tail) {  // free: [head_, cap_) and [0, tail)
+        if (cap_ - head_ >= n) {
+            *slot = head_;
+            return true;
+        }
+        if (tail >= n) {
+            *slot = 0;
+            return true;
+        }
+        return false;
+    }
+    if (tail - head_ >= n) {  // wrapped: free [head_, tail)
+        *slot = head_;
+        return true;
+    }
+    return false;
 }
 
 int Server::submit_updates(const uint32_t *u, const uint32_t *v, const uint8_t *del, size_t n,
@@ -78,22 +131,32 @@ int Server::submit_updates(const uint32_t *u, const uint32_t *v, const uint8_t *
 {
     for (size_t i = 0; i < n; i++)
         if (u[i] == v[i] || u[i] >= V || v[i] >= V) return CUPK_EINVAL;
-    const size_t bytes = n * 8;
-    if (bytes > opts_.mem_budget_bytes) return CUPK_EINVAL;  // can never be admitted
+    if (n > cap_) return CUPK_EINVAL;  // can never be admitted
     auto r = std::make_unique<Req>();
     r->query = false;
-    r->packed.resize(n);
-    for (size_t i = 0; i < n; i++)
-        r->packed[i] =
-            (uint64_t)u[i] | ((uint64_t)v[i] << 32) | ((uint64_t)(del[i] != 0) << 63);
+    r->n = n;
     std::unique_lock<std::mutex> g(m_);
-    if (pending_bytes_ + bytes > opts_.mem_budget_bytes) {
+    size_t slot = 0;
+    if (n && !reserve(n, &slot)) {
         if (opts_.nonblocking) return CUPK_EBUSY;
         stats_.admission_waits++;
-        cv_space_.wait(g, [&] { return stop_ || pending_bytes_ + bytes <= opts_.mem_budget_bytes; });
+        cv_space_.wait(g, [&] { return stop_ || reserve(n, &slot); });
         if (stop_) return CUPK_EBUSY;
     }
-    pending_bytes_ += bytes;
+    // pack into the slot's pinned twin and upload it now (its previous
+    // contents were uploaded and applied before the slot was freed)
+    if (n) {
+        uint64_t *h = h_ring_ + slot;
+        for (size_t i = 0; i < n; i++)
+            h[i] = (uint64_t)u[i] | ((uint64_t)v[i] << 32) | ((uint64_t)(del[i] != 0) << 63);
+        if (hipMemcpyAsync(d_ring_ + slot, h, n * 8, hipMemcpyHostToDevice, copy_s_) !=
+            hipSuccess)
+            return CUPK_EDEVICE;
+        slots_.push_back({slot, n});
+        head_ = slot + n;
+        pending_bytes_ += n * 8;
+    }
+    r->slot = slot;
     r->ticket = next_ticket_++;
     r->t_submit = now_us();
     *ticket = r->ticket;
@@ -180,56 +243,59 @@ void Server::reset_stats()
 
 void Server::loop()
 {
-    std::vector<uint64_t> batch;
     for (;;) {
-        // gather the next batch: a prefix of update requests, up to max_batch
-        // updates, stopping at the first query
-        std::vector<Req *> part;  // requests contributing to this batch
+        // gather the next batch: a prefix of update requests whose device
+        // slots are contiguous, up to max_batch updates, stopping at the
+        // first query
         std::vector<std::pair<Req *, size_t>> takes;
+        size_t start = 0, nb = 0;
         {
             std::unique_lock<std::mutex> g(m_);
             cv_work_.wait(g, [&] { return stop_ || !queue_.empty(); });
             if (queue_.empty() && stop_) return;
-            batch.clear();
             for (auto &rp : queue_) {
                 Req *r = rp.get();
                 if (r->query) break;
-                const size_t left = r->packed.size() - r->done_upd;
-                const size_t room = opts_.max_batch - batch.size();
-                const size_t take = std::min(left, room);
-                takes.push_back({r, take});
+                if (r->n == 0) continue;  // nothing to apply; retired below
+                const size_t from = r->slot + r->done_upd;
+                if (nb && from != start + nb) break;  // the ring wrapped here
+                const size_t left = r->n - r->done_upd;
+                const size_t take = std::min(left, (size_t)opts_.max_batch - nb);
                 if (take == 0) break;
-                batch.insert(batch.end(), r->packed.begin() + r->done_upd,
-                             r->packed.begin() + r->done_upd + take);
-                if (batch.size() >= opts_.max_batch) break;
+                if (!nb) start = from;
+                takes.push_back({r, take});
+                nb += take;
+                if (take < left || nb >= opts_.max_batch) break;
             }
+            // every gathered request's upload was queued before this event
+            if (nb && hipEventRecord(copied_, copy_s_) != hipSuccess) nb = 0, takes.clear();
         }
         int rc = CUPK_OK;
-        if (!batch.empty()) {
+        if (nb) {
             // no exception may leave the worker thread
             try {
-                rc = apply_(ctx_, batch.data(), batch.size());
+                rc = apply_(ctx_, d_ring_ + start, nb, copied_);
             } catch (const std::exception &) {
                 rc = CUPK_ENOMEM;
             }
             std::lock_guard<std::mutex> g(m_);
             stats_.batches++;
-            stats_.updates += batch.size();
+            stats_.updates += nb;
         }
-        // retire finished update requests and answer the queries that now
-        // head the queue
+        // retire finished update requests (freeing their slots, oldest
+        // first) and answer the queries that now head the queue
         {
             std::unique_lock<std::mutex> g(m_);
-            size_t freed = 0;
-            for (auto &t : takes) {
-                t.first->done_upd += t.second;
-                freed += t.second * 8;
-            }
+            for (auto &t : takes) t.first->done_upd += t.second;
             while (!queue_.empty()) {
                 Req *r = queue_.front().get();
                 if (!r->query) {
-                    if (r->done_upd < r->packed.size()) break;
+                    if (r->done_upd < r->n) break;
                     results_[r->ticket] = rc;
+                    if (r->n) {
+                        pending_bytes_ -= r->n * 8;
+                        slots_.pop_front();
+                    }
                     queue_.pop_front();
                     continue;
                 }
@@ -251,7 +317,6 @@ void Server::loop()
                 }
                 queue_.pop_front();
             }
-            pending_bytes_ -= freed;
         }
         cv_space_.notify_all();
         cv_done_.notify_all();

@@ -232,3 +232,61 @@ def test_query_bursts(cupk, mode):
     assert st["queries"] == sum(len(w) for _, _, w in bursts)
     assert st["query_p99_us"] >= st["query_p50_us"] > 0
     ctx.close()
+
+
+def test_pipelined_requests_merge_and_match_the_unmerged_run(cupk):
+    # One client submits many small update requests without waiting for
+    # them, with a query after every 5th: requests admitted while a batch is
+    # on the GPU (uploaded into their device slots meanwhile) join the next
+    # batch, so there are fewer batches than requests.  Every answer equals
+    # the union-find truth at its position and the answer of the same
+    # requests applied one at a time (each waited for).
+    V, C, D, S = 2000, 11, 22, 0x5EED5E
+    u, v, d = streamgen.er_standard(V, 0.002, 0.4, 31)
+    sz = 40
+    reqs = [(s, min(len(u), s + sz)) for s in range(0, len(u), sz)]
+    rng = np.random.default_rng(6)
+    qpos = {i: tuple(int(x) for x in rng.integers(0, V, 2)) for i in range(4, len(reqs), 5)}
+    uf_truth = {}
+    uf = oracle.UnionFind(V)
+    live = set()
+    for i, (a, b) in enumerate(reqs):
+        for x, y, z in zip(u[a:b].tolist(), v[a:b].tolist(), d[a:b].tolist()):
+            (live.remove if z else live.add)((x, y))
+        if i in qpos:
+            lu = np.array([e[0] for e in live], np.uint32)
+            lv = np.array([e[1] for e in live], np.uint32)
+            _, lab = oracle.uf_components(V, lu, lv)
+            uf_truth[i] = int(lab[qpos[i][0]] == lab[qpos[i][1]])
+
+    def run(pipelined):
+        ctx = cupk.Context(V, C, D, S)
+        ctx.serve_start(max_batch=4096, mem_budget_bytes=64 * sz * 8)
+        ans, pend = {}, []
+        for i, (a, b) in enumerate(reqs):
+            t = ctx.submit_updates(u[a:b], v[a:b], d[a:b])
+            if pipelined:
+                pend.append(t)
+            else:
+                assert ctx.wait(t) == 0
+            if i in qpos:
+                ans[i] = ctx.submit_query(*qpos[i])
+        for t in pend:
+            assert ctx.wait(t) == 0
+        ans = {i: ctx.wait(t) for i, t in ans.items()}
+        st = ctx.serve_stats()
+        ctx.serve_stop()
+        dg = ctx.digest()
+        ctx.close()
+        return ans, st, dg
+
+    alone, st1, dg1 = run(False)
+    mixed, st2, dg2 = run(True)
+    print(f"pipelined: {st2['update_requests']} requests in {st2['batches']} batches "
+          f"(one at a time: {st1['batches']})", flush=True)
+    assert alone == uf_truth and mixed == uf_truth
+    assert st1["batches"] == len(reqs)
+    assert st2["batches"] < st2["update_requests"] == len(reqs)
+    ref = oracle.Sketch(V, C, D, S)
+    ref.apply(u, v)
+    assert dg1 == dg2 == ref.digest()
