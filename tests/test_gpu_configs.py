@@ -38,7 +38,7 @@ def _cd(V):
 def _truth_labels(V, live):
     eu = np.array([e[0] for e in live], np.uint32)
     ev = np.array([e[1] for e in live], np.uint32)
-    return oracle.components_truth(V, eu, ev)
+    return oracle.uf_components(V, eu, ev)[1]
 
 
 @pytest.fixture(scope="module")
@@ -92,7 +92,16 @@ def test_rmat_ragged_batches(cupk, rmat_ref, mode, graph, walk_plain, split):
 def _forest_targeted_run(cupk, ctx_apply, ctx_query, want_forest_fn, cfg):
     """Drive the forest-targeted generator from the oracle's forest, apply
     every chunk to the oracle and (through ctx_apply) to the library, query
-    after each chunk.  Returns (answers, truths, oracle sketch, replay)."""
+    after each chunk.  Returns (answers, wants, oracle sketch, replay,
+    forest-edge deletions, deletions), where wants[i] is the oracle replay's
+    answer to query i; every want is also checked here against the live
+    graph's connectivity for as long as no oracle sample has failed.
+
+    The deletions hit the forest, whose edges are the sampler's own
+    outputs, so the stream depends on the sketch's randomness: it can drain
+    every verifying bucket of a vertex, and then a replacement exists that
+    no sample finds.  From the first such failure on, the replay's answers
+    (and the library's, which must equal them) may differ from the truth."""
     V = cfg["V"]
     C, D = _cd(V)
     g = streamgen.ForestTargetedDeletes(V, cfg["p"], cfg["del_frac"], cfg["forest_frac"],
@@ -101,7 +110,7 @@ def _forest_targeted_run(cupk, ctx_apply, ctx_query, want_forest_fn, cfg):
     fr = oracle.ForestReplay(sk)
     live = set()
     rng = np.random.default_rng(cfg["seed"])
-    answers, truths = [], []
+    answers, wants = [], []
     last_forest_del = (0, 1)
     n_forest_del = 0
 
@@ -118,10 +127,14 @@ def _forest_targeted_run(cupk, ctx_apply, ctx_query, want_forest_fn, cfg):
                 live.add((a, b))
         fr.apply_batch(u, v, d)
         ctx_apply(u, v, d)
+        # connectivity of the live graph at this point of the stream
+        lab = _truth_labels(V, live)
         qa, qb = (int(x) for x in rng.integers(0, V, 2))
         for (x, y) in ((qa, qb), last_forest_del):
             answers.append(ctx_query(x, y))
-            truths.append((x, y))
+            wants.append(int(fr.connected(x, y)))
+            if fr.n_failed == 0:
+                assert wants[-1] == int(lab[x] == lab[y]), (len(wants), x, y)
 
     for u, v, d in g.insert_chunks():
         step(u, v, d)
@@ -131,9 +144,7 @@ def _forest_targeted_run(cupk, ctx_apply, ctx_query, want_forest_fn, cfg):
         if ch is None:
             break
         step(*ch)
-    lab = _truth_labels(V, live)
-    want = [int(lab[x] == lab[y]) for x, y in truths]
-    return answers, want, sk, fr, n_forest_del, g.k
+    return answers, wants, sk, fr, n_forest_del, g.k
 
 
 @pytest.mark.parametrize("split", [False, True])

@@ -534,3 +534,49 @@ def test_device_batches_stream_ordered(cupk, mode):
         assert np.array_equal(dv[j, ..., 0], oa) and np.array_equal(dv[j, ..., 1], og)
         assert np.array_equal(ha[j], oa) and np.array_equal(hg[j], og)
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_mass_forest_deletion_batch(cupk, mode):
+    # One batch whose flagged updates are more than 16384 deletions of
+    # forest edges (the compacted flag list, not the inline one) shatters a
+    # spanning tree into about 20000 pieces, and the replacement rounds
+    # reconnect them: sketch, forest edges and counts equal the oracle's,
+    # and no sample fails.
+    V = 30000
+    C = max(1, math.ceil(math.log2(V)))
+    D = 2 * C
+    S = 0x5EEDDE1
+    rng = np.random.default_rng(7)
+    m = 8 * V
+    a = rng.integers(0, V, 2 * m)
+    b = rng.integers(0, V, 2 * m)
+    keep = a != b
+    key = np.unique(np.minimum(a, b)[keep].astype(np.int64) * V + np.maximum(a, b)[keep])[:m]
+    rng.shuffle(key)
+    eu, ev = (key // V).astype(np.uint32), (key % V).astype(np.uint32)
+    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    ref = oracle.Sketch(V, C, D, S)
+    fr = oracle.ForestReplay(ref)
+    for s in range(0, m, 60000):
+        e = min(m, s + 60000)
+        print(f"mass deletion mode={mode}: insert batch {s}:{e}", flush=True)
+        z = np.zeros(e - s, np.uint8)
+        ctx.apply_updates(eu[s:e], ev[s:e], z)
+        fr.apply_batch(eu[s:e], ev[s:e], z)
+    (u, v, d), = _forest_cut_batches(rng, V, eu, ev, fr, 1, 20000, 5000, 3000)
+    print(f"mass deletion mode={mode}: batch of {len(u)} with 20000 forest-edge deletions",
+          flush=True)
+    ctx.apply_updates(u, v, d)
+    fr.apply_batch(u, v, d)
+    _assert_same_sketch(ctx, ref)
+    assert ctx.forest_edges() == fr.forest_edges()
+    ctr = ctx.counters()
+    assert ctr["cuts"] == fr.n_cuts and ctr["rounds"] == fr.n_rounds
+    assert ctr["links"] == fr.n_links
+    assert ctr["sample_failed"] == fr.n_failed == 0
+    fu, fv = streamgen.final_edges(np.concatenate([eu, u]), np.concatenate([ev, v]),
+                                   np.concatenate([np.zeros(m, np.uint8), d]))
+    truth = oracle.components_truth(V, fu, fv)
+    assert ctx.num_components() == len(set(truth.tolist()))
+    ctx.close()
