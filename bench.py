@@ -712,6 +712,102 @@ def cpu_baseline_clusters(np, streamgen, phases_host_sample, cfg, budget_s=12.0)
             "one_thread": out["one_thread"]}
 
 
+def served_forest_targeted_leg(cupk, np, torch, streamgen, inflight=4):
+    """er65536_p0.2_forestdel through the serving loop: G(65536, 0.2) inserts
+    in random order (4.3e8), then 10% of them deleted, 30% of each deletion
+    chunk on current forest edges, in chunks of rho = 1e5 updates with two
+    connectivity queries after every chunk (a random pair and the endpoints
+    of the last deleted forest edge).  The stream is first recorded by
+    driving a context chunk by chunk (one device batch per chunk, timed:
+    the direct path), then replayed from host memory through the serving
+    loop, submitted as fast as the device-memory admission of `inflight`
+    chunks allows; latency is per query, submission to answer."""
+    cfg = streamgen.CONFIGS[3]
+    Vw, rho = cfg["V"], cfg["rho"]
+    Cw = streamgen_ceil_log2(Vw)
+    t0 = time.perf_counter()
+    gen = streamgen.ForestTargetedDeletes(Vw, cfg["p"], cfg["del_frac"], cfg["forest_frac"],
+                                          cfg["seed"], rho)
+    print(f"bench: forest-targeted stream: {gen.m} inserts drawn in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    rec = []
+    last_forest = {}  # deletion chunk -> its last deleted forest edge
+    ctx = cupk.Context(Vw, Cw, 2 * Cw, cfg["S"], max_batch=rho)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_upd = 0
+    for ch in gen.insert_chunks_packed():
+        ctx.apply_updates_device(torch.from_numpy(ch.view(np.int64)).to("cuda"))
+        rec.append(ch)
+        n_upd += len(ch)
+    n_forest = 0
+    while True:
+        fu, fv = ctx.forest_edge_arrays()
+        fkeys = fu.astype(np.uint64) * np.uint64(Vw) + fv
+        ch = gen.delete_chunk_packed(fkeys)
+        if ch is None:
+            break
+        ctx.apply_updates_device(torch.from_numpy(ch.view(np.int64)).to("cuda"))
+        u, v, _ = streamgen.unpack(ch)
+        hit = np.flatnonzero(np.isin(u.astype(np.uint64) * np.uint64(Vw) + v, fkeys))
+        n_forest += len(hit)
+        if len(hit):
+            last_forest[len(rec)] = (int(u[hit[-1]]), int(v[hit[-1]]))
+        rec.append(ch)
+        n_upd += len(ch)
+        if len(rec) % 100 == 0:
+            print(f"bench: forest-targeted recorded {len(rec)} chunks", file=sys.stderr,
+                  flush=True)
+    ctx.sync()
+    t_direct = time.perf_counter() - t0
+    cd = ctx.counters()
+    ctx.close()
+    gen.close()
+    print(f"bench: forest-targeted direct path {n_upd / t_direct:.3e} updates/s "
+          f"({n_forest} forest-edge deletions, {cd['cuts']} cuts, {cd['rounds']} rounds)",
+          file=sys.stderr, flush=True)
+    # queries: a random pair and the endpoints of the last deleted forest edge
+    rng = np.random.default_rng(17)
+    qs = rng.integers(0, Vw, size=(len(rec), 2)).astype(np.uint32)
+    ctx = cupk.Context(Vw, Cw, 2 * Cw, cfg["S"], max_batch=rho)
+    ctx.serve_start(max_batch=rho, mem_budget_bytes=inflight * rho * 8)
+    t0 = time.perf_counter()
+    tickets = []
+    last = (0, 1)
+    for k, ch in enumerate(rec):
+        u, v, d = streamgen.unpack(ch)
+        tickets.append(ctx.submit_updates(u, v, d))
+        tickets.append(ctx.submit_query(int(qs[k, 0]), int(qs[k, 1])))
+        if d[0]:
+            last = last_forest.get(k, last)
+            tickets.append(ctx.submit_query(*last))
+        if k % 500 == 0:
+            print(f"bench: served chunk {k} of {len(rec)}", file=sys.stderr, flush=True)
+    for t in tickets:
+        ctx.wait(t)
+    dt = time.perf_counter() - t0
+    st = ctx.serve_stats()
+    ctx.serve_stop()
+    c2 = ctx.counters()
+    ctx.close()
+    return {"workload": cfg["name"], "value": round(n_upd / dt, 1), "unit": "updates/s",
+            "updates": n_upd, "queries": st["queries"],
+            "query_p50_us": round(st["query_p50_us"], 1),
+            "query_p99_us": round(st["query_p99_us"], 1),
+            "query_max_us": round(st["query_max_us"], 1), "batches": st["batches"],
+            "admission_waits": st["admission_waits"], "cuts": c2["cuts"],
+            "rounds": c2["rounds"], "sample_failed": c2["sample_failed"],
+            "forest_edge_deletions": n_forest,
+            "direct": {"value": round(n_upd / t_direct, 1), "unit": "updates/s",
+                       "note": "the same chunks as device batches, one call per chunk, "
+                               "forest edges read before every deletion chunk"},
+            "setup": f"V={Vw}, C={Cw}, D={2 * Cw}; chunks of {rho} updates from host memory "
+                     f"(PCIe included), a random-pair query after every chunk and the "
+                     f"endpoints of the last deleted forest edge after every deletion chunk; "
+                     f"admission budget "
+                     f"{inflight} chunks of device ring ({inflight * rho * 8} B)"}
+
+
 def clusters_main(args, cupk, np, torch, streamgen):
     cfg = streamgen.CONFIGS[4]
     Vc = cfg["V"]
@@ -830,12 +926,20 @@ def clusters_main(args, cupk, np, torch, streamgen):
                         "basis": f"8 + 64*C = {bpu} B per update",
                         "host_flags_ms": round(pctr["host_flags_ms"], 1),
                         "host_rounds_ms": round(pctr["host_rounds_ms"], 1)}
+    sample = None
     if not args.no_cpu:
-        print("bench: timing CPU oracle", file=sys.stderr, flush=True)
         sample = np.concatenate([phases[0].cpu().numpy(), phases[1][:60_000_000].cpu().numpy()]
                                 ).view(np.uint64)
-        del phases
-        torch.cuda.empty_cache()
+    del phases
+    torch.cuda.empty_cache()
+    if not args.no_serve:
+        print("bench: timing served path (er65536 forest-targeted)", file=sys.stderr, flush=True)
+        out["served"] = served_forest_targeted_leg(cupk, np, torch, streamgen)
+        out["query_latency_us"] = {"p50": out["served"]["query_p50_us"],
+                                   "p99": out["served"]["query_p99_us"],
+                                   "workload": out["served"]["workload"]}
+    if sample is not None:
+        print("bench: timing CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline_clusters(np, streamgen, sample, cfg)
     print(json.dumps(out), flush=True)
 
