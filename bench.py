@@ -11,19 +11,21 @@ random bridges toggled every 1e5 updates (splits and merges of cluster
 groups).  Sketch: C=20 columns x D=40 depths per vertex (13.4 GB resident in
 HBM).  The whole stream is drawn before timing and held in HBM.
 
-One step = one churn round through the whole path, in 1M-update device
-batches: classification, staged scatter into both endpoints' sketches, host
-forest links/cuts, replacement rounds (component XOR-reduce + verify/sample)
-for every broken tree.  K steps walk the stream's rounds in order; after the
+One step = one churn round through the whole path, in device batches of
+the size and launch geometry the autotuner picks on a warm-up context:
+classification, staged scatter into both endpoints' sketches, host forest
+links/cuts, replacement rounds (component XOR-reduce + verify/sample) for
+every broken tree.  K steps walk the stream's rounds in order; after the
 last round a fresh context (set up untimed) starts from round 0 again.  The
 setup phase of every context runs before the timed region.
 
 Prints one JSON line: whole-job updates/s; the staged scatter's roofline
-(compulsory bytes = 8 B per update + 32 B per bucket the timed launches
-changed in HBM, counted by the kernel, over the kernel time of every 8th
-launch taken with HIP events on its stream; the HBM traffic of the committed
-rocprofv3 PMC profile; the VALU issue rate of the committed SQ counter
-profile); the plain (atomic) kernel on the same workload; and the CPU oracle
+(bound by its integer ALU work: the method's one column hash per (update,
+column) over the kernel time of every 8th launch taken with HIP events on
+its stream, against the vector ALU peak; beside it the compulsory HBM bytes
+= 8 B per update + 32 B per bucket the timed launches changed, counted by
+the kernel, the HBM traffic of the committed rocprofv3 PMC profile and the
+VALU issue rate of the committed SQ counter profile); the plain (atomic) kernel on the same workload; and the CPU oracle
 timed on a bounded sample of the same stream (all host cores, and one).
 --workload selects the extra measurements of the other workload recipes.
 """
@@ -42,9 +44,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-# VALU issue peak: 256 CUs x 4 SIMDs, one wave instruction per SIMD per
-# cycle, at 2.4 GHz
-VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9
+# Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz, i.e. one 64-lane
+# wave instruction per CU per clock (full-rate 32-bit integer operations,
+# multiplies included: measured at 0.85-0.89 per CU per clock).
+VALU_PEAK_WAVE_INSTS = 256 * 2.4e9
+ALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# The method's own ALU work: one column hash per (update, column).  The
+# SplitMix64 finalizer with the seed XOR on 64-bit words is 19 full-rate
+# 32-bit lane operations on gfx950 (2 for the seed XOR, 3 per shift-XOR
+# step, 4 per multiply by a 64-bit constant).
+HASH_LANE_OPS = 19
 CALIB_BYTES = 256 << 20  # plain copy used to scale the HBM byte counters
 BATCH4 = 1_000_000
 # the benchmark workload of the first build, kept as an extra measurement
@@ -588,18 +597,23 @@ def _ctr_delta(c1, c0):
 
 
 def run_clusters(cupk, torch, phases, cfg, steps, warmup, batch, mode, tune,
-                 time_kernels=TIME_EVERY, label="main", tune_sample=1 << 24):
+                 time_kernels=TIME_EVERY, label="main", tune_sample=1 << 24, geometry=None):
     """Time `steps` churn rounds (see the module docstring).  With `tune`,
     a warm-up context (setup phase, then 1M-update batches of round 0 so
     that it has measured its host time per batch) runs the autotuner on a
     sample of round 0, and the timed contexts use the tuned geometry and
     batch target instead of `batch`.  Returns (seconds, updates, counters
-    of the timed rounds, tune result, batch used)."""
+    of the timed rounds, tune result, batch used).  `geometry` (tile
+    vertices, LDS rows, chunk records) fixes the launch configuration
+    instead of tuning it."""
     Vc = cfg["V"]
     Cc = streamgen_ceil_log2(Vc)
     nr = len(phases) - 1
     tuned = {}
     geo = {}
+    if geometry:
+        geo = dict(zip(("tile_vertices", "lds_rows", "chunk_records"), geometry))
+        tune = False
 
     def new_ctx(bsz):
         ctx = cupk.Context(Vc, Cc, 2 * Cc, cfg["S"], scatter_mode=mode, max_batch=bsz,
@@ -820,8 +834,10 @@ def clusters_main(args, cupk, np, torch, streamgen):
     round_len = [int(p.shape[0]) for p in phases[1:]]
     mode = cupk.SCATTER_STAGED if args.mode == "staged" else cupk.SCATTER_ATOMIC
     print("bench: timing main path", file=sys.stderr, flush=True)
+    geometry = tuple(int(x) for x in args.geometry.split(",")) if args.geometry else None
     dt, total, ctr, tuned, batch = run_clusters(cupk, torch, phases, cfg, args.steps, args.warmup,
-                                                batch, mode, tune=not args.no_tune)
+                                                batch, mode, tune=not args.no_tune,
+                                                geometry=geometry)
     value = total / dt
     kname = "k_tile_scatter" if args.mode == "staged" else "k_scatter_atomic"
     launches = max(1, ctr["timed_launches"])
@@ -831,17 +847,28 @@ def clusters_main(args, cupk, np, torch, streamgen):
     if args.mode == "staged":
         buckets = ctr["timed_buckets"] / launches
         comp = 8 * upd_per_launch + 32 * buckets
-        achieved = comp / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        comp_gbs = comp / (avg_ms * 1e-3) / 1e9
+        alu_ops = HASH_LANE_OPS * Cc * upd_per_launch
+        alu_t = alu_ops / (avg_ms * 1e-3) / 1e12
+        alu_peak = ALU_PEAK_LANE_OPS / 1e12
+        roof = {"bound": "alu", "achieved": round(alu_t, 2), "peak": round(alu_peak, 2),
+                "unit": "Tops/s", "frac": round(alu_t / alu_peak, 4),
                 "traffic": prof.get("hbm_bytes_per_launch") if prof else None,
                 "kernel": kname, "kernel_avg_ms": round(avg_ms, 5),
-                "basis": "compulsory bytes per launch: 8 B per update + 32 B (16 B read + "
-                         "16 B written) per bucket the launch changed in HBM, counted by the "
-                         "kernel on the timed launches",
-                "compulsory_bytes_per_launch": round(comp),
-                "compulsory_bytes_per_update": round(comp / max(1.0, upd_per_launch), 1),
-                "buckets_changed_per_launch": round(buckets),
+                "basis": f"algorithmic ALU work per launch: one column hash per (update, "
+                         f"column), {HASH_LANE_OPS} 32-bit lane operations each (the SplitMix64 "
+                         f"finalizer with its seed XOR on gfx950), C = {Cc}; peak 256 CU x 64 "
+                         f"lanes x 2.4 GHz",
+                "alu_ops_per_launch": round(alu_ops),
+                "hbm": {"achieved": round(comp_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(comp_gbs / HBM_PEAK_GBS, 4),
+                        "basis": "compulsory bytes per launch: 8 B per update + 32 B (16 B "
+                                 "read + 16 B written) per bucket the launch changed in HBM, "
+                                 "counted by the kernel on the timed launches",
+                        "compulsory_bytes_per_launch": round(comp),
+                        "compulsory_bytes_per_update": round(comp / max(1.0, upd_per_launch),
+                                                             1),
+                        "buckets_changed_per_launch": round(buckets)},
                 "updates_per_launch": round(upd_per_launch, 1),
                 "timed_launches": ctr["timed_launches"], "timed_every": TIME_EVERY,
                 "bin_avg_ms": round(ctr["bin_ms"] / launches, 5),
@@ -851,15 +878,15 @@ def clusters_main(args, cupk, np, torch, streamgen):
                                      "update (every bucket update a 16 B read + write); not a "
                                      "roofline fraction"}
         if prof:
-            roof["traffic_frac"] = round(prof["hbm_bytes_per_launch"] / (avg_ms * 1e-3) /
-                                         (HBM_PEAK_GBS * 1e9), 4)
+            roof["hbm"]["traffic_frac"] = round(prof["hbm_bytes_per_launch"] /
+                                                (avg_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
             if prof.get("valu_insts_per_launch"):
                 vi = prof["valu_insts_per_launch"]
                 roof["valu"] = {"insts_per_launch": vi,
                                 "issue_frac": round(vi / (avg_ms * 1e-3) / VALU_PEAK_WAVE_INSTS,
                                                     4),
-                                "peak": "256 CU x 4 SIMD x 2.4 GHz = 2.46e12 wave "
-                                        "instructions/s"}
+                                "peak": "256 CU x 2.4 GHz = 6.14e11 wave instructions/s (one "
+                                        "64-lane instruction per CU per clock)"}
     else:
         bpu = algorithmic_bytes_per_update(Cc)
         achieved = bpu * upd_per_launch / (avg_ms * 1e-3) / 1e9
@@ -891,6 +918,9 @@ def clusters_main(args, cupk, np, torch, streamgen):
         "counters": {k: (round(val, 3) if isinstance(val, float) else val)
                      for k, val in ctr.items()},
     }
+    if geometry:
+        out["config"]["geometry"] = dict(zip(("tile_vertices", "lds_rows", "chunk_records"),
+                                             geometry))
     if tuned:
         out["config"]["tuned"] = {k: tuned[k] for k in ("tile_vertices", "lds_rows",
                                                         "chunk_records", "batch_target",
@@ -954,6 +984,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2,
                     help="churn rounds timed with the plain atomic kernel")
     ap.add_argument("--no-tune", action="store_true", help="headline: keep the default geometry")
+    ap.add_argument("--geometry", default="",
+                    help="headline: TILE_VERTICES,LDS_ROWS,CHUNK_RECORDS instead of the "
+                         "autotuner's (with --batch, a fixed launch configuration for profiling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel run")
     ap.add_argument("--no-serve", action="store_true", help="skip the served run")
@@ -972,8 +1005,8 @@ def main():
                          "for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
-              "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
+              "sketch across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

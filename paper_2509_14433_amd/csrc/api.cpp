@@ -787,6 +787,7 @@ int ensure_batch_buffers(cupk_ctx *ctx, size_t n)
     }
     if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
         HIPCHK(grow(ctx->d_bins, 2 * cap));
+        if (ctx->fshift) HIPCHK(grow(ctx->d_bins1, 2 * cap));
         const size_t icap = 2 * cap / ctx->chunk + ctx->ntiles + 1;
         HIPCHK(grow(ctx->d_items, 2 * icap));
     }
@@ -800,11 +801,13 @@ int ensure_batch_buffers(cupk_ctx *ctx, size_t n)
 constexpr size_t kRelMaxWords = (size_t)1 << 25;
 static size_t rel_words(cupk_ctx *ctx, size_t n)
 {
+    // the fill that uses them bins by coarse bin in two-level mode
+    const uint32_t nt = ctx->fshift ? ctx->ncoarse : ctx->ntiles;
     if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED || ctx->opts.fill_reserve ||
-        ctx->ntiles > kRelMaxTiles)
+        nt > kRelMaxTiles)
         return 0;
     const size_t w = (size_t)classify_blocks((uint32_t)std::min<size_t>(n, kMaxBatchPerLaunch)) *
-                     ctx->ntiles;
+                     nt;
     return w <= kRelMaxWords ? w : 0;
 }
 
@@ -864,9 +867,26 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
         if (ctx->ntiles > kScanOneBlockTiles) sa.sums = ctx->d_tsum.p;
     }
     uint32_t *rel = staged ? rel_ptr(ctx, grid_n) : nullptr;
+    uint32_t *cnt = staged ? ctx->d_tcnt.p : nullptr;
+    uint32_t cls_shift = ctx->tile_shift, cls_tiles = ctx->ntiles;
+    if (staged && ctx->fshift) {
+        // two-level: the classify kernel and its scan work on coarse bins
+        // (the tile counts come later, from the coarse-binned records)
+        sa = {};
+        sa.off = ctx->d_coff.p;
+        sa.cur = ctx->d_ccur.p;
+        sa.items = ctx->d_csink.p;
+        sa.nitems = ctx->d_csink.p + 2;
+        sa.chunk = 1u << 30;
+        sa.items_cap = 0;
+        sa.groups = 1;
+        cnt = ctx->d_ccnt.p;
+        cls_shift = ctx->tile_shift + ctx->fshift;
+        cls_tiles = ctx->ncoarse;
+    }
     if (rel) {
         sa.groups = kCntGroups;
-        sa.goff = ctx->d_tgoff.p;
+        sa.goff = ctx->fshift ? ctx->d_cgoff.p : ctx->d_tgoff.p;
     }
     // short flag lists come back with the header (not in exact mode, which
     // also needs their positions)
@@ -878,17 +898,37 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
     HIPCHK(launch_classify(s, desc_ptr(ctx), ctx->cur_desc, grid_n, ctx->V, ctx->d_lbl,
                            ctx->d_par, ctx->d_hdr, ctx->d_fupd.p,
                            ctx->opts.exact ? ctx->d_fpos.p : nullptr, ctx->d_fcnt.p,
-                           staged ? ctx->d_tcnt.p : nullptr, ctx->tile_shift, ctx->ntiles, sa,
-                           ctx->h_hdr, fi, rel));
+                           cnt, cls_shift, cls_tiles, sa, ctx->h_hdr, fi, rel));
     return CUPK_OK;
 }
 
 int enqueue_bin(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
 {
     if (ctx->opts.scatter_mode != CUPK_SCATTER_STAGED) return CUPK_OK;
-    HIPCHK(launch_bin(s, desc_ptr(ctx), ctx->cur_desc, grid_n, dev_sketch(ctx), ctx->d_hdr,
-                      staged_params(ctx, grid_n), ctx->d_tcur.p, ctx->d_bins.p, ctx->d_tgoff.p,
-                      rel_ptr(ctx, grid_n)));
+    const StagedParams p = staged_params(ctx, grid_n);
+    if (!ctx->fshift) {
+        HIPCHK(launch_bin(s, desc_ptr(ctx), ctx->cur_desc, grid_n, dev_sketch(ctx), ctx->d_hdr, p,
+                          ctx->d_tcur.p, ctx->d_bins.p, ctx->d_tgoff.p, rel_ptr(ctx, grid_n)));
+        return CUPK_OK;
+    }
+    // two-level: records by coarse bin into bins1, then by tile into bins
+    StagedParams pc = p;
+    pc.tile_shift = ctx->tile_shift + ctx->fshift;
+    pc.ntiles = ctx->ncoarse;
+    HIPCHK(launch_bin(s, desc_ptr(ctx), ctx->cur_desc, grid_n, dev_sketch(ctx), ctx->d_hdr, pc,
+                      ctx->d_ccur.p, ctx->d_bins1.p, ctx->d_cgoff.p, rel_ptr(ctx, grid_n)));
+    ScanArgs sa = {};
+    sa.off = ctx->d_toff.p;
+    sa.cur = ctx->d_tcur.p;
+    sa.items = ctx->d_items.p;
+    sa.nitems = ctx->d_nitems;
+    sa.chunk = ctx->chunk;
+    sa.items_cap = p.items_cap;
+    sa.groups = 1;
+    sa.sums = ctx->d_tsum.p;
+    HIPCHK(launch_fine(s, grid_n, ctx->d_hdr, ctx->d_bins1.p, ctx->d_coff.p + ctx->ncoarse,
+                       ctx->tile_shift, ctx->fshift, ctx->ntiles, ctx->d_tcnt.p, sa,
+                       ctx->d_bins.p));
     return CUPK_OK;
 }
 
@@ -1321,6 +1361,12 @@ void destroy(cupk_ctx *ctx)
     release(ctx->d_tgoff);
     release(ctx->d_items);
     release(ctx->d_bins);
+    release(ctx->d_bins1);
+    release(ctx->d_ccnt);
+    release(ctx->d_cgoff);
+    release(ctx->d_coff);
+    release(ctx->d_ccur);
+    release(ctx->d_csink);
     release(ctx->d_ridx);
     release(ctx->h_ridx);
     release(ctx->d_sig[0]);
@@ -1349,13 +1395,30 @@ int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk)
     while ((1u << sh) < tv) sh++;
     if (tv == 0 || (1u << sh) != tv) return ctx->invalid("tile_vertices must be a power of two");
     if (rows < 1 || rows > ctx->D) return ctx->invalid("lds_rows must be in [1, D]");
-    if ((size_t)2 * rows * ctx->C * tv * 8 > 65536)
-        return ctx->invalid("staged tile exceeds 64 KiB LDS");
+    if (!tile_geometry_fits(rows, ctx->C, tv))
+        return ctx->invalid("staged tile does not fit 64 KiB of LDS with its record stage");
     if (chunk < 64) return ctx->invalid("chunk_records must be >= 64");
     ctx->tile_shift = sh;
     ctx->rows = rows;
     ctx->chunk = chunk;
     ctx->ntiles = (uint32_t)(((uint64_t)ctx->V + tv - 1) >> sh);
+    // two-level binning beyond kFillStageTiles tiles: at most 256 coarse bins
+    ctx->fshift = 0;
+    ctx->ncoarse = 0;
+    if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED && ctx->ntiles > kFillStageTiles) {
+        uint32_t f = 1;
+        while ((((uint64_t)ctx->ntiles + (1u << f) - 1) >> f) > 256) f++;
+        ctx->fshift = f;
+        ctx->ncoarse = (uint32_t)(((uint64_t)ctx->V + (1ull << (sh + f)) - 1) >> (sh + f));
+        const size_t nc = (size_t)kCntGroups * ctx->ncoarse + 1;
+        HIPCHK(grow(ctx->d_ccnt, nc));
+        HIPCHK(grow(ctx->d_cgoff, nc));
+        HIPCHK(grow(ctx->d_coff, ctx->ncoarse + 1));
+        HIPCHK(grow(ctx->d_ccur, ctx->ncoarse + 1));
+        HIPCHK(grow(ctx->d_csink, 4));
+        HIPCHK(launch_zero32(ctx->s, ctx->d_ccnt.p, nc));
+        if (ctx->batch_cap) HIPCHK(grow(ctx->d_bins1, 2 * ctx->batch_cap));
+    }
     if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED) {
         // counts: kCntGroups copies (one in use unless classify blocks also
         // store where their records start)
@@ -2061,7 +2124,7 @@ int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_r
             for (uint32_t rows : rowss)
                 for (uint32_t ch : chunks) {
                     if (rc != CUPK_OK) break;
-                    if (rows > ctx->D || (size_t)2 * rows * ctx->C * tv * 8 > 65536) continue;
+                    if (rows > ctx->D || !tile_geometry_fits(rows, ctx->C, tv)) continue;
                     if (tv == tv0 && rows == rows0 && ch == chunk0) continue;
                     rc = set_geometry(ctx, tv, rows, ch);
                     if (rc != CUPK_OK) break;

@@ -90,6 +90,13 @@ struct cupk_ctx {
     cupk::DevBuf<uint32_t> d_trel;  // per (classify block, tile): start inside the tile's bin
     cupk::DevBuf<uint32_t> d_tgoff; // per (count copy, tile): where the copy's records start
     cupk::DevBuf<uint64_t> d_bins;
+    // two-level binning (more than kFillStageTiles tiles): coarse bins of
+    // 2^fshift tiles (fshift 0: one level), their counts, count-copy
+    // starts, offsets and cursors, the coarse-binned records, and a sink
+    // for the coarse scan's (unused) work items
+    uint32_t fshift = 0, ncoarse = 0;
+    cupk::DevBuf<uint32_t> d_ccnt, d_cgoff, d_coff, d_ccur, d_csink;
+    cupk::DevBuf<uint64_t> d_bins1;
     uint32_t *d_nitems = nullptr;
     unsigned long long *d_touched = nullptr;  // buckets changed by timed staged launches
 

@@ -24,6 +24,19 @@ DEVI uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
+// The same finalizer after its first step.  That step, z ^ (z >> 30), is
+// linear over XOR, so for z = x ^ seed it equals (x ^ (x >> 30)) ^
+// (seed ^ (seed >> 30)): callers hashing one x under many seeds compute
+// the two halves once each.
+DEVI uint64_t mix64_tail(uint64_t z)
+{
+    z *= 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+DEVI uint64_t mix64_head(uint64_t z) { return z ^ (z >> 30); }
+
 // Depth of a column hash: trailing zero count, capped at D-1.
 DEVI uint32_t depth_of(uint64_t h, uint32_t D)
 {
@@ -678,14 +691,14 @@ hipError_t launch_scatter_atomic(hipStream_t s, const BatchDesc *desc, BatchDesc
 //    record of v.  Slots are reserved per block in LDS first, so global
 //    atomics are per (block, tile), not per record.
 // 3. k_tile_scatter: one work item per block iteration.  The block keeps a
-//    zeroed LDS delta of depth rows 0..rows-1 for the tile's vertices, XORs
-//    every record of the chunk into it (LDS atomics; depths >= rows go
-//    straight to HBM with device atomics), then folds the nonzero delta
+//    zeroed LDS delta of depth rows 0..rows-1 for the tile's vertices,
+//    decodes the chunk's records into LDS, XORs every (record, column)
+//    pair into the delta (LDS atomics, one lane per pair; depths >= rows
+//    go straight to HBM with device atomics), then folds the nonzero delta
 //    words into HBM: a plain read-XOR-write when the chunk is the tile's
 //    whole bin (no other block touches these vertices), a device atomic XOR
 //    otherwise.  LDS holds alpha and gamma in separate planes ordered
-//    [d][c][vertex], so lanes working on different vertices of the same
-//    (c, d) hit consecutive words.
+//    [d][vertex][c], so the C lanes of one record hit consecutive words.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kRecV = 1ull << 63;  // the record is for endpoint v
 
@@ -763,7 +776,7 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(
 // so that the lanes of a wave store one (block, tile) run after another into
 // consecutive bin words (coalesced) instead of 8-byte words scattered over
 // all tiles.  Dynamic LDS: fill_stage_lds(ntiles) bytes.
-constexpr uint32_t kFillStageTiles = 2 * kFillThreads;
+static_assert(kFillStageTiles == 2 * kFillThreads, "two tiles per fill thread");
 static size_t fill_stage_lds(uint32_t ntiles)
 {
     return (size_t)2 * kFillPerBlock * 8 + (size_t)2 * ntiles * 4 + 160 * 4;
@@ -845,44 +858,193 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill_staged(
     }
 }
 
-constexpr uint32_t kTileThreads = 256;
+// ---------------------------------------------------------------------------
+// Two-level binning, for more tiles than one block's LDS histogram serves.
+// The classify kernel counts records per coarse bin (2^fshift consecutive
+// tiles) and the fill bins them by coarse bin into `bins1` (k_tile_fill_staged
+// on coarse bins).  Then every chunk of kFinePerBlock coarse-binned records
+// spans few tiles: k_fine_count counts the chunk's records per tile in LDS
+// and adds the counts to the tile counts (one global atomic per (chunk,
+// tile)), the multi-block tile scan turns them into bin offsets and work
+// items, and k_fine_fill ranks each chunk's records per tile in LDS,
+// reserves one range per (chunk, tile) from the tile's cursor and writes
+// the records there.  A tile more than kFineLdsTiles past the chunk's first
+// coarse bin is counted and reserved per record instead.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kFineThreads = 1024;
+constexpr uint32_t kFinePer = 8;
+constexpr uint32_t kFinePerBlock = kFineThreads * kFinePer;
+constexpr uint32_t kFineLdsTiles = 8192;
 
-// XOR one (record, column) pair into the endpoint's LDS delta, or into HBM
-// for depths beyond the rows held in LDS.  lq = c*TV + (local vertex index),
-// CTV = C*TV (words per LDS depth row); gb = the endpoint's first bucket in
-// HBM.  Index products use the full-rate 24-bit multiply (d < 64 and
-// C*TV, C < 2^24).  fmask = 2^r - 1 with r <= min(rows, D-1, 31): when the
-// hash's low word has a set bit below r, the depth is that bit's index
-// (one instruction); the full depth is computed only otherwise (odds 2^-r).
-DEVI void tile_column(uint64_t *la, uint64_t *lg, uint64_t *gb, uint32_t C, uint32_t D,
-                      uint32_t CTV, uint32_t rows, uint32_t fmask, uint32_t c, uint64_t seed,
-                      uint64_t x, uint32_t lq, uint32_t &deep)
+DEVI uint32_t rec_endpoint(uint64_t rec)
 {
-    const uint64_t h = mix64(x ^ seed);
-    const uint32_t lo = (uint32_t)h;
-    uint32_t d;
-    if (lo & fmask) {
-        d = (uint32_t)__builtin_ctz(lo);
-    } else {
-        d = depth_of(h, D);
-        if (d >= rows) {
-            uint64_t *bp = gb + 2 * (__umul24(d, C & 0xffffffu) + c);
-            gxor(bp, x);
-            gxor(bp + 1, h);
-            deep++;
-            return;
-        }
-    }
-    const uint32_t q = __umul24(d, CTV) + lq;
-    lxor(&la[q], x);
-    lxor(&lg[q], h);
+    return (rec & kRecV) ? (uint32_t)(rec >> 32) & 0x7fffffffu : (uint32_t)rec;
 }
 
-// CMAX > 0: columns unrolled at compile time (C <= CMAX); CMAX == 0: a
-// runtime loop for any C.  touched (may be null) receives the number of
-// buckets the launch changes in HBM: folded buckets with a nonzero delta,
-// plus one per record column that goes to a deep row directly.
-template <uint32_t CMAX>
+__global__ __launch_bounds__(kFineThreads) void k_fine_count(
+    const uint64_t *__restrict__ bins1, const uint32_t *__restrict__ total, uint32_t tile_shift,
+    uint32_t fshift, uint32_t *__restrict__ cnt, const uint32_t *__restrict__ hdr)
+{
+    __shared__ uint32_t hist[kFineLdsTiles];
+    if (hdr[HDR_ERR]) return;
+    const uint32_t n = *total;
+    const uint32_t begin = blockIdx.x * kFinePerBlock;
+    if (begin >= n) return;
+    const uint32_t t_lo = (rec_endpoint(bins1[begin]) >> (tile_shift + fshift)) << fshift;
+    for (uint32_t j = threadIdx.x; j < kFineLdsTiles; j += kFineThreads) hist[j] = 0;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kFinePer; k++) {
+        const uint32_t i = begin + k * kFineThreads + threadIdx.x;
+        if (i >= n) continue;
+        const uint32_t t = rec_endpoint(bins1[i]) >> tile_shift;
+        if (t - t_lo < kFineLdsTiles)
+            atomicAdd(&hist[t - t_lo], 1u);
+        else
+            atomicAdd(&cnt[t], 1u);
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < kFineLdsTiles; j += kFineThreads) {
+        const uint32_t c = hist[j];
+        if (c) atomicAdd(&cnt[t_lo + j], c);
+    }
+}
+
+__global__ __launch_bounds__(kFineThreads) void k_fine_fill(
+    const uint64_t *__restrict__ bins1, const uint32_t *__restrict__ total, uint32_t tile_shift,
+    uint32_t fshift, uint32_t *__restrict__ cur, uint64_t *__restrict__ bins,
+    const uint32_t *__restrict__ hdr)
+{
+    __shared__ uint32_t hist[kFineLdsTiles];
+    if (hdr[HDR_ERR]) return;
+    const uint32_t n = *total;
+    const uint32_t begin = blockIdx.x * kFinePerBlock;
+    if (begin >= n) return;
+    const uint32_t t_lo = (rec_endpoint(bins1[begin]) >> (tile_shift + fshift)) << fshift;
+    for (uint32_t j = threadIdx.x; j < kFineLdsTiles; j += kFineThreads) hist[j] = 0;
+    __syncthreads();
+    uint64_t rec[kFinePer];
+    uint32_t pos[kFinePer];  // rank in the (chunk, tile) range, or the final position
+#pragma unroll
+    for (uint32_t k = 0; k < kFinePer; k++) {
+        const uint32_t i = begin + k * kFineThreads + threadIdx.x;
+        rec[k] = i < n ? bins1[i] : 0;
+        pos[k] = 0;
+        if (i >= n) continue;
+        const uint32_t t = rec_endpoint(rec[k]) >> tile_shift;
+        pos[k] = t - t_lo < kFineLdsTiles ? atomicAdd(&hist[t - t_lo], 1u) : atomicAdd(&cur[t], 1u);
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < kFineLdsTiles; j += kFineThreads) {
+        const uint32_t c = hist[j];
+        if (c) hist[j] = atomicAdd(&cur[t_lo + j], c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kFinePer; k++) {
+        const uint32_t i = begin + k * kFineThreads + threadIdx.x;
+        if (i >= n) continue;
+        const uint32_t t = rec_endpoint(rec[k]) >> tile_shift;
+        const uint32_t q = t - t_lo < kFineLdsTiles ? hist[t - t_lo] + pos[k] : pos[k];
+        bins[q] = rec[k];
+    }
+}
+
+hipError_t launch_fine(hipStream_t s, uint32_t grid_n, const uint32_t *hdr, const uint64_t *bins1,
+                       const uint32_t *total, uint32_t tile_shift, uint32_t fshift,
+                       uint32_t ntiles, uint32_t *tile_cnt, const ScanArgs &sa, uint64_t *bins)
+{
+    if (grid_n == 0) return hipSuccess;
+    if (!sa.sums || sa.groups != 1 || fshift == 0 || (1u << fshift) > kFineLdsTiles)
+        return hipErrorInvalidValue;
+    const uint32_t nb = (uint32_t)((2 * (uint64_t)grid_n + kFinePerBlock - 1) / kFinePerBlock);
+    k_fine_count<<<nb, kFineThreads, 0, s>>>(bins1, total, tile_shift, fshift, tile_cnt, hdr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint32_t nch = tile_scan_chunks(ntiles);
+    k_tile_sums<<<nch, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa.chunk, sa.sums);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_tile_offsets<<<nch, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_fine_fill<<<nb, kFineThreads, 0, s>>>(bins1, total, tile_shift, fshift, sa.cur, bins, hdr);
+    return hipGetLastError();
+}
+
+constexpr uint32_t kTileThreads = 512;
+constexpr uint32_t kTileWaves = kTileThreads / 64;
+constexpr uint32_t kTileLdsMax = 65536;  // dynamic LDS per block, bytes
+constexpr uint32_t kTileStage = 512;     // records staged per pass
+
+// The staged records (24 B each: edge index and the first step of its
+// hash, byte offset of the endpoint's words in an LDS depth row, local
+// vertex) must fit beside the LDS delta.
+constexpr uint32_t kStagedRecBytes = 24;
+static bool tile_stage_fits(size_t delta_bytes)
+{
+    return delta_bytes + (size_t)kTileStage * kStagedRecBytes <= kTileLdsMax;
+}
+
+bool tile_geometry_fits(uint32_t rows, uint32_t C, uint32_t tv)
+{
+    const size_t delta = (size_t)2 * rows * C * tv * sizeof(uint64_t);
+    return C >= 1 && C <= 64 && rows >= 1 && tile_stage_fits(delta);
+}
+
+struct StagedRec {
+    uint64_t x;   // edge index u*V + v of the record's update
+    uint64_t y;   // mix64_head(x)
+    uint32_t qb;  // vl*C*8: byte offset of the endpoint's words in a depth row
+    uint32_t vl;  // endpoint - first vertex of the tile
+};
+
+// XOR one (record, column) pair into the LDS delta (or HBM for a deep row).
+// colb = column * 8; RSB = bytes per LDS depth row; pg = gamma plane offset
+// in bytes; seed1 = mix64_head(column seed).  The depth is ctz of the hash's low word with a stop bit at
+// rfast = min(rows, D-1, 31); only when no bit below rfast is set (odds
+// 2^-rfast) is the full depth taken, and a depth >= rows goes to HBM with
+// device atomics.
+DEVI void tile_pair(uint8_t *lds8, uint32_t RSB, uint32_t pg, uint32_t rows, uint32_t rfast,
+                    uint32_t stop, uint32_t colb, uint64_t seed1, const StagedRec &r,
+                    const DevSketch &sk, uint32_t w0, uint64_t DC2, uint32_t &nchanged)
+{
+    const uint64_t h = mix64_tail(r.y ^ seed1);
+    const uint32_t d0 = (uint32_t)__builtin_ctz((uint32_t)h | stop);  // <= 31
+    if (d0 != rfast) {
+        const uint32_t a = __umul24(d0, RSB) + r.qb + colb;
+        lxor((uint64_t *)(lds8 + a), r.x);
+        lxor((uint64_t *)(lds8 + a + pg), h);
+        return;
+    }
+    const uint32_t d = depth_of(h, sk.D);
+    if (d < rows) {
+        // (d < 64 and RSB < 2^24: the masks let the compiler use the
+        // 24-bit multiply)
+        const uint32_t a = __umul24(d & 63u, RSB & 0xffffffu) + r.qb + colb;
+        lxor((uint64_t *)(lds8 + a), r.x);
+        lxor((uint64_t *)(lds8 + a + pg), h);
+    } else {
+        uint64_t *bp = sk.b + (uint64_t)(w0 + r.vl) * DC2 + 2 * (uint64_t)d * sk.C + colb / 4;
+        gxor(bp, r.x);
+        gxor(bp + 1, h);
+        nchanged++;
+    }
+}
+
+// One (record, column) pair per lane: the edge index x = u*V + v of the
+// record's update is hashed for column c and (x, h) is XOR-ed into bucket
+// (d, c) of the record's endpoint.  Lane l of a wave takes column l mod C of
+// record l / C (G = 64 / C records per wave step, lanes l >= G*C idle), so
+// the C lanes of a record hit C consecutive LDS words and the hash seed is a
+// per-lane constant.
+//
+// LDS: the delta's alpha and gamma planes, word d*TV*C + vl*C + c for depth
+// row d < rows, local vertex vl, column c; then the staged records.
+//
+// touched (may be null) receives the number of buckets the launch changes
+// in HBM: folded buckets with a nonzero delta, plus one per pair that goes
+// to a deep row directly.
 __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
     DevSketch sk, const uint64_t *__restrict__ bins, const uint32_t *__restrict__ off,
     const uint32_t *__restrict__ items, const uint32_t *__restrict__ nitems_p, uint32_t tile_shift,
@@ -891,24 +1053,28 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
 {
     uint32_t nchanged = 0;  // buckets this thread changed in HBM
     extern __shared__ uint64_t lds[];
+    uint8_t *lds8 = (uint8_t *)lds;
     const bool err = hdr[HDR_ERR] != 0;
     const uint32_t TV = 1u << tile_shift;
-    const uint32_t C = sk.C, D = sk.D, V = sk.V;
-    const uint32_t plane = rows * C * TV;  // words per LDS plane
-    // words per LDS depth row (< 2^24: the mask lets the compiler use the
-    // 24-bit multiply for row offsets)
-    const uint32_t CTV = (C * TV) & 0xffffffu;
-    const uint64_t DC2 = (uint64_t)D * C * 2;  // words per vertex in HBM
-    const uint32_t rfast = min(min(rows, D - 1), 31u);
-    const uint32_t fmask = (1u << rfast) - 1;
-    uint64_t *la = lds;                    // alpha plane [d][c][vl]
-    uint64_t *lg = lds + plane;            // gamma plane
+    const uint32_t C = sk.C, V = sk.V;
+    const uint32_t RS = TV * C;             // words per LDS depth row (< 2^12)
+    const uint32_t plane = rows * RS;       // words per LDS plane
+    const uint64_t DC2 = (uint64_t)sk.D * C * 2;  // words per vertex in HBM
+    const uint32_t rfast = min(min(rows, sk.D - 1), 31u);
+    const uint32_t stop = 1u << rfast;
+    const uint64_t *la = lds;               // alpha plane
+    const uint64_t *lg = lds + plane;       // gamma plane
+    StagedRec *st = (StagedRec *)(lds + 2 * plane);
     const uint32_t nitems = err ? 0u : *nitems_p;
-    uint64_t seed[CMAX > 0 ? CMAX : 1];
-    if (CMAX > 0) {
-#pragma unroll
-        for (uint32_t c = 0; c < CMAX; c++) seed[c] = c < C ? sk.seeds[c] : 0;
-    }
+
+    const uint32_t lane = __lane_id(), wid = threadIdx.x / 64;
+    const uint32_t G = 64 / C;              // records (or rows) per wave step
+    const uint32_t WG = kTileWaves * G;     // records per block step
+    const uint32_t slot = lane / C;
+    const uint32_t col = lane - slot * C;
+    const bool active = slot < G;
+    const uint32_t colb = col * 8;
+    const uint64_t seed1 = active ? mix64_head(sk.seeds[col]) : 0;
 
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const uint32_t tile = items[2 * it];
@@ -918,52 +1084,72 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_scatter(
         const uint32_t ce = min(re, cb + chunk);
         const bool single = (re - rb) <= chunk;
         const uint32_t w0 = tile << tile_shift;
+        if (cb >= ce) continue;  // (block-uniform) nothing to fold
 
-        for (uint32_t q = threadIdx.x; q < 2 * plane; q += blockDim.x) lds[q] = 0;
-        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < 2 * plane; q += kTileThreads) lds[q] = 0;
 
-        for (uint32_t r = cb + threadIdx.x; r < ce; r += blockDim.x) {
-            const uint64_t rec = bins[r];
-            const uint32_t u = (uint32_t)rec, v = (uint32_t)(rec >> 32) & 0x7fffffffu;
-            const uint64_t x = (uint64_t)u * V + v;
-            // the record's endpoint in this tile
-            const uint32_t p = (rec & kRecV) ? v : u;
-            uint64_t *gb = sk.b + (uint64_t)p * DC2;
-            if (CMAX > 0) {
-#pragma unroll
-                for (uint32_t c = 0; c < (CMAX > 0 ? CMAX : 1); c++)
-                    if (c < C)
-                        tile_column(la, lg, gb, C, D, CTV, rows, fmask, c, seed[c], x,
-                                    c * TV + (p - w0), nchanged);
-            } else {
-                for (uint32_t c = 0; c < C; c++)
-                    tile_column(la, lg, gb, C, D, CTV, rows, fmask, c, sk.seeds[c], x,
-                                c * TV + (p - w0), nchanged);
+        for (uint32_t sb = cb; sb < ce; sb += kTileStage) {
+            const uint32_t ns = min(kTileStage, ce - sb);
+            // stage: decode each record once
+            for (uint32_t i = threadIdx.x; i < ns; i += kTileThreads) {
+                const uint64_t rec = bins[sb + i];
+                const uint32_t u = (uint32_t)rec, v = (uint32_t)(rec >> 32) & 0x7fffffffu;
+                const uint32_t vl = ((rec & kRecV) ? v : u) - w0;
+                StagedRec r;
+                r.x = (uint64_t)u * V + v;
+                r.y = mix64_head(r.x);
+                r.qb = __umul24(vl, C) * 8;
+                r.vl = vl;
+                st[i] = r;
             }
+            __syncthreads();
+            if (active) {
+                // full block steps need no bound check; the last one does
+                const uint32_t full = ns / WG * WG;
+                uint32_t i = wid * G + slot;
+                for (; i + WG < full; i += 2 * WG) {
+                    const StagedRec r0 = st[i], r1 = st[i + WG];
+                    tile_pair(lds8, RS * 8, plane * 8, rows, rfast, stop, colb, seed1, r0, sk,
+                              w0, DC2, nchanged);
+                    tile_pair(lds8, RS * 8, plane * 8, rows, rfast, stop, colb, seed1, r1, sk,
+                              w0, DC2, nchanged);
+                }
+                if (i < full) {
+                    tile_pair(lds8, RS * 8, plane * 8, rows, rfast, stop, colb, seed1, st[i], sk,
+                              w0, DC2, nchanged);
+                    i += WG;
+                }
+                if (i < ns)
+                    tile_pair(lds8, RS * 8, plane * 8, rows, rfast, stop, colb, seed1, st[i], sk,
+                              w0, DC2, nchanged);
+            }
+            __syncthreads();
         }
-        __syncthreads();
 
-        // Fold the delta into HBM, walking buckets in HBM order
-        // (vertex, d, c) so that consecutive lanes touch consecutive words.
-        // (Issuing several buckets' loads before their stores, to overlap
-        // the read-modify-writes, measured slower at V = 2^20.)
-        const uint32_t nvt = min(TV, V - w0);
-        const uint32_t per_v = rows * C;
-        const uint32_t nb = nvt * per_v;
-        for (uint32_t q = threadIdx.x; q < nb; q += blockDim.x) {
-            const uint32_t vl = q / per_v;
-            const uint32_t rc = q - vl * per_v;  // d*C + c
-            const uint64_t da = la[rc * TV + vl];
-            const uint64_t dg = lg[rc * TV + vl];
-            if ((da | dg) == 0) continue;
-            nchanged++;
-            uint64_t *g = sk.b + (((uint64_t)(w0 + vl) * D) * C + rc) * 2;
-            if (single) {
-                g[0] ^= da;
-                g[1] ^= dg;
-            } else {
-                if (da) gxor(g, da);
-                if (dg) gxor(g + 1, dg);
+        // Fold the delta into HBM: lanes (slot, column) of a wave take G
+        // vertices at a time and walk their depth rows, so each step reads
+        // C consecutive words per row in LDS and C consecutive buckets
+        // (16 B each) per row in HBM.
+        if (active) {
+            const uint32_t nvt = min(TV, V - w0);
+            for (uint32_t vl = wid * G + slot; vl < nvt; vl += WG) {
+                uint32_t q = __umul24(vl, C) + col;
+                uint64_t *g = sk.b + (uint64_t)(w0 + vl) * DC2 + 2 * col;
+                for (uint32_t d = 0; d < rows; d++, q += RS, g += 2 * C) {
+                    const uint64_t da = la[q], dg = lg[q];
+                    if ((da | dg) == 0) continue;
+                    nchanged++;
+                    if (single) {
+                        ulonglong2 *g2 = (ulonglong2 *)g;
+                        ulonglong2 b = *g2;
+                        b.x ^= da;
+                        b.y ^= dg;
+                        *g2 = b;
+                    } else {
+                        if (da) gxor(g, da);
+                        if (dg) gxor(g + 1, dg);
+                    }
+                }
             }
         }
         __syncthreads();
@@ -1003,19 +1189,13 @@ hipError_t launch_tile(hipStream_t s, DevSketch sk, uint32_t *hdr, const StagedP
                        const uint32_t *tile_off, const uint64_t *bins, const uint32_t *items,
                        const uint32_t *nitems, unsigned long long *touched)
 {
-    const size_t lds = (size_t)2 * p.rows * sk.C * (1u << p.tile_shift) * sizeof(uint64_t);
+    const size_t delta = (size_t)2 * p.rows * sk.C * (1u << p.tile_shift) * sizeof(uint64_t);
+    if (sk.C > 64 || !tile_stage_fits(delta)) return hipErrorInvalidValue;
+    const size_t lds = delta + (size_t)kTileStage * kStagedRecBytes;
     // Persistent grid: a few blocks per CU, each looping over work items.
     const uint32_t grid = min(p.items_cap, p.grid ? p.grid : 256u * 8u);
-#define CUPK_TILE_LAUNCH(CM)                                                                  \
-    k_tile_scatter<CM><<<grid, kTileThreads, lds, s>>>(sk, bins, tile_off, items, nitems,     \
-                                                       p.tile_shift, p.rows, p.chunk, hdr,   \
-                                                       touched)
-    if (sk.C <= 8) CUPK_TILE_LAUNCH(8);
-    else if (sk.C <= 16) CUPK_TILE_LAUNCH(16);
-    else if (sk.C <= 24) CUPK_TILE_LAUNCH(24);
-    else if (sk.C <= 32) CUPK_TILE_LAUNCH(32);
-    else CUPK_TILE_LAUNCH(0);
-#undef CUPK_TILE_LAUNCH
+    k_tile_scatter<<<grid, kTileThreads, lds, s>>>(sk, bins, tile_off, items, nitems, p.tile_shift,
+                                                   p.rows, p.chunk, hdr, touched);
     return hipGetLastError();
 }
 

@@ -159,6 +159,21 @@ hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32
 hipError_t launch_tile(hipStream_t s, DevSketch sk, uint32_t *hdr, const StagedParams &p,
                        const uint32_t *tile_off, const uint64_t *bins, const uint32_t *items,
                        const uint32_t *nitems, unsigned long long *touched);
+// Second level of the two-level binning (used when there are more tiles
+// than kFillStageTiles): bins1 holds the batch's records binned by coarse
+// bin (2^fshift tiles each; the classify kernel counted them and the fill
+// wrote them), total points at their number (the coarse scan's last
+// offset).  Counts them per tile into tile_cnt, scans with the multi-block
+// tile scan into sa (one count copy, sa.sums set) and writes them into
+// their tile bins in `bins`.
+constexpr uint32_t kFillStageTiles = 2048;
+hipError_t launch_fine(hipStream_t s, uint32_t grid_n, const uint32_t *hdr, const uint64_t *bins1,
+                       const uint32_t *total, uint32_t tile_shift, uint32_t fshift,
+                       uint32_t ntiles, uint32_t *tile_cnt, const ScanArgs &sa, uint64_t *bins);
+// Whether a staged-scatter geometry fits one block's LDS: the delta of
+// `rows` depth rows x C columns x tv vertices (alpha and gamma), plus room
+// to stage at least one block's worth of decoded records.
+bool tile_geometry_fits(uint32_t rows, uint32_t C, uint32_t tv);
 
 // Fill n words with zero.
 hipError_t launch_zero(hipStream_t s, uint64_t *p, size_t n);
