@@ -99,16 +99,26 @@ TIME_EVERY = 8
 
 
 def run_path(cupk, torch, packed, sizes, steps, warmup, mode, time_kernels=TIME_EVERY,
-             graph=False):
-    """Warm up, then time `steps` batches.  Returns (seconds, updates, ctr)."""
+             graph=False, tune=False):
+    """Warm up, then time `steps` batches.  With `tune` (staged mode), the
+    scatter geometry comes from the autotuner run on the stream's second
+    batch by a context that has applied the first.  Returns (seconds,
+    updates, ctr, geometry or None)."""
     offs = [0]
     for s in sizes:
         offs.append(offs[-1] + s)
     nb = len(sizes)
+    geo = {}
+    if tune and nb > 1:
+        t = cupk.Context(V, C, D, SEED, scatter_mode=mode, max_batch=BATCH)
+        t.apply_updates_device(packed[offs[0]:offs[1]])
+        res = t.autotune(packed[offs[1]:offs[2]].contiguous())
+        t.close()
+        geo = {k: res[k] for k in ("tile_vertices", "lds_rows", "chunk_records", "tile_layout")}
 
     def new_ctx():
         return cupk.Context(V, C, D, SEED, scatter_mode=mode, max_batch=BATCH,
-                            time_kernels=time_kernels, use_graph=graph)
+                            time_kernels=time_kernels, use_graph=graph, **geo)
 
     # warmup on a throwaway context (code objects, buffers, clocks)
     w = new_ctx()
@@ -139,7 +149,7 @@ def run_path(cupk, torch, packed, sizes, steps, warmup, mode, time_kernels=TIME_
             ctr[k] = ctr.get(k, 0) + val
     for c in ctxs:
         c.close()
-    return dt, total, ctr
+    return dt, total, ctr, (geo or None)
 
 
 def cpu_baseline(u, v, d, sizes, budget_s=15.0):
@@ -506,8 +516,9 @@ def er16384_leg(args, cupk, np, torch, streamgen):
 
     mode = cupk.SCATTER_STAGED if args.mode == "staged" else cupk.SCATTER_ATOMIC
     print("bench: timing main path", file=sys.stderr, flush=True)
-    dt, total, ctr = run_path(cupk, torch, packed, sizes, args.steps, args.warmup, mode,
-                              graph=bool(args.graph))
+    dt, total, ctr, geo = run_path(cupk, torch, packed, sizes, args.steps, args.warmup, mode,
+                                   graph=bool(args.graph),
+                                   tune=args.mode == "staged" and not args.no_tune)
     value = total / dt
     bpu = algorithmic_bytes_per_update(C)
     # the timed launches (every TIME_EVERY-th of the timed region)
@@ -533,15 +544,16 @@ def er16384_leg(args, cupk, np, torch, streamgen):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "V": V, "C": C, "D": D, "batch": BATCH,
-                   "scatter": args.mode, "graph": bool(args.graph), "parallelism": "single GPU"},
+                   "scatter": args.mode, "graph": bool(args.graph), "parallelism": "single GPU",
+                   "geometry": geo},
         "roofline": roofline,
         "counters": {k: (round(val, 3) if isinstance(val, float) else val)
                      for k, val in ctr.items()},
     }
     if not args.no_plain and args.mode == "staged":
         print("bench: timing plain path", file=sys.stderr, flush=True)
-        pdt, ptot, pctr = run_path(cupk, torch, packed, sizes, args.steps, args.warmup,
-                                   cupk.SCATTER_ATOMIC)
+        pdt, ptot, pctr, _ = run_path(cupk, torch, packed, sizes, args.steps, args.warmup,
+                                      cupk.SCATTER_ATOMIC)
         pl = max(1, pctr["timed_launches"])
         pavg = pctr["scatter_ms"] / pl
         pach = bpu * (pctr["timed_updates"] / pl) / (pavg * 1e-3) / 1e9
@@ -597,7 +609,8 @@ def _ctr_delta(c1, c0):
 
 
 def run_clusters(cupk, torch, phases, cfg, steps, warmup, batch, mode, tune,
-                 time_kernels=TIME_EVERY, label="main", tune_sample=1 << 24, geometry=None):
+                 time_kernels=TIME_EVERY, label="main", tune_sample=1 << 24, geometry=None,
+                 keep_batch=False):
     """Time `steps` churn rounds (see the module docstring).  With `tune`,
     a warm-up context (setup phase, then 1M-update batches of round 0 so
     that it has measured its host time per batch) runs the autotuner on a
@@ -605,19 +618,26 @@ def run_clusters(cupk, torch, phases, cfg, steps, warmup, batch, mode, tune,
     batch target instead of `batch`.  Returns (seconds, updates, counters
     of the timed rounds, tune result, batch used).  `geometry` (tile
     vertices, LDS rows, chunk records) fixes the launch configuration
-    instead of tuning it."""
+    instead of tuning it; `keep_batch` keeps `batch` and takes only the
+    tuned geometry."""
     Vc = cfg["V"]
     Cc = streamgen_ceil_log2(Vc)
     nr = len(phases) - 1
     tuned = {}
     geo = {}
     if geometry:
-        geo = dict(zip(("tile_vertices", "lds_rows", "chunk_records"), geometry))
+        geo = dict(zip(("tile_vertices", "lds_rows", "chunk_records", "tile_layout"), geometry))
         tune = False
 
-    def new_ctx(bsz):
+    def new_ctx(bsz, timed=False):
+        # timed contexts sample every k-th launch, k chosen so that the
+        # timed rounds hold at least four timed launches
+        k = time_kernels
+        if timed and time_kernels:
+            nb = steps * max(1, -(-int(phases[1].shape[0]) // bsz))
+            k = max(1, min(time_kernels, nb // 4))
         ctx = cupk.Context(Vc, Cc, 2 * Cc, cfg["S"], scatter_mode=mode, max_batch=bsz,
-                           time_kernels=time_kernels, **geo)
+                           time_kernels=k, **geo)
         _apply_phase(ctx, phases[0], bsz)
         ctx.sync()
         return ctx
@@ -633,8 +653,9 @@ def run_clusters(cupk, torch, phases, cfg, steps, warmup, batch, mode, tune,
             sample = phases[1][start:start + min(tune_sample, phases[1].shape[0] - start)]
             tuned = w.autotune(sample.contiguous())
             geo = {"tile_vertices": tuned["tile_vertices"], "lds_rows": tuned["lds_rows"],
-                   "chunk_records": tuned["chunk_records"]}
-            batch = tuned["batch_target"]
+                   "chunk_records": tuned["chunk_records"], "tile_layout": tuned["tile_layout"]}
+            if not keep_batch:
+                batch = tuned["batch_target"]
             print(f"bench: {label} tuned {geo} batch {batch} (host "
                   f"{tuned['host_ms_per_batch']:.2f} ms per batch)", file=sys.stderr, flush=True)
         for i in range(warmup):
@@ -647,7 +668,7 @@ def run_clusters(cupk, torch, phases, cfg, steps, warmup, batch, mode, tune,
             print(f"bench: {label} warmup round {i % nr}", file=sys.stderr, flush=True)
         w.close()
     n_ctx = max(1, (steps + nr - 1) // nr)
-    ctxs = [new_ctx(batch) for _ in range(n_ctx)]
+    ctxs = [new_ctx(batch, timed=True) for _ in range(n_ctx)]
     c0 = [c.counters() for c in ctxs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -837,7 +858,8 @@ def clusters_main(args, cupk, np, torch, streamgen):
     geometry = tuple(int(x) for x in args.geometry.split(",")) if args.geometry else None
     dt, total, ctr, tuned, batch = run_clusters(cupk, torch, phases, cfg, args.steps, args.warmup,
                                                 batch, mode, tune=not args.no_tune,
-                                                geometry=geometry)
+                                                geometry=geometry,
+                                                tune_sample=args.tune_sample)
     value = total / dt
     kname = "k_tile_scatter" if args.mode == "staged" else "k_scatter_atomic"
     launches = max(1, ctr["timed_launches"])
@@ -870,7 +892,7 @@ def clusters_main(args, cupk, np, torch, streamgen):
                                                              1),
                         "buckets_changed_per_launch": round(buckets)},
                 "updates_per_launch": round(upd_per_launch, 1),
-                "timed_launches": ctr["timed_launches"], "timed_every": TIME_EVERY,
+                "timed_launches": ctr["timed_launches"],
                 "bin_avg_ms": round(ctr["bin_ms"] / launches, 5),
                 "algorithmic_GBs": round(algorithmic_bytes_per_update(Cc) * upd_per_launch /
                                          (avg_ms * 1e-3) / 1e9, 1),
@@ -919,22 +941,27 @@ def clusters_main(args, cupk, np, torch, streamgen):
                      for k, val in ctr.items()},
     }
     if geometry:
-        out["config"]["geometry"] = dict(zip(("tile_vertices", "lds_rows", "chunk_records"),
-                                             geometry))
+        out["config"]["geometry"] = dict(zip(("tile_vertices", "lds_rows", "chunk_records",
+                                              "tile_layout"), geometry))
     if tuned:
-        out["config"]["tuned"] = {k: tuned[k] for k in ("tile_vertices", "lds_rows",
+        out["config"]["tuned"] = {k: tuned[k] for k in ("tile_layout", "tile_vertices", "lds_rows",
                                                         "chunk_records", "batch_target",
                                                         "host_ms_per_batch", "batch_sizes",
                                                         "batch_ms")}
     if not args.no_plain and args.mode == "staged":
         psteps = max(1, min(args.steps, args.plain_steps))
         print("bench: timing staged kernel in fixed 1M batches", file=sys.stderr, flush=True)
-        sdt, stot, sctr, _, _ = run_clusters(cupk, torch, phases, cfg, psteps, 0, BATCH4, mode,
-                                             tune=False, label="staged_1M")
+        sdt, stot, sctr, stuned, _ = run_clusters(cupk, torch, phases, cfg, psteps, 0, BATCH4,
+                                                  mode, tune=not args.no_tune,
+                                                  label="staged_1M", keep_batch=True,
+                                                  tune_sample=BATCH4)
         sl = max(1, sctr["timed_launches"])
         savg = sctr["scatter_ms"] / sl
         scomp = (8 * sctr["timed_updates"] + 32 * sctr["timed_buckets"]) / sl
         out["staged_1M"] = {"value": round(stot / sdt, 1), "unit": "updates/s", "steps": psteps,
+                            "geometry": ({k: stuned[k] for k in ("tile_layout", "tile_vertices",
+                                                                 "lds_rows", "chunk_records")}
+                                         if stuned else None),
                             "ms_per_step": round(sdt * 1e3 / psteps, 3), "batch": BATCH4,
                             "kernel_avg_ms": round(savg, 5),
                             "compulsory_bytes_per_launch": round(scomp),
@@ -984,9 +1011,13 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2,
                     help="churn rounds timed with the plain atomic kernel")
     ap.add_argument("--no-tune", action="store_true", help="headline: keep the default geometry")
+    ap.add_argument("--tune-sample", type=int, default=1 << 26,
+                    help="headline: updates in the autotuner's sample (the largest batch it "
+                         "can choose), taken from churn round 0 after 8M updates of history")
     ap.add_argument("--geometry", default="",
-                    help="headline: TILE_VERTICES,LDS_ROWS,CHUNK_RECORDS instead of the "
-                         "autotuner's (with --batch, a fixed launch configuration for profiling)")
+                    help="headline: TILE_VERTICES,LDS_ROWS,CHUNK_RECORDS[,LAYOUT] instead of "
+                         "the autotuner's (with --batch, a fixed launch configuration for "
+                         "profiling; LAYOUT 1 = record, 2 = pair)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel run")
     ap.add_argument("--no-serve", action="store_true", help="skip the served run")

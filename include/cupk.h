@@ -68,6 +68,10 @@ extern "C" {
 #define CUPK_SCATTER_ATOMIC 0 /* plain kernel: one device atomic XOR per word  */
 #define CUPK_SCATTER_STAGED 1 /* vertex-binned, LDS-staged kernel              */
 
+/* ---- staged-scatter lane layouts --------------------------------------- */
+#define CUPK_LAYOUT_RECORD 1  /* one lane per record, its C columns in turn    */
+#define CUPK_LAYOUT_PAIR 2    /* one lane per (record, column) pair            */
+
 typedef struct cupk_ctx cupk_ctx;
 
 /* One sketch bucket: XOR of indices and XOR of their checksums. */
@@ -161,6 +165,14 @@ typedef struct {
      * fill reserves), so that the fill reserves nothing.  Same bins up to
      * the order of records inside a tile, same sketch. */
     uint32_t fill_reserve;
+    /* Lane layout of the staged scatter: CUPK_LAYOUT_RECORD (each lane
+     * hashes one record's C columns as independent chains; LDS address
+     * conflicts grow with the records per vertex and batch) or
+     * CUPK_LAYOUT_PAIR (each lane one (record, column) pair, records decoded
+     * once into LDS; conflict-free, for large batches).  0 = default: PAIR
+     * when max_batch is at least 4M updates, else RECORD.  The autotuner
+     * tries both. */
+    uint32_t tile_layout;
 } cupk_opts;
 
 /* Counters, cumulative since init. */
@@ -413,6 +425,7 @@ typedef struct {
     double batch_ms[8];        /* device time of prefixes n/128, ... , n       */
     uint32_t batch_sizes[8];
     double host_ms_per_batch;  /* host time per batch the schedule assumed     */
+    uint32_t tile_layout;      /* chosen CUPK_LAYOUT_*                         */
 } cupk_tune_result;
 
 int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_result *out);

@@ -9,7 +9,7 @@ library's C++ host runtime.  This package is the thin Python binding.
 from ._binding import (  # noqa: F401
     Context, CupkError, pack_updates, lib, LIB_PATH,
     OK, EMPTY, SAMPLE_FAILED, EINVAL, ENOMEM, EDEVICE, EBUSY,
-    SCATTER_ATOMIC, SCATTER_STAGED,
+    SCATTER_ATOMIC, SCATTER_STAGED, LAYOUT_RECORD, LAYOUT_PAIR,
 )
 
 sketch_init = Context

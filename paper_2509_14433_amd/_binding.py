@@ -28,6 +28,7 @@ LIB_PATH = os.path.join(_HERE, "libcupk.so")
 OK, EMPTY, SAMPLE_FAILED = 0, 1, 2
 EINVAL, ENOMEM, EDEVICE, EBUSY = -1, -2, -3, -4
 SCATTER_ATOMIC, SCATTER_STAGED = 0, 1
+LAYOUT_RECORD, LAYOUT_PAIR = 1, 2
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -57,6 +58,7 @@ class cupk_opts(ctypes.Structure):
         ("walk_plain", ctypes.c_uint32),
         ("split_rounds", ctypes.c_uint32),
         ("fill_reserve", ctypes.c_uint32),
+        ("tile_layout", ctypes.c_uint32),
     ]
 
 
@@ -94,7 +96,8 @@ class cupk_tune_result(ctypes.Structure):
                 ("chunk_records", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
                 ("best_ms", ctypes.c_double), ("before_ms", ctypes.c_double),
                 ("batch_target", ctypes.c_uint32), ("batch_ms", ctypes.c_double * 8),
-                ("batch_sizes", ctypes.c_uint32 * 8), ("host_ms_per_batch", ctypes.c_double)]
+                ("batch_sizes", ctypes.c_uint32 * 8), ("host_ms_per_batch", ctypes.c_double),
+                ("tile_layout", ctypes.c_uint32)]
 
 
 class cupk_static_info(ctypes.Structure):
@@ -182,7 +185,8 @@ class Context:
     def __init__(self, V, C=0, D=0, seed=0, scatter_mode=SCATTER_STAGED, max_batch=0,
                  stream=None, use_torch_memory=True, time_kernels=False, tile_vertices=0,
                  lds_rows=0, chunk_records=0, tile_grid=0, use_graph=False, exact=False,
-                 levels=False, walk_plain=False, split_rounds=False, fill_reserve=False):
+                 levels=False, walk_plain=False, split_rounds=False, fill_reserve=False,
+                 tile_layout=0):
         self._h = None
         self._sk_tensor = None
         self._keep = {}
@@ -201,6 +205,7 @@ class Context:
         opts.walk_plain = 1 if walk_plain else 0
         opts.split_rounds = 1 if split_rounds else 0
         opts.fill_reserve = 1 if fill_reserve else 0
+        opts.tile_layout = tile_layout
         torch = _torch()
         if stream is None and torch is not None and torch.cuda.is_available():
             # launch on torch's current stream so that torch-produced device

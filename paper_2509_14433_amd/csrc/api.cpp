@@ -839,6 +839,7 @@ StagedParams staged_params(cupk_ctx *ctx, uint32_t grid_n)
     StagedParams p;
     p.tile_shift = ctx->tile_shift;
     p.rows = ctx->rows;
+    p.layout = ctx->layout == CUPK_LAYOUT_PAIR ? kLayoutPair : kLayoutRecord;
     p.ntiles = ctx->ntiles;
     p.chunk = ctx->chunk;
     p.items_cap = (uint32_t)(2 * (size_t)grid_n / ctx->chunk + ctx->ntiles + 1);
@@ -1388,19 +1389,23 @@ void destroy(cupk_ctx *ctx)
 
 // Staged-scatter geometry: tv vertices per tile (power of two), `rows` depth
 // rows in LDS, `chunk` records per work item.
-int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk)
+int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk, uint32_t layout)
 {
+    if (layout != CUPK_LAYOUT_RECORD && layout != CUPK_LAYOUT_PAIR)
+        return ctx->invalid("tile_layout must be CUPK_LAYOUT_RECORD or CUPK_LAYOUT_PAIR");
     drop_graphs(ctx);  // captured graphs embed the geometry and buffers
     uint32_t sh = 0;
     while ((1u << sh) < tv) sh++;
     if (tv == 0 || (1u << sh) != tv) return ctx->invalid("tile_vertices must be a power of two");
     if (rows < 1 || rows > ctx->D) return ctx->invalid("lds_rows must be in [1, D]");
-    if (!tile_geometry_fits(rows, ctx->C, tv))
-        return ctx->invalid("staged tile does not fit 64 KiB of LDS with its record stage");
+    if (!tile_geometry_fits(rows, ctx->C, tv, layout))
+        return ctx->invalid("staged tile does not fit 64 KiB of LDS (with the record stage of "
+                            "the pair layout)");
     if (chunk < 64) return ctx->invalid("chunk_records must be >= 64");
     ctx->tile_shift = sh;
     ctx->rows = rows;
     ctx->chunk = chunk;
+    ctx->layout = layout;
     ctx->ntiles = (uint32_t)(((uint64_t)ctx->V + tv - 1) >> sh);
     // two-level binning beyond kFillStageTiles tiles: at most 256 coarse bins
     ctx->fshift = 0;
@@ -1523,7 +1528,11 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
         while ((size_t)2 * rows * C * (tv * 2) * 8 <= 32768 && tv < 16) tv *= 2;
     }
     ctx->tile_grid = ctx->opts.tile_grid;
-    int rc0 = set_geometry(ctx, tv, rows, ctx->opts.chunk_records ? ctx->opts.chunk_records : 4096);
+    uint32_t layout = ctx->opts.tile_layout;
+    if (layout == 0)
+        layout = ctx->opts.max_batch >= (4u << 20) ? CUPK_LAYOUT_PAIR : CUPK_LAYOUT_RECORD;
+    int rc0 = set_geometry(ctx, tv, rows, ctx->opts.chunk_records ? ctx->opts.chunk_records : 4096,
+                           layout);
     if (rc0 != CUPK_OK) return rc0;
     const size_t mb = ctx->opts.max_batch ? ctx->opts.max_batch : (1u << 20);
     int rc = ensure_batch_buffers(ctx, mb);
@@ -2111,34 +2120,45 @@ int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_r
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         const uint32_t tv0 = 1u << ctx->tile_shift, rows0 = ctx->rows, chunk0 = ctx->chunk;
+        const uint32_t lay0 = ctx->layout;
         const uint32_t m = (uint32_t)n;
         double before = 0;
         rc = time_scatter(ctx, d_sample, m, 1, e0, e1, &before);  // also warms up
         if (rc == CUPK_OK) rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &before);
         double best = before;
-        uint32_t btv = tv0, brows = rows0, bchunk = chunk0, tried = 1;
+        uint32_t btv = tv0, brows = rows0, bchunk = chunk0, blay = lay0, tried = 1;
+        const uint32_t lays[] = {CUPK_LAYOUT_RECORD, CUPK_LAYOUT_PAIR};
         const uint32_t tvs[] = {4, 8, 16, 32, 64};
         const uint32_t rowss[] = {6, 8, 10, 12};
         const uint32_t chunks[] = {2048, 4096, 8192};
-        for (uint32_t tv : tvs)
-            for (uint32_t rows : rowss)
-                for (uint32_t ch : chunks) {
-                    if (rc != CUPK_OK) break;
-                    if (rows > ctx->D || !tile_geometry_fits(rows, ctx->C, tv)) continue;
-                    if (tv == tv0 && rows == rows0 && ch == chunk0) continue;
-                    rc = set_geometry(ctx, tv, rows, ch);
-                    if (rc != CUPK_OK) break;
-                    double ms = 0;
-                    rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &ms);
-                    tried++;
-                    if (rc == CUPK_OK && ms < best) {
-                        best = ms;
-                        btv = tv;
-                        brows = rows;
-                        bchunk = ch;
+        for (uint32_t lay : lays)
+            for (uint32_t tv : tvs)
+                for (uint32_t rows : rowss)
+                    for (uint32_t ch : chunks) {
+                        if (rc != CUPK_OK) break;
+                        if (rows > ctx->D || !tile_geometry_fits(rows, ctx->C, tv,
+                                                                 lay == CUPK_LAYOUT_PAIR
+                                                                     ? kLayoutPair
+                                                                     : kLayoutRecord))
+                            continue;
+                        if (tv == tv0 && rows == rows0 && ch == chunk0 && lay == lay0) continue;
+                        rc = set_geometry(ctx, tv, rows, ch, lay);
+                        if (rc != CUPK_OK) break;
+                        double ms = 0;
+                        rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &ms);
+                        tried++;
+                        if (ctx->trace)
+                            fprintf(stderr, "cupk tune layout=%u tv=%u rows=%u chunk=%u %.4f ms\n",
+                                    lay, tv, rows, ch, ms);
+                        if (rc == CUPK_OK && ms < best) {
+                            best = ms;
+                            btv = tv;
+                            brows = rows;
+                            bchunk = ch;
+                            blay = lay;
+                        }
                     }
-                }
-        if (rc == CUPK_OK) rc = set_geometry(ctx, btv, brows, bchunk);
+        if (rc == CUPK_OK) rc = set_geometry(ctx, btv, brows, bchunk, blay);
         // batch-size schedule: device time of prefixes n/128 .. n, plus the
         // host time per batch (flag walk and replacement rounds, which cost
         // about the same whatever the batch size) measured on this
@@ -2171,9 +2191,10 @@ int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_r
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc != CUPK_OK) {
-            (void)set_geometry(ctx, tv0, rows0, chunk0);
+            (void)set_geometry(ctx, tv0, rows0, chunk0, lay0);
             return rc;
         }
+        out->tile_layout = blay;
         out->tile_vertices = btv;
         out->lds_rows = brows;
         out->chunk_records = bchunk;

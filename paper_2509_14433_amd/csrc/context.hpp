@@ -85,6 +85,7 @@ struct cupk_ctx {
 
     // staged scatter
     uint32_t tile_shift = 5, rows = 8, chunk = 4096, ntiles = 0, tile_grid = 0;
+    uint32_t layout = CUPK_LAYOUT_RECORD;  // staged-scatter lane layout
     cupk::DevBuf<uint32_t> d_tcnt, d_toff, d_tcur, d_items;
     cupk::DevBuf<uint32_t> d_tsum;  // chunk totals of the multi-block tile scan
     cupk::DevBuf<uint32_t> d_trel;  // per (classify block, tile): start inside the tile's bin

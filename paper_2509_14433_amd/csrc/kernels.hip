@@ -972,6 +972,135 @@ hipError_t launch_fine(hipStream_t s, uint32_t grid_n, const uint32_t *hdr, cons
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Record layout of the staged scatter (StagedParams.layout == kLayoutRecord):
+// one lane per record, looping over the C columns (unrolled at compile time
+// for C <= CMAX, seeds in scalar registers), so each lane hashes its record
+// C times as independent chains.  LDS planes ordered [d][c][vertex]: the
+// lanes of a wave hit the same column of up to 64 records of one tile, so
+// many records per vertex mean LDS address conflicts; with few records per
+// tile and batch this layout still wins on its instruction-level
+// parallelism.  Everything else is as in the pair layout below.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRecThreads = 256;
+
+// XOR one (record, column) pair into the endpoint's LDS delta, or into HBM
+// for depths beyond the rows held in LDS.  lq = c*TV + (local vertex index),
+// CTV = C*TV (words per LDS depth row); gb = the endpoint's first bucket in
+// HBM; y = mix64_head(x), seed1 = mix64_head(column seed).  Index products
+// use the full-rate 24-bit multiply (d < 64 and C*TV, C < 2^24).
+DEVI void rec_column(uint64_t *la, uint64_t *lg, uint64_t *gb, uint32_t C, uint32_t D,
+                     uint32_t CTV, uint32_t rows, uint32_t rfast, uint32_t stop, uint32_t c,
+                     uint64_t seed1, uint64_t x, uint64_t y, uint32_t lq, uint32_t &deep)
+{
+    const uint64_t h = mix64_tail(y ^ seed1);
+    uint32_t d = (uint32_t)__builtin_ctz((uint32_t)h | stop);
+    if (d == rfast) {
+        d = depth_of(h, D);
+        if (d >= rows) {
+            uint64_t *bp = gb + 2 * (__umul24(d & 63u, C & 0xffffffu) + c);
+            gxor(bp, x);
+            gxor(bp + 1, h);
+            deep++;
+            return;
+        }
+    }
+    const uint32_t q = __umul24(d & 63u, CTV) + lq;
+    lxor(&la[q], x);
+    lxor(&lg[q], h);
+}
+
+template <uint32_t CMAX>
+__global__ __launch_bounds__(kRecThreads) void k_tile_scatter_rec(
+    DevSketch sk, const uint64_t *__restrict__ bins, const uint32_t *__restrict__ off,
+    const uint32_t *__restrict__ items, const uint32_t *__restrict__ nitems_p, uint32_t tile_shift,
+    uint32_t rows, uint32_t chunk, uint32_t *__restrict__ hdr,
+    unsigned long long *__restrict__ touched)
+{
+    uint32_t nchanged = 0;  // buckets this thread changed in HBM
+    extern __shared__ uint64_t lds[];
+    const bool err = hdr[HDR_ERR] != 0;
+    const uint32_t TV = 1u << tile_shift;
+    const uint32_t C = sk.C, D = sk.D, V = sk.V;
+    const uint32_t plane = rows * C * TV;  // words per LDS plane
+    const uint32_t CTV = (C * TV) & 0xffffffu;  // words per LDS depth row
+    const uint64_t DC2 = (uint64_t)D * C * 2;   // words per vertex in HBM
+    const uint32_t rfast = min(min(rows, D - 1), 31u);
+    const uint32_t stop = 1u << rfast;
+    uint64_t *la = lds;          // alpha plane [d][c][vl]
+    uint64_t *lg = lds + plane;  // gamma plane
+    const uint32_t nitems = err ? 0u : *nitems_p;
+    uint64_t seed1[CMAX > 0 ? CMAX : 1];
+    if (CMAX > 0) {
+#pragma unroll
+        for (uint32_t c = 0; c < CMAX; c++) seed1[c] = c < C ? mix64_head(sk.seeds[c]) : 0;
+    }
+
+    for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t tile = items[2 * it];
+        const uint32_t j = items[2 * it + 1];
+        const uint32_t rb = off[tile], re = off[tile + 1];
+        const uint32_t cb = rb + j * chunk;
+        const uint32_t ce = min(re, cb + chunk);
+        const bool single = (re - rb) <= chunk;
+        const uint32_t w0 = tile << tile_shift;
+
+        for (uint32_t q = threadIdx.x; q < 2 * plane; q += blockDim.x) lds[q] = 0;
+        __syncthreads();
+
+        for (uint32_t r = cb + threadIdx.x; r < ce; r += blockDim.x) {
+            const uint64_t rec = bins[r];
+            const uint32_t u = (uint32_t)rec, v = (uint32_t)(rec >> 32) & 0x7fffffffu;
+            const uint64_t x = (uint64_t)u * V + v;
+            const uint64_t y = mix64_head(x);
+            const uint32_t p = (rec & kRecV) ? v : u;  // the record's endpoint in this tile
+            uint64_t *gb = sk.b + (uint64_t)p * DC2;
+            if (CMAX > 0) {
+#pragma unroll
+                for (uint32_t c = 0; c < (CMAX > 0 ? CMAX : 1); c++)
+                    if (c < C)
+                        rec_column(la, lg, gb, C, D, CTV, rows, rfast, stop, c, seed1[c], x, y,
+                                   c * TV + (p - w0), nchanged);
+            } else {
+                for (uint32_t c = 0; c < C; c++)
+                    rec_column(la, lg, gb, C, D, CTV, rows, rfast, stop, c,
+                               mix64_head(sk.seeds[c]), x, y, c * TV + (p - w0), nchanged);
+            }
+        }
+        __syncthreads();
+
+        // Fold the delta into HBM, walking buckets in HBM order
+        // (vertex, d, c) so that consecutive lanes touch consecutive words.
+        const uint32_t nvt = min(TV, V - w0);
+        const uint32_t per_v = rows * C;
+        const uint32_t nb = nvt * per_v;
+        for (uint32_t q = threadIdx.x; q < nb; q += blockDim.x) {
+            const uint32_t vl = q / per_v;
+            const uint32_t rc = q - vl * per_v;  // d*C + c
+            const uint64_t da = la[rc * TV + vl];
+            const uint64_t dg = lg[rc * TV + vl];
+            if ((da | dg) == 0) continue;
+            nchanged++;
+            uint64_t *g = sk.b + (((uint64_t)(w0 + vl) * D) * C + rc) * 2;
+            if (single) {
+                g[0] ^= da;
+                g[1] ^= dg;
+            } else {
+                if (da) gxor(g, da);
+                if (dg) gxor(g + 1, dg);
+            }
+        }
+        __syncthreads();
+    }
+    if (touched) {
+        uint32_t t = nchanged;
+#pragma unroll
+        for (uint32_t o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (__lane_id() == 0 && t) atomicAdd(touched, (unsigned long long)t);
+    }
+    scatter_done(hdr);
+}
+
 constexpr uint32_t kTileThreads = 512;
 constexpr uint32_t kTileWaves = kTileThreads / 64;
 constexpr uint32_t kTileLdsMax = 65536;  // dynamic LDS per block, bytes
@@ -986,10 +1115,11 @@ static bool tile_stage_fits(size_t delta_bytes)
     return delta_bytes + (size_t)kTileStage * kStagedRecBytes <= kTileLdsMax;
 }
 
-bool tile_geometry_fits(uint32_t rows, uint32_t C, uint32_t tv)
+bool tile_geometry_fits(uint32_t rows, uint32_t C, uint32_t tv, uint32_t layout)
 {
     const size_t delta = (size_t)2 * rows * C * tv * sizeof(uint64_t);
-    return C >= 1 && C <= 64 && rows >= 1 && tile_stage_fits(delta);
+    if (C < 1 || C > 64 || rows < 1) return false;
+    return layout == kLayoutRecord ? delta <= kTileLdsMax : tile_stage_fits(delta);
 }
 
 struct StagedRec {
@@ -1190,10 +1320,24 @@ hipError_t launch_tile(hipStream_t s, DevSketch sk, uint32_t *hdr, const StagedP
                        const uint32_t *nitems, unsigned long long *touched)
 {
     const size_t delta = (size_t)2 * p.rows * sk.C * (1u << p.tile_shift) * sizeof(uint64_t);
-    if (sk.C > 64 || !tile_stage_fits(delta)) return hipErrorInvalidValue;
-    const size_t lds = delta + (size_t)kTileStage * kStagedRecBytes;
+    if (!tile_geometry_fits(p.rows, sk.C, 1u << p.tile_shift, p.layout))
+        return hipErrorInvalidValue;
     // Persistent grid: a few blocks per CU, each looping over work items.
     const uint32_t grid = min(p.items_cap, p.grid ? p.grid : 256u * 8u);
+    if (p.layout == kLayoutRecord) {
+#define CUPK_REC_LAUNCH(CM)                                                                    \
+    k_tile_scatter_rec<CM><<<grid, kRecThreads, delta, s>>>(sk, bins, tile_off, items, nitems, \
+                                                            p.tile_shift, p.rows, p.chunk, hdr, \
+                                                            touched)
+        if (sk.C <= 8) CUPK_REC_LAUNCH(8);
+        else if (sk.C <= 16) CUPK_REC_LAUNCH(16);
+        else if (sk.C <= 24) CUPK_REC_LAUNCH(24);
+        else if (sk.C <= 32) CUPK_REC_LAUNCH(32);
+        else CUPK_REC_LAUNCH(0);
+#undef CUPK_REC_LAUNCH
+        return hipGetLastError();
+    }
+    const size_t lds = delta + (size_t)kTileStage * kStagedRecBytes;
     k_tile_scatter<<<grid, kTileThreads, lds, s>>>(sk, bins, tile_off, items, nitems, p.tile_shift,
                                                    p.rows, p.chunk, hdr, touched);
     return hipGetLastError();

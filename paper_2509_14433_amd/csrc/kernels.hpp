@@ -75,9 +75,15 @@ struct ScanArgs {
 };
 uint32_t tile_scan_chunks(uint32_t ntiles);
 
+// Staged-scatter lane layouts: one lane per record (its C columns in turn)
+// or one lane per (record, column) pair.
+constexpr uint32_t kLayoutRecord = 1;
+constexpr uint32_t kLayoutPair = 2;
+
 struct StagedParams {
     uint32_t tile_shift;   // vertices per tile = 1 << tile_shift
     uint32_t rows;         // depth rows held in LDS (d < rows)
+    uint32_t layout;       // kLayoutRecord or kLayoutPair
     uint32_t ntiles;
     uint32_t chunk;        // max records per work item
     uint32_t items_cap;    // capacity of the work-item array
@@ -171,9 +177,9 @@ hipError_t launch_fine(hipStream_t s, uint32_t grid_n, const uint32_t *hdr, cons
                        const uint32_t *total, uint32_t tile_shift, uint32_t fshift,
                        uint32_t ntiles, uint32_t *tile_cnt, const ScanArgs &sa, uint64_t *bins);
 // Whether a staged-scatter geometry fits one block's LDS: the delta of
-// `rows` depth rows x C columns x tv vertices (alpha and gamma), plus room
-// to stage at least one block's worth of decoded records.
-bool tile_geometry_fits(uint32_t rows, uint32_t C, uint32_t tv);
+// `rows` depth rows x C columns x tv vertices (alpha and gamma), plus, in
+// the pair layout, room to stage one block's worth of decoded records.
+bool tile_geometry_fits(uint32_t rows, uint32_t C, uint32_t tv, uint32_t layout);
 
 // Fill n words with zero.
 hipError_t launch_zero(hipStream_t s, uint64_t *p, size_t n);

@@ -46,7 +46,7 @@ def workload():
                 ncomp=ncomp, comp=comp)
 
 
-@pytest.mark.parametrize("mode", ["staged", "atomic"])
+@pytest.mark.parametrize("mode", ["staged", "pair", "atomic"])
 def test_benchmark_workload_full_size(workload, mode):
     W = workload
     cupk, cfg = W["cupk"], W["cfg"]
@@ -54,8 +54,9 @@ def test_benchmark_workload_full_size(workload, mode):
     C = streamgen.ceil_log2(V)
     D = 2 * C
     S = cfg["S"]
-    sm = cupk.SCATTER_STAGED if mode == "staged" else cupk.SCATTER_ATOMIC
-    ctx = cupk.Context(V, C, D, S, scatter_mode=sm, max_batch=cfg["batch"])
+    sm = cupk.SCATTER_ATOMIC if mode == "atomic" else cupk.SCATTER_STAGED
+    lay = {"staged": cupk.LAYOUT_RECORD, "pair": cupk.LAYOUT_PAIR}.get(mode, 0)
+    ctx = cupk.Context(V, C, D, S, scatter_mode=sm, max_batch=cfg["batch"], tile_layout=lay)
     n = len(W["u"])
     print(f"full workload mode={mode} n={n}", flush=True)
     for s in range(0, n, cfg["batch"]):

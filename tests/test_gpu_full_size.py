@@ -1,9 +1,9 @@
 """Full-size parity of the largest workloads.
 
 clusters64x2048_churn (V = 2^20, C = 20, D = 40, 13.4 GB of sketches, 1.48e9
-updates) runs in the launch configuration the benchmark times: geometry and
-batch size from the autotuner on a warm-up context, then the setup phase and
-all 11 churn rounds.  rmat17_del15 runs the first 1e8 of its updates (full V,
+updates) runs in the launch configuration the benchmark times: lane layout,
+geometry and batch size from the autotuner on a warm-up context (64M-update
+sample), then the setup phase and all 11 churn rounds.  rmat17_del15 runs the first 1e8 of its updates (full V,
 C, D and recipe) in its ragged batches.  Both are compared with what the
 oracle computed for the same streams (tests/golden/full_size_parity.json,
 written by tests/golden/make_full_size_goldens.py, which calls only the
@@ -99,17 +99,19 @@ def test_clusters_full_size_in_the_benchmark_configuration(env):
             ctx.apply_updates_device(ph[s:s + b])
 
     # the benchmark's tuning: a warm-up context with 8 batches of host
-    # history, then the autotuner on a 16M-update sample of round 0
+    # history, then the autotuner on a 64M-update sample of round 0
     w = cupk.Context(V, C, D, S, max_batch=one_m)
     apply(w, phases[0], one_m)
     apply(w, phases[1][:8 * one_m], one_m)
-    tuned = w.autotune(phases[1][8 * one_m:8 * one_m + (1 << 24)].contiguous())
+    tuned = w.autotune(phases[1][8 * one_m:8 * one_m + (1 << 26)].contiguous())
     w.close()
     batch = tuned["batch_target"]
-    print(f"clusters: tuned {tuned['tile_vertices']} {tuned['lds_rows']} "
+    print(f"clusters: tuned layout {tuned['tile_layout']} {tuned['tile_vertices']} "
+          f"{tuned['lds_rows']} "
           f"{tuned['chunk_records']} batch {batch}", flush=True)
     ctx = cupk.Context(V, C, D, S, max_batch=batch, tile_vertices=tuned["tile_vertices"],
-                       lds_rows=tuned["lds_rows"], chunk_records=tuned["chunk_records"])
+                       lds_rows=tuned["lds_rows"], chunk_records=tuned["chunk_records"],
+                       tile_layout=tuned["tile_layout"])
     for k, ph in enumerate(phases):
         apply(ctx, ph, batch)
         ctx.sync()

@@ -25,15 +25,27 @@ def cupk():
     return m
 
 
-MODES = ["atomic", "staged"]
+# "staged": the staged scatter in the record layout (the default at these
+# batch sizes); "pair": the staged scatter in the pair layout
+MODES = ["atomic", "staged", "pair"]
 
 
 def _mode(cupk, name):
     return cupk.SCATTER_ATOMIC if name == "atomic" else cupk.SCATTER_STAGED
 
 
+def _mkw(cupk, name):
+    """Context keyword arguments of a scatter mode name."""
+    kw = {"scatter_mode": _mode(cupk, name)}
+    if name == "pair":
+        kw["tile_layout"] = cupk.LAYOUT_PAIR
+    elif name == "staged":
+        kw["tile_layout"] = cupk.LAYOUT_RECORD
+    return kw
+
+
 def _replay(cupk, mode, V, C, D, S, u, v, d, bs, **kw):
-    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode), **kw)
+    ctx = cupk.Context(V, C, D, S, **_mkw(cupk, mode), **kw)
     ref = oracle.Sketch(V, C, D, S)
     fr = oracle.ForestReplay(ref)
     n = len(u)
@@ -181,7 +193,7 @@ def test_sample_statuses(cupk):
 @pytest.mark.parametrize("mode", MODES)
 def test_invalid_batch_applies_nothing(cupk, mode):
     V, C, D, S = 100, 7, 14, 3
-    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    ctx = cupk.Context(V, C, D, S, **_mkw(cupk, mode))
     u, v, d = streamgen.er_standard(V, 0.1, 0.0, 4)
     ctx.apply_updates(u, v, d)
     dg = ctx.digest()
@@ -218,7 +230,7 @@ def test_device_batches_match_host_batches(cupk, mode):
     uu = np.where(sw, v, u)
     vv = np.where(sw, u, v)
     packed = torch.from_numpy(cupk.pack_updates(uu, vv, d).view(np.int64)).cuda()
-    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    ctx = cupk.Context(V, C, D, S, **_mkw(cupk, mode))
     ref = oracle.Sketch(V, C, D, S)
     fr = oracle.ForestReplay(ref)
     bs = 3001
@@ -280,7 +292,7 @@ def test_graph_replay_ragged_batches(cupk, mode):
     V, C, D, S = 700, 10, 20, 9
     u, v, d = streamgen.er_standard(V, 0.05, 0.5, 99)
     sizes = streamgen.ragged_sizes(len(u), 1, 3000, 5)
-    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode), use_graph=True, max_batch=512)
+    ctx = cupk.Context(V, C, D, S, **_mkw(cupk, mode), use_graph=True, max_batch=512)
     ref = oracle.Sketch(V, C, D, S)
     fr = oracle.ForestReplay(ref)
     off = 0
@@ -304,7 +316,7 @@ def test_small_batch_boundary(cupk, mode):
     u, v, d = streamgen.er_standard(V, 0.05, 0.5, 12)
     sizes = [4095, 4096, 4097, 1, 3000]
     assert len(u) >= sum(sizes)
-    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    ctx = cupk.Context(V, C, D, S, **_mkw(cupk, mode))
     ref = oracle.Sketch(V, C, D, S)
     fr = oracle.ForestReplay(ref)
     off = 0
@@ -343,7 +355,7 @@ def test_flag_list_boundary(cupk, mode):
     d3 = np.concatenate([np.ones(m, np.uint8), np.zeros(int(keep.sum()), np.uint8)])
     perm = rng.permutation(len(u3))
     batches.append((u3[perm], v3[perm], d3[perm]))
-    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    ctx = cupk.Context(V, C, D, S, **_mkw(cupk, mode))
     ref = oracle.Sketch(V, C, D, S)
     fr = oracle.ForestReplay(ref)
     flagged = []
@@ -408,9 +420,9 @@ def test_fill_reserve_option(cupk):
     D = 2 * C
     S = 0x5EEDF111
     u, v, d = streamgen.er_standard(V, p, df, 4242)
-    for reserve in (True, False):
-        print(f"fill_reserve={reserve} n={len(u)}", flush=True)
-        ctx, ref, fr = _replay(cupk, "staged", V, C, D, S, u, v, d, 4500, tile_vertices=8,
+    for reserve, lay in ((True, "staged"), (False, "staged"), (True, "pair")):
+        print(f"fill_reserve={reserve} layout={lay} n={len(u)}", flush=True)
+        ctx, ref, fr = _replay(cupk, lay, V, C, D, S, u, v, d, 4500, tile_vertices=8,
                                fill_reserve=reserve)
         _assert_same_sketch(ctx, ref)
         assert ctx.forest_edges() == fr.forest_edges()
@@ -463,7 +475,7 @@ def test_many_tiles_parity(cupk, mode, V, tv):
     key = np.unique(np.minimum(a, b)[keep].astype(np.int64) * V + np.maximum(a, b)[keep])[:m]
     rng.shuffle(key)
     eu, ev = (key // V).astype(np.uint32), (key % V).astype(np.uint32)
-    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode), tile_vertices=tv)
+    ctx = cupk.Context(V, C, D, S, **_mkw(cupk, mode), tile_vertices=tv)
     ref = oracle.Sketch(V, C, D, S)
     fr = oracle.ForestReplay(ref)
     bs = 5000 if V < 20000 else 60000
@@ -502,7 +514,7 @@ def test_device_batches_stream_ordered(cupk, mode):
     u, v, d = streamgen.er_standard(V, 0.01, 0.3, 77)
     nb = 8
     bounds = np.linspace(0, len(u), nb + 1).astype(int)
-    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    ctx = cupk.Context(V, C, D, S, **_mkw(cupk, mode))
     ref = oracle.Sketch(V, C, D, S)
     fr = oracle.ForestReplay(ref)
     side = torch.cuda.Stream()
@@ -555,7 +567,7 @@ def test_mass_forest_deletion_batch(cupk, mode):
     key = np.unique(np.minimum(a, b)[keep].astype(np.int64) * V + np.maximum(a, b)[keep])[:m]
     rng.shuffle(key)
     eu, ev = (key // V).astype(np.uint32), (key % V).astype(np.uint32)
-    ctx = cupk.Context(V, C, D, S, scatter_mode=_mode(cupk, mode))
+    ctx = cupk.Context(V, C, D, S, **_mkw(cupk, mode))
     ref = oracle.Sketch(V, C, D, S)
     fr = oracle.ForestReplay(ref)
     for s in range(0, m, 60000):
