@@ -777,6 +777,7 @@ int ensure_batch_buffers(cupk_ctx *ctx, size_t n)
     const size_t nb = (cap + 4095) / 4096;
     HIPCHK(grow(ctx->d_fupd, nb * 4096));
     HIPCHK(grow(ctx->d_fcnt, nb + 1));
+    HIPCHK(grow(ctx->d_fdel, nb + 1));
     HIPCHK(grow(ctx->d_foff, nb + 1));
     HIPCHK(grow(ctx->d_oupd, cap));
     HIPCHK(grow(ctx->h_fupd, cap, hipHostMallocCoherent));
@@ -894,6 +895,7 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
     FlagInline fi = {};
     fi.fupd = ctx->d_fupd.p;
     fi.fcnt = ctx->d_fcnt.p;
+    fi.fdel = ctx->d_fdel.p;
     fi.nb = classify_blocks(grid_n);
     fi.hflags = ctx->opts.exact ? nullptr : ctx->h_fupd.p;
     HIPCHK(launch_classify(s, desc_ptr(ctx), ctx->cur_desc, grid_n, ctx->V, ctx->d_lbl,
@@ -1350,6 +1352,7 @@ void destroy(cupk_ctx *ctx)
     release(ctx->d_oupd);
     release(ctx->d_foff);
     release(ctx->d_fcnt);
+    release(ctx->d_fdel);
     release(ctx->h_fupd);
     release(ctx->d_fpos);
     release(ctx->d_opos);
@@ -1407,12 +1410,19 @@ int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk, uint
     ctx->chunk = chunk;
     ctx->layout = layout;
     ctx->ntiles = (uint32_t)(((uint64_t)ctx->V + tv - 1) >> sh);
-    // two-level binning beyond kFillStageTiles tiles: at most 256 coarse bins
+    // two-level binning beyond kFillStageTiles tiles.  Both fills write runs
+    // of records per (block, bin): about 8192 / ncoarse records per coarse
+    // bin in the first, about 4096 / (tiles per coarse bin) per tile in the
+    // second; the coarse count is the power of two nearest sqrt(2 * ntiles),
+    // which evens out the two, within [64, 2048]
     ctx->fshift = 0;
     ctx->ncoarse = 0;
     if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED && ctx->ntiles > kFillStageTiles) {
+        uint32_t target = 64;
+        while (target < 2048 && (uint64_t)(2 * target) * (2 * target) <= 2 * (uint64_t)ctx->ntiles)
+            target *= 2;
         uint32_t f = 1;
-        while ((((uint64_t)ctx->ntiles + (1u << f) - 1) >> f) > 256) f++;
+        while ((((uint64_t)ctx->ntiles + (1u << f) - 1) >> f) > target) f++;
         ctx->fshift = f;
         ctx->ncoarse = (uint32_t)(((uint64_t)ctx->V + (1ull << (sh + f)) - 1) >> (sh + f));
         const size_t nc = (size_t)kCntGroups * ctx->ncoarse + 1;

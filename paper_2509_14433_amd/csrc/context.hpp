@@ -77,7 +77,8 @@ struct cupk_ctx {
     cupk::DevBuf<uint64_t> d_upd;
     cupk::HostBuf<uint64_t> h_upd;
     uint32_t *d_hdr = nullptr, *h_hdr = nullptr;
-    cupk::DevBuf<uint32_t> d_fcnt, d_foff;  // flagged updates: per-block counts and offsets,
+    cupk::DevBuf<uint32_t> d_fcnt, d_foff;
+    cupk::DevBuf<uint32_t> d_fdel;  // flagged deletes per classify block  // flagged updates: per-block counts and offsets,
     cupk::DevBuf<uint64_t> d_fupd, d_oupd;  // per-block regions, the compacted ordered list
     cupk::HostBuf<uint64_t> h_fupd;  // coherent: short flag lists are written there by the device
     cupk::DevBuf<uint32_t> d_fpos, d_opos;  // positions of flagged updates (exact mode)

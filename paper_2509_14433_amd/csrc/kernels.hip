@@ -81,14 +81,15 @@ DEVI void lxor(uint64_t *p, uint64_t v)
 //   delete {u,v} that is a forest edge (par[u]==v or par[v]==u), or with
 //   lbl[u] != lbl[v] (an edge linked earlier in this same batch)
 // Everything else can only touch the sketch.  Block b covers positions
-// [b*4096, (b+1)*4096) with 1024 threads (16 waves, so one block per CU
-// still hides latency); each thread issues the loads of all its 4 updates
-// (and their label / parent words) before using any.  The block writes its flagged updates in
+// [b*4096, (b+1)*4096) with 512 threads; each thread issues the loads of
+// all its 8 updates (and their label words) before using any, since the
+// kernel is bound by the latency of those dependent loads.  The block
+// writes its flagged updates in
 // stream order into its own region of the flag buffers (same offsets), at
 // positions from one prefix over (step, wave) counts; cnt[b] gets their
 // number.  k_flag_compact later packs the regions into one ordered list.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kClsThreads = 1024;
+constexpr uint32_t kClsThreads = 512;  // 8 updates per thread: 16 label loads in flight
 constexpr uint32_t kClsPerBlock = 4096;
 constexpr uint32_t kClsPerThread = kClsPerBlock / kClsThreads;
 constexpr uint32_t kClsWaves = kClsThreads / 64;
@@ -145,7 +146,17 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict
     __shared__ uint32_t boff[kInlineMaxBlocks];
     static_assert(kInlineFlags < 65536 && kClsPerBlock < 65536, "packed region words");
     const bool err = hdr[HDR_ERR] != 0;
-    const uint32_t nflag = hdr[HDR_NFLAG];
+    // the batch's flag counts: sums of the classify blocks' counts
+    uint32_t nflag, nflag_del;
+    {
+        uint32_t a = 0, b = 0;
+        for (uint32_t i = threadIdx.x; i < fi.nb; i += kScanThreads) {
+            a += fi.fcnt[i];
+            b += fi.fdel[i];
+        }
+        block_exscan<kScanThreads>(a, nflag, sh);
+        block_exscan<kScanThreads>(b, nflag_del, sh);
+    }
     // few flagged updates: compact them into host memory in stream order
     // (one wave per classify block's region)
     const bool inl = fi.hflags && !err && nflag <= kInlineFlags && fi.nb <= kInlineMaxBlocks;
@@ -181,8 +192,10 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict
     // first, then the sequence number with release semantics
     if (threadIdx.x == 0) {
         hout[HDR_ERR] = hdr[HDR_ERR];
+        hdr[HDR_NFLAG] = nflag;
+        hdr[HDR_NFLAG_DEL] = nflag_del;
         hout[HDR_NFLAG] = nflag;
-        hout[HDR_NFLAG_DEL] = hdr[HDR_NFLAG_DEL];
+        hout[HDR_NFLAG_DEL] = nflag_del;
         hout[HDR_INLINE] = inl ? 1u : 0u;
         const uint32_t seq = hdr[HDR_SEQ] + 1;
         hdr[HDR_SEQ] = seq;
@@ -334,11 +347,13 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_offsets(uint32_t *__restr
 __global__ __launch_bounds__(kClsThreads) void k_classify(
     const BatchDesc *__restrict__ desc, BatchDesc dv, uint32_t V, const uint32_t *__restrict__ lbl,
     const uint32_t *__restrict__ par, uint32_t *__restrict__ hdr, uint64_t *__restrict__ fupd,
-    uint32_t *__restrict__ fpos, uint32_t *__restrict__ fcnt, uint32_t *__restrict__ tile_cnt,
-    uint32_t tile_shift, uint32_t ntiles, uint32_t *__restrict__ tile_rel)
+    uint32_t *__restrict__ fpos, uint32_t *__restrict__ fcnt, uint32_t *__restrict__ fdel,
+    uint32_t *__restrict__ tile_cnt, uint32_t tile_shift, uint32_t ntiles,
+    uint32_t *__restrict__ tile_rel)
 {
     __shared__ uint32_t hist[kLdsHistMax];
     __shared__ uint32_t pre[64 + 1];  // flagged per (step, wave) -> exclusive prefix; total
+    __shared__ uint32_t wdel[kClsWaves];  // flagged deletes per wave
     const bool count = tile_cnt != nullptr;
     const bool use_lds = count && ntiles <= kLdsHistMax;
     if (use_lds)
@@ -410,6 +425,7 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
     }
 #pragma unroll
     for (uint32_t o = 32; o > 0; o >>= 1) ndel += __shfl_xor(ndel, o);
+    if (lane == 0) wdel[wid] = ndel;
     const uint64_t mb = __ballot(bad);
     if (mb && lane == (uint32_t)__builtin_ctzll(mb)) atomicOr(&hdr[HDR_ERR], 1u);
     __syncthreads();
@@ -435,12 +451,16 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
             if (fpos) fpos[q] = begin + k * kClsThreads + threadIdx.x;
         }
     }
+    // per-block counts only: the one-block scan after this kernel sums them
+    // (device atomics of every block on one header word would serialize)
     const uint32_t total = pre[64];
     if (threadIdx.x == 0) {
+        uint32_t dsum = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < kClsWaves; w++) dsum += wdel[w];
         fcnt[blockIdx.x] = total;
-        if (total) atomicAdd(&hdr[HDR_NFLAG], total);
+        fdel[blockIdx.x] = dsum;
     }
-    if (lane == 0 && ndel) atomicAdd(&hdr[HDR_NFLAG_DEL], ndel);
     if (use_lds) {
         __syncthreads();
         if (tile_rel) {
@@ -467,6 +487,7 @@ hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, u
                            uint32_t tile_shift, uint32_t ntiles, const ScanArgs &sa,
                            uint32_t *hout, const FlagInline &fi, uint32_t *tile_rel)
 {
+    if (!fi.fdel || fi.fcnt != fcnt || fi.nb != classify_blocks(grid_n)) return hipErrorInvalidValue;
     if (grid_n == 0) return hipSuccess;
     if (tile_rel && (!tile_cnt || ntiles > kRelMaxTiles || sa.groups != kCntGroups || !sa.goff))
         return hipErrorInvalidValue;
@@ -474,7 +495,8 @@ hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, u
     if (sa.sums && (tile_rel || sa.groups != 1 || ntiles <= kScanOneBlockTiles))
         return hipErrorInvalidValue;
     k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(
-        desc, dv, V, lbl, par, hdr, fupd, fpos, fcnt, tile_cnt, tile_shift, ntiles, tile_rel);
+        desc, dv, V, lbl, par, hdr, fupd, fpos, fcnt, fi.fdel, tile_cnt, tile_shift, ntiles,
+        tile_rel);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr, hout, fi);
@@ -868,8 +890,10 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill_staged(
 // tile)), the multi-block tile scan turns them into bin offsets and work
 // items, and k_fine_fill ranks each chunk's records per tile in LDS,
 // reserves one range per (chunk, tile) from the tile's cursor and writes
-// the records there.  A tile more than kFineLdsTiles past the chunk's first
-// coarse bin is counted and reserved per record instead.
+// the records there, staged in tile order in LDS so that each (chunk, tile)
+// run is written as consecutive words.  A tile more than kFineLdsTiles
+// (count) or kFillLdsTiles (fill) past the chunk's first coarse bin is
+// counted and reserved per record instead.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kFineThreads = 1024;
 constexpr uint32_t kFinePer = 8;
@@ -910,43 +934,68 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_count(
     }
 }
 
+// The fill takes half as many records per block as the count, so that its
+// LDS (the block's records staged in tile order, and per tile the count,
+// stage start and reserved bin start) stays within 64 KiB.
+constexpr uint32_t kFillPer2 = 4;
+constexpr uint32_t kFillPerBlock2 = kFineThreads * kFillPer2;
+constexpr uint32_t kFillLdsTiles = 2 * kFineThreads;
+
 __global__ __launch_bounds__(kFineThreads) void k_fine_fill(
     const uint64_t *__restrict__ bins1, const uint32_t *__restrict__ total, uint32_t tile_shift,
     uint32_t fshift, uint32_t *__restrict__ cur, uint64_t *__restrict__ bins,
     const uint32_t *__restrict__ hdr)
 {
-    __shared__ uint32_t hist[kFineLdsTiles];
+    __shared__ uint64_t stage[kFillPerBlock2];  // local records in tile order
+    __shared__ uint32_t lcnt[kFillLdsTiles];    // per tile: count, then reserved bin start
+    __shared__ uint32_t lpre[kFillLdsTiles];    // per tile: first stage slot
+    __shared__ uint32_t sh[160];
     if (hdr[HDR_ERR]) return;
     const uint32_t n = *total;
-    const uint32_t begin = blockIdx.x * kFinePerBlock;
+    const uint32_t begin = blockIdx.x * kFillPerBlock2;
     if (begin >= n) return;
     const uint32_t t_lo = (rec_endpoint(bins1[begin]) >> (tile_shift + fshift)) << fshift;
-    for (uint32_t j = threadIdx.x; j < kFineLdsTiles; j += kFineThreads) hist[j] = 0;
+    for (uint32_t j = threadIdx.x; j < kFillLdsTiles; j += kFineThreads) lcnt[j] = 0;
     __syncthreads();
-    uint64_t rec[kFinePer];
-    uint32_t pos[kFinePer];  // rank in the (chunk, tile) range, or the final position
+    uint64_t rec[kFillPer2];
+    uint32_t rk[kFillPer2];  // rank in the block's share of its tile, or the final position
 #pragma unroll
-    for (uint32_t k = 0; k < kFinePer; k++) {
+    for (uint32_t k = 0; k < kFillPer2; k++) {
         const uint32_t i = begin + k * kFineThreads + threadIdx.x;
         rec[k] = i < n ? bins1[i] : 0;
-        pos[k] = 0;
+        rk[k] = 0;
         if (i >= n) continue;
         const uint32_t t = rec_endpoint(rec[k]) >> tile_shift;
-        pos[k] = t - t_lo < kFineLdsTiles ? atomicAdd(&hist[t - t_lo], 1u) : atomicAdd(&cur[t], 1u);
+        rk[k] = t - t_lo < kFillLdsTiles ? atomicAdd(&lcnt[t - t_lo], 1u) : atomicAdd(&cur[t], 1u);
     }
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < kFineLdsTiles; j += kFineThreads) {
-        const uint32_t c = hist[j];
-        if (c) hist[j] = atomicAdd(&cur[t_lo + j], c);
-    }
+    // stage starts (a block scan, two tiles per thread) and one reserved bin
+    // range per tile present in this block
+    const uint32_t t0 = 2 * threadIdx.x;
+    const uint32_t c0 = lcnt[t0], c1 = lcnt[t0 + 1];
+    uint32_t tot;
+    const uint32_t ex = block_exscan<kFineThreads>(c0 + c1, tot, sh);
+    lpre[t0] = ex;
+    lpre[t0 + 1] = ex + c0;
+    lcnt[t0] = c0 ? atomicAdd(&cur[t_lo + t0], c0) : 0u;
+    lcnt[t0 + 1] = c1 ? atomicAdd(&cur[t_lo + t0 + 1], c1) : 0u;
     __syncthreads();
 #pragma unroll
-    for (uint32_t k = 0; k < kFinePer; k++) {
+    for (uint32_t k = 0; k < kFillPer2; k++) {
         const uint32_t i = begin + k * kFineThreads + threadIdx.x;
         if (i >= n) continue;
         const uint32_t t = rec_endpoint(rec[k]) >> tile_shift;
-        const uint32_t q = t - t_lo < kFineLdsTiles ? hist[t - t_lo] + pos[k] : pos[k];
-        bins[q] = rec[k];
+        if (t - t_lo < kFillLdsTiles)
+            stage[lpre[t - t_lo] + rk[k]] = rec[k];
+        else
+            bins[rk[k]] = rec[k];
+    }
+    __syncthreads();
+    // out in tile order: the lanes of a wave store runs of consecutive words
+    for (uint32_t j = threadIdx.x; j < tot; j += kFineThreads) {
+        const uint64_t r = stage[j];
+        const uint32_t t = (rec_endpoint(r) >> tile_shift) - t_lo;
+        bins[lcnt[t] + (j - lpre[t])] = r;
     }
 }
 
@@ -968,7 +1017,8 @@ hipError_t launch_fine(hipStream_t s, uint32_t grid_n, const uint32_t *hdr, cons
     k_tile_offsets<<<nch, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_fine_fill<<<nb, kFineThreads, 0, s>>>(bins1, total, tile_shift, fshift, sa.cur, bins, hdr);
+    const uint32_t nf = (uint32_t)((2 * (uint64_t)grid_n + kFillPerBlock2 - 1) / kFillPerBlock2);
+    k_fine_fill<<<nf, kFineThreads, 0, s>>>(bins1, total, tile_shift, fshift, sa.cur, bins, hdr);
     return hipGetLastError();
 }
 
@@ -1301,7 +1351,7 @@ hipError_t launch_bin(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32
     if (grid_n == 0) return hipSuccess;
     const uint32_t fb = (grid_n + kFillPerBlock - 1) / kFillPerBlock;
     // the fill's blocks cover the same updates as the classify blocks
-    static_assert(kFillPerBlock == kClsPerBlock && kFillThreads == kClsThreads,
+    static_assert(kFillPerBlock == kClsPerBlock,
                   "fill and classify blocks must cover the same updates");
     static_assert(kRelMaxTiles <= kFillStageTiles && kRelMaxTiles <= kLdsHistMax,
                   "tile_rel needs the classify's LDS counts and the staged fill");

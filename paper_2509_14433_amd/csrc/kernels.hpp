@@ -49,6 +49,7 @@ constexpr uint32_t kInlineMaxBlocks = 8192;
 struct FlagInline {
     const uint64_t *fupd;  // per-block regions (the classify kernel's output)
     const uint32_t *fcnt;  // flags per classify block
+    uint32_t *fdel;        // flagged deletes per classify block
     uint32_t nb;           // classify blocks
     uint64_t *hflags;      // coherent pinned host memory; null: never inline
 };
