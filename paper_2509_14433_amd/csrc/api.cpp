@@ -599,9 +599,19 @@ int run_rounds(cupk_ctx *ctx)
                     groups[gi].minv = lists[gi][0];
                 }
         } else {
+            // one search per tree, the trees split over the pool when their
+            // members are many (each writes its own list)
+            std::vector<size_t> todo;
             for (size_t gi = 0; gi < groups.size(); gi++)
-                if (gi != skip && !groups[gi].from_frags && lists[gi].empty())
-                    groups[gi].minv = F.collect(groups[gi].label, lists[gi]);
+                if (gi != skip && !groups[gi].from_frags && lists[gi].empty()) todo.push_back(gi);
+            auto one = [&](size_t i, unsigned) {
+                Group &g = groups[todo[i]];
+                g.minv = F.collect(g.label, lists[todo[i]]);
+            };
+            if (F.pool() && todo.size() > 1 && need >= F.parallel_work())
+                F.pool()->run(todo.size(), one);
+            else
+                for (size_t i = 0; i < todo.size(); i++) one(i, 0);
         }
         std::vector<size_t> gord;
         gord.reserve(groups.size());
@@ -730,6 +740,14 @@ bool apply_flags(cupk_ctx *ctx, const uint64_t *upd, uint32_t k0, uint32_t k1, b
         uint64_t nl = 0, nc = 0;
         bool changed = false;
         if (ctx->contract.run(F, upd, k0, k1, &nl, &nc, &changed)) {
+            if (ctx->trace)
+                fprintf(stderr,
+                        "cupk   contract k=%u pieces=%u links=%llu cuts=%llu: pieces %.3f "
+                        "replay %.3f split %.3f link %.3f ms\n",
+                        k1 - k0, ctx->contract.last_pieces, (unsigned long long)nl,
+                        (unsigned long long)nc, ctx->contract.last_ms[0],
+                        ctx->contract.last_ms[1], ctx->contract.last_ms[2],
+                        ctx->contract.last_ms[3]);
             ctx->ctr.links += nl;
             ctx->ctr.cuts += nc;
             ctx->ctr.walks_contracted++;
@@ -1519,6 +1537,12 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     memset(ctx->h_small, 0, sizeof(SmallResult));
     HIPCHK(hipHostMalloc((void **)&ctx->h_misc, 64, hipHostMallocDefault));
     ctx->forest.init(V, ctx->h_lbl, ctx->h_par);
+    if (V >= (1u << 17)) {
+        // host forest work of a batch (relabels, member lists) is split
+        // over a few threads when trees are large
+        ctx->pool.reset(new (std::nothrow) cupk::Pool());
+        if (ctx->pool) ctx->forest.set_pool(ctx->pool.get());
+    }
     if (ctx->opts.levels) {
         int rc = levels_init(ctx);
         if (rc != CUPK_OK) return rc;

@@ -143,6 +143,7 @@ struct cupk_ctx {
     uint32_t piece_epoch = 0;
     std::unique_ptr<cupk::Levels> levels;  // multi-level hierarchy (opts.levels)
     cupk::Forest forest;
+    std::unique_ptr<cupk::Pool> pool;  // host worker threads (large V only)
     cupk::Contraction contract;  // contracted walks of flagged runs
     std::vector<uint8_t> cand_linked;  // which round candidates linked
     // a carried set of the last round whose sketch was not reduced (the old

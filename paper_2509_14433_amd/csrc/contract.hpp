@@ -39,6 +39,7 @@
 
 #include <stdint.h>
 
+#include <chrono>
 #include <unordered_set>
 #include <vector>
 
@@ -70,6 +71,7 @@ class Contraction {
             std::fill(seen_.begin(), seen_.end(), 0);
             epoch_ = 1;
         }
+        const auto t0 = std::chrono::steady_clock::now();
         // labels exact, so that T0 is the current forest
         F.split_pending();
         // D0: T0 edges the run deletes (child endpoint marked)
@@ -102,6 +104,7 @@ class Contraction {
                 }
             }
         }
+        const auto t1 = std::chrono::steady_clock::now();
         // replay on the piece forest
         plbl_.resize(P);
         ppar_.resize(P);
@@ -136,6 +139,7 @@ class Contraction {
                 nc++;
             }
         }
+        const auto t2 = std::chrono::steady_clock::now();
         // net change on the whole forest
         bool ch = false;
         for (uint64_t e : d0_)
@@ -144,6 +148,7 @@ class Contraction {
                 ch = true;
             }
         F.split_pending();
+        const auto t3 = std::chrono::steady_clock::now();
         net_.clear();
         for (uint64_t e : added_) {
             if (!live_.count(e)) continue;
@@ -159,11 +164,24 @@ class Contraction {
             ch = true;
         }
         for (uint32_t x : removed_) F.set_dirty(F.label(x));
+        const auto t4 = std::chrono::steady_clock::now();
+        auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+            return std::chrono::duration<double, std::milli>(b - a).count();
+        };
+        last_ms[0] = ms(t0, t1);  // pending splits, D0, pieces
+        last_ms[1] = ms(t1, t2);  // replay on the piece forest
+        last_ms[2] = ms(t2, t3);  // removals and the split
+        last_ms[3] = ms(t3, t4);  // net links
+        last_pieces = P;
         *links += nl;
         *cuts += nc;
         *changed = ch;
         return true;
     }
+
+    // Host time of the last run's phases (ms) and its number of pieces.
+    double last_ms[4] = {0, 0, 0, 0};
+    uint32_t last_pieces = 0;
 
     // Parent steps the piece search may take: per update of the run, plus
     // a constant.

@@ -25,6 +25,8 @@
 #include <algorithm>
 #include <vector>
 
+#include "pool.hpp"
+
 namespace cupk {
 
 constexpr uint32_t kNone = 0xffffffffu;
@@ -326,14 +328,16 @@ class Forest {
         for (size_t i = 0; i < n; i++) lbl_[v[i]] = l;
     }
     // Relabel every vertex of the tree rooted at r (top-down).
-    void settle_relabel_tree(uint32_t r, uint32_t l)
+    void settle_relabel_tree(uint32_t r, uint32_t l) { relabel_tree_with(queue_, r, l); }
+    // Label every vertex of the tree rooted at r with l (q: scratch).
+    void relabel_tree_with(std::vector<uint32_t> &q, uint32_t r, uint32_t l)
     {
-        queue_.clear();
-        queue_.push_back(r);
-        for (size_t qi = 0; qi < queue_.size(); qi++) {
-            const uint32_t x = queue_[qi];
+        q.clear();
+        q.push_back(r);
+        for (size_t qi = 0; qi < q.size(); qi++) {
+            const uint32_t x = q[qi];
             lbl_[x] = l;
-            for (uint32_t y = first_kid_[x]; y != kNone; y = next_sib_[y]) queue_.push_back(y);
+            for (uint32_t y = first_kid_[x]; y != kNone; y = next_sib_[y]) q.push_back(y);
         }
     }
     void settle_tree(uint32_t l, uint32_t root, uint32_t size, bool dirty)
@@ -405,11 +409,18 @@ class Forest {
         }
         for (uint32_t l : lm_touched_)
             if (dirty_[l]) set_dirty(lm_best_[find(l)]);
-        // relabel the other parts in the structure before the links
+        // relabel the other parts in the structure before the links (the
+        // trees are disjoint: in parallel when there is enough of them)
+        lm_jobs_.clear();
+        size_t lm_work = 0;
         for (uint32_t l : lm_touched_) {
             const uint32_t keep = lm_best_[find(l)];
-            if (l != keep) settle_relabel_tree(root_[l], keep);
+            if (l != keep) {
+                lm_jobs_.push_back({root_[l], keep});
+                lm_work += size_[l];
+            }
         }
+        relabel_trees(lm_jobs_, lm_work);
         for (const auto &e : lm_edges_) link_structural_short(e.first, e.second);
         for (uint32_t l : lm_touched_) {
             const uint32_t r = find(l), keep = lm_best_[r];
@@ -430,7 +441,31 @@ class Forest {
 
     // Vertices of the tree with the given label (BFS from its root); also
     // returns the smallest vertex id.
-    uint32_t collect(uint32_t label, std::vector<uint32_t> &out)
+    // Use `p` (may be null) for the host work that splits over trees.
+    void set_pool(Pool *p)
+    {
+        pool_ = p;
+        wq_.resize(p ? p->size() : 1);
+    }
+    Pool *pool() const { return pool_; }
+
+    // Relabel whole trees: jobs (root, new label); `work` = their total
+    // size, which decides whether the pool is worth waking.
+    void relabel_trees(const std::vector<std::pair<uint32_t, uint32_t>> &jobs, size_t work)
+    {
+        if (pool_ && jobs.size() > 1 && work >= par_work_) {
+            pool_->run(jobs.size(), [&](size_t i, unsigned w) {
+                relabel_tree_with(wq_[w], jobs[i].first, jobs[i].second);
+            });
+        } else {
+            for (const auto &j : jobs) relabel_tree_with(queue_, j.first, j.second);
+        }
+    }
+    // Vertices from which splitting host work over the pool pays.
+    size_t parallel_work() const { return par_work_; }
+    void set_parallel_work(size_t n) { par_work_ = n; }
+
+    uint32_t collect(uint32_t label, std::vector<uint32_t> &out) const
     {
         const uint32_t r = root_[label];
         const size_t start = out.size();
@@ -524,6 +559,10 @@ class Forest {
     std::vector<uint32_t> free_;
     std::vector<uint32_t> live_, live_pos_;  // labels in use, and each one's slot
     std::vector<uint32_t> queue_;
+    Pool *pool_ = nullptr;
+    size_t par_work_ = 16384;
+    std::vector<std::vector<uint32_t>> wq_ = std::vector<std::vector<uint32_t>>(1);  // per worker
+    std::vector<std::pair<uint32_t, uint32_t>> lm_jobs_;
     std::vector<uint32_t> lm_up_, lm_sz_, lm_st_, lm_best_, lm_touched_;  // link_many, by label
     uint32_t lm_ep_ = 0;
     std::vector<std::pair<uint32_t, uint32_t>> lm_edges_;

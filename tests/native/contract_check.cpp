@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <map>
 #include <random>
+#include <memory>
 #include <set>
 #include <vector>
 
@@ -110,11 +111,20 @@ int main(int argc, char **argv)
     const uint32_t V = argc > 1 ? (uint32_t)atoi(argv[1]) : 200;
     const uint64_t runs = argc > 2 ? (uint64_t)atoll(argv[2]) : 300;
     const uint64_t seed = argc > 3 ? (uint64_t)atoll(argv[3]) : 1;
+    // threads > 0: B relabels merged trees on a pool of that many workers,
+    // whatever their size
+    const unsigned threads = argc > 4 ? (unsigned)atoi(argv[4]) : 0;
     std::mt19937_64 rng(seed);
     std::vector<uint32_t> la(V), pa(V), lb(V), pb(V);
     Forest A, B;
     A.init(V, la.data(), pa.data());
     B.init(V, lb.data(), pb.data());
+    std::unique_ptr<cupk::Pool> workers;
+    if (threads) {
+        workers.reset(new cupk::Pool(threads));
+        B.set_pool(workers.get());
+        B.set_parallel_work(1);
+    }
     Contraction C;
     uint64_t many_runs = 0;
     // the graph's edges (what a valid stream toggles)
