@@ -743,7 +743,7 @@ bool apply_flags(cupk_ctx *ctx, const uint64_t *upd, uint32_t k0, uint32_t k1, b
             if (ctx->trace)
                 fprintf(stderr,
                         "cupk   contract k=%u pieces=%u links=%llu cuts=%llu: pieces %.3f "
-                        "replay %.3f split %.3f link %.3f ms\n",
+                        "replay %.3f removals %.3f settle %.3f ms\n",
                         k1 - k0, ctx->contract.last_pieces, (unsigned long long)nl,
                         (unsigned long long)nc, ctx->contract.last_ms[0],
                         ctx->contract.last_ms[1], ctx->contract.last_ms[2],

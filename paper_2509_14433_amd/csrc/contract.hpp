@@ -69,6 +69,7 @@ class Contraction {
         if (++epoch_ == 0) {
             std::fill(cut_.begin(), cut_.end(), 0);
             std::fill(seen_.begin(), seen_.end(), 0);
+            std::fill(pstamp_.begin(), pstamp_.end(), 0);
             epoch_ = 1;
         }
         const auto t0 = std::chrono::steady_clock::now();
@@ -140,14 +141,15 @@ class Contraction {
             }
         }
         const auto t2 = std::chrono::steady_clock::now();
-        // net change on the whole forest
+        // net change on the whole forest: the removals, then every piece of
+        // the broken trees (and every tree a net edge joins) settled into its
+        // final tree at once, the final trees being the piece forest's
         bool ch = false;
         for (uint64_t e : d0_)
             if (!live_.count(e)) {
                 F.remove_edge((uint32_t)e, (uint32_t)(e >> 32));
                 ch = true;
             }
-        F.split_pending();
         const auto t3 = std::chrono::steady_clock::now();
         net_.clear();
         for (uint64_t e : added_) {
@@ -157,10 +159,33 @@ class Contraction {
             net_.push_back({a, b});
             live_.erase(e);  // linked once, even if added more than once
         }
-        // the net edges join different trees: all of them link (each merged
-        // tree relabelled once)
-        if (!net_.empty()) {
-            F.link_many(net_, net_linked_);
+        if (F.has_pending() || !net_.empty()) {
+            if (PF_.has_pending()) PF_.split_pending();
+            if (pstamp_.size() != V) pstamp_.assign(V, 0);
+            pieces_.clear();
+            uint32_t extra = P;  // group ids past the piece forest's labels
+            auto add = [&](uint32_t t) {
+                if (pstamp_[t] == epoch_) return;
+                pstamp_[t] = epoch_;
+                uint32_t g;
+                size_t big = (size_t)-1;
+                if (seen_[t] == epoch_ || find_top(F, t, big) != kNone) {
+                    const uint32_t q = pid_[top_[t]];
+                    g = (q < P && piece_top_[q] == top_[t]) ? PF_.label(q) : extra++;
+                } else {
+                    g = extra++;
+                }
+                pieces_.push_back({t, g});
+            };
+            for (const auto &pr : F.pending()) {
+                add(pr.second);
+                add(F.tree_root(pr.first));
+            }
+            for (const auto &e : net_) {
+                add(F.tree_root(F.label(e.first)));
+                add(F.tree_root(F.label(e.second)));
+            }
+            F.settle_regroup(pieces_, net_);
             ch = true;
         }
         for (uint32_t x : removed_) F.set_dirty(F.label(x));
@@ -170,8 +195,8 @@ class Contraction {
         };
         last_ms[0] = ms(t0, t1);  // pending splits, D0, pieces
         last_ms[1] = ms(t1, t2);  // replay on the piece forest
-        last_ms[2] = ms(t2, t3);  // removals and the split
-        last_ms[3] = ms(t3, t4);  // net links
+        last_ms[2] = ms(t2, t3);  // removals
+        last_ms[3] = ms(t3, t4);  // settling the pieces into their final trees
         last_pieces = P;
         *links += nl;
         *cuts += nc;
@@ -228,7 +253,8 @@ class Contraction {
         return t;
     }
 
-    std::vector<uint32_t> cut_, seen_, top_, pid_;  // by vertex; stamps are epochs
+    std::vector<uint32_t> cut_, seen_, top_, pid_, pstamp_;  // by vertex; stamps are epochs
+    std::vector<std::pair<uint32_t, uint32_t>> pieces_;  // (top, final group) to settle
     uint32_t epoch_ = 0;
     size_t budget_per_update_ = 64, budget_base_ = 4096;
     std::vector<uint32_t> piece_top_, path_;

@@ -327,6 +327,112 @@ class Forest {
     {
         for (size_t i = 0; i < n; i++) lbl_[v[i]] = l;
     }
+    // Settle a set of pieces into their final trees in one step (instead of
+    // split_pending() and then link_many()).  pieces: (top, group) for every
+    // piece of the trees broken by the pending removals (each the subtree
+    // below its top: the old root or a removed edge's child endpoint) and
+    // the root of every unbroken tree that a link joins; group ids name the
+    // final trees (any values).  links: the edges joining the pieces of a
+    // group into a tree (they must do so; no other piece is touched).
+    //   - A group keeps the label of the largest old tree whose root piece
+    //     it holds (ties: the smaller label), else takes a fresh label; only
+    //     the pieces whose label changes are relabelled (on the pool when
+    //     their vertices are many), so a tree whose pieces all end together
+    //     keeps its label and costs nothing.
+    //   - Labels no group keeps are freed.  Sizes follow from the relabelled
+    //     pieces' sizes (a kept label loses what left and gains what came).
+    //   - A group is dirty when one of its pieces was in a broken tree or in
+    //     a dirty one (as every piece of a split is dirty, and a link keeps
+    //     its parts' marks).
+    //   - The links are made by parent pointers; roots follow.
+    void settle_regroup(std::vector<std::pair<uint32_t, uint32_t>> &pieces,
+                        const std::vector<std::pair<uint32_t, uint32_t>> &links)
+    {
+        // old trees broken by the pending removals
+        for (const auto &pr : pending_) rg_broken_.push_back(pr.first);
+        std::sort(rg_broken_.begin(), rg_broken_.end());
+        rg_broken_.erase(std::unique(rg_broken_.begin(), rg_broken_.end()), rg_broken_.end());
+        auto broken = [&](uint32_t l) {
+            return std::binary_search(rg_broken_.begin(), rg_broken_.end(), l);
+        };
+        std::sort(pieces.begin(), pieces.end(),
+                  [](const std::pair<uint32_t, uint32_t> &a, const std::pair<uint32_t, uint32_t> &b) {
+                      return a.second != b.second ? a.second < b.second : a.first < b.first;
+                  });
+        // per group: its target label and dirty mark; per piece: the job
+        rg_target_.assign(pieces.size(), kNone);
+        rg_jobs_.clear();
+        rg_group_end_.clear();
+        rg_kept_.clear();
+        for (size_t g0 = 0; g0 < pieces.size();) {
+            size_t g1 = g0;
+            while (g1 < pieces.size() && pieces[g1].second == pieces[g0].second) g1++;
+            uint32_t keep = kNone;
+            bool dirty = false;
+            for (size_t i = g0; i < g1; i++) {
+                const uint32_t t = pieces[i].first, l = lbl_[t];
+                dirty = dirty || dirty_[l] || broken(l);
+                if (root_[l] != t) continue;  // not the old tree's root piece
+                if (keep == kNone || size_[l] > size_[keep] || (size_[l] == size_[keep] && l < keep))
+                    keep = l;
+            }
+            const bool fresh = keep == kNone;
+            if (fresh) keep = settle_take_label();
+            else rg_kept_.push_back(keep);
+            for (size_t i = g0; i < g1; i++) {
+                rg_target_[i] = keep;
+                if (lbl_[pieces[i].first] != keep) rg_jobs_.push_back((uint32_t)i);
+            }
+            if (fresh) size_[keep] = 0;
+            rg_group_end_.push_back({(uint32_t)g1, dirty ? 1u : 0u});
+            g0 = g1;
+        }
+        std::sort(rg_kept_.begin(), rg_kept_.end());
+        // relabel the pieces that change tree (disjoint subtrees)
+        rg_size_.assign(rg_jobs_.size(), 0);
+        rg_old_.assign(rg_jobs_.size(), 0);
+        size_t work = 0;
+        for (size_t j = 0; j < rg_jobs_.size(); j++) {
+            const uint32_t t = pieces[rg_jobs_[j]].first;
+            rg_old_[j] = lbl_[t];
+            work += size_[rg_old_[j]];  // a bound: the piece is part of its old tree
+        }
+        auto one = [&](size_t j, unsigned w) {
+            const uint32_t i = rg_jobs_[j];
+            std::vector<uint32_t> &q = pool_ ? wq_[w] : queue_;
+            relabel_tree_with(q, pieces[i].first, rg_target_[i]);
+            rg_size_[j] = (uint32_t)q.size();
+        };
+        if (pool_ && rg_jobs_.size() > 1 && work >= par_work_)
+            pool_->run(rg_jobs_.size(), one);
+        else
+            for (size_t j = 0; j < rg_jobs_.size(); j++) one(j, 0);
+        // sizes: what left each old tree, what came to each target
+        for (size_t j = 0; j < rg_jobs_.size(); j++) {
+            size_[rg_old_[j]] -= rg_size_[j];
+            size_[rg_target_[rg_jobs_[j]]] += rg_size_[j];
+        }
+        // labels no group keeps (all their pieces left) are freed once
+        for (size_t j = 0; j < rg_jobs_.size(); j++) {
+            const uint32_t l = rg_old_[j];
+            if (size_[l] == 0 && !std::binary_search(rg_kept_.begin(), rg_kept_.end(), l) &&
+                live_pos_[l] < live_.size() && live_[live_pos_[l]] == l) {
+                settle_drop_label(l);
+            }
+        }
+        // links by parent pointers, then roots and dirty marks per group
+        for (const auto &e : links) link_structural_short(e.first, e.second);
+        size_t g0 = 0;
+        for (const auto &ge : rg_group_end_) {
+            const uint32_t l = rg_target_[g0];
+            root_[l] = root_of(pieces[g0].first);
+            if (ge.second) set_dirty(l);
+            g0 = ge.first;
+        }
+        pending_.clear();
+        rg_broken_.clear();
+    }
+
     // Relabel every vertex of the tree rooted at r (top-down).
     void settle_relabel_tree(uint32_t r, uint32_t l) { relabel_tree_with(queue_, r, l); }
     // Label every vertex of the tree rooted at r with l (q: scratch).
@@ -563,6 +669,9 @@ class Forest {
     size_t par_work_ = 16384;
     std::vector<std::vector<uint32_t>> wq_ = std::vector<std::vector<uint32_t>>(1);  // per worker
     std::vector<std::pair<uint32_t, uint32_t>> lm_jobs_;
+    // settle_regroup
+    std::vector<uint32_t> rg_broken_, rg_target_, rg_jobs_, rg_size_, rg_old_, rg_kept_;
+    std::vector<std::pair<uint32_t, uint32_t>> rg_group_end_;
     std::vector<uint32_t> lm_up_, lm_sz_, lm_st_, lm_best_, lm_touched_;  // link_many, by label
     uint32_t lm_ep_ = 0;
     std::vector<std::pair<uint32_t, uint32_t>> lm_edges_;

@@ -96,6 +96,13 @@ static int compare(Forest &A, Forest &B, uint64_t r)
         }
         if (kids != nonroots) return fail("child list count", r);
     }
+    // the live label list names exactly the labels in use
+    for (const Forest *F : {&A, &B}) {
+        std::set<uint32_t> used, live(F->live_labels().begin(), F->live_labels().end());
+        for (uint32_t w = 0; w < F->V(); w++) used.insert(F->label(w));
+        if (used != live || live.size() != F->live_labels().size())
+            return fail("live labels", r);
+    }
     // each tree's recorded root is a root of that tree
     for (const Forest *F : {&A, &B})
         for (uint32_t w = 0; w < F->V(); w++) {
