@@ -98,6 +98,7 @@ int upload_forest(cupk_ctx *ctx)
     const size_t bytes = (size_t)ctx->V * sizeof(uint32_t);
     HIPCHK(hipMemcpyAsync(ctx->d_lbl, ctx->h_lbl, bytes, hipMemcpyHostToDevice, ctx->s));
     HIPCHK(hipMemcpyAsync(ctx->d_par, ctx->h_par, bytes, hipMemcpyHostToDevice, ctx->s));
+    HIPCHK(launch_pack_forest(ctx->s, ctx->d_lbl, ctx->d_par, ctx->d_lp, ctx->V));
     ctx->forest_dev_stale = false;
     return CUPK_OK;
 }
@@ -916,8 +917,8 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
     fi.fdel = ctx->d_fdel.p;
     fi.nb = classify_blocks(grid_n);
     fi.hflags = ctx->opts.exact ? nullptr : ctx->h_fupd.p;
-    HIPCHK(launch_classify(s, desc_ptr(ctx), ctx->cur_desc, grid_n, ctx->V, ctx->d_lbl,
-                           ctx->d_par, ctx->d_hdr, ctx->d_fupd.p,
+    HIPCHK(launch_classify(s, desc_ptr(ctx), ctx->cur_desc, grid_n, ctx->V, ctx->d_lp,
+                           ctx->d_hdr, ctx->d_fupd.p,
                            ctx->opts.exact ? ctx->d_fpos.p : nullptr, ctx->d_fcnt.p,
                            cnt, cls_shift, cls_tiles, sa, ctx->h_hdr, fi, rel));
     return CUPK_OK;
@@ -1350,6 +1351,7 @@ void destroy(cupk_ctx *ctx)
     if (ctx->d_seeds) (void)hipFree(ctx->d_seeds);
     if (ctx->d_lbl) (void)hipFree(ctx->d_lbl);
     if (ctx->d_par) (void)hipFree(ctx->d_par);
+    if (ctx->d_lp) (void)hipFree(ctx->d_lp);
     if (ctx->h_lbl) (void)hipHostFree(ctx->h_lbl);
     if (ctx->h_par) (void)hipHostFree(ctx->h_par);
     if (ctx->d_hdr) (void)hipFree(ctx->d_hdr);
@@ -1518,6 +1520,7 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     HIPCHK(hipMemcpy(ctx->d_seeds, ctx->seeds, 64 * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMalloc((void **)&ctx->d_lbl, (size_t)V * 4));
     HIPCHK(hipMalloc((void **)&ctx->d_par, (size_t)V * 4));
+    HIPCHK(hipMalloc((void **)&ctx->d_lp, (size_t)V * 8));
     HIPCHK(hipHostMalloc((void **)&ctx->h_lbl, (size_t)V * 4, hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&ctx->h_par, (size_t)V * 4, hipHostMallocDefault));
     HIPCHK(hipMalloc((void **)&ctx->d_hdr, HDR_WORDS * 4));

@@ -70,6 +70,7 @@ struct cupk_ctx {
     bool own_sk = false;
     uint64_t *d_seeds = nullptr;
     uint32_t *d_lbl = nullptr, *d_par = nullptr;
+    uint64_t *d_lp = nullptr;  // label | parent << 32 per vertex
     uint32_t *h_lbl = nullptr, *h_par = nullptr;
     bool forest_dev_stale = false;
 

@@ -345,8 +345,8 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_offsets(uint32_t *__restr
 }
 
 __global__ __launch_bounds__(kClsThreads) void k_classify(
-    const BatchDesc *__restrict__ desc, BatchDesc dv, uint32_t V, const uint32_t *__restrict__ lbl,
-    const uint32_t *__restrict__ par, uint32_t *__restrict__ hdr, uint64_t *__restrict__ fupd,
+    const BatchDesc *__restrict__ desc, BatchDesc dv, uint32_t V, const uint64_t *__restrict__ lp,
+    uint32_t *__restrict__ hdr, uint64_t *__restrict__ fupd,
     uint32_t *__restrict__ fpos, uint32_t *__restrict__ fcnt, uint32_t *__restrict__ fdel,
     uint32_t *__restrict__ tile_cnt, uint32_t tile_shift, uint32_t ntiles,
     uint32_t *__restrict__ tile_rel)
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
     const uint32_t lane = __lane_id();
     const uint32_t wid = threadIdx.x / 64;
     uint64_t p[kClsPerThread];
-    uint32_t lu[kClsPerThread], lv[kClsPerThread];
+    uint64_t lu[kClsPerThread], lv[kClsPerThread];  // label | parent << 32
 #pragma unroll
     for (uint32_t k = 0; k < kClsPerThread; k++) {
         const uint32_t i = begin + k * kClsThreads + threadIdx.x;
@@ -381,8 +381,8 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
         lu[k] = lv[k] = 0;
         if (i < n && unpack(p[k], V, u, v, del)) {
             ok |= 1u << k;
-            lu[k] = lbl[u];
-            lv[k] = lbl[v];
+            lu[k] = lp[u];
+            lv[k] = lp[v];
         }
     }
     bool bad = false;
@@ -398,8 +398,8 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
         uint32_t u, v;
         bool del;
         unpack(p[k], V, u, v, del);
-        bool f = lu[k] != lv[k];
-        if (!f && del) f = par[u] == v || par[v] == u;
+        bool f = (uint32_t)lu[k] != (uint32_t)lv[k];
+        if (!f && del) f = (uint32_t)(lu[k] >> 32) == v || (uint32_t)(lv[k] >> 32) == u;
         if (f) fl |= 1u << k;
     }
     __syncthreads();  // hist zeroed
@@ -481,8 +481,24 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
 
 uint32_t classify_blocks(uint32_t n) { return (n + kClsPerBlock - 1) / kClsPerBlock; }
 
+__global__ void k_pack_forest(const uint32_t *__restrict__ lbl, const uint32_t *__restrict__ par,
+                              uint64_t *__restrict__ lp, uint32_t V)
+{
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < V; w += gridDim.x * blockDim.x)
+        lp[w] = (uint64_t)lbl[w] | (uint64_t)par[w] << 32;
+}
+
+hipError_t launch_pack_forest(hipStream_t s, const uint32_t *lbl, const uint32_t *par, uint64_t *lp,
+                              uint32_t V)
+{
+    if (V == 0) return hipSuccess;
+    const uint32_t grid = min((V + 255) / 256, 8192u);
+    k_pack_forest<<<grid, 256, 0, s>>>(lbl, par, lp, V);
+    return hipGetLastError();
+}
+
 hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
-                           uint32_t V, const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
+                           uint32_t V, const uint64_t *lp, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles, const ScanArgs &sa,
                            uint32_t *hout, const FlagInline &fi, uint32_t *tile_rel)
@@ -495,8 +511,7 @@ hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, u
     if (sa.sums && (tile_rel || sa.groups != 1 || ntiles <= kScanOneBlockTiles))
         return hipErrorInvalidValue;
     k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(
-        desc, dv, V, lbl, par, hdr, fupd, fpos, fcnt, fi.fdel, tile_cnt, tile_shift, ntiles,
-        tile_rel);
+        desc, dv, V, lp, hdr, fupd, fpos, fcnt, fi.fdel, tile_cnt, tile_shift, ntiles, tile_rel);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr, hout, fi);

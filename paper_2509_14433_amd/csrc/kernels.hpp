@@ -113,11 +113,15 @@ struct StagedParams {
 // has records in), so that the fill reserves nothing.
 constexpr uint32_t kRelMaxTiles = 2048;
 hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
-                           uint32_t V, const uint32_t *lbl, const uint32_t *par, uint32_t *hdr,
+                           uint32_t V, const uint64_t *lp, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles, const ScanArgs &sa,
                            uint32_t *hout, const FlagInline &fi, uint32_t *tile_rel);
 uint32_t classify_blocks(uint32_t n);
+// lp[w] = lbl[w] | par[w] << 32 (the forest as the classify kernel reads it:
+// one 8-byte load per endpoint gives its label and its parent).
+hipError_t launch_pack_forest(hipStream_t s, const uint32_t *lbl, const uint32_t *par, uint64_t *lp,
+                              uint32_t V);
 
 // Pack the per-block flag regions into one list in stream order (foff:
 // classify_blocks(n) words of scratch); positions too when fpos and opos
