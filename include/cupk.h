@@ -173,6 +173,19 @@ typedef struct {
      * when max_batch is at least 4M updates, else RECORD.  The autotuner
      * tries both. */
     uint32_t tile_layout;
+    /* Nonzero: finish each batch's replacement rounds before the next batch
+     * is classified.  Default: when a device batch follows one whose host
+     * part is still pending (cupk_apply_updates_device), the new batch is
+     * classified against the forest as it stands after the pending batch's
+     * flag walk and binned while that batch's replacement rounds run (their
+     * reductions on a stream of their own).  The rounds only join trees, so
+     * the flags found that way include every flag of the forest after the
+     * rounds; they are checked again against that forest before the scatter,
+     * which leaves exactly the flags, forest and sketch of the serial
+     * order.  A walk that ends with cuts whose trees are not split yet
+     * (their pieces share a label until the rounds split them) has its
+     * rounds run first. */
+    uint32_t serial_rounds;
 } cupk_opts;
 
 /* Counters, cumulative since init. */
@@ -211,6 +224,8 @@ typedef struct {
                                     changed in HBM (nonzero folded delta, or a
                                     record's deep-row bucket): 32 B of
                                     compulsory traffic each (read + write)      */
+    uint64_t overlapped;         /* batches classified and binned while the
+                                    previous batch's rounds ran                 */
 } cupk_counters_t;
 
 /* Bytes of device memory the sketch of (V, C, D) occupies. */
@@ -268,7 +283,10 @@ int cupk_apply_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
  * wait for the GPU.  The host part of the batch (links and cuts of the
  * flagged updates, replacement rounds) stays pending until the next call on
  * ctx that needs it: the next apply call, cupk_sync, cupk_connected and
- * every other call that reads the forest, the sketch or the counters.
+ * every other call that reads the forest, the sketch or the counters.  The
+ * next apply call of a batch above 4096 updates overlaps the two: it
+ * classifies and bins its batch while the pending batch's replacement
+ * rounds run (cupk_opts.serial_rounds turns this off).
  * Validation runs on the GPU: a batch with u == v or an endpoint >= V
  * applies nothing, and CUPK_EINVAL is returned by the call that completes
  * its host part (the next such call).  In exact and levels modes the call

@@ -59,6 +59,7 @@ class cupk_opts(ctypes.Structure):
         ("split_rounds", ctypes.c_uint32),
         ("fill_reserve", ctypes.c_uint32),
         ("tile_layout", ctypes.c_uint32),
+        ("serial_rounds", ctypes.c_uint32),
     ]
 
 
@@ -77,7 +78,8 @@ class cupk_counters_t(ctypes.Structure):
         ("timed_updates", ctypes.c_uint64),
         ("pieces_sketchless", ctypes.c_uint64),
         ("sets_complemented", ctypes.c_uint64),
-        ("timed_buckets", ctypes.c_uint64)]
+        ("timed_buckets", ctypes.c_uint64),
+        ("overlapped", ctypes.c_uint64)]
 
 
 class cupk_serve_opts(ctypes.Structure):
@@ -186,7 +188,7 @@ class Context:
                  stream=None, use_torch_memory=True, time_kernels=False, tile_vertices=0,
                  lds_rows=0, chunk_records=0, tile_grid=0, use_graph=False, exact=False,
                  levels=False, walk_plain=False, split_rounds=False, fill_reserve=False,
-                 tile_layout=0):
+                 tile_layout=0, serial_rounds=False):
         self._h = None
         self._sk_tensor = None
         self._keep = {}
@@ -206,6 +208,7 @@ class Context:
         opts.split_rounds = 1 if split_rounds else 0
         opts.fill_reserve = 1 if fill_reserve else 0
         opts.tile_layout = tile_layout
+        opts.serial_rounds = 1 if serial_rounds else 0
         torch = _torch()
         if stream is None and torch is not None and torch.cuda.is_available():
             # launch on torch's current stream so that torch-produced device

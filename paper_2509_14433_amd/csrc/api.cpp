@@ -84,7 +84,7 @@ int harvest_timers(cupk_ctx *ctx, bool all)
         }
         float ms_b = 0.f, ms_s = 0.f;
         HIPCHK(hipEventElapsedTime(&ms_b, t.t0, t.tb));
-        HIPCHK(hipEventElapsedTime(&ms_s, t.tb, t.t1));
+        HIPCHK(hipEventElapsedTime(&ms_s, t.split ? t.tc : t.tb, t.t1));
         ctx->ctr.bin_ms += ms_b;
         ctx->ctr.scatter_ms += ms_s;
         t.busy = false;
@@ -126,6 +126,7 @@ int reduce_and_sample(cupk_ctx *ctx, int slot, const std::vector<uint32_t> &vmem
     const uint32_t k = kv + kf;
     if (k == 0) return CUPK_OK;
     const uint32_t W = ctx->W;
+    const hipStream_t rs = ctx->rstream;
     HIPCHK(grow(ctx->d_sig[slot], (size_t)k * W));
     HIPCHK(grow(ctx->d_res, (size_t)3 * k));
     HIPCHK(grow(ctx->h_res, (size_t)3 * k));
@@ -153,21 +154,21 @@ int reduce_and_sample(cupk_ctx *ctx, int slot, const std::vector<uint32_t> &vmem
     std::copy(items.begin(), items.end(), ctx->h_ridx.p + nmem);
     if (nall)
         HIPCHK(hipMemcpyAsync(ctx->d_ridx.p, ctx->h_ridx.p, nall * 4, hipMemcpyHostToDevice,
-                              ctx->s));
+                              rs));
     const uint32_t *d_items = ctx->d_ridx.p + nmem;
     uint64_t *sig = ctx->d_sig[slot].p;
-    HIPCHK(launch_zero(ctx->s, sig, (size_t)k * W));
+    HIPCHK(launch_zero(rs, sig, (size_t)k * W));
     if (nvi)
-        HIPCHK(launch_reduce(ctx->s, ctx->d_sk, W, ctx->d_ridx.p, d_items, (uint32_t)nvi,
+        HIPCHK(launch_reduce(rs, ctx->d_sk, W, ctx->d_ridx.p, d_items, (uint32_t)nvi,
                              sig));
     if (nitems > nvi)
-        HIPCHK(launch_reduce(ctx->s, ctx->d_sig[1 - slot].p, W, ctx->d_ridx.p,
+        HIPCHK(launch_reduce(rs, ctx->d_sig[1 - slot].p, W, ctx->d_ridx.p,
                              d_items + 3 * nvi, (uint32_t)(nitems - nvi), sig));
-    HIPCHK(launch_sample(ctx->s, sig, k, ctx->V, ctx->C, ctx->D, 1, ctx->C, W, ctx->d_seeds,
+    HIPCHK(launch_sample(rs, sig, k, ctx->V, ctx->C, ctx->D, 1, ctx->C, W, ctx->d_seeds,
                          ctx->d_res.p));
     HIPCHK(hipMemcpyAsync(ctx->h_res.p, ctx->d_res.p, (size_t)3 * k * 4, hipMemcpyDeviceToHost,
-                          ctx->s));
-    HIPCHK(hipStreamSynchronize(ctx->s));
+                          rs));
+    HIPCHK(hipStreamSynchronize(rs));
     ctx->ctr.sets_reduced += k;
     ctx->ctr.slabs_reduced += nmem;
     return CUPK_OK;
@@ -873,7 +874,23 @@ StagedParams staged_params(cupk_ctx *ctx, uint32_t grid_n)
 // batch's scatter (and at init).
 static const BatchDesc *desc_ptr(cupk_ctx *ctx) { return ctx->capturing ? ctx->d_desc : nullptr; }
 
-int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
+// Where the scan after classification finds the flag regions (and puts a
+// short flag list: straight into host memory, except in exact mode, which
+// also needs the flags' positions).
+static FlagInline flag_inline(cupk_ctx *ctx, uint32_t grid_n)
+{
+    FlagInline fi = {};
+    fi.fupd = ctx->d_fupd.p;
+    fi.fcnt = ctx->d_fcnt.p;
+    fi.fdel = ctx->d_fdel.p;
+    fi.nb = classify_blocks(grid_n);
+    fi.hflags = ctx->opts.exact ? nullptr : ctx->h_fupd.p;
+    return fi;
+}
+
+// tiles_only: leave the flags unpublished (an overlapped pass checks them
+// again against the forest after the previous batch's rounds).
+int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n, bool tiles_only = false)
 {
     const bool staged = ctx->opts.scatter_mode == CUPK_SCATTER_STAGED;
     ScanArgs sa = {};
@@ -909,14 +926,8 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n)
         sa.groups = kCntGroups;
         sa.goff = ctx->fshift ? ctx->d_cgoff.p : ctx->d_tgoff.p;
     }
-    // short flag lists come back with the header (not in exact mode, which
-    // also needs their positions)
-    FlagInline fi = {};
-    fi.fupd = ctx->d_fupd.p;
-    fi.fcnt = ctx->d_fcnt.p;
-    fi.fdel = ctx->d_fdel.p;
-    fi.nb = classify_blocks(grid_n);
-    fi.hflags = ctx->opts.exact ? nullptr : ctx->h_fupd.p;
+    FlagInline fi = flag_inline(ctx, grid_n);
+    fi.tiles_only = tiles_only ? 1u : 0u;
     HIPCHK(launch_classify(s, desc_ptr(ctx), ctx->cur_desc, grid_n, ctx->V, ctx->d_lp,
                            ctx->d_hdr, ctx->d_fupd.p,
                            ctx->opts.exact ? ctx->d_fpos.p : nullptr, ctx->d_fcnt.p,
@@ -1009,10 +1020,83 @@ int capture_graphs(cupk_ctx *ctx)
 // revert pass applies updates again to undo a speculative scatter (XOR
 // toggles back); it leaves the forest mirror alone and its flags are not
 // read.
+// The timer slot of the pass being enqueued (every time_kernels-th pass),
+// or null.
+static int take_timer(cupk_ctx *ctx, uint32_t n, cupk_ctx::TimerSlot **out)
+{
+    *out = nullptr;
+    if (!ctx->opts.time_kernels || ctx->ctr.scatter_launches % ctx->opts.time_kernels != 0)
+        return CUPK_OK;
+    ctx->ctr.timed_launches++;
+    ctx->ctr.timed_updates += n;
+    cupk_ctx::TimerSlot *ts = &ctx->timers[ctx->timer_head];
+    ctx->timer_head = (ctx->timer_head + 1) % kTimerRing;
+    if (ts->busy) {
+        HIPCHK(hipEventSynchronize(ts->t1));
+        const int rc = harvest_timers(ctx, false);
+        if (rc != CUPK_OK) return rc;
+    }
+    ts->split = false;
+    *out = ts;
+    return CUPK_OK;
+}
+
+// An overlapped pass in two halves.  Front: classify the batch against the
+// forest on the device (which the caller uploaded after the previous
+// batch's flag walk) without publishing its flags, and bin it.  Back (after
+// the previous batch's rounds): upload the forest as the rounds left it,
+// keep the flags that forest still gives, publish them with the header,
+// and scatter.
+static int enqueue_split_front(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
+{
+    int rc = harvest_timers(ctx, false);
+    if (rc != CUPK_OK) return rc;
+    ctx->small_pass = false;
+    ctx->cur_desc.upd = d_upd;
+    ctx->cur_desc.n = n;
+    cupk_ctx::TimerSlot *ts = nullptr;
+    rc = take_timer(ctx, n, &ts);
+    if (rc != CUPK_OK) return rc;
+    rc = enqueue_classify(ctx, ctx->s, n, true);
+    if (rc != CUPK_OK) return rc;
+    if (ts) HIPCHK(hipEventRecord(ts->t0, ctx->s));
+    rc = enqueue_bin(ctx, ctx->s, n);
+    if (rc != CUPK_OK) return rc;
+    if (ts) HIPCHK(hipEventRecord(ts->tb, ctx->s));
+    ctx->split_ts = ts;
+    return CUPK_OK;
+}
+
+static int enqueue_split_back(cupk_ctx *ctx, uint32_t n)
+{
+    int rc = upload_forest(ctx);
+    if (rc != CUPK_OK) return rc;
+    // the flags are packed on this stream before the header: packed by the
+    // walk on the copy stream, they would wait for the scatter's blocks
+    HIPCHK(launch_reflag(ctx->s, ctx->V, ctx->d_lp, ctx->d_hdr, ctx->d_fupd.p, ctx->h_hdr,
+                         flag_inline(ctx, n), ctx->d_foff.p, ctx->d_oupd.p));
+    ctx->flags_packed = true;
+    cupk_ctx::TimerSlot *ts = ctx->split_ts;
+    ctx->split_ts = nullptr;
+    if (ts) HIPCHK(hipEventRecord(ts->tc, ctx->s));
+    rc = enqueue_tile(ctx, ctx->s, n, ts != nullptr);
+    if (rc != CUPK_OK) return rc;
+    ctx->hdr_seq++;
+    ctx->hdr_word = &ctx->h_hdr[HDR_SEQ];
+    if (ts) {
+        HIPCHK(hipEventRecord(ts->t1, ctx->s));
+        ts->split = true;
+        ts->busy = true;
+    }
+    ctx->ctr.scatter_launches++;
+    return CUPK_OK;
+}
+
 int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
 {
     int rc = harvest_timers(ctx, false);
     if (rc != CUPK_OK) return rc;
+    ctx->flags_packed = false;
     if (!revert) {
         rc = upload_forest(ctx);
         if (rc != CUPK_OK) return rc;
@@ -1054,17 +1138,8 @@ int enqueue_pass(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool revert)
     // Timed passes (every time_kernels-th) get events around the binning and
     // the scatter; captured graphs are then launched in their three parts.
     cupk_ctx::TimerSlot *ts = nullptr;
-    if (ctx->opts.time_kernels && ctx->ctr.scatter_launches % ctx->opts.time_kernels == 0) {
-        ctx->ctr.timed_launches++;
-        ctx->ctr.timed_updates += n;
-        ts = &ctx->timers[ctx->timer_head];
-        ctx->timer_head = (ctx->timer_head + 1) % kTimerRing;
-        if (ts->busy) {
-            HIPCHK(hipEventSynchronize(ts->t1));
-            rc = harvest_timers(ctx, false);
-            if (rc != CUPK_OK) return rc;
-        }
-    }
+    rc = take_timer(ctx, n, &ts);
+    if (rc != CUPK_OK) return rc;
     // The classify step publishes the header to pinned host memory itself,
     // and the host waits for it by its sequence number, not an event: every
     // event recorded between two kernels leaves the GPU idle for a few
@@ -1199,7 +1274,7 @@ int walk_pass(cupk_ctx *ctx, uint32_t n, bool exact, uint32_t *cut_pos, uint32_t
         // already ordered after the classify kernel), then fetch and walk it
         // in growing chunks: the walk may stop early
         uint32_t *opos = exact ? ctx->d_opos.p : nullptr;
-        if (!have)
+        if (!have && !ctx->flags_packed)
             HIPCHK(launch_flag_compact(ctx->cs, n, ctx->d_fupd.p, exact ? ctx->d_fpos.p : nullptr,
                                        ctx->d_fcnt.p, ctx->d_foff.p, ctx->d_oupd.p, opos));
         uint32_t k0 = 0, step = have ? nflag : 1u << 16;
@@ -1270,24 +1345,135 @@ int flush_pending(cupk_ctx *ctx)
     return finish_pass(ctx, ctx->pending_n);
 }
 
+// Leave the host part of the batch just enqueued (n updates) pending.  A
+// large batch's scatter is marked for the replacement rounds of an
+// overlapped next batch (which reduce on another stream after it).
+static int set_pending(cupk_ctx *ctx, uint32_t n)
+{
+    ctx->scat_marked = false;
+    if (n > kSmallMax && !ctx->opts.serial_rounds) {
+        HIPCHK(hipEventRecord(ctx->ev_scat, ctx->s));
+        ctx->scat_marked = true;
+    }
+    ctx->pending = true;
+    ctx->pending_n = n;
+    return CUPK_OK;
+}
+
+// Whether batch k+1 (n updates) can be classified and binned while the
+// pending batch k's replacement rounds run: batch semantics, no captured
+// graphs, not a small batch, and batch buffers that already hold it (a
+// reallocation could free buffers that k's scatter still uses).
+static bool can_overlap(cupk_ctx *ctx, uint32_t n)
+{
+    return ctx->pending && !ctx->opts.serial_rounds && !ctx->opts.exact && !ctx->levels &&
+           ctx->opts.use_graph == 0 && n > kSmallMax && n <= ctx->batch_cap;
+}
+
+static int apply_flushed(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool defer);
+
+// Pending batch k, new batch k+1 (n updates at d_upd).  Walk k's flags into
+// the forest; upload that forest on the copy stream; classify and bin k+1
+// against it on the main stream while k's replacement rounds run on the
+// host, their reductions on the copy stream after k's scatter (the copy
+// stream is idle meanwhile: k's flags have been fetched, k+1's are not
+// published yet; a stream of their own would cost a hardware queue, and
+// streams that share one run in one order); then the
+// back half of k+1 (enqueue_split_back).  The rounds only link trees, so
+// the forest after the walk has finer trees and a subset of the edges of
+// the forest after the rounds: every update the classify rule flags against
+// the latter it also flags against the former (a delete of an edge the
+// rounds added joins two trees of the former), and the check against the
+// latter in the back half leaves exactly the serial order's flags.  This
+// needs exact labels after the walk: when it ends with removals whose trees
+// are not split yet (their pieces still share a label until the rounds
+// split them), k's rounds run first and k+1 takes the serial order.  An
+// error of k's rounds is this call's, and k+1 is then still applied.
+static int apply_overlapped(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool defer)
+{
+    ctx->pending = false;
+    const uint32_t nk = ctx->pending_n;
+    const unsigned long long bk = (unsigned long long)ctx->ctr.batches;
+    uint32_t nflag = 0;
+    double tw = 0, tc = 0;
+    const double t0 = now_ms();
+    int rc = walk_pass(ctx, nk, false, nullptr, nullptr, nullptr, &nflag, &tw, &tc);
+    if (rc != CUPK_OK) return rc;
+    const double t1 = now_ms();
+    if (ctx->forest.has_pending()) {
+        ctx->scat_marked = false;
+        const int rr = run_rounds(ctx);
+        const double t3 = now_ms();
+        ctx->ctr.host_rounds_ms += t3 - t1;
+        if (ctx->trace)
+            fprintf(stderr,
+                    "cupk batch %llu n=%u nflag=%u wait=%.3f copy=%.3f flags=%.3f rounds=%.3f ms\n",
+                    bk, nk, nflag, tw, tc, t1 - t0 - tw - tc, t3 - t1);
+        if (rr != CUPK_OK) return rr;
+        return apply_flushed(ctx, d_upd, n, defer);
+    }
+    if (!ctx->scat_marked) HIPCHK(hipEventRecord(ctx->ev_scat, ctx->s));
+    ctx->scat_marked = false;
+    // the forest after the walk, for k+1's classification (every earlier
+    // reader of the device forest has finished: k's header, which the walk
+    // waited for, is published after them)
+    const bool up = ctx->forest_dev_stale;
+    if (up) {
+        const size_t bytes = (size_t)ctx->V * sizeof(uint32_t);
+        HIPCHK(hipMemcpyAsync(ctx->d_lbl, ctx->h_lbl, bytes, hipMemcpyHostToDevice, ctx->cs));
+        HIPCHK(hipMemcpyAsync(ctx->d_par, ctx->h_par, bytes, hipMemcpyHostToDevice, ctx->cs));
+        HIPCHK(launch_pack_forest(ctx->cs, ctx->d_lbl, ctx->d_par, ctx->d_lp, ctx->V));
+        HIPCHK(hipEventRecord(ctx->ev_up, ctx->cs));
+        HIPCHK(hipStreamWaitEvent(ctx->s, ctx->ev_up, 0));
+        ctx->forest_dev_stale = false;
+    }
+    ctx->ctr.updates += n;
+    ctx->ctr.batches++;
+    ctx->ctr.overlapped++;
+    rc = enqueue_split_front(ctx, d_upd, n);
+    if (rc != CUPK_OK) return rc;
+    // the rounds write the host forest the copies read
+    if (up) HIPCHK(hipEventSynchronize(ctx->ev_up));
+    HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->ev_scat, 0));
+    ctx->rstream = ctx->cs;
+    const double t2 = now_ms();
+    const int rr = run_rounds(ctx);
+    const double t3 = now_ms();
+    ctx->rstream = ctx->s;
+    ctx->ctr.host_rounds_ms += t3 - t2;
+    if (ctx->trace)
+        fprintf(stderr,
+                "cupk batch %llu n=%u nflag=%u wait=%.3f copy=%.3f flags=%.3f rounds=%.3f ms "
+                "(next batch classified and binned meanwhile)\n",
+                bk, nk, nflag, tw, tc, t1 - t0 - tw - tc, t3 - t2);
+    rc = enqueue_split_back(ctx, n);
+    if (rr != CUPK_OK) return rr;
+    if (rc != CUPK_OK) return rc;
+    if (defer) return set_pending(ctx, n);
+    return finish_pass(ctx, n);
+}
+
 // One batch of at most kMaxBatchPerLaunch updates.  defer: leave the host
 // part pending (batch semantics only; exact mode always completes).
 int apply_device_one(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool defer)
 {
-    int rc = flush_pending(ctx);
+    if (can_overlap(ctx, n)) return apply_overlapped(ctx, d_upd, n, defer);
+    const int rc = flush_pending(ctx);
     if (rc != CUPK_OK) return rc;
-    rc = ensure_batch_buffers(ctx, n);
+    return apply_flushed(ctx, d_upd, n, defer);
+}
+
+// The rest of apply_device_one once no host part is pending.
+static int apply_flushed(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool defer)
+{
+    int rc = ensure_batch_buffers(ctx, n);
     if (rc != CUPK_OK) return rc;
     ctx->ctr.updates += n;
     ctx->ctr.batches++;
     if (!ctx->opts.exact) {
         rc = enqueue_pass(ctx, d_upd, n, false);
         if (rc != CUPK_OK) return rc;
-        if (defer && !ctx->levels) {
-            ctx->pending = true;
-            ctx->pending_n = n;
-            return CUPK_OK;
-        }
+        if (defer && !ctx->levels) return set_pending(ctx, n);
         return finish_pass(ctx, n);
     }
     // exact mode: speculate over the rest of the batch, stop at the first
@@ -1401,10 +1587,13 @@ void destroy(cupk_ctx *ctx)
     for (auto &t : ctx->timers) {
         if (t.t0) (void)hipEventDestroy(t.t0);
         if (t.tb) (void)hipEventDestroy(t.tb);
+        if (t.tc) (void)hipEventDestroy(t.tc);
         if (t.t1) (void)hipEventDestroy(t.t1);
     }
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->ev_scat) (void)hipEventDestroy(ctx->ev_scat);
+    if (ctx->ev_up) (void)hipEventDestroy(ctx->ev_up);
     if (ctx->cs) (void)hipStreamDestroy(ctx->cs);
     if (ctx->own_stream && ctx->s) (void)hipStreamDestroy(ctx->s);
     delete ctx;
@@ -1500,12 +1689,16 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
         ctx->own_stream = true;
     }
     HIPCHK(hipStreamCreateWithFlags(&ctx->cs, hipStreamNonBlocking));
+    ctx->rstream = ctx->s;
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_scat, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_up, hipEventDisableTiming));
     if (ctx->opts.time_kernels)
         for (auto &t : ctx->timers) {
             HIPCHK(hipEventCreate(&t.t0));
             HIPCHK(hipEventCreate(&t.tb));
+            HIPCHK(hipEventCreate(&t.tc));
             HIPCHK(hipEventCreate(&t.t1));
         }
     const size_t sk_bytes = cupk_sketch_bytes(V, C, D);
@@ -1688,10 +1881,10 @@ int cupk_apply_updates_device(cupk_ctx *ctx, const uint64_t *d_packed, size_t n,
     return guarded(ctx, [&]() -> int {
         if (n == 0) return CUPK_OK;
         if (!d_packed) return ctx->invalid("null device pointer");
-        // the host part of the previous batch first: its error is this call's
+        // the host part of the previous batch comes first, or overlaps the
+        // new batch's classification (apply_device_one): its error is this
+        // call's
         const hipStream_t cs = (hipStream_t)hip_stream;
-        int rc = flush_pending(ctx);
-        if (rc != CUPK_OK) return rc;
         // the batch is read on the library's stream after what the caller's
         // stream has queued so far, and the caller's stream waits for the
         // scatter (the last kernel that reads the batch)
@@ -1699,7 +1892,7 @@ int cupk_apply_updates_device(cupk_ctx *ctx, const uint64_t *d_packed, size_t n,
             HIPCHK(hipEventRecord(ctx->ev_in, cs));
             HIPCHK(hipStreamWaitEvent(ctx->s, ctx->ev_in, 0));
         }
-        rc = apply_device(ctx, d_packed, n, true);
+        const int rc = apply_device(ctx, d_packed, n, true);
         if (cs != ctx->s) {
             // also after a failure: whatever was enqueued is ordered
             if (hipEventRecord(ctx->ev_out, ctx->s) == hipSuccess)

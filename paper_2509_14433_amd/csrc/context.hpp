@@ -59,9 +59,12 @@ struct cupk_ctx {
     uint32_t hdr_seq = 0;          // headers published by the device so far (expected)
     uint32_t *hdr_word = nullptr;  // where the current pass publishes its sequence number
     bool query_often = false;      // the pass's batch was uploaded from host memory
+    // timed pass: t0 after classification, tb after binning, tc before the
+    // scatter (split passes only: reflagging and the wait for the previous
+    // batch's rounds come between), t1 after the scatter
     struct TimerSlot {
-        hipEvent_t t0, tb, t1;
-        bool busy;
+        hipEvent_t t0, tb, tc, t1;
+        bool busy, split;
     };
     TimerSlot timers[cupk::kTimerRing] = {};
     int timer_head = 0;
@@ -118,6 +121,15 @@ struct cupk_ctx {
     bool pending = false;
     uint32_t pending_n = 0;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;  // ordering with a caller's stream
+    // Overlapped passes: the pending batch's replacement rounds reduce on
+    // cs (after ev_scat, its scatter) while s classifies and bins the next
+    // batch (after ev_up, the forest's upload on cs); rstream is the stream
+    // the rounds use (s otherwise)
+    hipStream_t rstream = nullptr;
+    hipEvent_t ev_scat = nullptr, ev_up = nullptr;
+    TimerSlot *split_ts = nullptr;  // timer of the split pass in flight
+    bool scat_marked = false;       // ev_scat follows the pending batch's scatter
+    bool flags_packed = false;      // the last pass packed its flag list on the device
     // device address of the allocation-free entry point's scratch array on
     // this context's device (taken at init)
     uint64_t *noalloc_scratch = nullptr;

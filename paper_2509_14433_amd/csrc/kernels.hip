@@ -146,60 +146,62 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t *__restrict
     __shared__ uint32_t boff[kInlineMaxBlocks];
     static_assert(kInlineFlags < 65536 && kClsPerBlock < 65536, "packed region words");
     const bool err = hdr[HDR_ERR] != 0;
-    // the batch's flag counts: sums of the classify blocks' counts
-    uint32_t nflag, nflag_del;
-    {
-        uint32_t a = 0, b = 0;
-        for (uint32_t i = threadIdx.x; i < fi.nb; i += kScanThreads) {
-            a += fi.fcnt[i];
-            b += fi.fdel[i];
+    if (!fi.tiles_only) {
+        // the batch's flag counts: sums of the classify blocks' counts
+        uint32_t nflag, nflag_del;
+        {
+            uint32_t a = 0, b = 0;
+            for (uint32_t i = threadIdx.x; i < fi.nb; i += kScanThreads) {
+                a += fi.fcnt[i];
+                b += fi.fdel[i];
+            }
+            block_exscan<kScanThreads>(a, nflag, sh);
+            block_exscan<kScanThreads>(b, nflag_del, sh);
         }
-        block_exscan<kScanThreads>(a, nflag, sh);
-        block_exscan<kScanThreads>(b, nflag_del, sh);
-    }
-    // few flagged updates: compact them into host memory in stream order
-    // (one wave per classify block's region)
-    const bool inl = fi.hflags && !err && nflag <= kInlineFlags && fi.nb <= kInlineMaxBlocks;
-    if (inl && nflag) {
-        uint32_t carry = 0;
-        for (uint32_t base = 0; base < fi.nb; base += kScanThreads) {
-            const uint32_t b = base + threadIdx.x;
-            const uint32_t c = b < fi.nb ? fi.fcnt[b] : 0u;
-            uint32_t tot;
-            const uint32_t ex = block_exscan<kScanThreads>(c, tot, sh);
-            // count (<= 4096) and start (<= kInlineFlags) of the region,
-            // packed: the copy below reads no global count again
-            if (b < fi.nb) boff[b] = c << 16 | (carry + ex);
-            carry += tot;
+        // few flagged updates: compact them into host memory in stream order
+        // (one wave per classify block's region)
+        const bool inl = fi.hflags && !err && nflag <= kInlineFlags && fi.nb <= kInlineMaxBlocks;
+        if (inl && nflag) {
+            uint32_t carry = 0;
+            for (uint32_t base = 0; base < fi.nb; base += kScanThreads) {
+                const uint32_t b = base + threadIdx.x;
+                const uint32_t c = b < fi.nb ? fi.fcnt[b] : 0u;
+                uint32_t tot;
+                const uint32_t ex = block_exscan<kScanThreads>(c, tot, sh);
+                // count (<= 4096) and start (<= kInlineFlags) of the region,
+                // packed: the copy below reads no global count again
+                if (b < fi.nb) boff[b] = c << 16 | (carry + ex);
+                carry += tot;
+            }
+            __syncthreads();
+            const uint32_t lane = __lane_id();
+            for (uint32_t b = threadIdx.x / 64; b < fi.nb; b += kScanThreads / 64) {
+                const uint32_t w = boff[b];
+                const uint32_t c = w >> 16, o = w & 0xffffu;
+                for (uint32_t k = lane; k < c; k += 64)
+                    fi.hflags[o + k] = fi.fupd[(size_t)b * kClsPerBlock + k];
+            }
+            // every wave waits until its stores have been acknowledged; thread
+            // 0's system-scope release of the sequence number below then writes
+            // back L2 once for the whole block (a system fence in every wave
+            // would write it back once per wave)
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
         }
-        __syncthreads();
-        const uint32_t lane = __lane_id();
-        for (uint32_t b = threadIdx.x / 64; b < fi.nb; b += kScanThreads / 64) {
-            const uint32_t w = boff[b];
-            const uint32_t c = w >> 16, o = w & 0xffffu;
-            for (uint32_t k = lane; k < c; k += 64)
-                fi.hflags[o + k] = fi.fupd[(size_t)b * kClsPerBlock + k];
+        // the header goes straight to host memory (no copy, no event): words
+        // first, then the sequence number with release semantics
+        if (threadIdx.x == 0) {
+            hout[HDR_ERR] = hdr[HDR_ERR];
+            hdr[HDR_NFLAG] = nflag;
+            hdr[HDR_NFLAG_DEL] = nflag_del;
+            hout[HDR_NFLAG] = nflag;
+            hout[HDR_NFLAG_DEL] = nflag_del;
+            hout[HDR_INLINE] = inl ? 1u : 0u;
+            const uint32_t seq = hdr[HDR_SEQ] + 1;
+            hdr[HDR_SEQ] = seq;
+            __hip_atomic_store(&hout[HDR_SEQ], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
-        // every wave waits until its stores have been acknowledged; thread
-        // 0's system-scope release of the sequence number below then writes
-        // back L2 once for the whole block (a system fence in every wave
-        // would write it back once per wave)
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    }
-    // the header goes straight to host memory (no copy, no event): words
-    // first, then the sequence number with release semantics
-    if (threadIdx.x == 0) {
-        hout[HDR_ERR] = hdr[HDR_ERR];
-        hdr[HDR_NFLAG] = nflag;
-        hdr[HDR_NFLAG_DEL] = nflag_del;
-        hout[HDR_NFLAG] = nflag;
-        hout[HDR_NFLAG_DEL] = nflag_del;
-        hout[HDR_INLINE] = inl ? 1u : 0u;
-        const uint32_t seq = hdr[HDR_SEQ] + 1;
-        hdr[HDR_SEQ] = seq;
-        __hip_atomic_store(&hout[HDR_SEQ], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     if (!a.off || a.sums) return;  // no tile counts, or the multi-block kernels scan them
     const uint32_t ng = a.groups;  // count copies (1 or kCntGroups)
@@ -514,8 +516,12 @@ hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, u
         desc, dv, V, lp, hdr, fupd, fpos, fcnt, fi.fdel, tile_cnt, tile_shift, ntiles, tile_rel);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr, hout, fi);
-    e = hipGetLastError();
+    // (nothing to do for the one-block scan when it only scans tiles and
+    // the multi-block kernels do that, or there are no tile counts)
+    if (!fi.tiles_only || (tile_cnt && sa.off && !sa.sums)) {
+        k_tile_scan<<<1, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa, hdr, hout, fi);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess || !tile_cnt || !sa.sums) return e;
     const uint32_t nch = tile_scan_chunks(ntiles);
     k_tile_sums<<<nch, kScanThreads, 0, s>>>(tile_cnt, ntiles, sa.chunk, sa.sums);
@@ -1455,6 +1461,72 @@ hipError_t launch_flag_compact(hipStream_t s, uint32_t n, const uint64_t *fupd,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_flag_compact<<<nb, 256, 0, s>>>(fupd, fpos, fcnt, foff, oupd, opos);
+    return hipGetLastError();
+}
+
+// Flag check against a newer forest, one wave per classify block's region:
+// each step reads 64 flagged updates, keeps those the classify rule still
+// flags against `lp`, and writes them back packed at the front of the
+// region (a step writes below the next step's reads: in place is safe).
+constexpr uint32_t kReflagThreads = 256;
+
+__global__ __launch_bounds__(kReflagThreads) void k_reflag(uint32_t V, const uint64_t *__restrict__ lp,
+                                                           const uint32_t *__restrict__ hdr,
+                                                           uint64_t *__restrict__ fupd,
+                                                           uint32_t *__restrict__ fcnt,
+                                                           uint32_t *__restrict__ fdel, uint32_t nb)
+{
+    const uint32_t b = blockIdx.x * (kReflagThreads / 64) + threadIdx.x / 64;
+    if (b >= nb || hdr[HDR_ERR] != 0) return;  // whole waves
+    const uint32_t lane = __lane_id();
+    const uint32_t c = fcnt[b];
+    uint64_t *r = fupd + (size_t)b * kClsPerBlock;
+    uint32_t w = 0, nd = 0;
+    for (uint32_t k0 = 0; k0 < c; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        bool keep = false, del = false;
+        uint64_t p = 0;
+        if (k < c) {
+            p = r[k];
+            uint32_t u, v;
+            unpack(p, V, u, v, del);
+            const uint64_t lu = lp[u], lv = lp[v];
+            keep = (uint32_t)lu != (uint32_t)lv;
+            if (!keep && del) keep = (uint32_t)(lu >> 32) == v || (uint32_t)(lv >> 32) == u;
+        }
+        const uint64_t m = __ballot(keep);
+        if (keep) r[w + lanes_below(m)] = p;
+        w += (uint32_t)__popcll(m);
+        nd += (uint32_t)__popcll(__ballot(keep && del));
+    }
+    if (lane == 0) {
+        fcnt[b] = w;
+        fdel[b] = nd;
+    }
+}
+
+hipError_t launch_reflag(hipStream_t s, uint32_t V, const uint64_t *lp, uint32_t *hdr,
+                         uint64_t *fupd, uint32_t *hout, const FlagInline &fi, uint32_t *foff,
+                         uint64_t *oupd)
+{
+    if (!fi.fdel || !fi.fcnt || fi.fupd != fupd || fi.tiles_only || !foff || !oupd)
+        return hipErrorInvalidValue;
+    if (fi.nb) {
+        const uint32_t per = kReflagThreads / 64;
+        k_reflag<<<(fi.nb + per - 1) / per, kReflagThreads, 0, s>>>(
+            V, lp, hdr, fupd, const_cast<uint32_t *>(fi.fcnt), fi.fdel, fi.nb);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // the ordered list, before the header: the host only copies it
+        k_flag_scan<<<1, kScanThreads, 0, s>>>(fi.fcnt, fi.nb, foff);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_flag_compact<<<fi.nb, 256, 0, s>>>(fupd, nullptr, fi.fcnt, foff, oupd, nullptr);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // header only: no tile counts
+    k_tile_scan<<<1, kScanThreads, 0, s>>>(nullptr, 0, ScanArgs{}, hdr, hout, fi);
     return hipGetLastError();
 }
 

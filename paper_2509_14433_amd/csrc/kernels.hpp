@@ -52,6 +52,10 @@ struct FlagInline {
     uint32_t *fdel;        // flagged deletes per classify block
     uint32_t nb;           // classify blocks
     uint64_t *hflags;      // coherent pinned host memory; null: never inline
+    // 1: the scan after the classify kernel leaves the flags and the header
+    // alone (launch_reflag checks the flags against a newer forest and
+    // publishes them later); 0: it publishes them
+    uint32_t tiles_only;
 };
 
 // Where the one-block tile scan writes: bin offsets and fill cursors
@@ -122,6 +126,19 @@ uint32_t classify_blocks(uint32_t n);
 // one 8-byte load per endpoint gives its label and its parent).
 hipError_t launch_pack_forest(hipStream_t s, const uint32_t *lbl, const uint32_t *par, uint64_t *lp,
                               uint32_t V);
+// Second half of a classification launched with fi.tiles_only = 1: keep,
+// in each classify block's region of fi.fupd (in place, stream order kept),
+// only the updates the classify kernel's rule flags against the forest in
+// `lp`, and rewrite fi.fcnt and fi.fdel; pack the regions into one ordered
+// list at oupd (foff: fi.nb words of scratch), as launch_flag_compact does;
+// then publish the flag counts, the short flag lists and the header as
+// launch_classify does otherwise.  Exact when `lp` is a coarsening of the
+// forest the regions were flagged against that keeps all its edges (it then
+// flags a subset of what that forest flagged).  A rejected batch (header
+// error) keeps its regions.
+hipError_t launch_reflag(hipStream_t s, uint32_t V, const uint64_t *lp, uint32_t *hdr,
+                         uint64_t *fupd, uint32_t *hout, const FlagInline &fi, uint32_t *foff,
+                         uint64_t *oupd);
 
 // Pack the per-block flag regions into one list in stream order (foff:
 // classify_blocks(n) words of scratch); positions too when fpos and opos

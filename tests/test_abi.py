@@ -79,3 +79,32 @@ def test_context_roundtrip_on_gpu():
     assert ctx.num_components() == 64
     assert ctx.digest() == ctx.digest()
     ctx.close()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    # every field of every struct the binding mirrors: offset and size as a C
+    # compiler lays out the header's definition
+    import shutil
+    import subprocess
+    import paper_2509_14433_amd._binding as b
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = [b.cupk_bucket, b.cupk_opts, b.cupk_counters_t, b.cupk_static_info,
+               b.cupk_tune_result, b.cupk_serve_opts, b.cupk_serve_stats_t]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "cupk.h"', "int main(void) {"]
+    for st in structs:
+        lines.append(f'printf("{st.__name__} %zu\\n", sizeof({st.__name__}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{st.__name__}.{f} %zu\\n", offsetof({st.__name__}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(ln.split() for ln in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                   text=True).stdout.splitlines())
+    for st in structs:
+        assert int(got[st.__name__]) == ctypes.sizeof(st), st.__name__
+        for f, _ in st._fields_:
+            assert int(got[f"{st.__name__}.{f}"]) == getattr(st, f).offset, (st.__name__, f)
