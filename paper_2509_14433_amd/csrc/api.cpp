@@ -92,16 +92,53 @@ int harvest_timers(cupk_ctx *ctx, bool all)
     return CUPK_OK;
 }
 
-int upload_forest(cupk_ctx *ctx)
+// Bring the device forest (labels, parents, packed words) up to date on
+// stream st: the pages the host forest wrote since the last upload, through
+// a pinned staging block, when they are fewer than a quarter of all pages;
+// else the whole arrays, copied from the host forest itself (which must then
+// not change until the copy is done).
+int upload_forest_on(cupk_ctx *ctx, hipStream_t st)
 {
     if (!ctx->forest_dev_stale) return CUPK_OK;
-    const size_t bytes = (size_t)ctx->V * sizeof(uint32_t);
-    HIPCHK(hipMemcpyAsync(ctx->d_lbl, ctx->h_lbl, bytes, hipMemcpyHostToDevice, ctx->s));
-    HIPCHK(hipMemcpyAsync(ctx->d_par, ctx->h_par, bytes, hipMemcpyHostToDevice, ctx->s));
-    HIPCHK(launch_pack_forest(ctx->s, ctx->d_lbl, ctx->d_par, ctx->d_lp, ctx->V));
     ctx->forest_dev_stale = false;
+    std::vector<uint32_t> &pg = ctx->up_pages;
+    pg.clear();
+    ctx->forest.take_pages(pg);
+    if (pg.empty()) return CUPK_OK;
+    const uint32_t sh = ctx->forest.page_shift(), pv = 1u << sh;
+    if (pg.size() * 4 >= ctx->forest.n_pages()) {
+        const size_t bytes = (size_t)ctx->V * sizeof(uint32_t);
+        HIPCHK(hipMemcpyAsync(ctx->d_lbl, ctx->h_lbl, bytes, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ctx->d_par, ctx->h_par, bytes, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_pack_forest(st, ctx->d_lbl, ctx->d_par, ctx->d_lp, ctx->V));
+        return CUPK_OK;
+    }
+    // the previous staging block has been copied
+    if (ctx->stage_busy) {
+        HIPCHK(hipEventSynchronize(ctx->ev_stage));
+        ctx->stage_busy = false;
+    }
+    const size_t np = pg.size(), words = np * (1 + 2 * (size_t)pv);
+    HIPCHK(grow(ctx->h_stage, words));
+    HIPCHK(grow(ctx->d_stage, words));
+    uint32_t *h = ctx->h_stage.p;
+    std::copy(pg.begin(), pg.end(), h);
+    uint32_t *hl = h + np, *hp = hl + np * pv;
+    for (size_t i = 0; i < np; i++) {
+        const size_t base = (size_t)pg[i] << sh;
+        const size_t m = base < ctx->V ? std::min<size_t>(pv, ctx->V - base) : 0;
+        std::memcpy(hl + i * pv, ctx->h_lbl + base, m * 4);
+        std::memcpy(hp + i * pv, ctx->h_par + base, m * 4);
+    }
+    HIPCHK(hipMemcpyAsync(ctx->d_stage.p, h, words * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(ctx->ev_stage, st));
+    ctx->stage_busy = true;
+    HIPCHK(launch_forest_pages(st, ctx->d_stage.p, (uint32_t)np, sh, ctx->V, ctx->d_lbl,
+                               ctx->d_par, ctx->d_lp));
     return CUPK_OK;
 }
+
+int upload_forest(cupk_ctx *ctx) { return upload_forest_on(ctx, ctx->s); }
 
 // One replacement-search set: a tree of the forest, reduced either from its
 // vertices or from fragment sketches of the previous round.
@@ -1419,13 +1456,10 @@ static int apply_overlapped(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bo
     // waited for, is published after them)
     const bool up = ctx->forest_dev_stale;
     if (up) {
-        const size_t bytes = (size_t)ctx->V * sizeof(uint32_t);
-        HIPCHK(hipMemcpyAsync(ctx->d_lbl, ctx->h_lbl, bytes, hipMemcpyHostToDevice, ctx->cs));
-        HIPCHK(hipMemcpyAsync(ctx->d_par, ctx->h_par, bytes, hipMemcpyHostToDevice, ctx->cs));
-        HIPCHK(launch_pack_forest(ctx->cs, ctx->d_lbl, ctx->d_par, ctx->d_lp, ctx->V));
+        rc = upload_forest_on(ctx, ctx->cs);
+        if (rc != CUPK_OK) return rc;
         HIPCHK(hipEventRecord(ctx->ev_up, ctx->cs));
         HIPCHK(hipStreamWaitEvent(ctx->s, ctx->ev_up, 0));
-        ctx->forest_dev_stale = false;
     }
     ctx->ctr.updates += n;
     ctx->ctr.batches++;
@@ -1584,6 +1618,8 @@ void destroy(cupk_ctx *ctx)
     release(ctx->d_res);
     release(ctx->h_res);
     release(ctx->d_tmp);
+    release(ctx->h_stage);
+    release(ctx->d_stage);
     for (auto &t : ctx->timers) {
         if (t.t0) (void)hipEventDestroy(t.t0);
         if (t.tb) (void)hipEventDestroy(t.tb);
@@ -1594,6 +1630,7 @@ void destroy(cupk_ctx *ctx)
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->ev_scat) (void)hipEventDestroy(ctx->ev_scat);
     if (ctx->ev_up) (void)hipEventDestroy(ctx->ev_up);
+    if (ctx->ev_stage) (void)hipEventDestroy(ctx->ev_stage);
     if (ctx->cs) (void)hipStreamDestroy(ctx->cs);
     if (ctx->own_stream && ctx->s) (void)hipStreamDestroy(ctx->s);
     delete ctx;
@@ -1694,6 +1731,7 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_scat, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_up, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_stage, hipEventDisableTiming));
     if (ctx->opts.time_kernels)
         for (auto &t : ctx->timers) {
             HIPCHK(hipEventCreate(&t.t0));
@@ -1733,6 +1771,7 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     memset(ctx->h_small, 0, sizeof(SmallResult));
     HIPCHK(hipHostMalloc((void **)&ctx->h_misc, 64, hipHostMallocDefault));
     ctx->forest.init(V, ctx->h_lbl, ctx->h_par);
+    ctx->forest.track_pages(10);  // 4 KiB of labels (and of parents) per page
     if (V >= (1u << 17)) {
         // host forest work of a batch (relabels, member lists) is split
         // over a few threads when trees are large

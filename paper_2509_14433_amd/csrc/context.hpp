@@ -76,6 +76,14 @@ struct cupk_ctx {
     uint64_t *d_lp = nullptr;  // label | parent << 32 per vertex
     uint32_t *h_lbl = nullptr, *h_par = nullptr;
     bool forest_dev_stale = false;
+    // page-wise uploads of the forest: the pages written since the last
+    // upload, their staging block (pinned, then device) and whether its
+    // last copy (ev_stage) may still be in flight
+    std::vector<uint32_t> up_pages;
+    cupk::HostBuf<uint32_t> h_stage;
+    cupk::DevBuf<uint32_t> d_stage;
+    hipEvent_t ev_stage = nullptr;
+    bool stage_busy = false;
 
     // batch buffers
     cupk::DevBuf<uint64_t> d_upd;

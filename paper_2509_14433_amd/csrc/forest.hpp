@@ -125,6 +125,7 @@ class Forest {
         for (size_t qi = 0; qi < queue_.size(); qi++) {
             const uint32_t x = queue_[qi];
             lbl_[x] = lb;
+            touch(x);
             for (uint32_t y = first_kid_[x]; y != kNone; y = next_sib_[y]) queue_.push_back(y);
         }
         // re-root the endpoint with the shorter path to its root (the paths
@@ -157,17 +158,20 @@ class Forest {
         }
         remove_kid(parent, child);
         par_[child] = kNone;
+        touch(child);
         for (uint32_t c = s, below = kNone; c != kNone;) {
             const uint32_t up = par_[c];
             if (up != kNone) remove_kid(up, c);
             if (below != kNone) {
                 par_[c] = below;
+                touch(c);
                 add_kid(below, c);
             }
             below = c;
             c = up;
         }
         par_[s] = t;
+        touch(s);
         add_kid(t, s);
     }
 
@@ -191,6 +195,7 @@ class Forest {
         const uint32_t parent = child == a ? b : a;
         remove_kid(parent, child);
         par_[child] = kNone;
+        touch(child);
         pending_.push_back({lbl_[child], child});
         n_trees_++;
         n_edges_--;
@@ -235,7 +240,10 @@ class Forest {
                     const uint32_t nl = free_.back();
                     free_.pop_back();
                     live_add(nl);
-                    for (uint32_t x : pq_[i]) lbl_[x] = nl;
+                    for (uint32_t x : pq_[i]) {
+                        lbl_[x] = nl;
+                        touch(x);
+                    }
                     size_[nl] = (uint32_t)pq_[i].size();
                     root_[nl] = pq_[i][0];
                     dirty_[nl] = 0;
@@ -275,12 +283,14 @@ class Forest {
             if (up != kNone) remove_kid(up, c);
             if (below != kNone) {
                 par_[c] = below;
+                touch(c);
                 add_kid(below, c);
             }
             below = c;
             c = up;
         }
         par_[x] = y;
+        touch(x);
         add_kid(y, x);
         n_trees_--;
         n_edges_++;
@@ -443,6 +453,7 @@ class Forest {
         for (size_t qi = 0; qi < q.size(); qi++) {
             const uint32_t x = q[qi];
             lbl_[x] = l;
+            touch(x);
             for (uint32_t y = first_kid_[x]; y != kNone; y = next_sib_[y]) q.push_back(y);
         }
     }
@@ -596,7 +607,43 @@ class Forest {
             }
     }
 
+    // ---- pages written since the last take_pages() -----------------------
+    // With tracking on, every label or parent write marks its page of
+    // 2^shift vertices (from the pool's workers too), so that a copy
+    // elsewhere can be refreshed page by page.  Turning it on marks every
+    // page.
+    void track_pages(uint32_t shift)
+    {
+        pshift_ = shift;
+        pages_.assign(((size_t)V_ >> shift) + 1, 1);
+        track_ = true;
+    }
+    uint32_t page_shift() const { return pshift_; }
+    size_t n_pages() const { return pages_.size(); }
+    // Append the marked pages to `out` and clear their marks.
+    void take_pages(std::vector<uint32_t> &out)
+    {
+        for (size_t p = 0; p < pages_.size(); p++)
+            if (pages_[p]) {
+                out.push_back((uint32_t)p);
+                pages_[p] = 0;
+            }
+    }
+
   private:
+    void touch(uint32_t x)
+    {
+        // read first: a page is written many times between two takes, and
+        // stores to the few cache lines of marks from every pool worker
+        // would bounce those lines between cores
+        if (!track_) return;
+        uint8_t *m = &pages_[x >> pshift_];
+        if (!__atomic_load_n(m, __ATOMIC_RELAXED)) __atomic_store_n(m, (uint8_t)1, __ATOMIC_RELAXED);
+    }
+    std::vector<uint8_t> pages_;
+    uint32_t pshift_ = 0;
+    bool track_ = false;
+
     // position of a top-down piece search: queue index, and the next child
     // of that vertex to look at (kNone: start at its first child)
     struct Walk {

@@ -499,6 +499,35 @@ hipError_t launch_pack_forest(hipStream_t s, const uint32_t *lbl, const uint32_t
     return hipGetLastError();
 }
 
+// Page i of the staging block (id stage[i], then 2^pshift labels of each
+// page in turn, then 2^pshift parents of each page in turn) into lbl, par
+// and lp.
+__global__ void k_forest_pages(const uint32_t *__restrict__ stage, uint32_t np, uint32_t pshift,
+                               uint32_t V, uint32_t *__restrict__ lbl, uint32_t *__restrict__ par,
+                               uint64_t *__restrict__ lp)
+{
+    const uint32_t i = blockIdx.x;
+    const uint32_t pv = 1u << pshift;
+    const uint32_t base = stage[i] << pshift;
+    const uint32_t *sl = stage + np + (size_t)i * pv;
+    const uint32_t *sp = stage + np + (size_t)np * pv + (size_t)i * pv;
+    for (uint32_t j = threadIdx.x; j < pv && base + j < V; j += blockDim.x) {
+        const uint32_t w = base + j, l = sl[j], q = sp[j];
+        lbl[w] = l;
+        par[w] = q;
+        lp[w] = (uint64_t)l | (uint64_t)q << 32;
+    }
+}
+
+hipError_t launch_forest_pages(hipStream_t s, const uint32_t *stage, uint32_t np, uint32_t pshift,
+                               uint32_t V, uint32_t *lbl, uint32_t *par, uint64_t *lp)
+{
+    if (np == 0) return hipSuccess;
+    if (pshift > 16 || ((size_t)(V - 1) >> pshift) >= (1u << 31)) return hipErrorInvalidValue;
+    k_forest_pages<<<np, 256, 0, s>>>(stage, np, pshift, V, lbl, par, lp);
+    return hipGetLastError();
+}
+
 hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
                            uint32_t V, const uint64_t *lp, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,

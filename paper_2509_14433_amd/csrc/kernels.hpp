@@ -126,6 +126,11 @@ uint32_t classify_blocks(uint32_t n);
 // one 8-byte load per endpoint gives its label and its parent).
 hipError_t launch_pack_forest(hipStream_t s, const uint32_t *lbl, const uint32_t *par, uint64_t *lp,
                               uint32_t V);
+// Refresh np pages of 2^pshift vertices of the device forest from a staging
+// block: np page ids, then each page's labels in turn, then each page's
+// parents in turn (2^pshift words per page; entries past V are ignored).
+hipError_t launch_forest_pages(hipStream_t s, const uint32_t *stage, uint32_t np, uint32_t pshift,
+                               uint32_t V, uint32_t *lbl, uint32_t *par, uint64_t *lp);
 // Second half of a classification launched with fi.tiles_only = 1: keep,
 // in each classify block's region of fi.fupd (in place, stream order kept),
 // only the updates the classify kernel's rule flags against the forest in

@@ -1,7 +1,8 @@
 // Randomized check of the contracted walk (paper_2509_14433_amd/csrc/
 // contract.hpp) against the one-by-one walk of the same runs of updates on
 // a copy of the same forest: forest edges, trees, dirty trees and the counts
-// of links and cuts must agree after every run.  Runs toggle a small pool of
+// of links and cuts must agree after every run, and every label or parent
+// written must lie in a page the forest marked.  Runs toggle a small pool of
 // edges between trees many times (links and cuts undone within the run),
 // delete forest edges and insert random pairs; some runs get a piece-search
 // budget too small to finish, so the fallback is exercised as well.  Built
@@ -51,6 +52,23 @@ static int fail(const char *what, uint64_t run)
 {
     fprintf(stderr, "FAIL %s after run %llu\n", what, (unsigned long long)run);
     return 1;
+}
+
+// Every vertex whose label or parent changed since the last call lies in a
+// page the forest marked; then the marks are cleared and the copies
+// refreshed.
+static bool pages_cover(Forest &F, const std::vector<uint32_t> &l, const std::vector<uint32_t> &p,
+                        std::vector<uint32_t> &lc, std::vector<uint32_t> &pc)
+{
+    std::vector<uint32_t> pg;
+    F.take_pages(pg);
+    std::vector<uint8_t> mark(F.n_pages(), 0);
+    for (uint32_t x : pg) mark[x] = 1;
+    for (size_t w = 0; w < l.size(); w++)
+        if ((l[w] != lc[w] || p[w] != pc[w]) && !mark[w >> F.page_shift()]) return false;
+    lc = l;
+    pc = p;
+    return true;
 }
 
 static std::vector<uint32_t> canon(const Forest &F)
@@ -126,6 +144,14 @@ int main(int argc, char **argv)
     Forest A, B;
     A.init(V, la.data(), pa.data());
     B.init(V, lb.data(), pb.data());
+    // pages of 4 vertices: every write must mark its page
+    A.track_pages(2);
+    B.track_pages(2);
+    std::vector<uint32_t> lac(V, ~0u), pac(V, ~0u), lbc(V, ~0u), pbc(V, ~0u);
+    auto pages_ok = [&]() {
+        return pages_cover(A, la, pa, lac, pac) && pages_cover(B, lb, pb, lbc, pbc);
+    };
+    if (!pages_ok()) return fail("page marks after init", 0);
     std::unique_ptr<cupk::Pool> workers;
     if (threads) {
         workers.reset(new cupk::Pool(threads));
@@ -161,6 +187,7 @@ int main(int argc, char **argv)
             }
         if (B.link_many(cand, got) != nw) return fail("link_many: start forest", 0);
         if (compare(A, B, 0)) return 1;
+        if (!pages_ok()) return fail("page marks: start forest", 0);
     }
     uint64_t fallbacks = 0, contracted = 0;
     for (uint64_t r = 0; r < runs; r++) {
@@ -199,6 +226,7 @@ int main(int argc, char **argv)
                 if (want[i]) G.insert({std::min(cand[i].first, cand[i].second),
                                        std::max(cand[i].first, cand[i].second)});
             if (compare(A, B, r)) return 1;
+            if (!pages_ok()) return fail("page marks: link_many", r);
             many_runs++;
             continue;
         }
@@ -264,6 +292,7 @@ int main(int argc, char **argv)
         }
         if (l0 != l1 || c0 != c1) return fail("link / cut counts", r);
         if (compare(A, B, r)) return 1;
+        if (!pages_ok()) return fail("page marks", r);
     }
     printf("ok V=%u runs=%llu contracted=%llu fallbacks=%llu link lists=%llu\n", V,
            (unsigned long long)runs, (unsigned long long)contracted,
