@@ -114,7 +114,8 @@ def run_path(cupk, torch, packed, sizes, steps, warmup, mode, time_kernels=TIME_
         t.apply_updates_device(packed[offs[0]:offs[1]])
         res = t.autotune(packed[offs[1]:offs[2]].contiguous())
         t.close()
-        geo = {k: res[k] for k in ("tile_vertices", "lds_rows", "chunk_records", "tile_layout")}
+        geo = {k: res[k] for k in ("tile_vertices", "lds_rows", "chunk_records", "tile_layout",
+                                   "coarse_tiles")}
 
     def new_ctx():
         return cupk.Context(V, C, D, SEED, scatter_mode=mode, max_batch=BATCH,
@@ -626,7 +627,8 @@ def run_clusters(cupk, torch, phases, cfg, steps, warmup, batch, mode, tune,
     tuned = {}
     geo = {}
     if geometry:
-        geo = dict(zip(("tile_vertices", "lds_rows", "chunk_records", "tile_layout"), geometry))
+        geo = dict(zip(("tile_vertices", "lds_rows", "chunk_records", "tile_layout",
+                        "coarse_tiles"), geometry))
         tune = False
 
     def new_ctx(bsz, timed=False):
@@ -653,7 +655,8 @@ def run_clusters(cupk, torch, phases, cfg, steps, warmup, batch, mode, tune,
             sample = phases[1][start:start + min(tune_sample, phases[1].shape[0] - start)]
             tuned = w.autotune(sample.contiguous())
             geo = {"tile_vertices": tuned["tile_vertices"], "lds_rows": tuned["lds_rows"],
-                   "chunk_records": tuned["chunk_records"], "tile_layout": tuned["tile_layout"]}
+                   "chunk_records": tuned["chunk_records"], "tile_layout": tuned["tile_layout"],
+                   "coarse_tiles": tuned["coarse_tiles"]}
             if not keep_batch:
                 batch = tuned["batch_target"]
             print(f"bench: {label} tuned {geo} batch {batch} (host "
@@ -942,10 +945,11 @@ def clusters_main(args, cupk, np, torch, streamgen):
     }
     if geometry:
         out["config"]["geometry"] = dict(zip(("tile_vertices", "lds_rows", "chunk_records",
-                                              "tile_layout"), geometry))
+                                              "tile_layout", "coarse_tiles"), geometry))
     if tuned:
         out["config"]["tuned"] = {k: tuned[k] for k in ("tile_layout", "tile_vertices", "lds_rows",
-                                                        "chunk_records", "batch_target",
+                                                        "chunk_records", "coarse_tiles",
+                                                        "batch_target",
                                                         "host_ms_per_batch", "batch_sizes",
                                                         "batch_ms")}
     if not args.no_plain and args.mode == "staged":
@@ -960,7 +964,8 @@ def clusters_main(args, cupk, np, torch, streamgen):
         scomp = (8 * sctr["timed_updates"] + 32 * sctr["timed_buckets"]) / sl
         out["staged_1M"] = {"value": round(stot / sdt, 1), "unit": "updates/s", "steps": psteps,
                             "geometry": ({k: stuned[k] for k in ("tile_layout", "tile_vertices",
-                                                                 "lds_rows", "chunk_records")}
+                                                                 "lds_rows", "chunk_records",
+                                                                 "coarse_tiles")}
                                          if stuned else None),
                             "ms_per_step": round(sdt * 1e3 / psteps, 3), "batch": BATCH4,
                             "kernel_avg_ms": round(savg, 5),
@@ -1015,7 +1020,8 @@ def main():
                     help="headline: updates in the autotuner's sample (the largest batch it "
                          "can choose), taken from churn round 0 after 8M updates of history")
     ap.add_argument("--geometry", default="",
-                    help="headline: TILE_VERTICES,LDS_ROWS,CHUNK_RECORDS[,LAYOUT] instead of "
+                    help="headline: TILE_VERTICES,LDS_ROWS,CHUNK_RECORDS[,LAYOUT[,COARSE_TILES]] "
+                         "instead of "
                          "the autotuner's (with --batch, a fixed launch configuration for "
                          "profiling; LAYOUT 1 = record, 2 = pair)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

@@ -186,6 +186,12 @@ typedef struct {
      * (their pieces share a label until the rounds split them) has its
      * rounds run first. */
     uint32_t serial_rounds;
+    /* Tiles per coarse bin of the two-level binning the staged scatter uses
+     * beyond 2048 tiles (a power of two in [2, 8192], at most 8192 coarse
+     * bins; 0 = default: about sqrt(2 * tiles) coarse bins, which suits
+     * records spread over all tiles).  The autotuner tries smaller ones,
+     * which suit records that fall on few tiles. */
+    uint32_t coarse_tiles;
 } cupk_opts;
 
 /* Counters, cumulative since init. */
@@ -444,6 +450,7 @@ typedef struct {
     uint32_t batch_sizes[8];
     double host_ms_per_batch;  /* host time per batch the schedule assumed     */
     uint32_t tile_layout;      /* chosen CUPK_LAYOUT_*                         */
+    uint32_t coarse_tiles;     /* chosen tiles per coarse bin (0: one level)   */
 } cupk_tune_result;
 
 int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_result *out);

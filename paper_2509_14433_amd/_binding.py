@@ -60,6 +60,7 @@ class cupk_opts(ctypes.Structure):
         ("fill_reserve", ctypes.c_uint32),
         ("tile_layout", ctypes.c_uint32),
         ("serial_rounds", ctypes.c_uint32),
+        ("coarse_tiles", ctypes.c_uint32),
     ]
 
 
@@ -99,7 +100,7 @@ class cupk_tune_result(ctypes.Structure):
                 ("best_ms", ctypes.c_double), ("before_ms", ctypes.c_double),
                 ("batch_target", ctypes.c_uint32), ("batch_ms", ctypes.c_double * 8),
                 ("batch_sizes", ctypes.c_uint32 * 8), ("host_ms_per_batch", ctypes.c_double),
-                ("tile_layout", ctypes.c_uint32)]
+                ("tile_layout", ctypes.c_uint32), ("coarse_tiles", ctypes.c_uint32)]
 
 
 class cupk_static_info(ctypes.Structure):
@@ -188,7 +189,7 @@ class Context:
                  stream=None, use_torch_memory=True, time_kernels=False, tile_vertices=0,
                  lds_rows=0, chunk_records=0, tile_grid=0, use_graph=False, exact=False,
                  levels=False, walk_plain=False, split_rounds=False, fill_reserve=False,
-                 tile_layout=0, serial_rounds=False):
+                 tile_layout=0, serial_rounds=False, coarse_tiles=0):
         self._h = None
         self._sk_tensor = None
         self._keep = {}
@@ -209,6 +210,7 @@ class Context:
         opts.fill_reserve = 1 if fill_reserve else 0
         opts.tile_layout = tile_layout
         opts.serial_rounds = 1 if serial_rounds else 0
+        opts.coarse_tiles = coarse_tiles
         torch = _torch()
         if stream is None and torch is not None and torch.cuda.is_available():
             # launch on torch's current stream so that torch-produced device

@@ -1637,8 +1637,10 @@ void destroy(cupk_ctx *ctx)
 }
 
 // Staged-scatter geometry: tv vertices per tile (power of two), `rows` depth
-// rows in LDS, `chunk` records per work item.
-int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk, uint32_t layout)
+// rows in LDS, `chunk` records per work item; `coarse` tiles per coarse bin
+// of the two-level binning (a power of two; 0: the default).
+int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk, uint32_t layout,
+                 uint32_t coarse)
 {
     if (layout != CUPK_LAYOUT_RECORD && layout != CUPK_LAYOUT_PAIR)
         return ctx->invalid("tile_layout must be CUPK_LAYOUT_RECORD or CUPK_LAYOUT_PAIR");
@@ -1659,16 +1661,29 @@ int set_geometry(cupk_ctx *ctx, uint32_t tv, uint32_t rows, uint32_t chunk, uint
     // two-level binning beyond kFillStageTiles tiles.  Both fills write runs
     // of records per (block, bin): about 8192 / ncoarse records per coarse
     // bin in the first, about 4096 / (tiles per coarse bin) per tile in the
-    // second; the coarse count is the power of two nearest sqrt(2 * ntiles),
-    // which evens out the two, within [64, 2048]
+    // second; by default the coarse count is the power of two nearest
+    // sqrt(2 * ntiles), which evens out the two when records fall on every
+    // tile, within [64, 2048].  When they fall on a few tiles only (dense
+    // clusters), smaller coarse bins keep the second fill's runs long, and
+    // the autotuner tries them.
     ctx->fshift = 0;
     ctx->ncoarse = 0;
+    if (coarse && (coarse < 2 || coarse > kFineLdsTiles || (coarse & (coarse - 1))))
+        return ctx->invalid("coarse_tiles must be a power of two in [2, 8192]");
     if (ctx->opts.scatter_mode == CUPK_SCATTER_STAGED && ctx->ntiles > kFillStageTiles) {
-        uint32_t target = 64;
-        while (target < 2048 && (uint64_t)(2 * target) * (2 * target) <= 2 * (uint64_t)ctx->ntiles)
-            target *= 2;
         uint32_t f = 1;
-        while ((((uint64_t)ctx->ntiles + (1u << f) - 1) >> f) > target) f++;
+        if (coarse) {
+            while ((1u << f) < coarse) f++;
+            // the classify kernel counts coarse bins in LDS: at most 8192
+            if ((((uint64_t)ctx->ntiles + (1u << f) - 1) >> f) > kLdsHistMax)
+                return ctx->invalid("coarse_tiles too small: more than 8192 coarse bins");
+        } else {
+            uint32_t target = 64;
+            while (target < 2048 &&
+                   (uint64_t)(2 * target) * (2 * target) <= 2 * (uint64_t)ctx->ntiles)
+                target *= 2;
+            while ((((uint64_t)ctx->ntiles + (1u << f) - 1) >> f) > target) f++;
+        }
         ctx->fshift = f;
         ctx->ncoarse = (uint32_t)(((uint64_t)ctx->V + (1ull << (sh + f)) - 1) >> (sh + f));
         const size_t nc = (size_t)kCntGroups * ctx->ncoarse + 1;
@@ -1801,7 +1816,7 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     if (layout == 0)
         layout = ctx->opts.max_batch >= (4u << 20) ? CUPK_LAYOUT_PAIR : CUPK_LAYOUT_RECORD;
     int rc0 = set_geometry(ctx, tv, rows, ctx->opts.chunk_records ? ctx->opts.chunk_records : 4096,
-                           layout);
+                           layout, ctx->opts.coarse_tiles);
     if (rc0 != CUPK_OK) return rc0;
     const size_t mb = ctx->opts.max_batch ? ctx->opts.max_batch : (1u << 20);
     int rc = ensure_batch_buffers(ctx, mb);
@@ -2390,6 +2405,7 @@ int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_r
         HIPCHK(hipEventCreate(&e1));
         const uint32_t tv0 = 1u << ctx->tile_shift, rows0 = ctx->rows, chunk0 = ctx->chunk;
         const uint32_t lay0 = ctx->layout;
+        const uint32_t co0 = ctx->fshift ? 1u << ctx->fshift : 0u;
         const uint32_t m = (uint32_t)n;
         double before = 0;
         rc = time_scatter(ctx, d_sample, m, 1, e0, e1, &before);  // also warms up
@@ -2410,8 +2426,9 @@ int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_r
                                                                      ? kLayoutPair
                                                                      : kLayoutRecord))
                             continue;
-                        if (tv == tv0 && rows == rows0 && ch == chunk0 && lay == lay0) continue;
-                        rc = set_geometry(ctx, tv, rows, ch, lay);
+                        if (tv == tv0 && rows == rows0 && ch == chunk0 && lay == lay0 && !co0)
+                            continue;
+                        rc = set_geometry(ctx, tv, rows, ch, lay, 0);
                         if (rc != CUPK_OK) break;
                         double ms = 0;
                         rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &ms);
@@ -2427,7 +2444,39 @@ int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_r
                             blay = lay;
                         }
                     }
-        if (rc == CUPK_OK) rc = set_geometry(ctx, btv, brows, bchunk, blay);
+        if (rc == CUPK_OK) rc = set_geometry(ctx, btv, brows, bchunk, blay, 0);
+        // two-level binning: coarse bins from the default size down to 1/32
+        // of it, and twice it (where the records fall on a few tiles, smaller
+        // coarse bins keep the second fill's runs long)
+        uint32_t bco = 0;
+        if (rc == CUPK_OK && ctx->fshift) {
+            const uint32_t f0 = ctx->fshift;
+            double best_co = 0;
+            rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &best_co);
+            best = std::min(best, best_co);
+            bco = 1u << f0;
+            for (uint32_t f = f0 + 1; rc == CUPK_OK && f + 5 >= f0 && f >= 1; f--) {
+                if (f == f0) continue;
+                const uint32_t co = 1u << f;
+                if (co > kFineLdsTiles ||
+                    (((uint64_t)ctx->ntiles + co - 1) >> f) > kLdsHistMax)
+                    continue;
+                rc = set_geometry(ctx, btv, brows, bchunk, blay, co);
+                if (rc != CUPK_OK) break;
+                double ms = 0;
+                rc = time_scatter(ctx, d_sample, m, 2, e0, e1, &ms);
+                tried++;
+                if (ctx->trace)
+                    fprintf(stderr, "cupk tune coarse_tiles=%u %.4f ms\n", co, ms);
+                if (rc == CUPK_OK && ms < best_co) {
+                    best_co = ms;
+                    bco = co;
+                }
+                if (f == 1) break;
+            }
+            best = std::min(best, best_co);
+            if (rc == CUPK_OK) rc = set_geometry(ctx, btv, brows, bchunk, blay, bco);
+        }
         // batch-size schedule: device time of prefixes n/128 .. n, plus the
         // host time per batch (flag walk and replacement rounds, which cost
         // about the same whatever the batch size) measured on this
@@ -2460,13 +2509,14 @@ int cupk_autotune(cupk_ctx *ctx, const uint64_t *d_sample, size_t n, cupk_tune_r
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc != CUPK_OK) {
-            (void)set_geometry(ctx, tv0, rows0, chunk0, lay0);
+            (void)set_geometry(ctx, tv0, rows0, chunk0, lay0, co0);
             return rc;
         }
         out->tile_layout = blay;
         out->tile_vertices = btv;
         out->lds_rows = brows;
         out->chunk_records = bchunk;
+        out->coarse_tiles = bco;
         out->candidates = tried;
         out->best_ms = best;
         out->before_ms = before;

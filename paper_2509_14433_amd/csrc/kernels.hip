@@ -93,7 +93,6 @@ constexpr uint32_t kClsThreads = 512;  // 8 updates per thread: 16 label loads i
 constexpr uint32_t kClsPerBlock = 4096;
 constexpr uint32_t kClsPerThread = kClsPerBlock / kClsThreads;
 constexpr uint32_t kClsWaves = kClsThreads / 64;
-constexpr uint32_t kLdsHistMax = 8192;
 static_assert(kClsPerThread * kClsWaves == 64, "one wave scans the (step, wave) counts");
 
 constexpr uint32_t kScanThreads = 1024;
@@ -948,7 +947,6 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill_staged(
 constexpr uint32_t kFineThreads = 1024;
 constexpr uint32_t kFinePer = 8;
 constexpr uint32_t kFinePerBlock = kFineThreads * kFinePer;
-constexpr uint32_t kFineLdsTiles = 8192;
 
 DEVI uint32_t rec_endpoint(uint64_t rec)
 {

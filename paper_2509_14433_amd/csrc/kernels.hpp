@@ -200,6 +200,10 @@ hipError_t launch_tile(hipStream_t s, DevSketch sk, uint32_t *hdr, const StagedP
 // tile scan into sa (one count copy, sa.sums set) and writes them into
 // their tile bins in `bins`.
 constexpr uint32_t kFillStageTiles = 2048;
+// Most bins the classify kernel counts in LDS (beyond, with device atomics),
+// and most tiles per coarse bin (launch_fine).
+constexpr uint32_t kLdsHistMax = 8192;
+constexpr uint32_t kFineLdsTiles = 8192;
 hipError_t launch_fine(hipStream_t s, uint32_t grid_n, const uint32_t *hdr, const uint64_t *bins1,
                        const uint32_t *total, uint32_t tile_shift, uint32_t fshift,
                        uint32_t ntiles, uint32_t *tile_cnt, const ScanArgs &sa, uint64_t *bins);

@@ -108,10 +108,10 @@ def test_clusters_full_size_in_the_benchmark_configuration(env):
     batch = tuned["batch_target"]
     print(f"clusters: tuned layout {tuned['tile_layout']} {tuned['tile_vertices']} "
           f"{tuned['lds_rows']} "
-          f"{tuned['chunk_records']} batch {batch}", flush=True)
+          f"{tuned['chunk_records']} coarse {tuned['coarse_tiles']} batch {batch}", flush=True)
     ctx = cupk.Context(V, C, D, S, max_batch=batch, tile_vertices=tuned["tile_vertices"],
                        lds_rows=tuned["lds_rows"], chunk_records=tuned["chunk_records"],
-                       tile_layout=tuned["tile_layout"])
+                       tile_layout=tuned["tile_layout"], coarse_tiles=tuned["coarse_tiles"])
     for k, ph in enumerate(phases):
         apply(ctx, ph, batch)
         ctx.sync()

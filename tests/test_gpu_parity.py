@@ -464,6 +464,18 @@ def _forest_cut_batches(rng, V, eu, ev, fr, nb, n_forest, n_other, n_new):
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("V,tv", [(9000, 1), (140_000, 16)])
 def test_many_tiles_parity(cupk, mode, V, tv):
+    _many_tiles(cupk, mode, V, tv, 0)
+
+
+# The same with coarse bins of a given size (cupk_opts.coarse_tiles): 2 tiles
+# (4500 coarse bins: the coarse fill takes the per-record path) and 8 tiles
+# (1094 coarse bins: staged coarse fill, long fine runs).
+@pytest.mark.parametrize("V,tv,coarse", [(9000, 1, 2), (140_000, 16, 8)])
+def test_many_tiles_coarse_bins_parity(cupk, V, tv, coarse):
+    _many_tiles(cupk, "pair", V, tv, coarse)
+
+
+def _many_tiles(cupk, mode, V, tv, coarse):
     C = max(1, math.ceil(math.log2(V)))
     D = 2 * C
     S = 0x5EED8192 + V
@@ -475,20 +487,22 @@ def test_many_tiles_parity(cupk, mode, V, tv):
     key = np.unique(np.minimum(a, b)[keep].astype(np.int64) * V + np.maximum(a, b)[keep])[:m]
     rng.shuffle(key)
     eu, ev = (key // V).astype(np.uint32), (key % V).astype(np.uint32)
-    ctx = cupk.Context(V, C, D, S, **_mkw(cupk, mode), tile_vertices=tv)
+    ctx = cupk.Context(V, C, D, S, **_mkw(cupk, mode), tile_vertices=tv, coarse_tiles=coarse)
     ref = oracle.Sketch(V, C, D, S)
     fr = oracle.ForestReplay(ref)
     bs = 5000 if V < 20000 else 60000
     for s in range(0, m, bs):
         e = min(m, s + bs)
-        print(f"many tiles V={V} tv={tv} mode={mode} insert batch {s}:{e}", flush=True)
+        print(f"many tiles V={V} tv={tv} coarse={coarse} mode={mode} insert batch {s}:{e}",
+              flush=True)
         z = np.zeros(e - s, np.uint8)
         ctx.apply_updates(eu[s:e], ev[s:e], z)
         fr.apply_batch(eu[s:e], ev[s:e], z)
     assert ctx.digest() == ref.digest()
     nfor = 25 if V < 20000 else 30
     for k, (u, v, d) in enumerate(_forest_cut_batches(rng, V, eu, ev, fr, 3, nfor, 3000, 3000)):
-        print(f"many tiles V={V} tv={tv} mode={mode} cut batch {k} n={len(u)}", flush=True)
+        print(f"many tiles V={V} tv={tv} coarse={coarse} mode={mode} cut batch {k} n={len(u)}",
+              flush=True)
         ctx.apply_updates(u, v, d)
         fr.apply_batch(u, v, d)
         assert ctx.digest() == ref.digest()
@@ -592,3 +606,12 @@ def test_mass_forest_deletion_batch(cupk, mode):
     truth = oracle.components_truth(V, fu, fv)
     assert ctx.num_components() == len(set(truth.tolist()))
     ctx.close()
+
+
+@pytest.mark.parametrize("coarse", [1, 3, 16384])
+def test_coarse_tiles_rejected(cupk, coarse):
+    # not a power of two in [2, 8192]: the context is not created
+    with pytest.raises(cupk.CupkError) as ei:
+        cupk.Context(9000, 14, 28, 1, scatter_mode=cupk.SCATTER_STAGED, tile_vertices=1,
+                     coarse_tiles=coarse)
+    assert ei.value.code == cupk.EINVAL
