@@ -1096,6 +1096,8 @@ static int enqueue_split_front(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
     if (rc != CUPK_OK) return rc;
     rc = enqueue_classify(ctx, ctx->s, n, true);
     if (rc != CUPK_OK) return rc;
+    // the last reader of the uploaded forest until the back half
+    HIPCHK(hipEventRecord(ctx->ev_cls, ctx->s));
     if (ts) HIPCHK(hipEventRecord(ts->t0, ctx->s));
     rc = enqueue_bin(ctx, ctx->s, n);
     if (rc != CUPK_OK) return rc;
@@ -1106,17 +1108,28 @@ static int enqueue_split_front(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n)
 
 static int enqueue_split_back(cupk_ctx *ctx, uint32_t n)
 {
-    int rc = upload_forest(ctx);
-    if (rc != CUPK_OK) return rc;
+    // the forest as the rounds left it, uploaded on the copy stream (idle
+    // now) once the classification has read the previous upload, so that it
+    // overlaps the binning still running on the main stream
+    const bool changed = ctx->forest_dev_stale;
+    if (changed) {
+        HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->ev_cls, 0));
+        const int rc = upload_forest_on(ctx, ctx->cs);
+        if (rc != CUPK_OK) return rc;
+        HIPCHK(hipEventRecord(ctx->ev_up, ctx->cs));
+        HIPCHK(hipStreamWaitEvent(ctx->s, ctx->ev_up, 0));
+    }
     // the flags are packed on this stream before the header: packed by the
-    // walk on the copy stream, they would wait for the scatter's blocks
+    // walk on the copy stream, they would wait for the scatter's blocks.
+    // When the rounds changed nothing, the forest the batch was classified
+    // against is the one after the rounds: no check.
     HIPCHK(launch_reflag(ctx->s, ctx->V, ctx->d_lp, ctx->d_hdr, ctx->d_fupd.p, ctx->h_hdr,
-                         flag_inline(ctx, n), ctx->d_foff.p, ctx->d_oupd.p));
+                         flag_inline(ctx, n), ctx->d_foff.p, ctx->d_oupd.p, changed));
     ctx->flags_packed = true;
     cupk_ctx::TimerSlot *ts = ctx->split_ts;
     ctx->split_ts = nullptr;
     if (ts) HIPCHK(hipEventRecord(ts->tc, ctx->s));
-    rc = enqueue_tile(ctx, ctx->s, n, ts != nullptr);
+    const int rc = enqueue_tile(ctx, ctx->s, n, ts != nullptr);
     if (rc != CUPK_OK) return rc;
     ctx->hdr_seq++;
     ctx->hdr_word = &ctx->h_hdr[HDR_SEQ];
@@ -1630,6 +1643,7 @@ void destroy(cupk_ctx *ctx)
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->ev_scat) (void)hipEventDestroy(ctx->ev_scat);
     if (ctx->ev_up) (void)hipEventDestroy(ctx->ev_up);
+    if (ctx->ev_cls) (void)hipEventDestroy(ctx->ev_cls);
     if (ctx->ev_stage) (void)hipEventDestroy(ctx->ev_stage);
     if (ctx->cs) (void)hipStreamDestroy(ctx->cs);
     if (ctx->own_stream && ctx->s) (void)hipStreamDestroy(ctx->s);
@@ -1746,6 +1760,7 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_scat, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_up, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_cls, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_stage, hipEventDisableTiming));
     if (ctx->opts.time_kernels)
         for (auto &t : ctx->timers) {

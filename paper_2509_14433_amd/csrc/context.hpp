@@ -135,6 +135,7 @@ struct cupk_ctx {
     // the rounds use (s otherwise)
     hipStream_t rstream = nullptr;
     hipEvent_t ev_scat = nullptr, ev_up = nullptr;
+    hipEvent_t ev_cls = nullptr;  // after the split pass's classification
     TimerSlot *split_ts = nullptr;  // timer of the split pass in flight
     bool scat_marked = false;       // ev_scat follows the pending batch's scatter
     bool flags_packed = false;      // the last pass packed its flag list on the device

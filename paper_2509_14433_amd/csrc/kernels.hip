@@ -1534,16 +1534,19 @@ __global__ __launch_bounds__(kReflagThreads) void k_reflag(uint32_t V, const uin
 
 hipError_t launch_reflag(hipStream_t s, uint32_t V, const uint64_t *lp, uint32_t *hdr,
                          uint64_t *fupd, uint32_t *hout, const FlagInline &fi, uint32_t *foff,
-                         uint64_t *oupd)
+                         uint64_t *oupd, bool check)
 {
     if (!fi.fdel || !fi.fcnt || fi.fupd != fupd || fi.tiles_only || !foff || !oupd)
         return hipErrorInvalidValue;
     if (fi.nb) {
-        const uint32_t per = kReflagThreads / 64;
-        k_reflag<<<(fi.nb + per - 1) / per, kReflagThreads, 0, s>>>(
-            V, lp, hdr, fupd, const_cast<uint32_t *>(fi.fcnt), fi.fdel, fi.nb);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        hipError_t e = hipSuccess;
+        if (check) {
+            const uint32_t per = kReflagThreads / 64;
+            k_reflag<<<(fi.nb + per - 1) / per, kReflagThreads, 0, s>>>(
+                V, lp, hdr, fupd, const_cast<uint32_t *>(fi.fcnt), fi.fdel, fi.nb);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
         // the ordered list, before the header: the host only copies it
         k_flag_scan<<<1, kScanThreads, 0, s>>>(fi.fcnt, fi.nb, foff);
         e = hipGetLastError();

@@ -131,19 +131,19 @@ hipError_t launch_pack_forest(hipStream_t s, const uint32_t *lbl, const uint32_t
 // parents in turn (2^pshift words per page; entries past V are ignored).
 hipError_t launch_forest_pages(hipStream_t s, const uint32_t *stage, uint32_t np, uint32_t pshift,
                                uint32_t V, uint32_t *lbl, uint32_t *par, uint64_t *lp);
-// Second half of a classification launched with fi.tiles_only = 1: keep,
-// in each classify block's region of fi.fupd (in place, stream order kept),
-// only the updates the classify kernel's rule flags against the forest in
-// `lp`, and rewrite fi.fcnt and fi.fdel; pack the regions into one ordered
-// list at oupd (foff: fi.nb words of scratch), as launch_flag_compact does;
-// then publish the flag counts, the short flag lists and the header as
-// launch_classify does otherwise.  Exact when `lp` is a coarsening of the
-// forest the regions were flagged against that keeps all its edges (it then
-// flags a subset of what that forest flagged).  A rejected batch (header
-// error) keeps its regions.
+// Second half of a classification launched with fi.tiles_only = 1: with
+// `check`, keep, in each classify block's region of fi.fupd (in place,
+// stream order kept), only the updates the classify kernel's rule flags
+// against the forest in `lp`, and rewrite fi.fcnt and fi.fdel; pack the
+// regions into one ordered list at oupd (foff: fi.nb words of scratch), as
+// launch_flag_compact does; then publish the flag counts, the short flag
+// lists and the header as launch_classify does otherwise.  Exact when `lp`
+// is a coarsening of the forest the regions were flagged against that keeps
+// all its edges (it then flags a subset of what that forest flagged).  A
+// rejected batch (header error) keeps its regions.
 hipError_t launch_reflag(hipStream_t s, uint32_t V, const uint64_t *lp, uint32_t *hdr,
                          uint64_t *fupd, uint32_t *hout, const FlagInline &fi, uint32_t *foff,
-                         uint64_t *oupd);
+                         uint64_t *oupd, bool check);
 
 // Pack the per-block flag regions into one list in stream order (foff:
 // classify_blocks(n) words of scratch); positions too when fpos and opos
