@@ -183,8 +183,9 @@ typedef struct {
      * rounds; they are checked again against that forest before the scatter,
      * which leaves exactly the flags, forest and sketch of the serial
      * order.  A walk that ends with cuts whose trees are not split yet
-     * (their pieces share a label until the rounds split them) has its
-     * rounds run first. */
+     * (their pieces share a label until the rounds split them), or that
+     * leaves fewer than two dirty trees (nothing for the rounds to search),
+     * has its rounds run first. */
     uint32_t serial_rounds;
     /* Tiles per coarse bin of the two-level binning the staged scatter uses
      * beyond 2048 tiles (a power of two in [2, 8192], at most 8192 coarse

@@ -1437,8 +1437,11 @@ static int apply_flushed(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool 
 // latter in the back half leaves exactly the serial order's flags.  This
 // needs exact labels after the walk: when it ends with removals whose trees
 // are not split yet (their pieces still share a label until the rounds
-// split them), k's rounds run first and k+1 takes the serial order.  An
-// error of k's rounds is this call's, and k+1 is then still applied.
+// split them), k's rounds run first and k+1 takes the serial order.  So it
+// does when the walk leaves fewer than two dirty trees: the rounds then
+// have nothing to search, and the split pass's extra launches and stream
+// waits would only cost time.  An error of k's rounds is this call's, and
+// k+1 is then still applied.
 static int apply_overlapped(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool defer)
 {
     ctx->pending = false;
@@ -1450,7 +1453,7 @@ static int apply_overlapped(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bo
     int rc = walk_pass(ctx, nk, false, nullptr, nullptr, nullptr, &nflag, &tw, &tc);
     if (rc != CUPK_OK) return rc;
     const double t1 = now_ms();
-    if (ctx->forest.has_pending()) {
+    if (ctx->forest.has_pending() || ctx->forest.dirty_labels().size() < 2) {
         ctx->scat_marked = false;
         const int rr = run_rounds(ctx);
         const double t3 = now_ms();
