@@ -352,8 +352,11 @@ def workload_leg(args, cupk, torch, np, streamgen):
                                                              walk_plain=True), True))
         for label, kw, tune in legs:
             print(f"bench: {name} {label}", file=sys.stderr, flush=True)
+            # kernel timers on every TIME_EVERY-th launch, as in the main
+            # path: an event between two kernels idles the GPU for a few
+            # microseconds, much of a 1M-update pass
             dt, ctr, tr = _time_batches(cupk, torch, dict(kw, max_batch=max(sizes),
-                                                          time_kernels=True),
+                                                          time_kernels=TIME_EVERY),
                                         packed, sizes, Vw, Cw, Dw, cfg["S"],
                                         sample if tune else None)
             res[label] = {"value": round(n / dt, 1), "seconds": round(dt, 4),
@@ -369,8 +372,9 @@ def workload_leg(args, cupk, torch, np, streamgen):
                           # analogue of the paper's isolated updates)
                           "structural_rate": round((ctr["links"] + ctr["cuts"]) / n, 7)}
             if tr:
-                res[label]["tune"] = {k: tr[k] for k in ("tile_vertices", "lds_rows",
-                                                         "chunk_records", "batch_target")}
+                res[label]["tune"] = {k: tr[k] for k in ("tile_layout", "tile_vertices",
+                                                         "lds_rows", "chunk_records",
+                                                         "coarse_tiles", "batch_target")}
         out.update({"workload": cfg["name"], "updates": n, "batches": len(sizes), "V": Vw,
                     "C": Cw, "D": Dw, "results": res})
     elif name == "levels":
