@@ -185,7 +185,7 @@ typedef struct {
      * order.  A walk that ends with cuts whose trees are not split yet
      * (their pieces share a label until the rounds split them), or that
      * leaves fewer than two dirty trees (nothing for the rounds to search),
-     * has its rounds run first. */
+     * has its rounds run first, and so do batches below overlap_min_batch. */
     uint32_t serial_rounds;
     /* Tiles per coarse bin of the two-level binning the staged scatter uses
      * beyond 2048 tiles (a power of two in [2, 8192], at most 8192 coarse
@@ -193,6 +193,13 @@ typedef struct {
      * records spread over all tiles).  The autotuner tries smaller ones,
      * which suit records that fall on few tiles. */
     uint32_t coarse_tiles;
+    /* Smallest batch (updates) that may be classified and binned while the
+     * previous batch's replacement rounds run (serial_rounds above); 0 =
+     * default 4,194,304.  Below it the host work of a batch outlasts its
+     * device work, so the GPU idles during the rounds anyway, and running
+     * the rounds' reductions beside the next batch's kernels would only
+     * lengthen them. */
+    uint32_t overlap_min_batch;
 } cupk_opts;
 
 /* Counters, cumulative since init. */
@@ -291,9 +298,9 @@ int cupk_apply_updates(cupk_ctx *ctx, const uint32_t *u, const uint32_t *v,
  * flagged updates, replacement rounds) stays pending until the next call on
  * ctx that needs it: the next apply call, cupk_sync, cupk_connected and
  * every other call that reads the forest, the sketch or the counters.  The
- * next apply call of a batch above 4096 updates overlaps the two: it
- * classifies and bins its batch while the pending batch's replacement
- * rounds run (cupk_opts.serial_rounds turns this off).
+ * next apply call of a large batch (cupk_opts.overlap_min_batch) overlaps
+ * the two: it classifies and bins its batch while the pending batch's
+ * replacement rounds run (cupk_opts.serial_rounds turns this off).
  * Validation runs on the GPU: a batch with u == v or an endpoint >= V
  * applies nothing, and CUPK_EINVAL is returned by the call that completes
  * its host part (the next such call).  In exact and levels modes the call

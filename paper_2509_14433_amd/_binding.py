@@ -61,6 +61,7 @@ class cupk_opts(ctypes.Structure):
         ("tile_layout", ctypes.c_uint32),
         ("serial_rounds", ctypes.c_uint32),
         ("coarse_tiles", ctypes.c_uint32),
+        ("overlap_min_batch", ctypes.c_uint32),
     ]
 
 
@@ -189,7 +190,7 @@ class Context:
                  stream=None, use_torch_memory=True, time_kernels=False, tile_vertices=0,
                  lds_rows=0, chunk_records=0, tile_grid=0, use_graph=False, exact=False,
                  levels=False, walk_plain=False, split_rounds=False, fill_reserve=False,
-                 tile_layout=0, serial_rounds=False, coarse_tiles=0):
+                 tile_layout=0, serial_rounds=False, coarse_tiles=0, overlap_min_batch=0):
         self._h = None
         self._sk_tensor = None
         self._keep = {}
@@ -211,6 +212,7 @@ class Context:
         opts.tile_layout = tile_layout
         opts.serial_rounds = 1 if serial_rounds else 0
         opts.coarse_tiles = coarse_tiles
+        opts.overlap_min_batch = overlap_min_batch
         torch = _torch()
         if stream is None and torch is not None and torch.cuda.is_available():
             # launch on torch's current stream so that torch-produced device

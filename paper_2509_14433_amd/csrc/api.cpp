@@ -1412,12 +1412,16 @@ static int set_pending(cupk_ctx *ctx, uint32_t n)
 
 // Whether batch k+1 (n updates) can be classified and binned while the
 // pending batch k's replacement rounds run: batch semantics, no captured
-// graphs, not a small batch, and batch buffers that already hold it (a
-// reallocation could free buffers that k's scatter still uses).
+// graphs, a batch of at least overlap_min_batch updates (smaller ones leave
+// the GPU idle during the rounds anyway), and batch buffers that already
+// hold it (a reallocation could free buffers that k's scatter still uses).
+constexpr uint32_t kOverlapMinBatch = 1u << 22;
 static bool can_overlap(cupk_ctx *ctx, uint32_t n)
 {
+    const uint32_t lo = ctx->opts.overlap_min_batch ? ctx->opts.overlap_min_batch
+                                                    : kOverlapMinBatch;
     return ctx->pending && !ctx->opts.serial_rounds && !ctx->opts.exact && !ctx->levels &&
-           ctx->opts.use_graph == 0 && n > kSmallMax && n <= ctx->batch_cap;
+           ctx->opts.use_graph == 0 && n > kSmallMax && n >= lo && n <= ctx->batch_cap;
 }
 
 static int apply_flushed(cupk_ctx *ctx, const uint64_t *d_upd, uint32_t n, bool defer);

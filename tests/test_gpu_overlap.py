@@ -76,8 +76,10 @@ def _reference(name, skip=None):
 def _run(cupk, R, serial, timed, mode, bad=None):
     import torch
     sm = cupk.SCATTER_ATOMIC if mode == "atomic" else cupk.SCATTER_STAGED
+    # (overlap_min_batch 1: these small batches overlap too)
     ctx = cupk.Context(R["V"], R["C"], R["D"], R["S"], scatter_mode=sm,
-                       max_batch=max(R["sizes"]), time_kernels=timed, serial_rounds=serial)
+                       max_batch=max(R["sizes"]), time_kernels=timed, serial_rounds=serial,
+                       overlap_min_batch=1)
     packed = torch.from_numpy(cupk.pack_updates(R["u"], R["v"], R["d"]).view(np.int64)).cuda()
     off = 0
     for i, s in enumerate(R["sizes"]):
@@ -151,4 +153,21 @@ def test_invalid_batch_between_overlapped_batches(cupk, serial):
     assert ctx.forest_edges() == R["forest"]
     ctr = ctx.counters()
     assert (ctr["links"], ctr["cuts"], ctr["rounds"]) == R["counts"]
+    ctx.close()
+
+
+def test_small_batches_take_the_serial_order_by_default(cupk):
+    # below overlap_min_batch (default 4,194,304 updates) no batch overlaps
+    import torch
+    R = _reference("clusters")
+    ctx = cupk.Context(R["V"], R["C"], R["D"], R["S"], max_batch=max(R["sizes"]))
+    packed = torch.from_numpy(cupk.pack_updates(R["u"], R["v"], R["d"]).view(np.int64)).cuda()
+    off = 0
+    for s in R["sizes"]:
+        ctx.apply_updates_device(packed[off:off + s])
+        off += s
+    ctx.sync()
+    assert ctx.counters()["overlapped"] == 0
+    assert ctx.digest() == R["digest"]
+    assert ctx.forest_edges() == R["forest"]
     ctx.close()
