@@ -111,6 +111,7 @@ int upload_forest_on(cupk_ctx *ctx, hipStream_t st)
         HIPCHK(hipMemcpyAsync(ctx->d_lbl, ctx->h_lbl, bytes, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(ctx->d_par, ctx->h_par, bytes, hipMemcpyHostToDevice, st));
         HIPCHK(launch_pack_forest(st, ctx->d_lbl, ctx->d_par, ctx->d_lp, ctx->V));
+        HIPCHK(launch_block_labels(st, ctx->d_lbl, ctx->V, ctx->d_blk, nullptr, 0, 0));
         return CUPK_OK;
     }
     // the previous staging block has been copied
@@ -135,6 +136,8 @@ int upload_forest_on(cupk_ctx *ctx, hipStream_t st)
     ctx->stage_busy = true;
     HIPCHK(launch_forest_pages(st, ctx->d_stage.p, (uint32_t)np, sh, ctx->V, ctx->d_lbl,
                                ctx->d_par, ctx->d_lp));
+    HIPCHK(launch_block_labels(st, ctx->d_lbl, ctx->V, ctx->d_blk, ctx->d_stage.p, (uint32_t)np,
+                               sh));
     return CUPK_OK;
 }
 
@@ -966,7 +969,7 @@ int enqueue_classify(cupk_ctx *ctx, hipStream_t s, uint32_t grid_n, bool tiles_o
     FlagInline fi = flag_inline(ctx, grid_n);
     fi.tiles_only = tiles_only ? 1u : 0u;
     HIPCHK(launch_classify(s, desc_ptr(ctx), ctx->cur_desc, grid_n, ctx->V, ctx->d_lp,
-                           ctx->d_hdr, ctx->d_fupd.p,
+                           ctx->d_blk, ctx->d_hdr, ctx->d_fupd.p,
                            ctx->opts.exact ? ctx->d_fpos.p : nullptr, ctx->d_fcnt.p,
                            cnt, cls_shift, cls_tiles, sa, ctx->h_hdr, fi, rel));
     return CUPK_OK;
@@ -1592,6 +1595,7 @@ void destroy(cupk_ctx *ctx)
     if (ctx->d_lbl) (void)hipFree(ctx->d_lbl);
     if (ctx->d_par) (void)hipFree(ctx->d_par);
     if (ctx->d_lp) (void)hipFree(ctx->d_lp);
+    if (ctx->d_blk) (void)hipFree(ctx->d_blk);
     if (ctx->h_lbl) (void)hipHostFree(ctx->h_lbl);
     if (ctx->h_par) (void)hipHostFree(ctx->h_par);
     if (ctx->d_hdr) (void)hipFree(ctx->d_hdr);
@@ -1789,6 +1793,7 @@ int init_impl(cupk_ctx *ctx, const cupk_opts *opts)
     HIPCHK(hipMalloc((void **)&ctx->d_lbl, (size_t)V * 4));
     HIPCHK(hipMalloc((void **)&ctx->d_par, (size_t)V * 4));
     HIPCHK(hipMalloc((void **)&ctx->d_lp, (size_t)V * 8));
+    HIPCHK(hipMalloc((void **)&ctx->d_blk, (((size_t)V + 63) >> kBlkShift) * 4));
     HIPCHK(hipHostMalloc((void **)&ctx->h_lbl, (size_t)V * 4, hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&ctx->h_par, (size_t)V * 4, hipHostMallocDefault));
     HIPCHK(hipMalloc((void **)&ctx->d_hdr, HDR_WORDS * 4));

@@ -74,6 +74,7 @@ struct cupk_ctx {
     uint64_t *d_seeds = nullptr;
     uint32_t *d_lbl = nullptr, *d_par = nullptr;
     uint64_t *d_lp = nullptr;  // label | parent << 32 per vertex
+    uint32_t *d_blk = nullptr; // per 64 vertex ids: their common label, or kBlkMixed
     uint32_t *h_lbl = nullptr, *h_par = nullptr;
     bool forest_dev_stale = false;
     // page-wise uploads of the forest: the pages written since the last

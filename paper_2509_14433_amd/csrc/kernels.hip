@@ -347,7 +347,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_offsets(uint32_t *__restr
 
 __global__ __launch_bounds__(kClsThreads) void k_classify(
     const BatchDesc *__restrict__ desc, BatchDesc dv, uint32_t V, const uint64_t *__restrict__ lp,
-    uint32_t *__restrict__ hdr, uint64_t *__restrict__ fupd,
+    const uint32_t *__restrict__ blk, uint32_t *__restrict__ hdr, uint64_t *__restrict__ fupd,
     uint32_t *__restrict__ fpos, uint32_t *__restrict__ fcnt, uint32_t *__restrict__ fdel,
     uint32_t *__restrict__ tile_cnt, uint32_t tile_shift, uint32_t ntiles,
     uint32_t *__restrict__ tile_rel)
@@ -367,24 +367,42 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
     const uint32_t wid = threadIdx.x / 64;
     uint64_t p[kClsPerThread];
     uint64_t lu[kClsPerThread], lv[kClsPerThread];  // label | parent << 32
+    uint32_t bu[kClsPerThread], bv[kClsPerThread];  // block labels (inserts)
 #pragma unroll
     for (uint32_t k = 0; k < kClsPerThread; k++) {
         const uint32_t i = begin + k * kClsThreads + threadIdx.x;
         p[k] = i < n ? upd[i] : 0;
     }
-    // bit k of `ok`: update k exists and is valid
+    // bit k of `ok`: update k exists and is valid.  An insert whose
+    // endpoints both lie in blocks of one label each is decided by those
+    // labels (a table of V/64 words); the others load both forest words.
     uint32_t ok = 0;
 #pragma unroll
     for (uint32_t k = 0; k < kClsPerThread; k++) {
         const uint32_t i = begin + k * kClsThreads + threadIdx.x;
         uint32_t u, v;
         bool del;
-        lu[k] = lv[k] = 0;
+        bu[k] = bv[k] = kBlkMixed;
         if (i < n && unpack(p[k], V, u, v, del)) {
             ok |= 1u << k;
-            lu[k] = lp[u];
-            lv[k] = lp[v];
+            if (blk && !del) {
+                bu[k] = blk[u >> kBlkShift];
+                bv[k] = blk[v >> kBlkShift];
+            }
         }
+    }
+    uint32_t gath = 0;  // bit k: update k is decided by its forest words
+#pragma unroll
+    for (uint32_t k = 0; k < kClsPerThread; k++) {
+        lu[k] = lv[k] = 0;
+        if (!((ok >> k) & 1u)) continue;
+        if (bu[k] != kBlkMixed && bv[k] != kBlkMixed) continue;
+        uint32_t u, v;
+        bool del;
+        unpack(p[k], V, u, v, del);
+        gath |= 1u << k;
+        lu[k] = lp[u];
+        lv[k] = lp[v];
     }
     bool bad = false;
 #pragma unroll
@@ -396,11 +414,16 @@ __global__ __launch_bounds__(kClsThreads) void k_classify(
 #pragma unroll
     for (uint32_t k = 0; k < kClsPerThread; k++) {
         if (!((ok >> k) & 1u)) continue;
-        uint32_t u, v;
-        bool del;
-        unpack(p[k], V, u, v, del);
-        bool f = (uint32_t)lu[k] != (uint32_t)lv[k];
-        if (!f && del) f = (uint32_t)(lu[k] >> 32) == v || (uint32_t)(lv[k] >> 32) == u;
+        bool f;
+        if (!((gath >> k) & 1u)) {
+            f = bu[k] != bv[k];  // an insert between two uniform blocks
+        } else {
+            uint32_t u, v;
+            bool del;
+            unpack(p[k], V, u, v, del);
+            f = (uint32_t)lu[k] != (uint32_t)lv[k];
+            if (!f && del) f = (uint32_t)(lu[k] >> 32) == v || (uint32_t)(lv[k] >> 32) == u;
+        }
         if (f) fl |= 1u << k;
     }
     __syncthreads();  // hist zeroed
@@ -489,6 +512,40 @@ __global__ void k_pack_forest(const uint32_t *__restrict__ lbl, const uint32_t *
         lp[w] = (uint64_t)lbl[w] | (uint64_t)par[w] << 32;
 }
 
+// One wave per block of 2^kBlkShift = 64 vertex ids: the label they all
+// share, or kBlkMixed.  pages null: every block; else the blocks of the np
+// pages (2^pshift ids each) listed there.
+__global__ void k_block_labels(const uint32_t *__restrict__ lbl, uint32_t V,
+                               uint32_t *__restrict__ blk, const uint32_t *__restrict__ pages,
+                               uint32_t np, uint32_t pshift)
+{
+    const uint32_t nblk = (V + 63) >> kBlkShift;
+    const uint32_t per = pages ? 1u << (pshift - kBlkShift) : 0u;  // blocks per page
+    const uint32_t nw = pages ? np * per : nblk;
+    const uint32_t lane = __lane_id();
+    for (uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / 64; w < nw;
+         w += gridDim.x * blockDim.x / 64) {
+        const uint32_t b = pages ? (pages[w / per] << (pshift - kBlkShift)) + w % per : w;
+        if (b >= nblk) continue;  // (wave-uniform) past the last vertex
+        const uint32_t x = (b << kBlkShift) + lane;
+        const uint32_t l = x < V ? lbl[x] : 0u;
+        const uint32_t first = __shfl(l, 0);
+        const uint64_t differ = __ballot(x < V && l != first);
+        if (lane == 0) blk[b] = differ ? kBlkMixed : first;
+    }
+}
+
+hipError_t launch_block_labels(hipStream_t s, const uint32_t *lbl, uint32_t V, uint32_t *blk,
+                               const uint32_t *pages, uint32_t np, uint32_t pshift)
+{
+    if (V == 0 || (pages && np == 0)) return hipSuccess;
+    if (pages && (pshift < kBlkShift || pshift > 16)) return hipErrorInvalidValue;
+    const uint32_t nw = pages ? np << (pshift - kBlkShift) : (V + 63) >> kBlkShift;
+    const uint32_t grid = min((nw + 3) / 4, 8192u);
+    k_block_labels<<<grid, 256, 0, s>>>(lbl, V, blk, pages, np, pshift);
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_forest(hipStream_t s, const uint32_t *lbl, const uint32_t *par, uint64_t *lp,
                               uint32_t V)
 {
@@ -528,7 +585,7 @@ hipError_t launch_forest_pages(hipStream_t s, const uint32_t *stage, uint32_t np
 }
 
 hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
-                           uint32_t V, const uint64_t *lp, uint32_t *hdr,
+                           uint32_t V, const uint64_t *lp, const uint32_t *blk, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles, const ScanArgs &sa,
                            uint32_t *hout, const FlagInline &fi, uint32_t *tile_rel)
@@ -541,7 +598,8 @@ hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, u
     if (sa.sums && (tile_rel || sa.groups != 1 || ntiles <= kScanOneBlockTiles))
         return hipErrorInvalidValue;
     k_classify<<<classify_blocks(grid_n), kClsThreads, 0, s>>>(
-        desc, dv, V, lp, hdr, fupd, fpos, fcnt, fi.fdel, tile_cnt, tile_shift, ntiles, tile_rel);
+        desc, dv, V, lp, blk, hdr, fupd, fpos, fcnt, fi.fdel, tile_cnt, tile_shift, ntiles,
+        tile_rel);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // (nothing to do for the one-block scan when it only scans tiles and

@@ -115,9 +115,11 @@ struct StagedParams {
 // stores at tile_rel[b*ntiles + t] where its records start among the
 // records of count copy b % kCntGroups in tile t (written only for tiles it
 // has records in), so that the fill reserves nothing.
+// blk (may be null): the block labels (launch_block_labels) of the forest
+// in lp; inserts between two uniform blocks then skip the forest words.
 constexpr uint32_t kRelMaxTiles = 2048;
 hipError_t launch_classify(hipStream_t s, const BatchDesc *desc, BatchDesc dv, uint32_t grid_n,
-                           uint32_t V, const uint64_t *lp, uint32_t *hdr,
+                           uint32_t V, const uint64_t *lp, const uint32_t *blk, uint32_t *hdr,
                            uint64_t *fupd, uint32_t *fpos, uint32_t *fcnt, uint32_t *tile_cnt,
                            uint32_t tile_shift, uint32_t ntiles, const ScanArgs &sa,
                            uint32_t *hout, const FlagInline &fi, uint32_t *tile_rel);
@@ -126,6 +128,15 @@ uint32_t classify_blocks(uint32_t n);
 // one 8-byte load per endpoint gives its label and its parent).
 hipError_t launch_pack_forest(hipStream_t s, const uint32_t *lbl, const uint32_t *par, uint64_t *lp,
                               uint32_t V);
+// Block labels: blk[b] (b < ceil(V / 64)) = the label that all vertex ids
+// [64 b, 64 b + 64) below V share, or kBlkMixed.  With `pages` (np page ids
+// in device memory, pages of 2^pshift ids, pshift in [6, 16]) only the
+// blocks of those pages are recomputed.  The classify kernel (blk non-null)
+// decides an insert whose endpoints both lie in uniform blocks by them.
+constexpr uint32_t kBlkShift = 6;
+constexpr uint32_t kBlkMixed = 0xffffffffu;
+hipError_t launch_block_labels(hipStream_t s, const uint32_t *lbl, uint32_t V, uint32_t *blk,
+                               const uint32_t *pages, uint32_t np, uint32_t pshift);
 // Refresh np pages of 2^pshift vertices of the device forest from a staging
 // block: np page ids, then each page's labels in turn, then each page's
 // parents in turn (2^pshift words per page; entries past V are ignored).
