@@ -431,10 +431,12 @@ int cupk_static_components(cupk_ctx *ctx, uint32_t *labels, uint32_t *eu, uint32
                            cupk_static_info *info);
 
 /* ---- autotuner ------------------------------------------------------------
- * Picks the staged scatter's tile geometry (vertices per LDS tile, depth
- * rows in LDS, records per work item) by timing every candidate's device
- * work (classification, tile scan, binning, scatter) on a sample batch, and
- * derives a batch-size schedule: the device time of prefixes n/128 .. n of
+ * Picks the staged scatter's tile geometry (lane layout, vertices per LDS
+ * tile, depth rows in LDS, records per work item) by timing every
+ * candidate's device work (classification, tile scan, binning, scatter) on
+ * a sample batch and timing the best four again (two alternating passes,
+ * which decide), then the tiles per coarse bin of the two-level binning for
+ * that setting; and derives a batch-size schedule: the device time of prefixes n/128 .. n of
  * the sample plus the host time per batch this context has measured so far
  * (flag walk and replacement rounds, nearly independent of the batch size);
  * batch_target is the smallest prefix whose whole-path rate reaches 80% of
@@ -450,8 +452,10 @@ typedef struct {
     uint32_t lds_rows;
     uint32_t chunk_records;
     uint32_t candidates;       /* settings timed                               */
-    double best_ms;            /* bin + scatter time of the sample, chosen     */
-    double before_ms;          /* same with the setting in force before        */
+    double best_ms;            /* device time of the sample, chosen setting
+                                  (its second timing)                          */
+    double before_ms;          /* same with the setting in force before (its
+                                  first timing)                                */
     uint32_t batch_target;     /* smallest timed batch reaching 80% of the
                                   best whole-path rate (batch-size schedule)  */
     double batch_ms[8];        /* device time of prefixes n/128, ... , n       */
